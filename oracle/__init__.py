@@ -1,0 +1,264 @@
+"""ctypes wrapper of the plain FP64 CPU oracle (``oracle/rbl_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, by the smoke check and by
+the CPU-baseline leg of the benchmark, never by the product package.
+
+The shared library is compiled by ``oracle/build.py`` (gcc, -O2,
+-ffp-contract=off); ``load()`` compiles it on first use when it is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import build as _build
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_lib = None
+
+_i64p = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
+_i32p = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+_u32p = np.ctypeslib.ndpointer(dtype=np.uint32, flags="C_CONTIGUOUS")
+_f64p = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+
+
+def _ptr_or_null(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = _build.library_path()
+    if not os.path.exists(path) or _build.stale():
+        _build.build()
+    lib = C.CDLL(path)
+    lib.orc_philox4x32_10.argtypes = [_u32p, _u32p, _u32p]
+    lib.orc_floyd_choices.argtypes = [C.c_int, C.c_int, _u32p, _i32p]
+    lib.orc_floyd_choices.restype = C.c_int
+    lib.orc_batch_positions.argtypes = [C.c_uint64, C.c_uint32, C.c_uint64, C.c_uint32,
+                                        C.c_int, C.c_int, _i32p]
+    lib.orc_batch_positions.restype = C.c_int
+    lib.orc_lj.argtypes = [C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    lib.orc_wrap.argtypes = [C.c_int64, _f64p, _f64p]
+    lib.orc_cell_grid.argtypes = [_f64p, C.c_double, C.c_double, _i32p]
+    lib.orc_sys_new.argtypes = [C.c_int64, _f64p, _f64p, C.c_double, C.c_double, C.c_double]
+    lib.orc_sys_new.restype = C.c_void_p
+    lib.orc_sys_free.argtypes = [C.c_void_p]
+    lib.orc_sys_ncells.argtypes = [C.c_void_p]
+    lib.orc_sys_ncells.restype = C.c_int64
+    lib.orc_sys_info.argtypes = [C.c_void_p, _i32p, C.c_void_p, C.c_void_p, C.c_void_p]
+    lib.orc_list_counts.argtypes = [C.c_void_p, C.c_int, C.c_int64, C.c_void_p, _i64p]
+    lib.orc_list_counts.restype = C.c_int
+    lib.orc_list_fill.argtypes = [C.c_void_p, C.c_int, C.c_int64, C.c_void_p,
+                                  C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                  C.c_void_p, C.c_void_p]
+    lib.orc_list_fill.restype = C.c_int
+    lib.orc_forces_rbl.argtypes = [C.c_int64, _f64p, _f64p, C.c_double, C.c_double, C.c_int,
+                                   C.c_int64, C.c_void_p, _i64p, _i32p, _i64p, _i32p,
+                                   C.c_int, C.c_uint64, C.c_uint64, C.c_uint32, C.c_void_p,
+                                   _f64p, _f64p, _f64p]
+    lib.orc_forces_rbl.restype = C.c_int
+    lib.orc_forces_full.argtypes = [C.c_int64, _f64p, _f64p, C.c_double, C.c_int,
+                                    C.c_int64, C.c_void_p, _i64p, _i32p, _f64p, _f64p, _f64p]
+    lib.orc_forces_full.restype = C.c_int
+    lib.orc_mean_subtract.argtypes = [C.c_int64, _f64p, _f64p]
+    lib.orc_md_run.argtypes = [C.c_int64, _f64p, _f64p, _f64p, C.c_double, C.c_double,
+                               C.c_double, C.c_double, C.c_int64, C.c_int, C.c_uint64,
+                               C.c_int64, C.c_int, C.c_int, C.c_int, C.c_int, C.c_uint32,
+                               _f64p, C.c_void_p]
+    lib.orc_md_run.restype = C.c_int
+    _lib = lib
+    return lib
+
+
+# ---------------------------------------------------------------------------
+# random numbers and the batch draw
+
+def philox4x32_10(counter, key) -> np.ndarray:
+    lib = load()
+    out = np.zeros(4, dtype=np.uint32)
+    lib.orc_philox4x32_10(np.asarray(counter, dtype=np.uint32),
+                          np.asarray(key, dtype=np.uint32), out)
+    return out
+
+
+def floyd_choices(p: int, n: int, choices) -> np.ndarray:
+    lib = load()
+    out = np.zeros(max(p, 1), dtype=np.int32)
+    r = lib.orc_floyd_choices(p, n, np.asarray(choices, dtype=np.uint32), out)
+    if r < 0:
+        raise ValueError(f"invalid Floyd choices (code {r})")
+    return out[:p]
+
+
+def batch_positions(seed: int, pid: int, step: int, replica: int, p: int, n: int) -> np.ndarray:
+    lib = load()
+    out = np.zeros(max(p, n, 1), dtype=np.int32)
+    cnt = lib.orc_batch_positions(seed, pid, step, replica, p, n, out)
+    return out[:cnt].copy()
+
+
+def lj(r2: float):
+    """(fmag, u): force factor multiplying (x_i - x_j) and unshifted energy."""
+    lib = load()
+    f = C.c_double()
+    u = C.c_double()
+    lib.orc_lj(float(r2), C.byref(f), C.byref(u))
+    return f.value, u.value
+
+
+def wrap(pos: np.ndarray, box) -> np.ndarray:
+    lib = load()
+    p = np.ascontiguousarray(pos, dtype=np.float64).copy()
+    lib.orc_wrap(p.shape[1], p, np.asarray(box, dtype=np.float64))
+    return p
+
+
+def cell_grid(box, rc: float, skin: float) -> np.ndarray:
+    lib = load()
+    out = np.zeros(3, dtype=np.int32)
+    lib.orc_cell_grid(np.asarray(box, dtype=np.float64), rc, skin, out)
+    return out
+
+
+# ---------------------------------------------------------------------------
+# neighbour lists
+
+@dataclass
+class Lists:
+    rows: np.ndarray       # particle IDs of the rows
+    core_off: np.ndarray
+    core_idx: np.ndarray
+    shell_off: np.ndarray
+    shell_idx: np.ndarray
+    full_off: np.ndarray
+    full_idx: np.ndarray
+
+    def row(self, kind: str, k: int) -> np.ndarray:
+        off = getattr(self, kind + "_off")
+        idx = getattr(self, kind + "_idx")
+        return idx[off[k]:off[k + 1]]
+
+
+class System:
+    """Positions at a list build: wrapped copy, canonical cell binning, and
+    neighbour lists for any subset of rows."""
+
+    def __init__(self, pos, box, rs: float, rc: float, skin: float):
+        lib = load()
+        self.pos = np.ascontiguousarray(pos, dtype=np.float64)
+        self.box = np.ascontiguousarray(box, dtype=np.float64)
+        self.n = int(self.pos.shape[1])
+        self.rs, self.rc, self.skin = float(rs), float(rc), float(skin)
+        self._h = lib.orc_sys_new(self.n, self.pos, self.box, rs, rc, skin)
+        self._lib = lib
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            self._lib.orc_sys_free(self._h)
+            self._h = None
+
+    def binning(self):
+        """(ncell (3,), wrapped positions (3, n), slot_of_id (n,), cell_start)"""
+        nc = self._lib.orc_sys_ncells(self._h)
+        ncell = np.zeros(3, dtype=np.int32)
+        wpos = np.zeros((3, self.n))
+        slot = np.zeros(self.n, dtype=np.int64)
+        cs = np.zeros(nc + 1, dtype=np.int64)
+        self._lib.orc_sys_info(self._h, ncell, wpos.ctypes.data_as(C.c_void_p),
+                               slot.ctypes.data_as(C.c_void_p), cs.ctypes.data_as(C.c_void_p))
+        return ncell, wpos, slot, cs
+
+    def lists(self, rows=None, method: str = "cells", kinds=("core", "shell", "full")) -> Lists:
+        m = {"cells": 0, "brute": 1}[method]
+        if rows is None:
+            rows_arr = np.arange(self.n, dtype=np.int64)
+        else:
+            rows_arr = np.ascontiguousarray(rows, dtype=np.int64)
+        nrows = rows_arr.shape[0]
+        counts = np.zeros(3 * nrows, dtype=np.int64)
+        r = self._lib.orc_list_counts(self._h, m, nrows, rows_arr.ctypes.data_as(C.c_void_p), counts)
+        if r:
+            raise ValueError("bad row index")
+        counts = counts.reshape(3, nrows)
+        offs, idxs = [], []
+        for q, kind in enumerate(("core", "shell", "full")):
+            off = np.zeros(nrows + 1, dtype=np.int64)
+            off[1:] = np.cumsum(counts[q])
+            offs.append(off)
+            idxs.append(np.zeros(int(off[-1]), dtype=np.int32) if kind in kinds else None)
+        r = self._lib.orc_list_fill(
+            self._h, m, nrows, rows_arr.ctypes.data_as(C.c_void_p),
+            offs[0].ctypes.data_as(C.c_void_p), _ptr_or_null(idxs[0]),
+            offs[1].ctypes.data_as(C.c_void_p), _ptr_or_null(idxs[1]),
+            offs[2].ctypes.data_as(C.c_void_p), _ptr_or_null(idxs[2]))
+        if r:
+            raise RuntimeError(f"orc_list_fill failed ({r})")
+        empty = np.zeros(0, dtype=np.int32)
+        return Lists(rows_arr, offs[0], idxs[0] if idxs[0] is not None else empty,
+                     offs[1], idxs[1] if idxs[1] is not None else empty,
+                     offs[2], idxs[2] if idxs[2] is not None else empty)
+
+
+# ---------------------------------------------------------------------------
+# forces and dynamics
+
+def rbl_forces(pos, box, rs, rc, lists: Lists, p: int, seed: int, step: int,
+               replica: int = 0, shift: bool = True, pid=None):
+    """Raw RBL force (before mean subtraction) for the rows of ``lists``.
+    Returns (f (3, nrows), e (nrows,), w (nrows,))."""
+    lib = load()
+    pos = np.ascontiguousarray(pos, dtype=np.float64)
+    nrows = lists.rows.shape[0]
+    f = np.zeros((3, nrows))
+    e = np.zeros(nrows)
+    w = np.zeros(nrows)
+    pid_arr = None if pid is None else np.ascontiguousarray(pid, dtype=np.int64)
+    lib.orc_forces_rbl(pos.shape[1], pos, np.asarray(box, dtype=np.float64), rs, rc, int(shift),
+                       nrows, lists.rows.ctypes.data_as(C.c_void_p),
+                       lists.core_off, lists.core_idx, lists.shell_off, lists.shell_idx,
+                       p, seed, step, replica, _ptr_or_null(pid_arr), f, e, w)
+    return f, e, w
+
+
+def full_forces(pos, box, rc, lists: Lists, shift: bool = True):
+    lib = load()
+    pos = np.ascontiguousarray(pos, dtype=np.float64)
+    nrows = lists.rows.shape[0]
+    f = np.zeros((3, nrows))
+    e = np.zeros(nrows)
+    w = np.zeros(nrows)
+    lib.orc_forces_full(pos.shape[1], pos, np.asarray(box, dtype=np.float64), rc, int(shift),
+                        nrows, lists.rows.ctypes.data_as(C.c_void_p),
+                        lists.full_off, lists.full_idx, f, e, w)
+    return f, e, w
+
+
+def mean_subtract(f: np.ndarray):
+    lib = load()
+    g = np.ascontiguousarray(f, dtype=np.float64).copy()
+    mean = np.zeros(3)
+    lib.orc_mean_subtract(g.shape[1], g, mean)
+    return g, mean
+
+
+def md_run(pos, vel, box, rs, rc, skin, dt, nsteps, p=10, seed=1, step0=0, K=10,
+           use_full=False, shift=True, momentum_fix=True, replica=0, want_ev=False):
+    """Velocity-Verlet run (Algorithm 1, NVE).  Returns (pos, vel, force, ev)
+    with ev of shape (nsteps+1, 2) = (U, W) per force evaluation or None."""
+    lib = load()
+    x = np.ascontiguousarray(pos, dtype=np.float64).copy()
+    v = np.ascontiguousarray(vel, dtype=np.float64).copy()
+    f = np.zeros_like(x)
+    ev = np.zeros((nsteps + 1, 2)) if want_ev else None
+    r = lib.orc_md_run(x.shape[1], x, v, np.asarray(box, dtype=np.float64), rs, rc, skin, dt,
+                       nsteps, p, seed, step0, K, int(use_full), int(shift), int(momentum_fix),
+                       replica, f, _ptr_or_null(ev))
+    if r:
+        raise RuntimeError(f"orc_md_run failed ({r})")
+    return x, v, f, ev

@@ -1,0 +1,639 @@
+/*
+ * Plain FP64 CPU oracle of the random-batch list (RBL) short-range force path
+ * (Liang, Xu & Zhao, "Random-batch list algorithm for short-range molecular
+ * dynamics simulations", arXiv:2105.04884).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may call, link or
+ * load this file: only the tests, the smoke check and the benchmark's CPU
+ * baseline leg use it.  It shares no code, header, table or constant with the
+ * HIP path.
+ *
+ * It is written to be read against the paper, not to be fast: single
+ * threaded, no blocking, loops in the order the definitions give them.
+ * Build with -ffp-contract=off so that every multiply-add below is rounded
+ * exactly as written (fma() only where it is spelled out).
+ *
+ * Radius names: the paper calls the core radius r_c and the outer cut-off
+ * r_s.  This file uses the names of the public interface instead:
+ *   rs = core radius (direct sum, eq. (coreF)),
+ *   rc = outer cut-off (end of the shell zone, eq. (shellF)).
+ *
+ * What each function follows:
+ *   orc_philox4x32_10   Philox4x32-10 of Salmon, Moraes, Dror & Shaw (SC'11);
+ *                       the paper only says "randomly choose", the generator
+ *                       is a reading of the batch draw (Sec. II).
+ *   orc_floyd_choices   Floyd's sampling without replacement (Bentley &
+ *                       Floyd, CACM 1987): the batch B(i) of Sec. II, with the
+ *                       without-replacement moments of Appendix A.
+ *   orc_lj              LJ 12-6 pair potential eq. (12-6), truncated at the
+ *                       cut-off and shifted to zero there (Sec. II).
+ *   orc_build_*         cell list and core/shell neighbour lists (Sec. II,
+ *                       Fig. 1); brute force is the plain definition.
+ *   orc_forces_rbl      F_i = F_ic + (n/p) sum_{B(i)} f~_ij, eq. (coreF) and
+ *                       eq. (shellF); small shells (n <= p) taken whole.
+ *   orc_mean_subtract   subtraction of the average net force (Sec. II,
+ *                       Algorithm 1, F_cor of Appendix A).
+ *   orc_md_run          Algorithm 1 with velocity Verlet (NVE).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10 (Salmon et al., SC'11, "Parallel random numbers: as easy as
+ * 1, 2, 3").  Round multipliers and key (Weyl) increments from that paper. */
+
+#define ORC_PHILOX_MUL0 0xD2511F53u
+#define ORC_PHILOX_MUL1 0xCD9E8D57u
+#define ORC_PHILOX_WEYL0 0x9E3779B9u
+#define ORC_PHILOX_WEYL1 0xBB67AE85u
+
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {            /* key schedule: bump before rounds 2..10 */
+            k0 += ORC_PHILOX_WEYL0;
+            k1 += ORC_PHILOX_WEYL1;
+        }
+        uint64_t p0 = (uint64_t)ORC_PHILOX_MUL0 * (uint64_t)x0;
+        uint64_t p1 = (uint64_t)ORC_PHILOX_MUL1 * (uint64_t)x2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t y0 = hi1 ^ x1 ^ k0;
+        uint32_t y1 = lo1;
+        uint32_t y2 = hi0 ^ x3 ^ k1;
+        uint32_t y3 = lo0;
+        x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Batch draw.  Floyd's algorithm picks p distinct positions out of
+ * {0, ..., n-1}: for m = 0..p-1 with J = n-p+m it takes a uniform t in
+ * {0..J}; if t was already taken it takes J instead.  Every p-subset comes
+ * out with the same probability (simple random sampling without
+ * replacement, whose second moment (p-1)/(N-1) Appendix A uses).
+ *
+ * orc_floyd_choices takes the choices t[m] themselves, so that a test can
+ * enumerate them all; the positions are returned sorted ascending. */
+
+static int cmp_i32(const void* a, const void* b)
+{
+    int32_t x = *(const int32_t*)a, y = *(const int32_t*)b;
+    return (x > y) - (x < y);
+}
+
+int orc_floyd_choices(int p, int n, const uint32_t* t, int32_t* out)
+{
+    if (p <= 0 || n < p) return -1;
+    for (int m = 0; m < p; ++m) {
+        int32_t J = (int32_t)(n - p + m);
+        int32_t pick = (int32_t)t[m];
+        if (pick < 0 || pick > J) return -2;
+        int taken = 0;
+        for (int q = 0; q < m; ++q)
+            if (out[q] == pick) taken = 1;
+        out[m] = taken ? J : pick;
+    }
+    qsort(out, (size_t)p, sizeof(int32_t), cmp_i32);
+    return p;
+}
+
+/* Positions of the batch of particle `pid` at force evaluation `step`.
+ * Counter words: (pid, step mod 2^32, replica, block b), key = seed split in
+ * two 32-bit halves.  Draw m uses word m mod 4 of block floor(m/4); the
+ * uniform word u maps to t = floor(u (J+1) / 2^32).
+ * If n <= p the whole shell is the batch (positions 0..n-1).
+ * Returns the batch size min(n, p). */
+int orc_batch_positions(uint64_t seed, uint32_t pid, uint64_t step, uint32_t replica,
+                        int p, int n, int32_t* out)
+{
+    if (n <= 0) return 0;
+    if (n <= p) {
+        for (int k = 0; k < n; ++k) out[k] = k;
+        return n;
+    }
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t* t = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)p);
+    uint32_t words[4] = {0, 0, 0, 0};
+    for (int m = 0; m < p; ++m) {
+        if (m % 4 == 0) {
+            uint32_t ctr[4] = {pid, (uint32_t)step, replica, (uint32_t)(m / 4)};
+            orc_philox4x32_10(ctr, key, words);
+        }
+        uint32_t u = words[m % 4];
+        uint64_t J = (uint64_t)(n - p + m);
+        t[m] = (uint32_t)(((uint64_t)u * (J + 1)) >> 32);
+    }
+    int r = orc_floyd_choices(p, n, t, out);
+    free(t);
+    return r;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Pair term, eq. (12-6) with epsilon = sigma = 1:
+ *   U(r) = 4 (r^-12 - r^-6),
+ *   f_ij = -dU/dr * (x_i - x_j)/r = 24 r^-8 (2 r^-6 - 1) (x_i - x_j).
+ * fmag is the factor multiplying (x_i - x_j); u is the unshifted energy. */
+void orc_lj(double r2, double* fmag, double* u)
+{
+    double r2i = 1.0 / r2;
+    double sr6 = r2i * r2i * r2i;
+    *fmag = 24.0 * r2i * sr6 * (2.0 * sr6 - 1.0);
+    *u = 4.0 * sr6 * (sr6 - 1.0);
+}
+
+/* Minimum-image component of x_i - x_j in a periodic box of side L. */
+static double min_image(double d, double L, double invL)
+{
+    double k = rint(d * invL);
+    return fma(-k, L, d);
+}
+
+static double dist2(const double* pos, int64_t n, int64_t i, int64_t j,
+                    const double box[3], const double inv[3], double d[3])
+{
+    for (int a = 0; a < 3; ++a)
+        d[a] = min_image(pos[a * n + i] - pos[a * n + j], box[a], inv[a]);
+    return fma(d[2], d[2], fma(d[1], d[1], d[0] * d[0]));
+}
+
+/* ------------------------------------------------------------------------ */
+/* Canonical cell list.  Positions are first wrapped into the box; cells have
+ * edge >= (rc + skin)/2, so any pair closer than rc + skin lies within two
+ * cells of each other in every direction.  Particles are ordered by cell
+ * (z-major linear index) and by ID within a cell; that order ("slot") is the
+ * order in which a neighbour row lists its partners, and therefore the order
+ * the batch positions of orc_batch_positions index into. */
+
+#define ORC_HALF_STENCIL 2
+
+typedef struct orc_sys {
+    int64_t n;
+    double box[3], inv[3];
+    double rs, rc, skin;
+    double *pos;          /* wrapped copy, [3][n] */
+    int ncell[3];
+    int64_t ncells;
+    int64_t *cell_of;     /* per ID */
+    int64_t *slot_of;     /* per ID */
+    int64_t *id_of;       /* per slot */
+    int64_t *cell_start;  /* ncells + 1 */
+} orc_sys;
+
+void orc_wrap(int64_t n, double* pos, const double box[3])
+{
+    for (int a = 0; a < 3; ++a) {
+        double inv = 1.0 / box[a];
+        for (int64_t i = 0; i < n; ++i) {
+            double x = pos[a * n + i];
+            double k = floor(x * inv);
+            pos[a * n + i] = fma(-k, box[a], x);
+        }
+    }
+}
+
+int orc_cell_grid(const double box[3], double rc, double skin, int ncell[3])
+{
+    double w = 0.5 * (rc + skin) * 1.000001;
+    for (int a = 0; a < 3; ++a) {
+        double c = floor(box[a] / w);
+        if (c < 1.0) c = 1.0;
+        ncell[a] = (int)c;
+    }
+    return 0;
+}
+
+static int64_t cell_of_pos(const orc_sys* s, int64_t i)
+{
+    int64_t c[3];
+    for (int a = 0; a < 3; ++a) {
+        double scale = (double)s->ncell[a] / s->box[a];
+        double f = floor(s->pos[a * s->n + i] * scale);
+        int64_t k = (int64_t)f;
+        if (k < 0) k = 0;
+        if (k > s->ncell[a] - 1) k = s->ncell[a] - 1;
+        c[a] = k;
+    }
+    return (c[2] * s->ncell[1] + c[1]) * s->ncell[0] + c[0];
+}
+
+orc_sys* orc_sys_new(int64_t n, const double* pos, const double box[3],
+                     double rs, double rc, double skin)
+{
+    orc_sys* s = (orc_sys*)calloc(1, sizeof(orc_sys));
+    s->n = n;
+    for (int a = 0; a < 3; ++a) {
+        s->box[a] = box[a];
+        s->inv[a] = 1.0 / box[a];
+    }
+    s->rs = rs; s->rc = rc; s->skin = skin;
+    s->pos = (double*)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
+    memcpy(s->pos, pos, sizeof(double) * 3 * (size_t)n);
+    orc_wrap(n, s->pos, box);
+    orc_cell_grid(box, rc, skin, s->ncell);
+    s->ncells = (int64_t)s->ncell[0] * s->ncell[1] * s->ncell[2];
+    s->cell_of = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n + 1));
+    s->slot_of = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n + 1));
+    s->id_of = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n + 1));
+    s->cell_start = (int64_t*)calloc((size_t)s->ncells + 1, sizeof(int64_t));
+    /* counting sort by cell, stable in ID */
+    for (int64_t i = 0; i < n; ++i) {
+        s->cell_of[i] = cell_of_pos(s, i);
+        s->cell_start[s->cell_of[i] + 1] += 1;
+    }
+    for (int64_t c = 0; c < s->ncells; ++c) s->cell_start[c + 1] += s->cell_start[c];
+    int64_t* fill = (int64_t*)malloc(sizeof(int64_t) * (size_t)(s->ncells + 1));
+    memcpy(fill, s->cell_start, sizeof(int64_t) * (size_t)(s->ncells + 1));
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t slot = fill[s->cell_of[i]]++;
+        s->slot_of[i] = slot;
+        s->id_of[slot] = i;
+    }
+    free(fill);
+    return s;
+}
+
+void orc_sys_free(orc_sys* s)
+{
+    if (!s) return;
+    free(s->pos); free(s->cell_of); free(s->slot_of); free(s->id_of); free(s->cell_start);
+    free(s);
+}
+
+int64_t orc_sys_ncells(const orc_sys* s) { return s->ncells; }
+
+void orc_sys_info(const orc_sys* s, int32_t ncell[3], double* wrapped_pos,
+                  int64_t* slot_of_id, int64_t* cell_start)
+{
+    for (int a = 0; a < 3; ++a) ncell[a] = s->ncell[a];
+    if (wrapped_pos) memcpy(wrapped_pos, s->pos, sizeof(double) * 3 * (size_t)s->n);
+    if (slot_of_id) memcpy(slot_of_id, s->slot_of, sizeof(int64_t) * (size_t)s->n);
+    if (cell_start) memcpy(cell_start, s->cell_start, sizeof(int64_t) * (size_t)(s->ncells + 1));
+}
+
+/* Neighbour-list thresholds, squared distances (skin on both sides of the
+ * core radius and outside the cut-off):
+ *   core  C_i = { j : r^2 <  (rs+skin)^2 }
+ *   shell S_i = { j : max(rs-skin,0)^2 <= r^2 < (rc+skin)^2 }
+ *   full  V_i = { j : r^2 <  (rc+skin)^2 }            (direct truncation) */
+typedef struct { double core, shell_in, out; } orc_thr;
+
+static orc_thr thresholds(double rs, double rc, double skin)
+{
+    orc_thr t;
+    double a = rs + skin;
+    double b = rs - skin;
+    if (b < 0.0) b = 0.0;
+    double c = rc + skin;
+    t.core = a * a;
+    t.shell_in = b * b;
+    t.out = c * c;
+    return t;
+}
+
+/* Candidates of row i, collected either from the 5x5x5 cell stencil around
+ * i's cell (method 0; the paper's stenciled cells) or from all particles
+ * (method 1, brute force).  `emit` receives every candidate j != i with its
+ * squared distance.  Rows are put into slot order afterwards. */
+typedef struct {
+    int64_t* core; int64_t nc;
+    int64_t* shell; int64_t ns;
+    int64_t* full; int64_t nf;
+    int64_t cap;
+} orc_row;
+
+static void row_push(int64_t** arr, int64_t* len, int64_t* cap, int64_t v)
+{
+    if (*len == *cap) {
+        *cap = (*cap) * 2 + 16;
+        *arr = (int64_t*)realloc(*arr, sizeof(int64_t) * (size_t)(*cap));
+    }
+    (*arr)[(*len)++] = v;
+}
+
+typedef struct { int64_t ccap, scap, fcap; } orc_rowcap;
+
+static void classify(const orc_sys* s, orc_thr th, int64_t i, int64_t j,
+                     orc_row* row, orc_rowcap* cap)
+{
+    double d[3];
+    double r2 = dist2(s->pos, s->n, i, j, s->box, s->inv, d);
+    if (r2 < th.core) row_push(&row->core, &row->nc, &cap->ccap, j);
+    if (r2 >= th.shell_in && r2 < th.out) row_push(&row->shell, &row->ns, &cap->scap, j);
+    if (r2 < th.out) row_push(&row->full, &row->nf, &cap->fcap, j);
+}
+
+/* unique wrapped cell coordinates within +-2 of c along an axis of nc cells */
+static int stencil_axis(int c, int nc, int out[5])
+{
+    int k = 0;
+    if (nc <= 2 * ORC_HALF_STENCIL + 1) {
+        for (int q = 0; q < nc; ++q) out[k++] = q;
+        return k;
+    }
+    for (int d = -ORC_HALF_STENCIL; d <= ORC_HALF_STENCIL; ++d)
+        out[k++] = ((c + d) % nc + nc) % nc;
+    return k;
+}
+
+static const orc_sys* g_sort_sys;
+static int cmp_slot(const void* a, const void* b)
+{
+    int64_t x = g_sort_sys->slot_of[*(const int64_t*)a];
+    int64_t y = g_sort_sys->slot_of[*(const int64_t*)b];
+    return (x > y) - (x < y);
+}
+
+static void build_row(const orc_sys* s, orc_thr th, int method, int64_t i,
+                      orc_row* row, orc_rowcap* cap)
+{
+    row->nc = row->ns = row->nf = 0;
+    if (method == 1) {
+        for (int64_t j = 0; j < s->n; ++j)
+            if (j != i) classify(s, th, i, j, row, cap);
+    } else {
+        int64_t ci = s->cell_of[i];
+        int cx = (int)(ci % s->ncell[0]);
+        int cy = (int)((ci / s->ncell[0]) % s->ncell[1]);
+        int cz = (int)(ci / ((int64_t)s->ncell[0] * s->ncell[1]));
+        int sx[5], sy[5], sz[5];
+        int nx = stencil_axis(cx, s->ncell[0], sx);
+        int ny = stencil_axis(cy, s->ncell[1], sy);
+        int nz = stencil_axis(cz, s->ncell[2], sz);
+        for (int a = 0; a < nz; ++a)
+            for (int b = 0; b < ny; ++b)
+                for (int c = 0; c < nx; ++c) {
+                    int64_t cell = ((int64_t)sz[a] * s->ncell[1] + sy[b]) * s->ncell[0] + sx[c];
+                    for (int64_t q = s->cell_start[cell]; q < s->cell_start[cell + 1]; ++q) {
+                        int64_t j = s->id_of[q];
+                        if (j != i) classify(s, th, i, j, row, cap);
+                    }
+                }
+    }
+    g_sort_sys = s;
+    qsort(row->core, (size_t)row->nc, sizeof(int64_t), cmp_slot);
+    qsort(row->shell, (size_t)row->ns, sizeof(int64_t), cmp_slot);
+    qsort(row->full, (size_t)row->nf, sizeof(int64_t), cmp_slot);
+}
+
+/* Row lengths for the requested rows (all rows when rows == NULL):
+ * counts[0*nrows+k] core, counts[1*nrows+k] shell, counts[2*nrows+k] full. */
+int orc_list_counts(const orc_sys* s, int method, int64_t nrows, const int64_t* rows,
+                    int64_t* counts)
+{
+    orc_thr th = thresholds(s->rs, s->rc, s->skin);
+    orc_row row = {0};
+    orc_rowcap cap = {0, 0, 0};
+    for (int64_t k = 0; k < nrows; ++k) {
+        int64_t i = rows ? rows[k] : k;
+        if (i < 0 || i >= s->n) return -1;
+        build_row(s, th, method, i, &row, &cap);
+        counts[k] = row.nc;
+        counts[nrows + k] = row.ns;
+        counts[2 * nrows + k] = row.nf;
+    }
+    free(row.core); free(row.shell); free(row.full);
+    return 0;
+}
+
+/* CSR fill; offsets are exclusive prefix sums of the counts (length nrows+1).
+ * Any of the index arrays may be NULL to skip that list. */
+int orc_list_fill(const orc_sys* s, int method, int64_t nrows, const int64_t* rows,
+                  const int64_t* core_off, int32_t* core_idx,
+                  const int64_t* shell_off, int32_t* shell_idx,
+                  const int64_t* full_off, int32_t* full_idx)
+{
+    orc_thr th = thresholds(s->rs, s->rc, s->skin);
+    orc_row row = {0};
+    orc_rowcap cap = {0, 0, 0};
+    for (int64_t k = 0; k < nrows; ++k) {
+        int64_t i = rows ? rows[k] : k;
+        if (i < 0 || i >= s->n) return -1;
+        build_row(s, th, method, i, &row, &cap);
+        if (core_idx) {
+            if (core_off[k + 1] - core_off[k] != row.nc) return -2;
+            for (int64_t q = 0; q < row.nc; ++q) core_idx[core_off[k] + q] = (int32_t)row.core[q];
+        }
+        if (shell_idx) {
+            if (shell_off[k + 1] - shell_off[k] != row.ns) return -2;
+            for (int64_t q = 0; q < row.ns; ++q) shell_idx[shell_off[k] + q] = (int32_t)row.shell[q];
+        }
+        if (full_idx) {
+            if (full_off[k + 1] - full_off[k] != row.nf) return -2;
+            for (int64_t q = 0; q < row.nf; ++q) full_idx[full_off[k] + q] = (int32_t)row.full[q];
+        }
+    }
+    free(row.core); free(row.shell); free(row.full);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Forces.  Positions `pos` ([3][n]) are the current ones (not necessarily
+ * the ones the lists were built at); every pair is classified by its current
+ * squared distance.  Row k of the CSR lists belongs to particle rows[k]
+ * (rows == NULL: row k is particle k).  Outputs per row: f ([3][nrows]),
+ * e (pair energy, half per particle), w (virial sum of r.f, half per
+ * particle).  No mean-force subtraction here. */
+
+int orc_forces_rbl(int64_t n, const double* pos, const double box[3],
+                   double rs, double rc, int shift,
+                   int64_t nrows, const int64_t* rows,
+                   const int64_t* core_off, const int32_t* core_idx,
+                   const int64_t* shell_off, const int32_t* shell_idx,
+                   int p, uint64_t seed, uint64_t step, uint32_t replica,
+                   const int64_t* pid, double* f, double* e, double* w)
+{
+    double inv[3] = {1.0 / box[0], 1.0 / box[1], 1.0 / box[2]};
+    double rs2 = rs * rs, rc2 = rc * rc;
+    double fc_unused, uc = 0.0;
+    if (shift) orc_lj(rc2, &fc_unused, &uc);
+    int32_t* K = (int32_t*)malloc(sizeof(int32_t) * (size_t)(p > 0 ? p : 1));
+    for (int64_t k = 0; k < nrows; ++k) {
+        int64_t i = rows ? rows[k] : k;
+        double d[3], fm, u;
+        /* core: exact sum over r < rs, eq. (coreF) */
+        double Fc[3] = {0, 0, 0}, ec = 0.0, wc = 0.0;
+        for (int64_t q = core_off[k]; q < core_off[k + 1]; ++q) {
+            int64_t j = core_idx[q];
+            double r2 = dist2(pos, n, i, j, box, inv, d);
+            if (r2 < rs2) {
+                orc_lj(r2, &fm, &u);
+                for (int a = 0; a < 3; ++a) Fc[a] += fm * d[a];
+                ec += u - uc;
+                wc += fm * r2;
+            }
+        }
+        /* shell: batch of p candidates, scaled by n_i/p, eq. (shellF); only
+         * candidates whose current distance lies in [rs, rc) contribute. */
+        int ns = (int)(shell_off[k + 1] - shell_off[k]);
+        uint32_t id_for_rng = (uint32_t)(pid ? pid[k] : i);
+        int cnt = orc_batch_positions(seed, id_for_rng, step, replica, p, ns, K);
+        double scale = ns > p ? (double)ns / (double)p : 1.0;
+        double Fs[3] = {0, 0, 0}, es = 0.0, ws = 0.0;
+        for (int m = 0; m < cnt; ++m) {
+            int64_t j = shell_idx[shell_off[k] + K[m]];
+            double r2 = dist2(pos, n, i, j, box, inv, d);
+            if (r2 >= rs2 && r2 < rc2) {
+                orc_lj(r2, &fm, &u);
+                for (int a = 0; a < 3; ++a) Fs[a] += fm * d[a];
+                es += u - uc;
+                ws += fm * r2;
+            }
+        }
+        for (int a = 0; a < 3; ++a) f[a * nrows + k] = Fc[a] + scale * Fs[a];
+        if (e) e[k] = 0.5 * (ec + scale * es);
+        if (w) w[k] = 0.5 * (wc + scale * ws);
+    }
+    free(K);
+    return 0;
+}
+
+int orc_forces_full(int64_t n, const double* pos, const double box[3],
+                    double rc, int shift, int64_t nrows, const int64_t* rows,
+                    const int64_t* full_off, const int32_t* full_idx,
+                    double* f, double* e, double* w)
+{
+    double inv[3] = {1.0 / box[0], 1.0 / box[1], 1.0 / box[2]};
+    double rc2 = rc * rc;
+    double fc_unused, uc = 0.0;
+    if (shift) orc_lj(rc2, &fc_unused, &uc);
+    for (int64_t k = 0; k < nrows; ++k) {
+        int64_t i = rows ? rows[k] : k;
+        double d[3], fm, u;
+        double F[3] = {0, 0, 0}, ei = 0.0, wi = 0.0;
+        for (int64_t q = full_off[k]; q < full_off[k + 1]; ++q) {
+            int64_t j = full_idx[q];
+            double r2 = dist2(pos, n, i, j, box, inv, d);
+            if (r2 < rc2) {
+                orc_lj(r2, &fm, &u);
+                for (int a = 0; a < 3; ++a) F[a] += fm * d[a];
+                ei += u - uc;
+                wi += fm * r2;
+            }
+        }
+        for (int a = 0; a < 3; ++a) f[a * nrows + k] = F[a];
+        if (e) e[k] = 0.5 * ei;
+        if (w) w[k] = 0.5 * wi;
+    }
+    return 0;
+}
+
+/* Average net force (F_cor of Appendix A) subtracted from every particle, so
+ * that the total force, and with it the total momentum, is conserved. */
+void orc_mean_subtract(int64_t n, double* f, double out_mean[3])
+{
+    for (int a = 0; a < 3; ++a) {
+        double sum = 0.0;
+        for (int64_t i = 0; i < n; ++i) sum += f[a * n + i];
+        double mean = sum / (double)n;
+        for (int64_t i = 0; i < n; ++i) f[a * n + i] = f[a * n + i] - mean;
+        if (out_mean) out_mean[a] = mean;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Algorithm 1 for NVE velocity Verlet (unit mass).  Lists are built at the
+ * first force evaluation and rebuilt whenever the index of the next force
+ * evaluation is a multiple of K; positions are wrapped into the box at every
+ * build.  Force evaluation s draws its batches with step counter s.
+ *   v += (dt/2) F;  x += dt v;  [rebuild];  F = force(s+1);  v += (dt/2) F
+ * ev_out (may be NULL) receives, per force evaluation (nsteps+1 of them),
+ * the potential energy and the virial. */
+
+typedef struct {
+    int64_t *core_off, *shell_off, *full_off;
+    int32_t *core_idx, *shell_idx, *full_idx;
+} orc_lists;
+
+static void free_lists(orc_lists* L)
+{
+    free(L->core_off); free(L->shell_off); free(L->full_off);
+    free(L->core_idx); free(L->shell_idx); free(L->full_idx);
+    memset(L, 0, sizeof(*L));
+}
+
+static int build_all(int64_t n, double* pos, const double box[3], double rs, double rc,
+                     double skin, int use_full, orc_lists* L)
+{
+    free_lists(L);
+    orc_wrap(n, pos, box);
+    orc_sys* s = orc_sys_new(n, pos, box, rs, rc, skin);
+    int64_t* counts = (int64_t*)malloc(sizeof(int64_t) * 3 * (size_t)n);
+    orc_list_counts(s, 0, n, NULL, counts);
+    L->core_off = (int64_t*)calloc((size_t)n + 1, sizeof(int64_t));
+    L->shell_off = (int64_t*)calloc((size_t)n + 1, sizeof(int64_t));
+    L->full_off = (int64_t*)calloc((size_t)n + 1, sizeof(int64_t));
+    for (int64_t i = 0; i < n; ++i) {
+        L->core_off[i + 1] = L->core_off[i] + counts[i];
+        L->shell_off[i + 1] = L->shell_off[i] + counts[n + i];
+        L->full_off[i + 1] = L->full_off[i] + counts[2 * n + i];
+    }
+    free(counts);
+    if (use_full) {
+        L->full_idx = (int32_t*)malloc(sizeof(int32_t) * (size_t)(L->full_off[n] + 1));
+    } else {
+        L->core_idx = (int32_t*)malloc(sizeof(int32_t) * (size_t)(L->core_off[n] + 1));
+        L->shell_idx = (int32_t*)malloc(sizeof(int32_t) * (size_t)(L->shell_off[n] + 1));
+    }
+    int rcode = orc_list_fill(s, 0, n, NULL, L->core_off, L->core_idx, L->shell_off,
+                              L->shell_idx, L->full_off, L->full_idx);
+    orc_sys_free(s);
+    return rcode;
+}
+
+static void total_ev(int64_t n, const double* e, const double* w, double* out)
+{
+    double U = 0.0, W = 0.0;
+    for (int64_t i = 0; i < n; ++i) { U += e[i]; W += w[i]; }
+    out[0] = U;
+    out[1] = W;
+}
+
+int orc_md_run(int64_t n, double* pos, double* vel, const double box[3],
+               double rs, double rc, double skin, double dt, int64_t nsteps,
+               int p, uint64_t seed, int64_t step0, int K, int use_full,
+               int shift, int momentum_fix, uint32_t replica,
+               double* force_out, double* ev_out)
+{
+    if (K < 1 || n < 1) return -1;
+    orc_lists L = {0};
+    double* F = (double*)malloc(sizeof(double) * 3 * (size_t)n);
+    double* e = (double*)malloc(sizeof(double) * (size_t)n);
+    double* w = (double*)malloc(sizeof(double) * (size_t)n);
+    double h = 0.5 * dt;
+    int rcode = 0;
+    for (int64_t it = 0; it <= nsteps; ++it) {
+        int64_t s = step0 + it;
+        if (it > 0) {
+            /* first half of step it-1: kick and drift */
+            for (int64_t i = 0; i < 3 * n; ++i) vel[i] = vel[i] + h * F[i];
+            for (int64_t i = 0; i < 3 * n; ++i) pos[i] = pos[i] + dt * vel[i];
+        }
+        if (it == 0 || s % K == 0) {
+            rcode = build_all(n, pos, box, rs, rc, skin, use_full, &L);
+            if (rcode) break;
+        }
+        if (use_full) {
+            orc_forces_full(n, pos, box, rc, shift, n, NULL, L.full_off, L.full_idx, F, e, w);
+        } else {
+            orc_forces_rbl(n, pos, box, rs, rc, shift, n, NULL, L.core_off, L.core_idx,
+                           L.shell_off, L.shell_idx, p, seed, (uint64_t)s, replica, NULL,
+                           F, e, w);
+            if (momentum_fix) orc_mean_subtract(n, F, NULL);
+        }
+        if (ev_out) total_ev(n, e, w, ev_out + 2 * it);
+        if (it > 0) {
+            /* second half of step it-1: kick with the new force */
+            for (int64_t i = 0; i < 3 * n; ++i) vel[i] = vel[i] + h * F[i];
+        }
+    }
+    if (force_out) memcpy(force_out, F, sizeof(double) * 3 * (size_t)n);
+    free(F); free(e); free(w);
+    free_lists(&L);
+    return rcode;
+}
