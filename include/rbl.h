@@ -1,0 +1,211 @@
+/*
+ * rbl.h -- C-ABI of librbl: the random-batch list (RBL) short-range force
+ * path of a Lennard-Jones molecular-dynamics step on an AMD Instinct MI355X
+ * (gfx950), after Liang, Xu & Zhao, "Random-batch list algorithm for
+ * short-range molecular dynamics simulations" (arXiv:2105.04884).
+ *
+ * Radius names (the paper swaps them):
+ *   r_s = core radius: pairs closer than r_s are summed exactly, eq. (coreF);
+ *   r_c = outer cut-off: pairs with r_s <= r < r_c form the shell zone, from
+ *         which each particle draws a batch of P partners whose summed force
+ *         is scaled by n_i/P, eq. (shellF).
+ *
+ * Conventions for every call:
+ *  - Return value: RBL_OK (0), a warning (> 0) or an error (< 0).  No C++
+ *    exception crosses this boundary.  rbl_last_error() returns a message
+ *    for the last failing call on the calling thread.
+ *  - Arguments are checked before any work is queued; a failing check
+ *    queues nothing.
+ *  - Work is queued on the HIP stream given to rbl_create and runs
+ *    asynchronously unless the call says it synchronises.  Device-side
+ *    errors (non-finite positions) surface at the next synchronising call.
+ *  - Device pointers point to GPU memory owned by the caller and must stay
+ *    valid until the queued work has finished.  Host pointers are read or
+ *    written before the call returns.
+ *  - Particle arrays are in the caller's order ("ID" = index in the
+ *    caller's arrays) and laid out as structure of arrays: pos[0..n) holds
+ *    x, pos[n..2n) y, pos[2n..3n) z (same for velocities and forces).
+ *    For an ensemble the replicas are concatenated in replica order.
+ *  - A context is not thread-safe; use one per host thread.
+ *  - Units are reduced LJ units: epsilon = sigma = mass = 1.
+ */
+#ifndef RBL_H
+#define RBL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rbl_ctx rbl_ctx;
+
+typedef enum rbl_status {
+    RBL_OK = 0,
+    RBL_W_SKIN = 1,        /* warning: some particle moved more than skin/2 between list builds */
+    RBL_E_ARG = -1,        /* invalid argument (NULL pointer, non-positive size, bad radius, P out of range) */
+    RBL_E_BOX = -2,        /* a box edge is not larger than 2 (r_c + skin) */
+    RBL_E_STATE = -3,      /* call needs a list build first, or the build lacks the list asked for */
+    RBL_E_CAPACITY = -4,   /* neighbour rows exceeded their capacity and could not be regrown */
+    RBL_E_NONFINITE = -5,  /* a position was NaN or infinite at a list build */
+    RBL_E_HIP = -6,        /* HIP runtime error */
+    RBL_E_NOMEM = -7       /* device allocation failed */
+} rbl_status;
+
+enum { RBL_PREC_FP64 = 0, RBL_PREC_MIXED = 1 };
+enum { RBL_PAIR_LJ = 0, RBL_PAIR_LJ_ERFC = 1 };
+enum { RBL_LIST_CORE = 1, RBL_LIST_SHELL = 2, RBL_LIST_FULL = 4 };
+
+/* Largest batch size P accepted by rbl_forces, rbl_step and
+ * rbl_export_batches. */
+#define RBL_MAX_P 128
+
+typedef struct rbl_config {
+    int64_t n;                 /* particles over all replicas, >= 1 */
+    int32_t n_replicas;        /* independent systems sharing the launches, >= 1 */
+    int32_t precision;         /* RBL_PREC_FP64: all pair arithmetic in FP64.
+                                  RBL_PREC_MIXED: distances, r^2 and the core/shell/cut-off
+                                  classification in FP64; r^-2, r^-6 and the force
+                                  magnitude in FP32; per-particle force, energy and
+                                  virial accumulated in FP64. */
+    int32_t pair;              /* RBL_PAIR_LJ, or RBL_PAIR_LJ_ERFC (adds q_i q_j erfc(alpha r)/r) */
+    int32_t lists;             /* RBL_LIST_* mask built by rbl_build (default core|shell) */
+    double skin;               /* Verlet skin (default 0.3): lists hold candidates within
+                                  r_s + skin (core), [max(r_s - skin, 0), r_c + skin) (shell)
+                                  and r_c + skin (full) */
+    double alpha;              /* erfc screening parameter for RBL_PAIR_LJ_ERFC */
+    int32_t shift;             /* 1: pair energy shifted to zero at r_c (default 1) */
+    int32_t momentum_fix;      /* 1: subtract the average net force per replica from the
+                                  RBL force (default 1; Sec. II, Appendix A) */
+    int32_t predraw;           /* 1: rbl_step draws the batches of a whole list lifetime at
+                                  each rebuild (bit-identical to drawing inline; default 1) */
+    int32_t reserved0;
+    double capacity_factor;    /* headroom of list rows over the longest row seen (default 1.25) */
+    const int64_t* replica_offsets; /* host, n_replicas + 1 prefix offsets into the particle
+                                       arrays; NULL when n_replicas == 1 */
+    const double* charges;     /* device, n charges in caller order, or NULL (all zero) */
+} rbl_config;
+
+/* Fills *cfg with the defaults above for n particles in one replica. */
+void rbl_config_init(rbl_config* cfg, int64_t n);
+
+/* Creates a context.  hip_stream: a hipStream_t (NULL = the null stream).
+ * Errors: RBL_E_ARG (bad config), RBL_E_NOMEM, RBL_E_HIP. */
+rbl_status rbl_create(const rbl_config* cfg, void* hip_stream, rbl_ctx** out);
+
+/* Frees everything the context owns.  NULL is accepted. Synchronises. */
+rbl_status rbl_destroy(rbl_ctx* ctx);
+
+/*
+ * Builds the cell list and the neighbour lists at positions `pos` (device,
+ * SoA [3][n] FP64), Sec. II: particles are binned into cells of edge
+ * >= (r_c + skin)/2 and each particle's candidates are searched in the 5x5x5
+ * block of cells around its own.  Positions are wrapped into the box for the
+ * build (the caller's array is not modified).  `box` (host) holds 3 edges
+ * per replica.  Rows list their partners in the order of the cell traversal
+ * (cells by z-major index, particles within a cell by ID), and a batch
+ * position k in [0, n_i) refers to the k-th shell partner in that order.
+ * Synchronises (once, to size list capacities).
+ * Errors: RBL_E_ARG (NULL, r_s <= 0, r_c <= r_s), RBL_E_BOX, RBL_E_NONFINITE,
+ * RBL_E_NOMEM, RBL_E_HIP.
+ */
+rbl_status rbl_build(rbl_ctx* ctx, const double* pos, const double* box,
+                     double r_s, double r_c);
+
+/*
+ * RBL force at positions `pos` (device, SoA FP64, usually close to the
+ * positions of the last build), eq. (coreF) + eq. (shellF):
+ *   F_i = sum_{j in core, r < r_s} f_ij
+ *       + (n_i/P) sum_{j in B_i, r_s <= r < r_c} f_ij
+ * where B_i is P shell candidates drawn without replacement (Floyd's
+ * algorithm on Philox4x32-10, key = seed, counter = (replica-local particle
+ * ID, step mod 2^32, replica, block)); when n_i <= P the whole shell is used
+ * unscaled.  With momentum_fix the average net force of each replica is
+ * subtracted afterwards.  force: device SoA [3][n] (written).  ev: device,
+ * 2 doubles per replica (potential energy U, virial W = sum over pairs of
+ * r.f, both with the same estimator), or NULL.  1 <= P <= RBL_MAX_P.
+ * Errors: RBL_E_ARG, RBL_E_STATE (no build, or the build has no shell list).
+ */
+rbl_status rbl_forces(rbl_ctx* ctx, int P, uint64_t seed, uint64_t step,
+                      const double* pos, double* force, double* ev);
+
+/* Direct-truncation force at `pos` from the full list (needs
+ * RBL_LIST_FULL in cfg.lists): F_i = sum_{j, r < r_c} f_ij.  No mean-force
+ * subtraction.  Same pointer conventions as rbl_forces. */
+rbl_status rbl_full_forces(rbl_ctx* ctx, const double* pos, double* force, double* ev);
+
+/*
+ * Velocity-Verlet molecular dynamics (Algorithm 1, NVE), in place on the
+ * device arrays pos and vel (SoA FP64).  The lists are built at the first
+ * force evaluation and again before every force evaluation whose index s
+ * (counted from step0) satisfies s % rebuild_every == 0; positions are
+ * wrapped into the box at each build.  Force evaluation s draws batches with
+ * Philox step counter s.  Per step:
+ *   v += (dt/2) F;  x += dt v;  [rebuild];  F = force(s + 1);  v += (dt/2) F
+ * use_full = 1 runs the direct-truncation force instead (needs no shell list).
+ * force (device, may be NULL) receives the final force, ev (device, may be
+ * NULL) the final [U, W] per replica.  Box and radii are those of the last
+ * rbl_build.  Returns RBL_W_SKIN if any particle moved more than skin/2
+ * within one list lifetime.
+ * Errors: RBL_E_ARG, RBL_E_STATE, RBL_E_NONFINITE, RBL_E_NOMEM, RBL_E_HIP.
+ */
+rbl_status rbl_step(rbl_ctx* ctx, double* pos, double* vel, double* force,
+                    int64_t nsteps, double dt, int P, uint64_t seed, int64_t step0,
+                    int rebuild_every, int use_full, double* ev);
+
+/* ---- parity exports (host buffers, caller-allocated; synchronising) ---- */
+
+/* Row lengths of the last build for the particles rows[0..nrows) (IDs; NULL
+ * = all n): counts[k] core, counts[nrows+k] shell, counts[2 nrows+k] full
+ * (0 for a list that was not built). */
+rbl_status rbl_row_counts(rbl_ctx* ctx, int64_t nrows, const int64_t* rows, int64_t* counts);
+
+/* Rows of the last build as CSR over the requested rows; partners are
+ * particle IDs in row order.  *_off are prefix offsets of rbl_row_counts
+ * (nrows + 1 entries); an index pointer may be NULL to skip that list. */
+rbl_status rbl_export_lists(rbl_ctx* ctx, int64_t nrows, const int64_t* rows,
+                            const int64_t* core_off, int32_t* core_idx,
+                            const int64_t* shell_off, int32_t* shell_idx,
+                            const int64_t* full_off, int32_t* full_idx);
+
+/* The batches rbl_forces would draw: batch[k*P + m] = ID of the m-th drawn
+ * partner of particle rows[k] (in increasing batch position), -1 past
+ * count[k] = min(n_i, P). */
+rbl_status rbl_export_batches(rbl_ctx* ctx, int P, uint64_t seed, uint64_t step,
+                              int64_t nrows, const int64_t* rows,
+                              int32_t* batch, int32_t* count);
+
+/* Cell binning of the last build: ncell[3r..3r+2] cells per axis of replica
+ * r; slot_of_id[i] = position of particle i in the cell-sorted order of its
+ * replica (0-based within the replica); cell_count (may be NULL) per cell,
+ * replicas concatenated (size: sum of ncell products). */
+rbl_status rbl_export_binning(rbl_ctx* ctx, int32_t* ncell, int64_t* slot_of_id,
+                              int32_t* cell_count);
+
+/* ---- control ---- */
+
+/* Waits for the context's queued work and returns pending device errors
+ * (RBL_E_NONFINITE) or warnings (RBL_W_SKIN), clearing them. */
+rbl_status rbl_sync(rbl_ctx* ctx);
+
+/* Per-kernel timing with HIP events recorded on the context's stream around
+ * every launch while enabled.  rbl_kernel_stats fills, for kernel class
+ * `kind` (0 force RBL, 1 force full, 2 list build, 3 binning, 4 integrate,
+ * 5 reduce, 6 predraw), the number of launches and their summed duration in
+ * milliseconds since profiling was enabled; it synchronises. */
+rbl_status rbl_set_profiling(rbl_ctx* ctx, int on);
+rbl_status rbl_kernel_stats(rbl_ctx* ctx, int kind, int64_t* launches, double* total_ms);
+
+/* Size information: n_slots (particles plus per-replica padding to 64) and
+ * current list capacities (entries per row). */
+rbl_status rbl_info(rbl_ctx* ctx, int64_t* n_slots, int32_t* cap_core,
+                    int32_t* cap_shell, int32_t* cap_full);
+
+const char* rbl_last_error(void);
+const char* rbl_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RBL_H */

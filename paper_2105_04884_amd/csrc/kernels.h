@@ -1,0 +1,875 @@
+// HIP kernels of the RBL force path (gfx950, wave64).
+//
+// Data layout in HBM (n_slots = particles padded per replica to 64):
+//   xs        double4[n_slots]   cell-sorted positions (x, y, z, charge)
+//   vs, f     double[3][n_slots] cell-sorted velocities / raw forces (SoA)
+//   perm      int[n_slots]       slot -> caller ID (-1 = padding slot)
+//   lists     int[n_slices][cap][64] sliced ELL, partner slots in row order
+//   len       int[n_slots]       row lengths
+//   batch     int[K][P][n_slots] pre-drawn shell partners (slots)
+//   partial   double[5][n_slices] per-wavefront sums (Fx, Fy, Fz, U, W)
+#pragma once
+
+#include "device.h"
+
+namespace rbl {
+
+enum { kSrcCaller = 0, kSrcSorted = 1 };
+enum { kShellNone = 0, kShellInline = 1, kShellPredraw = 2 };
+enum { kIntFirst = 0, kIntMid = 1, kIntLast = 2 };
+enum { kFlagOverflow = 0, kFlagMaxCore = 1, kFlagMaxShell = 2, kFlagMaxFull = 3,
+       kFlagNonfinite = 4, kFlagSkin = 5, kFlagBadSlot = 6, kNumFlags = 8 };
+
+__global__ void k_fill_i32(int* p, int64_t n, int v)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// Binning: cell index of every particle (positions wrapped into the box),
+// counting-sort histogram.  Source is either the caller's SoA arrays (one
+// thread per ID) or the current cell-sorted state (one thread per slot).
+struct BinArgs {
+    const DevReplica* rep;
+    const int* id_rep;
+    const int* slice_rep;
+    const double* pos;     // caller SoA [3][n]
+    const double4* xs;     // sorted source
+    const int* perm_old;   // sorted source: slot -> ID
+    int64_t n;
+    int64_t n_src;
+    int* cell_of_src;
+    int* rank_of_src;
+    int* cell_count;
+    int* flags;
+};
+
+template <int SRC>
+__global__ __launch_bounds__(256) void k_bin_count(BinArgs a)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= a.n_src) return;
+    int r;
+    double x[3];
+    if (SRC == kSrcCaller) {
+        r = a.id_rep[s];
+        x[0] = a.pos[s];
+        x[1] = a.pos[a.n + s];
+        x[2] = a.pos[2 * a.n + s];
+    } else {
+        if (a.perm_old[s] < 0) {
+            a.cell_of_src[s] = -1;
+            return;
+        }
+        r = a.slice_rep[s >> 6];
+        const double4 p = a.xs[s];
+        x[0] = p.x;
+        x[1] = p.y;
+        x[2] = p.z;
+    }
+    const DevReplica& R = a.rep[r];
+    int c[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        if (!isfinite(x[d])) {
+            atomicOr(&a.flags[kFlagNonfinite], 1);
+            x[d] = 0.0;
+        }
+        const double w = wrap_coord(x[d], R.L[d], R.inv[d]);
+        int k = (int)floor(w * R.cscale[d]);
+        k = k < 0 ? 0 : (k > R.nc[d] - 1 ? R.nc[d] - 1 : k);
+        c[d] = k;
+    }
+    const int cell = (int)(R.cell_base + ((int64_t)c[2] * R.nc[1] + c[1]) * R.nc[0] + c[0]);
+    a.cell_of_src[s] = cell;
+    a.rank_of_src[s] = atomicAdd(&a.cell_count[cell], 1);
+}
+
+// Exclusive scan of the cell histogram (three passes, 2048 cells per block),
+// then shifted by each replica's slot offset so that replica r starts at its
+// 64-aligned slot base.
+constexpr int kScanPerThread = 8;
+constexpr int kScanBlock = 256;
+constexpr int kScanTile = kScanBlock * kScanPerThread;
+
+__device__ __forceinline__ int block_excl_scan(int v, int* lds_waves, int& total)
+{
+    const int incl = wave_incl_scan(v);
+    const int w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int nw = blockDim.x >> 6;
+    if (lane == 63) lds_waves[w] = incl;
+    __syncthreads();
+    int off = 0, tot = 0;
+    for (int q = 0; q < nw; ++q) {
+        const int t = lds_waves[q];
+        if (q < w) off += t;
+        tot += t;
+    }
+    __syncthreads();
+    total = tot;
+    return incl - v + off;
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_tiles(const int* cnt, int64_t n, int* tile_sum)
+{
+    __shared__ int lds[16];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPerThread;
+    int s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPerThread; ++k)
+        if (base + k < n) s += cnt[base + k];
+    int total;
+    block_excl_scan(s, lds, total);
+    if (threadIdx.x == 0) tile_sum[blockIdx.x] = total;
+}
+
+// One block of 1024 threads scans up to 1024*8 tile sums (exclusive, in place).
+__global__ __launch_bounds__(1024) void k_scan_tile_sums(int* tile_sum, int ntiles)
+{
+    __shared__ int lds[16];
+    const int base = threadIdx.x * kScanPerThread;
+    int v[kScanPerThread];
+    int s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPerThread; ++k) {
+        v[k] = base + k < ntiles ? tile_sum[base + k] : 0;
+        s += v[k];
+    }
+    int total;
+    int run = block_excl_scan(s, lds, total);
+#pragma unroll
+    for (int k = 0; k < kScanPerThread; ++k) {
+        if (base + k < ntiles) tile_sum[base + k] = run;
+        run += v[k];
+    }
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_final(const int* cnt, int64_t n,
+                                                           const int* tile_sum, const int* cell_rep,
+                                                           const DevReplica* rep, int* start)
+{
+    __shared__ int lds[16];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPerThread;
+    int v[kScanPerThread];
+    int s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPerThread; ++k) {
+        v[k] = base + k < n ? cnt[base + k] : 0;
+        s += v[k];
+    }
+    int total;
+    int run = block_excl_scan(s, lds, total) + tile_sum[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < kScanPerThread; ++k) {
+        const int64_t c = base + k;
+        if (c < n) {
+            const DevReplica& R = rep[cell_rep[c]];
+            start[c] = run + (int)(R.slot_base - R.id_base);
+        }
+        run += v[k];
+    }
+}
+
+template <int SRC>
+__global__ __launch_bounds__(256) void k_bin_scatter(BinArgs a, const int* cell_start,
+                                                     int* perm_new, int* src_of_slot,
+                                                     int64_t n_slots)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= a.n_src) return;
+    const int cell = a.cell_of_src[s];
+    if (cell < 0) return;
+    const int id = SRC == kSrcCaller ? (int)s : a.perm_old[s];
+    const int64_t slot = (int64_t)cell_start[cell] + a.rank_of_src[s];
+    if (slot < 0 || slot >= n_slots) {
+        atomicOr(&a.flags[kFlagBadSlot], 1);
+        return;
+    }
+    perm_new[slot] = id;
+    src_of_slot[slot] = (int)s;
+}
+
+// Within each cell, order particles by ID (insertion sort; cells hold a
+// handful of particles).  Makes the slot order independent of atomic order.
+__global__ __launch_bounds__(256) void k_cell_sort(const int* cell_start, const int* cell_count,
+                                                   int64_t n_cells, int64_t n_slots, int* perm,
+                                                   int* src_of_slot, int* flags)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_cells) return;
+    const int b = cell_start[c];
+    const int m = cell_count[c];
+    if (b < 0 || (int64_t)b + m > n_slots) {
+        atomicOr(&flags[kFlagBadSlot], 4);
+        return;
+    }
+    for (int i = 1; i < m; ++i) {
+        const int key = perm[b + i];
+        const int val = src_of_slot[b + i];
+        int j = i - 1;
+        while (j >= 0 && perm[b + j] > key) {
+            perm[b + j + 1] = perm[b + j];
+            src_of_slot[b + j + 1] = src_of_slot[b + j];
+            --j;
+        }
+        perm[b + j + 1] = key;
+        src_of_slot[b + j + 1] = val;
+    }
+}
+
+struct GatherArgs {
+    const DevReplica* rep;
+    const int* slice_rep;
+    const int* perm;          // new slot -> ID
+    const int* src_of_slot;
+    const double* pos;        // caller SoA
+    const double* vel;        // caller SoA (may be null)
+    const double* charges;    // caller order (may be null)
+    const double4* xs_old;
+    const double* vs_old;
+    int64_t n;
+    int64_t n_src;
+    int64_t n_slots;
+    int* flags;
+    double4* xs;
+    double* vs;               // may be null
+    double* xb;               // positions at the build, [3][n_slots] (skin monitor)
+    int* slot_of_id;
+};
+
+template <int SRC, bool VEL>
+__global__ __launch_bounds__(256) void k_gather(GatherArgs a)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= a.n_slots) return;
+    const int id = a.perm[s];
+    if (id < 0) {
+        a.xs[s] = make_double4(0.0, 0.0, 0.0, 0.0);
+        if (VEL) {
+            a.vs[s] = 0.0;
+            a.vs[a.n_slots + s] = 0.0;
+            a.vs[2 * a.n_slots + s] = 0.0;
+        }
+        return;
+    }
+    const DevReplica& R = a.rep[a.slice_rep[s >> 6]];
+    const int src = a.src_of_slot[s];
+    if (src < 0 || src >= a.n_src) {
+        atomicOr(&a.flags[kFlagBadSlot], 8);
+        return;
+    }
+    double x[3];
+    double q;
+    if (SRC == kSrcCaller) {
+        x[0] = a.pos[src];
+        x[1] = a.pos[a.n + src];
+        x[2] = a.pos[2 * a.n + src];
+        q = a.charges ? a.charges[id] : 0.0;
+    } else {
+        const double4 p = a.xs_old[src];
+        x[0] = p.x;
+        x[1] = p.y;
+        x[2] = p.z;
+        q = p.w;
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        x[d] = isfinite(x[d]) ? wrap_coord(x[d], R.L[d], R.inv[d]) : 0.0;
+        a.xb[d * a.n_slots + s] = x[d];
+    }
+    a.xs[s] = make_double4(x[0], x[1], x[2], q);
+    if (VEL) {
+        if (SRC == kSrcCaller) {
+            a.vs[s] = a.vel[src];
+            a.vs[a.n_slots + s] = a.vel[a.n + src];
+            a.vs[2 * a.n_slots + s] = a.vel[2 * a.n + src];
+        } else {
+            a.vs[s] = a.vs_old[src];
+            a.vs[a.n_slots + s] = a.vs_old[a.n_slots + src];
+            a.vs[2 * a.n_slots + s] = a.vs_old[2 * a.n_slots + src];
+        }
+    }
+    a.slot_of_id[id] = (int)s;
+}
+
+// ---------------------------------------------------------------------------
+// Core / shell / full list build.  One wavefront per centre cell: the lanes
+// walk the candidates of the 5x5x5 cell stencil (up to 50 runs of
+// consecutive slots, in increasing slot order) 64 at a time, and every
+// candidate is tested against each particle of the centre cell, whose
+// position is broadcast from a lane with readlane.  Ballot + mbcnt compaction
+// appends the accepted candidates to each row in candidate order, so rows
+// come out in slot order with no sort.
+struct BuildArgs {
+    const DevReplica* rep;
+    const int* cell_rep;
+    const int* cell_start;
+    const int* cell_count;
+    const double4* xs;
+    int64_t n_cells;
+    int64_t n_slots;
+    double thr_core, thr_shell_in, thr_out;  // squared distances
+    int cap_core, cap_shell, cap_full;
+    int* core;
+    int* shell;
+    int* full;
+    int* core_len;
+    int* shell_len;
+    int* full_len;
+    int* flags;
+};
+
+// Along one axis of nc cells, the stencil of cells within +-2 of c, sorted
+// by wrapped coordinate, as at most two runs [p0, p0+l0) and [p1, p1+l1).
+struct AxisRuns {
+    int p0, l0, p1, l1;
+};
+
+__device__ __forceinline__ AxisRuns axis_runs(int c, int nc)
+{
+    AxisRuns a;
+    if (nc <= 5) {
+        a.p0 = 0;
+        a.l0 = nc;
+        a.p1 = 0;
+        a.l1 = 0;
+        return a;
+    }
+    const int lo = c - 2, hi = c + 2;
+    if (lo >= 0 && hi <= nc - 1) {
+        a.p0 = lo;
+        a.l0 = 5;
+        a.p1 = 0;
+        a.l1 = 0;
+    } else if (lo < 0) {
+        a.p0 = 0;
+        a.l0 = hi + 1;
+        a.p1 = lo + nc;
+        a.l1 = nc - (lo + nc);
+    } else {
+        a.p0 = 0;
+        a.l0 = hi - nc + 1;
+        a.p1 = lo;
+        a.l1 = nc - lo;
+    }
+    return a;
+}
+
+__device__ __forceinline__ int axis_cell(const AxisRuns& a, int k)
+{
+    return k < a.l0 ? a.p0 + k : a.p1 + (k - a.l0);
+}
+
+__device__ __forceinline__ double bcast(double v, int lane)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ int shfl_i32(int v, int src_lane)
+{
+    return __builtin_amdgcn_ds_bpermute(src_lane << 2, v);
+}
+
+template <bool COUNT_ONLY, bool WC, bool WS, bool WF>
+__global__ __launch_bounds__(256) void k_build(BuildArgs a)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t cell = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (cell >= a.n_cells) return;
+    const int m = a.cell_count[cell];
+    if (m == 0) return;
+    const int i0 = a.cell_start[cell];
+    if (i0 < 0 || (int64_t)i0 + m > a.n_slots) {
+        if ((threadIdx.x & 63) == 0) atomicOr(&a.flags[kFlagBadSlot], 2);
+        return;
+    }
+    const DevReplica& R = a.rep[a.cell_rep[cell]];
+    const int64_t lc = cell - R.cell_base;
+    const int cx = (int)(lc % R.nc[0]);
+    const int cy = (int)((lc / R.nc[0]) % R.nc[1]);
+    const int cz = (int)(lc / ((int64_t)R.nc[0] * R.nc[1]));
+    const AxisRuns ax = axis_runs(cx, R.nc[0]);
+    const AxisRuns ay = axis_runs(cy, R.nc[1]);
+    const AxisRuns az = axis_runs(cz, R.nc[2]);
+    const int ny_s = ay.l0 + ay.l1;
+    const int nz_s = az.l0 + az.l1;
+
+    // lane q describes run q = ((z * ny_s) + y) * 2 + xrun of the stencil
+    int rstart = 0, rlen = 0;
+    {
+        const int q = lane;
+        const int zi = q / (2 * ny_s);
+        const int yi = (q >> 1) % ny_s;
+        const int xr = q & 1;
+        if (zi < nz_s) {
+            const int zc = axis_cell(az, zi);
+            const int yc = axis_cell(ay, yi);
+            const int px = xr == 0 ? ax.p0 : ax.p1;
+            const int lx = xr == 0 ? ax.l0 : ax.l1;
+            if (lx > 0) {
+                const int64_t row = R.cell_base + ((int64_t)zc * R.nc[1] + yc) * R.nc[0];
+                const int64_t c0 = row + px;
+                const int64_t c1 = row + px + lx - 1;
+                rstart = a.cell_start[c0];
+                rlen = a.cell_start[c1] + a.cell_count[c1] - rstart;
+            }
+        }
+    }
+    // exclusive prefix of the run lengths: non-decreasing over the lanes, so
+    // the largest lane with rpre <= f owns candidate f (empty runs share the
+    // prefix of the next non-empty run and lose the search to it)
+    const int incl = wave_incl_scan(rlen);
+    const int total = __builtin_amdgcn_readlane(incl, 63);
+    const int rpre = incl - rlen;
+
+    for (int g0 = 0; g0 < m; g0 += 64) {
+        const int mg = min(64, m - g0);
+        double4 xc = make_double4(0.0, 0.0, 0.0, 0.0);
+        if (lane < mg) xc = a.xs[i0 + g0 + lane];
+        int cnt_c = 0, cnt_s = 0, cnt_f = 0;
+        for (int base = 0; base < total; base += 64) {
+            const int f = base + lane;
+            // largest run q with rpre[q] <= f
+            int q = 0;
+#pragma unroll
+            for (int step = 32; step > 0; step >>= 1) {
+                const int t = shfl_i32(rpre, q + step);
+                if (t <= f) q += step;
+            }
+            const int qs = shfl_i32(rstart, q);
+            const int qp = shfl_i32(rpre, q);
+            const int j = qs + (f - qp);
+            const bool valid = f < total && j >= 0 && (int64_t)j < a.n_slots;
+            double4 xj = make_double4(0.0, 0.0, 0.0, 0.0);
+            if (valid) xj = a.xs[j];
+            for (int ii = 0; ii < mg; ++ii) {
+                const int islot = i0 + g0 + ii;
+                const double4 xi = make_double4(bcast(xc.x, ii), bcast(xc.y, ii), bcast(xc.z, ii), 0.0);
+                const Delta d = delta(xi, xj, R);
+                const bool ok = valid && j != islot;
+                if (WC) {
+                    const bool in = ok && d.r2 < a.thr_core;
+                    const uint64_t mk = __ballot(in);
+                    const int b0 = __builtin_amdgcn_readlane(cnt_c, ii);
+                    if (!COUNT_ONLY && in) {
+                        const int p = b0 + (int)mbcnt(mk);
+                        if (p < a.cap_core) a.core[ell(islot, p, a.cap_core)] = j;
+                    }
+                    if (lane == ii) cnt_c += __popcll(mk);
+                }
+                if (WS) {
+                    const bool in = ok && d.r2 >= a.thr_shell_in && d.r2 < a.thr_out;
+                    const uint64_t mk = __ballot(in);
+                    const int b0 = __builtin_amdgcn_readlane(cnt_s, ii);
+                    if (!COUNT_ONLY && in) {
+                        const int p = b0 + (int)mbcnt(mk);
+                        if (p < a.cap_shell) a.shell[ell(islot, p, a.cap_shell)] = j;
+                    }
+                    if (lane == ii) cnt_s += __popcll(mk);
+                }
+                if (WF) {
+                    const bool in = ok && d.r2 < a.thr_out;
+                    const uint64_t mk = __ballot(in);
+                    const int b0 = __builtin_amdgcn_readlane(cnt_f, ii);
+                    if (!COUNT_ONLY && in) {
+                        const int p = b0 + (int)mbcnt(mk);
+                        if (p < a.cap_full) a.full[ell(islot, p, a.cap_full)] = j;
+                    }
+                    if (lane == ii) cnt_f += __popcll(mk);
+                }
+            }
+        }
+        const bool mine = lane < mg;
+        const int islot = i0 + g0 + lane;
+        if (WC) {
+            if (mine && !COUNT_ONLY) a.core_len[islot] = min(cnt_c, a.cap_core);
+            const int mx = wave_max(mine ? cnt_c : 0);
+            if (lane == 0) {
+                atomicMax(&a.flags[kFlagMaxCore], mx);
+                if (!COUNT_ONLY && mx > a.cap_core) atomicOr(&a.flags[kFlagOverflow], 1);
+            }
+        }
+        if (WS) {
+            if (mine && !COUNT_ONLY) a.shell_len[islot] = min(cnt_s, a.cap_shell);
+            const int mx = wave_max(mine ? cnt_s : 0);
+            if (lane == 0) {
+                atomicMax(&a.flags[kFlagMaxShell], mx);
+                if (!COUNT_ONLY && mx > a.cap_shell) atomicOr(&a.flags[kFlagOverflow], 1);
+            }
+        }
+        if (WF) {
+            if (mine && !COUNT_ONLY) a.full_len[islot] = min(cnt_f, a.cap_full);
+            const int mx = wave_max(mine ? cnt_f : 0);
+            if (lane == 0) {
+                atomicMax(&a.flags[kFlagMaxFull], mx);
+                if (!COUNT_ONLY && mx > a.cap_full) atomicOr(&a.flags[kFlagOverflow], 1);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Batch pre-draw: for steps step0 .. step0+K-1 the partners of every
+// particle's batch, gathered from its shell row (bit-identical to the draw
+// the inline force kernel makes).
+struct DrawArgs {
+    const DevReplica* rep;
+    const int* slice_rep;
+    const int* perm;
+    const int* shell;
+    const int* shell_len;
+    int cap_shell;
+    int64_t n_slots;
+    int64_t n_slices;
+    uint64_t seed;
+    uint64_t step0;
+    int K;
+    int P;
+    int* batch;  // [K][P][n_slots]
+};
+
+template <int PMAX>
+__global__ __launch_bounds__(256) void k_predraw(DrawArgs a)
+{
+    const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if ((slot >> 6) >= a.n_slices) return;
+    const int rep_id = a.slice_rep[slot >> 6];
+    const DevReplica& R = a.rep[rep_id];
+    if (slot - R.slot_base >= R.n) return;
+    const int n = a.shell_len[slot];
+    const uint32_t pid = (uint32_t)(a.perm[slot] - R.id_base);
+    const int P = a.P;
+    for (int rr = 0; rr < a.K; ++rr) {
+        int* out = a.batch + (int64_t)rr * P * a.n_slots + slot;
+        if (n <= P) {
+            for (int q = 0; q < n; ++q) out[(int64_t)q * a.n_slots] = a.shell[ell(slot, q, a.cap_shell)];
+        } else {
+            uint32_t S[PMAX];
+            floyd_draw<PMAX>(S, a.seed, pid, (uint32_t)(a.step0 + rr), (uint32_t)rep_id, P, n);
+#pragma unroll
+            for (int q = 0; q < PMAX; ++q)
+                if (q < P) out[(int64_t)q * a.n_slots] = a.shell[ell(slot, (int)S[q], a.cap_shell)];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Force kernel.  One lane per particle slot, one wavefront per slice of 64
+// cell-sorted particles.  Core rows are summed exactly (r < r_s); the shell
+// batch (drawn inline with Philox + Floyd, or pre-drawn) is summed over
+// r_s <= r < r_c and scaled by n_i/P.  Each wavefront also leaves its sums
+// of F, U and W for the per-replica reduction.
+struct ForceArgs {
+    const DevReplica* rep;
+    const int* slice_rep;
+    const int* perm;
+    const double4* xs;
+    const int* core;
+    const int* core_len;
+    int cap_core;
+    const int* shell;      // shell list (inline) or full list (full mode)
+    const int* shell_len;
+    int cap_shell;
+    const int* batch;      // pre-drawn: [P][n_slots] for this step
+    int64_t n_slots;
+    int64_t n_slices;
+    double rs2, rc2, uc;   // core radius^2, cut-off^2, LJ energy at the cut-off
+    double uce;            // erfc(alpha r_c)/r_c (energy shift per unit charge product)
+    double alpha;
+    uint64_t seed;
+    uint64_t step;
+    int P;
+    double* f;             // [3][n_slots]
+    double* partial;       // [5][n_slices]
+};
+
+template <int PREC, bool ERFC>
+__device__ __forceinline__ void pair_term(double r2, double qq, double alpha, double& fm, double& u)
+{
+    LJ<PREC>::eval(r2, fm, u);
+    if (ERFC) {
+        double fe, ue;
+        Erfc<PREC>::eval(r2, qq, alpha, fe, ue);
+        fm += fe;
+        u += ue;
+    }
+}
+
+template <int PREC, int MODE, bool ENERGY, bool ERFC, int PMAX>
+__global__ __launch_bounds__(256) void k_forces(ForceArgs a)
+{
+    __shared__ uint32_t s_pos[MODE == kShellInline ? PMAX * 256 : 1];
+    const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t slice = slot >> 6;
+    if (slice >= a.n_slices) return;
+    const int rep_id = a.slice_rep[slice];
+    const DevReplica& R = a.rep[rep_id];
+    const bool real = slot - R.slot_base < R.n;
+    double fx = 0.0, fy = 0.0, fz = 0.0, e = 0.0, w = 0.0;
+    if (real) {
+        const double4 xi = a.xs[slot];
+        const double cut_in = MODE == kShellNone ? a.rc2 : a.rs2;
+        {
+            const int len = a.core_len[slot];
+            for (int k = 0; k < len; ++k) {
+                const int j = a.core[ell(slot, k, a.cap_core)];
+                const double4 xj = a.xs[j];
+                const Delta d = delta(xi, xj, R);
+                if (d.r2 < cut_in) {
+                    double fm, u;
+                    pair_term<PREC, ERFC>(d.r2, xi.w * xj.w, a.alpha, fm, u);
+                    fx += fm * d.x;
+                    fy += fm * d.y;
+                    fz += fm * d.z;
+                    if (ENERGY) {
+                        e += u - (ERFC ? a.uc + xi.w * xj.w * a.uce : a.uc);
+                        w += fm * d.r2;
+                    }
+                }
+            }
+        }
+        if (MODE != kShellNone) {
+            const int n = a.shell_len[slot];
+            const int P = a.P;
+            const int cnt = n < P ? n : P;
+            const double scale = n > P ? (double)n / (double)P : 1.0;
+            if (MODE == kShellInline && n > P) {
+                uint32_t S[PMAX];
+                const uint32_t pid = (uint32_t)(a.perm[slot] - R.id_base);
+                floyd_draw<PMAX>(S, a.seed, pid, (uint32_t)a.step, (uint32_t)rep_id, P, n);
+#pragma unroll
+                for (int q = 0; q < PMAX; ++q) s_pos[q * 256 + threadIdx.x] = S[q];
+            }
+            double sx = 0.0, sy = 0.0, sz = 0.0, se = 0.0, sw = 0.0;
+            for (int m = 0; m < cnt; ++m) {
+                int j;
+                if (MODE == kShellInline) {
+                    const int k = n > P ? (int)s_pos[m * 256 + threadIdx.x] : m;
+                    j = a.shell[ell(slot, k, a.cap_shell)];
+                } else {
+                    j = a.batch[(int64_t)m * a.n_slots + slot];
+                }
+                const double4 xj = a.xs[j];
+                const Delta d = delta(xi, xj, R);
+                if (d.r2 >= a.rs2 && d.r2 < a.rc2) {
+                    double fm, u;
+                    pair_term<PREC, ERFC>(d.r2, xi.w * xj.w, a.alpha, fm, u);
+                    sx += fm * d.x;
+                    sy += fm * d.y;
+                    sz += fm * d.z;
+                    if (ENERGY) {
+                        se += u - (ERFC ? a.uc + xi.w * xj.w * a.uce : a.uc);
+                        sw += fm * d.r2;
+                    }
+                }
+            }
+            fx = fx + scale * sx;
+            fy = fy + scale * sy;
+            fz = fz + scale * sz;
+            if (ENERGY) {
+                e = 0.5 * (e + scale * se);
+                w = 0.5 * (w + scale * sw);
+            }
+        } else if (ENERGY) {
+            e = 0.5 * e;
+            w = 0.5 * w;
+        }
+    }
+    a.f[slot] = fx;
+    a.f[a.n_slots + slot] = fy;
+    a.f[2 * a.n_slots + slot] = fz;
+    const double tx = wave_sum(fx);
+    const double ty = wave_sum(fy);
+    const double tz = wave_sum(fz);
+    double te = 0.0, tw = 0.0;
+    if (ENERGY) {
+        te = wave_sum(e);
+        tw = wave_sum(w);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        a.partial[slice] = tx;
+        a.partial[a.n_slices + slice] = ty;
+        a.partial[2 * a.n_slices + slice] = tz;
+        a.partial[3 * a.n_slices + slice] = te;
+        a.partial[4 * a.n_slices + slice] = tw;
+    }
+}
+
+// Per-replica sums of the wavefront partials, in a fixed order (the result
+// does not depend on scheduling).  rep_sum[8r + q], q = Fx, Fy, Fz, U, W.
+__global__ __launch_bounds__(256) void k_reduce(const DevReplica* rep, const double* partial,
+                                               int64_t n_slices, double* rep_sum)
+{
+    __shared__ double lds[4];
+    const DevReplica& R = rep[blockIdx.x];
+    const int64_t s0 = R.slot_base >> 6;
+    const int64_t ns = (R.n + 63) >> 6;
+    for (int q = 0; q < 5; ++q) {
+        double acc = 0.0;
+        for (int64_t s = threadIdx.x; s < ns; s += blockDim.x) acc += partial[q * n_slices + s0 + s];
+        acc = wave_sum(acc);
+        if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = acc;
+        __syncthreads();
+        if (threadIdx.x == 0) rep_sum[8 * blockIdx.x + q] = ((lds[0] + lds[1]) + lds[2]) + lds[3];
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Velocity Verlet (unit mass) on the sorted state; F' = F - F_cor where
+// F_cor = (sum_i F_i)/N_r is the replica's average net force.
+//   first: v += h F';           x += dt v
+//   mid:   v += h F'; v += h F'; x += dt v   (end of one step + start of next)
+//   last:  v += h F'
+// The skin monitor flags a particle that moved more than skin/2 since the
+// last build.
+struct IntArgs {
+    const DevReplica* rep;
+    const int* slice_rep;
+    const double* rep_sum;
+    double4* xs;
+    double* vs;
+    const double* f;
+    const double* xb;
+    int64_t n_slots;
+    int64_t n_slices;
+    double h, dt;
+    int momentum_fix;
+    double half_skin2;
+    int* flags;
+};
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_integrate(IntArgs a)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if ((s >> 6) >= a.n_slices) return;
+    const int r = a.slice_rep[s >> 6];
+    const DevReplica& R = a.rep[r];
+    if (s - R.slot_base >= R.n) return;
+    double fc[3] = {0.0, 0.0, 0.0};
+    if (a.momentum_fix) {
+        const double nr = (double)R.n;
+        fc[0] = a.rep_sum[8 * r] / nr;
+        fc[1] = a.rep_sum[8 * r + 1] / nr;
+        fc[2] = a.rep_sum[8 * r + 2] / nr;
+    }
+    double v[3], F[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        v[d] = a.vs[d * a.n_slots + s];
+        F[d] = a.f[d * a.n_slots + s] - fc[d];
+        v[d] = v[d] + a.h * F[d];
+        if (MODE == kIntMid) v[d] = v[d] + a.h * F[d];
+        a.vs[d * a.n_slots + s] = v[d];
+    }
+    if (MODE != kIntLast) {
+        double4 x = a.xs[s];
+        x.x = x.x + a.dt * v[0];
+        x.y = x.y + a.dt * v[1];
+        x.z = x.z + a.dt * v[2];
+        a.xs[s] = x;
+        const double dx = x.x - a.xb[s];
+        const double dy = x.y - a.xb[a.n_slots + s];
+        const double dz = x.z - a.xb[2 * a.n_slots + s];
+        if (dx * dx + dy * dy + dz * dz > a.half_skin2) atomicOr(&a.flags[kFlagSkin], 1);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Caller-order I/O.
+struct IoArgs {
+    const DevReplica* rep;
+    const int* slice_rep;
+    const int* perm;
+    const double* rep_sum;
+    const double* charges;
+    int64_t n;
+    int64_t n_slots;
+    int64_t n_slices;
+    int momentum_fix;
+    double4* xs;
+    const double* vs;
+    const double* f;
+    const double* pos_in;
+    double* pos_out;
+    double* vel_out;
+    double* f_out;
+};
+
+// xs[slot] <- caller positions as given (no wrapping), for a force call.
+__global__ __launch_bounds__(256) void k_load_positions(IoArgs a)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= a.n_slots) return;
+    const int id = a.perm[s];
+    if (id < 0) return;
+    const double q = a.charges ? a.charges[id] : 0.0;
+    a.xs[s] = make_double4(a.pos_in[id], a.pos_in[a.n + id], a.pos_in[2 * a.n + id], q);
+}
+
+__global__ __launch_bounds__(256) void k_scatter_out(IoArgs a)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if ((s >> 6) >= a.n_slices) return;
+    const int id = a.perm[s];
+    if (id < 0) return;
+    const int r = a.slice_rep[s >> 6];
+    if (a.pos_out) {
+        const double4 x = a.xs[s];
+        a.pos_out[id] = x.x;
+        a.pos_out[a.n + id] = x.y;
+        a.pos_out[2 * a.n + id] = x.z;
+    }
+    if (a.vel_out) {
+        a.vel_out[id] = a.vs[s];
+        a.vel_out[a.n + id] = a.vs[a.n_slots + s];
+        a.vel_out[2 * a.n + id] = a.vs[2 * a.n_slots + s];
+    }
+    if (a.f_out) {
+        const double nr = (double)a.rep[r].n;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const double fc = a.momentum_fix ? a.rep_sum[8 * r + d] / nr : 0.0;
+            a.f_out[d * a.n + id] = a.f[d * a.n_slots + s] - fc;
+        }
+    }
+}
+
+__global__ void k_ev_out(const double* rep_sum, int nrep, double* ev)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrep) return;
+    ev[2 * r] = rep_sum[8 * r + 3];
+    ev[2 * r + 1] = rep_sum[8 * r + 4];
+}
+
+// Copies requested rows of a sliced-ELL list into CSR, partners as IDs.
+__global__ __launch_bounds__(256) void k_export_rows(const int64_t* rows, int64_t nrows,
+                                                     const int* slot_of_id, const int* perm,
+                                                     const int* list, const int* len, int cap,
+                                                     const int64_t* off, int* out)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nrows) return;
+    const int slot = slot_of_id[rows[k]];
+    const int l = len[slot];
+    const int64_t o = off[k];
+    const int64_t room = off[k + 1] - o;
+    for (int q = 0; q < l && q < room; ++q) out[o + q] = perm[list[ell(slot, q, cap)]];
+}
+
+__global__ __launch_bounds__(256) void k_row_counts(const int64_t* rows, int64_t nrows,
+                                                    const int* slot_of_id, const int* len,
+                                                    int64_t* counts)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nrows) return;
+    counts[k] = len ? len[slot_of_id[rows[k]]] : 0;
+}
+
+}  // namespace rbl

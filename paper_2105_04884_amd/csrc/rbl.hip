@@ -1,0 +1,1144 @@
+// Host runtime and C-ABI of librbl (see include/rbl.h).
+//
+// A context owns the cell-sorted particle state, the cell list, the sliced
+// ELL neighbour lists, the pre-drawn batches and the reduction buffers, all in
+// HBM.  Every call queues kernels on the context's stream; the only host
+// synchronisations are the capacity check after a list build and the flag
+// read-back at the end of rbl_step / rbl_sync.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/rbl.h"
+#include "kernels.h"
+
+using namespace rbl;
+
+namespace {
+
+thread_local std::string g_err;
+
+rbl_status fail(rbl_status s, const std::string& msg)
+{
+    g_err = msg;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                     \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return fail(e_ == hipErrorOutOfMemory ? RBL_E_NOMEM : RBL_E_HIP,              \
+                        std::string(#expr) + ": " + hipGetErrorString(e_));               \
+    } while (0)
+
+#define RBL_TRY(expr)                      \
+    do {                                   \
+        rbl_status s_ = (expr);            \
+        if (s_ < 0) return s_;             \
+    } while (0)
+
+constexpr int kBlock = 256;
+constexpr int kKinds = 7;
+enum { kKForceRbl = 0, kKForceFull = 1, kKBuild = 2, kKBin = 3, kKIntegrate = 4, kKReduce = 5,
+       kKPredraw = 6 };
+
+inline unsigned grid_for(int64_t n, int block = kBlock)
+{
+    return (unsigned)((n + block - 1) / block);
+}
+
+template <typename T>
+rbl_status dalloc(T** p, size_t count)
+{
+    *p = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc((void**)p, sizeof(T) * count);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return fail(e == hipErrorOutOfMemory ? RBL_E_NOMEM : RBL_E_HIP,
+                    std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    return RBL_OK;
+}
+
+template <typename T>
+void dfree(T*& p)
+{
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+
+}  // namespace
+
+struct rbl_ctx {
+    rbl_config cfg;
+    hipStream_t stream = nullptr;
+    int R = 1;
+    int64_t n = 0, n_slots = 0, n_slices = 0;
+    std::vector<int64_t> id_base, rep_n, slot_base;
+
+    // geometry of the last build
+    bool built = false;
+    int built_mask = 0;
+    double r_s = 0, r_c = 0;
+    std::vector<DevReplica> h_rep;
+    int64_t n_cells = 0, cells_alloc = 0;
+
+    DevReplica* d_rep = nullptr;
+    int* d_id_rep = nullptr;
+    int* d_slice_rep = nullptr;
+    int* d_cell_rep = nullptr;
+    int* d_cell_count = nullptr;
+    int* d_cell_start = nullptr;
+    int* d_tile_sum = nullptr;
+    int* d_cell_of_src = nullptr;
+    int* d_rank_of_src = nullptr;
+    int* d_src_of_slot = nullptr;
+    int* d_perm[2] = {nullptr, nullptr};
+    int cur = 0;
+    int* d_slot_of_id = nullptr;
+    double4* d_xs[2] = {nullptr, nullptr};
+    double* d_vs[2] = {nullptr, nullptr};
+    double* d_xb = nullptr;
+    double* d_f = nullptr;
+
+    int cap[3] = {0, 0, 0};
+    int* d_list[3] = {nullptr, nullptr, nullptr};
+    int* d_len[3] = {nullptr, nullptr, nullptr};
+
+    int* d_batch = nullptr;
+    size_t batch_alloc = 0;
+
+    double* d_partial = nullptr;
+    double* d_rep_sum = nullptr;
+    int* d_flags = nullptr;
+    int h_flags[kNumFlags];
+
+    bool profiling = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending[kKinds];
+    std::vector<hipEvent_t> ev_pool;
+    int64_t stat_launches[kKinds] = {0};
+    double stat_ms[kKinds] = {0};
+
+    int* cur_perm() { return d_perm[cur]; }
+    double4* cur_xs() { return d_xs[cur]; }
+    double* cur_vs() { return d_vs[cur]; }
+};
+
+namespace {
+
+hipEvent_t take_event(rbl_ctx* c)
+{
+    if (!c->ev_pool.empty()) {
+        hipEvent_t e = c->ev_pool.back();
+        c->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Runs `fn` (which queues one kernel) between two events when profiling.
+template <typename F>
+rbl_status timed(rbl_ctx* c, int kind, F&& fn)
+{
+    hipEvent_t a = nullptr, b = nullptr;
+    if (c->profiling) {
+        a = take_event(c);
+        b = take_event(c);
+        if (a && b) HIP_TRY(hipEventRecord(a, c->stream));
+    }
+    fn();
+    HIP_TRY(hipGetLastError());
+    if (c->profiling && a && b) {
+        HIP_TRY(hipEventRecord(b, c->stream));
+        c->ev_pending[kind].push_back({a, b});
+    }
+    return RBL_OK;
+}
+
+rbl_status resolve_events(rbl_ctx* c)
+{
+    for (int k = 0; k < kKinds; ++k) {
+        for (auto& pr : c->ev_pending[k]) {
+            HIP_TRY(hipEventSynchronize(pr.second));
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, pr.first, pr.second));
+            c->stat_ms[k] += ms;
+            c->stat_launches[k] += 1;
+            c->ev_pool.push_back(pr.first);
+            c->ev_pool.push_back(pr.second);
+        }
+        c->ev_pending[k].clear();
+    }
+    return RBL_OK;
+}
+
+rbl_status fill_i32(rbl_ctx* c, int* p, int64_t n, int v)
+{
+    if (n <= 0) return RBL_OK;
+    k_fill_i32<<<grid_for(n), kBlock, 0, c->stream>>>(p, n, v);
+    HIP_TRY(hipGetLastError());
+    return RBL_OK;
+}
+
+rbl_status read_flags(rbl_ctx* c)
+{
+    HIP_TRY(hipMemcpyAsync(c->h_flags, c->d_flags, sizeof(int) * kNumFlags, hipMemcpyDeviceToHost,
+                           c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return RBL_OK;
+}
+
+rbl_status clear_flags(rbl_ctx* c) { return fill_i32(c, c->d_flags, kNumFlags, 0); }
+
+// Clears only the list-capacity flags (overflow and longest rows), keeping
+// the error flags raised by the binning of the same build.
+rbl_status clear_list_flags(rbl_ctx* c) { return fill_i32(c, c->d_flags, kFlagMaxFull + 1, 0); }
+
+// ---------------------------------------------------------------------------
+// geometry
+
+rbl_status setup_geometry(rbl_ctx* c, const double* box, double r_s, double r_c)
+{
+    const double skin = c->cfg.skin;
+    const double reach = r_c + skin;
+    std::vector<DevReplica> reps(c->R);
+    int64_t cell_base = 0;
+    for (int r = 0; r < c->R; ++r) {
+        DevReplica& d = reps[r];
+        std::memset(&d, 0, sizeof(d));
+        // cells of edge >= (r_c + skin)/2 with a small margin, so that any pair
+        // closer than r_c + skin lies within two cells along every axis
+        const double w = 0.5 * (r_c + skin) * 1.000001;
+        int64_t ncell = 1;
+        for (int a = 0; a < 3; ++a) {
+            const double L = box[3 * r + a];
+            if (!(std::isfinite(L) && L > 2.0 * reach))
+                return fail(RBL_E_BOX, "box edge " + std::to_string(L) + " of replica " +
+                                           std::to_string(r) + " must exceed 2 (r_c + skin) = " +
+                                           std::to_string(2.0 * reach));
+            double nc = std::floor(L / w);
+            if (nc < 1.0) nc = 1.0;
+            if (nc > 1 << 20) return fail(RBL_E_BOX, "box too large for the cell grid");
+            d.L[a] = L;
+            d.inv[a] = 1.0 / L;
+            d.nc[a] = (int)nc;
+            d.cscale[a] = (double)d.nc[a] / L;
+            ncell *= d.nc[a];
+        }
+        d.id_base = c->id_base[r];
+        d.n = c->rep_n[r];
+        d.slot_base = c->slot_base[r];
+        d.cell_base = cell_base;
+        cell_base += ncell;
+    }
+    if (cell_base > (int64_t)1 << 30) return fail(RBL_E_BOX, "too many cells");
+    c->n_cells = cell_base;
+    if (c->n_cells > c->cells_alloc) {
+        dfree(c->d_cell_rep);
+        dfree(c->d_cell_count);
+        dfree(c->d_cell_start);
+        dfree(c->d_tile_sum);
+        RBL_TRY(dalloc(&c->d_cell_rep, c->n_cells));
+        RBL_TRY(dalloc(&c->d_cell_count, c->n_cells));
+        RBL_TRY(dalloc(&c->d_cell_start, c->n_cells + 1));
+        RBL_TRY(dalloc(&c->d_tile_sum, (c->n_cells + kScanTile - 1) / kScanTile + 1));
+        c->cells_alloc = c->n_cells;
+    }
+    if ((c->n_cells + kScanTile - 1) / kScanTile > 1024 * kScanPerThread)
+        return fail(RBL_E_BOX, "cell grid exceeds the scan capacity");
+    bool same = c->h_rep.size() == reps.size();
+    for (size_t r = 0; same && r < reps.size(); ++r)
+        same = std::memcmp(&reps[r], &c->h_rep[r], sizeof(DevReplica)) == 0;
+    if (!same) {
+        std::vector<int> cell_rep(c->n_cells);
+        for (int r = 0; r < c->R; ++r) {
+            const int64_t nc = (int64_t)reps[r].nc[0] * reps[r].nc[1] * reps[r].nc[2];
+            std::fill(cell_rep.begin() + reps[r].cell_base, cell_rep.begin() + reps[r].cell_base + nc, r);
+        }
+        HIP_TRY(hipMemcpyAsync(c->d_rep, reps.data(), sizeof(DevReplica) * c->R, hipMemcpyHostToDevice,
+                               c->stream));
+        HIP_TRY(hipMemcpyAsync(c->d_cell_rep, cell_rep.data(), sizeof(int) * c->n_cells,
+                               hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        c->h_rep = reps;
+    }
+    c->r_s = r_s;
+    c->r_c = r_c;
+    return RBL_OK;
+}
+
+struct Thresholds {
+    double core, shell_in, out, rs2, rc2, uc, uce;
+};
+
+Thresholds thresholds(const rbl_ctx* c)
+{
+    Thresholds t;
+    const double skin = c->cfg.skin;
+    const double a = c->r_s + skin;
+    double b = c->r_s - skin;
+    if (b < 0.0) b = 0.0;
+    const double o = c->r_c + skin;
+    t.core = a * a;
+    t.shell_in = b * b;
+    t.out = o * o;
+    t.rs2 = c->r_s * c->r_s;
+    t.rc2 = c->r_c * c->r_c;
+    t.uc = 0.0;
+    t.uce = 0.0;
+    if (c->cfg.shift) {
+        const double r2i = 1.0 / t.rc2;
+        const double sr6 = r2i * r2i * r2i;
+        t.uc = 4.0 * sr6 * (sr6 - 1.0);
+        // erfc(alpha r)/r at the cut-off, per unit charge product
+        if (c->cfg.pair == RBL_PAIR_LJ_ERFC) t.uce = std::erfc(c->cfg.alpha * c->r_c) / c->r_c;
+    }
+    return t;
+}
+
+// ---------------------------------------------------------------------------
+// binning: histogram, scan, scatter, per-cell ID sort, gather into new buffers
+
+template <int SRC>
+rbl_status bin_particles(rbl_ctx* c, const double* pos, const double* vel, bool with_vel)
+{
+    const int nxt = 1 - c->cur;
+    BinArgs b;
+    b.rep = c->d_rep;
+    b.id_rep = c->d_id_rep;
+    b.slice_rep = c->d_slice_rep;
+    b.pos = pos;
+    b.xs = c->cur_xs();
+    b.perm_old = c->cur_perm();
+    b.n = c->n;
+    b.n_src = SRC == kSrcCaller ? c->n : c->n_slots;
+    b.cell_of_src = c->d_cell_of_src;
+    b.rank_of_src = c->d_rank_of_src;
+    b.cell_count = c->d_cell_count;
+    b.flags = c->d_flags;
+    const int64_t ntiles = (c->n_cells + kScanTile - 1) / kScanTile;
+    RBL_TRY(timed(c, kKBin, [&] {
+        k_fill_i32<<<grid_for(c->n_cells), kBlock, 0, c->stream>>>(c->d_cell_count, c->n_cells, 0);
+    }));
+    RBL_TRY(timed(c, kKBin, [&] { k_bin_count<SRC><<<grid_for(b.n_src), kBlock, 0, c->stream>>>(b); }));
+    RBL_TRY(timed(c, kKBin, [&] {
+        k_scan_tiles<<<(unsigned)ntiles, kScanBlock, 0, c->stream>>>(c->d_cell_count, c->n_cells,
+                                                                     c->d_tile_sum);
+    }));
+    RBL_TRY(timed(c, kKBin, [&] {
+        k_scan_tile_sums<<<1, 1024, 0, c->stream>>>(c->d_tile_sum, (int)ntiles);
+    }));
+    RBL_TRY(timed(c, kKBin, [&] {
+        k_scan_final<<<(unsigned)ntiles, kScanBlock, 0, c->stream>>>(
+            c->d_cell_count, c->n_cells, c->d_tile_sum, c->d_cell_rep, c->d_rep, c->d_cell_start);
+    }));
+    RBL_TRY(timed(c, kKBin, [&] {
+        k_bin_scatter<SRC><<<grid_for(b.n_src), kBlock, 0, c->stream>>>(
+            b, c->d_cell_start, c->d_perm[nxt], c->d_src_of_slot, c->n_slots);
+    }));
+    RBL_TRY(timed(c, kKBin, [&] {
+        k_cell_sort<<<grid_for(c->n_cells), kBlock, 0, c->stream>>>(
+            c->d_cell_start, c->d_cell_count, c->n_cells, c->n_slots, c->d_perm[nxt],
+            c->d_src_of_slot, c->d_flags);
+    }));
+    GatherArgs g;
+    g.rep = c->d_rep;
+    g.slice_rep = c->d_slice_rep;
+    g.perm = c->d_perm[nxt];
+    g.src_of_slot = c->d_src_of_slot;
+    g.pos = pos;
+    g.vel = vel;
+    g.charges = c->cfg.charges;
+    g.xs_old = c->cur_xs();
+    g.vs_old = c->cur_vs();
+    g.n = c->n;
+    g.n_src = b.n_src;
+    g.n_slots = c->n_slots;
+    g.flags = c->d_flags;
+    g.xs = c->d_xs[nxt];
+    g.vs = c->d_vs[nxt];
+    g.xb = c->d_xb;
+    g.slot_of_id = c->d_slot_of_id;
+    RBL_TRY(timed(c, kKBin, [&] {
+        if (with_vel)
+            k_gather<SRC, true><<<grid_for(c->n_slots), kBlock, 0, c->stream>>>(g);
+        else
+            k_gather<SRC, false><<<grid_for(c->n_slots), kBlock, 0, c->stream>>>(g);
+    }));
+    c->cur = nxt;
+    return RBL_OK;
+}
+
+// ---------------------------------------------------------------------------
+// list build
+
+BuildArgs build_args(rbl_ctx* c)
+{
+    const Thresholds t = thresholds(c);
+    BuildArgs a;
+    a.rep = c->d_rep;
+    a.cell_rep = c->d_cell_rep;
+    a.cell_start = c->d_cell_start;
+    a.cell_count = c->d_cell_count;
+    a.xs = c->cur_xs();
+    a.n_cells = c->n_cells;
+    a.n_slots = c->n_slots;
+    a.thr_core = t.core;
+    a.thr_shell_in = t.shell_in;
+    a.thr_out = t.out;
+    a.cap_core = c->cap[0];
+    a.cap_shell = c->cap[1];
+    a.cap_full = c->cap[2];
+    a.core = c->d_list[0];
+    a.shell = c->d_list[1];
+    a.full = c->d_list[2];
+    a.core_len = c->d_len[0];
+    a.shell_len = c->d_len[1];
+    a.full_len = c->d_len[2];
+    a.flags = c->d_flags;
+    return a;
+}
+
+template <bool COUNT_ONLY>
+void launch_build(rbl_ctx* c, const BuildArgs& a, int mask)
+{
+    const unsigned g = grid_for(c->n_cells, 4);
+    const bool wc = mask & RBL_LIST_CORE, ws = mask & RBL_LIST_SHELL, wf = mask & RBL_LIST_FULL;
+#define RBL_B(C, S, F) k_build<COUNT_ONLY, C, S, F><<<g, kBlock, 0, c->stream>>>(a)
+    if (wc && ws && wf) RBL_B(true, true, true);
+    else if (wc && ws) RBL_B(true, true, false);
+    else if (wc && wf) RBL_B(true, false, true);
+    else if (ws && wf) RBL_B(false, true, true);
+    else if (wc) RBL_B(true, false, false);
+    else if (ws) RBL_B(false, true, false);
+    else RBL_B(false, false, true);
+#undef RBL_B
+}
+
+rbl_status ensure_list_storage(rbl_ctx* c, int q, int need)
+{
+    const double f = c->cfg.capacity_factor > 1.0 ? c->cfg.capacity_factor : 1.0;
+    int cap = (int)std::ceil(need * f) + 8;
+    cap = (cap + 3) & ~3;
+    if (cap <= c->cap[q] && c->d_list[q]) return RBL_OK;
+    dfree(c->d_list[q]);
+    c->cap[q] = 0;
+    RBL_TRY(dalloc(&c->d_list[q], (size_t)c->n_slots * cap));
+    c->cap[q] = cap;
+    return RBL_OK;
+}
+
+// Builds the lists in `mask` at the current sorted positions.  The first
+// build of a list (or one that overflowed) runs a counting pass, sizes the
+// rows to the longest one times capacity_factor, and fills.
+rbl_status build_lists(rbl_ctx* c, int mask)
+{
+    for (int q = 0; q < 3; ++q)
+        if ((mask >> q) & 1)
+            if (!c->d_len[q]) RBL_TRY(dalloc(&c->d_len[q], c->n_slots));
+    bool need_count = false;
+    for (int q = 0; q < 3; ++q)
+        if (((mask >> q) & 1) && c->cap[q] == 0) need_count = true;
+    for (int attempt = 0; attempt < 3; ++attempt) {
+        RBL_TRY(clear_list_flags(c));
+        if (need_count) {
+            BuildArgs a = build_args(c);
+            RBL_TRY(timed(c, kKBuild, [&] { launch_build<true>(c, a, mask); }));
+            RBL_TRY(read_flags(c));
+            if (c->h_flags[kFlagBadSlot]) return fail(RBL_E_HIP, "inconsistent cell binning");
+            for (int q = 0; q < 3; ++q)
+                if ((mask >> q) & 1) RBL_TRY(ensure_list_storage(c, q, c->h_flags[kFlagMaxCore + q]));
+            RBL_TRY(clear_list_flags(c));
+        }
+        BuildArgs a = build_args(c);
+        RBL_TRY(timed(c, kKBuild, [&] { launch_build<false>(c, a, mask); }));
+        RBL_TRY(read_flags(c));
+        if (c->h_flags[kFlagBadSlot]) return fail(RBL_E_HIP, "inconsistent cell binning");
+        if (c->h_flags[kFlagNonfinite]) {
+            c->built = false;
+            return fail(RBL_E_NONFINITE, "non-finite particle position at list build");
+        }
+        if (!c->h_flags[kFlagOverflow]) {
+            c->built_mask = mask;
+            return RBL_OK;
+        }
+        for (int q = 0; q < 3; ++q)
+            if ((mask >> q) & 1) RBL_TRY(ensure_list_storage(c, q, c->h_flags[kFlagMaxCore + q]));
+        need_count = false;
+    }
+    return fail(RBL_E_CAPACITY, "neighbour rows kept overflowing their capacity");
+}
+
+// ---------------------------------------------------------------------------
+// forces
+
+ForceArgs force_args(rbl_ctx* c, int P, uint64_t seed, uint64_t step, bool full)
+{
+    const Thresholds t = thresholds(c);
+    ForceArgs a;
+    a.rep = c->d_rep;
+    a.slice_rep = c->d_slice_rep;
+    a.perm = c->cur_perm();
+    a.xs = c->cur_xs();
+    a.core = full ? c->d_list[2] : c->d_list[0];
+    a.core_len = full ? c->d_len[2] : c->d_len[0];
+    a.cap_core = full ? c->cap[2] : c->cap[0];
+    a.shell = c->d_list[1];
+    a.shell_len = c->d_len[1];
+    a.cap_shell = c->cap[1];
+    a.batch = nullptr;
+    a.n_slots = c->n_slots;
+    a.n_slices = c->n_slices;
+    a.rs2 = t.rs2;
+    a.rc2 = t.rc2;
+    a.uc = t.uc;
+    a.uce = t.uce;
+    a.alpha = c->cfg.alpha;
+    a.seed = seed;
+    a.step = step;
+    a.P = P;
+    a.f = c->d_f;
+    a.partial = c->d_partial;
+    return a;
+}
+
+template <int PREC, int MODE, bool EN, bool ERFC>
+void launch_force_p(rbl_ctx* c, const ForceArgs& a)
+{
+    const unsigned g = grid_for(c->n_slots);
+    if (MODE == kShellInline) {
+        if (a.P <= 16) k_forces<PREC, MODE, EN, ERFC, 16><<<g, kBlock, 0, c->stream>>>(a);
+        else k_forces<PREC, MODE, EN, ERFC, 32><<<g, kBlock, 0, c->stream>>>(a);
+    } else {
+        k_forces<PREC, MODE, EN, ERFC, 1><<<g, kBlock, 0, c->stream>>>(a);
+    }
+}
+
+template <int MODE>
+void launch_force(rbl_ctx* c, const ForceArgs& a, bool energy)
+{
+    const bool mixed = c->cfg.precision == RBL_PREC_MIXED;
+    const bool erfc = c->cfg.pair == RBL_PAIR_LJ_ERFC;
+#define RBL_F(P, E, X) launch_force_p<P, MODE, E, X>(c, a)
+    if (!mixed && !energy && !erfc) RBL_F(kFP64, false, false);
+    else if (!mixed && energy && !erfc) RBL_F(kFP64, true, false);
+    else if (mixed && !energy && !erfc) RBL_F(kMixed, false, false);
+    else if (mixed && energy && !erfc) RBL_F(kMixed, true, false);
+    else if (!mixed && !energy) RBL_F(kFP64, false, true);
+    else if (!mixed) RBL_F(kFP64, true, true);
+    else if (!energy) RBL_F(kMixed, false, true);
+    else RBL_F(kMixed, true, true);
+#undef RBL_F
+}
+
+rbl_status ensure_batch(rbl_ctx* c, int K, int P)
+{
+    const size_t need = (size_t)K * P * c->n_slots;
+    if (need <= c->batch_alloc) return RBL_OK;
+    dfree(c->d_batch);
+    c->batch_alloc = 0;
+    RBL_TRY(dalloc(&c->d_batch, need));
+    c->batch_alloc = need;
+    return RBL_OK;
+}
+
+rbl_status predraw(rbl_ctx* c, int P, uint64_t seed, uint64_t step0, int K)
+{
+    RBL_TRY(ensure_batch(c, K, P));
+    DrawArgs d;
+    d.rep = c->d_rep;
+    d.slice_rep = c->d_slice_rep;
+    d.perm = c->cur_perm();
+    d.shell = c->d_list[1];
+    d.shell_len = c->d_len[1];
+    d.cap_shell = c->cap[1];
+    d.n_slots = c->n_slots;
+    d.n_slices = c->n_slices;
+    d.seed = seed;
+    d.step0 = step0;
+    d.K = K;
+    d.P = P;
+    d.batch = c->d_batch;
+    const unsigned g = grid_for(c->n_slots);
+    return timed(c, kKPredraw, [&] {
+        if (P <= 16) k_predraw<16><<<g, kBlock, 0, c->stream>>>(d);
+        else if (P <= 32) k_predraw<32><<<g, kBlock, 0, c->stream>>>(d);
+        else if (P <= 64) k_predraw<64><<<g, kBlock, 0, c->stream>>>(d);
+        else k_predraw<128><<<g, kBlock, 0, c->stream>>>(d);
+    });
+}
+
+rbl_status reduce(rbl_ctx* c)
+{
+    return timed(c, kKReduce, [&] {
+        k_reduce<<<c->R, kBlock, 0, c->stream>>>(c->d_rep, c->d_partial, c->n_slices, c->d_rep_sum);
+    });
+}
+
+// RBL force at the current sorted positions (raw; per-replica sums reduced).
+// batch_rel >= 0 selects pre-drawn batches of that relative step.
+rbl_status rbl_force_sorted(rbl_ctx* c, int P, uint64_t seed, uint64_t step, int batch_rel,
+                            bool energy)
+{
+    ForceArgs a = force_args(c, P, seed, step, false);
+    if (batch_rel >= 0) {
+        a.batch = c->d_batch + (size_t)batch_rel * P * c->n_slots;
+        RBL_TRY(timed(c, kKForceRbl, [&] { launch_force<kShellPredraw>(c, a, energy); }));
+    } else {
+        RBL_TRY(timed(c, kKForceRbl, [&] { launch_force<kShellInline>(c, a, energy); }));
+    }
+    return reduce(c);
+}
+
+rbl_status full_force_sorted(rbl_ctx* c, bool energy)
+{
+    ForceArgs a = force_args(c, 0, 0, 0, true);
+    RBL_TRY(timed(c, kKForceFull, [&] { launch_force<kShellNone>(c, a, energy); }));
+    return reduce(c);
+}
+
+IoArgs io_args(rbl_ctx* c, bool momentum_fix)
+{
+    IoArgs io;
+    io.rep = c->d_rep;
+    io.slice_rep = c->d_slice_rep;
+    io.perm = c->cur_perm();
+    io.rep_sum = c->d_rep_sum;
+    io.charges = c->cfg.charges;
+    io.n = c->n;
+    io.n_slots = c->n_slots;
+    io.n_slices = c->n_slices;
+    io.momentum_fix = momentum_fix ? 1 : 0;
+    io.xs = c->cur_xs();
+    io.vs = c->cur_vs();
+    io.f = c->d_f;
+    io.pos_in = nullptr;
+    io.pos_out = nullptr;
+    io.vel_out = nullptr;
+    io.f_out = nullptr;
+    return io;
+}
+
+rbl_status emit_ev(rbl_ctx* c, double* ev)
+{
+    if (!ev) return RBL_OK;
+    k_ev_out<<<grid_for(c->R), kBlock, 0, c->stream>>>(c->d_rep_sum, c->R, ev);
+    HIP_TRY(hipGetLastError());
+    return RBL_OK;
+}
+
+rbl_status integrate(rbl_ctx* c, int mode, double dt, bool momentum_fix)
+{
+    IntArgs a;
+    a.rep = c->d_rep;
+    a.slice_rep = c->d_slice_rep;
+    a.rep_sum = c->d_rep_sum;
+    a.xs = c->cur_xs();
+    a.vs = c->cur_vs();
+    a.f = c->d_f;
+    a.xb = c->d_xb;
+    a.n_slots = c->n_slots;
+    a.n_slices = c->n_slices;
+    a.h = 0.5 * dt;
+    a.dt = dt;
+    a.momentum_fix = momentum_fix ? 1 : 0;
+    const double hs = 0.5 * c->cfg.skin;
+    a.half_skin2 = hs * hs;
+    a.flags = c->d_flags;
+    const unsigned g = grid_for(c->n_slots);
+    return timed(c, kKIntegrate, [&] {
+        if (mode == kIntFirst) k_integrate<kIntFirst><<<g, kBlock, 0, c->stream>>>(a);
+        else if (mode == kIntMid) k_integrate<kIntMid><<<g, kBlock, 0, c->stream>>>(a);
+        else k_integrate<kIntLast><<<g, kBlock, 0, c->stream>>>(a);
+    });
+}
+
+rbl_status check_p(int P)
+{
+    if (P < 1 || P > RBL_MAX_P)
+        return fail(RBL_E_ARG, "batch size P must be in [1, " + std::to_string(RBL_MAX_P) + "]");
+    return RBL_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C-ABI
+
+extern "C" {
+
+void rbl_config_init(rbl_config* cfg, int64_t n)
+{
+    if (!cfg) return;
+    std::memset(cfg, 0, sizeof(*cfg));
+    cfg->n = n;
+    cfg->n_replicas = 1;
+    cfg->precision = RBL_PREC_FP64;
+    cfg->pair = RBL_PAIR_LJ;
+    cfg->lists = RBL_LIST_CORE | RBL_LIST_SHELL;
+    cfg->skin = 0.3;
+    cfg->alpha = 0.0;
+    cfg->shift = 1;
+    cfg->momentum_fix = 1;
+    cfg->predraw = 1;
+    cfg->capacity_factor = 1.25;
+    cfg->replica_offsets = nullptr;
+    cfg->charges = nullptr;
+}
+
+const char* rbl_last_error(void) { return g_err.c_str(); }
+
+const char* rbl_version(void) { return "librbl 0.1 (gfx950)"; }
+
+rbl_status rbl_destroy(rbl_ctx* c)
+{
+    if (!c) return RBL_OK;
+    (void)hipStreamSynchronize(c->stream);
+    for (int k = 0; k < kKinds; ++k)
+        for (auto& pr : c->ev_pending[k]) {
+            (void)hipEventDestroy(pr.first);
+            (void)hipEventDestroy(pr.second);
+        }
+    for (auto e : c->ev_pool) (void)hipEventDestroy(e);
+    dfree(c->d_rep);
+    dfree(c->d_id_rep);
+    dfree(c->d_slice_rep);
+    dfree(c->d_cell_rep);
+    dfree(c->d_cell_count);
+    dfree(c->d_cell_start);
+    dfree(c->d_tile_sum);
+    dfree(c->d_cell_of_src);
+    dfree(c->d_rank_of_src);
+    dfree(c->d_src_of_slot);
+    dfree(c->d_perm[0]);
+    dfree(c->d_perm[1]);
+    dfree(c->d_slot_of_id);
+    dfree(c->d_xs[0]);
+    dfree(c->d_xs[1]);
+    dfree(c->d_vs[0]);
+    dfree(c->d_vs[1]);
+    dfree(c->d_xb);
+    dfree(c->d_f);
+    for (int q = 0; q < 3; ++q) {
+        dfree(c->d_list[q]);
+        dfree(c->d_len[q]);
+    }
+    dfree(c->d_batch);
+    dfree(c->d_partial);
+    dfree(c->d_rep_sum);
+    dfree(c->d_flags);
+    delete c;
+    return RBL_OK;
+}
+
+rbl_status rbl_create(const rbl_config* cfg, void* hip_stream, rbl_ctx** out)
+{
+    if (!cfg || !out) return fail(RBL_E_ARG, "NULL config or output pointer");
+    *out = nullptr;
+    if (cfg->n < 1 || cfg->n > 0x7fffffff - 64 * (int64_t)std::max(cfg->n_replicas, 1))
+        return fail(RBL_E_ARG, "particle count out of range");
+    if (cfg->n_replicas < 1) return fail(RBL_E_ARG, "n_replicas must be >= 1");
+    if (cfg->n_replicas > 1 && !cfg->replica_offsets)
+        return fail(RBL_E_ARG, "replica_offsets required for n_replicas > 1");
+    if (cfg->precision != RBL_PREC_FP64 && cfg->precision != RBL_PREC_MIXED)
+        return fail(RBL_E_ARG, "unknown precision");
+    if (cfg->pair != RBL_PAIR_LJ && cfg->pair != RBL_PAIR_LJ_ERFC) return fail(RBL_E_ARG, "unknown pair");
+    if (cfg->lists <= 0 || cfg->lists > 7) return fail(RBL_E_ARG, "list mask must be in 1..7");
+    if (!(cfg->skin >= 0.0) || !std::isfinite(cfg->skin)) return fail(RBL_E_ARG, "skin must be >= 0");
+    if (cfg->pair == RBL_PAIR_LJ_ERFC && !(cfg->alpha > 0.0)) return fail(RBL_E_ARG, "alpha must be > 0");
+    std::vector<int64_t> off(cfg->n_replicas + 1);
+    if (cfg->n_replicas == 1) {
+        off[0] = 0;
+        off[1] = cfg->n;
+    } else {
+        for (int r = 0; r <= cfg->n_replicas; ++r) off[r] = cfg->replica_offsets[r];
+        if (off[0] != 0 || off[cfg->n_replicas] != cfg->n)
+            return fail(RBL_E_ARG, "replica_offsets must run from 0 to n");
+        for (int r = 0; r < cfg->n_replicas; ++r)
+            if (off[r + 1] <= off[r]) return fail(RBL_E_ARG, "every replica needs >= 1 particle");
+    }
+    rbl_ctx* c = new rbl_ctx();
+    c->cfg = *cfg;
+    c->cfg.replica_offsets = nullptr;
+    c->stream = (hipStream_t)hip_stream;
+    c->R = cfg->n_replicas;
+    c->n = cfg->n;
+    int64_t slot = 0;
+    for (int r = 0; r < c->R; ++r) {
+        c->id_base.push_back(off[r]);
+        c->rep_n.push_back(off[r + 1] - off[r]);
+        c->slot_base.push_back(slot);
+        slot += (off[r + 1] - off[r] + 63) / 64 * 64;
+    }
+    c->n_slots = slot;
+    c->n_slices = slot / 64;
+
+    auto bail = [&](rbl_status s) {
+        std::string keep = g_err;
+        rbl_destroy(c);
+        g_err = keep;
+        return s;
+    };
+#define CR(expr)                             \
+    do {                                     \
+        rbl_status s_ = (expr);              \
+        if (s_ < 0) return bail(s_);         \
+    } while (0)
+    CR(dalloc(&c->d_rep, c->R));
+    CR(dalloc(&c->d_id_rep, c->n));
+    CR(dalloc(&c->d_slice_rep, c->n_slices));
+    CR(dalloc(&c->d_cell_of_src, c->n_slots));
+    CR(dalloc(&c->d_rank_of_src, c->n_slots));
+    CR(dalloc(&c->d_src_of_slot, c->n_slots));
+    CR(dalloc(&c->d_perm[0], c->n_slots));
+    CR(dalloc(&c->d_perm[1], c->n_slots));
+    CR(dalloc(&c->d_slot_of_id, c->n));
+    CR(dalloc(&c->d_xs[0], c->n_slots));
+    CR(dalloc(&c->d_xs[1], c->n_slots));
+    CR(dalloc(&c->d_vs[0], 3 * c->n_slots));
+    CR(dalloc(&c->d_vs[1], 3 * c->n_slots));
+    CR(dalloc(&c->d_xb, 3 * c->n_slots));
+    CR(dalloc(&c->d_f, 3 * c->n_slots));
+    CR(dalloc(&c->d_partial, 5 * c->n_slices));
+    CR(dalloc(&c->d_rep_sum, 8 * c->R));
+    CR(dalloc(&c->d_flags, kNumFlags));
+    {
+        std::vector<int> id_rep(c->n), slice_rep(c->n_slices);
+        for (int r = 0; r < c->R; ++r) {
+            std::fill(id_rep.begin() + off[r], id_rep.begin() + off[r + 1], r);
+            const int64_t s0 = c->slot_base[r] / 64;
+            const int64_t ns = (c->rep_n[r] + 63) / 64;
+            std::fill(slice_rep.begin() + s0, slice_rep.begin() + s0 + ns, r);
+        }
+        if (hipMemcpy(c->d_id_rep, id_rep.data(), sizeof(int) * c->n, hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(c->d_slice_rep, slice_rep.data(), sizeof(int) * c->n_slices,
+                      hipMemcpyHostToDevice) != hipSuccess)
+            return bail(fail(RBL_E_HIP, "upload of replica tables failed"));
+    }
+    CR(fill_i32(c, c->d_perm[0], c->n_slots, -1));
+    CR(fill_i32(c, c->d_perm[1], c->n_slots, -1));
+    CR(fill_i32(c, c->d_flags, kNumFlags, 0));
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return bail(fail(RBL_E_HIP, "stream sync failed"));
+#undef CR
+    *out = c;
+    return RBL_OK;
+}
+
+rbl_status rbl_build(rbl_ctx* c, const double* pos, const double* box, double r_s, double r_c)
+{
+    if (!c || !pos || !box) return fail(RBL_E_ARG, "NULL argument");
+    if (!(r_s > 0.0) || !(r_c > r_s) || !std::isfinite(r_c))
+        return fail(RBL_E_ARG, "radii must satisfy 0 < r_s < r_c");
+    RBL_TRY(setup_geometry(c, box, r_s, r_c));
+    c->built = false;
+    RBL_TRY(clear_flags(c));
+    RBL_TRY(bin_particles<kSrcCaller>(c, pos, nullptr, false));
+    RBL_TRY(build_lists(c, c->cfg.lists));
+    c->built = true;
+    return RBL_OK;
+}
+
+rbl_status rbl_forces(rbl_ctx* c, int P, uint64_t seed, uint64_t step, const double* pos,
+                      double* force, double* ev)
+{
+    if (!c || !pos || !force) return fail(RBL_E_ARG, "NULL argument");
+    RBL_TRY(check_p(P));
+    if (!c->built) return fail(RBL_E_STATE, "rbl_forces needs a list build first");
+    if ((c->built_mask & (RBL_LIST_CORE | RBL_LIST_SHELL)) != (RBL_LIST_CORE | RBL_LIST_SHELL))
+        return fail(RBL_E_STATE, "the last build has no core and shell lists");
+    IoArgs io = io_args(c, c->cfg.momentum_fix != 0);
+    io.pos_in = pos;
+    k_load_positions<<<grid_for(c->n_slots), kBlock, 0, c->stream>>>(io);
+    HIP_TRY(hipGetLastError());
+    if (P <= 32) {
+        RBL_TRY(rbl_force_sorted(c, P, seed, step, -1, ev != nullptr));
+    } else {
+        RBL_TRY(predraw(c, P, seed, step, 1));
+        RBL_TRY(rbl_force_sorted(c, P, seed, step, 0, ev != nullptr));
+    }
+    io.f_out = force;
+    k_scatter_out<<<grid_for(c->n_slots), kBlock, 0, c->stream>>>(io);
+    HIP_TRY(hipGetLastError());
+    return emit_ev(c, ev);
+}
+
+rbl_status rbl_full_forces(rbl_ctx* c, const double* pos, double* force, double* ev)
+{
+    if (!c || !pos || !force) return fail(RBL_E_ARG, "NULL argument");
+    if (!c->built) return fail(RBL_E_STATE, "rbl_full_forces needs a list build first");
+    if (!(c->built_mask & RBL_LIST_FULL)) return fail(RBL_E_STATE, "the last build has no full list");
+    IoArgs io = io_args(c, false);
+    io.pos_in = pos;
+    k_load_positions<<<grid_for(c->n_slots), kBlock, 0, c->stream>>>(io);
+    HIP_TRY(hipGetLastError());
+    RBL_TRY(full_force_sorted(c, ev != nullptr));
+    io.f_out = force;
+    k_scatter_out<<<grid_for(c->n_slots), kBlock, 0, c->stream>>>(io);
+    HIP_TRY(hipGetLastError());
+    return emit_ev(c, ev);
+}
+
+rbl_status rbl_step(rbl_ctx* c, double* pos, double* vel, double* force, int64_t nsteps, double dt,
+                    int P, uint64_t seed, int64_t step0, int rebuild_every, int use_full, double* ev)
+{
+    if (!c || !pos || !vel) return fail(RBL_E_ARG, "NULL argument");
+    if (nsteps < 0 || step0 < 0) return fail(RBL_E_ARG, "nsteps and step0 must be >= 0");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(RBL_E_ARG, "dt must be > 0");
+    if (rebuild_every < 1) return fail(RBL_E_ARG, "rebuild_every must be >= 1");
+    if (!use_full) RBL_TRY(check_p(P));
+    if (c->r_c <= 0.0) return fail(RBL_E_STATE, "rbl_step needs box and radii from rbl_build");
+    const bool full = use_full != 0;
+    const bool fix = !full && c->cfg.momentum_fix;
+    const int mask = full ? RBL_LIST_FULL : (RBL_LIST_CORE | RBL_LIST_SHELL);
+    const bool pre = !full && c->cfg.predraw;
+    const int64_t K = rebuild_every;
+    RBL_TRY(clear_flags(c));
+    int64_t build_step = step0;
+
+    auto do_build = [&](int64_t s, bool from_caller) -> rbl_status {
+        if (from_caller) RBL_TRY(bin_particles<kSrcCaller>(c, pos, vel, true));
+        else RBL_TRY(bin_particles<kSrcSorted>(c, nullptr, nullptr, true));
+        c->built = false;
+        RBL_TRY(build_lists(c, mask));
+        c->built = true;
+        build_step = s;
+        if (pre) {
+            // batches for every force evaluation until the next rebuild
+            int64_t until = (s / K + 1) * K;
+            int64_t last = step0 + nsteps;
+            int64_t cnt = std::min(until, last + 1) - s;
+            RBL_TRY(predraw(c, P, seed, (uint64_t)s, (int)cnt));
+        }
+        return RBL_OK;
+    };
+    auto do_force = [&](int64_t s, bool energy) -> rbl_status {
+        if (full) return full_force_sorted(c, energy);
+        return rbl_force_sorted(c, P, seed, (uint64_t)s, pre ? (int)(s - build_step) : -1, energy);
+    };
+
+    RBL_TRY(do_build(step0, true));
+    RBL_TRY(do_force(step0, ev != nullptr && nsteps == 0));
+    for (int64_t it = 1; it <= nsteps; ++it) {
+        const int64_t s = step0 + it;
+        RBL_TRY(integrate(c, it == 1 ? kIntFirst : kIntMid, dt, fix));
+        if (s % K == 0) RBL_TRY(do_build(s, false));
+        RBL_TRY(do_force(s, ev != nullptr && it == nsteps));
+    }
+    if (nsteps > 0) RBL_TRY(integrate(c, kIntLast, dt, fix));
+    IoArgs io = io_args(c, fix);
+    io.pos_out = pos;
+    io.vel_out = vel;
+    io.f_out = force;
+    k_scatter_out<<<grid_for(c->n_slots), kBlock, 0, c->stream>>>(io);
+    HIP_TRY(hipGetLastError());
+    RBL_TRY(emit_ev(c, ev));
+    RBL_TRY(read_flags(c));
+    if (c->h_flags[kFlagNonfinite]) return fail(RBL_E_NONFINITE, "non-finite position during the run");
+    if (c->h_flags[kFlagBadSlot]) return fail(RBL_E_HIP, "inconsistent cell binning");
+    if (c->h_flags[kFlagSkin]) {
+        g_err = "a particle moved more than skin/2 within one list lifetime";
+        return RBL_W_SKIN;
+    }
+    return RBL_OK;
+}
+
+rbl_status rbl_row_counts(rbl_ctx* c, int64_t nrows, const int64_t* rows, int64_t* counts)
+{
+    if (!c || !counts || nrows < 0) return fail(RBL_E_ARG, "bad argument");
+    if (!c->built) return fail(RBL_E_STATE, "no list build");
+    std::vector<int64_t> h_rows;
+    if (!rows) {
+        nrows = c->n;
+        h_rows.resize(c->n);
+        for (int64_t i = 0; i < c->n; ++i) h_rows[i] = i;
+    } else {
+        h_rows.assign(rows, rows + nrows);
+        for (auto r : h_rows)
+            if (r < 0 || r >= c->n) return fail(RBL_E_ARG, "row ID out of range");
+    }
+    if (nrows == 0) return RBL_OK;
+    int64_t* d_rows = nullptr;
+    int64_t* d_cnt = nullptr;
+    RBL_TRY(dalloc(&d_rows, nrows));
+    rbl_status st = dalloc(&d_cnt, nrows);
+    if (st < 0) {
+        dfree(d_rows);
+        return st;
+    }
+    (void)hipMemcpyAsync(d_rows, h_rows.data(), sizeof(int64_t) * nrows, hipMemcpyHostToDevice, c->stream);
+    for (int q = 0; q < 3; ++q) {
+        const int* len = (c->built_mask >> q) & 1 ? c->d_len[q] : nullptr;
+        k_row_counts<<<grid_for(nrows), kBlock, 0, c->stream>>>(d_rows, nrows, c->d_slot_of_id, len, d_cnt);
+        (void)hipMemcpyAsync(counts + q * nrows, d_cnt, sizeof(int64_t) * nrows, hipMemcpyDeviceToHost,
+                             c->stream);
+    }
+    hipError_t e = hipStreamSynchronize(c->stream);
+    dfree(d_rows);
+    dfree(d_cnt);
+    if (e != hipSuccess) return fail(RBL_E_HIP, hipGetErrorString(e));
+    return RBL_OK;
+}
+
+rbl_status rbl_export_lists(rbl_ctx* c, int64_t nrows, const int64_t* rows, const int64_t* core_off,
+                            int32_t* core_idx, const int64_t* shell_off, int32_t* shell_idx,
+                            const int64_t* full_off, int32_t* full_idx)
+{
+    if (!c || nrows < 0) return fail(RBL_E_ARG, "bad argument");
+    if (!c->built) return fail(RBL_E_STATE, "no list build");
+    std::vector<int64_t> h_rows;
+    if (!rows) {
+        nrows = c->n;
+        h_rows.resize(c->n);
+        for (int64_t i = 0; i < c->n; ++i) h_rows[i] = i;
+    } else {
+        h_rows.assign(rows, rows + nrows);
+        for (auto r : h_rows)
+            if (r < 0 || r >= c->n) return fail(RBL_E_ARG, "row ID out of range");
+    }
+    if (nrows == 0) return RBL_OK;
+    const int64_t* offs[3] = {core_off, shell_off, full_off};
+    int32_t* outs[3] = {core_idx, shell_idx, full_idx};
+    int64_t* d_rows = nullptr;
+    RBL_TRY(dalloc(&d_rows, nrows));
+    (void)hipMemcpyAsync(d_rows, h_rows.data(), sizeof(int64_t) * nrows, hipMemcpyHostToDevice, c->stream);
+    rbl_status st = RBL_OK;
+    for (int q = 0; q < 3 && st == RBL_OK; ++q) {
+        if (!outs[q]) continue;
+        if (!offs[q]) {
+            st = fail(RBL_E_ARG, "offsets missing for a requested list");
+            break;
+        }
+        if (!((c->built_mask >> q) & 1)) {
+            st = fail(RBL_E_STATE, "list was not built");
+            break;
+        }
+        const int64_t total = offs[q][nrows];
+        int64_t* d_off = nullptr;
+        int* d_out = nullptr;
+        st = dalloc(&d_off, nrows + 1);
+        if (st < 0) break;
+        st = dalloc(&d_out, std::max<int64_t>(total, 1));
+        if (st < 0) {
+            dfree(d_off);
+            break;
+        }
+        (void)hipMemcpyAsync(d_off, offs[q], sizeof(int64_t) * (nrows + 1), hipMemcpyHostToDevice, c->stream);
+        k_export_rows<<<grid_for(nrows), kBlock, 0, c->stream>>>(d_rows, nrows, c->d_slot_of_id,
+                                                                 c->cur_perm(), c->d_list[q], c->d_len[q],
+                                                                 c->cap[q], d_off, d_out);
+        if (total > 0)
+            (void)hipMemcpyAsync(outs[q], d_out, sizeof(int) * total, hipMemcpyDeviceToHost, c->stream);
+        hipError_t e = hipStreamSynchronize(c->stream);
+        dfree(d_off);
+        dfree(d_out);
+        if (e != hipSuccess) st = fail(RBL_E_HIP, hipGetErrorString(e));
+    }
+    dfree(d_rows);
+    return st;
+}
+
+rbl_status rbl_export_batches(rbl_ctx* c, int P, uint64_t seed, uint64_t step, int64_t nrows,
+                              const int64_t* rows, int32_t* batch, int32_t* count)
+{
+    if (!c || !batch || !count || nrows < 0) return fail(RBL_E_ARG, "bad argument");
+    RBL_TRY(check_p(P));
+    if (!c->built || !(c->built_mask & RBL_LIST_SHELL)) return fail(RBL_E_STATE, "no shell list built");
+    for (int64_t k = 0; k < nrows; ++k)
+        if (!rows || rows[k] < 0 || rows[k] >= c->n) return fail(RBL_E_ARG, "row ID out of range");
+    RBL_TRY(predraw(c, P, seed, step, 1));
+    std::vector<int> h_batch((size_t)P * c->n_slots), h_perm(c->n_slots), h_slot(c->n), h_len(c->n_slots);
+    HIP_TRY(hipMemcpyAsync(h_batch.data(), c->d_batch, sizeof(int) * h_batch.size(), hipMemcpyDeviceToHost,
+                           c->stream));
+    HIP_TRY(hipMemcpyAsync(h_perm.data(), c->cur_perm(), sizeof(int) * c->n_slots, hipMemcpyDeviceToHost,
+                           c->stream));
+    HIP_TRY(hipMemcpyAsync(h_slot.data(), c->d_slot_of_id, sizeof(int) * c->n, hipMemcpyDeviceToHost,
+                           c->stream));
+    HIP_TRY(hipMemcpyAsync(h_len.data(), c->d_len[1], sizeof(int) * c->n_slots, hipMemcpyDeviceToHost,
+                           c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    for (int64_t k = 0; k < nrows; ++k) {
+        const int slot = h_slot[rows[k]];
+        const int cnt = std::min(h_len[slot], P);
+        count[k] = cnt;
+        for (int m = 0; m < P; ++m)
+            batch[k * P + m] = m < cnt ? h_perm[h_batch[(size_t)m * c->n_slots + slot]] : -1;
+    }
+    return RBL_OK;
+}
+
+rbl_status rbl_export_binning(rbl_ctx* c, int32_t* ncell, int64_t* slot_of_id, int32_t* cell_count)
+{
+    if (!c || !ncell || !slot_of_id) return fail(RBL_E_ARG, "NULL argument");
+    if (!c->built) return fail(RBL_E_STATE, "no list build");
+    std::vector<int> h_slot(c->n);
+    HIP_TRY(hipMemcpyAsync(h_slot.data(), c->d_slot_of_id, sizeof(int) * c->n, hipMemcpyDeviceToHost,
+                           c->stream));
+    if (cell_count)
+        HIP_TRY(hipMemcpyAsync(cell_count, c->d_cell_count, sizeof(int) * c->n_cells, hipMemcpyDeviceToHost,
+                               c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    for (int r = 0; r < c->R; ++r) {
+        for (int a = 0; a < 3; ++a) ncell[3 * r + a] = c->h_rep[r].nc[a];
+        for (int64_t i = c->id_base[r]; i < c->id_base[r] + c->rep_n[r]; ++i)
+            slot_of_id[i] = h_slot[i] - c->slot_base[r];
+    }
+    return RBL_OK;
+}
+
+rbl_status rbl_sync(rbl_ctx* c)
+{
+    if (!c) return fail(RBL_E_ARG, "NULL context");
+    RBL_TRY(read_flags(c));
+    const int nonfinite = c->h_flags[kFlagNonfinite];
+    const int skin = c->h_flags[kFlagSkin];
+    RBL_TRY(clear_flags(c));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    if (nonfinite) return fail(RBL_E_NONFINITE, "non-finite particle position");
+    if (skin) {
+        g_err = "a particle moved more than skin/2 within one list lifetime";
+        return RBL_W_SKIN;
+    }
+    return RBL_OK;
+}
+
+rbl_status rbl_set_profiling(rbl_ctx* c, int on)
+{
+    if (!c) return fail(RBL_E_ARG, "NULL context");
+    RBL_TRY(resolve_events(c));
+    c->profiling = on != 0;
+    for (int k = 0; k < kKinds; ++k) {
+        c->stat_launches[k] = 0;
+        c->stat_ms[k] = 0.0;
+    }
+    return RBL_OK;
+}
+
+rbl_status rbl_kernel_stats(rbl_ctx* c, int kind, int64_t* launches, double* total_ms)
+{
+    if (!c || kind < 0 || kind >= kKinds || !launches || !total_ms) return fail(RBL_E_ARG, "bad argument");
+    RBL_TRY(resolve_events(c));
+    *launches = c->stat_launches[kind];
+    *total_ms = c->stat_ms[kind];
+    return RBL_OK;
+}
+
+rbl_status rbl_info(rbl_ctx* c, int64_t* n_slots, int32_t* cap_core, int32_t* cap_shell, int32_t* cap_full)
+{
+    if (!c) return fail(RBL_E_ARG, "NULL context");
+    if (n_slots) *n_slots = c->n_slots;
+    if (cap_core) *cap_core = c->cap[0];
+    if (cap_shell) *cap_shell = c->cap[1];
+    if (cap_full) *cap_full = c->cap[2];
+    return RBL_OK;
+}
+
+}  // extern "C"

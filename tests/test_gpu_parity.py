@@ -1,0 +1,328 @@
+"""GPU path (librbl through its C-ABI) against the CPU oracle.
+
+Integer and index work (cell binning, neighbour lists, batches) must match
+bit for bit; forces match within 1e-12 relative L2 in FP64 and 2e-5 in the
+mixed FP32-pair / FP64-accumulate form, always at identical states.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2105_04884_amd import Context, RblError, inputs
+from paper_2105_04884_amd import _lib
+
+from gpu_util import (FP64_TOL, MIXED_TOL, RC, RS, SKIN, assert_lists_equal, dev, host,
+                      oracle_rbl_total, rel_l2, torch_cuda)
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(name):
+    if name == "fluid1000":
+        st = inputs.small_fluid(seed=1)
+        return st.pos, st.box
+    if name == "gas_small_box":
+        box = np.array([9.1, 9.1, 9.1])
+        return inputs.random_gas(300, box, seed=5).pos, box
+    if name == "elongated":
+        box = np.array([8.2, 9.5, 24.0])
+        return inputs.random_gas(900, box, seed=6).pos, box
+    if name == "tiny_grid":
+        box = np.array([7.7, 7.9, 12.0])
+        return inputs.random_gas(250, box, seed=8).pos, box
+    if name == "ragged_65":
+        box = np.array([8.0, 8.0, 8.0])
+        return inputs.random_gas(65, box, seed=9, min_dist=0.9).pos, box
+    if name == "single":
+        return np.array([[1.0], [2.0], [3.0]]), np.array([8.0, 8.0, 8.0])
+    if name == "vapour":
+        st = inputs.lj_fluid(3000, 0.02, 1.0, seed=4)
+        return st.pos, st.box
+    if name == "unwrapped":
+        st = inputs.small_fluid(seed=2)
+        shift = np.array([[2.0], [-3.0], [1.0]]) * st.box[:, None]
+        return st.pos + shift, st.box
+    raise KeyError(name)
+
+
+CASES = ["fluid1000", "gas_small_box", "elongated", "tiny_grid", "ragged_65", "single",
+         "vapour", "unwrapped"]
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_binning_matches_oracle(case):
+    torch_cuda()
+    pos, box = _case(case)
+    n = pos.shape[1]
+    with Context(n, lists=("core", "shell", "full")) as ctx:
+        ctx.build(dev(pos), box, RS, RC)
+        ncell, slot, cnt = ctx.export_binning(with_counts=True)
+    onc, _, oslot, ocs = oracle.System(pos, box, RS, RC, SKIN).binning()
+    assert np.array_equal(ncell[0], onc)
+    assert np.array_equal(slot, oslot)
+    assert np.array_equal(cnt, np.diff(ocs))
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_lists_match_oracle(case):
+    torch_cuda()
+    pos, box = _case(case)
+    n = pos.shape[1]
+    with Context(n, lists=("core", "shell", "full")) as ctx:
+        ctx.build(dev(pos), box, RS, RC)
+        got = ctx.export_lists()
+    ref = oracle.System(pos, box, RS, RC, SKIN).lists(method="cells")
+    assert_lists_equal(got, ref)
+
+
+@pytest.mark.parametrize("P", [1, 3, 10, 20, 33, 64, 128])
+def test_batches_match_oracle(P):
+    torch_cuda()
+    pos, box = _case("fluid1000")
+    n = pos.shape[1]
+    rows = np.arange(n)
+    L = oracle.System(pos, box, RS, RC, SKIN).lists(kinds=("shell",))
+    with Context(n) as ctx:
+        ctx.build(dev(pos), box, RS, RC)
+        for seed, step in ((1, 0), (7, 12345), (2**40 + 3, 2**32 + 5)):
+            batch, count = ctx.export_batches(P, seed, step, rows)
+            for i in range(n):
+                sh = L.row("shell", i)
+                kpos = oracle.batch_positions(seed, i, step, 0, P, len(sh))
+                assert count[i] == len(kpos)
+                assert np.array_equal(batch[i, :count[i]], sh[kpos]), (seed, step, i)
+                assert np.all(batch[i, count[i]:] == -1)
+
+
+def _displaced(pos, amount, seed):
+    rng = np.random.default_rng(seed)
+    return pos + rng.uniform(-amount, amount, size=pos.shape)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("mixed", MIXED_TOL)])
+@pytest.mark.parametrize("P", [5, 10, 20, 64])
+def test_rbl_forces_match_oracle(precision, tol, P):
+    """Force at the build state and at displaced positions (classification
+    by current distance), with mean-force subtraction; energy and virial."""
+    torch_cuda()
+    pos, box = _case("fluid1000")
+    n = pos.shape[1]
+    L = oracle.System(pos, box, RS, RC, SKIN).lists()
+    with Context(n, precision=precision) as ctx:
+        ctx.build(dev(pos), box, RS, RC)
+        for k, p in enumerate((pos, _displaced(pos, 0.1, 3))):
+            f, ev = ctx.forces(P, seed=11 + k, step=3 * k, pos=dev(p), want_ev=True)
+            fo, eo, wo = oracle_rbl_total(p, box, L, P, 11 + k, 3 * k)
+            assert rel_l2(host(f), fo) < tol
+            U, W = host(ev)
+            assert abs(U - eo) <= tol * max(1.0, abs(eo)) * 10
+            assert abs(W - wo) <= tol * max(1.0, abs(wo)) * 10
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("mixed", MIXED_TOL)])
+def test_full_forces_match_oracle(precision, tol):
+    torch_cuda()
+    for case in ("fluid1000", "elongated", "vapour"):
+        pos, box = _case(case)
+        n = pos.shape[1]
+        L = oracle.System(pos, box, RS, RC, SKIN).lists()
+        with Context(n, precision=precision, lists=("full",)) as ctx:
+            ctx.build(dev(pos), box, RS, RC)
+            p = _displaced(pos, 0.05, 1)
+            f, ev = ctx.full_forces(dev(p), want_ev=True)
+            fo, eo, wo = oracle.full_forces(p, box, RC, L)
+            assert rel_l2(host(f), fo) < tol, case
+            U, W = host(ev)
+            assert abs(U - eo.sum()) <= 10 * tol * abs(eo.sum())
+            assert abs(W - wo.sum()) <= 10 * tol * abs(wo.sum())
+
+
+def test_rbl_forces_edge_cases():
+    """Empty shells (vapour), n_i <= P (taken whole), one particle, ragged N."""
+    torch_cuda()
+    for case in ("vapour", "single", "ragged_65", "tiny_grid"):
+        pos, box = _case(case)
+        n = pos.shape[1]
+        L = oracle.System(pos, box, RS, RC, SKIN).lists()
+        with Context(n) as ctx:
+            ctx.build(dev(pos), box, RS, RC)
+            for P in (1, 10):
+                f = ctx.forces(P, seed=5, step=1, pos=dev(pos))
+                fo, _, _ = oracle_rbl_total(pos, box, L, P, 5, 1)
+                if np.linalg.norm(fo) == 0:
+                    assert np.abs(host(f)).max() == 0.0
+                else:
+                    assert rel_l2(host(f), fo) < FP64_TOL, (case, P)
+
+
+def test_trajectory_matches_oracle():
+    """100 velocity-Verlet steps of the N = 1000 fluid (P = 10, lists every
+    10 steps): final state, force and energy against the oracle run; the
+    lists of the final build bit-exact at the GPU's own final state."""
+    torch = torch_cuda()
+    st = inputs.small_fluid(seed=1)
+    n = st.n
+    x = dev(st.pos)
+    v = dev(st.vel)
+    f = torch.zeros_like(x)
+    with Context(n, lists=("core", "shell")) as ctx:
+        ctx.build(x, st.box, RS, RC)
+        status, ev = ctx.step(x, v, nsteps=100, dt=0.005, P=10, seed=1, step0=0,
+                              rebuild_every=10, force=f, want_ev=True)
+        got_lists = ctx.export_lists(kinds=("core", "shell"))
+    xo, vo, fo, evo = oracle.md_run(st.pos, st.vel, st.box, RS, RC, SKIN, 0.005, 100, p=10,
+                                    seed=1, K=10, want_ev=True)
+    assert rel_l2(host(x), xo) < 1e-12
+    assert rel_l2(host(v), vo) < 1e-9
+    assert rel_l2(host(f), fo) < 1e-9
+    assert abs(host(ev)[0] - evo[-1, 0]) < 1e-9 * abs(evo[-1, 0])
+    xg = host(x)
+    ref = oracle.System(xg, st.box, RS, RC, SKIN).lists(kinds=("core", "shell"))
+    assert_lists_equal(got_lists, ref, kinds=("core", "shell"))
+
+
+@pytest.mark.parametrize("predraw", [True, False])
+def test_step_restart_and_determinism(predraw):
+    """20 steps straight equal 10 + 10 resumed at a rebuild boundary, bit for
+    bit; pre-drawn and inline batches give the same trajectory."""
+    torch = torch_cuda()
+    st = inputs.small_fluid(seed=3)
+    n = st.n
+    runs = []
+    for chunks in ((20,), (10, 10)):
+        x, v = dev(st.pos), dev(st.vel)
+        with Context(n, predraw=predraw) as ctx:
+            ctx.build(x, st.box, RS, RC)
+            s0 = 0
+            for c in chunks:
+                ctx.step(x, v, nsteps=c, dt=0.005, P=10, seed=9, step0=s0, rebuild_every=10)
+                s0 += c
+        runs.append((host(x), host(v)))
+    assert np.array_equal(runs[0][0], runs[1][0])
+    assert np.array_equal(runs[0][1], runs[1][1])
+    x2, v2 = dev(st.pos), dev(st.vel)
+    with Context(n, predraw=not predraw) as ctx:
+        ctx.build(x2, st.box, RS, RC)
+        ctx.step(x2, v2, nsteps=20, dt=0.005, P=10, seed=9, step0=0, rebuild_every=10)
+    assert np.array_equal(runs[0][0], host(x2))
+
+
+def test_full_list_nve_energy():
+    """NVE with the direct-truncation force conserves energy on the GPU."""
+    torch = torch_cuda()
+    st = inputs.small_fluid(seed=1)
+    x, v = dev(st.pos), dev(st.vel)
+    with Context(st.n, lists=("full",)) as ctx:
+        ctx.build(x, st.box, RS, RC)
+        _, ev0 = ctx.step(x, v, nsteps=0, dt=0.004, use_full=True, want_ev=True)
+        e0 = host(ev0)[0] + 0.5 * float((v * v).sum())
+        _, ev1 = ctx.step(x, v, nsteps=200, dt=0.004, use_full=True, want_ev=True)
+        e1 = host(ev1)[0] + 0.5 * float((v * v).sum())
+    assert abs(e1 - e0) / abs(e0) < 2e-4
+
+
+def test_ensemble_matches_oracle_per_replica():
+    torch = torch_cuda()
+    specs = [(500, 0.8, 1.0, 1), (777, 0.6, 1.2, 2), (1200, 0.9, 0.8, 3), (300, 0.3, 1.0, 4)]
+    states = [inputs.lj_fluid(*s) for s in specs]
+    pos = np.concatenate([s.pos for s in states], axis=1)
+    boxes = np.stack([s.box for s in states])
+    off = np.zeros(len(states) + 1, dtype=np.int64)
+    off[1:] = np.cumsum([s.n for s in states])
+    n = int(off[-1])
+    with Context(n, replica_offsets=off, lists=("core", "shell", "full")) as ctx:
+        ctx.build(dev(pos), boxes, RS, RC)
+        got = ctx.export_lists()
+        f = ctx.forces(10, seed=3, step=7, pos=dev(pos))
+        ff = ctx.full_forces(dev(pos))
+    f, ff = host(f), host(ff)
+    for r, s in enumerate(states):
+        L = oracle.System(s.pos, s.box, RS, RC, SKIN).lists()
+        sl = slice(off[r], off[r + 1])
+        for kind in ("core", "shell", "full"):
+            go = got[kind + "_off"][off[r]:off[r + 1] + 1]
+            gi = got[kind + "_idx"][go[0]:go[-1]] - off[r]
+            assert np.array_equal(go - go[0], getattr(L, kind + "_off"))
+            assert np.array_equal(gi, getattr(L, kind + "_idx"))
+        fo, _, _ = oracle_rbl_total(s.pos, s.box, L, 10, 3, 7, replica=r)
+        assert rel_l2(f[:, sl], fo) < FP64_TOL
+        fu, _, _ = oracle.full_forces(s.pos, s.box, RC, L)
+        assert rel_l2(ff[:, sl], fu) < FP64_TOL
+
+
+def test_million_particle_sampled_parity():
+    """N = 1,000,000 LJ fluid at density 0.8442 (the benchmark workload):
+    sampled rows' lists and batches bit-exact, sampled raw forces (no mean
+    subtraction) within tolerance in both precisions."""
+    torch_cuda()
+    st = inputs.million_fluid(seed=1)
+    n = st.n
+    rows = np.random.default_rng(0).choice(n, size=400, replace=False)
+    rows = np.concatenate([rows, [0, n - 1]])
+    L = oracle.System(st.pos, st.box, RS, RC, SKIN).lists(rows=rows)
+    x = dev(st.pos)
+    for precision, tol in (("fp64", FP64_TOL), ("mixed", MIXED_TOL)):
+        with Context(n, precision=precision, momentum_fix=False,
+                     lists=("core", "shell", "full")) as ctx:
+            ctx.build(x, st.box, RS, RC)
+            if precision == "fp64":
+                got = ctx.export_lists(rows=rows)
+                assert_lists_equal(got, L)
+                batch, count = ctx.export_batches(10, 1, 0, rows)
+                for k, i in enumerate(rows):
+                    sh = L.row("shell", k)
+                    kp = oracle.batch_positions(1, int(i), 0, 0, 10, len(sh))
+                    assert np.array_equal(batch[k, :count[k]], sh[kp])
+            f = host(ctx.forces(10, seed=1, step=0, pos=x))[:, rows]
+            fo, _, _ = oracle.rbl_forces(st.pos, st.box, RS, RC, L, 10, 1, 0)
+            assert rel_l2(f, fo) < tol
+            ff = host(ctx.full_forces(x))[:, rows]
+            ffo, _, _ = oracle.full_forces(st.pos, st.box, RC, L)
+            assert rel_l2(ff, ffo) < tol
+
+
+def test_error_paths():
+    torch = torch_cuda()
+    pos, box = _case("fluid1000")
+    n = pos.shape[1]
+    x = dev(pos)
+    with Context(n) as ctx:
+        with pytest.raises(RblError) as e:
+            ctx.forces(10, 1, 0, x)
+        assert e.value.status == _lib.RBL_E_STATE
+        with pytest.raises(RblError) as e:
+            ctx.build(x, np.array([7.0, 7.0, 7.0]), RS, RC)
+        assert e.value.status == _lib.RBL_E_BOX
+        with pytest.raises(RblError) as e:
+            ctx.build(x, box, 2.0, 1.0)
+        assert e.value.status == _lib.RBL_E_ARG
+        ctx.build(x, box, RS, RC)
+        for P in (0, _lib.MAX_P + 1):
+            with pytest.raises(RblError) as e:
+                ctx.forces(P, 1, 0, x)
+            assert e.value.status == _lib.RBL_E_ARG
+        with pytest.raises(RblError) as e:
+            ctx.full_forces(x)
+        assert e.value.status == _lib.RBL_E_STATE
+        bad = pos.copy()
+        bad[0, 5] = np.nan
+        with pytest.raises(RblError) as e:
+            ctx.build(dev(bad), box, RS, RC)
+        assert e.value.status == _lib.RBL_E_NONFINITE
+
+
+def test_skin_warning_on_large_displacement():
+    """A particle that moves more than skin/2 in one list lifetime makes
+    rbl_step return the skin warning."""
+    torch_cuda()
+    box = np.array([20.0, 20.0, 20.0])
+    pos = np.array([[2.0, 12.0], [2.0, 12.0], [2.0, 12.0]])
+    vel = np.array([[40.0, 0.0], [0.0, 0.0], [0.0, 0.0]])
+    x, v = dev(pos), dev(vel)
+    with Context(2) as ctx:
+        ctx.build(x, box, RS, RC)
+        status, _ = ctx.step(x, v, nsteps=10, dt=0.005, P=10, seed=1, rebuild_every=10)
+        assert status == _lib.RBL_W_SKIN
+        x, v = dev(pos), dev(np.zeros((3, 2)))
+        status, _ = ctx.step(x, v, nsteps=10, dt=0.005, P=10, seed=1, rebuild_every=10)
+        assert status == _lib.RBL_OK
