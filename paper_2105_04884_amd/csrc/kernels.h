@@ -513,6 +513,239 @@ __global__ __launch_bounds__(256) void k_build(BuildArgs a)
 }
 
 // ---------------------------------------------------------------------------
+// Fused list build + batch draw (the molecular-dynamics loop path).  As in
+// k_build, one wavefront per centre cell walks the 5x5x5 stencil, but only
+// the core rows go to HBM: shell membership stays in LDS as one 64-bit ballot
+// mask per (centre particle, candidate chunk).  Its popcount is n_i, and the
+// batches of the next K force evaluations are drawn right away (one lane per
+// (particle, step) pair), the k-th shell partner being found by walking the
+// masks.  Bit-identical to k_build + k_predraw, without writing or re-reading
+// the shell rows.
+constexpr int kMaskBudget = 512;  // 64-bit masks per wavefront
+
+struct FusedArgs {
+    BuildArgs b;
+    const int* perm;
+    int* batch;        // [K][P][n_slots]
+    uint64_t seed;
+    uint64_t step0;
+    int K;
+    int P;
+};
+
+__device__ __forceinline__ void wave_lds_fence()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Position of the r-th set bit (0-based) of w; w has more than r set bits.
+__device__ __forceinline__ int select_bit(uint64_t w, int r)
+{
+    int pos = 0;
+#pragma unroll
+    for (int s = 32; s >= 1; s >>= 1) {
+        const uint64_t low = w & ((1ull << s) - 1ull);
+        const int c = __popcll(low);
+        if (r >= c) {
+            r -= c;
+            w >>= s;
+            pos += s;
+        }
+    }
+    return pos;
+}
+
+// Walks a particle's shell masks in increasing order: returns the slot of
+// the k-th shell candidate (k non-decreasing between calls).
+struct MaskWalker {
+    int c;    // current chunk
+    int cum;  // set bits before chunk c
+    int q;    // current run
+};
+
+__device__ __forceinline__ int walk_to(const uint64_t* masks, int nch, int k, MaskWalker& wk,
+                                       const int* rstart, const int* rpre)
+{
+    int pc = __popcll(masks[wk.c]);
+    while (wk.cum + pc <= k && wk.c < nch - 1) {
+        wk.cum += pc;
+        ++wk.c;
+        pc = __popcll(masks[wk.c]);
+    }
+    const int f = wk.c * 64 + select_bit(masks[wk.c], k - wk.cum);
+    while (wk.q < 63 && rpre[wk.q + 1] <= f) ++wk.q;
+    return rstart[wk.q] + (f - rpre[wk.q]);
+}
+
+template <int PMAX>
+__global__ __launch_bounds__(256) void k_build_draw(FusedArgs fa)
+{
+    __shared__ double4 s_ctr[4][64];
+    __shared__ uint64_t s_mask[4][kMaskBudget];
+    __shared__ int s_rstart[4][64];
+    __shared__ int s_rpre[4][64];
+    __shared__ int s_ccnt[4][64];
+    __shared__ int s_ncnt[4][64];
+    const BuildArgs& a = fa.b;
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t cell = (int64_t)blockIdx.x * 4 + w;
+    if (cell >= a.n_cells) return;
+    const int m = a.cell_count[cell];
+    if (m == 0) return;
+    const int i0 = a.cell_start[cell];
+    if (i0 < 0 || (int64_t)i0 + m > a.n_slots) {
+        if (lane == 0) atomicOr(&a.flags[kFlagBadSlot], 2);
+        return;
+    }
+    const int rep_id = a.cell_rep[cell];
+    const DevReplica& R = a.rep[rep_id];
+    const int64_t lc = cell - R.cell_base;
+    const int cx = (int)(lc % R.nc[0]);
+    const int cy = (int)((lc / R.nc[0]) % R.nc[1]);
+    const int cz = (int)(lc / ((int64_t)R.nc[0] * R.nc[1]));
+    const AxisRuns ax = axis_runs(cx, R.nc[0]);
+    const AxisRuns ay = axis_runs(cy, R.nc[1]);
+    const AxisRuns az = axis_runs(cz, R.nc[2]);
+    const int ny_s = ay.l0 + ay.l1;
+    const int nz_s = az.l0 + az.l1;
+    int rstart = 0, rlen = 0;
+    {
+        const int q = lane;
+        const int zi = q / (2 * ny_s);
+        const int yi = (q >> 1) % ny_s;
+        const int xr = q & 1;
+        if (zi < nz_s) {
+            const int zc = axis_cell(az, zi);
+            const int yc = axis_cell(ay, yi);
+            const int px = xr == 0 ? ax.p0 : ax.p1;
+            const int lx = xr == 0 ? ax.l0 : ax.l1;
+            if (lx > 0) {
+                const int64_t row = R.cell_base + ((int64_t)zc * R.nc[1] + yc) * R.nc[0];
+                const int64_t c0 = row + px;
+                const int64_t c1 = row + px + lx - 1;
+                rstart = a.cell_start[c0];
+                rlen = a.cell_start[c1] + a.cell_count[c1] - rstart;
+            }
+        }
+    }
+    const int incl = wave_incl_scan(rlen);
+    const int total = __builtin_amdgcn_readlane(incl, 63);
+    const int rpre = incl - rlen;
+    s_rstart[w][lane] = rstart;
+    s_rpre[w][lane] = rpre;
+    const int nch = (total + 63) >> 6;
+    if (nch > kMaskBudget) {
+        if (lane == 0) atomicOr(&a.flags[kFlagBadSlot], 16);
+        return;
+    }
+    const int gmax = nch > 0 ? min(64, kMaskBudget / nch) : 64;
+    const int P = fa.P;
+
+    for (int g0 = 0; g0 < m; g0 += gmax) {
+        const int mg = min(gmax, m - g0);
+        if (lane < mg) {
+            s_ctr[w][lane] = a.xs[i0 + g0 + lane];
+            s_ccnt[w][lane] = 0;
+        }
+        wave_lds_fence();
+        for (int ch = 0; ch < nch; ++ch) {
+            const int f = ch * 64 + lane;
+            int q = 0;
+#pragma unroll
+            for (int step = 32; step > 0; step >>= 1)
+                if (s_rpre[w][q + step] <= f) q += step;
+            const int j = s_rstart[w][q] + (f - s_rpre[w][q]);
+            const bool valid = f < total && j >= 0 && (int64_t)j < a.n_slots;
+            double4 xj = make_double4(0.0, 0.0, 0.0, 0.0);
+            if (valid) xj = a.xs[j];
+            for (int ii = 0; ii < mg; ++ii) {
+                const int islot = i0 + g0 + ii;
+                const double4 xi = s_ctr[w][ii];
+                const Delta d = delta(xi, xj, R);
+                const bool ok = valid && j != islot;
+                const bool in_core = ok && d.r2 < a.thr_core;
+                const bool in_shell = ok && d.r2 >= a.thr_shell_in && d.r2 < a.thr_out;
+                const uint64_t mc = __ballot(in_core);
+                const uint64_t ms = __ballot(in_shell);
+                if (mc) {
+                    const int b0 = s_ccnt[w][ii];
+                    if (in_core) {
+                        const int p = b0 + (int)mbcnt(mc);
+                        if (p < a.cap_core) a.core[ell(islot, p, a.cap_core)] = j;
+                    }
+                    wave_lds_fence();
+                    if (lane == 0) s_ccnt[w][ii] = b0 + (int)__popcll(mc);
+                }
+                if (lane == 0) s_mask[w][ii * nch + ch] = ms;
+            }
+            wave_lds_fence();
+        }
+        // row lengths
+        int cc = 0, ns = 0;
+        if (lane < mg) {
+            cc = s_ccnt[w][lane];
+            for (int ch = 0; ch < nch; ++ch) ns += __popcll(s_mask[w][lane * nch + ch]);
+            a.core_len[i0 + g0 + lane] = min(cc, a.cap_core);
+            a.shell_len[i0 + g0 + lane] = ns;
+            s_ncnt[w][lane] = ns;
+        }
+        wave_lds_fence();
+        const int mxc = wave_max(cc);
+        const int mxs = wave_max(ns);
+        if (lane == 0) {
+            atomicMax(&a.flags[kFlagMaxCore], mxc);
+            atomicMax(&a.flags[kFlagMaxShell], mxs);
+            if (mxc > a.cap_core) atomicOr(&a.flags[kFlagOverflow], 1);
+        }
+        // batches: one lane per (particle, step) pair
+        const int pairs = mg * fa.K;
+        for (int pb = 0; pb < pairs; pb += 64) {
+            const int pr = pb + lane;
+            if (pr < pairs) {
+                const int ii = pr / fa.K;
+                const int rr = pr - ii * fa.K;
+                const int islot = i0 + g0 + ii;
+                const int n = s_ncnt[w][ii];
+                const uint64_t* masks = &s_mask[w][ii * nch];
+                int* out = fa.batch + ((int64_t)rr * P) * a.n_slots + islot;
+                MaskWalker wk = {0, 0, 0};
+                bool bad = false;
+                if (n <= P) {
+                    for (int k = 0; k < n; ++k) {
+                        int j = walk_to(masks, nch, k, wk, s_rstart[w], s_rpre[w]);
+                        if (j < 0 || (int64_t)j >= a.n_slots) {
+                            bad = true;
+                            j = islot;
+                        }
+                        out[(int64_t)k * a.n_slots] = j;
+                    }
+                } else {
+                    uint32_t S[PMAX];
+                    const uint32_t pid = (uint32_t)(fa.perm[islot] - R.id_base);
+                    floyd_draw<PMAX>(S, fa.seed, pid, (uint32_t)(fa.step0 + rr), (uint32_t)rep_id, P, n);
+#pragma unroll
+                    for (int q = 0; q < PMAX; ++q) {
+                        if (q < P) {
+                            int j = walk_to(masks, nch, (int)S[q], wk, s_rstart[w], s_rpre[w]);
+                            if (j < 0 || (int64_t)j >= a.n_slots) {
+                                bad = true;
+                                j = islot;
+                            }
+                            out[(int64_t)q * a.n_slots] = j;
+                        }
+                    }
+                }
+                if (bad) atomicOr(&a.flags[kFlagBadSlot], 32);
+            }
+        }
+        wave_lds_fence();
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Batch pre-draw: for steps step0 .. step0+K-1 the partners of every
 // particle's batch, gathered from its shell row (bit-identical to the draw
 // the inline force kernel makes).
@@ -599,10 +832,45 @@ __device__ __forceinline__ void pair_term(double r2, double qq, double alpha, do
     }
 }
 
+// Accumulates the pair terms of U partners whose indices and positions were
+// fetched together (all gathers in flight before any arithmetic).  A partner
+// counts when `live` and lo2 <= r^2 < hi2; masked partners take r^2 = 1 so
+// that no infinities are formed, and contribute exact zeros.
+struct Acc {
+    double fx, fy, fz, e, w;
+};
+
+template <int PREC, bool ENERGY, bool ERFC, int U>
+__device__ __forceinline__ void accumulate(const double4& xi, const double4 (&xj)[U], const bool (&live)[U],
+                                           double lo2, double hi2, const DevReplica& R,
+                                           const ForceArgs& a, Acc& acc)
+{
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const Delta d = delta(xi, xj[u], R);
+        const bool in = live[u] && d.r2 >= lo2 && d.r2 < hi2;
+        const double r2 = in ? d.r2 : 1.0;
+        double fm, en;
+        pair_term<PREC, ERFC>(r2, xi.w * xj[u].w, a.alpha, fm, en);
+        fm = in ? fm : 0.0;
+        acc.fx += fm * d.x;
+        acc.fy += fm * d.y;
+        acc.fz += fm * d.z;
+        if (ENERGY) {
+            const double shift = ERFC ? a.uc + xi.w * xj[u].w * a.uce : a.uc;
+            acc.e += in ? en - shift : 0.0;
+            acc.w += fm * r2;
+        }
+    }
+}
+
+constexpr int kGatherBatch = 4;
+
 template <int PREC, int MODE, bool ENERGY, bool ERFC, int PMAX>
 __global__ __launch_bounds__(256) void k_forces(ForceArgs a)
 {
     __shared__ uint32_t s_pos[MODE == kShellInline ? PMAX * 256 : 1];
+    constexpr int U = kGatherBatch;
     const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t slice = slot >> 6;
     if (slice >= a.n_slices) return;
@@ -612,24 +880,24 @@ __global__ __launch_bounds__(256) void k_forces(ForceArgs a)
     double fx = 0.0, fy = 0.0, fz = 0.0, e = 0.0, w = 0.0;
     if (real) {
         const double4 xi = a.xs[slot];
-        const double cut_in = MODE == kShellNone ? a.rc2 : a.rs2;
+        // core rows (or the full list in direct-truncation mode): r < cut
+        Acc c = {0.0, 0.0, 0.0, 0.0, 0.0};
         {
+            const double cut = MODE == kShellNone ? a.rc2 : a.rs2;
             const int len = a.core_len[slot];
-            for (int k = 0; k < len; ++k) {
-                const int j = a.core[ell(slot, k, a.cap_core)];
-                const double4 xj = a.xs[j];
-                const Delta d = delta(xi, xj, R);
-                if (d.r2 < cut_in) {
-                    double fm, u;
-                    pair_term<PREC, ERFC>(d.r2, xi.w * xj.w, a.alpha, fm, u);
-                    fx += fm * d.x;
-                    fy += fm * d.y;
-                    fz += fm * d.z;
-                    if (ENERGY) {
-                        e += u - (ERFC ? a.uc + xi.w * xj.w * a.uce : a.uc);
-                        w += fm * d.r2;
-                    }
+            const int* row = a.core + ell(slot, 0, a.cap_core);
+            for (int k = 0; k < len; k += U) {
+                int j[U];
+                bool live[U];
+                double4 xj[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    live[u] = k + u < len;
+                    j[u] = live[u] ? row[(int64_t)(k + u) * 64] : (int)slot;
                 }
+#pragma unroll
+                for (int u = 0; u < U; ++u) xj[u] = a.xs[j[u]];
+                accumulate<PREC, ENERGY, ERFC, U>(xi, xj, live, -1.0, cut, R, a, c);
             }
         }
         if (MODE != kShellNone) {
@@ -644,39 +912,45 @@ __global__ __launch_bounds__(256) void k_forces(ForceArgs a)
 #pragma unroll
                 for (int q = 0; q < PMAX; ++q) s_pos[q * 256 + threadIdx.x] = S[q];
             }
-            double sx = 0.0, sy = 0.0, sz = 0.0, se = 0.0, sw = 0.0;
-            for (int m = 0; m < cnt; ++m) {
-                int j;
-                if (MODE == kShellInline) {
-                    const int k = n > P ? (int)s_pos[m * 256 + threadIdx.x] : m;
-                    j = a.shell[ell(slot, k, a.cap_shell)];
-                } else {
-                    j = a.batch[(int64_t)m * a.n_slots + slot];
-                }
-                const double4 xj = a.xs[j];
-                const Delta d = delta(xi, xj, R);
-                if (d.r2 >= a.rs2 && d.r2 < a.rc2) {
-                    double fm, u;
-                    pair_term<PREC, ERFC>(d.r2, xi.w * xj.w, a.alpha, fm, u);
-                    sx += fm * d.x;
-                    sy += fm * d.y;
-                    sz += fm * d.z;
-                    if (ENERGY) {
-                        se += u - (ERFC ? a.uc + xi.w * xj.w * a.uce : a.uc);
-                        sw += fm * d.r2;
+            Acc sh = {0.0, 0.0, 0.0, 0.0, 0.0};
+            const int* srow = a.shell + ell(slot, 0, a.cap_shell);
+            for (int m = 0; m < cnt; m += U) {
+                int j[U];
+                bool live[U];
+                double4 xj[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    live[u] = m + u < cnt;
+                    int jj = (int)slot;
+                    if (live[u]) {
+                        if (MODE == kShellInline) {
+                            const int kq = n > P ? (int)s_pos[(m + u) * 256 + threadIdx.x] : m + u;
+                            jj = srow[(int64_t)kq * 64];
+                        } else {
+                            jj = a.batch[(int64_t)(m + u) * a.n_slots + slot];
+                        }
                     }
+                    j[u] = jj;
                 }
+#pragma unroll
+                for (int u = 0; u < U; ++u) xj[u] = a.xs[j[u]];
+                accumulate<PREC, ENERGY, ERFC, U>(xi, xj, live, a.rs2, a.rc2, R, a, sh);
             }
-            fx = fx + scale * sx;
-            fy = fy + scale * sy;
-            fz = fz + scale * sz;
+            fx = c.fx + scale * sh.fx;
+            fy = c.fy + scale * sh.fy;
+            fz = c.fz + scale * sh.fz;
             if (ENERGY) {
-                e = 0.5 * (e + scale * se);
-                w = 0.5 * (w + scale * sw);
+                e = 0.5 * (c.e + scale * sh.e);
+                w = 0.5 * (c.w + scale * sh.w);
             }
-        } else if (ENERGY) {
-            e = 0.5 * e;
-            w = 0.5 * w;
+        } else {
+            fx = c.fx;
+            fy = c.fy;
+            fz = c.fz;
+            if (ENERGY) {
+                e = 0.5 * c.e;
+                w = 0.5 * c.w;
+            }
         }
     }
     a.f[slot] = fx;
@@ -699,24 +973,59 @@ __global__ __launch_bounds__(256) void k_forces(ForceArgs a)
     }
 }
 
-// Per-replica sums of the wavefront partials, in a fixed order (the result
-// does not depend on scheduling).  rep_sum[8r + q], q = Fx, Fy, Fz, U, W.
+// Per-replica sums of the wavefront partials in a fixed order, so the result
+// does not depend on scheduling.  Block (b, r) sums slices b*per .. of
+// replica r into part2[r][b]; the last block of a replica to finish (counted
+// with an atomic that it resets) adds the part2 entries in block order.
+// rep_sum[8r + q], q = Fx, Fy, Fz, U, W.
+constexpr int kReduceSlicesPerBlock = 256;
+
 __global__ __launch_bounds__(256) void k_reduce(const DevReplica* rep, const double* partial,
-                                               int64_t n_slices, double* rep_sum)
+                                               int64_t n_slices, int blocks_per_rep, double* part2,
+                                               unsigned* counter, double* rep_sum)
 {
-    __shared__ double lds[4];
-    const DevReplica& R = rep[blockIdx.x];
+    __shared__ double lds[5][4];
+    __shared__ bool is_last;
+    const int r = blockIdx.y;
+    const int b = blockIdx.x;
+    const DevReplica& R = rep[r];
     const int64_t s0 = R.slot_base >> 6;
     const int64_t ns = (R.n + 63) >> 6;
-    for (int q = 0; q < 5; ++q) {
-        double acc = 0.0;
-        for (int64_t s = threadIdx.x; s < ns; s += blockDim.x) acc += partial[q * n_slices + s0 + s];
-        acc = wave_sum(acc);
-        if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = acc;
+    const int64_t lo = (int64_t)b * kReduceSlicesPerBlock;
+    const int64_t hi = min(ns, lo + kReduceSlicesPerBlock);
+    const int wv = threadIdx.x >> 6;
+    const int nb = (int)((ns + kReduceSlicesPerBlock - 1) / kReduceSlicesPerBlock);
+    if (b < nb) {
+        for (int q = 0; q < 5; ++q) {
+            const int64_t s = lo + threadIdx.x;
+            double acc = s < hi ? partial[q * n_slices + s0 + s] : 0.0;
+            acc = wave_sum(acc);
+            if ((threadIdx.x & 63) == 0) lds[q][wv] = acc;
+        }
         __syncthreads();
-        if (threadIdx.x == 0) rep_sum[8 * blockIdx.x + q] = ((lds[0] + lds[1]) + lds[2]) + lds[3];
-        __syncthreads();
+        if (threadIdx.x < 5) {
+            const int q = threadIdx.x;
+            part2[((int64_t)r * blocks_per_rep + b) * 5 + q] = ((lds[q][0] + lds[q][1]) + lds[q][2]) + lds[q][3];
+        }
     }
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned done = atomicAdd(&counter[r], 1u);
+        is_last = done == (unsigned)(blocks_per_rep - 1);
+    }
+    __syncthreads();
+    if (!is_last) return;
+    __threadfence();
+    if (threadIdx.x < 5) {
+        const int q = threadIdx.x;
+        double acc = 0.0;
+        for (int k = 0; k < nb; ++k)
+            acc += __hip_atomic_load(&part2[((int64_t)r * blocks_per_rep + k) * 5 + q], __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_AGENT);
+        rep_sum[8 * r + q] = acc;
+    }
+    if (threadIdx.x == 0) counter[r] = 0u;
 }
 
 // ---------------------------------------------------------------------------

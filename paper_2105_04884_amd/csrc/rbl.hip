@@ -86,6 +86,7 @@ struct rbl_ctx {
     // geometry of the last build
     bool built = false;
     int built_mask = 0;
+    bool shell_counts = false;  // shell_len valid (explicit shell list or fused build)
     double r_s = 0, r_c = 0;
     std::vector<DevReplica> h_rep;
     int64_t n_cells = 0, cells_alloc = 0;
@@ -116,6 +117,9 @@ struct rbl_ctx {
     size_t batch_alloc = 0;
 
     double* d_partial = nullptr;
+    double* d_part2 = nullptr;
+    unsigned* d_red_counter = nullptr;
+    int red_blocks = 1;
     double* d_rep_sum = nullptr;
     int* d_flags = nullptr;
     int h_flags[kNumFlags];
@@ -469,6 +473,7 @@ rbl_status build_lists(rbl_ctx* c, int mask)
         }
         if (!c->h_flags[kFlagOverflow]) {
             c->built_mask = mask;
+            c->shell_counts = (mask & RBL_LIST_SHELL) != 0;
             return RBL_OK;
         }
         for (int q = 0; q < 3; ++q)
@@ -476,6 +481,59 @@ rbl_status build_lists(rbl_ctx* c, int mask)
         need_count = false;
     }
     return fail(RBL_E_CAPACITY, "neighbour rows kept overflowing their capacity");
+}
+
+
+// Core rows + shell counts + the batches of force evaluations step0 ..
+// step0+K-1 in one pass (no shell rows in HBM).
+rbl_status ensure_batch(rbl_ctx* c, int K, int P);
+
+rbl_status build_fused(rbl_ctx* c, int P, uint64_t seed, uint64_t step0, int K)
+{
+    for (int q = 0; q < 2; ++q)
+        if (!c->d_len[q]) RBL_TRY(dalloc(&c->d_len[q], c->n_slots));
+    RBL_TRY(ensure_batch(c, K, P));
+    if (c->cap[0] == 0) {
+        RBL_TRY(clear_list_flags(c));
+        BuildArgs a = build_args(c);
+        RBL_TRY(timed(c, kKBuild, [&] { launch_build<true>(c, a, RBL_LIST_CORE); }));
+        RBL_TRY(read_flags(c));
+        if (c->h_flags[kFlagBadSlot]) return fail(RBL_E_HIP, "inconsistent cell binning");
+        RBL_TRY(ensure_list_storage(c, 0, c->h_flags[kFlagMaxCore]));
+    }
+    for (int attempt = 0; attempt < 3; ++attempt) {
+        RBL_TRY(clear_list_flags(c));
+        FusedArgs fa;
+        fa.b = build_args(c);
+        fa.perm = c->cur_perm();
+        fa.batch = c->d_batch;
+        fa.seed = seed;
+        fa.step0 = step0;
+        fa.K = K;
+        fa.P = P;
+        const unsigned g = grid_for(c->n_cells, 4);
+        RBL_TRY(timed(c, kKBuild, [&] {
+            if (P <= 16) k_build_draw<16><<<g, kBlock, 0, c->stream>>>(fa);
+            else if (P <= 32) k_build_draw<32><<<g, kBlock, 0, c->stream>>>(fa);
+            else if (P <= 64) k_build_draw<64><<<g, kBlock, 0, c->stream>>>(fa);
+            else k_build_draw<128><<<g, kBlock, 0, c->stream>>>(fa);
+        }));
+        RBL_TRY(read_flags(c));
+        if (c->h_flags[kFlagBadSlot] & 16)
+            return fail(RBL_E_CAPACITY, "cell stencil holds too many candidates for the fused build");
+        if (c->h_flags[kFlagBadSlot]) return fail(RBL_E_HIP, "inconsistent cell binning");
+        if (c->h_flags[kFlagNonfinite]) {
+            c->built = false;
+            return fail(RBL_E_NONFINITE, "non-finite particle position at list build");
+        }
+        if (!c->h_flags[kFlagOverflow]) {
+            c->built_mask = RBL_LIST_CORE;
+            c->shell_counts = true;
+            return RBL_OK;
+        }
+        RBL_TRY(ensure_list_storage(c, 0, c->h_flags[kFlagMaxCore]));
+    }
+    return fail(RBL_E_CAPACITY, "core rows kept overflowing their capacity");
 }
 
 // ---------------------------------------------------------------------------
@@ -580,7 +638,8 @@ rbl_status predraw(rbl_ctx* c, int P, uint64_t seed, uint64_t step0, int K)
 rbl_status reduce(rbl_ctx* c)
 {
     return timed(c, kKReduce, [&] {
-        k_reduce<<<c->R, kBlock, 0, c->stream>>>(c->d_rep, c->d_partial, c->n_slices, c->d_rep_sum);
+        k_reduce<<<dim3(c->red_blocks, c->R), kBlock, 0, c->stream>>>(
+            c->d_rep, c->d_partial, c->n_slices, c->red_blocks, c->d_part2, c->d_red_counter, c->d_rep_sum);
     });
 }
 
@@ -734,6 +793,8 @@ rbl_status rbl_destroy(rbl_ctx* c)
     }
     dfree(c->d_batch);
     dfree(c->d_partial);
+    dfree(c->d_part2);
+    dfree(c->d_red_counter);
     dfree(c->d_rep_sum);
     dfree(c->d_flags);
     delete c;
@@ -809,6 +870,13 @@ rbl_status rbl_create(const rbl_config* cfg, void* hip_stream, rbl_ctx** out)
     CR(dalloc(&c->d_xb, 3 * c->n_slots));
     CR(dalloc(&c->d_f, 3 * c->n_slots));
     CR(dalloc(&c->d_partial, 5 * c->n_slices));
+    {
+        int64_t mx = 1;
+        for (int r = 0; r < c->R; ++r) mx = std::max<int64_t>(mx, (c->rep_n[r] + 63) / 64);
+        c->red_blocks = (int)((mx + kReduceSlicesPerBlock - 1) / kReduceSlicesPerBlock);
+    }
+    CR(dalloc(&c->d_part2, (size_t)5 * c->red_blocks * c->R));
+    CR(dalloc(&c->d_red_counter, c->R));
     CR(dalloc(&c->d_rep_sum, 8 * c->R));
     CR(dalloc(&c->d_flags, kNumFlags));
     {
@@ -827,6 +895,7 @@ rbl_status rbl_create(const rbl_config* cfg, void* hip_stream, rbl_ctx** out)
     CR(fill_i32(c, c->d_perm[0], c->n_slots, -1));
     CR(fill_i32(c, c->d_perm[1], c->n_slots, -1));
     CR(fill_i32(c, c->d_flags, kNumFlags, 0));
+    CR(fill_i32(c, (int*)c->d_red_counter, c->R, 0));
     if (hipStreamSynchronize(c->stream) != hipSuccess) return bail(fail(RBL_E_HIP, "stream sync failed"));
 #undef CR
     *out = c;
@@ -840,6 +909,7 @@ rbl_status rbl_build(rbl_ctx* c, const double* pos, const double* box, double r_
         return fail(RBL_E_ARG, "radii must satisfy 0 < r_s < r_c");
     RBL_TRY(setup_geometry(c, box, r_s, r_c));
     c->built = false;
+    c->shell_counts = false;
     RBL_TRY(clear_flags(c));
     RBL_TRY(bin_particles<kSrcCaller>(c, pos, nullptr, false));
     RBL_TRY(build_lists(c, c->cfg.lists));
@@ -908,16 +978,17 @@ rbl_status rbl_step(rbl_ctx* c, double* pos, double* vel, double* force, int64_t
         if (from_caller) RBL_TRY(bin_particles<kSrcCaller>(c, pos, vel, true));
         else RBL_TRY(bin_particles<kSrcSorted>(c, nullptr, nullptr, true));
         c->built = false;
-        RBL_TRY(build_lists(c, mask));
-        c->built = true;
         build_step = s;
         if (pre) {
             // batches for every force evaluation until the next rebuild
-            int64_t until = (s / K + 1) * K;
-            int64_t last = step0 + nsteps;
-            int64_t cnt = std::min(until, last + 1) - s;
-            RBL_TRY(predraw(c, P, seed, (uint64_t)s, (int)cnt));
+            const int64_t until = (s / K + 1) * K;
+            const int64_t last = step0 + nsteps;
+            const int64_t cnt = std::min(until, last + 1) - s;
+            RBL_TRY(build_fused(c, P, seed, (uint64_t)s, (int)cnt));
+        } else {
+            RBL_TRY(build_lists(c, mask));
         }
+        c->built = true;
         return RBL_OK;
     };
     auto do_force = [&](int64_t s, bool energy) -> rbl_status {
@@ -976,7 +1047,8 @@ rbl_status rbl_row_counts(rbl_ctx* c, int64_t nrows, const int64_t* rows, int64_
     }
     (void)hipMemcpyAsync(d_rows, h_rows.data(), sizeof(int64_t) * nrows, hipMemcpyHostToDevice, c->stream);
     for (int q = 0; q < 3; ++q) {
-        const int* len = (c->built_mask >> q) & 1 ? c->d_len[q] : nullptr;
+        const bool valid = q == 1 ? c->shell_counts : ((c->built_mask >> q) & 1) != 0;
+        const int* len = valid ? c->d_len[q] : nullptr;
         k_row_counts<<<grid_for(nrows), kBlock, 0, c->stream>>>(d_rows, nrows, c->d_slot_of_id, len, d_cnt);
         (void)hipMemcpyAsync(counts + q * nrows, d_cnt, sizeof(int64_t) * nrows, hipMemcpyDeviceToHost,
                              c->stream);
