@@ -6,7 +6,7 @@
 //   perm      int[n_slots]       slot -> caller ID (-1 = padding slot)
 //   lists     int[n_slices][cap][64] sliced ELL, partner slots in row order
 //   len       int[n_slots]       row lengths
-//   batch     int[K][P][n_slots] pre-drawn shell partners (slots)
+//   batch     int[K][n_slots][P] pre-drawn shell partners (slots)
 //   partial   double[5][n_slices] per-wavefront sums (Fx, Fy, Fz, U, W)
 #pragma once
 
@@ -19,6 +19,31 @@ enum { kShellNone = 0, kShellInline = 1, kShellPredraw = 2 };
 enum { kIntFirst = 0, kIntMid = 1, kIntLast = 2 };
 enum { kFlagOverflow = 0, kFlagMaxCore = 1, kFlagMaxShell = 2, kFlagMaxFull = 3,
        kFlagNonfinite = 4, kFlagSkin = 5, kFlagBadSlot = 6, kNumFlags = 8 };
+
+// Block -> work-tile map that gives XCD x (blocks x, x+8, ...) a contiguous
+// range of tiles.
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t nb)
+{
+    const int64_t x = b & 7;
+    const int64_t q = nb >> 3;
+    const int64_t r = nb & 7;
+    return x * q + (x < r ? x : r) + (b >> 3);
+}
+
+// Raises *p to v.  Every wavefront reports its longest row here, and atomics
+// on one address serialise in L2, so the atomic is issued only when v
+// exceeds the value already stored (a relaxed read; the maximum grows a few
+// times per launch).
+__device__ __forceinline__ void raise_max(int* p, int v)
+{
+    if (v > __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(p, v);
+}
+
+// Sets *p to 1 unless it is already set (same reasoning as raise_max).
+__device__ __forceinline__ void raise_flag(int* p)
+{
+    if (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) atomicOr(p, 1);
+}
 
 __global__ void k_fill_i32(int* p, int64_t n, int v)
 {
@@ -73,7 +98,7 @@ __global__ __launch_bounds__(256) void k_bin_count(BinArgs a)
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         if (!isfinite(x[d])) {
-            atomicOr(&a.flags[kFlagNonfinite], 1);
+            raise_flag(&a.flags[kFlagNonfinite]);
             x[d] = 0.0;
         }
         const double w = wrap_coord(x[d], R.L[d], R.inv[d]);
@@ -489,44 +514,44 @@ __global__ __launch_bounds__(256) void k_build(BuildArgs a)
             if (mine && !COUNT_ONLY) a.core_len[islot] = min(cnt_c, a.cap_core);
             const int mx = wave_max(mine ? cnt_c : 0);
             if (lane == 0) {
-                atomicMax(&a.flags[kFlagMaxCore], mx);
-                if (!COUNT_ONLY && mx > a.cap_core) atomicOr(&a.flags[kFlagOverflow], 1);
+                raise_max(&a.flags[kFlagMaxCore], mx);
+                if (!COUNT_ONLY && mx > a.cap_core) raise_flag(&a.flags[kFlagOverflow]);
             }
         }
         if (WS) {
             if (mine && !COUNT_ONLY) a.shell_len[islot] = min(cnt_s, a.cap_shell);
             const int mx = wave_max(mine ? cnt_s : 0);
             if (lane == 0) {
-                atomicMax(&a.flags[kFlagMaxShell], mx);
-                if (!COUNT_ONLY && mx > a.cap_shell) atomicOr(&a.flags[kFlagOverflow], 1);
+                raise_max(&a.flags[kFlagMaxShell], mx);
+                if (!COUNT_ONLY && mx > a.cap_shell) raise_flag(&a.flags[kFlagOverflow]);
             }
         }
         if (WF) {
             if (mine && !COUNT_ONLY) a.full_len[islot] = min(cnt_f, a.cap_full);
             const int mx = wave_max(mine ? cnt_f : 0);
             if (lane == 0) {
-                atomicMax(&a.flags[kFlagMaxFull], mx);
-                if (!COUNT_ONLY && mx > a.cap_full) atomicOr(&a.flags[kFlagOverflow], 1);
+                raise_max(&a.flags[kFlagMaxFull], mx);
+                if (!COUNT_ONLY && mx > a.cap_full) raise_flag(&a.flags[kFlagOverflow]);
             }
         }
     }
 }
 
 // ---------------------------------------------------------------------------
-// Fused list build + batch draw (the molecular-dynamics loop path).  As in
-// k_build, one wavefront per centre cell walks the 5x5x5 stencil, but only
-// the core rows go to HBM: shell membership stays in LDS as one 64-bit ballot
-// mask per (centre particle, candidate chunk).  Its popcount is n_i, and the
-// batches of the next K force evaluations are drawn right away (one lane per
-// (particle, step) pair), the k-th shell partner being found by walking the
-// masks.  Bit-identical to k_build + k_predraw, without writing or re-reading
-// the shell rows.
+// Batches in HBM: batch[(rr * n_slots + slot) * P + m] is the m-th partner
+// (slot) of the particle in `slot` for the rr-th force evaluation after the
+// build; a particle's P partners are contiguous.
+__device__ __forceinline__ int64_t batch_index(int rr, int64_t slot, int m, int64_t n_slots, int P)
+{
+    return ((int64_t)rr * n_slots + slot) * P + m;
+}
+
 constexpr int kMaskBudget = 512;  // 64-bit masks per wavefront
 
 struct FusedArgs {
     BuildArgs b;
     const int* perm;
-    int* batch;        // [K][P][n_slots]
+    int* batch;        // [K][n_slots][P]
     uint64_t seed;
     uint64_t step0;
     int K;
@@ -557,41 +582,74 @@ __device__ __forceinline__ int select_bit(uint64_t w, int r)
     return pos;
 }
 
-// Walks a particle's shell masks in increasing order: returns the slot of
-// the k-th shell candidate (k non-decreasing between calls).
-struct MaskWalker {
-    int c;    // current chunk
-    int cum;  // set bits before chunk c
-    int q;    // current run
+// ---------------------------------------------------------------------------
+// Fused list build + batch draw (the molecular-dynamics loop path).  As in
+// k_build, one wavefront per centre cell walks the 5x5x5 stencil, but only
+// the core rows go to HBM: shell membership stays in LDS as one 64-bit ballot
+// mask per (centre particle, candidate chunk).  Its popcount is n_i, and the
+// batches of the next K force evaluations are drawn right away (one lane per
+// (particle, step) pair), the k-th shell partner being found by walking the
+// masks.  Bit-identical to k_build + k_predraw, without writing or re-reading
+// the shell rows.  Inner-loop details:
+//  - the periodic image of every candidate run is known from the stencil
+//    geometry when every axis has >= 7 cells, so dx = (x_i - x_j) + s with
+//    s in {-L, 0, L} exactly equals the canonical fma(-rint(d/L), L, d);
+//    smaller grids use the canonical formula per pair;
+//  - the core/shell ballot masks of centre particle ii go to lane ii of four
+//    VGPRs, written to LDS once per chunk;
+//  - core rows are scattered once per chunk by the centre-particle lanes,
+//    each walking its own mask bits (the partner slot comes from the owning
+//    lane via ds_bpermute);
+//  - the next chunk's candidates are fetched before the current chunk is
+//    tested;
+//  - centre cells are mapped to blocks so that each XCD works on a
+//    contiguous range of cells (its L2 keeps the neighbourhood).
+struct AxisRunsS {
+    int p0, l0, p1, l1;
+    int s0, s1;  // image shift (in box lengths, added to x_i - x_j) of run 0 / run 1
 };
 
-__device__ __forceinline__ int walk_to(const uint64_t* masks, int nch, int k, MaskWalker& wk,
-                                       const int* rstart, const int* rpre)
+__device__ __forceinline__ AxisRunsS axis_runs_s(int c, int nc)
 {
-    int pc = __popcll(masks[wk.c]);
-    while (wk.cum + pc <= k && wk.c < nch - 1) {
-        wk.cum += pc;
-        ++wk.c;
-        pc = __popcll(masks[wk.c]);
+    AxisRunsS a;
+    const AxisRuns b = axis_runs(c, nc);
+    a.p0 = b.p0;
+    a.l0 = b.l0;
+    a.p1 = b.p1;
+    a.l1 = b.l1;
+    a.s0 = 0;
+    a.s1 = 0;
+    if (nc > 5) {
+        const int lo = c - 2, hi = c + 2;
+        if (lo < 0) {
+            a.s1 = 1;   // cells lo+nc..nc-1 are images one box below
+        } else if (hi > nc - 1) {
+            a.s0 = -1;  // cells 0..hi-nc are images one box above
+        }
     }
-    const int f = wk.c * 64 + select_bit(masks[wk.c], k - wk.cum);
-    while (wk.q < 63 && rpre[wk.q + 1] <= f) ++wk.q;
-    return rstart[wk.q] + (f - rpre[wk.q]);
+    return a;
+}
+
+__device__ __forceinline__ int axis_shift(const AxisRunsS& a, int k)
+{
+    return k < a.l0 ? a.s0 : a.s1;
 }
 
 template <int PMAX>
-__global__ __launch_bounds__(256) void k_build_draw(FusedArgs fa)
+__global__ __launch_bounds__(256) void k_build_draw2(FusedArgs fa)
 {
     __shared__ double4 s_ctr[4][64];
-    __shared__ uint64_t s_mask[4][kMaskBudget];
+    __shared__ ulonglong2 s_mask[4][kMaskBudget / 2];  // (core, shell) per (ii, chunk)
     __shared__ int s_rstart[4][64];
     __shared__ int s_rpre[4][64];
-    __shared__ int s_ccnt[4][64];
+    __shared__ int s_rshift[4][64];                     // packed image shifts of each run
     __shared__ int s_ncnt[4][64];
+    __shared__ int s_cum[4][kMaskBudget / 2];           // shell-rank prefix per (ii, chunk)
     const BuildArgs& a = fa.b;
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t cell = (int64_t)blockIdx.x * 4 + w;
+    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int64_t cell = tile * 4 + w;
     if (cell >= a.n_cells) return;
     const int m = a.cell_count[cell];
     if (m == 0) return;
@@ -606,20 +664,21 @@ __global__ __launch_bounds__(256) void k_build_draw(FusedArgs fa)
     const int cx = (int)(lc % R.nc[0]);
     const int cy = (int)((lc / R.nc[0]) % R.nc[1]);
     const int cz = (int)(lc / ((int64_t)R.nc[0] * R.nc[1]));
-    const AxisRuns ax = axis_runs(cx, R.nc[0]);
-    const AxisRuns ay = axis_runs(cy, R.nc[1]);
-    const AxisRuns az = axis_runs(cz, R.nc[2]);
+    const AxisRunsS ax = axis_runs_s(cx, R.nc[0]);
+    const AxisRunsS ay = axis_runs_s(cy, R.nc[1]);
+    const AxisRunsS az = axis_runs_s(cz, R.nc[2]);
+    const bool shift_path = R.nc[0] >= 7 && R.nc[1] >= 7 && R.nc[2] >= 7;
     const int ny_s = ay.l0 + ay.l1;
     const int nz_s = az.l0 + az.l1;
-    int rstart = 0, rlen = 0;
+    int rstart = 0, rlen = 0, rshift = 0;
     {
         const int q = lane;
         const int zi = q / (2 * ny_s);
         const int yi = (q >> 1) % ny_s;
         const int xr = q & 1;
         if (zi < nz_s) {
-            const int zc = axis_cell(az, zi);
-            const int yc = axis_cell(ay, yi);
+            const int zc = axis_cell(AxisRuns{az.p0, az.l0, az.p1, az.l1}, zi);
+            const int yc = axis_cell(AxisRuns{ay.p0, ay.l0, ay.p1, ay.l1}, yi);
             const int px = xr == 0 ? ax.p0 : ax.p1;
             const int lx = xr == 0 ? ax.l0 : ax.l1;
             if (lx > 0) {
@@ -629,78 +688,125 @@ __global__ __launch_bounds__(256) void k_build_draw(FusedArgs fa)
                 rstart = a.cell_start[c0];
                 rlen = a.cell_start[c1] + a.cell_count[c1] - rstart;
             }
+            const int sx = xr == 0 ? ax.s0 : ax.s1;
+            const int sy = axis_shift(ay, yi);
+            const int sz = axis_shift(az, zi);
+            rshift = (sx + 1) | ((sy + 1) << 2) | ((sz + 1) << 4);
         }
     }
     const int incl = wave_incl_scan(rlen);
     const int total = __builtin_amdgcn_readlane(incl, 63);
-    const int rpre = incl - rlen;
     s_rstart[w][lane] = rstart;
-    s_rpre[w][lane] = rpre;
+    s_rpre[w][lane] = incl - rlen;
+    s_rshift[w][lane] = rshift;
     const int nch = (total + 63) >> 6;
-    if (nch > kMaskBudget) {
+    if (nch > kMaskBudget / 2) {
         if (lane == 0) atomicOr(&a.flags[kFlagBadSlot], 16);
         return;
     }
-    const int gmax = nch > 0 ? min(64, kMaskBudget / nch) : 64;
+    const int gmax = nch > 0 ? min(64, (kMaskBudget / 2) / nch) : 64;
     const int P = fa.P;
+    wave_lds_fence();
+
+    // candidate f of the flattened stencil: its slot, position and the packed
+    // periodic image shift of its run (j = -1 past the end of the stencil)
+    auto candidate = [&](int f, int& j, double4& xj, int& code) {
+        int q = 0;
+#pragma unroll
+        for (int step = 32; step > 0; step >>= 1)
+            if (s_rpre[w][q + step] <= f) q += step;
+        j = s_rstart[w][q] + (f - s_rpre[w][q]);
+        code = s_rshift[w][q];
+        const bool valid = f < total && j >= 0 && (int64_t)j < a.n_slots;
+        if (valid) {
+            xj = a.xs[j];
+        } else {
+            j = -1;
+            xj = make_double4(1.0e30, 1.0e30, 1.0e30, 0.0);
+            code = 1 | (1 << 2) | (1 << 4);
+        }
+    };
 
     for (int g0 = 0; g0 < m; g0 += gmax) {
         const int mg = min(gmax, m - g0);
-        if (lane < mg) {
-            s_ctr[w][lane] = a.xs[i0 + g0 + lane];
-            s_ccnt[w][lane] = 0;
+        if (lane < mg) s_ctr[w][lane] = a.xs[i0 + g0 + lane];
+        wave_lds_fence();
+        int cnt_core = 0;  // lane ii: entries written to particle ii's core row
+        const int my_slot = i0 + g0 + lane;
+        int jn = -1, coden = 0;
+        double4 xn = make_double4(0.0, 0.0, 0.0, 0.0);
+        if (nch > 0) candidate(lane, jn, xn, coden);
+        for (int ch = 0; ch < nch; ++ch) {
+            const int jc = jn;
+            const double4 xc = xn;
+            const int code = coden;
+            if (ch + 1 < nch) candidate((ch + 1) * 64 + lane, jn, xn, coden);
+            const double shx = (double)((code & 3) - 1) * R.L[0];
+            const double shy = (double)(((code >> 2) & 3) - 1) * R.L[1];
+            const double shz = (double)(((code >> 4) & 3) - 1) * R.L[2];
+            uint32_t mclo = 0, mchi = 0, mslo = 0, mshi = 0;
+            for (int ii = 0; ii < mg; ++ii) {
+                const double4 xi = s_ctr[w][ii];
+                double dx, dy, dz;
+                if (shift_path) {
+                    dx = (xi.x - xc.x) + shx;
+                    dy = (xi.y - xc.y) + shy;
+                    dz = (xi.z - xc.z) + shz;
+                } else {
+                    dx = min_image(xi.x - xc.x, R.L[0], R.inv[0]);
+                    dy = min_image(xi.y - xc.y, R.L[1], R.inv[1]);
+                    dz = min_image(xi.z - xc.z, R.L[2], R.inv[2]);
+                }
+                const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+                const bool notself = jc >= 0 && jc != i0 + g0 + ii;
+                const uint64_t mc = __ballot(notself && r2 < a.thr_core);
+                const uint64_t ms = __ballot(notself && r2 >= a.thr_shell_in && r2 < a.thr_out);
+                const bool mine = lane == ii;
+                mclo = mine ? (uint32_t)mc : mclo;
+                mchi = mine ? (uint32_t)(mc >> 32) : mchi;
+                mslo = mine ? (uint32_t)ms : mslo;
+                mshi = mine ? (uint32_t)(ms >> 32) : mshi;
+            }
+            uint64_t mcore = ((uint64_t)mchi << 32) | mclo;
+            const uint64_t mshell = ((uint64_t)mshi << 32) | mslo;
+            if (lane < mg) s_mask[w][lane * nch + ch] = make_ulonglong2(mcore, mshell);
+            // core scatter: lane ii appends the partners of its set bits
+            if (lane >= mg) mcore = 0;
+            while (__ballot(mcore != 0)) {
+                const int b = mcore ? (int)__builtin_ctzll(mcore) : 0;
+                const int jb = shfl_i32(jc, b);
+                if (mcore) {
+                    if (cnt_core < a.cap_core) a.core[ell(my_slot, cnt_core, a.cap_core)] = jb;
+                    ++cnt_core;
+                    mcore &= mcore - 1;
+                }
+            }
         }
         wave_lds_fence();
-        for (int ch = 0; ch < nch; ++ch) {
-            const int f = ch * 64 + lane;
-            int q = 0;
-#pragma unroll
-            for (int step = 32; step > 0; step >>= 1)
-                if (s_rpre[w][q + step] <= f) q += step;
-            const int j = s_rstart[w][q] + (f - s_rpre[w][q]);
-            const bool valid = f < total && j >= 0 && (int64_t)j < a.n_slots;
-            double4 xj = make_double4(0.0, 0.0, 0.0, 0.0);
-            if (valid) xj = a.xs[j];
-            for (int ii = 0; ii < mg; ++ii) {
-                const int islot = i0 + g0 + ii;
-                const double4 xi = s_ctr[w][ii];
-                const Delta d = delta(xi, xj, R);
-                const bool ok = valid && j != islot;
-                const bool in_core = ok && d.r2 < a.thr_core;
-                const bool in_shell = ok && d.r2 >= a.thr_shell_in && d.r2 < a.thr_out;
-                const uint64_t mc = __ballot(in_core);
-                const uint64_t ms = __ballot(in_shell);
-                if (mc) {
-                    const int b0 = s_ccnt[w][ii];
-                    if (in_core) {
-                        const int p = b0 + (int)mbcnt(mc);
-                        if (p < a.cap_core) a.core[ell(islot, p, a.cap_core)] = j;
-                    }
-                    wave_lds_fence();
-                    if (lane == 0) s_ccnt[w][ii] = b0 + (int)__popcll(mc);
-                }
-                if (lane == 0) s_mask[w][ii * nch + ch] = ms;
-            }
-            wave_lds_fence();
-        }
-        // row lengths
-        int cc = 0, ns = 0;
+        // row lengths, shell counts and, per particle, the exclusive prefix of
+        // shell-mask popcounts over the chunks (rank -> chunk lookup)
+        int ns = 0;
         if (lane < mg) {
-            cc = s_ccnt[w][lane];
-            for (int ch = 0; ch < nch; ++ch) ns += __popcll(s_mask[w][lane * nch + ch]);
-            a.core_len[i0 + g0 + lane] = min(cc, a.cap_core);
-            a.shell_len[i0 + g0 + lane] = ns;
+            for (int ch = 0; ch < nch; ++ch) {
+                s_cum[w][lane * nch + ch] = ns;
+                ns += __popcll(s_mask[w][lane * nch + ch].y);
+            }
+            a.core_len[my_slot] = min(cnt_core, a.cap_core);
+            a.shell_len[my_slot] = ns;
             s_ncnt[w][lane] = ns;
         }
         wave_lds_fence();
-        const int mxc = wave_max(cc);
+        const int mxc = wave_max(lane < mg ? cnt_core : 0);
         const int mxs = wave_max(ns);
         if (lane == 0) {
-            atomicMax(&a.flags[kFlagMaxCore], mxc);
-            atomicMax(&a.flags[kFlagMaxShell], mxs);
-            if (mxc > a.cap_core) atomicOr(&a.flags[kFlagOverflow], 1);
+            raise_max(&a.flags[kFlagMaxCore], mxc);
+            raise_max(&a.flags[kFlagMaxShell], mxs);
+            if (mxc > a.cap_core) raise_flag(&a.flags[kFlagOverflow]);
         }
-        // batches: one lane per (particle, step) pair
+        // batches: one lane per (particle, step) pair.  Each drawn rank k is
+        // located independently (fixed-step binary searches, so the P
+        // lookups of a lane overlap): chunk by the popcount prefix, bit by
+        // select, run by the run prefix.
         const int pairs = mg * fa.K;
         for (int pb = 0; pb < pairs; pb += 64) {
             const int pr = pb + lane;
@@ -709,34 +815,39 @@ __global__ __launch_bounds__(256) void k_build_draw(FusedArgs fa)
                 const int rr = pr - ii * fa.K;
                 const int islot = i0 + g0 + ii;
                 const int n = s_ncnt[w][ii];
-                const uint64_t* masks = &s_mask[w][ii * nch];
-                int* out = fa.batch + ((int64_t)rr * P) * a.n_slots + islot;
-                MaskWalker wk = {0, 0, 0};
+                const ulonglong2* mk = &s_mask[w][ii * nch];
+                const int* cum = &s_cum[w][ii * nch];
+                int* out = fa.batch + batch_index(rr, islot, 0, a.n_slots, P);
                 bool bad = false;
-                if (n <= P) {
-                    for (int k = 0; k < n; ++k) {
-                        int j = walk_to(masks, nch, k, wk, s_rstart[w], s_rpre[w]);
-                        if (j < 0 || (int64_t)j >= a.n_slots) {
-                            bad = true;
-                            j = islot;
-                        }
-                        out[(int64_t)k * a.n_slots] = j;
+                auto lookup = [&](int k) -> int {
+                    // nch <= kMaskBudget / 2 = 256: eight fixed steps
+                    int c = 0;
+#pragma unroll
+                    for (int st = 128; st > 0; st >>= 1) {
+                        const int t = min(c + st, nch - 1);
+                        c = (c + st < nch && cum[t] <= k) ? c + st : c;
                     }
+                    const int f = c * 64 + select_bit(mk[c].y, k - cum[c]);
+                    int q = 0;
+#pragma unroll
+                    for (int st = 32; st > 0; st >>= 1)
+                        if (s_rpre[w][q + st] <= f) q += st;
+                    int j = s_rstart[w][q] + (f - s_rpre[w][q]);
+                    if (j < 0 || (int64_t)j >= a.n_slots) {
+                        bad = true;
+                        j = islot;
+                    }
+                    return j;
+                };
+                if (n <= P) {
+                    for (int k = 0; k < n; ++k) out[k] = lookup(k);
                 } else {
                     uint32_t S[PMAX];
                     const uint32_t pid = (uint32_t)(fa.perm[islot] - R.id_base);
                     floyd_draw<PMAX>(S, fa.seed, pid, (uint32_t)(fa.step0 + rr), (uint32_t)rep_id, P, n);
 #pragma unroll
-                    for (int q = 0; q < PMAX; ++q) {
-                        if (q < P) {
-                            int j = walk_to(masks, nch, (int)S[q], wk, s_rstart[w], s_rpre[w]);
-                            if (j < 0 || (int64_t)j >= a.n_slots) {
-                                bad = true;
-                                j = islot;
-                            }
-                            out[(int64_t)q * a.n_slots] = j;
-                        }
-                    }
+                    for (int qq = 0; qq < PMAX; ++qq)
+                        if (qq < P) out[qq] = lookup((int)S[qq]);
                 }
                 if (bad) atomicOr(&a.flags[kFlagBadSlot], 32);
             }
@@ -762,7 +873,7 @@ struct DrawArgs {
     uint64_t step0;
     int K;
     int P;
-    int* batch;  // [K][P][n_slots]
+    int* batch;  // [K][n_slots][P]
 };
 
 template <int PMAX>
@@ -777,15 +888,15 @@ __global__ __launch_bounds__(256) void k_predraw(DrawArgs a)
     const uint32_t pid = (uint32_t)(a.perm[slot] - R.id_base);
     const int P = a.P;
     for (int rr = 0; rr < a.K; ++rr) {
-        int* out = a.batch + (int64_t)rr * P * a.n_slots + slot;
+        int* out = a.batch + batch_index(rr, slot, 0, a.n_slots, P);
         if (n <= P) {
-            for (int q = 0; q < n; ++q) out[(int64_t)q * a.n_slots] = a.shell[ell(slot, q, a.cap_shell)];
+            for (int q = 0; q < n; ++q) out[q] = a.shell[ell(slot, q, a.cap_shell)];
         } else {
             uint32_t S[PMAX];
             floyd_draw<PMAX>(S, a.seed, pid, (uint32_t)(a.step0 + rr), (uint32_t)rep_id, P, n);
 #pragma unroll
             for (int q = 0; q < PMAX; ++q)
-                if (q < P) out[(int64_t)q * a.n_slots] = a.shell[ell(slot, (int)S[q], a.cap_shell)];
+                if (q < P) out[q] = a.shell[ell(slot, (int)S[q], a.cap_shell)];
         }
     }
 }
@@ -807,7 +918,7 @@ struct ForceArgs {
     const int* shell;      // shell list (inline) or full list (full mode)
     const int* shell_len;
     int cap_shell;
-    const int* batch;      // pre-drawn: [P][n_slots] for this step
+    const int* batch;      // pre-drawn: [n_slots][P] for this step
     int64_t n_slots;
     int64_t n_slices;
     double rs2, rc2, uc;   // core radius^2, cut-off^2, LJ energy at the cut-off
@@ -871,7 +982,7 @@ __global__ __launch_bounds__(256) void k_forces(ForceArgs a)
 {
     __shared__ uint32_t s_pos[MODE == kShellInline ? PMAX * 256 : 1];
     constexpr int U = kGatherBatch;
-    const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t slot = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     const int64_t slice = slot >> 6;
     if (slice >= a.n_slices) return;
     const int rep_id = a.slice_rep[slice];
@@ -927,7 +1038,7 @@ __global__ __launch_bounds__(256) void k_forces(ForceArgs a)
                             const int kq = n > P ? (int)s_pos[(m + u) * 256 + threadIdx.x] : m + u;
                             jj = srow[(int64_t)kq * 64];
                         } else {
-                            jj = a.batch[(int64_t)(m + u) * a.n_slots + slot];
+                            jj = a.batch[slot * P + m + u];
                         }
                     }
                     j[u] = jj;
@@ -1085,7 +1196,7 @@ __global__ __launch_bounds__(256) void k_integrate(IntArgs a)
         const double dx = x.x - a.xb[s];
         const double dy = x.y - a.xb[a.n_slots + s];
         const double dz = x.z - a.xb[2 * a.n_slots + s];
-        if (dx * dx + dy * dy + dz * dz > a.half_skin2) atomicOr(&a.flags[kFlagSkin], 1);
+        if (dx * dx + dy * dy + dz * dz > a.half_skin2) raise_flag(&a.flags[kFlagSkin]);
     }
 }
 

@@ -513,10 +513,13 @@ rbl_status build_fused(rbl_ctx* c, int P, uint64_t seed, uint64_t step0, int K)
         fa.P = P;
         const unsigned g = grid_for(c->n_cells, 4);
         RBL_TRY(timed(c, kKBuild, [&] {
-            if (P <= 16) k_build_draw<16><<<g, kBlock, 0, c->stream>>>(fa);
-            else if (P <= 32) k_build_draw<32><<<g, kBlock, 0, c->stream>>>(fa);
-            else if (P <= 64) k_build_draw<64><<<g, kBlock, 0, c->stream>>>(fa);
-            else k_build_draw<128><<<g, kBlock, 0, c->stream>>>(fa);
+            if (P <= 8) k_build_draw2<8><<<g, kBlock, 0, c->stream>>>(fa);
+            else if (P <= 12) k_build_draw2<12><<<g, kBlock, 0, c->stream>>>(fa);
+            else if (P <= 16) k_build_draw2<16><<<g, kBlock, 0, c->stream>>>(fa);
+            else if (P <= 24) k_build_draw2<24><<<g, kBlock, 0, c->stream>>>(fa);
+            else if (P <= 32) k_build_draw2<32><<<g, kBlock, 0, c->stream>>>(fa);
+            else if (P <= 64) k_build_draw2<64><<<g, kBlock, 0, c->stream>>>(fa);
+            else k_build_draw2<128><<<g, kBlock, 0, c->stream>>>(fa);
         }));
         RBL_TRY(read_flags(c));
         if (c->h_flags[kFlagBadSlot] & 16)
@@ -1142,7 +1145,7 @@ rbl_status rbl_export_batches(rbl_ctx* c, int P, uint64_t seed, uint64_t step, i
         const int cnt = std::min(h_len[slot], P);
         count[k] = cnt;
         for (int m = 0; m < P; ++m)
-            batch[k * P + m] = m < cnt ? h_perm[h_batch[(size_t)m * c->n_slots + slot]] : -1;
+            batch[k * P + m] = m < cnt ? h_perm[h_batch[(size_t)slot * P + m]] : -1;
     }
     return RBL_OK;
 }
