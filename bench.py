@@ -89,6 +89,7 @@ def run_variant(name, x0, v0, box, precision, P, use_full, steps, warmup, torch)
     stats = {k: ctx.kernel_stats(q) for k, q in kinds.items()}
     ctx.set_profiling(False)
     info = ctx.info()
+    tuning = ctx.tuning()
     counts = ctx.row_counts()
     ctx.close()
     mean = {"core": float(counts[0].mean()), "shell": float(counts[1].mean()),
@@ -102,6 +103,7 @@ def run_variant(name, x0, v0, box, precision, P, use_full, steps, warmup, torch)
                            "avg_us": 1e3 * s[1] / s[0] if s[0] else 0.0} for k, s in stats.items()},
         "mean_row": mean,
         "caps": info,
+        "tuning": tuning,
     }
     log(f"[bench] {name}: {res['ms_per_step']:.4f} ms/step, {res['atom_steps_per_s']:.3e} atom-steps/s")
     return res
@@ -243,7 +245,7 @@ def main():
                                             if s["launches"]},
                          "kernels_total_ms": {q: round(s["total_ms"], 3) for q, s in r["kernels_ms"].items()
                                               if s["launches"]},
-                         "mean_row": r["mean_row"]}
+                         "mean_row": r["mean_row"], "tuning": r["tuning"]}
                      for k, r in results.items()},
         "speedup_rbl_mixed_vs_full_fp64": (speed("rbl_mixed_p10") / speed("full_fp64")
                                            if speed("rbl_mixed_p10") and speed("full_fp64") else None),

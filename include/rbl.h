@@ -79,8 +79,19 @@ typedef struct rbl_config {
                                   RBL force (default 1; Sec. II, Appendix A) */
     int32_t predraw;           /* 1: rbl_step draws the batches of a whole list lifetime at
                                   each rebuild (bit-identical to drawing inline; default 1) */
+    int32_t graphs;            /* 1: rbl_step replays each list lifetime as a captured HIP
+                                  graph on an internal stream (default 1; not while
+                                  per-kernel profiling is on) */
+    int32_t lanes;             /* lanes per particle of the pre-drawn RBL and full-list force
+                                  kernels: 1, 2 or 4; 0 (default) lets the first rbl_step of
+                                  the context time the three and keep the fastest (see
+                                  rbl_tuning).  The choice changes the order of the per-
+                                  particle sums, so bit-identical runs need the same value. */
     int32_t reserved0;
-    double capacity_factor;    /* headroom of list rows over the longest row seen (default 1.25) */
+    double capacity_factor;    /* rows are first sized to capacity_factor x the longest row
+                                  seen + 8 (default 1.25); rows that overflow later are regrown
+                                  (rbl_build) or the run is repeated with longer rows
+                                  (rbl_step), so results never depend on it */
     const int64_t* replica_offsets; /* host, n_replicas + 1 prefix offsets into the particle
                                        arrays; NULL when n_replicas == 1 */
     const double* charges;     /* device, n charges in caller order, or NULL (all zero) */
@@ -195,6 +206,13 @@ rbl_status rbl_sync(rbl_ctx* ctx);
  * milliseconds since profiling was enabled; it synchronises. */
 rbl_status rbl_set_profiling(rbl_ctx* ctx, int on);
 rbl_status rbl_kernel_stats(rbl_ctx* ctx, int kind, int64_t* launches, double* total_ms);
+
+/* Lanes per particle chosen for the RBL (pre-drawn batches) and the
+ * full-list force kernels, and the times measured by the autotuner:
+ * force_us[3k + q] = microseconds per launch at 1, 2, 4 lanes (q = 0, 1, 2)
+ * for k = 0 (RBL) and k = 1 (full list); zeros before tuning.  Any pointer
+ * may be NULL. */
+rbl_status rbl_tuning(rbl_ctx* ctx, int32_t* lpp_rbl, int32_t* lpp_full, double* force_us);
 
 /* Size information: n_slots (particles plus per-replica padding to 64) and
  * current list capacities (entries per row). */

@@ -79,7 +79,9 @@ class Context:
 
     def __init__(self, n: int, *, precision: str = "fp64", lists=("core", "shell"),
                  skin: float = 0.3, shift: bool = True, momentum_fix: bool = True,
-                 predraw: bool = True, capacity_factor: float = 1.25, replica_offsets=None,
+                 predraw: bool = True, graphs: bool = True, lanes: int = 0,
+                 capacity_factor: float = 1.25,
+                 replica_offsets=None,
                  pair: str = "lj", alpha: float = 0.0, charges=None, stream=None):
         torch = _torch()
         lib = _lib.load()
@@ -96,6 +98,8 @@ class Context:
         cfg.shift = int(bool(shift))
         cfg.momentum_fix = int(bool(momentum_fix))
         cfg.predraw = int(bool(predraw))
+        cfg.graphs = int(bool(graphs))
+        cfg.lanes = int(lanes)
         cfg.capacity_factor = float(capacity_factor)
         self._offsets = None
         if replica_offsets is not None:
@@ -237,6 +241,13 @@ class Context:
         ms = C.c_double()
         _check(self._lib.rbl_kernel_stats(self._h, int(kind), C.byref(launches), C.byref(ms)))
         return launches.value, ms.value
+
+    def tuning(self):
+        a, b = C.c_int32(), C.c_int32()
+        us = (C.c_double * 6)()
+        _check(self._lib.rbl_tuning(self._h, C.byref(a), C.byref(b), us))
+        return {"lpp_rbl": a.value, "lpp_full": b.value,
+                "rbl_us": list(us[0:3]), "full_us": list(us[3:6])}
 
     def info(self):
         ns = C.c_int64()

@@ -62,6 +62,8 @@ struct BinArgs {
     const double* pos;     // caller SoA [3][n]
     const double4* xs;     // sorted source
     const int* perm_old;   // sorted source: slot -> ID
+    const double* xb;      // sorted source: positions at the previous build [3][n_slots]
+    double half_skin2;     // (skin/2)^2
     int64_t n;
     int64_t n_src;
     int* cell_of_src;
@@ -92,6 +94,11 @@ __global__ __launch_bounds__(256) void k_bin_count(BinArgs a)
         x[0] = p.x;
         x[1] = p.y;
         x[2] = p.z;
+        // skin monitor: displacement over the list lifetime that ends here
+        const double dx = p.x - a.xb[s];
+        const double dy = p.y - a.xb[a.n_src + s];
+        const double dz = p.z - a.xb[2 * a.n_src + s];
+        if (dx * dx + dy * dy + dz * dz > a.half_skin2) raise_flag(&a.flags[kFlagSkin]);
     }
     const DevReplica& R = a.rep[r];
     int c[3];
@@ -554,6 +561,7 @@ struct FusedArgs {
     int* batch;        // [K][n_slots][P]
     uint64_t seed;
     uint64_t step0;
+    const uint64_t* step_dev;  // if set, the draw's first step is *step_dev + step0
     int K;
     int P;
 };
@@ -844,7 +852,8 @@ __global__ __launch_bounds__(256) void k_build_draw2(FusedArgs fa)
                 } else {
                     uint32_t S[PMAX];
                     const uint32_t pid = (uint32_t)(fa.perm[islot] - R.id_base);
-                    floyd_draw<PMAX>(S, fa.seed, pid, (uint32_t)(fa.step0 + rr), (uint32_t)rep_id, P, n);
+                    const uint64_t s0 = fa.step_dev ? *fa.step_dev + fa.step0 : fa.step0;
+                    floyd_draw<PMAX>(S, fa.seed, pid, (uint32_t)(s0 + rr), (uint32_t)rep_id, P, n);
 #pragma unroll
                     for (int qq = 0; qq < PMAX; ++qq)
                         if (qq < P) out[qq] = lookup((int)S[qq]);
@@ -926,6 +935,7 @@ struct ForceArgs {
     double alpha;
     uint64_t seed;
     uint64_t step;
+    const uint64_t* step_dev;  // if set, the step counter is *step_dev + step
     int P;
     double* f;             // [3][n_slots]
     double* partial;       // [5][n_slices]
@@ -1019,7 +1029,8 @@ __global__ __launch_bounds__(256) void k_forces(ForceArgs a)
             if (MODE == kShellInline && n > P) {
                 uint32_t S[PMAX];
                 const uint32_t pid = (uint32_t)(a.perm[slot] - R.id_base);
-                floyd_draw<PMAX>(S, a.seed, pid, (uint32_t)a.step, (uint32_t)rep_id, P, n);
+                const uint64_t st = a.step_dev ? *a.step_dev + a.step : a.step;
+                floyd_draw<PMAX>(S, a.seed, pid, (uint32_t)st, (uint32_t)rep_id, P, n);
 #pragma unroll
                 for (int q = 0; q < PMAX; ++q) s_pos[q * 256 + threadIdx.x] = S[q];
             }
@@ -1084,6 +1095,140 @@ __global__ __launch_bounds__(256) void k_forces(ForceArgs a)
     }
 }
 
+// Force kernel with LPP lanes per particle (LPP = 2 or 4; pre-drawn
+// batches or the full list).  A wavefront covers 64/LPP consecutive slots;
+// lane l of a particle takes row entries l, l+LPP, ...  The core and shell
+// sums are reduced over the particle's lanes with DPP quad permutations, in
+// a fixed order, and combined as F = F_core + scale * F_shell by lane 0.
+// More, shorter wavefronts keep more gathers in flight than one lane per
+// particle.
+template <int CTRL>
+__device__ __forceinline__ double dpp_quad_f64(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+template <int LPP>
+__device__ __forceinline__ double group_sum(double v)
+{
+    if (LPP >= 2) v += dpp_quad_f64<0xB1>(v);  // quad_perm [1,0,3,2]
+    if (LPP >= 4) v += dpp_quad_f64<0x4E>(v);  // quad_perm [2,3,0,1]
+    return v;
+}
+
+template <int PREC, int MODE, bool ENERGY, bool ERFC, int LPP>
+__global__ __launch_bounds__(256) void k_forces_lpp(ForceArgs a)
+{
+    constexpr int U = 2;
+    const int64_t g = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const int64_t slot = g / LPP;
+    const int l = (int)(g % LPP);
+    const int64_t slice = slot >> 6;
+    if (slice >= a.n_slices) return;
+    const int rep_id = a.slice_rep[slice];
+    const DevReplica& R = a.rep[rep_id];
+    const bool real = slot - R.slot_base < R.n;
+    Acc c = {0.0, 0.0, 0.0, 0.0, 0.0};
+    Acc sh = {0.0, 0.0, 0.0, 0.0, 0.0};
+    double scale = 1.0;
+    if (real) {
+        const double4 xi = a.xs[slot];
+        {
+            const double cut = MODE == kShellNone ? a.rc2 : a.rs2;
+            const int len = a.core_len[slot];
+            const int* row = a.core + ell(slot, 0, a.cap_core);
+            for (int k = l; k < len; k += U * LPP) {
+                int j[U];
+                bool live[U];
+                double4 xj[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    live[u] = k + u * LPP < len;
+                    j[u] = live[u] ? row[(int64_t)(k + u * LPP) * 64] : (int)slot;
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) xj[u] = a.xs[j[u]];
+                accumulate<PREC, ENERGY, ERFC, U>(xi, xj, live, -1.0, cut, R, a, c);
+            }
+        }
+        if (MODE != kShellNone) {
+            const int n = a.shell_len[slot];
+            const int P = a.P;
+            const int cnt = n < P ? n : P;
+            scale = n > P ? (double)n / (double)P : 1.0;
+            const int* brow = a.batch + slot * P;
+            for (int m = l; m < cnt; m += U * LPP) {
+                int j[U];
+                bool live[U];
+                double4 xj[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    live[u] = m + u * LPP < cnt;
+                    j[u] = live[u] ? brow[m + u * LPP] : (int)slot;
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) xj[u] = a.xs[j[u]];
+                accumulate<PREC, ENERGY, ERFC, U>(xi, xj, live, a.rs2, a.rc2, R, a, sh);
+            }
+        }
+    }
+    c.fx = group_sum<LPP>(c.fx);
+    c.fy = group_sum<LPP>(c.fy);
+    c.fz = group_sum<LPP>(c.fz);
+    if (MODE != kShellNone) {
+        sh.fx = group_sum<LPP>(sh.fx);
+        sh.fy = group_sum<LPP>(sh.fy);
+        sh.fz = group_sum<LPP>(sh.fz);
+    }
+    double fx = c.fx, fy = c.fy, fz = c.fz, e = 0.0, w = 0.0;
+    if (MODE != kShellNone) {
+        fx = c.fx + scale * sh.fx;
+        fy = c.fy + scale * sh.fy;
+        fz = c.fz + scale * sh.fz;
+    }
+    if (ENERGY) {
+        c.e = group_sum<LPP>(c.e);
+        c.w = group_sum<LPP>(c.w);
+        if (MODE != kShellNone) {
+            sh.e = group_sum<LPP>(sh.e);
+            sh.w = group_sum<LPP>(sh.w);
+            e = 0.5 * (c.e + scale * sh.e);
+            w = 0.5 * (c.w + scale * sh.w);
+        } else {
+            e = 0.5 * c.e;
+            w = 0.5 * c.w;
+        }
+    }
+    const bool lead = l == 0;
+    if (lead) {
+        a.f[slot] = fx;
+        a.f[a.n_slots + slot] = fy;
+        a.f[2 * a.n_slots + slot] = fz;
+    }
+    // per-slice partials: one wavefront covers 64/LPP slots, so LPP
+    // wavefronts share a slice; each adds its part into the slice's entry in
+    // a fixed order via a per-wave slot [slice][sub]
+    const double tx = wave_sum(lead ? fx : 0.0);
+    const double ty = wave_sum(lead ? fy : 0.0);
+    const double tz = wave_sum(lead ? fz : 0.0);
+    double te = 0.0, tw = 0.0;
+    if (ENERGY) {
+        te = wave_sum(lead ? e : 0.0);
+        tw = wave_sum(lead ? w : 0.0);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        const int64_t wv = g >> 6;  // wavefront index: LPP per slice
+        const int64_t ns = a.n_slices * LPP;
+        a.partial[wv] = tx;
+        a.partial[ns + wv] = ty;
+        a.partial[2 * ns + wv] = tz;
+        a.partial[3 * ns + wv] = te;
+        a.partial[4 * ns + wv] = tw;
+    }
+}
+
 // Per-replica sums of the wavefront partials in a fixed order, so the result
 // does not depend on scheduling.  Block (b, r) sums slices b*per .. of
 // replica r into part2[r][b]; the last block of a replica to finish (counted
@@ -1092,16 +1237,18 @@ __global__ __launch_bounds__(256) void k_forces(ForceArgs a)
 constexpr int kReduceSlicesPerBlock = 256;
 
 __global__ __launch_bounds__(256) void k_reduce(const DevReplica* rep, const double* partial,
-                                               int64_t n_slices, int blocks_per_rep, double* part2,
-                                               unsigned* counter, double* rep_sum)
+                                               int64_t n_slices, int per, int blocks_per_rep,
+                                               double* part2, unsigned* counter, double* rep_sum)
 {
     __shared__ double lds[5][4];
     __shared__ bool is_last;
     const int r = blockIdx.y;
     const int b = blockIdx.x;
     const DevReplica& R = rep[r];
-    const int64_t s0 = R.slot_base >> 6;
-    const int64_t ns = (R.n + 63) >> 6;
+    // `per` partial entries per slice (one per wavefront of the force kernel)
+    const int64_t s0 = (R.slot_base >> 6) * per;
+    const int64_t ns = ((R.n + 63) >> 6) * per;
+    n_slices *= per;
     const int64_t lo = (int64_t)b * kReduceSlicesPerBlock;
     const int64_t hi = min(ns, lo + kReduceSlicesPerBlock);
     const int wv = threadIdx.x >> 6;
@@ -1128,13 +1275,20 @@ __global__ __launch_bounds__(256) void k_reduce(const DevReplica* rep, const dou
     __syncthreads();
     if (!is_last) return;
     __threadfence();
-    if (threadIdx.x < 5) {
-        const int q = threadIdx.x;
+    // the last block adds the per-block sums: thread t takes blocks t,
+    // t+256, ..., then the fixed-order block reduction
+    for (int q = 0; q < 5; ++q) {
         double acc = 0.0;
-        for (int k = 0; k < nb; ++k)
+        for (int k = threadIdx.x; k < nb; k += blockDim.x)
             acc += __hip_atomic_load(&part2[((int64_t)r * blocks_per_rep + k) * 5 + q], __ATOMIC_RELAXED,
                                      __HIP_MEMORY_SCOPE_AGENT);
-        rep_sum[8 * r + q] = acc;
+        acc = wave_sum(acc);
+        if ((threadIdx.x & 63) == 0) lds[q][wv] = acc;
+    }
+    __syncthreads();
+    if (threadIdx.x < 5) {
+        const int q = threadIdx.x;
+        rep_sum[8 * r + q] = ((lds[q][0] + lds[q][1]) + lds[q][2]) + lds[q][3];
     }
     if (threadIdx.x == 0) counter[r] = 0u;
 }
@@ -1146,7 +1300,7 @@ __global__ __launch_bounds__(256) void k_reduce(const DevReplica* rep, const dou
 //   mid:   v += h F'; v += h F'; x += dt v   (end of one step + start of next)
 //   last:  v += h F'
 // The skin monitor flags a particle that moved more than skin/2 since the
-// last build.
+// last build: at the end of a run here, at every rebuild in k_bin_count.
 struct IntArgs {
     const DevReplica* rep;
     const int* slice_rep;
@@ -1193,6 +1347,10 @@ __global__ __launch_bounds__(256) void k_integrate(IntArgs a)
         x.y = x.y + a.dt * v[1];
         x.z = x.z + a.dt * v[2];
         a.xs[s] = x;
+    } else {
+        // displacement since the last build (the rebuilds check their own
+        // list lifetimes while binning)
+        const double4 x = a.xs[s];
         const double dx = x.x - a.xb[s];
         const double dy = x.y - a.xb[a.n_slots + s];
         const double dz = x.z - a.xb[2 * a.n_slots + s];
@@ -1258,6 +1416,13 @@ __global__ __launch_bounds__(256) void k_scatter_out(IoArgs a)
             a.f_out[d * a.n + id] = a.f[d * a.n_slots + s] - fc;
         }
     }
+}
+
+// Last node of a captured block: moves the device step counter to the next
+// block.
+__global__ void k_advance(uint64_t* step_dev, uint64_t by)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *step_dev += by;
 }
 
 __global__ void k_ev_out(const double* rep_sum, int nrep, double* ev)

@@ -78,7 +78,13 @@ void dfree(T*& p)
 
 struct rbl_ctx {
     rbl_config cfg;
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;  // the caller's stream
+    hipStream_t ls = nullptr;      // stream the helpers launch on (the caller's, or gs)
+    hipStream_t gs = nullptr;      // internal stream for captured step blocks
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    std::vector<unsigned char> gsig;  // parameters the captured blocks were made with
+    uint64_t* d_step = nullptr;       // device step counter read by captured kernels
     int R = 1;
     int64_t n = 0, n_slots = 0, n_slices = 0;
     std::vector<int64_t> id_base, rep_n, slot_base;
@@ -116,7 +122,11 @@ struct rbl_ctx {
     int* d_batch = nullptr;
     size_t batch_alloc = 0;
 
-    double* d_partial = nullptr;
+    double* d_partial = nullptr;    // [5][n_slices * 4] wavefront partial sums
+    int part_per = 1;               // partial entries per slice of the last force launch
+    int lpp_rbl = 4, lpp_full = 4;  // lanes per particle of the force kernels
+    bool tuned_rbl = false, tuned_full = false;
+    double tune_us[2][3] = {{0, 0, 0}, {0, 0, 0}};  // measured force time per LPP 1, 2, 4
     double* d_part2 = nullptr;
     unsigned* d_red_counter = nullptr;
     int red_blocks = 1;
@@ -157,12 +167,12 @@ rbl_status timed(rbl_ctx* c, int kind, F&& fn)
     if (c->profiling) {
         a = take_event(c);
         b = take_event(c);
-        if (a && b) HIP_TRY(hipEventRecord(a, c->stream));
+        if (a && b) HIP_TRY(hipEventRecord(a, c->ls));
     }
     fn();
     HIP_TRY(hipGetLastError());
     if (c->profiling && a && b) {
-        HIP_TRY(hipEventRecord(b, c->stream));
+        HIP_TRY(hipEventRecord(b, c->ls));
         c->ev_pending[kind].push_back({a, b});
     }
     return RBL_OK;
@@ -188,7 +198,7 @@ rbl_status resolve_events(rbl_ctx* c)
 rbl_status fill_i32(rbl_ctx* c, int* p, int64_t n, int v)
 {
     if (n <= 0) return RBL_OK;
-    k_fill_i32<<<grid_for(n), kBlock, 0, c->stream>>>(p, n, v);
+    k_fill_i32<<<grid_for(n), kBlock, 0, c->ls>>>(p, n, v);
     HIP_TRY(hipGetLastError());
     return RBL_OK;
 }
@@ -196,8 +206,8 @@ rbl_status fill_i32(rbl_ctx* c, int* p, int64_t n, int v)
 rbl_status read_flags(rbl_ctx* c)
 {
     HIP_TRY(hipMemcpyAsync(c->h_flags, c->d_flags, sizeof(int) * kNumFlags, hipMemcpyDeviceToHost,
-                           c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));
+                           c->ls));
+    HIP_TRY(hipStreamSynchronize(c->ls));
     return RBL_OK;
 }
 
@@ -269,10 +279,10 @@ rbl_status setup_geometry(rbl_ctx* c, const double* box, double r_s, double r_c)
             std::fill(cell_rep.begin() + reps[r].cell_base, cell_rep.begin() + reps[r].cell_base + nc, r);
         }
         HIP_TRY(hipMemcpyAsync(c->d_rep, reps.data(), sizeof(DevReplica) * c->R, hipMemcpyHostToDevice,
-                               c->stream));
+                               c->ls));
         HIP_TRY(hipMemcpyAsync(c->d_cell_rep, cell_rep.data(), sizeof(int) * c->n_cells,
-                               hipMemcpyHostToDevice, c->stream));
-        HIP_TRY(hipStreamSynchronize(c->stream));
+                               hipMemcpyHostToDevice, c->ls));
+        HIP_TRY(hipStreamSynchronize(c->ls));
         c->h_rep = reps;
     }
     c->r_s = r_s;
@@ -323,6 +333,11 @@ rbl_status bin_particles(rbl_ctx* c, const double* pos, const double* vel, bool 
     b.pos = pos;
     b.xs = c->cur_xs();
     b.perm_old = c->cur_perm();
+    b.xb = c->d_xb;
+    {
+        const double hs = 0.5 * c->cfg.skin;
+        b.half_skin2 = hs * hs;
+    }
     b.n = c->n;
     b.n_src = SRC == kSrcCaller ? c->n : c->n_slots;
     b.cell_of_src = c->d_cell_of_src;
@@ -331,26 +346,26 @@ rbl_status bin_particles(rbl_ctx* c, const double* pos, const double* vel, bool 
     b.flags = c->d_flags;
     const int64_t ntiles = (c->n_cells + kScanTile - 1) / kScanTile;
     RBL_TRY(timed(c, kKBin, [&] {
-        k_fill_i32<<<grid_for(c->n_cells), kBlock, 0, c->stream>>>(c->d_cell_count, c->n_cells, 0);
+        k_fill_i32<<<grid_for(c->n_cells), kBlock, 0, c->ls>>>(c->d_cell_count, c->n_cells, 0);
     }));
-    RBL_TRY(timed(c, kKBin, [&] { k_bin_count<SRC><<<grid_for(b.n_src), kBlock, 0, c->stream>>>(b); }));
+    RBL_TRY(timed(c, kKBin, [&] { k_bin_count<SRC><<<grid_for(b.n_src), kBlock, 0, c->ls>>>(b); }));
     RBL_TRY(timed(c, kKBin, [&] {
-        k_scan_tiles<<<(unsigned)ntiles, kScanBlock, 0, c->stream>>>(c->d_cell_count, c->n_cells,
+        k_scan_tiles<<<(unsigned)ntiles, kScanBlock, 0, c->ls>>>(c->d_cell_count, c->n_cells,
                                                                      c->d_tile_sum);
     }));
     RBL_TRY(timed(c, kKBin, [&] {
-        k_scan_tile_sums<<<1, 1024, 0, c->stream>>>(c->d_tile_sum, (int)ntiles);
+        k_scan_tile_sums<<<1, 1024, 0, c->ls>>>(c->d_tile_sum, (int)ntiles);
     }));
     RBL_TRY(timed(c, kKBin, [&] {
-        k_scan_final<<<(unsigned)ntiles, kScanBlock, 0, c->stream>>>(
+        k_scan_final<<<(unsigned)ntiles, kScanBlock, 0, c->ls>>>(
             c->d_cell_count, c->n_cells, c->d_tile_sum, c->d_cell_rep, c->d_rep, c->d_cell_start);
     }));
     RBL_TRY(timed(c, kKBin, [&] {
-        k_bin_scatter<SRC><<<grid_for(b.n_src), kBlock, 0, c->stream>>>(
+        k_bin_scatter<SRC><<<grid_for(b.n_src), kBlock, 0, c->ls>>>(
             b, c->d_cell_start, c->d_perm[nxt], c->d_src_of_slot, c->n_slots);
     }));
     RBL_TRY(timed(c, kKBin, [&] {
-        k_cell_sort<<<grid_for(c->n_cells), kBlock, 0, c->stream>>>(
+        k_cell_sort<<<grid_for(c->n_cells), kBlock, 0, c->ls>>>(
             c->d_cell_start, c->d_cell_count, c->n_cells, c->n_slots, c->d_perm[nxt],
             c->d_src_of_slot, c->d_flags);
     }));
@@ -374,9 +389,9 @@ rbl_status bin_particles(rbl_ctx* c, const double* pos, const double* vel, bool 
     g.slot_of_id = c->d_slot_of_id;
     RBL_TRY(timed(c, kKBin, [&] {
         if (with_vel)
-            k_gather<SRC, true><<<grid_for(c->n_slots), kBlock, 0, c->stream>>>(g);
+            k_gather<SRC, true><<<grid_for(c->n_slots), kBlock, 0, c->ls>>>(g);
         else
-            k_gather<SRC, false><<<grid_for(c->n_slots), kBlock, 0, c->stream>>>(g);
+            k_gather<SRC, false><<<grid_for(c->n_slots), kBlock, 0, c->ls>>>(g);
     }));
     c->cur = nxt;
     return RBL_OK;
@@ -417,7 +432,7 @@ void launch_build(rbl_ctx* c, const BuildArgs& a, int mask)
 {
     const unsigned g = grid_for(c->n_cells, 4);
     const bool wc = mask & RBL_LIST_CORE, ws = mask & RBL_LIST_SHELL, wf = mask & RBL_LIST_FULL;
-#define RBL_B(C, S, F) k_build<COUNT_ONLY, C, S, F><<<g, kBlock, 0, c->stream>>>(a)
+#define RBL_B(C, S, F) k_build<COUNT_ONLY, C, S, F><<<g, kBlock, 0, c->ls>>>(a)
     if (wc && ws && wf) RBL_B(true, true, true);
     else if (wc && ws) RBL_B(true, true, false);
     else if (wc && wf) RBL_B(true, false, true);
@@ -428,10 +443,19 @@ void launch_build(rbl_ctx* c, const BuildArgs& a, int mask)
 #undef RBL_B
 }
 
-rbl_status ensure_list_storage(rbl_ctx* c, int q, int need)
+// Row capacity of list q for rows of up to `need` entries.  The first
+// sizing applies capacity_factor (values below 1 size rows short on
+// purpose); after an overflow rows grow to at least 1.5x the longest row
+// seen and by at least 16 entries, so a run regrows a bounded number of
+// times.
+rbl_status ensure_list_storage(rbl_ctx* c, int q, int need, bool regrow = false)
 {
-    const double f = c->cfg.capacity_factor > 1.0 ? c->cfg.capacity_factor : 1.0;
-    int cap = (int)std::ceil(need * f) + 8;
+    int cap;
+    if (regrow) {
+        cap = std::max((int)std::ceil(need * std::max(1.5, c->cfg.capacity_factor)) + 8, c->cap[q] + 16);
+    } else {
+        cap = (int)std::ceil(need * c->cfg.capacity_factor) + 8;
+    }
     cap = (cap + 3) & ~3;
     if (cap <= c->cap[q] && c->d_list[q]) return RBL_OK;
     dfree(c->d_list[q]);
@@ -477,7 +501,7 @@ rbl_status build_lists(rbl_ctx* c, int mask)
             return RBL_OK;
         }
         for (int q = 0; q < 3; ++q)
-            if ((mask >> q) & 1) RBL_TRY(ensure_list_storage(c, q, c->h_flags[kFlagMaxCore + q]));
+            if ((mask >> q) & 1) RBL_TRY(ensure_list_storage(c, q, c->h_flags[kFlagMaxCore + q], true));
         need_count = false;
     }
     return fail(RBL_E_CAPACITY, "neighbour rows kept overflowing their capacity");
@@ -488,7 +512,36 @@ rbl_status build_lists(rbl_ctx* c, int mask)
 // step0+K-1 in one pass (no shell rows in HBM).
 rbl_status ensure_batch(rbl_ctx* c, int K, int P);
 
-rbl_status build_fused(rbl_ctx* c, int P, uint64_t seed, uint64_t step0, int K)
+// Queues the fused build (core rows, shell counts, batches of K force
+// evaluations from step0, or from *step_dev + step0 when step_dev is set).
+rbl_status launch_fused(rbl_ctx* c, int P, uint64_t seed, uint64_t step0, int K,
+                        const uint64_t* step_dev)
+{
+    FusedArgs fa;
+    fa.b = build_args(c);
+    fa.perm = c->cur_perm();
+    fa.batch = c->d_batch;
+    fa.seed = seed;
+    fa.step0 = step0;
+    fa.step_dev = step_dev;
+    fa.K = K;
+    fa.P = P;
+    const unsigned g = grid_for(c->n_cells, 4);
+    return timed(c, kKBuild, [&] {
+        if (P <= 8) k_build_draw2<8><<<g, kBlock, 0, c->ls>>>(fa);
+        else if (P <= 12) k_build_draw2<12><<<g, kBlock, 0, c->ls>>>(fa);
+        else if (P <= 16) k_build_draw2<16><<<g, kBlock, 0, c->ls>>>(fa);
+        else if (P <= 24) k_build_draw2<24><<<g, kBlock, 0, c->ls>>>(fa);
+        else if (P <= 32) k_build_draw2<32><<<g, kBlock, 0, c->ls>>>(fa);
+        else if (P <= 64) k_build_draw2<64><<<g, kBlock, 0, c->ls>>>(fa);
+        else k_build_draw2<128><<<g, kBlock, 0, c->ls>>>(fa);
+    });
+}
+
+// Sizes the core rows if needed (a counting pass and one synchronisation,
+// the first time only) and makes sure the shell-count and batch buffers
+// exist for `K` steps of batch size P.
+rbl_status prepare_fused(rbl_ctx* c, int P, int K)
 {
     for (int q = 0; q < 2; ++q)
         if (!c->d_len[q]) RBL_TRY(dalloc(&c->d_len[q], c->n_slots));
@@ -501,42 +554,26 @@ rbl_status build_fused(rbl_ctx* c, int P, uint64_t seed, uint64_t step0, int K)
         if (c->h_flags[kFlagBadSlot]) return fail(RBL_E_HIP, "inconsistent cell binning");
         RBL_TRY(ensure_list_storage(c, 0, c->h_flags[kFlagMaxCore]));
     }
-    for (int attempt = 0; attempt < 3; ++attempt) {
-        RBL_TRY(clear_list_flags(c));
-        FusedArgs fa;
-        fa.b = build_args(c);
-        fa.perm = c->cur_perm();
-        fa.batch = c->d_batch;
-        fa.seed = seed;
-        fa.step0 = step0;
-        fa.K = K;
-        fa.P = P;
-        const unsigned g = grid_for(c->n_cells, 4);
-        RBL_TRY(timed(c, kKBuild, [&] {
-            if (P <= 8) k_build_draw2<8><<<g, kBlock, 0, c->stream>>>(fa);
-            else if (P <= 12) k_build_draw2<12><<<g, kBlock, 0, c->stream>>>(fa);
-            else if (P <= 16) k_build_draw2<16><<<g, kBlock, 0, c->stream>>>(fa);
-            else if (P <= 24) k_build_draw2<24><<<g, kBlock, 0, c->stream>>>(fa);
-            else if (P <= 32) k_build_draw2<32><<<g, kBlock, 0, c->stream>>>(fa);
-            else if (P <= 64) k_build_draw2<64><<<g, kBlock, 0, c->stream>>>(fa);
-            else k_build_draw2<128><<<g, kBlock, 0, c->stream>>>(fa);
-        }));
-        RBL_TRY(read_flags(c));
-        if (c->h_flags[kFlagBadSlot] & 16)
-            return fail(RBL_E_CAPACITY, "cell stencil holds too many candidates for the fused build");
-        if (c->h_flags[kFlagBadSlot]) return fail(RBL_E_HIP, "inconsistent cell binning");
-        if (c->h_flags[kFlagNonfinite]) {
-            c->built = false;
-            return fail(RBL_E_NONFINITE, "non-finite particle position at list build");
-        }
-        if (!c->h_flags[kFlagOverflow]) {
-            c->built_mask = RBL_LIST_CORE;
-            c->shell_counts = true;
-            return RBL_OK;
-        }
-        RBL_TRY(ensure_list_storage(c, 0, c->h_flags[kFlagMaxCore]));
-    }
-    return fail(RBL_E_CAPACITY, "core rows kept overflowing their capacity");
+    return RBL_OK;
+}
+
+// Sizes the rows of `mask` if needed (counting pass + one synchronisation).
+rbl_status prepare_lists(rbl_ctx* c, int mask)
+{
+    for (int q = 0; q < 3; ++q)
+        if (((mask >> q) & 1) && !c->d_len[q]) RBL_TRY(dalloc(&c->d_len[q], c->n_slots));
+    bool need = false;
+    for (int q = 0; q < 3; ++q)
+        if (((mask >> q) & 1) && c->cap[q] == 0) need = true;
+    if (!need) return RBL_OK;
+    RBL_TRY(clear_list_flags(c));
+    BuildArgs a = build_args(c);
+    RBL_TRY(timed(c, kKBuild, [&] { launch_build<true>(c, a, mask); }));
+    RBL_TRY(read_flags(c));
+    if (c->h_flags[kFlagBadSlot]) return fail(RBL_E_HIP, "inconsistent cell binning");
+    for (int q = 0; q < 3; ++q)
+        if ((mask >> q) & 1) RBL_TRY(ensure_list_storage(c, q, c->h_flags[kFlagMaxCore + q]));
+    return RBL_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -566,6 +603,7 @@ ForceArgs force_args(rbl_ctx* c, int P, uint64_t seed, uint64_t step, bool full)
     a.alpha = c->cfg.alpha;
     a.seed = seed;
     a.step = step;
+    a.step_dev = nullptr;
     a.P = P;
     a.f = c->d_f;
     a.partial = c->d_partial;
@@ -575,12 +613,18 @@ ForceArgs force_args(rbl_ctx* c, int P, uint64_t seed, uint64_t step, bool full)
 template <int PREC, int MODE, bool EN, bool ERFC>
 void launch_force_p(rbl_ctx* c, const ForceArgs& a)
 {
-    const unsigned g = grid_for(c->n_slots);
-    if (MODE == kShellInline) {
-        if (a.P <= 16) k_forces<PREC, MODE, EN, ERFC, 16><<<g, kBlock, 0, c->stream>>>(a);
-        else k_forces<PREC, MODE, EN, ERFC, 32><<<g, kBlock, 0, c->stream>>>(a);
+    if constexpr (MODE == kShellInline) {
+        const unsigned g = grid_for(c->n_slots);
+        c->part_per = 1;
+        if (a.P <= 16) k_forces<PREC, MODE, EN, ERFC, 16><<<g, kBlock, 0, c->ls>>>(a);
+        else k_forces<PREC, MODE, EN, ERFC, 32><<<g, kBlock, 0, c->ls>>>(a);
     } else {
-        k_forces<PREC, MODE, EN, ERFC, 1><<<g, kBlock, 0, c->stream>>>(a);
+        const int lpp = MODE == kShellNone ? c->lpp_full : c->lpp_rbl;
+        c->part_per = lpp;
+        const unsigned g = grid_for(c->n_slots * lpp);
+        if (lpp == 4) k_forces_lpp<PREC, MODE, EN, ERFC, 4><<<g, kBlock, 0, c->ls>>>(a);
+        else if (lpp == 2) k_forces_lpp<PREC, MODE, EN, ERFC, 2><<<g, kBlock, 0, c->ls>>>(a);
+        else k_forces<PREC, MODE, EN, ERFC, 1><<<grid_for(c->n_slots), kBlock, 0, c->ls>>>(a);
     }
 }
 
@@ -631,27 +675,29 @@ rbl_status predraw(rbl_ctx* c, int P, uint64_t seed, uint64_t step0, int K)
     d.batch = c->d_batch;
     const unsigned g = grid_for(c->n_slots);
     return timed(c, kKPredraw, [&] {
-        if (P <= 16) k_predraw<16><<<g, kBlock, 0, c->stream>>>(d);
-        else if (P <= 32) k_predraw<32><<<g, kBlock, 0, c->stream>>>(d);
-        else if (P <= 64) k_predraw<64><<<g, kBlock, 0, c->stream>>>(d);
-        else k_predraw<128><<<g, kBlock, 0, c->stream>>>(d);
+        if (P <= 16) k_predraw<16><<<g, kBlock, 0, c->ls>>>(d);
+        else if (P <= 32) k_predraw<32><<<g, kBlock, 0, c->ls>>>(d);
+        else if (P <= 64) k_predraw<64><<<g, kBlock, 0, c->ls>>>(d);
+        else k_predraw<128><<<g, kBlock, 0, c->ls>>>(d);
     });
 }
 
 rbl_status reduce(rbl_ctx* c)
 {
     return timed(c, kKReduce, [&] {
-        k_reduce<<<dim3(c->red_blocks, c->R), kBlock, 0, c->stream>>>(
-            c->d_rep, c->d_partial, c->n_slices, c->red_blocks, c->d_part2, c->d_red_counter, c->d_rep_sum);
+        k_reduce<<<dim3(c->red_blocks, c->R), kBlock, 0, c->ls>>>(
+            c->d_rep, c->d_partial, c->n_slices, c->part_per, c->red_blocks, c->d_part2, c->d_red_counter,
+            c->d_rep_sum);
     });
 }
 
 // RBL force at the current sorted positions (raw; per-replica sums reduced).
 // batch_rel >= 0 selects pre-drawn batches of that relative step.
 rbl_status rbl_force_sorted(rbl_ctx* c, int P, uint64_t seed, uint64_t step, int batch_rel,
-                            bool energy)
+                            bool energy, const uint64_t* step_dev = nullptr)
 {
     ForceArgs a = force_args(c, P, seed, step, false);
+    a.step_dev = step_dev;
     if (batch_rel >= 0) {
         a.batch = c->d_batch + (size_t)batch_rel * P * c->n_slots;
         RBL_TRY(timed(c, kKForceRbl, [&] { launch_force<kShellPredraw>(c, a, energy); }));
@@ -693,7 +739,7 @@ IoArgs io_args(rbl_ctx* c, bool momentum_fix)
 rbl_status emit_ev(rbl_ctx* c, double* ev)
 {
     if (!ev) return RBL_OK;
-    k_ev_out<<<grid_for(c->R), kBlock, 0, c->stream>>>(c->d_rep_sum, c->R, ev);
+    k_ev_out<<<grid_for(c->R), kBlock, 0, c->ls>>>(c->d_rep_sum, c->R, ev);
     HIP_TRY(hipGetLastError());
     return RBL_OK;
 }
@@ -718,9 +764,9 @@ rbl_status integrate(rbl_ctx* c, int mode, double dt, bool momentum_fix)
     a.flags = c->d_flags;
     const unsigned g = grid_for(c->n_slots);
     return timed(c, kKIntegrate, [&] {
-        if (mode == kIntFirst) k_integrate<kIntFirst><<<g, kBlock, 0, c->stream>>>(a);
-        else if (mode == kIntMid) k_integrate<kIntMid><<<g, kBlock, 0, c->stream>>>(a);
-        else k_integrate<kIntLast><<<g, kBlock, 0, c->stream>>>(a);
+        if (mode == kIntFirst) k_integrate<kIntFirst><<<g, kBlock, 0, c->ls>>>(a);
+        else if (mode == kIntMid) k_integrate<kIntMid><<<g, kBlock, 0, c->ls>>>(a);
+        else k_integrate<kIntLast><<<g, kBlock, 0, c->ls>>>(a);
     });
 }
 
@@ -728,6 +774,276 @@ rbl_status check_p(int P)
 {
     if (P < 1 || P > RBL_MAX_P)
         return fail(RBL_E_ARG, "batch size P must be in [1, " + std::to_string(RBL_MAX_P) + "]");
+    return RBL_OK;
+}
+
+
+// ---------------------------------------------------------------------------
+// molecular-dynamics driver and captured step blocks
+
+__global__ void k_set_u64(uint64_t* p, uint64_t v)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+
+void drop_graphs(rbl_ctx* c)
+{
+    for (int q = 0; q < 2; ++q)
+        if (c->gexec[q]) {
+            (void)hipGraphExecDestroy(c->gexec[q]);
+            c->gexec[q] = nullptr;
+        }
+    c->gsig.clear();
+}
+
+struct StepParams {
+    int P;
+    uint64_t seed;
+    int64_t K;
+    double dt;
+    bool full, pre, fix;
+};
+
+template <typename T>
+void sig_put(std::vector<unsigned char>& v, const T& x)
+{
+    const unsigned char* p = reinterpret_cast<const unsigned char*>(&x);
+    v.insert(v.end(), p, p + sizeof(T));
+}
+
+std::vector<unsigned char> block_signature(const rbl_ctx* c, const StepParams& sp)
+{
+    std::vector<unsigned char> v;
+    sig_put(v, sp.P);
+    sig_put(v, sp.seed);
+    sig_put(v, sp.K);
+    sig_put(v, sp.dt);
+    sig_put(v, (int)sp.full);
+    sig_put(v, (int)sp.pre);
+    sig_put(v, (int)sp.fix);
+    sig_put(v, c->r_s);
+    sig_put(v, c->r_c);
+    sig_put(v, c->n_cells);
+    for (int q = 0; q < 3; ++q) {
+        sig_put(v, c->cap[q]);
+        sig_put(v, (const void*)c->d_list[q]);
+        sig_put(v, (const void*)c->d_len[q]);
+    }
+    sig_put(v, (const void*)c->d_batch);
+    sig_put(v, (const void*)c->d_cell_start);
+    sig_put(v, (const void*)c->d_cell_rep);
+    sig_put(v, c->profiling);
+    return v;
+}
+
+// Queues one list lifetime: steps s_b .. s_b+K-1 (kick/drift, rebuild at
+// s_b, force, reduction at every step).  Step-dependent values come from
+// the device counter d_step = s_b, so the same queue serves every block.
+rbl_status queue_block(rbl_ctx* c, const StepParams& sp)
+{
+    const int mask = sp.full ? RBL_LIST_FULL : (RBL_LIST_CORE | RBL_LIST_SHELL);
+    RBL_TRY(integrate(c, kIntMid, sp.dt, sp.fix));
+    RBL_TRY(bin_particles<kSrcSorted>(c, nullptr, nullptr, true));
+    if (sp.pre) {
+        RBL_TRY(launch_fused(c, sp.P, sp.seed, 0, (int)sp.K, c->d_step));
+    } else {
+        BuildArgs a = build_args(c);
+        RBL_TRY(timed(c, kKBuild, [&] { launch_build<false>(c, a, mask); }));
+    }
+    for (int64_t r = 0; r < sp.K; ++r) {
+        if (r > 0) RBL_TRY(integrate(c, kIntMid, sp.dt, sp.fix));
+        if (sp.full) RBL_TRY(full_force_sorted(c, false));
+        else if (sp.pre) RBL_TRY(rbl_force_sorted(c, sp.P, sp.seed, 0, (int)r, false));
+        else RBL_TRY(rbl_force_sorted(c, sp.P, sp.seed, (uint64_t)r, -1, false, c->d_step));
+    }
+    return RBL_OK;
+}
+
+rbl_status capture_block(rbl_ctx* c, int parity, const StepParams& sp)
+{
+    const int saved = c->cur;
+    c->cur = parity;
+    hipGraph_t g = nullptr;
+    HIP_TRY(hipStreamBeginCapture(c->ls, hipStreamCaptureModeThreadLocal));
+    const rbl_status st = queue_block(c, sp);
+    const hipError_t e = hipStreamEndCapture(c->ls, &g);
+    c->cur = saved;
+    if (st < 0) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess) return fail(RBL_E_HIP, std::string("stream capture: ") + hipGetErrorString(e));
+    hipGraphExec_t exec = nullptr;
+    const hipError_t e2 = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e2 != hipSuccess) return fail(RBL_E_HIP, std::string("graph instantiate: ") + hipGetErrorString(e2));
+    c->gexec[parity] = exec;
+    return RBL_OK;
+}
+
+rbl_status run_block(rbl_ctx* c, int64_t s_b, const StepParams& sp)
+{
+    std::vector<unsigned char> sig = block_signature(c, sp);
+    if (sig != c->gsig) {
+        drop_graphs(c);
+        c->gsig = sig;
+    }
+    const int parity = c->cur;
+    if (!c->gexec[parity]) RBL_TRY(capture_block(c, parity, sp));
+    k_set_u64<<<1, 64, 0, c->ls>>>(c->d_step, (uint64_t)s_b);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipGraphLaunch(c->gexec[parity], c->ls));
+    c->cur = 1 - parity;
+    return RBL_OK;
+}
+
+// Autotuner: times the force kernel at 1, 2 and 4 lanes per particle on
+// the state at hand (lists and batches built) and keeps the fastest for the
+// context.  Runs once per context and force kind, outside any capture.
+rbl_status autotune_forces(rbl_ctx* c, const StepParams& sp)
+{
+    const int kind = sp.full ? 1 : 0;
+    if (sp.full ? c->tuned_full : c->tuned_rbl) return RBL_OK;
+    if (!sp.full && !sp.pre) {  // the inline-draw kernel has one lane per particle
+        c->tuned_rbl = true;
+        return RBL_OK;
+    }
+    hipEvent_t e0 = take_event(c), e1 = take_event(c);
+    if (!e0 || !e1) return fail(RBL_E_HIP, "event creation failed");
+    const int cand[3] = {1, 2, 4};
+    double best = 1e30;
+    int best_lpp = 4;
+    const bool prof = c->profiling;
+    c->profiling = false;
+    for (int q = 0; q < 3; ++q) {
+        (sp.full ? c->lpp_full : c->lpp_rbl) = cand[q];
+        float total = 0.f;
+        for (int rep = 0; rep < 3; ++rep) {
+            HIP_TRY(hipEventRecord(e0, c->ls));
+            if (sp.full) RBL_TRY(full_force_sorted(c, false));
+            else RBL_TRY(rbl_force_sorted(c, sp.P, sp.seed, 0, 0, false));
+            HIP_TRY(hipEventRecord(e1, c->ls));
+            HIP_TRY(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+            if (rep > 0) total += ms;
+        }
+        c->tune_us[kind][q] = 1e3 * total / 2.0;
+        if (c->tune_us[kind][q] < best) {
+            best = c->tune_us[kind][q];
+            best_lpp = cand[q];
+        }
+    }
+    c->profiling = prof;
+    c->ev_pool.push_back(e0);
+    c->ev_pool.push_back(e1);
+    (sp.full ? c->lpp_full : c->lpp_rbl) = best_lpp;
+    (sp.full ? c->tuned_full : c->tuned_rbl) = true;
+    return RBL_OK;
+}
+
+struct LaunchStreamGuard {
+    rbl_ctx* c;
+    ~LaunchStreamGuard() { c->ls = c->stream; }
+};
+
+rbl_status md_run(rbl_ctx* c, double* pos, double* vel, double* force, int64_t nsteps, double dt, int P,
+                  uint64_t seed, int64_t step0, int64_t K, bool full, double* ev, bool& overflow)
+{
+    overflow = false;
+    StepParams sp;
+    sp.P = P;
+    sp.seed = seed;
+    sp.K = K;
+    sp.dt = dt;
+    sp.full = full;
+    sp.fix = !full && c->cfg.momentum_fix;
+    sp.pre = !full && c->cfg.predraw;
+    const int mask = full ? RBL_LIST_FULL : (RBL_LIST_CORE | RBL_LIST_SHELL);
+    const bool use_graph = c->cfg.graphs && !c->profiling && c->gs;
+    LaunchStreamGuard guard{c};
+    if (use_graph) {
+        HIP_TRY(hipEventRecord(c->ev_in, c->stream));
+        HIP_TRY(hipStreamWaitEvent(c->gs, c->ev_in, 0));
+        c->ls = c->gs;
+    }
+    RBL_TRY(clear_flags(c));
+    const int64_t last = step0 + nsteps;
+    int64_t build_step = step0;
+
+    auto do_build = [&](int64_t s, bool from_caller) -> rbl_status {
+        if (from_caller) RBL_TRY(bin_particles<kSrcCaller>(c, pos, vel, true));
+        else RBL_TRY(bin_particles<kSrcSorted>(c, nullptr, nullptr, true));
+        c->built = false;
+        build_step = s;
+        if (sp.pre) {
+            // batches for every force evaluation until the next rebuild
+            const int64_t until = (s / K + 1) * K;
+            const int64_t cnt = std::min(until, last + 1) - s;
+            RBL_TRY(prepare_fused(c, P, (int)K));
+            RBL_TRY(launch_fused(c, P, seed, (uint64_t)s, (int)cnt, nullptr));
+            c->built_mask = RBL_LIST_CORE;
+            c->shell_counts = true;
+        } else {
+            RBL_TRY(prepare_lists(c, mask));
+            BuildArgs a = build_args(c);
+            RBL_TRY(timed(c, kKBuild, [&] { launch_build<false>(c, a, mask); }));
+            c->built_mask = mask;
+            c->shell_counts = (mask & RBL_LIST_SHELL) != 0;
+        }
+        c->built = true;
+        return RBL_OK;
+    };
+    auto do_force = [&](int64_t s, bool energy) -> rbl_status {
+        if (full) return full_force_sorted(c, energy);
+        return rbl_force_sorted(c, P, seed, (uint64_t)s, sp.pre ? (int)(s - build_step) : -1, energy);
+    };
+
+    RBL_TRY(do_build(step0, true));
+    if (c->cfg.lanes == 0) RBL_TRY(autotune_forces(c, sp));
+    RBL_TRY(do_force(step0, ev != nullptr && nsteps == 0));
+    int64_t it = 1;
+    while (it <= nsteps) {
+        const int64_t s = step0 + it;
+        // whole list lifetimes strictly before the last force evaluation run
+        // as captured blocks; the rest is queued step by step
+        if (use_graph && it >= 2 && s % K == 0 && s + K - 1 < last) {
+            RBL_TRY(run_block(c, s, sp));
+            build_step = s;
+            c->built = true;
+            c->built_mask = sp.full ? RBL_LIST_FULL : (sp.pre ? RBL_LIST_CORE : mask);
+            c->shell_counts = !sp.full;
+            it += K;
+            continue;
+        }
+        RBL_TRY(integrate(c, it == 1 ? kIntFirst : kIntMid, dt, sp.fix));
+        if (s % K == 0) RBL_TRY(do_build(s, false));
+        RBL_TRY(do_force(s, ev != nullptr && it == nsteps));
+        ++it;
+    }
+    if (nsteps > 0) RBL_TRY(integrate(c, kIntLast, dt, sp.fix));
+    RBL_TRY(read_flags(c));
+    if (c->h_flags[kFlagOverflow]) {
+        overflow = true;
+        return RBL_OK;
+    }
+    if (c->h_flags[kFlagNonfinite]) return fail(RBL_E_NONFINITE, "non-finite position during the run");
+    if (c->h_flags[kFlagBadSlot]) return fail(RBL_E_HIP, "inconsistent cell binning");
+    IoArgs io = io_args(c, sp.fix);
+    io.pos_out = pos;
+    io.vel_out = vel;
+    io.f_out = force;
+    k_scatter_out<<<grid_for(c->n_slots), kBlock, 0, c->ls>>>(io);
+    HIP_TRY(hipGetLastError());
+    RBL_TRY(emit_ev(c, ev));
+    if (use_graph) {
+        HIP_TRY(hipEventRecord(c->ev_out, c->gs));
+        HIP_TRY(hipStreamWaitEvent(c->stream, c->ev_out, 0));
+    }
+    if (c->h_flags[kFlagSkin]) {
+        g_err = "a particle moved more than skin/2 within one list lifetime";
+        return RBL_W_SKIN;
+    }
     return RBL_OK;
 }
 
@@ -752,6 +1068,8 @@ void rbl_config_init(rbl_config* cfg, int64_t n)
     cfg->shift = 1;
     cfg->momentum_fix = 1;
     cfg->predraw = 1;
+    cfg->graphs = 1;
+    cfg->lanes = 0;
     cfg->capacity_factor = 1.25;
     cfg->replica_offsets = nullptr;
     cfg->charges = nullptr;
@@ -765,6 +1083,13 @@ rbl_status rbl_destroy(rbl_ctx* c)
 {
     if (!c) return RBL_OK;
     (void)hipStreamSynchronize(c->stream);
+    if (c->gs) (void)hipStreamSynchronize(c->gs);
+    for (int q = 0; q < 2; ++q)
+        if (c->gexec[q]) (void)hipGraphExecDestroy(c->gexec[q]);
+    if (c->gs) (void)hipStreamDestroy(c->gs);
+    if (c->ev_in) (void)hipEventDestroy(c->ev_in);
+    if (c->ev_out) (void)hipEventDestroy(c->ev_out);
+    dfree(c->d_step);
     for (int k = 0; k < kKinds; ++k)
         for (auto& pr : c->ev_pending[k]) {
             (void)hipEventDestroy(pr.first);
@@ -817,7 +1142,11 @@ rbl_status rbl_create(const rbl_config* cfg, void* hip_stream, rbl_ctx** out)
         return fail(RBL_E_ARG, "unknown precision");
     if (cfg->pair != RBL_PAIR_LJ && cfg->pair != RBL_PAIR_LJ_ERFC) return fail(RBL_E_ARG, "unknown pair");
     if (cfg->lists <= 0 || cfg->lists > 7) return fail(RBL_E_ARG, "list mask must be in 1..7");
+    if (cfg->lanes != 0 && cfg->lanes != 1 && cfg->lanes != 2 && cfg->lanes != 4)
+        return fail(RBL_E_ARG, "lanes must be 0, 1, 2 or 4");
     if (!(cfg->skin >= 0.0) || !std::isfinite(cfg->skin)) return fail(RBL_E_ARG, "skin must be >= 0");
+    if (!(cfg->capacity_factor > 0.0) || !std::isfinite(cfg->capacity_factor))
+        return fail(RBL_E_ARG, "capacity_factor must be > 0");
     if (cfg->pair == RBL_PAIR_LJ_ERFC && !(cfg->alpha > 0.0)) return fail(RBL_E_ARG, "alpha must be > 0");
     std::vector<int64_t> off(cfg->n_replicas + 1);
     if (cfg->n_replicas == 1) {
@@ -834,8 +1163,10 @@ rbl_status rbl_create(const rbl_config* cfg, void* hip_stream, rbl_ctx** out)
     c->cfg = *cfg;
     c->cfg.replica_offsets = nullptr;
     c->stream = (hipStream_t)hip_stream;
+    c->ls = c->stream;
     c->R = cfg->n_replicas;
     c->n = cfg->n;
+    if (cfg->lanes > 0) c->lpp_rbl = c->lpp_full = cfg->lanes;
     int64_t slot = 0;
     for (int r = 0; r < c->R; ++r) {
         c->id_base.push_back(off[r]);
@@ -872,16 +1203,21 @@ rbl_status rbl_create(const rbl_config* cfg, void* hip_stream, rbl_ctx** out)
     CR(dalloc(&c->d_vs[1], 3 * c->n_slots));
     CR(dalloc(&c->d_xb, 3 * c->n_slots));
     CR(dalloc(&c->d_f, 3 * c->n_slots));
-    CR(dalloc(&c->d_partial, 5 * c->n_slices));
+    CR(dalloc(&c->d_partial, 5 * 4 * c->n_slices));
     {
         int64_t mx = 1;
-        for (int r = 0; r < c->R; ++r) mx = std::max<int64_t>(mx, (c->rep_n[r] + 63) / 64);
+        for (int r = 0; r < c->R; ++r) mx = std::max<int64_t>(mx, 4 * ((c->rep_n[r] + 63) / 64));
         c->red_blocks = (int)((mx + kReduceSlicesPerBlock - 1) / kReduceSlicesPerBlock);
     }
     CR(dalloc(&c->d_part2, (size_t)5 * c->red_blocks * c->R));
     CR(dalloc(&c->d_red_counter, c->R));
     CR(dalloc(&c->d_rep_sum, 8 * c->R));
     CR(dalloc(&c->d_flags, kNumFlags));
+    CR(dalloc(&c->d_step, 1));
+    if (hipStreamCreateWithFlags(&c->gs, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) != hipSuccess)
+        return bail(fail(RBL_E_HIP, "could not create the internal stream"));
     {
         std::vector<int> id_rep(c->n), slice_rep(c->n_slices);
         for (int r = 0; r < c->R; ++r) {
@@ -930,7 +1266,7 @@ rbl_status rbl_forces(rbl_ctx* c, int P, uint64_t seed, uint64_t step, const dou
         return fail(RBL_E_STATE, "the last build has no core and shell lists");
     IoArgs io = io_args(c, c->cfg.momentum_fix != 0);
     io.pos_in = pos;
-    k_load_positions<<<grid_for(c->n_slots), kBlock, 0, c->stream>>>(io);
+    k_load_positions<<<grid_for(c->n_slots), kBlock, 0, c->ls>>>(io);
     HIP_TRY(hipGetLastError());
     if (P <= 32) {
         RBL_TRY(rbl_force_sorted(c, P, seed, step, -1, ev != nullptr));
@@ -939,7 +1275,7 @@ rbl_status rbl_forces(rbl_ctx* c, int P, uint64_t seed, uint64_t step, const dou
         RBL_TRY(rbl_force_sorted(c, P, seed, step, 0, ev != nullptr));
     }
     io.f_out = force;
-    k_scatter_out<<<grid_for(c->n_slots), kBlock, 0, c->stream>>>(io);
+    k_scatter_out<<<grid_for(c->n_slots), kBlock, 0, c->ls>>>(io);
     HIP_TRY(hipGetLastError());
     return emit_ev(c, ev);
 }
@@ -951,11 +1287,11 @@ rbl_status rbl_full_forces(rbl_ctx* c, const double* pos, double* force, double*
     if (!(c->built_mask & RBL_LIST_FULL)) return fail(RBL_E_STATE, "the last build has no full list");
     IoArgs io = io_args(c, false);
     io.pos_in = pos;
-    k_load_positions<<<grid_for(c->n_slots), kBlock, 0, c->stream>>>(io);
+    k_load_positions<<<grid_for(c->n_slots), kBlock, 0, c->ls>>>(io);
     HIP_TRY(hipGetLastError());
     RBL_TRY(full_force_sorted(c, ev != nullptr));
     io.f_out = force;
-    k_scatter_out<<<grid_for(c->n_slots), kBlock, 0, c->stream>>>(io);
+    k_scatter_out<<<grid_for(c->n_slots), kBlock, 0, c->ls>>>(io);
     HIP_TRY(hipGetLastError());
     return emit_ev(c, ev);
 }
@@ -970,59 +1306,19 @@ rbl_status rbl_step(rbl_ctx* c, double* pos, double* vel, double* force, int64_t
     if (!use_full) RBL_TRY(check_p(P));
     if (c->r_c <= 0.0) return fail(RBL_E_STATE, "rbl_step needs box and radii from rbl_build");
     const bool full = use_full != 0;
-    const bool fix = !full && c->cfg.momentum_fix;
-    const int mask = full ? RBL_LIST_FULL : (RBL_LIST_CORE | RBL_LIST_SHELL);
-    const bool pre = !full && c->cfg.predraw;
-    const int64_t K = rebuild_every;
-    RBL_TRY(clear_flags(c));
-    int64_t build_step = step0;
-
-    auto do_build = [&](int64_t s, bool from_caller) -> rbl_status {
-        if (from_caller) RBL_TRY(bin_particles<kSrcCaller>(c, pos, vel, true));
-        else RBL_TRY(bin_particles<kSrcSorted>(c, nullptr, nullptr, true));
-        c->built = false;
-        build_step = s;
-        if (pre) {
-            // batches for every force evaluation until the next rebuild
-            const int64_t until = (s / K + 1) * K;
-            const int64_t last = step0 + nsteps;
-            const int64_t cnt = std::min(until, last + 1) - s;
-            RBL_TRY(build_fused(c, P, seed, (uint64_t)s, (int)cnt));
-        } else {
-            RBL_TRY(build_lists(c, mask));
-        }
-        c->built = true;
-        return RBL_OK;
-    };
-    auto do_force = [&](int64_t s, bool energy) -> rbl_status {
-        if (full) return full_force_sorted(c, energy);
-        return rbl_force_sorted(c, P, seed, (uint64_t)s, pre ? (int)(s - build_step) : -1, energy);
-    };
-
-    RBL_TRY(do_build(step0, true));
-    RBL_TRY(do_force(step0, ev != nullptr && nsteps == 0));
-    for (int64_t it = 1; it <= nsteps; ++it) {
-        const int64_t s = step0 + it;
-        RBL_TRY(integrate(c, it == 1 ? kIntFirst : kIntMid, dt, fix));
-        if (s % K == 0) RBL_TRY(do_build(s, false));
-        RBL_TRY(do_force(s, ev != nullptr && it == nsteps));
+    // A run whose rows outgrew their capacity is repeated from the caller's
+    // arrays (written only at the end) with rows sized to what it saw.
+    for (int attempt = 0; attempt < 3; ++attempt) {
+        bool overflow = false;
+        const rbl_status st = md_run(c, pos, vel, force, nsteps, dt, P, seed, step0, rebuild_every,
+                                     full, ev, overflow);
+        if (st < 0 || !overflow) return st;
+        const int mask = full ? RBL_LIST_FULL : (c->cfg.predraw ? RBL_LIST_CORE : (RBL_LIST_CORE | RBL_LIST_SHELL));
+        for (int q = 0; q < 3; ++q)
+            if ((mask >> q) & 1) RBL_TRY(ensure_list_storage(c, q, c->h_flags[kFlagMaxCore + q], true));
+        drop_graphs(c);
     }
-    if (nsteps > 0) RBL_TRY(integrate(c, kIntLast, dt, fix));
-    IoArgs io = io_args(c, fix);
-    io.pos_out = pos;
-    io.vel_out = vel;
-    io.f_out = force;
-    k_scatter_out<<<grid_for(c->n_slots), kBlock, 0, c->stream>>>(io);
-    HIP_TRY(hipGetLastError());
-    RBL_TRY(emit_ev(c, ev));
-    RBL_TRY(read_flags(c));
-    if (c->h_flags[kFlagNonfinite]) return fail(RBL_E_NONFINITE, "non-finite position during the run");
-    if (c->h_flags[kFlagBadSlot]) return fail(RBL_E_HIP, "inconsistent cell binning");
-    if (c->h_flags[kFlagSkin]) {
-        g_err = "a particle moved more than skin/2 within one list lifetime";
-        return RBL_W_SKIN;
-    }
-    return RBL_OK;
+    return fail(RBL_E_CAPACITY, "neighbour rows kept overflowing their capacity");
 }
 
 rbl_status rbl_row_counts(rbl_ctx* c, int64_t nrows, const int64_t* rows, int64_t* counts)
@@ -1048,15 +1344,15 @@ rbl_status rbl_row_counts(rbl_ctx* c, int64_t nrows, const int64_t* rows, int64_
         dfree(d_rows);
         return st;
     }
-    (void)hipMemcpyAsync(d_rows, h_rows.data(), sizeof(int64_t) * nrows, hipMemcpyHostToDevice, c->stream);
+    (void)hipMemcpyAsync(d_rows, h_rows.data(), sizeof(int64_t) * nrows, hipMemcpyHostToDevice, c->ls);
     for (int q = 0; q < 3; ++q) {
         const bool valid = q == 1 ? c->shell_counts : ((c->built_mask >> q) & 1) != 0;
         const int* len = valid ? c->d_len[q] : nullptr;
-        k_row_counts<<<grid_for(nrows), kBlock, 0, c->stream>>>(d_rows, nrows, c->d_slot_of_id, len, d_cnt);
+        k_row_counts<<<grid_for(nrows), kBlock, 0, c->ls>>>(d_rows, nrows, c->d_slot_of_id, len, d_cnt);
         (void)hipMemcpyAsync(counts + q * nrows, d_cnt, sizeof(int64_t) * nrows, hipMemcpyDeviceToHost,
-                             c->stream);
+                             c->ls);
     }
-    hipError_t e = hipStreamSynchronize(c->stream);
+    hipError_t e = hipStreamSynchronize(c->ls);
     dfree(d_rows);
     dfree(d_cnt);
     if (e != hipSuccess) return fail(RBL_E_HIP, hipGetErrorString(e));
@@ -1084,7 +1380,7 @@ rbl_status rbl_export_lists(rbl_ctx* c, int64_t nrows, const int64_t* rows, cons
     int32_t* outs[3] = {core_idx, shell_idx, full_idx};
     int64_t* d_rows = nullptr;
     RBL_TRY(dalloc(&d_rows, nrows));
-    (void)hipMemcpyAsync(d_rows, h_rows.data(), sizeof(int64_t) * nrows, hipMemcpyHostToDevice, c->stream);
+    (void)hipMemcpyAsync(d_rows, h_rows.data(), sizeof(int64_t) * nrows, hipMemcpyHostToDevice, c->ls);
     rbl_status st = RBL_OK;
     for (int q = 0; q < 3 && st == RBL_OK; ++q) {
         if (!outs[q]) continue;
@@ -1106,13 +1402,13 @@ rbl_status rbl_export_lists(rbl_ctx* c, int64_t nrows, const int64_t* rows, cons
             dfree(d_off);
             break;
         }
-        (void)hipMemcpyAsync(d_off, offs[q], sizeof(int64_t) * (nrows + 1), hipMemcpyHostToDevice, c->stream);
-        k_export_rows<<<grid_for(nrows), kBlock, 0, c->stream>>>(d_rows, nrows, c->d_slot_of_id,
+        (void)hipMemcpyAsync(d_off, offs[q], sizeof(int64_t) * (nrows + 1), hipMemcpyHostToDevice, c->ls);
+        k_export_rows<<<grid_for(nrows), kBlock, 0, c->ls>>>(d_rows, nrows, c->d_slot_of_id,
                                                                  c->cur_perm(), c->d_list[q], c->d_len[q],
                                                                  c->cap[q], d_off, d_out);
         if (total > 0)
-            (void)hipMemcpyAsync(outs[q], d_out, sizeof(int) * total, hipMemcpyDeviceToHost, c->stream);
-        hipError_t e = hipStreamSynchronize(c->stream);
+            (void)hipMemcpyAsync(outs[q], d_out, sizeof(int) * total, hipMemcpyDeviceToHost, c->ls);
+        hipError_t e = hipStreamSynchronize(c->ls);
         dfree(d_off);
         dfree(d_out);
         if (e != hipSuccess) st = fail(RBL_E_HIP, hipGetErrorString(e));
@@ -1132,14 +1428,14 @@ rbl_status rbl_export_batches(rbl_ctx* c, int P, uint64_t seed, uint64_t step, i
     RBL_TRY(predraw(c, P, seed, step, 1));
     std::vector<int> h_batch((size_t)P * c->n_slots), h_perm(c->n_slots), h_slot(c->n), h_len(c->n_slots);
     HIP_TRY(hipMemcpyAsync(h_batch.data(), c->d_batch, sizeof(int) * h_batch.size(), hipMemcpyDeviceToHost,
-                           c->stream));
+                           c->ls));
     HIP_TRY(hipMemcpyAsync(h_perm.data(), c->cur_perm(), sizeof(int) * c->n_slots, hipMemcpyDeviceToHost,
-                           c->stream));
+                           c->ls));
     HIP_TRY(hipMemcpyAsync(h_slot.data(), c->d_slot_of_id, sizeof(int) * c->n, hipMemcpyDeviceToHost,
-                           c->stream));
+                           c->ls));
     HIP_TRY(hipMemcpyAsync(h_len.data(), c->d_len[1], sizeof(int) * c->n_slots, hipMemcpyDeviceToHost,
-                           c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));
+                           c->ls));
+    HIP_TRY(hipStreamSynchronize(c->ls));
     for (int64_t k = 0; k < nrows; ++k) {
         const int slot = h_slot[rows[k]];
         const int cnt = std::min(h_len[slot], P);
@@ -1156,11 +1452,11 @@ rbl_status rbl_export_binning(rbl_ctx* c, int32_t* ncell, int64_t* slot_of_id, i
     if (!c->built) return fail(RBL_E_STATE, "no list build");
     std::vector<int> h_slot(c->n);
     HIP_TRY(hipMemcpyAsync(h_slot.data(), c->d_slot_of_id, sizeof(int) * c->n, hipMemcpyDeviceToHost,
-                           c->stream));
+                           c->ls));
     if (cell_count)
         HIP_TRY(hipMemcpyAsync(cell_count, c->d_cell_count, sizeof(int) * c->n_cells, hipMemcpyDeviceToHost,
-                               c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));
+                               c->ls));
+    HIP_TRY(hipStreamSynchronize(c->ls));
     for (int r = 0; r < c->R; ++r) {
         for (int a = 0; a < 3; ++a) ncell[3 * r + a] = c->h_rep[r].nc[a];
         for (int64_t i = c->id_base[r]; i < c->id_base[r] + c->rep_n[r]; ++i)
@@ -1176,7 +1472,7 @@ rbl_status rbl_sync(rbl_ctx* c)
     const int nonfinite = c->h_flags[kFlagNonfinite];
     const int skin = c->h_flags[kFlagSkin];
     RBL_TRY(clear_flags(c));
-    HIP_TRY(hipStreamSynchronize(c->stream));
+    HIP_TRY(hipStreamSynchronize(c->ls));
     if (nonfinite) return fail(RBL_E_NONFINITE, "non-finite particle position");
     if (skin) {
         g_err = "a particle moved more than skin/2 within one list lifetime";
@@ -1203,6 +1499,17 @@ rbl_status rbl_kernel_stats(rbl_ctx* c, int kind, int64_t* launches, double* tot
     RBL_TRY(resolve_events(c));
     *launches = c->stat_launches[kind];
     *total_ms = c->stat_ms[kind];
+    return RBL_OK;
+}
+
+rbl_status rbl_tuning(rbl_ctx* c, int32_t* lpp_rbl, int32_t* lpp_full, double* force_us)
+{
+    if (!c) return fail(RBL_E_ARG, "NULL context");
+    if (lpp_rbl) *lpp_rbl = c->lpp_rbl;
+    if (lpp_full) *lpp_full = c->lpp_full;
+    if (force_us)
+        for (int k = 0; k < 2; ++k)
+            for (int q = 0; q < 3; ++q) force_us[3 * k + q] = c->tune_us[k][q];
     return RBL_OK;
 }
 

@@ -187,15 +187,17 @@ def test_trajectory_matches_oracle():
 
 @pytest.mark.parametrize("predraw", [True, False])
 def test_step_restart_and_determinism(predraw):
-    """20 steps straight equal 10 + 10 resumed at a rebuild boundary, bit for
-    bit; pre-drawn and inline batches give the same trajectory."""
-    torch = torch_cuda()
+    """40 steps straight equal 20 + 20 resumed at a rebuild boundary, bit for
+    bit; pre-drawn and inline batches, and captured-graph and step-by-step
+    execution, give the same trajectory (one lane per particle, the layout
+    the inline-draw kernel has)."""
+    torch_cuda()
     st = inputs.small_fluid(seed=3)
     n = st.n
     runs = []
-    for chunks in ((20,), (10, 10)):
+    for chunks in ((40,), (20, 20)):
         x, v = dev(st.pos), dev(st.vel)
-        with Context(n, predraw=predraw) as ctx:
+        with Context(n, predraw=predraw, lanes=1) as ctx:
             ctx.build(x, st.box, RS, RC)
             s0 = 0
             for c in chunks:
@@ -204,11 +206,33 @@ def test_step_restart_and_determinism(predraw):
         runs.append((host(x), host(v)))
     assert np.array_equal(runs[0][0], runs[1][0])
     assert np.array_equal(runs[0][1], runs[1][1])
-    x2, v2 = dev(st.pos), dev(st.vel)
-    with Context(n, predraw=not predraw) as ctx:
-        ctx.build(x2, st.box, RS, RC)
-        ctx.step(x2, v2, nsteps=20, dt=0.005, P=10, seed=9, step0=0, rebuild_every=10)
-    assert np.array_equal(runs[0][0], host(x2))
+    for kw in ({"predraw": not predraw}, {"predraw": predraw, "graphs": False}):
+        x2, v2 = dev(st.pos), dev(st.vel)
+        with Context(n, lanes=1, **kw) as ctx:
+            ctx.build(x2, st.box, RS, RC)
+            ctx.step(x2, v2, nsteps=40, dt=0.005, P=10, seed=9, step0=0, rebuild_every=10)
+        assert np.array_equal(runs[0][0], host(x2)), kw
+        assert np.array_equal(runs[0][1], host(v2)), kw
+
+
+def test_step_overflow_restart():
+    """Rows sized tightly at a lattice-like first build overflow once the
+    fluid melts; the run is repeated from the caller's arrays with larger
+    rows and matches a run that never overflowed, bit for bit."""
+    torch_cuda()
+    st = inputs.small_fluid(seed=4)
+    runs, caps = [], []
+    for factor in (0.5, 3.0):
+        x, v = dev(st.pos), dev(st.vel)
+        with Context(st.n, capacity_factor=factor, lists=("core",), lanes=4) as ctx:
+            ctx.build(x, st.box, RS, RC)
+            cap0 = ctx.info()["cap_core"]
+            ctx.step(x, v, nsteps=200, dt=0.005, P=10, seed=2, rebuild_every=10)
+            caps.append((cap0, ctx.info()["cap_core"]))
+        runs.append((host(x), host(v)))
+    assert caps[0][1] > caps[0][0], caps          # the tight context regrew its rows
+    assert np.array_equal(runs[0][0], runs[1][0])
+    assert np.array_equal(runs[0][1], runs[1][1])
 
 
 def test_full_list_nve_energy():
@@ -330,3 +354,35 @@ def test_skin_warning_on_large_displacement():
         x, v = dev(pos), dev(np.zeros((3, 2)))
         status, _ = ctx.step(x, v, nsteps=10, dt=0.005, P=10, seed=1, rebuild_every=10)
         assert status == _lib.RBL_OK
+
+
+@pytest.mark.parametrize("lanes", [1, 2, 4])
+def test_lanes_per_particle_variants_match_oracle(lanes):
+    """Every lanes-per-particle layout of the pre-drawn RBL and full-list
+    kernels stays within tolerance of the oracle along a trajectory."""
+    torch_cuda()
+    st = inputs.small_fluid(seed=1)
+    for use_full in (False, True):
+        x, v = dev(st.pos), dev(st.vel)
+        lists = ("full",) if use_full else ("core", "shell")
+        with Context(st.n, lanes=lanes, lists=lists) as ctx:
+            ctx.build(x, st.box, RS, RC)
+            ctx.step(x, v, nsteps=30, dt=0.005, P=10, seed=1, rebuild_every=10, use_full=use_full)
+            assert ctx.tuning()["lpp_rbl"] == lanes
+        xo, vo, _, _ = oracle.md_run(st.pos, st.vel, st.box, RS, RC, SKIN, 0.005, 30, p=10, seed=1,
+                                     K=10, use_full=use_full)
+        assert rel_l2(host(x), xo) < 1e-12
+        assert rel_l2(host(v), vo) < 1e-9
+
+
+def test_autotuner_picks_a_measured_layout():
+    torch_cuda()
+    st = inputs.small_fluid(seed=1)
+    x, v = dev(st.pos), dev(st.vel)
+    with Context(st.n) as ctx:
+        ctx.build(x, st.box, RS, RC)
+        ctx.step(x, v, nsteps=20, dt=0.005, P=10, seed=1, rebuild_every=10)
+        t = ctx.tuning()
+    assert t["lpp_rbl"] in (1, 2, 4)
+    assert all(u > 0 for u in t["rbl_us"])
+    assert t["rbl_us"][(1, 2, 4).index(t["lpp_rbl"])] == min(t["rbl_us"])
