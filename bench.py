@@ -48,6 +48,9 @@ def parse():
     ap.add_argument("--cpu-rows", type=int, default=100_000,
                     help="rows of the N = 1M state the CPU oracle leg processes")
     ap.add_argument("--variants", default="all", help="comma list or 'all'")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (a reference for "
+                         "the HBM byte counters of a profiler run)")
     return ap.parse_args()
 
 
@@ -168,6 +171,15 @@ def main():
     import torch
     from paper_2105_04884_amd import inputs
 
+    if args.calib_copy_mb > 0:
+        src = torch.empty(args.calib_copy_mb * 2**20 // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy: {args.calib_copy_mb} MiB read + {args.calib_copy_mb} MiB written, 3 launches")
+        del src, dst
     log("[bench] generating the N=1M fluid")
     st = inputs.million_fluid(seed=1)
     x0 = torch.from_numpy(st.pos).cuda()

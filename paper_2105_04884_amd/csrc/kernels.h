@@ -643,39 +643,88 @@ __device__ __forceinline__ int axis_shift(const AxisRunsS& a, int k)
     return k < a.l0 ? a.s0 : a.s1;
 }
 
-template <int PMAX>
-__global__ __launch_bounds__(256) void k_build_draw2(FusedArgs fa)
+// ---------------------------------------------------------------------------
+// Implementation notes of k_build_draw:
+//  - every cell-level quantity (cell range, replica geometry) is made
+//    wave-uniform with readfirstlane, so it lives in SGPRs;
+//  - SHIFT (all axes >= 7 cells) and canonical-formula variants are
+//    separate kernels, so the inner loop has no branch;
+//  - a byte table maps each flat stencil candidate to its run, so a
+//    candidate (and a drawn partner) is resolved with one LDS read instead
+//    of a binary search (stencils of up to kCandBudget candidates; larger
+//    ones use the search);
+//  - per centre particle and chunk, the core and shell ballots are written
+//    into lane ii of four VGPRs with v_writelane.
+constexpr int kCandBudget = 2048;
+
+__device__ __forceinline__ int rfl(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ double rfl(double v)
+{
+    const int lo = __builtin_amdgcn_readfirstlane(__double2loint(v));
+    const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ int64_t rfl(int64_t v)
+{
+    const int lo = __builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const int hi = __builtin_amdgcn_readfirstlane((int)(v >> 32));
+    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// v_writelane_b32 through its LLVM intrinsic, so that the compiler itself
+// places the lane select (in M0 when the data operand is an SGPR).
+extern "C" __device__ int rbl_writelane(int value, int lane, int old) __asm("llvm.amdgcn.writelane");
+
+// Lane `lane` of v0..v3 takes the wave-uniform values s0..s3.
+__device__ __forceinline__ void write_lane4(uint32_t& v0, uint32_t& v1, uint32_t& v2, uint32_t& v3,
+                                            uint32_t s0, uint32_t s1, uint32_t s2, uint32_t s3, int lane)
+{
+    v0 = (uint32_t)rbl_writelane((int)s0, lane, (int)v0);
+    v1 = (uint32_t)rbl_writelane((int)s1, lane, (int)v1);
+    v2 = (uint32_t)rbl_writelane((int)s2, lane, (int)v2);
+    v3 = (uint32_t)rbl_writelane((int)s3, lane, (int)v3);
+}
+
+template <int PMAX, bool SHIFT>
+__global__ __launch_bounds__(256) void k_build_draw(FusedArgs fa)
 {
     __shared__ double4 s_ctr[4][64];
-    __shared__ ulonglong2 s_mask[4][kMaskBudget / 2];  // (core, shell) per (ii, chunk)
+    __shared__ uint64_t s_smask[4][kMaskBudget / 2];    // shell mask per (ii, chunk)
+    __shared__ int s_cum[4][kMaskBudget / 2];           // shell-rank prefix per (ii, chunk)
     __shared__ int s_rstart[4][64];
     __shared__ int s_rpre[4][64];
-    __shared__ int s_rshift[4][64];                     // packed image shifts of each run
+    __shared__ int s_rshift[4][64];
     __shared__ int s_ncnt[4][64];
-    __shared__ int s_cum[4][kMaskBudget / 2];           // shell-rank prefix per (ii, chunk)
+    __shared__ unsigned char s_runf[4][kCandBudget];    // run of each flat candidate
     const BuildArgs& a = fa.b;
     const int lane = threadIdx.x & 63;
-    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int w = rfl((int)(threadIdx.x >> 6));
     const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
     const int64_t cell = tile * 4 + w;
     if (cell >= a.n_cells) return;
-    const int m = a.cell_count[cell];
+    const int m = rfl(a.cell_count[cell]);
     if (m == 0) return;
-    const int i0 = a.cell_start[cell];
+    const int i0 = rfl(a.cell_start[cell]);
     if (i0 < 0 || (int64_t)i0 + m > a.n_slots) {
         if (lane == 0) atomicOr(&a.flags[kFlagBadSlot], 2);
         return;
     }
-    const int rep_id = a.cell_rep[cell];
-    const DevReplica& R = a.rep[rep_id];
-    const int64_t lc = cell - R.cell_base;
-    const int cx = (int)(lc % R.nc[0]);
-    const int cy = (int)((lc / R.nc[0]) % R.nc[1]);
-    const int cz = (int)(lc / ((int64_t)R.nc[0] * R.nc[1]));
-    const AxisRunsS ax = axis_runs_s(cx, R.nc[0]);
-    const AxisRunsS ay = axis_runs_s(cy, R.nc[1]);
-    const AxisRunsS az = axis_runs_s(cz, R.nc[2]);
-    const bool shift_path = R.nc[0] >= 7 && R.nc[1] >= 7 && R.nc[2] >= 7;
+    const int rep_id = rfl(a.cell_rep[cell]);
+    const DevReplica* Rp = a.rep + rep_id;
+    const double L0 = rfl(Rp->L[0]), L1 = rfl(Rp->L[1]), L2 = rfl(Rp->L[2]);
+    const double iL0 = rfl(Rp->inv[0]), iL1 = rfl(Rp->inv[1]), iL2 = rfl(Rp->inv[2]);
+    const int nc0 = rfl(Rp->nc[0]), nc1 = rfl(Rp->nc[1]), nc2 = rfl(Rp->nc[2]);
+    const int64_t cell_base = rfl(Rp->cell_base);
+    const int64_t id_base = rfl(Rp->id_base);
+    const int64_t lc = cell - cell_base;
+    const int cx = (int)(lc % nc0);
+    const int cy = (int)((lc / nc0) % nc1);
+    const int cz = (int)(lc / ((int64_t)nc0 * nc1));
+    const AxisRunsS ax = axis_runs_s(cx, nc0);
+    const AxisRunsS ay = axis_runs_s(cy, nc1);
+    const AxisRunsS az = axis_runs_s(cz, nc2);
     const int ny_s = ay.l0 + ay.l1;
     const int nz_s = az.l0 + az.l1;
     int rstart = 0, rlen = 0, rshift = 0;
@@ -690,7 +739,7 @@ __global__ __launch_bounds__(256) void k_build_draw2(FusedArgs fa)
             const int px = xr == 0 ? ax.p0 : ax.p1;
             const int lx = xr == 0 ? ax.l0 : ax.l1;
             if (lx > 0) {
-                const int64_t row = R.cell_base + ((int64_t)zc * R.nc[1] + yc) * R.nc[0];
+                const int64_t row = cell_base + ((int64_t)zc * nc1 + yc) * nc0;
                 const int64_t c0 = row + px;
                 const int64_t c1 = row + px + lx - 1;
                 rstart = a.cell_start[c0];
@@ -703,30 +752,37 @@ __global__ __launch_bounds__(256) void k_build_draw2(FusedArgs fa)
         }
     }
     const int incl = wave_incl_scan(rlen);
-    const int total = __builtin_amdgcn_readlane(incl, 63);
+    const int total = rfl(__builtin_amdgcn_readlane(incl, 63));
+    const int rpre = incl - rlen;
     s_rstart[w][lane] = rstart;
-    s_rpre[w][lane] = incl - rlen;
+    s_rpre[w][lane] = rpre;
     s_rshift[w][lane] = rshift;
     const int nch = (total + 63) >> 6;
     if (nch > kMaskBudget / 2) {
         if (lane == 0) atomicOr(&a.flags[kFlagBadSlot], 16);
         return;
     }
+    const bool table = total <= kCandBudget;
+    if (table)
+        for (int t = 0; t < rlen; ++t) s_runf[w][rpre + t] = (unsigned char)lane;
     const int gmax = nch > 0 ? min(64, (kMaskBudget / 2) / nch) : 64;
     const int P = fa.P;
     wave_lds_fence();
 
-    // candidate f of the flattened stencil: its slot, position and the packed
-    // periodic image shift of its run (j = -1 past the end of the stencil)
-    auto candidate = [&](int f, int& j, double4& xj, int& code) {
+    auto run_of = [&](int f) -> int {
+        if (table) return s_runf[w][f];
         int q = 0;
 #pragma unroll
-        for (int step = 32; step > 0; step >>= 1)
-            if (s_rpre[w][q + step] <= f) q += step;
+        for (int st = 32; st > 0; st >>= 1) q = s_rpre[w][q + st] <= f ? q + st : q;
+        return q;
+    };
+    // candidate f: slot (-1 past the stencil), position, image-shift code
+    auto candidate = [&](int f, int& j, double4& xj, int& code) {
+        const bool in = f < total;
+        const int q = run_of(in ? f : 0);
         j = s_rstart[w][q] + (f - s_rpre[w][q]);
         code = s_rshift[w][q];
-        const bool valid = f < total && j >= 0 && (int64_t)j < a.n_slots;
-        if (valid) {
+        if (in && j >= 0 && (int64_t)j < a.n_slots) {
             xj = a.xs[j];
         } else {
             j = -1;
@@ -739,7 +795,7 @@ __global__ __launch_bounds__(256) void k_build_draw2(FusedArgs fa)
         const int mg = min(gmax, m - g0);
         if (lane < mg) s_ctr[w][lane] = a.xs[i0 + g0 + lane];
         wave_lds_fence();
-        int cnt_core = 0;  // lane ii: entries written to particle ii's core row
+        int cnt_core = 0;
         const int my_slot = i0 + g0 + lane;
         int jn = -1, coden = 0;
         double4 xn = make_double4(0.0, 0.0, 0.0, 0.0);
@@ -749,36 +805,36 @@ __global__ __launch_bounds__(256) void k_build_draw2(FusedArgs fa)
             const double4 xc = xn;
             const int code = coden;
             if (ch + 1 < nch) candidate((ch + 1) * 64 + lane, jn, xn, coden);
-            const double shx = (double)((code & 3) - 1) * R.L[0];
-            const double shy = (double)(((code >> 2) & 3) - 1) * R.L[1];
-            const double shz = (double)(((code >> 4) & 3) - 1) * R.L[2];
+            double shx = 0.0, shy = 0.0, shz = 0.0;
+            if (SHIFT) {
+                shx = (double)((code & 3) - 1) * L0;
+                shy = (double)(((code >> 2) & 3) - 1) * L1;
+                shz = (double)(((code >> 4) & 3) - 1) * L2;
+            }
+            const uint64_t valid = __ballot(jc >= 0);
             uint32_t mclo = 0, mchi = 0, mslo = 0, mshi = 0;
             for (int ii = 0; ii < mg; ++ii) {
                 const double4 xi = s_ctr[w][ii];
                 double dx, dy, dz;
-                if (shift_path) {
+                if (SHIFT) {
                     dx = (xi.x - xc.x) + shx;
                     dy = (xi.y - xc.y) + shy;
                     dz = (xi.z - xc.z) + shz;
                 } else {
-                    dx = min_image(xi.x - xc.x, R.L[0], R.inv[0]);
-                    dy = min_image(xi.y - xc.y, R.L[1], R.inv[1]);
-                    dz = min_image(xi.z - xc.z, R.L[2], R.inv[2]);
+                    dx = min_image(xi.x - xc.x, L0, iL0);
+                    dy = min_image(xi.y - xc.y, L1, iL1);
+                    dz = min_image(xi.z - xc.z, L2, iL2);
                 }
                 const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-                const bool notself = jc >= 0 && jc != i0 + g0 + ii;
-                const uint64_t mc = __ballot(notself && r2 < a.thr_core);
-                const uint64_t ms = __ballot(notself && r2 >= a.thr_shell_in && r2 < a.thr_out);
-                const bool mine = lane == ii;
-                mclo = mine ? (uint32_t)mc : mclo;
-                mchi = mine ? (uint32_t)(mc >> 32) : mchi;
-                mslo = mine ? (uint32_t)ms : mslo;
-                mshi = mine ? (uint32_t)(ms >> 32) : mshi;
+                const uint64_t other = valid & ~__ballot(jc == i0 + g0 + ii);
+                const uint64_t mc = other & __ballot(r2 < a.thr_core);
+                const uint64_t ms = other & __ballot(r2 >= a.thr_shell_in) & __ballot(r2 < a.thr_out);
+                write_lane4(mclo, mchi, mslo, mshi, (uint32_t)mc, (uint32_t)(mc >> 32), (uint32_t)ms,
+                            (uint32_t)(ms >> 32), ii);
             }
             uint64_t mcore = ((uint64_t)mchi << 32) | mclo;
             const uint64_t mshell = ((uint64_t)mshi << 32) | mslo;
-            if (lane < mg) s_mask[w][lane * nch + ch] = make_ulonglong2(mcore, mshell);
-            // core scatter: lane ii appends the partners of its set bits
+            if (lane < mg) s_smask[w][lane * nch + ch] = mshell;
             if (lane >= mg) mcore = 0;
             while (__ballot(mcore != 0)) {
                 const int b = mcore ? (int)__builtin_ctzll(mcore) : 0;
@@ -791,13 +847,11 @@ __global__ __launch_bounds__(256) void k_build_draw2(FusedArgs fa)
             }
         }
         wave_lds_fence();
-        // row lengths, shell counts and, per particle, the exclusive prefix of
-        // shell-mask popcounts over the chunks (rank -> chunk lookup)
         int ns = 0;
         if (lane < mg) {
             for (int ch = 0; ch < nch; ++ch) {
                 s_cum[w][lane * nch + ch] = ns;
-                ns += __popcll(s_mask[w][lane * nch + ch].y);
+                ns += __popcll(s_smask[w][lane * nch + ch]);
             }
             a.core_len[my_slot] = min(cnt_core, a.cap_core);
             a.shell_len[my_slot] = ns;
@@ -811,10 +865,9 @@ __global__ __launch_bounds__(256) void k_build_draw2(FusedArgs fa)
             raise_max(&a.flags[kFlagMaxShell], mxs);
             if (mxc > a.cap_core) raise_flag(&a.flags[kFlagOverflow]);
         }
-        // batches: one lane per (particle, step) pair.  Each drawn rank k is
-        // located independently (fixed-step binary searches, so the P
-        // lookups of a lane overlap): chunk by the popcount prefix, bit by
-        // select, run by the run prefix.
+        // batches: one lane per (particle, step) pair; each drawn rank is
+        // located independently: chunk by the popcount prefix, bit by
+        // select, run by the byte table
         const int pairs = mg * fa.K;
         for (int pb = 0; pb < pairs; pb += 64) {
             const int pr = pb + lane;
@@ -823,40 +876,44 @@ __global__ __launch_bounds__(256) void k_build_draw2(FusedArgs fa)
                 const int rr = pr - ii * fa.K;
                 const int islot = i0 + g0 + ii;
                 const int n = s_ncnt[w][ii];
-                const ulonglong2* mk = &s_mask[w][ii * nch];
+                const uint64_t* mk = &s_smask[w][ii * nch];
                 const int* cum = &s_cum[w][ii * nch];
                 int* out = fa.batch + batch_index(rr, islot, 0, a.n_slots, P);
-                bool bad = false;
-                auto lookup = [&](int k) -> int {
-                    // nch <= kMaskBudget / 2 = 256: eight fixed steps
+                uint32_t S[PMAX];
+                if (n <= P) {
+#pragma unroll
+                    for (int qq = 0; qq < PMAX; ++qq) S[qq] = (uint32_t)qq;
+                } else {
+                    const uint32_t pid = (uint32_t)(fa.perm[islot] - id_base);
+                    const uint64_t s0 = fa.step_dev ? *fa.step_dev + fa.step0 : fa.step0;
+                    floyd_draw<PMAX>(S, fa.seed, pid, (uint32_t)(s0 + rr), (uint32_t)rep_id, P, n);
+                }
+                const int cnt = n < P ? n : P;
+                int jv[PMAX];
+#pragma unroll
+                for (int qq = 0; qq < PMAX; ++qq) {
+                    const int k = (int)min(S[qq], (uint32_t)max(n - 1, 0));
                     int c = 0;
 #pragma unroll
                     for (int st = 128; st > 0; st >>= 1) {
-                        const int t = min(c + st, nch - 1);
+                        const int t = min(c + st, max(nch - 1, 0));
                         c = (c + st < nch && cum[t] <= k) ? c + st : c;
                     }
-                    const int f = c * 64 + select_bit(mk[c].y, k - cum[c]);
-                    int q = 0;
+                    const int f = c * 64 + select_bit(mk[c], k - cum[c]);
+                    const int q = run_of(f);
+                    jv[qq] = s_rstart[w][q] + (f - s_rpre[w][q]);
+                }
+                bool bad = false;
 #pragma unroll
-                    for (int st = 32; st > 0; st >>= 1)
-                        if (s_rpre[w][q + st] <= f) q += st;
-                    int j = s_rstart[w][q] + (f - s_rpre[w][q]);
-                    if (j < 0 || (int64_t)j >= a.n_slots) {
-                        bad = true;
-                        j = islot;
+                for (int qq = 0; qq < PMAX; ++qq) {
+                    if (qq < cnt) {
+                        int j = jv[qq];
+                        if (j < 0 || (int64_t)j >= a.n_slots) {
+                            bad = true;
+                            j = islot;
+                        }
+                        out[qq] = j;
                     }
-                    return j;
-                };
-                if (n <= P) {
-                    for (int k = 0; k < n; ++k) out[k] = lookup(k);
-                } else {
-                    uint32_t S[PMAX];
-                    const uint32_t pid = (uint32_t)(fa.perm[islot] - R.id_base);
-                    const uint64_t s0 = fa.step_dev ? *fa.step_dev + fa.step0 : fa.step0;
-                    floyd_draw<PMAX>(S, fa.seed, pid, (uint32_t)(s0 + rr), (uint32_t)rep_id, P, n);
-#pragma unroll
-                    for (int qq = 0; qq < PMAX; ++qq)
-                        if (qq < P) out[qq] = lookup((int)S[qq]);
                 }
                 if (bad) atomicOr(&a.flags[kFlagBadSlot], 32);
             }
@@ -1230,58 +1287,53 @@ __global__ __launch_bounds__(256) void k_forces_lpp(ForceArgs a)
 }
 
 // Per-replica sums of the wavefront partials in a fixed order, so the result
-// does not depend on scheduling.  Block (b, r) sums slices b*per .. of
-// replica r into part2[r][b]; the last block of a replica to finish (counted
-// with an atomic that it resets) adds the part2 entries in block order.
-// rep_sum[8r + q], q = Fx, Fy, Fz, U, W.
+// does not depend on scheduling.  Stage 1: block (b, r) sums entries
+// b*256 .. of replica r into part2[r][b].  Stage 2: one block per replica
+// adds its part2 entries (no atomics: all blocks of stage 1 are done when
+// stage 2 starts).  rep_sum[8r + q], q = Fx, Fy, Fz, U, W.
 constexpr int kReduceSlicesPerBlock = 256;
 
 __global__ __launch_bounds__(256) void k_reduce(const DevReplica* rep, const double* partial,
                                                int64_t n_slices, int per, int blocks_per_rep,
-                                               double* part2, unsigned* counter, double* rep_sum)
+                                               double* part2)
 {
     __shared__ double lds[5][4];
-    __shared__ bool is_last;
     const int r = blockIdx.y;
     const int b = blockIdx.x;
     const DevReplica& R = rep[r];
     // `per` partial entries per slice (one per wavefront of the force kernel)
     const int64_t s0 = (R.slot_base >> 6) * per;
     const int64_t ns = ((R.n + 63) >> 6) * per;
-    n_slices *= per;
+    const int64_t stride = n_slices * per;
     const int64_t lo = (int64_t)b * kReduceSlicesPerBlock;
+    if (lo >= ns) return;
     const int64_t hi = min(ns, lo + kReduceSlicesPerBlock);
     const int wv = threadIdx.x >> 6;
+    for (int q = 0; q < 5; ++q) {
+        const int64_t s = lo + threadIdx.x;
+        double acc = s < hi ? partial[q * stride + s0 + s] : 0.0;
+        acc = wave_sum(acc);
+        if ((threadIdx.x & 63) == 0) lds[q][wv] = acc;
+    }
+    __syncthreads();
+    if (threadIdx.x < 5) {
+        const int q = threadIdx.x;
+        part2[((int64_t)r * blocks_per_rep + b) * 5 + q] = ((lds[q][0] + lds[q][1]) + lds[q][2]) + lds[q][3];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_reduce_final(const DevReplica* rep, int per, int blocks_per_rep,
+                                                     const double* part2, double* rep_sum)
+{
+    __shared__ double lds[5][4];
+    const int r = blockIdx.x;
+    const DevReplica& R = rep[r];
+    const int64_t ns = ((R.n + 63) >> 6) * per;
     const int nb = (int)((ns + kReduceSlicesPerBlock - 1) / kReduceSlicesPerBlock);
-    if (b < nb) {
-        for (int q = 0; q < 5; ++q) {
-            const int64_t s = lo + threadIdx.x;
-            double acc = s < hi ? partial[q * n_slices + s0 + s] : 0.0;
-            acc = wave_sum(acc);
-            if ((threadIdx.x & 63) == 0) lds[q][wv] = acc;
-        }
-        __syncthreads();
-        if (threadIdx.x < 5) {
-            const int q = threadIdx.x;
-            part2[((int64_t)r * blocks_per_rep + b) * 5 + q] = ((lds[q][0] + lds[q][1]) + lds[q][2]) + lds[q][3];
-        }
-    }
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const unsigned done = atomicAdd(&counter[r], 1u);
-        is_last = done == (unsigned)(blocks_per_rep - 1);
-    }
-    __syncthreads();
-    if (!is_last) return;
-    __threadfence();
-    // the last block adds the per-block sums: thread t takes blocks t,
-    // t+256, ..., then the fixed-order block reduction
+    const int wv = threadIdx.x >> 6;
     for (int q = 0; q < 5; ++q) {
         double acc = 0.0;
-        for (int k = threadIdx.x; k < nb; k += blockDim.x)
-            acc += __hip_atomic_load(&part2[((int64_t)r * blocks_per_rep + k) * 5 + q], __ATOMIC_RELAXED,
-                                     __HIP_MEMORY_SCOPE_AGENT);
+        for (int k = threadIdx.x; k < nb; k += blockDim.x) acc += part2[((int64_t)r * blocks_per_rep + k) * 5 + q];
         acc = wave_sum(acc);
         if ((threadIdx.x & 63) == 0) lds[q][wv] = acc;
     }
@@ -1290,7 +1342,6 @@ __global__ __launch_bounds__(256) void k_reduce(const DevReplica* rep, const dou
         const int q = threadIdx.x;
         rep_sum[8 * r + q] = ((lds[q][0] + lds[q][1]) + lds[q][2]) + lds[q][3];
     }
-    if (threadIdx.x == 0) counter[r] = 0u;
 }
 
 // ---------------------------------------------------------------------------

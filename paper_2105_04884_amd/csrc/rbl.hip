@@ -128,7 +128,6 @@ struct rbl_ctx {
     bool tuned_rbl = false, tuned_full = false;
     double tune_us[2][3] = {{0, 0, 0}, {0, 0, 0}};  // measured force time per LPP 1, 2, 4
     double* d_part2 = nullptr;
-    unsigned* d_red_counter = nullptr;
     int red_blocks = 1;
     double* d_rep_sum = nullptr;
     int* d_flags = nullptr;
@@ -527,14 +526,23 @@ rbl_status launch_fused(rbl_ctx* c, int P, uint64_t seed, uint64_t step0, int K,
     fa.K = K;
     fa.P = P;
     const unsigned g = grid_for(c->n_cells, 4);
+    bool shift = true;  // every axis of every replica has >= 7 cells
+    for (const DevReplica& r : c->h_rep)
+        for (int d = 0; d < 3; ++d) shift = shift && r.nc[d] >= 7;
     return timed(c, kKBuild, [&] {
-        if (P <= 8) k_build_draw2<8><<<g, kBlock, 0, c->ls>>>(fa);
-        else if (P <= 12) k_build_draw2<12><<<g, kBlock, 0, c->ls>>>(fa);
-        else if (P <= 16) k_build_draw2<16><<<g, kBlock, 0, c->ls>>>(fa);
-        else if (P <= 24) k_build_draw2<24><<<g, kBlock, 0, c->ls>>>(fa);
-        else if (P <= 32) k_build_draw2<32><<<g, kBlock, 0, c->ls>>>(fa);
-        else if (P <= 64) k_build_draw2<64><<<g, kBlock, 0, c->ls>>>(fa);
-        else k_build_draw2<128><<<g, kBlock, 0, c->ls>>>(fa);
+#define RBL_BD(PM)                                                          \
+    do {                                                                    \
+        if (shift) k_build_draw<PM, true><<<g, kBlock, 0, c->ls>>>(fa);    \
+        else k_build_draw<PM, false><<<g, kBlock, 0, c->ls>>>(fa);         \
+    } while (0)
+        if (P <= 8) RBL_BD(8);
+        else if (P <= 12) RBL_BD(12);
+        else if (P <= 16) RBL_BD(16);
+        else if (P <= 24) RBL_BD(24);
+        else if (P <= 32) RBL_BD(32);
+        else if (P <= 64) RBL_BD(64);
+        else RBL_BD(128);
+#undef RBL_BD
     });
 }
 
@@ -686,8 +694,9 @@ rbl_status reduce(rbl_ctx* c)
 {
     return timed(c, kKReduce, [&] {
         k_reduce<<<dim3(c->red_blocks, c->R), kBlock, 0, c->ls>>>(
-            c->d_rep, c->d_partial, c->n_slices, c->part_per, c->red_blocks, c->d_part2, c->d_red_counter,
-            c->d_rep_sum);
+            c->d_rep, c->d_partial, c->n_slices, c->part_per, c->red_blocks, c->d_part2);
+        k_reduce_final<<<c->R, kBlock, 0, c->ls>>>(c->d_rep, c->part_per, c->red_blocks, c->d_part2,
+                                                   c->d_rep_sum);
     });
 }
 
@@ -1122,7 +1131,6 @@ rbl_status rbl_destroy(rbl_ctx* c)
     dfree(c->d_batch);
     dfree(c->d_partial);
     dfree(c->d_part2);
-    dfree(c->d_red_counter);
     dfree(c->d_rep_sum);
     dfree(c->d_flags);
     delete c;
@@ -1210,7 +1218,6 @@ rbl_status rbl_create(const rbl_config* cfg, void* hip_stream, rbl_ctx** out)
         c->red_blocks = (int)((mx + kReduceSlicesPerBlock - 1) / kReduceSlicesPerBlock);
     }
     CR(dalloc(&c->d_part2, (size_t)5 * c->red_blocks * c->R));
-    CR(dalloc(&c->d_red_counter, c->R));
     CR(dalloc(&c->d_rep_sum, 8 * c->R));
     CR(dalloc(&c->d_flags, kNumFlags));
     CR(dalloc(&c->d_step, 1));
@@ -1234,7 +1241,6 @@ rbl_status rbl_create(const rbl_config* cfg, void* hip_stream, rbl_ctx** out)
     CR(fill_i32(c, c->d_perm[0], c->n_slots, -1));
     CR(fill_i32(c, c->d_perm[1], c->n_slots, -1));
     CR(fill_i32(c, c->d_flags, kNumFlags, 0));
-    CR(fill_i32(c, (int*)c->d_red_counter, c->R, 0));
     if (hipStreamSynchronize(c->stream) != hipSuccess) return bail(fail(RBL_E_HIP, "stream sync failed"));
 #undef CR
     *out = c;
