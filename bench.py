@@ -19,6 +19,7 @@ Prints one JSON line (rank 0, N = 1 GPU).
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -45,21 +46,152 @@ def parse():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rows", type=int, default=100_000,
+    ap.add_argument("--cpu-rows", type=int, default=400_000,
                     help="rows of the N = 1M state the CPU oracle leg processes")
     ap.add_argument("--variants", default="all", help="comma list or 'all'")
-    ap.add_argument("--calib-copy-mb", type=int, default=0,
-                    help="also run a plain device copy of this many MiB (a reference for "
-                         "the HBM byte counters of a profiler run)")
+    ap.add_argument("--summarize", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
+                    help="instead of running: write the profiles/ summaries from the output "
+                         "folders of a rocprofv3 --kernel-trace --stats run and two --pmc runs "
+                         "(FETCH_SIZE, WRITE_SIZE) of this script")
+    ap.add_argument("--profile-command", default="",
+                    help="with --summarize: the bench.py arguments the profiled runs used")
+    ap.add_argument("--calib-copy-mb", type=int, default=1024,
+                    help="size of the plain device copy timed first: the attainable HBM "
+                         "bandwidth, and the reference for the byte counters of a profiler run")
     return ap.parse_args()
 
 
-def force_algorithmic_bytes(ctx, n, P, mean_core):
+FP64_VECTOR_PEAK_TFLOPS = 78.6   # 256 CUs x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
+BUILD_FLOPS_PER_CANDIDATE = 11   # per stencil candidate: image-shifted displacement (2 per
+                                 # axis) and r^2 as one multiply and two FMAs
+PROFILES = os.path.join(ROOT, "profiles")
+KERNEL_SOURCES = ("paper_2105_04884_amd/csrc/device.h", "paper_2105_04884_amd/csrc/kernels.h",
+                  "paper_2105_04884_amd/csrc/rbl.hip")
+
+
+def force_algorithmic_bytes(n, P, mean_core):
     """Algorithmic HBM bytes of one pre-drawn RBL force launch: per particle
     the own position (double4, 32 B), core row length (4 B) and entries
     (4 B each), shell length (4 B), P batch entries (4 B each) and the force
     written (3 x 8 B).  Neighbour positions are gathered from cache."""
     return n * (32 + 4 + 4 * mean_core + 4 + 4 * P + 24)
+
+
+def full_force_algorithmic_bytes(n, mean_full):
+    """Same for the full-list force: own position, row length and entries,
+    force written."""
+    return n * (32 + 4 + 4 * mean_full + 24)
+
+
+def stencil_candidates(ncell, counts):
+    """Candidate pairs the list build tests: for every cell, its population
+    times the population of its 5 x 5 x 5 periodic stencil (each cell once
+    when an axis has fewer than 5 cells), summed over cells."""
+    nz, ny, nx = int(ncell[2]), int(ncell[1]), int(ncell[0])
+    grid = counts.reshape(nz, ny, nx).astype(np.int64)
+    offs = [sorted({d % m for d in range(-2, 3)}) for m in (nz, ny, nx)]
+    acc = np.zeros_like(grid)
+    for oz in offs[0]:
+        for oy in offs[1]:
+            for ox in offs[2]:
+                acc += np.roll(grid, shift=(oz, oy, ox), axis=(0, 1, 2))
+    return int((grid * acc).sum())
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(key):
+    """HBM bytes per launch of kernel class `key` from the committed rocprofv3
+    counter summary (FETCH_SIZE and WRITE_SIZE runs, each scaled by the
+    factor a plain copy of known size gives), or None when that summary is
+    missing or was taken from other kernel sources."""
+    path = os.path.join(PROFILES, "hbm_traffic_n1m.txt")
+    if not os.path.exists(path):
+        return None
+    src_hash, found = None, None
+    with open(path) as f:
+        for line in f:
+            parts = line.split()
+            if len(parts) >= 2 and parts[0] == "source_sha256":
+                src_hash = parts[1]
+            if len(parts) >= 4 and parts[0] == "traffic" and parts[1] == key:
+                found = float(parts[3])
+    if src_hash != kernel_source_hash():
+        return None
+    return found
+
+
+def copy_bandwidth(torch, mib):
+    """Attainable HBM bandwidth of a plain device-to-device copy of `mib`
+    MiB (read + write bytes over the event-timed duration, best of 5)."""
+    if mib <= 0:
+        return None
+    src = torch.empty(mib * 2**20 // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    best = None
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    del src, dst
+    gbs = 2 * mib * 2**20 / (best * 1e-3) / 1e9
+    log(f"[bench] device copy of {mib} MiB: {gbs:.0f} GB/s (read + write)")
+    return gbs
+
+
+def build_roofline(res):
+    """Fused list build + batch draw: bound by FP64 vector arithmetic (the
+    stencil candidate tests), priced at the FP64 vector peak."""
+    km = res["kernels_ms"]["build"]
+    avg_s = km["avg_us"] * 1e-6
+    flops = res["build_candidates"] * BUILD_FLOPS_PER_CANDIDATE
+    ach = flops / avg_s / 1e12 if avg_s > 0 else None
+    return {
+        "kernel": "k_build_draw (cell-stencil core list + shell count + batch draw for 10 steps)",
+        "bound": "alu",
+        "achieved": ach,
+        "peak": FP64_VECTOR_PEAK_TFLOPS,
+        "unit": "TFLOP/s",
+        "frac": ach / FP64_VECTOR_PEAK_TFLOPS if ach else None,
+        "traffic": recorded_traffic("build"),
+        "flops_per_launch": flops,
+        "candidates_per_launch": res["build_candidates"],
+        "avg_launch_us": km["avg_us"],
+    }
+
+
+def force_roofline(res, fk):
+    km = res["kernels_ms"][fk]
+    avg_s = km["avg_us"] * 1e-6
+    if res["full"]:
+        nbytes = full_force_algorithmic_bytes(N, res["mean_row"]["full"])
+        name = "k_forces (full list)"
+    else:
+        nbytes = force_algorithmic_bytes(N, res["P"], res["mean_row"]["core"])
+        name = "k_forces (RBL, pre-drawn batches)"
+    ach = nbytes / avg_s / 1e9 if avg_s > 0 else None
+    key = f"force_{'full' if res['full'] else 'rbl'}_{res['precision']}_p{res['P']}"
+    return {
+        "kernel": f"{name}, {res['precision']}",
+        "bound": "hbm",
+        "achieved": ach,
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": ach / HBM_PEAK_GBS if ach else None,
+        "traffic": recorded_traffic(key),
+        "bytes_per_launch": nbytes,
+        "avg_launch_us": km["avg_us"],
+    }
 
 
 def run_variant(name, x0, v0, box, precision, P, use_full, steps, warmup, torch):
@@ -94,6 +226,8 @@ def run_variant(name, x0, v0, box, precision, P, use_full, steps, warmup, torch)
     info = ctx.info()
     tuning = ctx.tuning()
     counts = ctx.row_counts()
+    ncell, _, cell_counts = ctx.export_binning(with_counts=True)
+    candidates = stencil_candidates(ncell[0], cell_counts)
     ctx.close()
     mean = {"core": float(counts[0].mean()), "shell": float(counts[1].mean()),
             "full": float(counts[2].mean())}
@@ -107,6 +241,7 @@ def run_variant(name, x0, v0, box, precision, P, use_full, steps, warmup, torch)
         "mean_row": mean,
         "caps": info,
         "tuning": tuning,
+        "build_candidates": candidates,
     }
     log(f"[bench] {name}: {res['ms_per_step']:.4f} ms/step, {res['atom_steps_per_s']:.3e} atom-steps/s")
     return res
@@ -159,8 +294,103 @@ def cpu_baseline(st, rows_n):
     }
 
 
+def _read_csv(folder, suffix):
+    import csv
+    import glob
+    paths = sorted(glob.glob(os.path.join(folder, "**", "*" + suffix), recursive=True))
+    if not paths:
+        raise SystemExit(f"no *{suffix} under {folder}")
+    with open(paths[0]) as f:
+        return list(csv.DictReader(f))
+
+
+def kernel_class(name, P):
+    """Kernel class key of a kernel instantiation name (see KERNEL_SOURCES)."""
+    if "k_build_draw<" in name:
+        return "build"
+    for tmpl in ("k_forces_lpp<", "k_forces<"):
+        if tmpl in name:
+            args = name.split(tmpl, 1)[1].split(">", 1)[0].split(",")
+            prec = "mixed" if args[0].strip() == "1" else "fp64"
+            kind = {"0": "full", "1": "rbl_inline", "2": "rbl"}[args[1].strip()]
+            return f"force_{kind}_{prec}_p{P}"
+    return None
+
+
+def summarize(trace_dir, fetch_dir, write_dir, command, calib_mib, P=10):
+    """Writes profiles/kernel_trace_n1m.txt (per-kernel launch statistics)
+    and profiles/hbm_traffic_n1m.txt (HBM bytes per launch of each kernel
+    class: FETCH_SIZE and WRITE_SIZE averaged over its dispatches, each
+    scaled by expected / measured for the plain copy of calib_mib MiB)."""
+    os.makedirs(PROFILES, exist_ok=True)
+    stats = _read_csv(trace_dir, "kernel_stats.csv")
+    stats.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    lines = ["# rocprofv3 kernel trace, N = 1,000,000 LJ fluid (density 0.8442), RBL mixed P = 10",
+             "# and full list FP64 variants of bench.py",
+             f"# command: rocprofv3 --kernel-trace --stats -d <dir> -o bench --output-format csv "
+             f"-- python3 bench.py {command}",
+             "# columns: calls, total ms, average us, min us, max us, share %, kernel", ""]
+    for r in stats:
+        lines.append(f"{int(r['Calls']):7d} {float(r['TotalDurationNs']) / 1e6:10.3f} "
+                     f"{float(r['AverageNs']) / 1e3:10.2f} {float(r['MinNs']) / 1e3:10.2f} "
+                     f"{float(r['MaxNs']) / 1e3:10.2f} {float(r['Percentage']):6.2f}  {r['Name']}")
+    with open(os.path.join(PROFILES, "kernel_trace_n1m.txt"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+    expected_kib = calib_mib * 1024.0
+    per = {}
+    factors = {}
+    for tag, folder in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        rows = _read_csv(folder, "counter_collection.csv")
+        copies = [float(r["Counter_Value"]) for r in rows
+                  if "copyBuffer" in r["Kernel_Name"] and r["Counter_Name"] == tag
+                  and float(r["Counter_Value"]) >= 0.25 * expected_kib]
+        if not copies:
+            raise SystemExit(f"{tag}: no dispatch of the {calib_mib} MiB calibration copy found")
+        factors[tag] = expected_kib / float(np.median(copies))
+        agg = {}
+        for r in rows:
+            if r["Counter_Name"] != tag:
+                continue
+            agg.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        for name, vals in agg.items():
+            per.setdefault(name, {})[tag] = (len(vals), float(np.mean(vals)))
+    lines = ["# HBM traffic per kernel launch from two rocprofv3 counter runs of bench.py,",
+             "# N = 1,000,000 LJ fluid (density 0.8442)",
+             f"# command 1: rocprofv3 --pmc FETCH_SIZE -d <dir> -o bench --output-format csv "
+             f"-- python3 bench.py {command}",
+             f"# command 2: rocprofv3 --pmc WRITE_SIZE -d <dir> -o bench --output-format csv "
+             f"-- python3 bench.py {command}",
+             f"# calibration: a plain {calib_mib} MiB device copy (expected {expected_kib:.0f} KiB "
+             f"read and written) reads FETCH_SIZE x{factors['FETCH_SIZE']:.4f} and "
+             f"WRITE_SIZE x{factors['WRITE_SIZE']:.4f} of that",
+             f"calibration fetch_factor {factors['FETCH_SIZE']:.6f} write_factor {factors['WRITE_SIZE']:.6f}",
+             f"source_sha256 {kernel_source_hash()}",
+             "# per kernel: dispatches, mean FETCH_SIZE KiB, mean WRITE_SIZE KiB (raw), name", ""]
+    classes = {}
+    for name, d in sorted(per.items(), key=lambda kv: -kv[1].get("FETCH_SIZE", (0, 0))[1]):
+        nf, fk = d.get("FETCH_SIZE", (0, 0.0))
+        nw, wk = d.get("WRITE_SIZE", (0, 0.0))
+        lines.append(f"kernel {nf:6d} {fk:14.1f} {wk:14.1f}  {name}")
+        cls = kernel_class(name, P)
+        if cls and (cls not in classes or nf > classes[cls][0]):
+            scaled = (fk * factors["FETCH_SIZE"] + wk * factors["WRITE_SIZE"]) * 1024.0
+            classes[cls] = (nf, scaled, name)
+    lines.append("")
+    lines.append("# scaled HBM bytes per launch of each kernel class (the instantiation with")
+    lines.append("# the most dispatches): traffic <class> bytes_per_launch <bytes> <name>")
+    for cls, (nf, scaled, name) in sorted(classes.items()):
+        lines.append(f"traffic {cls} bytes_per_launch {scaled:.0f}  {name}")
+    with open(os.path.join(PROFILES, "hbm_traffic_n1m.txt"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def main():
     args = parse()
+    if args.summarize:
+        summarize(*args.summarize, args.profile_command, args.calib_copy_mb)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only (this build has no multi-GPU path); "
               "run with --gpus 1", file=sys.stderr)
@@ -171,15 +401,7 @@ def main():
     import torch
     from paper_2105_04884_amd import inputs
 
-    if args.calib_copy_mb > 0:
-        src = torch.empty(args.calib_copy_mb * 2**20 // 8, dtype=torch.float64, device="cuda").fill_(1.0)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        log(f"[bench] calibration copy: {args.calib_copy_mb} MiB read + {args.calib_copy_mb} MiB written, 3 launches")
-        del src, dst
+    copy_gbs = copy_bandwidth(torch, args.calib_copy_mb)
     log("[bench] generating the N=1M fluid")
     st = inputs.million_fluid(seed=1)
     x0 = torch.from_numpy(st.pos).cuda()
@@ -206,24 +428,21 @@ def main():
     rows = np.random.default_rng(0).choice(N, size=2000, replace=False)
     errs = force_error_vs_oracle(x0, st.box, torch, rows)
 
-    # roofline of the dominant kernel of the headline variant
+    # roofline of the dominant kernel of the headline variant (largest
+    # share of the event-timed pass), and of the force kernel beside it
     km = head["kernels_ms"]
     dom = max(km, key=lambda k: km[k]["total_ms"])
     fk = "force_full" if head["full"] else "force_rbl"
-    f_avg_s = km[fk]["avg_us"] * 1e-6
-    f_bytes = force_algorithmic_bytes(None, N, head["P"], head["mean_row"]["core"])
-    roof = {
-        "kernel": "k_forces (RBL, pre-drawn batches, mixed)",
-        "bound": "hbm",
-        "achieved": f_bytes / f_avg_s / 1e9 if f_avg_s > 0 else None,
-        "peak": HBM_PEAK_GBS,
-        "unit": "GB/s",
-        "frac": (f_bytes / f_avg_s / 1e9) / HBM_PEAK_GBS if f_avg_s > 0 else None,
-        "traffic": None,
-        "bytes_per_launch": f_bytes,
-        "avg_launch_us": km[fk]["avg_us"],
-        "dominant_kernel_class": dom,
-    }
+    force_roof = force_roofline(head, fk)
+    if dom == "build":
+        roof = build_roofline(head)
+        roof["secondary"] = force_roof
+    else:
+        roof = force_roof
+        roof["secondary"] = build_roofline(head)
+    roof["dominant_kernel_class"] = dom
+    roof["share_of_step"] = km[dom]["total_ms"] / sum(k["total_ms"] for k in km.values())
+    roof["hbm_copy_GBs"] = copy_gbs
 
     cpu = None
     if not args.no_cpu_baseline:

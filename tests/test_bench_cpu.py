@@ -1,0 +1,61 @@
+"""Host-side helpers of bench.py: the stencil candidate count that prices the
+list build, kernel-class names of profiler rows, and the one-GPU guard."""
+import itertools
+import os
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def _brute_candidates(nc, counts):
+    nx, ny, nz = nc
+    grid = counts.reshape(nz, ny, nx)
+    total = 0
+    for z, y, x in itertools.product(range(nz), range(ny), range(nx)):
+        cells = {((z + dz) % nz, (y + dy) % ny, (x + dx) % nx)
+                 for dz in range(-2, 3) for dy in range(-2, 3) for dx in range(-2, 3)}
+        total += int(grid[z, y, x]) * sum(int(grid[c]) for c in cells)
+    return total
+
+
+@pytest.mark.parametrize("nc", [(7, 7, 7), (6, 8, 9), (3, 5, 7), (1, 2, 4)])
+def test_stencil_candidates_brute_force(nc):
+    rng = np.random.default_rng(sum(nc))
+    counts = rng.integers(0, 9, size=int(np.prod(nc))).astype(np.int32)
+    assert bench.stencil_candidates(np.array(nc), counts) == _brute_candidates(nc, counts)
+
+
+def test_kernel_class_names():
+    assert bench.kernel_class("void rbl::k_build_draw<12, true>(rbl::FusedArgs)", 10) == "build"
+    assert bench.kernel_class("void rbl::k_forces_lpp<1, 2, false, false, 2>(rbl::ForceArgs)",
+                              10) == "force_rbl_mixed_p10"
+    assert bench.kernel_class("void rbl::k_forces_lpp<0, 0, false, false, 4>(rbl::ForceArgs)",
+                              10) == "force_full_fp64_p10"
+    assert bench.kernel_class("void rbl::k_forces<0, 1, false, false, 16>(rbl::ForceArgs)",
+                              5) == "force_rbl_inline_fp64_p5"
+    assert bench.kernel_class("rbl::k_integrate<1>(rbl::IntArgs)", 10) is None
+
+
+def test_recorded_traffic_needs_matching_sources(tmp_path, monkeypatch):
+    monkeypatch.setattr(bench, "PROFILES", str(tmp_path))
+    (tmp_path / "hbm_traffic_n1m.txt").write_text(
+        f"source_sha256 {bench.kernel_source_hash()}\n"
+        "traffic build bytes_per_launch 123456  k_build_draw<12, true>\n")
+    assert bench.recorded_traffic("build") == 123456.0
+    assert bench.recorded_traffic("force_rbl_mixed_p10") is None
+    (tmp_path / "hbm_traffic_n1m.txt").write_text(
+        "source_sha256 0000\ntraffic build bytes_per_launch 123456  k\n")
+    assert bench.recorded_traffic("build") is None
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=60)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
