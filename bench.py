@@ -476,7 +476,7 @@ def main():
                                             if s["launches"]},
                          "kernels_total_ms": {q: round(s["total_ms"], 3) for q, s in r["kernels_ms"].items()
                                               if s["launches"]},
-                         "mean_row": r["mean_row"], "tuning": r["tuning"]}
+                         "mean_row": r["mean_row"], "tuning": r["tuning"], "caps": r["caps"]}
                      for k, r in results.items()},
         "speedup_rbl_mixed_vs_full_fp64": (speed("rbl_mixed_p10") / speed("full_fp64")
                                            if speed("rbl_mixed_p10") and speed("full_fp64") else None),

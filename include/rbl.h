@@ -5,10 +5,10 @@
  * short-range molecular dynamics simulations" (arXiv:2105.04884).
  *
  * Radius names (the paper swaps them):
- *   r_s = core radius: pairs closer than r_s are summed exactly, eq. (coreF);
+ *   r_s = core radius: pairs closer than r_s are summed exactly, eq. (3);
  *   r_c = outer cut-off: pairs with r_s <= r < r_c form the shell zone, from
  *         which each particle draws a batch of P partners whose summed force
- *         is scaled by n_i/P, eq. (shellF).
+ *         is scaled by n_i/P, eq. (4).
  *
  * Conventions for every call:
  *  - Return value: RBL_OK (0), a warning (> 0) or an error (< 0).  No C++
@@ -125,7 +125,7 @@ rbl_status rbl_build(rbl_ctx* ctx, const double* pos, const double* box,
 
 /*
  * RBL force at positions `pos` (device, SoA FP64, usually close to the
- * positions of the last build), eq. (coreF) + eq. (shellF):
+ * positions of the last build), eq. (3) + eq. (4):
  *   F_i = sum_{j in core, r < r_s} f_ij
  *       + (n_i/P) sum_{j in B_i, r_s <= r < r_c} f_ij
  * where B_i is P shell candidates drawn without replacement (Floyd's

@@ -15,8 +15,8 @@
  *
  * Radius names: the paper calls the core radius r_c and the outer cut-off
  * r_s.  This file uses the names of the public interface instead:
- *   rs = core radius (direct sum, eq. (coreF)),
- *   rc = outer cut-off (end of the shell zone, eq. (shellF)).
+ *   rs = core radius (direct sum, eq. (3)),
+ *   rc = outer cut-off (end of the shell zone, eq. (4)).
  *
  * What each function follows:
  *   orc_philox4x32_10   Philox4x32-10 of Salmon, Moraes, Dror & Shaw (SC'11);
@@ -25,12 +25,12 @@
  *   orc_floyd_choices   Floyd's sampling without replacement (Bentley &
  *                       Floyd, CACM 1987): the batch B(i) of Sec. II, with the
  *                       without-replacement moments of Appendix A.
- *   orc_lj              LJ 12-6 pair potential eq. (12-6), truncated at the
+ *   orc_lj              LJ 12-6 pair potential eq. (1), truncated at the
  *                       cut-off and shifted to zero there (Sec. II).
  *   orc_build_*         cell list and core/shell neighbour lists (Sec. II,
  *                       Fig. 1); brute force is the plain definition.
- *   orc_forces_rbl      F_i = F_ic + (n/p) sum_{B(i)} f~_ij, eq. (coreF) and
- *                       eq. (shellF); small shells (n <= p) taken whole.
+ *   orc_forces_rbl      F_i = F_ic + (n/p) sum_{B(i)} f~_ij, eq. (3) and
+ *                       eq. (4); small shells (n <= p) taken whole.
  *   orc_mean_subtract   subtraction of the average net force (Sec. II,
  *                       Algorithm 1, F_cor of Appendix A).
  *   orc_md_run          Algorithm 1 with velocity Verlet (NVE).
@@ -135,7 +135,7 @@ int orc_batch_positions(uint64_t seed, uint32_t pid, uint64_t step, uint32_t rep
 }
 
 /* ------------------------------------------------------------------------ */
-/* Pair term, eq. (12-6) with epsilon = sigma = 1:
+/* Pair term, eq. (1) with epsilon = sigma = 1:
  *   U(r) = 4 (r^-12 - r^-6),
  *   f_ij = -dU/dr * (x_i - x_j)/r = 24 r^-8 (2 r^-6 - 1) (x_i - x_j).
  * fmag is the factor multiplying (x_i - x_j); u is the unshifted energy. */
@@ -456,7 +456,7 @@ int orc_forces_rbl(int64_t n, const double* pos, const double box[3],
     for (int64_t k = 0; k < nrows; ++k) {
         int64_t i = rows ? rows[k] : k;
         double d[3], fm, u;
-        /* core: exact sum over r < rs, eq. (coreF) */
+        /* core: exact sum over r < rs, eq. (3) */
         double Fc[3] = {0, 0, 0}, ec = 0.0, wc = 0.0;
         for (int64_t q = core_off[k]; q < core_off[k + 1]; ++q) {
             int64_t j = core_idx[q];
@@ -468,7 +468,7 @@ int orc_forces_rbl(int64_t n, const double* pos, const double box[3],
                 wc += fm * r2;
             }
         }
-        /* shell: batch of p candidates, scaled by n_i/p, eq. (shellF); only
+        /* shell: batch of p candidates, scaled by n_i/p, eq. (4); only
          * candidates whose current distance lies in [rs, rc) contribute. */
         int ns = (int)(shell_off[k + 1] - shell_off[k]);
         uint32_t id_for_rng = (uint32_t)(pid ? pid[k] : i);

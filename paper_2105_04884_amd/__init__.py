@@ -7,7 +7,7 @@ device memory (``tensor.data_ptr()``) and the HIP stream.
 
     ctx = Context(n, lists=("core", "shell"))
     ctx.build(pos, box, r_s=1.5, r_c=3.5)          # pos: cuda float64 (3, n)
-    f = ctx.forces(P=10, seed=1, step=0, pos=pos)   # RBL force, eq. (coreF)+(shellF)
+    f = ctx.forces(P=10, seed=1, step=0, pos=pos)   # RBL force, eqs. (3)+(4)
     ctx.step(pos, vel, nsteps=100, dt=0.005, P=10, seed=1)
 """
 from __future__ import annotations

@@ -119,7 +119,7 @@ __device__ __forceinline__ Delta delta(const double4& a, const double4& b, const
 }
 
 // ---------------------------------------------------------------------------
-// LJ 12-6 pair term, eq. (12-6), epsilon = sigma = 1.  fmag multiplies
+// LJ 12-6 pair term, eq. (1), epsilon = sigma = 1.  fmag multiplies
 // (x_i - x_j); u is unshifted.
 enum { kFP64 = 0, kMixed = 1 };
 

@@ -1,7 +1,7 @@
 """Pins of the CPU oracle against what the paper and the mathematics fix.
 
 Every check here is independent of the oracle's own formulas: closed forms
-of eq. (12-6), brute force against the cell-list construction of Sec. II,
+of eq. (1), brute force against the cell-list construction of Sec. II,
 finite differences of the total energy, momentum conservation, the
 unbiasedness and the exact without-replacement variance of Appendix A,
 exhaustive enumeration of Floyd's sampler, rocRAND's Philox, energy
