@@ -39,15 +39,15 @@ __device__ __forceinline__ void philox4x32_10(uint32_t& x0, uint32_t& x1, uint32
 {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t m0 = 0xD2511F53u, m1 = 0xCD9E8D57u;
-        uint32_t hi0 = __umulhi(m0, x0), lo0 = m0 * x0;
-        uint32_t hi1 = __umulhi(m1, x2), lo1 = m1 * x2;
-        uint32_t y0 = hi1 ^ x1 ^ k0;
-        uint32_t y2 = hi0 ^ x3 ^ k1;
+        // one 32 x 32 -> 64-bit product per multiplier gives both halves
+        const uint64_t p0 = (uint64_t)0xD2511F53u * x0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * x2;
+        const uint32_t y0 = (uint32_t)(p1 >> 32) ^ x1 ^ k0;
+        const uint32_t y2 = (uint32_t)(p0 >> 32) ^ x3 ^ k1;
         x0 = y0;
-        x1 = lo1;
+        x1 = (uint32_t)p1;
         x2 = y2;
-        x3 = lo0;
+        x3 = (uint32_t)p0;
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
     }
@@ -58,7 +58,10 @@ __device__ __forceinline__ void philox4x32_10(uint32_t& x0, uint32_t& x1, uint32
 // Random words: Philox block b = m/4 at counter (pid, step, replica, b),
 // word m % 4; choice t = floor(u (J+1) / 2^32) with J = n - P + m.
 // Insertion into the sorted array uses only static indices, so S stays in
-// VGPRs: new S[q] = min(S[q], max(S[q-1], v)).
+// VGPRs: new S[q] = min(S[q], max(S[q-1], v)).  Up to PMAX = 32 the loop
+// over m is unrolled, so that step m compares and inserts against the m
+// filled entries only (the unfilled ones hold 0xFFFFFFFF, which no choice
+// equals and which the insertion leaves in place).
 template <int PMAX>
 __device__ __forceinline__ void floyd_draw(uint32_t (&S)[PMAX], uint64_t seed, uint32_t pid,
                                            uint32_t step, uint32_t replica, int P, int n)
@@ -66,26 +69,51 @@ __device__ __forceinline__ void floyd_draw(uint32_t (&S)[PMAX], uint64_t seed, u
 #pragma unroll
     for (int q = 0; q < PMAX; ++q) S[q] = 0xFFFFFFFFu;
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
-    uint32_t w0 = 0, w1 = 0, w2 = 0, w3 = 0;
-    for (int m = 0; m < P; ++m) {
-        const int sub = m & 3;
-        if (sub == 0) {
-            w0 = pid;
-            w1 = step;
-            w2 = replica;
-            w3 = (uint32_t)(m >> 2);
-            philox4x32_10(w0, w1, w2, w3, k0, k1);
+    if constexpr (PMAX <= 32) {
+        uint32_t w[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (int m = 0; m < PMAX; ++m) {
+            if (m >= P) continue;  // P is uniform across the wavefront
+            if ((m & 3) == 0) {
+                w[0] = pid;
+                w[1] = step;
+                w[2] = replica;
+                w[3] = (uint32_t)(m >> 2);
+                philox4x32_10(w[0], w[1], w[2], w[3], k0, k1);
+            }
+            const uint32_t u = w[m & 3];
+            const uint32_t J = (uint32_t)(n - P + m);
+            const uint32_t t = (uint32_t)(((uint64_t)u * (uint64_t)(J + 1u)) >> 32);
+            bool taken = false;
+#pragma unroll
+            for (int q = 0; q < m; ++q) taken |= (S[q] == t);
+            const uint32_t v = taken ? J : t;
+#pragma unroll
+            for (int q = m; q > 0; --q) S[q] = min(S[q], max(S[q - 1], v));
+            S[0] = min(S[0], v);
         }
-        const uint32_t u = sub == 0 ? w0 : sub == 1 ? w1 : sub == 2 ? w2 : w3;
-        const uint32_t J = (uint32_t)(n - P + m);
-        const uint32_t t = __umulhi(u, J + 1u);
-        bool taken = false;
+    } else {
+        uint32_t w0 = 0, w1 = 0, w2 = 0, w3 = 0;
+        for (int m = 0; m < P; ++m) {
+            const int sub = m & 3;
+            if (sub == 0) {
+                w0 = pid;
+                w1 = step;
+                w2 = replica;
+                w3 = (uint32_t)(m >> 2);
+                philox4x32_10(w0, w1, w2, w3, k0, k1);
+            }
+            const uint32_t u = sub == 0 ? w0 : sub == 1 ? w1 : sub == 2 ? w2 : w3;
+            const uint32_t J = (uint32_t)(n - P + m);
+            const uint32_t t = __umulhi(u, J + 1u);
+            bool taken = false;
 #pragma unroll
-        for (int q = 0; q < PMAX; ++q) taken |= (S[q] == t);
-        const uint32_t v = taken ? J : t;
+            for (int q = 0; q < PMAX; ++q) taken |= (S[q] == t);
+            const uint32_t v = taken ? J : t;
 #pragma unroll
-        for (int q = PMAX - 1; q > 0; --q) S[q] = min(S[q], max(S[q - 1], v));
-        S[0] = min(S[0], v);
+            for (int q = PMAX - 1; q > 0; --q) S[q] = min(S[q], max(S[q - 1], v));
+            S[0] = min(S[0], v);
+        }
     }
 }
 

@@ -18,7 +18,7 @@ enum { kSrcCaller = 0, kSrcSorted = 1 };
 enum { kShellNone = 0, kShellInline = 1, kShellPredraw = 2 };
 enum { kIntFirst = 0, kIntMid = 1, kIntLast = 2 };
 enum { kFlagOverflow = 0, kFlagMaxCore = 1, kFlagMaxShell = 2, kFlagMaxFull = 3,
-       kFlagNonfinite = 4, kFlagSkin = 5, kFlagBadSlot = 6, kNumFlags = 8 };
+       kFlagNonfinite = 4, kFlagSkin = 5, kFlagBadSlot = 6, kFlagStencil = 7, kNumFlags = 8 };
 
 // Block -> work-tile map that gives XCD x (blocks x, x+8, ...) a contiguous
 // range of tiles.
@@ -547,13 +547,12 @@ __global__ __launch_bounds__(256) void k_build(BuildArgs a)
 // ---------------------------------------------------------------------------
 // Batches in HBM: batch[(rr * n_slots + slot) * P + m] is the m-th partner
 // (slot) of the particle in `slot` for the rr-th force evaluation after the
-// build; a particle's P partners are contiguous.
+// build; a particle's P partners are contiguous, and so are the batches of
+// the particles of one cell.
 __device__ __forceinline__ int64_t batch_index(int rr, int64_t slot, int m, int64_t n_slots, int P)
 {
     return ((int64_t)rr * n_slots + slot) * P + m;
 }
-
-constexpr int kMaskBudget = 512;  // 64-bit masks per wavefront
 
 struct FusedArgs {
     BuildArgs b;
@@ -564,6 +563,7 @@ struct FusedArgs {
     const uint64_t* step_dev;  // if set, the draw's first step is *step_dev + step0
     int K;
     int P;
+    int cap_list;              // LDS shell-list room per centre particle (<= 0: all candidates)
 };
 
 __device__ __forceinline__ void wave_lds_fence()
@@ -573,43 +573,32 @@ __device__ __forceinline__ void wave_lds_fence()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Position of the r-th set bit (0-based) of w; w has more than r set bits.
-__device__ __forceinline__ int select_bit(uint64_t w, int r)
-{
-    int pos = 0;
-#pragma unroll
-    for (int s = 32; s >= 1; s >>= 1) {
-        const uint64_t low = w & ((1ull << s) - 1ull);
-        const int c = __popcll(low);
-        if (r >= c) {
-            r -= c;
-            w >>= s;
-            pos += s;
-        }
-    }
-    return pos;
-}
-
 // ---------------------------------------------------------------------------
 // Fused list build + batch draw (the molecular-dynamics loop path).  As in
 // k_build, one wavefront per centre cell walks the 5x5x5 stencil, but only
-// the core rows go to HBM: shell membership stays in LDS as one 64-bit ballot
-// mask per (centre particle, candidate chunk).  Its popcount is n_i, and the
-// batches of the next K force evaluations are drawn right away (one lane per
-// (particle, step) pair), the k-th shell partner being found by walking the
-// masks.  Bit-identical to k_build + k_predraw, without writing or re-reading
-// the shell rows.  Inner-loop details:
+// the core rows go to HBM.  Each centre particle's shell candidates are
+// appended, in stencil order, to a list of 16-bit (run, offset-in-run)
+// entries in LDS; its length is n_i, and the batches of the next K force
+// evaluations are drawn right away, one lane per (particle, step) pair, the
+// k-th shell candidate being one LDS read away.  Bit-identical to k_build +
+// k_predraw, without writing or re-reading the shell rows.  Details:
+//  - the stencil's cells merge into x-runs of contiguous slots (at most 50);
+//    run starts, prefix counts and image shifts sit in LDS, and every lane
+//    walks the runs forward as its candidate index grows by 64 per chunk;
 //  - the periodic image of every candidate run is known from the stencil
 //    geometry when every axis has >= 7 cells, so dx = (x_i - x_j) + s with
-//    s in {-L, 0, L} exactly equals the canonical fma(-rint(d/L), L, d);
-//    smaller grids use the canonical formula per pair;
-//  - the core/shell ballot masks of centre particle ii go to lane ii of four
-//    VGPRs, written to LDS once per chunk;
-//  - core rows are scattered once per chunk by the centre-particle lanes,
-//    each walking its own mask bits (the partner slot comes from the owning
-//    lane via ds_bpermute);
-//  - the next chunk's candidates are fetched before the current chunk is
-//    tested;
+//    s in {-L, 0, L} exactly equals the canonical fma(-rint(d/L), L, d)
+//    (the SHIFT variant); smaller grids use the canonical formula per pair;
+//  - every cell-level quantity is made wave-uniform with readfirstlane, so
+//    it lives in SGPRs;
+//  - per centre particle and chunk, the core ballot goes to lane ii of two
+//    VGPRs with v_writelane and the core rows are scattered once per chunk
+//    by the centre-particle lanes (coalesced ELL writes); the shell ballot
+//    is compacted into the particle's LDS list with mbcnt;
+//  - a centre particle's list has room for every stencil candidate, so the
+//    centre particles go in groups of kListBudget / (candidates) at most;
+//    a stencil beyond kListBudget candidates (or a run beyond 1023) raises
+//    kFlagStencil and the host redoes the run on explicit lists;
 //  - centre cells are mapped to blocks so that each XCD works on a
 //    contiguous range of cells (its L2 keeps the neighbourhood).
 struct AxisRunsS {
@@ -643,20 +632,6 @@ __device__ __forceinline__ int axis_shift(const AxisRunsS& a, int k)
     return k < a.l0 ? a.s0 : a.s1;
 }
 
-// ---------------------------------------------------------------------------
-// Implementation notes of k_build_draw:
-//  - every cell-level quantity (cell range, replica geometry) is made
-//    wave-uniform with readfirstlane, so it lives in SGPRs;
-//  - SHIFT (all axes >= 7 cells) and canonical-formula variants are
-//    separate kernels, so the inner loop has no branch;
-//  - a byte table maps each flat stencil candidate to its run, so a
-//    candidate (and a drawn partner) is resolved with one LDS read instead
-//    of a binary search (stencils of up to kCandBudget candidates; larger
-//    ones use the search);
-//  - per centre particle and chunk, the core and shell ballots are written
-//    into lane ii of four VGPRs with v_writelane.
-constexpr int kCandBudget = 2048;
-
 __device__ __forceinline__ int rfl(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 __device__ __forceinline__ double rfl(double v)
@@ -677,27 +652,29 @@ __device__ __forceinline__ int64_t rfl(int64_t v)
 // places the lane select (in M0 when the data operand is an SGPR).
 extern "C" __device__ int rbl_writelane(int value, int lane, int old) __asm("llvm.amdgcn.writelane");
 
-// Lane `lane` of v0..v3 takes the wave-uniform values s0..s3.
-__device__ __forceinline__ void write_lane4(uint32_t& v0, uint32_t& v1, uint32_t& v2, uint32_t& v3,
-                                            uint32_t s0, uint32_t s1, uint32_t s2, uint32_t s3, int lane)
+// Lane `lane` of v0, v1 takes the wave-uniform values s0, s1.
+__device__ __forceinline__ void write_lane2(uint32_t& v0, uint32_t& v1, uint32_t s0, uint32_t s1, int lane)
 {
     v0 = (uint32_t)rbl_writelane((int)s0, lane, (int)v0);
     v1 = (uint32_t)rbl_writelane((int)s1, lane, (int)v1);
-    v2 = (uint32_t)rbl_writelane((int)s2, lane, (int)v2);
-    v3 = (uint32_t)rbl_writelane((int)s3, lane, (int)v3);
 }
+
+// s_waitcnt immediate with vmcnt = 0 and the expcnt / lgkmcnt fields at
+// their maximum (no wait on them)
+constexpr int kWaitVmcnt0 = 0x0F70;
+constexpr int kCtrMax = 16;        // centre particles per group
+constexpr int kListBudget = 3072;  // 16-bit shell-list entries per wavefront
+constexpr int kRunOffBits = 10;    // list entry = run << 10 | offset in the run
 
 template <int PMAX, bool SHIFT>
 __global__ __launch_bounds__(256) void k_build_draw(FusedArgs fa)
 {
-    __shared__ double4 s_ctr[4][64];
-    __shared__ uint64_t s_smask[4][kMaskBudget / 2];    // shell mask per (ii, chunk)
-    __shared__ int s_cum[4][kMaskBudget / 2];           // shell-rank prefix per (ii, chunk)
+    __shared__ double4 s_ctr[4][kCtrMax];
     __shared__ int s_rstart[4][64];
     __shared__ int s_rpre[4][64];
     __shared__ int s_rshift[4][64];
-    __shared__ int s_ncnt[4][64];
-    __shared__ unsigned char s_runf[4][kCandBudget];    // run of each flat candidate
+    __shared__ int s_ncnt[4][kCtrMax];
+    __shared__ unsigned short s_list[4][kListBudget];
     const BuildArgs& a = fa.b;
     const int lane = threadIdx.x & 63;
     const int w = rfl((int)(threadIdx.x >> 6));
@@ -757,84 +734,111 @@ __global__ __launch_bounds__(256) void k_build_draw(FusedArgs fa)
     s_rstart[w][lane] = rstart;
     s_rpre[w][lane] = rpre;
     s_rshift[w][lane] = rshift;
-    const int nch = (total + 63) >> 6;
-    if (nch > kMaskBudget / 2) {
-        if (lane == 0) atomicOr(&a.flags[kFlagBadSlot], 16);
+    if (total > kListBudget || wave_max(rlen) >= (1 << kRunOffBits)) {
+        // the host repeats the run on explicit rows; until it does, this
+        // cell's particles have empty rows, so no force kernel of the run
+        // reads a batch entry or core row that was never written
+        for (int t = lane; t < m; t += 64) {
+            a.core_len[i0 + t] = 0;
+            a.shell_len[i0 + t] = 0;
+        }
+        if (lane == 0) {
+            raise_flag(&a.flags[kFlagStencil]);
+            raise_flag(&a.flags[kFlagOverflow]);
+        }
         return;
     }
-    const bool table = total <= kCandBudget;
-    if (table)
-        for (int t = 0; t < rlen; ++t) s_runf[w][rpre + t] = (unsigned char)lane;
-    const int gmax = nch > 0 ? min(64, (kMaskBudget / 2) / nch) : 64;
+    const int nch = (total + 63) >> 6;  // >= 1: the cell itself is in the stencil
+    // list room per centre particle: the host's bound on shell counts (a
+    // particle beyond it raises the overflow flag), never above the stencil
+    const int cap = (fa.cap_list > 0 && fa.cap_list < total) ? fa.cap_list : total;
+    const int gmax = min(kCtrMax, kListBudget / cap);  // >= 1
     const int P = fa.P;
     wave_lds_fence();
 
-    auto run_of = [&](int f) -> int {
-        if (table) return s_runf[w][f];
-        int q = 0;
-#pragma unroll
-        for (int st = 32; st > 0; st >>= 1) q = s_rpre[w][q + st] <= f ? q + st : q;
-        return q;
-    };
-    // candidate f: slot (-1 past the stencil), position, image-shift code
-    auto candidate = [&](int f, int& j, double4& xj, int& code) {
-        const bool in = f < total;
-        const int q = run_of(in ? f : 0);
-        j = s_rstart[w][q] + (f - s_rpre[w][q]);
-        code = s_rshift[w][q];
-        if (in && j >= 0 && (int64_t)j < a.n_slots) {
-            xj = a.xs[j];
-        } else {
-            j = -1;
-            xj = make_double4(1.0e30, 1.0e30, 1.0e30, 0.0);
-            code = 1 | (1 << 2) | (1 << 4);
+    int qrun = 0;  // this lane's current run (its candidate index only grows)
+    // candidate f: slot (-1 past the stencil), position, image-shift code,
+    // list entry
+    auto candidate = [&](int f, int& j, double4& xj, int& code, int& ent) {
+        j = -1;
+        code = 1 | (1 << 2) | (1 << 4);
+        ent = 0;
+        xj = make_double4(1.0e30, 1.0e30, 1.0e30, 0.0);
+        if (f < total) {
+            while (qrun < 63 && s_rpre[w][qrun + 1] <= f) ++qrun;
+            const int off = f - s_rpre[w][qrun];
+            const int jj = s_rstart[w][qrun] + off;
+            if (jj >= 0 && (int64_t)jj < a.n_slots) {
+                j = jj;
+                code = s_rshift[w][qrun];
+                ent = (qrun << kRunOffBits) | off;
+                xj = a.xs[jj];
+            } else {
+                atomicOr(&a.flags[kFlagBadSlot], 64);
+            }
         }
     };
 
     for (int g0 = 0; g0 < m; g0 += gmax) {
-        const int mg = min(gmax, m - g0);
+        const int mg = rfl(min(gmax, m - g0));
         if (lane < mg) s_ctr[w][lane] = a.xs[i0 + g0 + lane];
         wave_lds_fence();
+        qrun = 0;
         int cnt_core = 0;
+        uint32_t nshell = 0;  // lane ii: shell candidates of centre ii so far
         const int my_slot = i0 + g0 + lane;
-        int jn = -1, coden = 0;
-        double4 xn = make_double4(0.0, 0.0, 0.0, 0.0);
-        if (nch > 0) candidate(lane, jn, xn, coden);
+        int jn, coden, entn;
+        double4 xn;
+        candidate(lane, jn, xn, coden, entn);
+        // the first chunk's candidates are complete before the chunk loop:
+        // with nothing of this load pending at the loop head, the inner loop
+        // waits on no vector-memory counter, and each chunk's prefetch of the
+        // next one overlaps with its tests
+        __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
         for (int ch = 0; ch < nch; ++ch) {
             const int jc = jn;
             const double4 xc = xn;
             const int code = coden;
-            if (ch + 1 < nch) candidate((ch + 1) * 64 + lane, jn, xn, coden);
-            double shx = 0.0, shy = 0.0, shz = 0.0;
-            if (SHIFT) {
-                shx = (double)((code & 3) - 1) * L0;
-                shy = (double)(((code >> 2) & 3) - 1) * L1;
-                shz = (double)(((code >> 4) & 3) - 1) * L2;
-            }
-            const uint64_t valid = __ballot(jc >= 0);
-            uint32_t mclo = 0, mchi = 0, mslo = 0, mshi = 0;
-            for (int ii = 0; ii < mg; ++ii) {
-                const double4 xi = s_ctr[w][ii];
-                double dx, dy, dz;
-                if (SHIFT) {
-                    dx = (xi.x - xc.x) + shx;
-                    dy = (xi.y - xc.y) + shy;
-                    dz = (xi.z - xc.z) + shz;
-                } else {
-                    dx = min_image(xi.x - xc.x, L0, iL0);
-                    dy = min_image(xi.y - xc.y, L1, iL1);
-                    dz = min_image(xi.z - xc.z, L2, iL2);
-                }
+            const int ent = entn;
+            if (ch + 1 < nch) candidate((ch + 1) * 64 + lane, jn, xn, coden, entn);
+            uint32_t mclo = 0, mchi = 0;
+            // one centre particle against the chunk: core ballot to lane ii,
+            // shell candidates appended to its LDS list
+            auto test = [&](int ii, double dx, double dy, double dz) {
                 const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-                const uint64_t other = valid & ~__ballot(jc == i0 + g0 + ii);
+                const uint64_t other = ~__ballot(jc == i0 + g0 + ii);
                 const uint64_t mc = other & __ballot(r2 < a.thr_core);
                 const uint64_t ms = other & __ballot(r2 >= a.thr_shell_in) & __ballot(r2 < a.thr_out);
-                write_lane4(mclo, mchi, mslo, mshi, (uint32_t)mc, (uint32_t)(mc >> 32), (uint32_t)ms,
-                            (uint32_t)(ms >> 32), ii);
+                write_lane2(mclo, mchi, (uint32_t)mc, (uint32_t)(mc >> 32), ii);
+                const int base = rfl((int)__builtin_amdgcn_readlane((int)nshell, ii));
+                const int pos = base + (int)mbcnt(ms);
+                if (__builtin_amdgcn_inverse_ballot_w64(ms) && pos < cap)
+                    s_list[w][ii * cap + pos] = (unsigned short)ent;
+                nshell = (uint32_t)rbl_writelane(base + (int)__popcll(ms), ii, (int)nshell);
+            };
+            constexpr int kNoShift = 1 | (1 << 2) | (1 << 4);
+            if (SHIFT && __ballot(code != kNoShift) == 0) {
+                // no periodic image in the chunk: (x_i - x_j) + 0 is x_i - x_j
+                for (int ii = 0; ii < mg; ++ii) {
+                    const double4 xi = s_ctr[w][ii];
+                    test(ii, xi.x - xc.x, xi.y - xc.y, xi.z - xc.z);
+                }
+            } else if (SHIFT) {
+                const double shx = (double)((code & 3) - 1) * L0;
+                const double shy = (double)(((code >> 2) & 3) - 1) * L1;
+                const double shz = (double)(((code >> 4) & 3) - 1) * L2;
+                for (int ii = 0; ii < mg; ++ii) {
+                    const double4 xi = s_ctr[w][ii];
+                    test(ii, (xi.x - xc.x) + shx, (xi.y - xc.y) + shy, (xi.z - xc.z) + shz);
+                }
+            } else {
+                for (int ii = 0; ii < mg; ++ii) {
+                    const double4 xi = s_ctr[w][ii];
+                    test(ii, min_image(xi.x - xc.x, L0, iL0), min_image(xi.y - xc.y, L1, iL1),
+                         min_image(xi.z - xc.z, L2, iL2));
+                }
             }
             uint64_t mcore = ((uint64_t)mchi << 32) | mclo;
-            const uint64_t mshell = ((uint64_t)mshi << 32) | mslo;
-            if (lane < mg) s_smask[w][lane * nch + ch] = mshell;
             if (lane >= mg) mcore = 0;
             while (__ballot(mcore != 0)) {
                 const int b = mcore ? (int)__builtin_ctzll(mcore) : 0;
@@ -846,13 +850,8 @@ __global__ __launch_bounds__(256) void k_build_draw(FusedArgs fa)
                 }
             }
         }
-        wave_lds_fence();
-        int ns = 0;
+        const int ns = lane < mg ? (int)nshell : 0;
         if (lane < mg) {
-            for (int ch = 0; ch < nch; ++ch) {
-                s_cum[w][lane * nch + ch] = ns;
-                ns += __popcll(s_smask[w][lane * nch + ch]);
-            }
             a.core_len[my_slot] = min(cnt_core, a.cap_core);
             a.shell_len[my_slot] = ns;
             s_ncnt[w][lane] = ns;
@@ -863,12 +862,15 @@ __global__ __launch_bounds__(256) void k_build_draw(FusedArgs fa)
         if (lane == 0) {
             raise_max(&a.flags[kFlagMaxCore], mxc);
             raise_max(&a.flags[kFlagMaxShell], mxs);
-            if (mxc > a.cap_core) raise_flag(&a.flags[kFlagOverflow]);
+            if (mxc > a.cap_core || mxs > cap) raise_flag(&a.flags[kFlagOverflow]);
         }
-        // batches: one lane per (particle, step) pair; each drawn rank is
-        // located independently: chunk by the popcount prefix, bit by
-        // select, run by the byte table
+        // batches: one lane per (particle, step) pair; the k-th shell
+        // candidate of centre ii is entry k of its list.  Loop bounds are
+        // wave-uniform; a lane whose shell is small (n <= P) takes positions
+        // 0..n-1, and entries it does not own (never read by the force
+        // kernels) hold the particle itself
         const int pairs = mg * fa.K;
+        const uint64_t s0 = fa.step_dev ? *fa.step_dev + fa.step0 : fa.step0;
         for (int pb = 0; pb < pairs; pb += 64) {
             const int pr = pb + lane;
             if (pr < pairs) {
@@ -876,43 +878,25 @@ __global__ __launch_bounds__(256) void k_build_draw(FusedArgs fa)
                 const int rr = pr - ii * fa.K;
                 const int islot = i0 + g0 + ii;
                 const int n = s_ncnt[w][ii];
-                const uint64_t* mk = &s_smask[w][ii * nch];
-                const int* cum = &s_cum[w][ii * nch];
+                const bool small = n <= P;
+                const unsigned short* lst = &s_list[w][ii * cap];
                 int* out = fa.batch + batch_index(rr, islot, 0, a.n_slots, P);
                 uint32_t S[PMAX];
-                if (n <= P) {
-#pragma unroll
-                    for (int qq = 0; qq < PMAX; ++qq) S[qq] = (uint32_t)qq;
-                } else {
-                    const uint32_t pid = (uint32_t)(fa.perm[islot] - id_base);
-                    const uint64_t s0 = fa.step_dev ? *fa.step_dev + fa.step0 : fa.step0;
-                    floyd_draw<PMAX>(S, fa.seed, pid, (uint32_t)(s0 + rr), (uint32_t)rep_id, P, n);
-                }
-                const int cnt = n < P ? n : P;
-                int jv[PMAX];
-#pragma unroll
-                for (int qq = 0; qq < PMAX; ++qq) {
-                    const int k = (int)min(S[qq], (uint32_t)max(n - 1, 0));
-                    int c = 0;
-#pragma unroll
-                    for (int st = 128; st > 0; st >>= 1) {
-                        const int t = min(c + st, max(nch - 1, 0));
-                        c = (c + st < nch && cum[t] <= k) ? c + st : c;
-                    }
-                    const int f = c * 64 + select_bit(mk[c], k - cum[c]);
-                    const int q = run_of(f);
-                    jv[qq] = s_rstart[w][q] + (f - s_rpre[w][q]);
-                }
+                const uint32_t pid = (uint32_t)(fa.perm[islot] - id_base);
+                floyd_draw<PMAX>(S, fa.seed, pid, (uint32_t)(s0 + rr), (uint32_t)rep_id, P, small ? P + 1 : n);
                 bool bad = false;
 #pragma unroll
                 for (int qq = 0; qq < PMAX; ++qq) {
-                    if (qq < cnt) {
-                        int j = jv[qq];
-                        if (j < 0 || (int64_t)j >= a.n_slots) {
-                            bad = true;
-                            j = islot;
-                        }
-                        out[qq] = j;
+                    if (qq < P) {
+                        const uint32_t k = small ? (uint32_t)qq : S[qq];
+                        const bool own = (int)k < n;
+                        // past the list room (an overflowing run, repeated by
+                        // the host) the entry is read from within the room
+                        const int e = lst[min(k, (uint32_t)(cap - 1))];
+                        const int j = s_rstart[w][e >> kRunOffBits] + (e & ((1 << kRunOffBits) - 1));
+                        const bool ok = j >= 0 && (int64_t)j < a.n_slots;
+                        bad |= own && !ok;
+                        out[qq] = (own && ok) ? j : islot;
                     }
                 }
                 if (bad) atomicOr(&a.flags[kFlagBadSlot], 32);
@@ -954,15 +938,15 @@ __global__ __launch_bounds__(256) void k_predraw(DrawArgs a)
     const uint32_t pid = (uint32_t)(a.perm[slot] - R.id_base);
     const int P = a.P;
     for (int rr = 0; rr < a.K; ++rr) {
-        int* out = a.batch + batch_index(rr, slot, 0, a.n_slots, P);
         if (n <= P) {
-            for (int q = 0; q < n; ++q) out[q] = a.shell[ell(slot, q, a.cap_shell)];
+            for (int q = 0; q < n; ++q)
+                a.batch[batch_index(rr, slot, q, a.n_slots, P)] = a.shell[ell(slot, q, a.cap_shell)];
         } else {
             uint32_t S[PMAX];
             floyd_draw<PMAX>(S, a.seed, pid, (uint32_t)(a.step0 + rr), (uint32_t)rep_id, P, n);
 #pragma unroll
             for (int q = 0; q < PMAX; ++q)
-                if (q < P) out[q] = a.shell[ell(slot, (int)S[q], a.cap_shell)];
+                if (q < P) a.batch[batch_index(rr, slot, q, a.n_slots, P)] = a.shell[ell(slot, (int)S[q], a.cap_shell)];
         }
     }
 }
@@ -1107,6 +1091,7 @@ __global__ __launch_bounds__(256) void k_forces(ForceArgs a)
                             jj = srow[(int64_t)kq * 64];
                         } else {
                             jj = a.batch[slot * P + m + u];
+                            if ((uint64_t)(uint32_t)jj >= (uint64_t)a.n_slots) jj = (int)slot;
                         }
                     }
                     j[u] = jj;
@@ -1224,6 +1209,9 @@ __global__ __launch_bounds__(256) void k_forces_lpp(ForceArgs a)
                 for (int u = 0; u < U; ++u) {
                     live[u] = m + u * LPP < cnt;
                     j[u] = live[u] ? brow[m + u * LPP] : (int)slot;
+                    // a batch entry outside the slots (never written) reads the
+                    // particle itself, whose pair term is zero
+                    if ((uint64_t)(uint32_t)j[u] >= (uint64_t)a.n_slots) j[u] = (int)slot;
                 }
 #pragma unroll
                 for (int u = 0; u < U; ++u) xj[u] = a.xs[j[u]];

@@ -93,6 +93,8 @@ struct rbl_ctx {
     bool built = false;
     int built_mask = 0;
     bool shell_counts = false;  // shell_len valid (explicit shell list or fused build)
+    bool fused_ok = true;       // false once a stencil outgrew the fused kernel's LDS lists
+    int cap_list = 0;           // fused kernel: LDS shell-list room per centre particle
     double r_s = 0, r_c = 0;
     std::vector<DevReplica> h_rep;
     int64_t n_cells = 0, cells_alloc = 0;
@@ -525,6 +527,7 @@ rbl_status launch_fused(rbl_ctx* c, int P, uint64_t seed, uint64_t step0, int K,
     fa.step_dev = step_dev;
     fa.K = K;
     fa.P = P;
+    fa.cap_list = c->cap_list;
     const unsigned g = grid_for(c->n_cells, 4);
     bool shift = true;  // every axis of every replica has >= 7 cells
     for (const DevReplica& r : c->h_rep)
@@ -546,6 +549,18 @@ rbl_status launch_fused(rbl_ctx* c, int P, uint64_t seed, uint64_t step0, int K,
     });
 }
 
+// LDS shell-list room per centre particle of the fused kernel: the longest
+// shell row seen, with the context's headroom (at least 1.5x after an
+// overflow), rounded up to 8 entries.
+void grow_cap_list(rbl_ctx* c, int need, bool regrow)
+{
+    const double f = regrow ? std::max(1.5, c->cfg.capacity_factor) : c->cfg.capacity_factor;
+    int64_t cap = (int64_t)std::ceil(std::max(need, 1) * f) + 8;
+    if (regrow) cap = std::max<int64_t>(cap, (int64_t)c->cap_list + 16);
+    cap = (cap + 7) / 8 * 8;
+    c->cap_list = (int)std::min<int64_t>(cap, 1 << 20);
+}
+
 // Sizes the core rows if needed (a counting pass and one synchronisation,
 // the first time only) and makes sure the shell-count and batch buffers
 // exist for `K` steps of batch size P.
@@ -554,13 +569,14 @@ rbl_status prepare_fused(rbl_ctx* c, int P, int K)
     for (int q = 0; q < 2; ++q)
         if (!c->d_len[q]) RBL_TRY(dalloc(&c->d_len[q], c->n_slots));
     RBL_TRY(ensure_batch(c, K, P));
-    if (c->cap[0] == 0) {
+    if (c->cap[0] == 0 || c->cap_list == 0) {
         RBL_TRY(clear_list_flags(c));
         BuildArgs a = build_args(c);
-        RBL_TRY(timed(c, kKBuild, [&] { launch_build<true>(c, a, RBL_LIST_CORE); }));
+        RBL_TRY(timed(c, kKBuild, [&] { launch_build<true>(c, a, RBL_LIST_CORE | RBL_LIST_SHELL); }));
         RBL_TRY(read_flags(c));
         if (c->h_flags[kFlagBadSlot]) return fail(RBL_E_HIP, "inconsistent cell binning");
-        RBL_TRY(ensure_list_storage(c, 0, c->h_flags[kFlagMaxCore]));
+        if (c->cap[0] == 0) RBL_TRY(ensure_list_storage(c, 0, c->h_flags[kFlagMaxCore]));
+        if (c->cap_list == 0) grow_cap_list(c, c->h_flags[kFlagMaxShell], false);
     }
     return RBL_OK;
 }
@@ -833,6 +849,7 @@ std::vector<unsigned char> block_signature(const rbl_ctx* c, const StepParams& s
     sig_put(v, c->r_s);
     sig_put(v, c->r_c);
     sig_put(v, c->n_cells);
+    sig_put(v, c->cap_list);
     for (int q = 0; q < 3; ++q) {
         sig_put(v, c->cap[q]);
         sig_put(v, (const void*)c->d_list[q]);
@@ -967,7 +984,7 @@ rbl_status md_run(rbl_ctx* c, double* pos, double* vel, double* force, int64_t n
     sp.dt = dt;
     sp.full = full;
     sp.fix = !full && c->cfg.momentum_fix;
-    sp.pre = !full && c->cfg.predraw;
+    sp.pre = !full && c->cfg.predraw && c->fused_ok;
     const int mask = full ? RBL_LIST_FULL : (RBL_LIST_CORE | RBL_LIST_SHELL);
     const bool use_graph = c->cfg.graphs && !c->profiling && c->gs;
     LaunchStreamGuard guard{c};
@@ -1032,7 +1049,15 @@ rbl_status md_run(rbl_ctx* c, double* pos, double* vel, double* force, int64_t n
     }
     if (nsteps > 0) RBL_TRY(integrate(c, kIntLast, dt, sp.fix));
     RBL_TRY(read_flags(c));
+    if (c->h_flags[kFlagStencil]) {
+        // a stencil held more candidates than the fused kernel's LDS lists:
+        // the run is repeated on explicit core and shell rows
+        c->fused_ok = false;
+        overflow = true;
+        return RBL_OK;
+    }
     if (c->h_flags[kFlagOverflow]) {
+        if (sp.pre && c->h_flags[kFlagMaxShell] > c->cap_list) grow_cap_list(c, c->h_flags[kFlagMaxShell], true);
         overflow = true;
         return RBL_OK;
     }
@@ -1319,10 +1344,12 @@ rbl_status rbl_step(rbl_ctx* c, double* pos, double* vel, double* force, int64_t
         const rbl_status st = md_run(c, pos, vel, force, nsteps, dt, P, seed, step0, rebuild_every,
                                      full, ev, overflow);
         if (st < 0 || !overflow) return st;
-        const int mask = full ? RBL_LIST_FULL : (c->cfg.predraw ? RBL_LIST_CORE : (RBL_LIST_CORE | RBL_LIST_SHELL));
+        drop_graphs(c);
+        if (c->h_flags[kFlagStencil]) continue;  // rows of the explicit path get counted afresh
+        const int mask = full ? RBL_LIST_FULL
+                              : ((c->cfg.predraw && c->fused_ok) ? RBL_LIST_CORE : (RBL_LIST_CORE | RBL_LIST_SHELL));
         for (int q = 0; q < 3; ++q)
             if ((mask >> q) & 1) RBL_TRY(ensure_list_storage(c, q, c->h_flags[kFlagMaxCore + q], true));
-        drop_graphs(c);
     }
     return fail(RBL_E_CAPACITY, "neighbour rows kept overflowing their capacity");
 }

@@ -215,6 +215,34 @@ def test_step_restart_and_determinism(predraw):
         assert np.array_equal(runs[0][1], host(v2)), kw
 
 
+@pytest.mark.parametrize("n,rc,steps", [
+    (6400, 5.0, 20),   # ~1860 stencil candidates: one centre particle per LDS group
+    (4666, 6.5, 10),   # ~4700 candidates, beyond the fused kernel's LDS lists
+])
+def test_large_stencils_match_oracle(n, rc, steps):
+    """Fused build + draw with stencils far above the N = 1M fluid's (751
+    candidates per cell): the LDS shell lists then take one centre particle
+    per group, and past their budget the run falls back to explicit rows
+    with inline draws.  Trajectory against the oracle (FP64, one lane per
+    particle), core rows and shell counts bit-exact at the final state."""
+    torch_cuda()
+    st = inputs.lj_fluid(n, 0.8, 1.0, seed=11)
+    x, v = dev(st.pos), dev(st.vel)
+    with Context(n, lanes=1) as ctx:
+        ctx.build(x, st.box, RS, rc)
+        status, _ = ctx.step(x, v, nsteps=steps, dt=0.002, P=10, seed=3, rebuild_every=10)
+        got_lists = ctx.export_lists(kinds=("core",))
+        got_counts = ctx.row_counts()
+    assert status in (0, _lib.RBL_W_SKIN)
+    xo, vo, _, _ = oracle.md_run(st.pos, st.vel, st.box, RS, rc, SKIN, 0.002, steps, p=10,
+                                 seed=3, K=10)
+    assert rel_l2(host(x), xo) < 1e-13
+    assert rel_l2(host(v), vo) < 1e-11
+    ref = oracle.System(host(x), st.box, RS, rc, SKIN).lists(kinds=("core", "shell"))
+    assert_lists_equal(got_lists, ref, kinds=("core",))
+    assert np.array_equal(got_counts[1], np.diff(ref.shell_off))
+
+
 def test_step_overflow_restart():
     """Rows sized tightly at a lattice-like first build overflow once the
     fluid melts; the run is repeated from the caller's arrays with larger
