@@ -662,6 +662,16 @@ __device__ __forceinline__ void write_lane2(uint32_t& v0, uint32_t& v1, uint32_t
 // s_waitcnt immediate with vmcnt = 0 and the expcnt / lgkmcnt fields at
 // their maximum (no wait on them)
 constexpr int kWaitVmcnt0 = 0x0F70;
+// Per lane: a where the lane's bit of the wave-uniform mask is set, else b.
+// A plain v_cndmask_b32 on the mask; written out so that the compiler keeps
+// it a select instead of branching around the computation of a.
+__device__ __forceinline__ int select_lanes(uint64_t mask, int a, int b)
+{
+    int r;
+    asm volatile("v_cndmask_b32 %0, %2, %1, %3" : "=v"(r) : "v"(a), "v"(b), "s"(mask));
+    return r;
+}
+
 constexpr int kCtrMax = 16;        // centre particles per group
 constexpr int kListBudget = 3072;  // 16-bit shell-list entries per wavefront
 constexpr int kRunOffBits = 10;    // list entry = run << 10 | offset in the run
@@ -674,7 +684,7 @@ __global__ __launch_bounds__(256) void k_build_draw(FusedArgs fa)
     __shared__ int s_rpre[4][64];
     __shared__ int s_rshift[4][64];
     __shared__ int s_ncnt[4][kCtrMax];
-    __shared__ unsigned short s_list[4][kListBudget];
+    __shared__ unsigned short s_list[4][kListBudget + 64];  // + a write-off word per lane
     const BuildArgs& a = fa.b;
     const int lane = threadIdx.x & 63;
     const int w = rfl((int)(threadIdx.x >> 6));
@@ -811,9 +821,11 @@ __global__ __launch_bounds__(256) void k_build_draw(FusedArgs fa)
                 const uint64_t ms = other & __ballot(r2 >= a.thr_shell_in) & __ballot(r2 < a.thr_out);
                 write_lane2(mclo, mchi, (uint32_t)mc, (uint32_t)(mc >> 32), ii);
                 const int base = rfl((int)__builtin_amdgcn_readlane((int)nshell, ii));
-                const int pos = base + (int)mbcnt(ms);
-                if (__builtin_amdgcn_inverse_ballot_w64(ms) && pos < cap)
-                    s_list[w][ii * cap + pos] = (unsigned short)ent;
+                // every lane writes (no branch): a selected lane to its list
+                // position (clamped into the room; an overflowing run is
+                // repeated by the host), the others to their write-off word
+                const int pos = ii * cap + min(base + (int)mbcnt(ms), cap - 1);
+                s_list[w][select_lanes(ms, pos, kListBudget + lane)] = (unsigned short)ent;
                 nshell = (uint32_t)rbl_writelane(base + (int)__popcll(ms), ii, (int)nshell);
             };
             constexpr int kNoShift = 1 | (1 << 2) | (1 << 4);
