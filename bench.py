@@ -49,6 +49,9 @@ def parse():
     ap.add_argument("--cpu-rows", type=int, default=400_000,
                     help="rows of the N = 1M state the CPU oracle leg processes")
     ap.add_argument("--variants", default="all", help="comma list or 'all'")
+    ap.add_argument("--workloads", default="ensemble,large",
+                    help="further workloads reported beside the headline: comma list of "
+                         "'ensemble' (512 replicas), 'large' (N = 2^24), or 'none'")
     ap.add_argument("--summarize", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
                     help="instead of running: write the profiles/ summaries from the output "
                          "folders of a rocprofv3 --kernel-trace --stats run and two --pmc runs "
@@ -245,6 +248,87 @@ def run_variant(name, x0, v0, box, precision, P, use_full, steps, warmup, torch)
     }
     log(f"[bench] {name}: {res['ms_per_step']:.4f} ms/step, {res['atom_steps_per_s']:.3e} atom-steps/s")
     return res
+
+
+def timed_steps(ctx, x, v, steps, warmup, P, torch, profile_steps):
+    """Warm-up, then `steps` steps between synchronisations (the clock of
+    the result), then a shorter pass with per-kernel events."""
+    from paper_2105_04884_amd import KIND_BUILD, KIND_FORCE_RBL, KIND_INTEGRATE, KIND_BIN, KIND_REDUCE
+    if warmup:
+        ctx.step(x, v, nsteps=warmup, dt=DT, P=P, seed=1, step0=0, rebuild_every=K_REBUILD)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    status, _ = ctx.step(x, v, nsteps=steps, dt=DT, P=P, seed=1, step0=warmup, rebuild_every=K_REBUILD)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ctx.set_profiling(True)
+    ctx.step(x, v, nsteps=profile_steps, dt=DT, P=P, seed=1, step0=warmup + steps,
+             rebuild_every=K_REBUILD)
+    kinds = {"force_rbl": KIND_FORCE_RBL, "build": KIND_BUILD, "binning": KIND_BIN,
+             "integrate": KIND_INTEGRATE, "reduce": KIND_REDUCE}
+    avg = {}
+    for k, q in kinds.items():
+        nl, ms = ctx.kernel_stats(q)
+        if nl:
+            avg[k] = round(1e3 * ms / nl, 2)
+    ctx.set_profiling(False)
+    return elapsed, int(status), avg
+
+
+def run_ensemble(torch, steps=500, warmup=20, seq_replicas=16, seq_steps=100):
+    """512 independent replicas (N log-uniform in [2000, 65536], density
+    uniform in [0.6, 0.9], T uniform in [0.8, 1.5]) advanced together, one
+    launch per kernel per step, against the same replicas one context each."""
+    from paper_2105_04884_amd import Context, inputs
+    ens = inputs.ensemble(512, seed=1)
+    pos, vel, boxes, off = ens.concat()
+    n = int(off[-1])
+    out = {"workload": "512 LJ replicas, N log-uniform in [2000, 65536] (sum %d), density U[0.6, 0.9], "
+                       "T U[0.8, 1.5], r_s=1.5 r_c=3.5 skin=0.3, P=10, rebuild every 10 steps, "
+                       "dt=0.005" % n,
+           "replicas": 512, "n_total": n, "steps": steps}
+    for precision in ("mixed", "fp64"):
+        x, v = torch.from_numpy(pos).cuda(), torch.from_numpy(vel).cuda()
+        with Context(n, precision=precision, replica_offsets=off, skin=SKIN) as ctx:
+            ctx.build(x, boxes, RS, RC)
+            el, st, avg = timed_steps(ctx, x, v, steps, warmup, 10, torch, 100)
+        out[precision] = {"atom_steps_per_s": n * steps / el, "ms_per_step": 1e3 * el / steps,
+                          "status": st, "kernels_avg_us": avg}
+        log(f"[bench] ensemble {precision}: {1e3 * el / steps:.3f} ms/step, {n * steps / el:.3e} atom-steps/s")
+    # the same replicas one context each, on a sample of them
+    picks = np.linspace(0, 511, seq_replicas).astype(int)
+    tot_atoms, tot_s = 0, 0.0
+    for r in picks:
+        s_ = ens.states[r]
+        x, v = torch.from_numpy(s_.pos).cuda(), torch.from_numpy(s_.vel).cuda()
+        with Context(s_.n, precision="mixed", skin=SKIN) as ctx:
+            ctx.build(x, s_.box, RS, RC)
+            el, _, _ = timed_steps(ctx, x, v, seq_steps, warmup, 10, torch, 10)
+        tot_atoms += s_.n * seq_steps
+        tot_s += el
+    out["sequential_mixed"] = {"atom_steps_per_s": tot_atoms / tot_s,
+                               "sample": f"{seq_replicas} of the 512 replicas, one context each, "
+                                         f"{seq_steps} steps each"}
+    out["speedup_batched_vs_sequential"] = out["mixed"]["atom_steps_per_s"] / (tot_atoms / tot_s)
+    log(f"[bench] ensemble sequential: {tot_atoms / tot_s:.3e} atom-steps/s")
+    return out
+
+
+def run_large(torch, steps=200, warmup=20):
+    """N = 2^24 LJ fluid, density 0.8, T = 1.2, r_s = 1.3, r_c = 4.0, P = 10,
+    mixed precision, lists every 10 steps."""
+    from paper_2105_04884_amd import Context, inputs
+    st = inputs.large_fluid(seed=1)
+    n = st.n
+    x, v = torch.from_numpy(st.pos).cuda(), torch.from_numpy(st.vel).cuda()
+    with Context(n, precision="mixed", skin=SKIN) as ctx:
+        ctx.build(x, st.box, 1.3, 4.0)
+        el, status, avg = timed_steps(ctx, x, v, steps, warmup, 10, torch, 50)
+    log(f"[bench] large: {1e3 * el / steps:.3f} ms/step, {n * steps / el:.3e} atom-steps/s")
+    return {"workload": "LJ fluid N=16,777,216 rho=0.8 T=1.2, r_s=1.3 r_c=4.0 skin=0.3, P=10, "
+                        "rebuild every 10 steps, dt=0.005, mixed",
+            "n_particles": n, "steps": steps, "atom_steps_per_s": n * steps / el,
+            "ms_per_step": 1e3 * el / steps, "status": status, "kernels_avg_us": avg}
 
 
 def force_error_vs_oracle(x0, box, torch, rows):
@@ -444,6 +528,15 @@ def main():
     roof["share_of_step"] = km[dom]["total_ms"] / sum(k["total_ms"] for k in km.values())
     roof["hbm_copy_GBs"] = copy_gbs
 
+    extra = {}
+    wl = [w for w in args.workloads.split(",") if w and w != "none"]
+    if "ensemble" in wl:
+        log("[bench] workload: 512-replica ensemble")
+        extra["ensemble"] = run_ensemble(torch)
+    if "large" in wl:
+        log("[bench] workload: N = 2^24")
+        extra["large"] = run_large(torch)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline")
@@ -485,6 +578,7 @@ def main():
         "speedup_rbl_mixed_vs_rbl_fp64": (speed("rbl_mixed_p10") / speed("rbl_fp64_p10")
                                           if speed("rbl_mixed_p10") and speed("rbl_fp64_p10") else None),
         "force_rel_l2_err_vs_fp64_oracle": errs,
+        "workloads": extra,
     }
     print(json.dumps(line), flush=True)
 

@@ -588,7 +588,8 @@ __device__ __forceinline__ void wave_lds_fence()
 //  - the periodic image of every candidate run is known from the stencil
 //    geometry when every axis has >= 7 cells, so dx = (x_i - x_j) + s with
 //    s in {-L, 0, L} exactly equals the canonical fma(-rint(d/L), L, d)
-//    (the SHIFT variant); smaller grids use the canonical formula per pair;
+//    (decided per wavefront: each cell belongs to one replica); smaller
+//    grids use the canonical formula per pair;
 //  - every cell-level quantity is made wave-uniform with readfirstlane, so
 //    it lives in SGPRs;
 //  - per centre particle and chunk, the core ballot goes to lane ii of two
@@ -676,7 +677,7 @@ constexpr int kCtrMax = 16;        // centre particles per group
 constexpr int kListBudget = 3072;  // 16-bit shell-list entries per wavefront
 constexpr int kRunOffBits = 10;    // list entry = run << 10 | offset in the run
 
-template <int PMAX, bool SHIFT>
+template <int PMAX>
 __global__ __launch_bounds__(256) void k_build_draw(FusedArgs fa)
 {
     __shared__ double4 s_ctr[4][kCtrMax];
@@ -709,6 +710,7 @@ __global__ __launch_bounds__(256) void k_build_draw(FusedArgs fa)
     const int cx = (int)(lc % nc0);
     const int cy = (int)((lc / nc0) % nc1);
     const int cz = (int)(lc / ((int64_t)nc0 * nc1));
+    const bool SHIFT = nc0 >= 7 && nc1 >= 7 && nc2 >= 7;  // image of every run known
     const AxisRunsS ax = axis_runs_s(cx, nc0);
     const AxisRunsS ay = axis_runs_s(cy, nc1);
     const AxisRunsS az = axis_runs_s(cz, nc2);

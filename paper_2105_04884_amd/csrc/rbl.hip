@@ -529,15 +529,8 @@ rbl_status launch_fused(rbl_ctx* c, int P, uint64_t seed, uint64_t step0, int K,
     fa.P = P;
     fa.cap_list = c->cap_list;
     const unsigned g = grid_for(c->n_cells, 4);
-    bool shift = true;  // every axis of every replica has >= 7 cells
-    for (const DevReplica& r : c->h_rep)
-        for (int d = 0; d < 3; ++d) shift = shift && r.nc[d] >= 7;
     return timed(c, kKBuild, [&] {
-#define RBL_BD(PM)                                                          \
-    do {                                                                    \
-        if (shift) k_build_draw<PM, true><<<g, kBlock, 0, c->ls>>>(fa);    \
-        else k_build_draw<PM, false><<<g, kBlock, 0, c->ls>>>(fa);         \
-    } while (0)
+#define RBL_BD(PM) k_build_draw<PM><<<g, kBlock, 0, c->ls>>>(fa)
         if (P <= 8) RBL_BD(8);
         else if (P <= 12) RBL_BD(12);
         else if (P <= 16) RBL_BD(16);

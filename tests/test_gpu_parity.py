@@ -337,6 +337,65 @@ def test_million_particle_sampled_parity():
             assert rel_l2(ff, ffo) < tol
 
 
+def test_large_fluid_sampled_parity():
+    """N = 2^24 LJ fluid at density 0.8 with r_s = 1.3, r_c = 4.0 (the large
+    single-system workload): explicit rows, batches and raw forces of
+    sampled particles against the oracle, then 10 fused MD steps and the
+    sampled core rows and shell counts at the GPU's final state."""
+    torch_cuda()
+    rs, rc = 1.3, 4.0
+    st = inputs.large_fluid(seed=1)
+    n = st.n
+    rows = np.random.default_rng(1).choice(n, size=300, replace=False)
+    rows = np.concatenate([rows, [0, n - 1]])
+    L = oracle.System(st.pos, st.box, rs, rc, SKIN).lists(rows=rows, kinds=("core", "shell"))
+    x = dev(st.pos)
+    with Context(n, precision="fp64", momentum_fix=False, lanes=1) as ctx:
+        ctx.build(x, st.box, rs, rc)
+        got = ctx.export_lists(rows=rows, kinds=("core", "shell"))
+        assert_lists_equal(got, L, kinds=("core", "shell"))
+        batch, count = ctx.export_batches(10, 1, 0, rows)
+        for k, i in enumerate(rows):
+            sh = L.row("shell", k)
+            kp = oracle.batch_positions(1, int(i), 0, 0, 10, len(sh))
+            assert np.array_equal(batch[k, :count[k]], sh[kp])
+        f = host(ctx.forces(10, seed=1, step=0, pos=x))[:, rows]
+        fo, _, _ = oracle.rbl_forces(st.pos, st.box, rs, rc, L, 10, 1, 0)
+        assert rel_l2(f, fo) < FP64_TOL
+        v = dev(st.vel)
+        status, _ = ctx.step(x, v, nsteps=10, dt=0.005, P=10, seed=1, rebuild_every=10)
+        assert status in (0, _lib.RBL_W_SKIN)
+        got = ctx.export_lists(rows=rows, kinds=("core",))
+        counts = ctx.row_counts(rows)
+    L2 = oracle.System(host(x), st.box, rs, rc, SKIN).lists(rows=rows, kinds=("core", "shell"))
+    assert_lists_equal(got, L2, kinds=("core",))
+    assert np.array_equal(counts[1], np.diff(L2.shell_off))
+
+
+def test_ensemble_512_sampled_replicas_md():
+    """The 512-replica ensemble (N log-uniform in [2000, 65536], densities
+    and temperatures uniform) advanced together, 20 FP64 steps with lists
+    every 10: eight sampled replicas against the oracle's run of each alone
+    (replica index in the Philox counter)."""
+    torch_cuda()
+    ens = inputs.ensemble(512, seed=1)
+    pos, vel, boxes, off = ens.concat()
+    n = int(off[-1])
+    x, v = dev(pos), dev(vel)
+    with Context(n, replica_offsets=off, lanes=1) as ctx:
+        ctx.build(x, boxes, RS, RC)
+        status, _ = ctx.step(x, v, nsteps=20, dt=0.005, P=10, seed=5, rebuild_every=10)
+    assert status in (0, _lib.RBL_W_SKIN)
+    xg, vg = host(x), host(v)
+    for r in np.linspace(0, 511, 8).astype(int):
+        s = ens.states[r]
+        sl = slice(off[r], off[r + 1])
+        xo, vo, _, _ = oracle.md_run(s.pos, s.vel, s.box, RS, RC, SKIN, 0.005, 20, p=10, seed=5, K=10,
+                                     replica=int(r))
+        assert rel_l2(xg[:, sl], xo) < 1e-13, r
+        assert rel_l2(vg[:, sl], vo) < 1e-11, r
+
+
 def test_error_paths():
     torch = torch_cuda()
     pos, box = _case("fluid1000")
