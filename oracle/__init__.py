@@ -61,16 +61,19 @@ def load():
     lib.orc_forces_rbl.argtypes = [C.c_int64, _f64p, _f64p, C.c_double, C.c_double, C.c_int,
                                    C.c_int64, C.c_void_p, _i64p, _i32p, _i64p, _i32p,
                                    C.c_int, C.c_uint64, C.c_uint64, C.c_uint32, C.c_void_p,
-                                   _f64p, _f64p, _f64p]
+                                   C.c_void_p, C.c_double, _f64p, _f64p, _f64p]
     lib.orc_forces_rbl.restype = C.c_int
     lib.orc_forces_full.argtypes = [C.c_int64, _f64p, _f64p, C.c_double, C.c_int,
-                                    C.c_int64, C.c_void_p, _i64p, _i32p, _f64p, _f64p, _f64p]
+                                    C.c_int64, C.c_void_p, _i64p, _i32p, C.c_void_p, C.c_double,
+                                    _f64p, _f64p, _f64p]
     lib.orc_forces_full.restype = C.c_int
     lib.orc_mean_subtract.argtypes = [C.c_int64, _f64p, _f64p]
+    lib.orc_erfc_pair.argtypes = [C.c_double, C.c_double, C.c_double,
+                                  C.POINTER(C.c_double), C.POINTER(C.c_double)]
     lib.orc_md_run.argtypes = [C.c_int64, _f64p, _f64p, _f64p, C.c_double, C.c_double,
                                C.c_double, C.c_double, C.c_int64, C.c_int, C.c_uint64,
                                C.c_int64, C.c_int, C.c_int, C.c_int, C.c_int, C.c_uint32,
-                               _f64p, C.c_void_p]
+                               C.c_void_p, C.c_double, _f64p, C.c_void_p]
     lib.orc_md_run.restype = C.c_int
     _lib = lib
     return lib
@@ -109,6 +112,15 @@ def lj(r2: float):
     f = C.c_double()
     u = C.c_double()
     lib.orc_lj(float(r2), C.byref(f), C.byref(u))
+    return f.value, u.value
+
+
+def erfc_pair(r2: float, qq: float, alpha: float):
+    """(fmag, u) of the real-space Ewald term qq erfc(alpha r)/r (unshifted)."""
+    lib = load()
+    f = C.c_double()
+    u = C.c_double()
+    lib.orc_erfc_pair(float(r2), float(qq), float(alpha), C.byref(f), C.byref(u))
     return f.value, u.value
 
 
@@ -208,10 +220,20 @@ class System:
 # ---------------------------------------------------------------------------
 # forces and dynamics
 
+def _charges(charges, n):
+    if charges is None:
+        return None
+    q = np.ascontiguousarray(charges, dtype=np.float64)
+    if q.shape != (n,):
+        raise ValueError("charges must have one entry per particle")
+    return q
+
+
 def rbl_forces(pos, box, rs, rc, lists: Lists, p: int, seed: int, step: int,
-               replica: int = 0, shift: bool = True, pid=None):
+               replica: int = 0, shift: bool = True, pid=None, charges=None, alpha: float = 0.0):
     """Raw RBL force (before mean subtraction) for the rows of ``lists``.
-    Returns (f (3, nrows), e (nrows,), w (nrows,))."""
+    With ``charges`` the real-space Ewald term (screening ``alpha``) is added
+    to the LJ pair.  Returns (f (3, nrows), e (nrows,), w (nrows,))."""
     lib = load()
     pos = np.ascontiguousarray(pos, dtype=np.float64)
     nrows = lists.rows.shape[0]
@@ -219,23 +241,26 @@ def rbl_forces(pos, box, rs, rc, lists: Lists, p: int, seed: int, step: int,
     e = np.zeros(nrows)
     w = np.zeros(nrows)
     pid_arr = None if pid is None else np.ascontiguousarray(pid, dtype=np.int64)
+    q = _charges(charges, pos.shape[1])
     lib.orc_forces_rbl(pos.shape[1], pos, np.asarray(box, dtype=np.float64), rs, rc, int(shift),
                        nrows, lists.rows.ctypes.data_as(C.c_void_p),
                        lists.core_off, lists.core_idx, lists.shell_off, lists.shell_idx,
-                       p, seed, step, replica, _ptr_or_null(pid_arr), f, e, w)
+                       p, seed, step, replica, _ptr_or_null(pid_arr), _ptr_or_null(q), float(alpha),
+                       f, e, w)
     return f, e, w
 
 
-def full_forces(pos, box, rc, lists: Lists, shift: bool = True):
+def full_forces(pos, box, rc, lists: Lists, shift: bool = True, charges=None, alpha: float = 0.0):
     lib = load()
     pos = np.ascontiguousarray(pos, dtype=np.float64)
+    q = _charges(charges, pos.shape[1])
     nrows = lists.rows.shape[0]
     f = np.zeros((3, nrows))
     e = np.zeros(nrows)
     w = np.zeros(nrows)
     lib.orc_forces_full(pos.shape[1], pos, np.asarray(box, dtype=np.float64), rc, int(shift),
                         nrows, lists.rows.ctypes.data_as(C.c_void_p),
-                        lists.full_off, lists.full_idx, f, e, w)
+                        lists.full_off, lists.full_idx, _ptr_or_null(q), float(alpha), f, e, w)
     return f, e, w
 
 
@@ -248,7 +273,8 @@ def mean_subtract(f: np.ndarray):
 
 
 def md_run(pos, vel, box, rs, rc, skin, dt, nsteps, p=10, seed=1, step0=0, K=10,
-           use_full=False, shift=True, momentum_fix=True, replica=0, want_ev=False):
+           use_full=False, shift=True, momentum_fix=True, replica=0, want_ev=False,
+           charges=None, alpha: float = 0.0):
     """Velocity-Verlet run (Algorithm 1, NVE).  Returns (pos, vel, force, ev)
     with ev of shape (nsteps+1, 2) = (U, W) per force evaluation or None."""
     lib = load()
@@ -256,9 +282,10 @@ def md_run(pos, vel, box, rs, rc, skin, dt, nsteps, p=10, seed=1, step0=0, K=10,
     v = np.ascontiguousarray(vel, dtype=np.float64).copy()
     f = np.zeros_like(x)
     ev = np.zeros((nsteps + 1, 2)) if want_ev else None
+    q = _charges(charges, x.shape[1])
     r = lib.orc_md_run(x.shape[1], x, v, np.asarray(box, dtype=np.float64), rs, rc, skin, dt,
                        nsteps, p, seed, step0, K, int(use_full), int(shift), int(momentum_fix),
-                       replica, f, _ptr_or_null(ev))
+                       replica, _ptr_or_null(q), float(alpha), f, _ptr_or_null(ev))
     if r:
         raise RuntimeError(f"orc_md_run failed ({r})")
     return x, v, f, ev

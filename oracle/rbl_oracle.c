@@ -27,6 +27,12 @@
  *                       without-replacement moments of Appendix A.
  *   orc_lj              LJ 12-6 pair potential eq. (1), truncated at the
  *                       cut-off and shifted to zero there (Sec. II).
+ *   orc_erfc_pair       real-space Ewald term q_i q_j erfc(alpha r)/r of a
+ *                       pair of charges, added to the LJ pair for charged
+ *                       systems (the short-range part that a random-batch
+ *                       list would serve beside random-batch Ewald, Sec. IV);
+ *                       its form is the standard one, not printed in the
+ *                       paper, and is shifted to zero at the cut-off too.
  *   orc_build_*         cell list and core/shell neighbour lists (Sec. II,
  *                       Fig. 1); brute force is the plain definition.
  *   orc_forces_rbl      F_i = F_ic + (n/p) sum_{B(i)} f~_ij, eq. (3) and
@@ -145,6 +151,55 @@ void orc_lj(double r2, double* fmag, double* u)
     double sr6 = r2i * r2i * r2i;
     *fmag = 24.0 * r2i * sr6 * (2.0 * sr6 - 1.0);
     *u = 4.0 * sr6 * (sr6 - 1.0);
+}
+
+/* Real-space Ewald pair of charges with product qq at squared distance r2:
+ *   u(r) = qq erfc(alpha r) / r,
+ *   -du/dr = qq [erfc(alpha r) / r^2 + (2 alpha / sqrt(pi)) exp(-alpha^2 r^2) / r],
+ * and fmag = (-du/dr) / r, the factor of the displacement x_i - x_j. */
+void orc_erfc_pair(double r2, double qq, double alpha, double* fmag, double* u)
+{
+    double r = sqrt(r2);
+    double er = erfc(alpha * r);
+    double gauss = exp(-(alpha * alpha) * r2);
+    double two_over_sqrt_pi = 2.0 / sqrt(3.14159265358979323846);
+    *u = qq * er / r;
+    *fmag = qq * (er / (r2 * r) + two_over_sqrt_pi * alpha * gauss / r2);
+}
+
+/* Pair term of particles i and j: LJ, plus the erfc term when charges are
+ * given (q == NULL: LJ only). */
+static void pair_term(double r2, const double* q, double alpha, int64_t i, int64_t j,
+                      double* fmag, double* u)
+{
+    orc_lj(r2, fmag, u);
+    if (q) {
+        double fe, ue;
+        orc_erfc_pair(r2, q[i] * q[j], alpha, &fe, &ue);
+        *fmag = *fmag + fe;
+        *u = *u + ue;
+    }
+}
+
+/* Energies at the cut-off, for shifting the pair energy to zero there: the
+ * LJ part, and the erfc part per unit charge product. */
+typedef struct {
+    double lj, erfc_per_qq;
+} orc_shift;
+
+static orc_shift cutoff_shift(double rc2, int shift, const double* q, double alpha)
+{
+    orc_shift sh = {0.0, 0.0};
+    if (!shift) return sh;
+    double fm;
+    orc_lj(rc2, &fm, &sh.lj);
+    if (q) orc_erfc_pair(rc2, 1.0, alpha, &fm, &sh.erfc_per_qq);
+    return sh;
+}
+
+static double pair_shift(orc_shift sh, const double* q, int64_t i, int64_t j)
+{
+    return q ? sh.lj + q[i] * q[j] * sh.erfc_per_qq : sh.lj;
 }
 
 /* Minimum-image component of x_i - x_j in a periodic box of side L. */
@@ -446,12 +501,12 @@ int orc_forces_rbl(int64_t n, const double* pos, const double box[3],
                    const int64_t* core_off, const int32_t* core_idx,
                    const int64_t* shell_off, const int32_t* shell_idx,
                    int p, uint64_t seed, uint64_t step, uint32_t replica,
-                   const int64_t* pid, double* f, double* e, double* w)
+                   const int64_t* pid, const double* charge, double alpha,
+                   double* f, double* e, double* w)
 {
     double inv[3] = {1.0 / box[0], 1.0 / box[1], 1.0 / box[2]};
     double rs2 = rs * rs, rc2 = rc * rc;
-    double fc_unused, uc = 0.0;
-    if (shift) orc_lj(rc2, &fc_unused, &uc);
+    orc_shift sh = cutoff_shift(rc2, shift, charge, alpha);
     int32_t* K = (int32_t*)malloc(sizeof(int32_t) * (size_t)(p > 0 ? p : 1));
     for (int64_t k = 0; k < nrows; ++k) {
         int64_t i = rows ? rows[k] : k;
@@ -462,9 +517,9 @@ int orc_forces_rbl(int64_t n, const double* pos, const double box[3],
             int64_t j = core_idx[q];
             double r2 = dist2(pos, n, i, j, box, inv, d);
             if (r2 < rs2) {
-                orc_lj(r2, &fm, &u);
+                pair_term(r2, charge, alpha, i, j, &fm, &u);
                 for (int a = 0; a < 3; ++a) Fc[a] += fm * d[a];
-                ec += u - uc;
+                ec += u - pair_shift(sh, charge, i, j);
                 wc += fm * r2;
             }
         }
@@ -479,9 +534,9 @@ int orc_forces_rbl(int64_t n, const double* pos, const double box[3],
             int64_t j = shell_idx[shell_off[k] + K[m]];
             double r2 = dist2(pos, n, i, j, box, inv, d);
             if (r2 >= rs2 && r2 < rc2) {
-                orc_lj(r2, &fm, &u);
+                pair_term(r2, charge, alpha, i, j, &fm, &u);
                 for (int a = 0; a < 3; ++a) Fs[a] += fm * d[a];
-                es += u - uc;
+                es += u - pair_shift(sh, charge, i, j);
                 ws += fm * r2;
             }
         }
@@ -496,12 +551,11 @@ int orc_forces_rbl(int64_t n, const double* pos, const double box[3],
 int orc_forces_full(int64_t n, const double* pos, const double box[3],
                     double rc, int shift, int64_t nrows, const int64_t* rows,
                     const int64_t* full_off, const int32_t* full_idx,
-                    double* f, double* e, double* w)
+                    const double* charge, double alpha, double* f, double* e, double* w)
 {
     double inv[3] = {1.0 / box[0], 1.0 / box[1], 1.0 / box[2]};
     double rc2 = rc * rc;
-    double fc_unused, uc = 0.0;
-    if (shift) orc_lj(rc2, &fc_unused, &uc);
+    orc_shift sh = cutoff_shift(rc2, shift, charge, alpha);
     for (int64_t k = 0; k < nrows; ++k) {
         int64_t i = rows ? rows[k] : k;
         double d[3], fm, u;
@@ -510,9 +564,9 @@ int orc_forces_full(int64_t n, const double* pos, const double box[3],
             int64_t j = full_idx[q];
             double r2 = dist2(pos, n, i, j, box, inv, d);
             if (r2 < rc2) {
-                orc_lj(r2, &fm, &u);
+                pair_term(r2, charge, alpha, i, j, &fm, &u);
                 for (int a = 0; a < 3; ++a) F[a] += fm * d[a];
-                ei += u - uc;
+                ei += u - pair_shift(sh, charge, i, j);
                 wi += fm * r2;
             }
         }
@@ -598,7 +652,7 @@ int orc_md_run(int64_t n, double* pos, double* vel, const double box[3],
                double rs, double rc, double skin, double dt, int64_t nsteps,
                int p, uint64_t seed, int64_t step0, int K, int use_full,
                int shift, int momentum_fix, uint32_t replica,
-               double* force_out, double* ev_out)
+               const double* charge, double alpha, double* force_out, double* ev_out)
 {
     if (K < 1 || n < 1) return -1;
     orc_lists L = {0};
@@ -619,11 +673,11 @@ int orc_md_run(int64_t n, double* pos, double* vel, const double box[3],
             if (rcode) break;
         }
         if (use_full) {
-            orc_forces_full(n, pos, box, rc, shift, n, NULL, L.full_off, L.full_idx, F, e, w);
+            orc_forces_full(n, pos, box, rc, shift, n, NULL, L.full_off, L.full_idx, charge, alpha, F, e, w);
         } else {
             orc_forces_rbl(n, pos, box, rs, rc, shift, n, NULL, L.core_off, L.core_idx,
                            L.shell_off, L.shell_idx, p, seed, (uint64_t)s, replica, NULL,
-                           F, e, w);
+                           charge, alpha, F, e, w);
             if (momentum_fix) orc_mean_subtract(n, F, NULL);
         }
         if (ev_out) total_ev(n, e, w, ev_out + 2 * it);

@@ -425,3 +425,95 @@ def test_rbl_momentum_conserved_along_run():
     st = inputs.small_fluid(seed=1)
     _, v, _, _ = oracle.md_run(st.pos, st.vel, st.box, RS, RC, SKIN, 0.005, 30, p=10, seed=2)
     assert np.abs(v.sum(axis=1)).max() < 1e-10
+
+
+# ------------------------------------------ real-space Ewald (erfc) term ---
+
+def test_erfc_pair_closed_forms():
+    """At r = 1, alpha = 1, qq = 1: u = erfc(1) and fmag = erfc(1) +
+    (2/sqrt(pi)) e^-1, with erfc(1) = 0.15729920705028513066 (tabulated);
+    the term is linear in the charge product."""
+    erfc1 = 0.15729920705028513066
+    f, u = oracle.erfc_pair(1.0, 1.0, 1.0)
+    assert abs(u - erfc1) < 1e-15
+    assert abs(f - (erfc1 + 2.0 / math.sqrt(math.pi) * math.exp(-1.0))) < 1e-15
+    f2, u2 = oracle.erfc_pair(1.0, -3.0, 1.0)
+    assert abs(u2 + 3.0 * u) < 1e-15 and abs(f2 + 3.0 * f) < 1e-15
+
+
+def test_erfc_pair_force_is_minus_gradient():
+    for alpha in (0.3, 1.0):
+        for r in np.linspace(0.8, 5.2, 12):
+            h = 1e-6
+            _, up = oracle.erfc_pair((r + h) ** 2, 1.0, alpha)
+            _, um = oracle.erfc_pair((r - h) ** 2, 1.0, alpha)
+            f, _ = oracle.erfc_pair(r * r, 1.0, alpha)
+            assert abs(f - (-(up - um) / (2 * h) / r)) < 1e-7 * max(1.0, abs(f))
+
+
+def test_erfc_pair_coulomb_limit():
+    """alpha -> 0: the bare Coulomb pair qq/r, force factor qq/r^3."""
+    for r in (0.9, 2.0, 4.7):
+        f, u = oracle.erfc_pair(r * r, 2.0, 1e-9)
+        assert abs(u - 2.0 / r) < 1e-8 * (2.0 / r)
+        assert abs(f - 2.0 / r ** 3) < 1e-8 * (2.0 / r ** 3)
+
+
+def _charged_gas(n, box, seed):
+    st = inputs.random_gas(n, box, seed=seed, min_dist=0.95)
+    q = np.where(np.random.default_rng(seed).permutation(n) < n // 2, 1.0, -1.0)
+    return st, q
+
+
+def test_charged_full_force_is_minus_energy_gradient():
+    """LJ + erfc pair (alpha 0.3, cut-off 5): F_i = -dU/dx_i of the total
+    shifted energy, by central differences."""
+    box = np.array([11.0, 11.0, 11.0])
+    rc = 5.0
+    st, q = _charged_gas(150, box, 21)
+    L = oracle.System(st.pos, box, RS, rc, SKIN).lists()
+    f, _, _ = oracle.full_forces(st.pos, box, rc, L, charges=q, alpha=0.3)
+
+    def total(p):
+        _, e, _ = oracle.full_forces(p, box, rc, L, charges=q, alpha=0.3)
+        return float(e.sum())
+
+    h = 1e-6
+    for i in (0, 41, 149):
+        for a in range(3):
+            p = st.pos.copy()
+            p[a, i] += h
+            up = total(p)
+            p[a, i] -= 2 * h
+            um = total(p)
+            g = -(up - um) / (2 * h)
+            assert abs(g - f[a, i]) < 2e-5 * max(1.0, abs(f[a, i])), (i, a, g, f[a, i])
+    # charges change the force: the erfc term is really there
+    f0, _, _ = oracle.full_forces(st.pos, box, rc, L)
+    assert np.abs(f - f0).max() > 1e-3
+
+
+def test_charged_newton_third_law_and_full_batch():
+    box = np.array([11.0, 11.0, 11.0])
+    rc = 5.0
+    st, q = _charged_gas(200, box, 22)
+    L = oracle.System(st.pos, box, RS, rc, SKIN).lists()
+    ff, ef, _ = oracle.full_forces(st.pos, box, rc, L, charges=q, alpha=0.3)
+    assert np.all(np.abs(ff.sum(axis=1)) < 1e-10 * np.abs(ff).sum(axis=1))
+    p = int(np.diff(L.shell_off).max())
+    fr, er, _ = oracle.rbl_forces(st.pos, box, RS, rc, L, p, seed=2, step=0, charges=q, alpha=0.3)
+    assert np.abs(fr - ff).max() < 1e-12 * np.abs(ff).max()
+    assert abs(er.sum() - ef.sum()) < 1e-10 * abs(ef.sum())
+
+
+def test_charged_nve_energy_conservation():
+    box = np.array([11.0, 11.0, 11.0])
+    rc = 5.0
+    st, q = _charged_gas(200, box, 23)
+    _, _, _, ev0 = oracle.md_run(st.pos, st.vel, box, RS, rc, SKIN, 0.002, 0, use_full=True,
+                                 want_ev=True, charges=q, alpha=0.3)
+    x, v, _, ev = oracle.md_run(st.pos, st.vel, box, RS, rc, SKIN, 0.002, 200, use_full=True,
+                                want_ev=True, charges=q, alpha=0.3)
+    e0 = ev0[0, 0] + 0.5 * float(np.sum(st.vel ** 2))
+    e1 = ev[-1, 0] + 0.5 * float(np.sum(v ** 2))
+    assert abs(e1 - e0) < 2e-4 * abs(e0)
