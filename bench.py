@@ -49,9 +49,10 @@ def parse():
     ap.add_argument("--cpu-rows", type=int, default=400_000,
                     help="rows of the N = 1M state the CPU oracle leg processes")
     ap.add_argument("--variants", default="all", help="comma list or 'all'")
-    ap.add_argument("--workloads", default="ensemble,large",
+    ap.add_argument("--workloads", default="ensemble,large,slab",
                     help="further workloads reported beside the headline: comma list of "
-                         "'ensemble' (512 replicas), 'large' (N = 2^24), or 'none'")
+                         "'ensemble' (512 replicas), 'large' (N = 2^24), 'slab' (charged "
+                         "slab, N = 2M, LJ + erfc), or 'none'")
     ap.add_argument("--summarize", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
                     help="instead of running: write the profiles/ summaries from the output "
                          "folders of a rocprofv3 --kernel-trace --stats run and two --pmc runs "
@@ -248,6 +249,25 @@ def run_variant(name, x0, v0, box, precision, P, use_full, steps, warmup, torch)
     }
     log(f"[bench] {name}: {res['ms_per_step']:.4f} ms/step, {res['atom_steps_per_s']:.3e} atom-steps/s")
     return res
+
+
+def run_slab(torch, steps=500, warmup=20, P=20):
+    """Charged liquid slab in vapour, N = 2,000,000, LJ + real-space Ewald
+    (alpha 0.3), r_s = 1.5, r_c = 5.0, P = 20, mixed precision."""
+    from paper_2105_04884_amd import Context, inputs
+    st = inputs.slab(seed=1)
+    n = st.n
+    x, v = torch.from_numpy(st.pos).cuda(), torch.from_numpy(st.vel).cuda()
+    q = torch.from_numpy(st.charges).cuda()
+    with Context(n, precision="mixed", skin=SKIN, pair="lj_erfc", alpha=0.3, charges=q) as ctx:
+        ctx.build(x, st.box, 1.5, 5.0)
+        el, status, avg = timed_steps(ctx, x, v, steps, warmup, P, torch, 50)
+    log(f"[bench] slab: {1e3 * el / steps:.3f} ms/step, {n * steps / el:.3e} atom-steps/s")
+    return {"workload": "charged LJ slab N=2,000,000, box L x L x 3L (L=133.5), liquid rho=0.8 in the "
+                        "middle third, vapour rho=0.02, charges +-1, T=0.9; LJ + erfc(alpha r)/r with "
+                        "alpha=0.3, r_s=1.5 r_c=5.0 skin=0.3, P=20, rebuild every 10 steps, dt=0.005, mixed",
+            "n_particles": n, "steps": steps, "atom_steps_per_s": n * steps / el,
+            "ms_per_step": 1e3 * el / steps, "status": status, "kernels_avg_us": avg}
 
 
 def timed_steps(ctx, x, v, steps, warmup, P, torch, profile_steps):
@@ -536,6 +556,9 @@ def main():
     if "large" in wl:
         log("[bench] workload: N = 2^24")
         extra["large"] = run_large(torch)
+    if "slab" in wl:
+        log("[bench] workload: charged slab")
+        extra["slab"] = run_slab(torch)
 
     cpu = None
     if not args.no_cpu_baseline:

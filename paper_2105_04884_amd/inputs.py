@@ -17,6 +17,7 @@ from __future__ import annotations
 
 import math
 from dataclasses import dataclass
+from typing import Optional
 
 import numpy as np
 
@@ -30,6 +31,7 @@ class State:
     pos: np.ndarray  # (3, N) float64
     vel: np.ndarray  # (3, N) float64
     box: np.ndarray  # (3,) float64
+    charges: Optional[np.ndarray] = None  # (N,) float64, charged systems only
 
     @property
     def n(self) -> int:
@@ -134,6 +136,37 @@ def million_fluid(seed: int = 1) -> State:
 def large_fluid(seed: int = 1) -> State:
     """N = 16,777,216, density 0.8, T = 1.2: the large single-system case."""
     return lj_fluid(16_777_216, 0.8, 1.2, seed)
+
+
+def slab(n: int = 2_000_000, rho_liquid: float = 0.8, rho_vapour: float = 0.02,
+         temperature: float = 0.9, seed: int = 1, jitter: float = 0.05) -> State:
+    """Charged liquid slab in vapour.  Box (L, L, 3L) with
+    L = (n / (rho_liquid + 2 rho_vapour))^(1/3); the liquid (FCC + jitter at
+    rho_liquid, round(rho_liquid L^3) particles) fills the middle third
+    L <= z < 2L, the rest is vapour, split evenly over the two outer thirds
+    (FCC + jitter, about rho_vapour each).  Charges +1 and -1, n/2 of each
+    (n odd: one more +1), assigned by a random permutation; Maxwell-Boltzmann
+    velocities at ``temperature``."""
+    L = (n / (rho_liquid + 2.0 * rho_vapour)) ** (1.0 / 3.0)
+    cube = np.array([L, L, L], dtype=np.float64)
+    n_l = min(n, int(round(rho_liquid * L**3)))
+    n_v = n - n_l
+    n_v1 = n_v // 2
+    rng = np.random.default_rng(seed)
+    parts = []
+    for count, z0 in ((n_v1, 0.0), (n_l, L), (n_v - n_v1, 2.0 * L)):
+        if count == 0:
+            continue
+        p = fcc_sites(count, cube)
+        p += rng.uniform(-jitter, jitter, size=(3, count))
+        p[2] += z0
+        parts.append(p)
+    pos = np.concatenate(parts, axis=1)
+    vel = maxwell_boltzmann(rng, n, temperature)
+    order = rng.permutation(n)
+    charges = np.where(order < (n + 1) // 2, 1.0, -1.0)
+    box = np.array([L, L, 3.0 * L], dtype=np.float64)
+    return State(np.ascontiguousarray(pos), np.ascontiguousarray(vel), box, charges)
 
 
 @dataclass

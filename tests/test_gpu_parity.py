@@ -396,6 +396,87 @@ def test_ensemble_512_sampled_replicas_md():
         assert rel_l2(vg[:, sl], vo) < 1e-11, r
 
 
+ALPHA = 0.3  # real-space Ewald screening of the charged slab
+
+
+def test_charged_slab_forces_match_oracle():
+    """LJ + real-space Ewald pair (alpha 0.3, r_c = 5.0, P = 20) on a small
+    charged liquid slab in vapour: lists bit-exact, RBL and full forces and
+    the energy within tolerance in both precisions."""
+    torch_cuda()
+    rc, P = 5.0, 20
+    st = inputs.slab(6000, seed=2)
+    L = oracle.System(st.pos, st.box, RS, rc, SKIN).lists()
+    x, q = dev(st.pos), dev(st.charges)
+    fo, eo, _ = oracle.rbl_forces(st.pos, st.box, RS, rc, L, P, 4, 3, charges=st.charges, alpha=ALPHA)
+    ffo, efo, _ = oracle.full_forces(st.pos, st.box, rc, L, charges=st.charges, alpha=ALPHA)
+    for precision, tol in (("fp64", FP64_TOL), ("mixed", MIXED_TOL)):
+        with Context(st.n, precision=precision, momentum_fix=False, pair="lj_erfc", alpha=ALPHA,
+                     charges=q, lists=("core", "shell", "full")) as ctx:
+            ctx.build(x, st.box, RS, rc)
+            if precision == "fp64":
+                assert_lists_equal(ctx.export_lists(), L)
+            f, ev = ctx.forces(P, seed=4, step=3, pos=x, want_ev=True)
+            assert rel_l2(host(f), fo) < tol
+            assert abs(host(ev)[0] - eo.sum()) < 10 * tol * abs(eo.sum())
+            ff, evf = ctx.full_forces(x, want_ev=True)
+            assert rel_l2(host(ff), ffo) < tol
+            assert abs(host(evf)[0] - efo.sum()) < 10 * tol * abs(efo.sum())
+
+
+def test_charged_slab_trajectory_matches_oracle():
+    """20 FP64 steps of the charged slab (lists every 10, fused build and
+    draw) against the oracle's run."""
+    torch_cuda()
+    rc, P = 5.0, 20
+    st = inputs.slab(6000, seed=3)
+    x, v, q = dev(st.pos), dev(st.vel), dev(st.charges)
+    with Context(st.n, pair="lj_erfc", alpha=ALPHA, charges=q, lanes=1) as ctx:
+        ctx.build(x, st.box, RS, rc)
+        status, _ = ctx.step(x, v, nsteps=20, dt=0.004, P=P, seed=6, rebuild_every=10)
+    assert status in (0, _lib.RBL_W_SKIN)
+    xo, vo, _, _ = oracle.md_run(st.pos, st.vel, st.box, RS, rc, SKIN, 0.004, 20, p=P, seed=6, K=10,
+                                 charges=st.charges, alpha=ALPHA)
+    assert rel_l2(host(x), xo) < 1e-12
+    assert rel_l2(host(v), vo) < 1e-9
+
+
+def test_slab_two_million_sampled_parity():
+    """The N = 2,000,000 charged slab (box L x L x 3L, liquid at 0.8 in the
+    middle third, vapour at 0.02 around it; r_c = 5.0, P = 20): sampled
+    rows' lists, batches and forces, then 10 fused MD steps and the sampled
+    core rows and shell counts at the final state."""
+    torch_cuda()
+    rc, P = 5.0, 20
+    st = inputs.slab(seed=1)
+    n = st.n
+    rows = np.random.default_rng(3).choice(n, size=300, replace=False)
+    rows = np.concatenate([rows, [0, n - 1]])
+    L = oracle.System(st.pos, st.box, RS, rc, SKIN).lists(rows=rows, kinds=("core", "shell"))
+    x, q = dev(st.pos), dev(st.charges)
+    with Context(n, precision="fp64", momentum_fix=False, pair="lj_erfc", alpha=ALPHA, charges=q,
+                 lanes=1) as ctx:
+        ctx.build(x, st.box, RS, rc)
+        assert_lists_equal(ctx.export_lists(rows=rows, kinds=("core", "shell")), L,
+                           kinds=("core", "shell"))
+        batch, count = ctx.export_batches(P, 1, 0, rows)
+        for k, i in enumerate(rows):
+            sh = L.row("shell", k)
+            kp = oracle.batch_positions(1, int(i), 0, 0, P, len(sh))
+            assert np.array_equal(batch[k, :count[k]], sh[kp])
+        f = host(ctx.forces(P, seed=1, step=0, pos=x))[:, rows]
+        fo, _, _ = oracle.rbl_forces(st.pos, st.box, RS, rc, L, P, 1, 0, charges=st.charges, alpha=ALPHA)
+        assert rel_l2(f, fo) < FP64_TOL
+        v = dev(st.vel)
+        status, _ = ctx.step(x, v, nsteps=10, dt=0.004, P=P, seed=1, rebuild_every=10)
+        assert status in (0, _lib.RBL_W_SKIN)
+        got = ctx.export_lists(rows=rows, kinds=("core",))
+        counts = ctx.row_counts(rows)
+    L2 = oracle.System(host(x), st.box, RS, rc, SKIN).lists(rows=rows, kinds=("core", "shell"))
+    assert_lists_equal(got, L2, kinds=("core",))
+    assert np.array_equal(counts[1], np.diff(L2.shell_off))
+
+
 def test_error_paths():
     torch = torch_cuda()
     pos, box = _case("fluid1000")
