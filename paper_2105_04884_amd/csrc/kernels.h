@@ -20,14 +20,21 @@ enum { kIntFirst = 0, kIntMid = 1, kIntLast = 2 };
 enum { kFlagOverflow = 0, kFlagMaxCore = 1, kFlagMaxShell = 2, kFlagMaxFull = 3,
        kFlagNonfinite = 4, kFlagSkin = 5, kFlagBadSlot = 6, kFlagStencil = 7, kNumFlags = 8 };
 
-// Block -> work-tile map that gives XCD x (blocks x, x+8, ...) a contiguous
-// range of tiles.
+// Block -> work-tile map.  Blocks are dispatched to the 8 XCDs round-robin
+// (block b to XCD b % 8); this map hands every XCD chunks of kXcdChunk
+// consecutive tiles, the chunks dealt round-robin too, so that an XCD's L2
+// sees neighbouring tiles while the load stays balanced when the work is
+// concentrated in one part of the tile range (a liquid slab, one dense
+// replica).  Tiles past the last whole round map to themselves.
+constexpr int64_t kXcdChunk = 16;
+
 __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t nb)
 {
-    const int64_t x = b & 7;
-    const int64_t q = nb >> 3;
-    const int64_t r = nb & 7;
-    return x * q + (x < r ? x : r) + (b >> 3);
+    const int64_t full = nb / (8 * kXcdChunk) * (8 * kXcdChunk);
+    if (b >= full) return b;
+    const int64_t x = b & 7;   // XCD of block b
+    const int64_t r = b >> 3;  // its rank among that XCD's blocks
+    return ((r / kXcdChunk) * 8 + x) * kXcdChunk + r % kXcdChunk;
 }
 
 // Raises *p to v.  Every wavefront reports its longest row here, and atomics
@@ -564,6 +571,7 @@ struct FusedArgs {
     int K;
     int P;
     int cap_list;              // LDS shell-list room per centre particle (<= 0: all candidates)
+    int list_budget;           // LDS list entries per wavefront (dynamic LDS of the launch)
 };
 
 __device__ __forceinline__ void wave_lds_fence()
@@ -597,8 +605,9 @@ __device__ __forceinline__ void wave_lds_fence()
 //    by the centre-particle lanes (coalesced ELL writes); the shell ballot
 //    is compacted into the particle's LDS list with mbcnt;
 //  - a centre particle's list has room for every stencil candidate, so the
-//    centre particles go in groups of kListBudget / (candidates) at most;
-//    a stencil beyond kListBudget candidates (or a run beyond 1023) raises
+//    centre particles go in groups of (LDS list budget) / (room) at most,
+//    the budget being set by the host from the shell counts it has seen
+//    (dynamic LDS); a room beyond the budget (or a run beyond 1023) raises
 //    kFlagStencil and the host redoes the run on explicit lists;
 //  - centre cells are mapped to blocks so that each XCD works on a
 //    contiguous range of cells (its L2 keeps the neighbourhood).
@@ -674,7 +683,8 @@ __device__ __forceinline__ int select_lanes(uint64_t mask, int a, int b)
 }
 
 constexpr int kCtrMax = 16;        // centre particles per group
-constexpr int kListBudget = 3072;  // 16-bit shell-list entries per wavefront
+constexpr int kListBudgetMin = 3072;  // 16-bit shell-list entries per wavefront, at least
+constexpr int kListBudgetMax = 6912;  // at most (the block's LDS stays within 64 KB)
 constexpr int kRunOffBits = 10;    // list entry = run << 10 | offset in the run
 
 template <int PMAX>
@@ -685,10 +695,13 @@ __global__ __launch_bounds__(256) void k_build_draw(FusedArgs fa)
     __shared__ int s_rpre[4][64];
     __shared__ int s_rshift[4][64];
     __shared__ int s_ncnt[4][kCtrMax];
-    __shared__ unsigned short s_list[4][kListBudget + 64];  // + a write-off word per lane
+    // per wavefront: list_budget entries + a write-off word per lane
+    extern __shared__ unsigned short s_dyn[];
     const BuildArgs& a = fa.b;
     const int lane = threadIdx.x & 63;
     const int w = rfl((int)(threadIdx.x >> 6));
+    const int budget = fa.list_budget;
+    unsigned short* const s_lst = s_dyn + w * (budget + 64);
     const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
     const int64_t cell = tile * 4 + w;
     if (cell >= a.n_cells) return;
@@ -746,7 +759,10 @@ __global__ __launch_bounds__(256) void k_build_draw(FusedArgs fa)
     s_rstart[w][lane] = rstart;
     s_rpre[w][lane] = rpre;
     s_rshift[w][lane] = rshift;
-    if (total > kListBudget || wave_max(rlen) >= (1 << kRunOffBits)) {
+    // list room per centre particle: the host's bound on shell counts (a
+    // particle beyond it raises the overflow flag), never above the stencil
+    const int cap = (fa.cap_list > 0 && fa.cap_list < total) ? fa.cap_list : max(total, 1);
+    if (cap > budget || wave_max(rlen) >= (1 << kRunOffBits)) {
         // the host repeats the run on explicit rows; until it does, this
         // cell's particles have empty rows, so no force kernel of the run
         // reads a batch entry or core row that was never written
@@ -761,10 +777,7 @@ __global__ __launch_bounds__(256) void k_build_draw(FusedArgs fa)
         return;
     }
     const int nch = (total + 63) >> 6;  // >= 1: the cell itself is in the stencil
-    // list room per centre particle: the host's bound on shell counts (a
-    // particle beyond it raises the overflow flag), never above the stencil
-    const int cap = (fa.cap_list > 0 && fa.cap_list < total) ? fa.cap_list : total;
-    const int gmax = min(kCtrMax, kListBudget / cap);  // >= 1
+    const int gmax = min(kCtrMax, budget / cap);  // >= 1
     const int P = fa.P;
     wave_lds_fence();
 
@@ -827,7 +840,7 @@ __global__ __launch_bounds__(256) void k_build_draw(FusedArgs fa)
                 // position (clamped into the room; an overflowing run is
                 // repeated by the host), the others to their write-off word
                 const int pos = ii * cap + min(base + (int)mbcnt(ms), cap - 1);
-                s_list[w][select_lanes(ms, pos, kListBudget + lane)] = (unsigned short)ent;
+                s_lst[select_lanes(ms, pos, budget + lane)] = (unsigned short)ent;
                 nshell = (uint32_t)rbl_writelane(base + (int)__popcll(ms), ii, (int)nshell);
             };
             constexpr int kNoShift = 1 | (1 << 2) | (1 << 4);
@@ -893,7 +906,7 @@ __global__ __launch_bounds__(256) void k_build_draw(FusedArgs fa)
                 const int islot = i0 + g0 + ii;
                 const int n = s_ncnt[w][ii];
                 const bool small = n <= P;
-                const unsigned short* lst = &s_list[w][ii * cap];
+                const unsigned short* lst = &s_lst[ii * cap];
                 int* out = fa.batch + batch_index(rr, islot, 0, a.n_slots, P);
                 uint32_t S[PMAX];
                 const uint32_t pid = (uint32_t)(fa.perm[islot] - id_base);

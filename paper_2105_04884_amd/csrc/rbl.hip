@@ -528,9 +528,14 @@ rbl_status launch_fused(rbl_ctx* c, int P, uint64_t seed, uint64_t step0, int K,
     fa.K = K;
     fa.P = P;
     fa.cap_list = c->cap_list;
+    // room for about eight centre particles per group, within the block's
+    // 64 KB of LDS
+    fa.list_budget = (int)std::min<int64_t>(kListBudgetMax,
+                                            std::max<int64_t>(kListBudgetMin, ((int64_t)8 * c->cap_list + 63) / 64 * 64));
+    const size_t lds = (size_t)4 * (fa.list_budget + 64) * sizeof(unsigned short);
     const unsigned g = grid_for(c->n_cells, 4);
     return timed(c, kKBuild, [&] {
-#define RBL_BD(PM) k_build_draw<PM><<<g, kBlock, 0, c->ls>>>(fa)
+#define RBL_BD(PM) k_build_draw<PM><<<g, kBlock, lds, c->ls>>>(fa)
         if (P <= 8) RBL_BD(8);
         else if (P <= 12) RBL_BD(12);
         else if (P <= 16) RBL_BD(16);
