@@ -79,50 +79,77 @@ struct BinArgs {
     int* flags;
 };
 
+// Cell of every source particle and its rank within the cell (a unique
+// index; the in-cell order is fixed later by k_cell_sort).  A cell-sorted
+// source has runs of equal cells along the wavefront, so there one lane per
+// distinct cell adds the run's size to the histogram and the others take
+// consecutive ranks after it: a handful of atomics per wavefront instead of
+// one per particle.
 template <int SRC>
 __global__ __launch_bounds__(256) void k_bin_count(BinArgs a)
 {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= a.n_src) return;
-    int r;
-    double x[3];
-    if (SRC == kSrcCaller) {
-        r = a.id_rep[s];
-        x[0] = a.pos[s];
-        x[1] = a.pos[a.n + s];
-        x[2] = a.pos[2 * a.n + s];
-    } else {
-        if (a.perm_old[s] < 0) {
-            a.cell_of_src[s] = -1;
-            return;
+    bool live = s < a.n_src;
+    int cell = -1;
+    if (live) {
+        int r;
+        double x[3];
+        if (SRC == kSrcCaller) {
+            r = a.id_rep[s];
+            x[0] = a.pos[s];
+            x[1] = a.pos[a.n + s];
+            x[2] = a.pos[2 * a.n + s];
+        } else {
+            live = a.perm_old[s] >= 0;
+            r = a.slice_rep[s >> 6];
+            const double4 p = a.xs[s];
+            x[0] = p.x;
+            x[1] = p.y;
+            x[2] = p.z;
+            if (live) {
+                // skin monitor: displacement over the list lifetime that ends here
+                const double dx = p.x - a.xb[s];
+                const double dy = p.y - a.xb[a.n_src + s];
+                const double dz = p.z - a.xb[2 * a.n_src + s];
+                if (dx * dx + dy * dy + dz * dz > a.half_skin2) raise_flag(&a.flags[kFlagSkin]);
+            }
         }
-        r = a.slice_rep[s >> 6];
-        const double4 p = a.xs[s];
-        x[0] = p.x;
-        x[1] = p.y;
-        x[2] = p.z;
-        // skin monitor: displacement over the list lifetime that ends here
-        const double dx = p.x - a.xb[s];
-        const double dy = p.y - a.xb[a.n_src + s];
-        const double dz = p.z - a.xb[2 * a.n_src + s];
-        if (dx * dx + dy * dy + dz * dz > a.half_skin2) raise_flag(&a.flags[kFlagSkin]);
-    }
-    const DevReplica& R = a.rep[r];
-    int c[3];
+        if (live) {
+            const DevReplica& R = a.rep[r];
+            int c[3];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        if (!isfinite(x[d])) {
-            raise_flag(&a.flags[kFlagNonfinite]);
-            x[d] = 0.0;
+            for (int d = 0; d < 3; ++d) {
+                if (!isfinite(x[d])) {
+                    raise_flag(&a.flags[kFlagNonfinite]);
+                    x[d] = 0.0;
+                }
+                const double w = wrap_coord(x[d], R.L[d], R.inv[d]);
+                int k = (int)floor(w * R.cscale[d]);
+                k = k < 0 ? 0 : (k > R.nc[d] - 1 ? R.nc[d] - 1 : k);
+                c[d] = k;
+            }
+            cell = (int)(R.cell_base + ((int64_t)c[2] * R.nc[1] + c[1]) * R.nc[0] + c[0]);
         }
-        const double w = wrap_coord(x[d], R.L[d], R.inv[d]);
-        int k = (int)floor(w * R.cscale[d]);
-        k = k < 0 ? 0 : (k > R.nc[d] - 1 ? R.nc[d] - 1 : k);
-        c[d] = k;
+        a.cell_of_src[s] = cell;
     }
-    const int cell = (int)(R.cell_base + ((int64_t)c[2] * R.nc[1] + c[1]) * R.nc[0] + c[0]);
-    a.cell_of_src[s] = cell;
-    a.rank_of_src[s] = atomicAdd(&a.cell_count[cell], 1);
+    if (SRC == kSrcCaller) {
+        if (live) a.rank_of_src[s] = atomicAdd(&a.cell_count[cell], 1);
+        return;
+    }
+    const int lane = threadIdx.x & 63;
+    uint64_t todo = __ballot(live);
+    int rank = 0;
+    while (todo) {  // one pass per distinct cell of the wavefront
+        const int lead = (int)__builtin_ctzll(todo);
+        const int lc = __builtin_amdgcn_readlane(cell, lead);
+        const uint64_t same = __ballot(cell == lc) & todo;
+        int base = 0;
+        if (lane == lead) base = atomicAdd(&a.cell_count[lc], (int)__popcll(same));
+        base = __builtin_amdgcn_readlane(base, lead);
+        if ((same >> lane) & 1ull) rank = base + (int)mbcnt(same);
+        todo &= ~same;
+    }
+    if (live) a.rank_of_src[s] = rank;
 }
 
 // Exclusive scan of the cell histogram (three passes, 2048 cells per block),
