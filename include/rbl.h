@@ -87,7 +87,11 @@ typedef struct rbl_config {
                                   the context time the three and keep the fastest (see
                                   rbl_tuning).  The choice changes the order of the per-
                                   particle sums, so bit-identical runs need the same value. */
-    int32_t reserved0;
+    int32_t persistent;        /* force-kernel launch: 1 one block per work tile, 2 a
+                                  persistent grid of the blocks the device keeps resident,
+                                  each walking tiles in turn; 0 (default) lets the first
+                                  rbl_step of the context time both and keep the faster
+                                  (see rbl_launch_modes).  Results are the same. */
     double capacity_factor;    /* rows are first sized to capacity_factor x the longest row
                                   seen + 8 (default 1.25); rows that overflow later are regrown
                                   (rbl_build) or the run is repeated with longer rows
@@ -213,6 +217,15 @@ rbl_status rbl_kernel_stats(rbl_ctx* ctx, int kind, int64_t* launches, double* t
  * for k = 0 (RBL) and k = 1 (full list); zeros before tuning.  Any pointer
  * may be NULL. */
 rbl_status rbl_tuning(rbl_ctx* ctx, int32_t* lpp_rbl, int32_t* lpp_full, double* force_us);
+
+/* Launch mode chosen for the RBL and the full-list force kernels (1:
+ * persistent grid, 0: one block per tile) and the autotuner's times:
+ * force_us[2k + q] = microseconds per launch for k = 0 (RBL), 1 (full list)
+ * with q = 0 one block per tile, q = 1 persistent; zeros before tuning.
+ * Any pointer may be NULL.  Used by callers that size launches (the
+ * persistent grid of the large single-system workload). */
+rbl_status rbl_launch_modes(rbl_ctx* ctx, int32_t* persistent_rbl, int32_t* persistent_full,
+                            double* force_us);
 
 /* Size information: n_slots (particles plus per-replica padding to 64) and
  * current list capacities (entries per row). */

@@ -79,7 +79,7 @@ class Context:
 
     def __init__(self, n: int, *, precision: str = "fp64", lists=("core", "shell"),
                  skin: float = 0.3, shift: bool = True, momentum_fix: bool = True,
-                 predraw: bool = True, graphs: bool = True, lanes: int = 0,
+                 predraw: bool = True, graphs: bool = True, lanes: int = 0, persistent: int = 0,
                  capacity_factor: float = 1.25,
                  replica_offsets=None,
                  pair: str = "lj", alpha: float = 0.0, charges=None, stream=None):
@@ -100,6 +100,7 @@ class Context:
         cfg.predraw = int(bool(predraw))
         cfg.graphs = int(bool(graphs))
         cfg.lanes = int(lanes)
+        cfg.persistent = int(persistent)
         cfg.capacity_factor = float(capacity_factor)
         self._offsets = None
         if replica_offsets is not None:
@@ -246,8 +247,14 @@ class Context:
         a, b = C.c_int32(), C.c_int32()
         us = (C.c_double * 6)()
         _check(self._lib.rbl_tuning(self._h, C.byref(a), C.byref(b), us))
+        pr, pf = C.c_int32(), C.c_int32()
+        pus = (C.c_double * 4)()
+        _check(self._lib.rbl_launch_modes(self._h, C.byref(pr), C.byref(pf), pus))
         return {"lpp_rbl": a.value, "lpp_full": b.value,
-                "rbl_us": list(us[0:3]), "full_us": list(us[3:6])}
+                "rbl_us": list(us[0:3]), "full_us": list(us[3:6]),
+                "persistent_rbl": pr.value, "persistent_full": pf.value,
+                "rbl_grid_vs_persistent_us": list(pus[0:2]),
+                "full_grid_vs_persistent_us": list(pus[2:4])}
 
     def info(self):
         ns = C.c_int64()

@@ -48,7 +48,7 @@ class Config(C.Structure):
         ("predraw", C.c_int32),
         ("graphs", C.c_int32),
         ("lanes", C.c_int32),
-        ("reserved0", C.c_int32),
+        ("persistent", C.c_int32),
         ("capacity_factor", C.c_double),
         ("replica_offsets", C.POINTER(C.c_int64)),
         ("charges", C.c_void_p),
@@ -59,7 +59,8 @@ _lib = None
 _names = [
     "rbl_config_init", "rbl_create", "rbl_destroy", "rbl_build", "rbl_forces", "rbl_full_forces",
     "rbl_step", "rbl_row_counts", "rbl_export_lists", "rbl_export_batches", "rbl_export_binning",
-    "rbl_sync", "rbl_set_profiling", "rbl_kernel_stats", "rbl_info", "rbl_tuning", "rbl_last_error",
+    "rbl_sync", "rbl_set_profiling", "rbl_kernel_stats", "rbl_info", "rbl_tuning", "rbl_launch_modes",
+    "rbl_last_error",
     "rbl_version",
 ]
 
@@ -98,6 +99,7 @@ def load(path: str = LIB_PATH):
         "rbl_kernel_stats": (i32, [vp, i32, p64, pd]),
         "rbl_info": (i32, [vp, p64, p32, p32, p32]),
         "rbl_tuning": (i32, [vp, p32, p32, pd]),
+        "rbl_launch_modes": (i32, [vp, p32, p32, pd]),
         "rbl_last_error": (C.c_char_p, []),
         "rbl_version": (C.c_char_p, []),
     }

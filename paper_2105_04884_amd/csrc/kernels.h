@@ -1034,6 +1034,8 @@ struct ForceArgs {
     int P;
     double* f;             // [3][n_slots]
     double* partial;       // [5][n_slices]
+    int64_t vblocks;       // work tiles of 256 lanes; a launch of fewer blocks (a
+                           // persistent grid) walks them in steps of its size
 };
 
 template <int PREC, bool ERFC>
@@ -1083,11 +1085,10 @@ __device__ __forceinline__ void accumulate(const double4& xi, const double4 (&xj
 constexpr int kGatherBatch = 4;
 
 template <int PREC, int MODE, bool ENERGY, bool ERFC, int PMAX>
-__global__ __launch_bounds__(256) void k_forces(ForceArgs a)
+__device__ __forceinline__ void force_tile(const ForceArgs& a, int64_t tile, uint32_t* s_pos)
 {
-    __shared__ uint32_t s_pos[MODE == kShellInline ? PMAX * 256 : 1];
     constexpr int U = kGatherBatch;
-    const int64_t slot = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const int64_t slot = tile * blockDim.x + threadIdx.x;
     const int64_t slice = slot >> 6;
     if (slice >= a.n_slices) return;
     const int rep_id = a.slice_rep[slice];
@@ -1198,6 +1199,17 @@ __global__ __launch_bounds__(256) void k_forces(ForceArgs a)
 // a fixed order, and combined as F = F_core + scale * F_shell by lane 0.
 // More, shorter wavefronts keep more gathers in flight than one lane per
 // particle.
+// One tile per block, or (persistent grid) tiles b, b + gridDim.x, ... in
+// turn; the grid is a multiple of 8 blocks, so a block keeps to its XCD's
+// tiles of the XCD map.
+template <int PREC, int MODE, bool ENERGY, bool ERFC, int PMAX>
+__global__ __launch_bounds__(256) void k_forces(ForceArgs a)
+{
+    __shared__ uint32_t s_pos[MODE == kShellInline ? PMAX * 256 : 1];
+    for (int64_t b = blockIdx.x; b < a.vblocks; b += gridDim.x)
+        force_tile<PREC, MODE, ENERGY, ERFC, PMAX>(a, xcd_tile(b, a.vblocks), s_pos);
+}
+
 template <int CTRL>
 __device__ __forceinline__ double dpp_quad_f64(double v)
 {
@@ -1215,10 +1227,10 @@ __device__ __forceinline__ double group_sum(double v)
 }
 
 template <int PREC, int MODE, bool ENERGY, bool ERFC, int LPP>
-__global__ __launch_bounds__(256) void k_forces_lpp(ForceArgs a)
+__device__ __forceinline__ void force_tile_lpp(const ForceArgs& a, int64_t tile)
 {
     constexpr int U = 2;
-    const int64_t g = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const int64_t g = tile * blockDim.x + threadIdx.x;
     const int64_t slot = g / LPP;
     const int l = (int)(g % LPP);
     const int64_t slice = slot >> 6;
@@ -1326,6 +1338,13 @@ __global__ __launch_bounds__(256) void k_forces_lpp(ForceArgs a)
         a.partial[3 * ns + wv] = te;
         a.partial[4 * ns + wv] = tw;
     }
+}
+
+template <int PREC, int MODE, bool ENERGY, bool ERFC, int LPP>
+__global__ __launch_bounds__(256) void k_forces_lpp(ForceArgs a)
+{
+    for (int64_t b = blockIdx.x; b < a.vblocks; b += gridDim.x)
+        force_tile_lpp<PREC, MODE, ENERGY, ERFC, LPP>(a, xcd_tile(b, a.vblocks));
 }
 
 // Per-replica sums of the wavefront partials in a fixed order, so the result

@@ -127,6 +127,9 @@ struct rbl_ctx {
     double* d_partial = nullptr;    // [5][n_slices * 4] wavefront partial sums
     int part_per = 1;               // partial entries per slice of the last force launch
     int lpp_rbl = 4, lpp_full = 4;  // lanes per particle of the force kernels
+    bool persist[2] = {false, false};  // persistent force grid (RBL, full list)
+    double persist_us[2][2] = {{0, 0}, {0, 0}};  // per launch: one block per tile, persistent
+    int n_cu = 256;                 // compute units of the device
     bool tuned_rbl = false, tuned_full = false;
     double tune_us[2][3] = {{0, 0, 0}, {0, 0, 0}};  // measured force time per LPP 1, 2, 4
     double* d_part2 = nullptr;
@@ -632,21 +635,48 @@ ForceArgs force_args(rbl_ctx* c, int P, uint64_t seed, uint64_t step, bool full)
     return a;
 }
 
-template <int PREC, int MODE, bool EN, bool ERFC>
-void launch_force_p(rbl_ctx* c, const ForceArgs& a)
+// Blocks of a force launch: one per work tile, or (persistent) as many as
+// the device keeps resident, a multiple of 8 so that every block stays on
+// the tiles the XCD map gives its XCD.
+template <typename Kernel>
+unsigned force_grid(rbl_ctx* c, Kernel kernel, int64_t vblocks, bool persistent)
 {
+    if (!persistent) return (unsigned)vblocks;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    int64_t g = (int64_t)c->n_cu * per_cu / 8 * 8;
+    if (g < 8) g = 8;
+    return (unsigned)std::min<int64_t>(g, vblocks);
+}
+
+template <int PREC, int MODE, bool EN, bool ERFC>
+void launch_force_p(rbl_ctx* c, const ForceArgs& a0)
+{
+    ForceArgs a = a0;
+    const bool pers = c->persist[MODE == kShellNone ? 1 : 0];
     if constexpr (MODE == kShellInline) {
-        const unsigned g = grid_for(c->n_slots);
+        a.vblocks = grid_for(c->n_slots);
         c->part_per = 1;
-        if (a.P <= 16) k_forces<PREC, MODE, EN, ERFC, 16><<<g, kBlock, 0, c->ls>>>(a);
-        else k_forces<PREC, MODE, EN, ERFC, 32><<<g, kBlock, 0, c->ls>>>(a);
+        if (a.P <= 16) {
+            auto k = k_forces<PREC, MODE, EN, ERFC, 16>;
+            k<<<force_grid(c, k, a.vblocks, pers), kBlock, 0, c->ls>>>(a);
+        } else {
+            auto k = k_forces<PREC, MODE, EN, ERFC, 32>;
+            k<<<force_grid(c, k, a.vblocks, pers), kBlock, 0, c->ls>>>(a);
+        }
     } else {
         const int lpp = MODE == kShellNone ? c->lpp_full : c->lpp_rbl;
         c->part_per = lpp;
-        const unsigned g = grid_for(c->n_slots * lpp);
-        if (lpp == 4) k_forces_lpp<PREC, MODE, EN, ERFC, 4><<<g, kBlock, 0, c->ls>>>(a);
-        else if (lpp == 2) k_forces_lpp<PREC, MODE, EN, ERFC, 2><<<g, kBlock, 0, c->ls>>>(a);
-        else k_forces<PREC, MODE, EN, ERFC, 1><<<grid_for(c->n_slots), kBlock, 0, c->ls>>>(a);
+        if (lpp == 4 || lpp == 2) {
+            a.vblocks = grid_for(c->n_slots * lpp);
+            auto k = lpp == 4 ? k_forces_lpp<PREC, MODE, EN, ERFC, 4> : k_forces_lpp<PREC, MODE, EN, ERFC, 2>;
+            k<<<force_grid(c, k, a.vblocks, pers), kBlock, 0, c->ls>>>(a);
+        } else {
+            a.vblocks = grid_for(c->n_slots);
+            auto k = k_forces<PREC, MODE, EN, ERFC, 1>;
+            k<<<force_grid(c, k, a.vblocks, pers), kBlock, 0, c->ls>>>(a);
+        }
     }
 }
 
@@ -928,40 +958,53 @@ rbl_status autotune_forces(rbl_ctx* c, const StepParams& sp)
 {
     const int kind = sp.full ? 1 : 0;
     if (sp.full ? c->tuned_full : c->tuned_rbl) return RBL_OK;
-    if (!sp.full && !sp.pre) {  // the inline-draw kernel has one lane per particle
-        c->tuned_rbl = true;
-        return RBL_OK;
-    }
     hipEvent_t e0 = take_event(c), e1 = take_event(c);
     if (!e0 || !e1) return fail(RBL_E_HIP, "event creation failed");
-    const int cand[3] = {1, 2, 4};
-    double best = 1e30;
-    int best_lpp = 4;
     const bool prof = c->profiling;
     c->profiling = false;
-    for (int q = 0; q < 3; ++q) {
-        (sp.full ? c->lpp_full : c->lpp_rbl) = cand[q];
+    // microseconds per launch: mean of the second and third of three
+    auto time_force = [&](double& us) -> rbl_status {
         float total = 0.f;
         for (int rep = 0; rep < 3; ++rep) {
             HIP_TRY(hipEventRecord(e0, c->ls));
             if (sp.full) RBL_TRY(full_force_sorted(c, false));
-            else RBL_TRY(rbl_force_sorted(c, sp.P, sp.seed, 0, 0, false));
+            else if (sp.pre) RBL_TRY(rbl_force_sorted(c, sp.P, sp.seed, 0, 0, false));
+            else RBL_TRY(rbl_force_sorted(c, sp.P, sp.seed, 0, -1, false));
             HIP_TRY(hipEventRecord(e1, c->ls));
             HIP_TRY(hipEventSynchronize(e1));
             float ms = 0.f;
             HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
             if (rep > 0) total += ms;
         }
-        c->tune_us[kind][q] = 1e3 * total / 2.0;
-        if (c->tune_us[kind][q] < best) {
-            best = c->tune_us[kind][q];
-            best_lpp = cand[q];
+        us = 1e3 * total / 2.0;
+        return RBL_OK;
+    };
+    // lanes per particle (the inline-draw kernel has one lane per particle)
+    if (c->cfg.lanes == 0 && (sp.full || sp.pre)) {
+        const int cand[3] = {1, 2, 4};
+        double best = 1e30;
+        int best_lpp = 4;
+        for (int q = 0; q < 3; ++q) {
+            (sp.full ? c->lpp_full : c->lpp_rbl) = cand[q];
+            RBL_TRY(time_force(c->tune_us[kind][q]));
+            if (c->tune_us[kind][q] < best) {
+                best = c->tune_us[kind][q];
+                best_lpp = cand[q];
+            }
         }
+        (sp.full ? c->lpp_full : c->lpp_rbl) = best_lpp;
+    }
+    // one block per tile or a persistent grid (same results either way)
+    if (c->cfg.persistent == 0) {
+        for (int q = 0; q < 2; ++q) {
+            c->persist[kind] = q == 1;
+            RBL_TRY(time_force(c->persist_us[kind][q]));
+        }
+        c->persist[kind] = c->persist_us[kind][1] < c->persist_us[kind][0];
     }
     c->profiling = prof;
     c->ev_pool.push_back(e0);
     c->ev_pool.push_back(e1);
-    (sp.full ? c->lpp_full : c->lpp_rbl) = best_lpp;
     (sp.full ? c->tuned_full : c->tuned_rbl) = true;
     return RBL_OK;
 }
@@ -1024,7 +1067,7 @@ rbl_status md_run(rbl_ctx* c, double* pos, double* vel, double* force, int64_t n
     };
 
     RBL_TRY(do_build(step0, true));
-    if (c->cfg.lanes == 0) RBL_TRY(autotune_forces(c, sp));
+    if (c->cfg.lanes == 0 || c->cfg.persistent == 0) RBL_TRY(autotune_forces(c, sp));
     RBL_TRY(do_force(step0, ev != nullptr && nsteps == 0));
     int64_t it = 1;
     while (it <= nsteps) {
@@ -1102,6 +1145,7 @@ void rbl_config_init(rbl_config* cfg, int64_t n)
     cfg->predraw = 1;
     cfg->graphs = 1;
     cfg->lanes = 0;
+    cfg->persistent = 0;
     cfg->capacity_factor = 1.25;
     cfg->replica_offsets = nullptr;
     cfg->charges = nullptr;
@@ -1175,6 +1219,7 @@ rbl_status rbl_create(const rbl_config* cfg, void* hip_stream, rbl_ctx** out)
     if (cfg->lists <= 0 || cfg->lists > 7) return fail(RBL_E_ARG, "list mask must be in 1..7");
     if (cfg->lanes != 0 && cfg->lanes != 1 && cfg->lanes != 2 && cfg->lanes != 4)
         return fail(RBL_E_ARG, "lanes must be 0, 1, 2 or 4");
+    if (cfg->persistent < 0 || cfg->persistent > 2) return fail(RBL_E_ARG, "persistent must be 0, 1 or 2");
     if (!(cfg->skin >= 0.0) || !std::isfinite(cfg->skin)) return fail(RBL_E_ARG, "skin must be >= 0");
     if (!(cfg->capacity_factor > 0.0) || !std::isfinite(cfg->capacity_factor))
         return fail(RBL_E_ARG, "capacity_factor must be > 0");
@@ -1198,6 +1243,13 @@ rbl_status rbl_create(const rbl_config* cfg, void* hip_stream, rbl_ctx** out)
     c->R = cfg->n_replicas;
     c->n = cfg->n;
     if (cfg->lanes > 0) c->lpp_rbl = c->lpp_full = cfg->lanes;
+    c->persist[0] = c->persist[1] = cfg->persistent == 2;
+    {
+        int dev = 0, ncu = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
+            c->n_cu = ncu;
+    }
     int64_t slot = 0;
     for (int r = 0; r < c->R; ++r) {
         c->id_base.push_back(off[r]);
@@ -1541,6 +1593,17 @@ rbl_status rbl_tuning(rbl_ctx* c, int32_t* lpp_rbl, int32_t* lpp_full, double* f
     if (force_us)
         for (int k = 0; k < 2; ++k)
             for (int q = 0; q < 3; ++q) force_us[3 * k + q] = c->tune_us[k][q];
+    return RBL_OK;
+}
+
+rbl_status rbl_launch_modes(rbl_ctx* c, int32_t* persistent_rbl, int32_t* persistent_full, double* force_us)
+{
+    if (!c) return fail(RBL_E_ARG, "NULL context");
+    if (persistent_rbl) *persistent_rbl = c->persist[0] ? 1 : 0;
+    if (persistent_full) *persistent_full = c->persist[1] ? 1 : 0;
+    if (force_us)
+        for (int k = 0; k < 2; ++k)
+            for (int q = 0; q < 2; ++q) force_us[2 * k + q] = c->persist_us[k][q];
     return RBL_OK;
 }
 

@@ -477,6 +477,25 @@ def test_slab_two_million_sampled_parity():
     assert np.array_equal(counts[1], np.diff(L2.shell_off))
 
 
+def test_persistent_force_grid_matches_tile_grid():
+    """The persistent force grid (resident blocks walking the work tiles)
+    and one block per tile give the same forces and trajectory bit for bit
+    at N = 10^6, where the persistent blocks take several tiles each."""
+    torch_cuda()
+    st = inputs.million_fluid(seed=2)
+    out = []
+    for persistent in (1, 2):
+        x, v = dev(st.pos), dev(st.vel)
+        with Context(st.n, precision="mixed", lanes=2, persistent=persistent) as ctx:
+            ctx.build(x, st.box, RS, RC)
+            f = host(ctx.forces(10, seed=1, step=0, pos=x))
+            ctx.step(x, v, nsteps=20, dt=0.005, P=10, seed=1, rebuild_every=10)
+            assert ctx.tuning()["persistent_rbl"] == persistent - 1
+        out.append((f, host(x), host(v)))
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(a, b)
+
+
 def test_error_paths():
     torch = torch_cuda()
     pos, box = _case("fluid1000")
