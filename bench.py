@@ -371,8 +371,8 @@ def force_error_vs_oracle(x0, box, torch, rows):
 def cpu_baseline(st, rows_n):
     """The CPU oracle (single thread, FP64, as it stands) on a bounded sample
     of the workload: one list build and K_REBUILD RBL force evaluations for
-    `rows_n` rows of the N = 1M state, plus the integrator over all N; the
-    per-row cost is scaled to atom-steps/s of the full system."""
+    `rows_n` rows of the N = 1M state; the per-row cost is scaled to
+    atom-steps/s of the full system."""
     import oracle
     rows = np.arange(0, N, max(1, N // rows_n), dtype=np.int64)[:rows_n]
     t0 = time.perf_counter()
@@ -396,6 +396,41 @@ def cpu_baseline(st, rows_n):
                    f"every {K_REBUILD} steps; single-threaded FP64 C"),
         "seconds": t_build + K_REBUILD * t_force,
     }
+
+
+def cpu_full_list(st, rows_n):
+    """The same oracle timing for the full Verlet list (direct truncation at
+    r_c), the comparator of the method."""
+    import oracle
+    rows = np.arange(0, N, max(1, N // rows_n), dtype=np.int64)[:rows_n]
+    t0 = time.perf_counter()
+    L = oracle.System(st.pos, st.box, RS, RC, SKIN).lists(rows=rows, kinds=("full",))
+    t_build = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for _ in range(K_REBUILD):
+        oracle.full_forces(st.pos, st.box, RC, L)
+    t_force = (time.perf_counter() - t0) / K_REBUILD
+    per_row_step = t_build / K_REBUILD / len(rows) + t_force / len(rows)
+    return {"value": 1.0 / per_row_step, "unit": "atom-steps/s", "cores": 1, "kind": "oracle",
+            "sample": (f"{len(rows)} rows: one full-list build ({t_build:.1f} s) and {K_REBUILD} "
+                       f"full-list force evaluations ({t_force * K_REBUILD:.1f} s), scaled per "
+                       f"atom-step; single-threaded FP64 C")}
+
+
+def method_error(x0, box):
+    """Relative L2 distance of the RBL force from the full-list force at the
+    same state (mean force subtracted, as in the MD loop) for each batch
+    size: the statistical error of the method itself, not an error of the
+    implementation."""
+    from paper_2105_04884_amd import Context
+    out = {}
+    with Context(N, precision="fp64", lists=("core", "shell", "full")) as ctx:
+        ctx.build(x0, box, RS, RC)
+        ff = ctx.full_forces(x0)
+        for P in (5, 10, 20):
+            f = ctx.forces(P, seed=1, step=0, pos=x0)
+            out[str(P)] = float((f - ff).norm() / ff.norm())
+    return out
 
 
 def _read_csv(folder, suffix):
@@ -531,6 +566,8 @@ def main():
     log("[bench] force error vs the FP64 oracle (sampled rows)")
     rows = np.random.default_rng(0).choice(N, size=2000, replace=False)
     errs = force_error_vs_oracle(x0, st.box, torch, rows)
+    log("[bench] method error of RBL against the full list")
+    merr = method_error(x0, st.box)
 
     # roofline of the dominant kernel of the headline variant (largest
     # share of the event-timed pass), and of the force kernel beside it
@@ -561,9 +598,11 @@ def main():
         extra["slab"] = run_slab(torch)
 
     cpu = None
+    cpu_full = None
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline")
         cpu = cpu_baseline(st, args.cpu_rows)
+        cpu_full = cpu_full_list(st, max(1, args.cpu_rows // 4))
 
     def speed(name):
         r = results.get(name)
@@ -601,6 +640,8 @@ def main():
         "speedup_rbl_mixed_vs_rbl_fp64": (speed("rbl_mixed_p10") / speed("rbl_fp64_p10")
                                           if speed("rbl_mixed_p10") and speed("rbl_fp64_p10") else None),
         "force_rel_l2_err_vs_fp64_oracle": errs,
+        "method_rel_l2_rbl_vs_full_list": merr,
+        "cpu_baseline_full_list": cpu_full,
         "workloads": extra,
     }
     print(json.dumps(line), flush=True)
