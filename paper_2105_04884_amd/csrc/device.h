@@ -79,7 +79,12 @@ __device__ __forceinline__ void floyd_draw(uint32_t (&S)[PMAX], uint64_t seed, u
                 w[1] = step;
                 w[2] = replica;
                 w[3] = (uint32_t)(m >> 2);
-                philox4x32_10(w[0], w[1], w[2], w[3], k0, k1);
+                // the key schedule is advanced round by round in SGPRs
+                // instead of being precomputed for all blocks (20 values that
+                // would be spilled); the empty asm marks the key as changed
+                uint32_t kk0 = k0, kk1 = k1;
+                asm volatile("" : "+s"(kk0), "+s"(kk1));
+                philox4x32_10(w[0], w[1], w[2], w[3], kk0, kk1);
             }
             const uint32_t u = w[m & 3];
             const uint32_t J = (uint32_t)(n - P + m);
