@@ -68,12 +68,14 @@ def load():
                                     _f64p, _f64p, _f64p]
     lib.orc_forces_full.restype = C.c_int
     lib.orc_mean_subtract.argtypes = [C.c_int64, _f64p, _f64p]
+    lib.orc_stencil_rows.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]
+    lib.orc_stencil_rows.restype = C.c_int
     lib.orc_erfc_pair.argtypes = [C.c_double, C.c_double, C.c_double,
                                   C.POINTER(C.c_double), C.POINTER(C.c_double)]
     lib.orc_md_run.argtypes = [C.c_int64, _f64p, _f64p, _f64p, C.c_double, C.c_double,
                                C.c_double, C.c_double, C.c_int64, C.c_int, C.c_uint64,
                                C.c_int64, C.c_int, C.c_int, C.c_int, C.c_int, C.c_uint32,
-                               C.c_void_p, C.c_double, _f64p, C.c_void_p]
+                               C.c_void_p, C.c_double, C.c_int, _f64p, C.c_void_p]
     lib.orc_md_run.restype = C.c_int
     _lib = lib
     return lib
@@ -216,6 +218,33 @@ class System:
                      offs[1], idxs[1] if idxs[1] is not None else empty,
                      offs[2], idxs[2] if idxs[2] is not None else empty)
 
+    def stencil_rows(self, rows=None):
+        """(off, idx): for each row all particles of the stencil cells around
+        its cell, itself included, in slot order (the paper's draw
+        population I, of size N_I)."""
+        rows_arr = (np.arange(self.n, dtype=np.int64) if rows is None
+                    else np.ascontiguousarray(rows, dtype=np.int64))
+        nrows = rows_arr.shape[0]
+        cnt = np.zeros(max(nrows, 1), dtype=np.int64)
+        rp = rows_arr.ctypes.data_as(C.c_void_p)
+        if self._lib.orc_stencil_rows(self._h, nrows, rp, cnt.ctypes.data_as(C.c_void_p), None):
+            raise ValueError("bad row index")
+        off = np.zeros(nrows + 1, dtype=np.int64)
+        off[1:] = np.cumsum(cnt[:nrows])
+        idx = np.zeros(int(off[-1]), dtype=np.int32)
+        r = self._lib.orc_stencil_rows(self._h, nrows, rp, off.ctypes.data_as(C.c_void_p),
+                                       idx.ctypes.data_as(C.c_void_p))
+        if r:
+            raise RuntimeError(f"orc_stencil_rows failed ({r})")
+        return off, idx
+
+    def stencil_lists(self, rows=None) -> Lists:
+        """Core rows as in lists(), shell rows replaced by the stencil rows:
+        the draw population of the paper's own form of eq. (4)."""
+        L = self.lists(rows=rows, kinds=("core",))
+        off, idx = self.stencil_rows(rows)
+        return Lists(L.rows, L.core_off, L.core_idx, off, idx, L.full_off, L.full_idx)
+
 
 # ---------------------------------------------------------------------------
 # forces and dynamics
@@ -274,7 +303,7 @@ def mean_subtract(f: np.ndarray):
 
 def md_run(pos, vel, box, rs, rc, skin, dt, nsteps, p=10, seed=1, step0=0, K=10,
            use_full=False, shift=True, momentum_fix=True, replica=0, want_ev=False,
-           charges=None, alpha: float = 0.0):
+           charges=None, alpha: float = 0.0, shell_source: str = "shell"):
     """Velocity-Verlet run (Algorithm 1, NVE).  Returns (pos, vel, force, ev)
     with ev of shape (nsteps+1, 2) = (U, W) per force evaluation or None."""
     lib = load()
@@ -285,7 +314,8 @@ def md_run(pos, vel, box, rs, rc, skin, dt, nsteps, p=10, seed=1, step0=0, K=10,
     q = _charges(charges, x.shape[1])
     r = lib.orc_md_run(x.shape[1], x, v, np.asarray(box, dtype=np.float64), rs, rc, skin, dt,
                        nsteps, p, seed, step0, K, int(use_full), int(shift), int(momentum_fix),
-                       replica, _ptr_or_null(q), float(alpha), f, _ptr_or_null(ev))
+                       replica, _ptr_or_null(q), float(alpha),
+                       {"shell": 0, "stencil": 1}[shell_source], f, _ptr_or_null(ev))
     if r:
         raise RuntimeError(f"orc_md_run failed ({r})")
     return x, v, f, ev

@@ -37,6 +37,11 @@
  *                       Fig. 1); brute force is the plain definition.
  *   orc_forces_rbl      F_i = F_ic + (n/p) sum_{B(i)} f~_ij, eq. (3) and
  *                       eq. (4); small shells (n <= p) taken whole.
+ *   orc_stencil_rows    the paper's own draw population: every particle of
+ *                       the stencil cells around i's cell, i included, N_I of
+ *                       them (Sec. II, Fig. 1); with these rows in place of
+ *                       the shell rows, orc_forces_rbl is eq. (4) with N_I/p
+ *                       and f~_ij = 0 outside the shell zone.
  *   orc_mean_subtract   subtraction of the average net force (Sec. II,
  *                       Algorithm 1, F_cor of Appendix A).
  *   orc_md_run          Algorithm 1 with velocity Verlet (NVE).
@@ -487,6 +492,54 @@ int orc_list_fill(const orc_sys* s, int method, int64_t nrows, const int64_t* ro
     return 0;
 }
 
+/* Stencil rows: for each requested row (all when rows == NULL) the IDs of
+ * all particles in the stencil cells of its cell (the 5 x 5 x 5 block, each
+ * cell once when an axis has fewer than 5 cells), the particle itself
+ * included, in ascending slot order.  With idx == NULL only the counts are
+ * written to off[k] (length nrows); otherwise off holds the nrows + 1 CSR
+ * offsets and idx is filled. */
+int orc_stencil_rows(const orc_sys* s, int64_t nrows, const int64_t* rows, int64_t* off,
+                     int32_t* idx)
+{
+    int64_t cap = 64;
+    int64_t* buf = (int64_t*)malloc(sizeof(int64_t) * (size_t)cap);
+    for (int64_t k = 0; k < nrows; ++k) {
+        int64_t i = rows ? rows[k] : k;
+        if (i < 0 || i >= s->n) { free(buf); return -1; }
+        int64_t ci = s->cell_of[i];
+        int cx = (int)(ci % s->ncell[0]);
+        int cy = (int)((ci / s->ncell[0]) % s->ncell[1]);
+        int cz = (int)(ci / ((int64_t)s->ncell[0] * s->ncell[1]));
+        int sx[5], sy[5], sz[5];
+        int nx = stencil_axis(cx, s->ncell[0], sx);
+        int ny = stencil_axis(cy, s->ncell[1], sy);
+        int nz = stencil_axis(cz, s->ncell[2], sz);
+        int64_t m = 0;
+        for (int a = 0; a < nz; ++a)
+            for (int b = 0; b < ny; ++b)
+                for (int c = 0; c < nx; ++c) {
+                    int64_t cell = ((int64_t)sz[a] * s->ncell[1] + sy[b]) * s->ncell[0] + sx[c];
+                    for (int64_t q = s->cell_start[cell]; q < s->cell_start[cell + 1]; ++q) {
+                        if (m == cap) {
+                            cap *= 2;
+                            buf = (int64_t*)realloc(buf, sizeof(int64_t) * (size_t)cap);
+                        }
+                        buf[m++] = s->id_of[q];
+                    }
+                }
+        if (!idx) {
+            off[k] = m;
+            continue;
+        }
+        if (off[k + 1] - off[k] != m) { free(buf); return -2; }
+        g_sort_sys = s;
+        qsort(buf, (size_t)m, sizeof(int64_t), cmp_slot);
+        for (int64_t q = 0; q < m; ++q) idx[off[k] + q] = (int32_t)buf[q];
+    }
+    free(buf);
+    return 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Forces.  Positions `pos` ([3][n]) are the current ones (not necessarily
  * the ones the lists were built at); every pair is classified by its current
@@ -612,7 +665,7 @@ static void free_lists(orc_lists* L)
 }
 
 static int build_all(int64_t n, double* pos, const double box[3], double rs, double rc,
-                     double skin, int use_full, orc_lists* L)
+                     double skin, int use_full, int stencil, orc_lists* L)
 {
     free_lists(L);
     orc_wrap(n, pos, box);
@@ -634,8 +687,20 @@ static int build_all(int64_t n, double* pos, const double box[3], double rs, dou
         L->core_idx = (int32_t*)malloc(sizeof(int32_t) * (size_t)(L->core_off[n] + 1));
         L->shell_idx = (int32_t*)malloc(sizeof(int32_t) * (size_t)(L->shell_off[n] + 1));
     }
-    int rcode = orc_list_fill(s, 0, n, NULL, L->core_off, L->core_idx, L->shell_off,
-                              L->shell_idx, L->full_off, L->full_idx);
+    int rcode = orc_list_fill(s, 0, n, NULL, L->core_off, L->core_idx,
+                              stencil ? NULL : L->shell_off, stencil ? NULL : L->shell_idx,
+                              L->full_off, L->full_idx);
+    if (!rcode && stencil && !use_full) {
+        /* the draw population is the stencil cells (the paper's own form) */
+        int64_t* cnt = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+        orc_stencil_rows(s, n, NULL, cnt, NULL);
+        L->shell_off[0] = 0;
+        for (int64_t i = 0; i < n; ++i) L->shell_off[i + 1] = L->shell_off[i] + cnt[i];
+        free(cnt);
+        free(L->shell_idx);
+        L->shell_idx = (int32_t*)malloc(sizeof(int32_t) * (size_t)(L->shell_off[n] + 1));
+        rcode = orc_stencil_rows(s, n, NULL, L->shell_off, L->shell_idx);
+    }
     orc_sys_free(s);
     return rcode;
 }
@@ -652,7 +717,7 @@ int orc_md_run(int64_t n, double* pos, double* vel, const double box[3],
                double rs, double rc, double skin, double dt, int64_t nsteps,
                int p, uint64_t seed, int64_t step0, int K, int use_full,
                int shift, int momentum_fix, uint32_t replica,
-               const double* charge, double alpha, double* force_out, double* ev_out)
+               const double* charge, double alpha, int stencil, double* force_out, double* ev_out)
 {
     if (K < 1 || n < 1) return -1;
     orc_lists L = {0};
@@ -669,7 +734,7 @@ int orc_md_run(int64_t n, double* pos, double* vel, const double box[3],
             for (int64_t i = 0; i < 3 * n; ++i) pos[i] = pos[i] + dt * vel[i];
         }
         if (it == 0 || s % K == 0) {
-            rcode = build_all(n, pos, box, rs, rc, skin, use_full, &L);
+            rcode = build_all(n, pos, box, rs, rc, skin, use_full, stencil, &L);
             if (rcode) break;
         }
         if (use_full) {

@@ -517,3 +517,102 @@ def test_charged_nve_energy_conservation():
     e0 = ev0[0, 0] + 0.5 * float(np.sum(st.vel ** 2))
     e1 = ev[-1, 0] + 0.5 * float(np.sum(v ** 2))
     assert abs(e1 - e0) < 2e-4 * abs(e0)
+
+
+# ------------------------------------- the paper's stencil-cell population ---
+
+def _cell_coords(S):
+    """Cell coordinates of every particle, from the binning's slot order and
+    cell starts (not from the position formula)."""
+    ncell, _, slot, cs = S.binning()
+    cell = np.searchsorted(cs, slot, side="right") - 1
+    nx, ny = int(ncell[0]), int(ncell[1])
+    return ncell, slot, np.stack([cell % nx, (cell // nx) % ny, cell // (nx * ny)])
+
+
+@pytest.mark.parametrize("n,rho,seed", [(3000, 0.8442, 13), (1000, 0.8, 1)])
+def test_stencil_rows_are_the_stencil_cells(n, rho, seed):
+    """Row i holds every particle whose cell is within two cells of i's cell
+    along each axis (periodically; the whole axis when it has 5 cells or
+    fewer), i itself included, in slot order (Sec. II, the stencil I)."""
+    st = inputs.lj_fluid(n, rho, 1.0, seed=seed)
+    S = oracle.System(st.pos, st.box, RS, RC, SKIN)
+    ncell, slot, cc = _cell_coords(S)
+    rows = np.arange(0, n, 97)
+    off, idx = S.stencil_rows(rows)
+    for k, i in enumerate(rows):
+        ok = np.ones(n, dtype=bool)
+        for a in range(3):
+            if ncell[a] > 5:
+                d = np.abs(cc[a] - cc[a, i])
+                ok &= np.minimum(d, ncell[a] - d) <= 2
+        want = np.nonzero(ok)[0]
+        want = want[np.argsort(slot[want])]
+        assert np.array_equal(idx[off[k]:off[k + 1]], want)
+        assert i in idx[off[k]:off[k + 1]]
+
+
+def test_stencil_rows_contain_the_shell_rows():
+    st = inputs.lj_fluid(3000, 0.8442, 1.0, seed=14)
+    S = oracle.System(st.pos, st.box, RS, RC, SKIN)
+    rows = np.arange(0, 3000, 41)
+    L = S.lists(rows=rows, kinds=("shell",))
+    off, idx = S.stencil_rows(rows)
+    for k in range(len(rows)):
+        assert set(L.row("shell", k)) <= set(idx[off[k]:off[k + 1]])
+        assert off[k + 1] - off[k] > len(L.row("shell", k))
+
+
+def test_stencil_rbl_unbiased_with_exact_srswor_variance():
+    """The paper's form of eq. (4), drawing from the stencil cells with
+    N_I/p: unbiased, and the variance over 3000 seeds equals the exact
+    without-replacement variance N_I (N_I - p) S^2 / p with zero terms for
+    the population members outside the shell zone (Appendix A)."""
+    p = 10
+    st = inputs.lj_fluid(3000, 0.8442, 1.0, seed=15)
+    S = oracle.System(st.pos, st.box, RS, RC, SKIN)
+    rows = np.arange(0, 3000, 101)
+    L = S.stencil_lists(rows=rows)
+    seeds = 3000
+    samples = np.zeros((seeds, 3, len(rows)))
+    for s in range(seeds):
+        samples[s], _, _ = oracle.rbl_forces(st.pos, st.box, RS, RC, L, p, seed=5000 + s, step=0)
+    exact_var = np.zeros((3, len(rows)))
+    for k in range(len(rows)):
+        t = _shell_terms(st, L, k)
+        n = t.shape[0]
+        exact_var[:, k] = n * (n - p) * t.var(axis=0, ddof=1) / p
+    full, _, _ = oracle.full_forces(st.pos, st.box, RC, S.lists(rows=rows, kinds=("full",)))
+    mean = samples.mean(axis=0)
+    sem = np.sqrt(exact_var / seeds)
+    z = (mean - full) / np.where(sem > 0, sem, 1.0)
+    assert np.all(np.abs(z[sem > 0]) < 5.0)
+    ratio = samples.var(axis=0, ddof=1).sum() / exact_var.sum()
+    assert abs(ratio - 1.0) < 0.08, ratio
+    # the stencil draw has the larger variance: it spends draws off the shell
+    Ls = S.lists(rows=rows, kinds=("shell",))
+    shell_var = sum(np.diff(Ls.shell_off)[k] * (np.diff(Ls.shell_off)[k] - p)
+                    * _shell_terms(st, Ls, k).var(axis=0, ddof=1).sum() / p for k in range(len(rows)))
+    assert exact_var.sum() > shell_var
+
+
+def test_stencil_rbl_with_full_batch_equals_full():
+    """p >= N_I: every member of the stencil, unscaled; those outside the
+    shell zone add zero, so core + shell is the truncation at rc."""
+    st = inputs.small_fluid(seed=16)
+    S = oracle.System(st.pos, st.box, RS, RC, SKIN)
+    L = S.stencil_lists()
+    p = int(np.diff(L.shell_off).max())
+    fr, _, _ = oracle.rbl_forces(st.pos, st.box, RS, RC, L, p, seed=1, step=0)
+    ff, _, _ = oracle.full_forces(st.pos, st.box, RC, S.lists(kinds=("full",)))
+    assert np.abs(fr - ff).max() < 1e-12 * np.abs(ff).max()
+
+
+def test_stencil_md_conserves_momentum_and_differs_from_shell_draws():
+    st = inputs.lj_fluid(3000, 0.8442, 1.0, seed=17)
+    x, v, _, _ = oracle.md_run(st.pos, st.vel, st.box, RS, RC, SKIN, 0.005, 20, p=10, seed=2,
+                               K=10, shell_source="stencil")
+    assert np.abs(v.sum(axis=1) - st.vel.sum(axis=1)).max() < 1e-9
+    x2, _, _, _ = oracle.md_run(st.pos, st.vel, st.box, RS, RC, SKIN, 0.005, 20, p=10, seed=2,
+                                K=10, shell_source="shell")
+    assert not np.array_equal(x, x2)
