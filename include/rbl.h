@@ -55,6 +55,7 @@ typedef enum rbl_status {
 enum { RBL_PREC_FP64 = 0, RBL_PREC_MIXED = 1 };
 enum { RBL_PAIR_LJ = 0, RBL_PAIR_LJ_ERFC = 1 };
 enum { RBL_LIST_CORE = 1, RBL_LIST_SHELL = 2, RBL_LIST_FULL = 4 };
+enum { RBL_SHELL_LIST = 0, RBL_SHELL_STENCIL = 1 };
 
 /* Largest batch size P accepted by rbl_forces, rbl_step and
  * rbl_export_batches. */
@@ -99,6 +100,16 @@ typedef struct rbl_config {
     const int64_t* replica_offsets; /* host, n_replicas + 1 prefix offsets into the particle
                                        arrays; NULL when n_replicas == 1 */
     const double* charges;     /* device, n charges in caller order, or NULL (all zero) */
+    int32_t shell_source;      /* population each batch is drawn from, eq. (4):
+                                  RBL_SHELL_LIST (default): the particle's shell row,
+                                  n_i = its length;
+                                  RBL_SHELL_STENCIL: every particle of the 5x5x5 stencil
+                                  cells around the particle's cell, itself included (the
+                                  form of Sec. II), n_i = N_I of that cell; partners
+                                  outside [r_s, r_c) add zero.  Batches are then always
+                                  drawn at the list build (predraw is implied) and no
+                                  shell row is needed by rbl_forces or rbl_step. */
+    int32_t reserved;          /* must be 0 */
 } rbl_config;
 
 /* Fills *cfg with the defaults above for n particles in one replica. */
@@ -132,14 +143,16 @@ rbl_status rbl_build(rbl_ctx* ctx, const double* pos, const double* box,
  * positions of the last build), eq. (3) + eq. (4):
  *   F_i = sum_{j in core, r < r_s} f_ij
  *       + (n_i/P) sum_{j in B_i, r_s <= r < r_c} f_ij
- * where B_i is P shell candidates drawn without replacement (Floyd's
- * algorithm on Philox4x32-10, key = seed, counter = (replica-local particle
- * ID, step mod 2^32, replica, block)); when n_i <= P the whole shell is used
- * unscaled.  With momentum_fix the average net force of each replica is
+ * where B_i is P members of the draw population (cfg.shell_source: the
+ * shell row, or all particles of the stencil cells) drawn without
+ * replacement (Floyd's algorithm on Philox4x32-10, key = seed, counter =
+ * (replica-local particle ID, step mod 2^32, replica, block)); when
+ * n_i <= P the whole population is used unscaled.  With momentum_fix the average net force of each replica is
  * subtracted afterwards.  force: device SoA [3][n] (written).  ev: device,
  * 2 doubles per replica (potential energy U, virial W = sum over pairs of
  * r.f, both with the same estimator), or NULL.  1 <= P <= RBL_MAX_P.
- * Errors: RBL_E_ARG, RBL_E_STATE (no build, or the build has no shell list).
+ * Errors: RBL_E_ARG, RBL_E_STATE (no build, or the build has no core list,
+ * or, with RBL_SHELL_LIST, no shell list).
  */
 rbl_status rbl_forces(rbl_ctx* ctx, int P, uint64_t seed, uint64_t step,
                       const double* pos, double* force, double* ev);
@@ -185,7 +198,8 @@ rbl_status rbl_export_lists(rbl_ctx* ctx, int64_t nrows, const int64_t* rows,
 
 /* The batches rbl_forces would draw: batch[k*P + m] = ID of the m-th drawn
  * partner of particle rows[k] (in increasing batch position), -1 past
- * count[k] = min(n_i, P). */
+ * count[k] = min(n_i, P).  With RBL_SHELL_STENCIL, n_i is N_I and the
+ * partners are stencil particles (the particle itself among them). */
 rbl_status rbl_export_batches(rbl_ctx* ctx, int P, uint64_t seed, uint64_t step,
                               int64_t nrows, const int64_t* rows,
                               int32_t* batch, int32_t* count);

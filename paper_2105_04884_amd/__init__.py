@@ -82,7 +82,8 @@ class Context:
                  predraw: bool = True, graphs: bool = True, lanes: int = 0, persistent: int = 0,
                  capacity_factor: float = 1.25,
                  replica_offsets=None,
-                 pair: str = "lj", alpha: float = 0.0, charges=None, stream=None):
+                 pair: str = "lj", alpha: float = 0.0, charges=None, shell_source: str = "shell",
+                 stream=None):
         torch = _torch()
         lib = _lib.load()
         cfg = _lib.Config()
@@ -102,6 +103,7 @@ class Context:
         cfg.lanes = int(lanes)
         cfg.persistent = int(persistent)
         cfg.capacity_factor = float(capacity_factor)
+        cfg.shell_source = {"shell": _lib.SHELL_LIST, "stencil": _lib.SHELL_STENCIL}[shell_source]
         self._offsets = None
         if replica_offsets is not None:
             self._offsets = np.ascontiguousarray(replica_offsets, dtype=np.int64)

@@ -393,20 +393,20 @@ struct AxisRuns {
     int p0, l0, p1, l1;
 };
 
-__device__ __forceinline__ AxisRuns axis_runs(int c, int nc)
+__device__ __forceinline__ AxisRuns axis_runs(int c, int nc, int h = 2)
 {
     AxisRuns a;
-    if (nc <= 5) {
+    if (nc <= 2 * h + 1) {
         a.p0 = 0;
         a.l0 = nc;
         a.p1 = 0;
         a.l1 = 0;
         return a;
     }
-    const int lo = c - 2, hi = c + 2;
+    const int lo = c - h, hi = c + h;
     if (lo >= 0 && hi <= nc - 1) {
         a.p0 = lo;
-        a.l0 = 5;
+        a.l0 = 2 * h + 1;
         a.p1 = 0;
         a.l1 = 0;
     } else if (lo < 0) {
@@ -599,6 +599,9 @@ struct FusedArgs {
     int P;
     int cap_list;              // LDS shell-list room per centre particle (<= 0: all candidates)
     int list_budget;           // LDS list entries per wavefront (dynamic LDS of the launch)
+    // stencil draw population only:
+    double core_reach;         // r_s + skin: 3 x 3 x 3 cells hold the core when it fits a cell
+    int draw_only;             // 1: batches and population sizes only, core rows untouched
 };
 
 __device__ __forceinline__ void wave_lds_fence()
@@ -636,25 +639,34 @@ __device__ __forceinline__ void wave_lds_fence()
 //    the budget being set by the host from the shell counts it has seen
 //    (dynamic LDS); a room beyond the budget (or a run beyond 1023) raises
 //    kFlagStencil and the host redoes the run on explicit lists;
-//  - centre cells are mapped to blocks so that each XCD works on a
-//    contiguous range of cells (its L2 keeps the neighbourhood).
+//  - centre cells are mapped to blocks by xcd_tile, so that each XCD works
+//    on runs of neighbouring cells (its L2 keeps the neighbourhood).
+// STENCIL = true draws from the paper's own population instead (Sec. II):
+// all N_I particles of the stencil cells, the centre particle included,
+// scaled by N_I/P in eq. (4), with the pair term zero outside the shell
+// zone.  N_I is the same for every particle of a cell, so no shell list is
+// kept: the k-th stencil particle is found by a binary search over the run
+// prefix counts.  The core test then walks only the 3 x 3 x 3 cells around
+// the centre cell when r_s + skin fits one cell edge (else the 5 x 5 x 5
+// stencil), and with draw_only set the kernel writes just the batches and
+// N_I (the batch export and single force evaluations of a build).
 struct AxisRunsS {
     int p0, l0, p1, l1;
     int s0, s1;  // image shift (in box lengths, added to x_i - x_j) of run 0 / run 1
 };
 
-__device__ __forceinline__ AxisRunsS axis_runs_s(int c, int nc)
+__device__ __forceinline__ AxisRunsS axis_runs_s(int c, int nc, int h = 2)
 {
     AxisRunsS a;
-    const AxisRuns b = axis_runs(c, nc);
+    const AxisRuns b = axis_runs(c, nc, h);
     a.p0 = b.p0;
     a.l0 = b.l0;
     a.p1 = b.p1;
     a.l1 = b.l1;
     a.s0 = 0;
     a.s1 = 0;
-    if (nc > 5) {
-        const int lo = c - 2, hi = c + 2;
+    if (nc > 2 * h + 1) {
+        const int lo = c - h, hi = c + h;
         if (lo < 0) {
             a.s1 = 1;   // cells lo+nc..nc-1 are images one box below
         } else if (hi > nc - 1) {
@@ -714,7 +726,7 @@ constexpr int kListBudgetMin = 3072;  // 16-bit shell-list entries per wavefront
 constexpr int kListBudgetMax = 6912;  // at most (the block's LDS stays within 64 KB)
 constexpr int kRunOffBits = 10;    // list entry = run << 10 | offset in the run
 
-template <int PMAX>
+template <int PMAX, bool STENCIL>
 __global__ __launch_bounds__(256) void k_build_draw(FusedArgs fa)
 {
     __shared__ double4 s_ctr[4][kCtrMax];
@@ -722,6 +734,10 @@ __global__ __launch_bounds__(256) void k_build_draw(FusedArgs fa)
     __shared__ int s_rpre[4][64];
     __shared__ int s_rshift[4][64];
     __shared__ int s_ncnt[4][kCtrMax];
+    // STENCIL: run table of the core test (3 x 3 x 3 cells when they reach)
+    __shared__ int s_crstart[STENCIL ? 4 : 1][64];
+    __shared__ int s_crpre[STENCIL ? 4 : 1][64];
+    __shared__ int s_crshift[STENCIL ? 4 : 1][64];
     // per wavefront: list_budget entries + a write-off word per lane
     extern __shared__ unsigned short s_dyn[];
     const BuildArgs& a = fa.b;
@@ -751,13 +767,17 @@ __global__ __launch_bounds__(256) void k_build_draw(FusedArgs fa)
     const int cy = (int)((lc / nc0) % nc1);
     const int cz = (int)(lc / ((int64_t)nc0 * nc1));
     const bool SHIFT = nc0 >= 7 && nc1 >= 7 && nc2 >= 7;  // image of every run known
-    const AxisRunsS ax = axis_runs_s(cx, nc0);
-    const AxisRunsS ay = axis_runs_s(cy, nc1);
-    const AxisRunsS az = axis_runs_s(cz, nc2);
-    const int ny_s = ay.l0 + ay.l1;
-    const int nz_s = az.l0 + az.l1;
-    int rstart = 0, rlen = 0, rshift = 0;
-    {
+    // runs of the stencil of half-width h around the cell: lane q holds run
+    // q (z-row, y-row, x-part) as slot start, length and image-shift code
+    auto run_table = [&](int h, int& rstart, int& rlen, int& rshift) {
+        const AxisRunsS ax = axis_runs_s(cx, nc0, h);
+        const AxisRunsS ay = axis_runs_s(cy, nc1, h);
+        const AxisRunsS az = axis_runs_s(cz, nc2, h);
+        const int ny_s = ay.l0 + ay.l1;
+        const int nz_s = az.l0 + az.l1;
+        rstart = 0;
+        rlen = 0;
+        rshift = 0;
         const int q = lane;
         const int zi = q / (2 * ny_s);
         const int yi = (q >> 1) % ny_s;
@@ -779,17 +799,37 @@ __global__ __launch_bounds__(256) void k_build_draw(FusedArgs fa)
             const int sz = axis_shift(az, zi);
             rshift = (sx + 1) | ((sy + 1) << 2) | ((sz + 1) << 4);
         }
-    }
+    };
+    int rstart, rlen, rshift;
+    run_table(2, rstart, rlen, rshift);
     const int incl = wave_incl_scan(rlen);
     const int total = rfl(__builtin_amdgcn_readlane(incl, 63));
     const int rpre = incl - rlen;
     s_rstart[w][lane] = rstart;
     s_rpre[w][lane] = rpre;
     s_rshift[w][lane] = rshift;
+    // the table the core test walks: the stencil's own, or (STENCIL, when
+    // r_s + skin fits one cell edge with the cell grid's margin) the
+    // 3 x 3 x 3 cells around the centre cell
+    int ctotal = total;
+    if constexpr (STENCIL) {
+        const double edge = fmin(L0 / nc0, fmin(L1 / nc1, L2 / nc2));
+        const int hc = fa.core_reach * (1.0 + 1e-6) <= edge ? 1 : 2;
+        int cs, cl, csh;
+        run_table(hc, cs, cl, csh);
+        const int cincl = wave_incl_scan(cl);
+        ctotal = rfl(__builtin_amdgcn_readlane(cincl, 63));
+        s_crstart[w][lane] = cs;
+        s_crpre[w][lane] = cincl - cl;
+        s_crshift[w][lane] = csh;
+    }
+    auto t_start = [&](int q) { if constexpr (STENCIL) return s_crstart[w][q]; else return s_rstart[w][q]; };
+    auto t_pre = [&](int q) { if constexpr (STENCIL) return s_crpre[w][q]; else return s_rpre[w][q]; };
+    auto t_shift = [&](int q) { if constexpr (STENCIL) return s_crshift[w][q]; else return s_rshift[w][q]; };
     // list room per centre particle: the host's bound on shell counts (a
     // particle beyond it raises the overflow flag), never above the stencil
     const int cap = (fa.cap_list > 0 && fa.cap_list < total) ? fa.cap_list : max(total, 1);
-    if (cap > budget || wave_max(rlen) >= (1 << kRunOffBits)) {
+    if (!STENCIL && (cap > budget || wave_max(rlen) >= (1 << kRunOffBits))) {
         // the host repeats the run on explicit rows; until it does, this
         // cell's particles have empty rows, so no force kernel of the run
         // reads a batch entry or core row that was never written
@@ -803,9 +843,10 @@ __global__ __launch_bounds__(256) void k_build_draw(FusedArgs fa)
         }
         return;
     }
-    const int nch = (total + 63) >> 6;  // >= 1: the cell itself is in the stencil
-    const int gmax = min(kCtrMax, budget / cap);  // >= 1
+    const int nch = (ctotal + 63) >> 6;  // >= 1: the cell itself is in the table
+    const int gmax = STENCIL ? kCtrMax : min(kCtrMax, budget / cap);  // >= 1
     const int P = fa.P;
+    const bool do_core = !STENCIL || !fa.draw_only;
     wave_lds_fence();
 
     int qrun = 0;  // this lane's current run (its candidate index only grows)
@@ -816,13 +857,13 @@ __global__ __launch_bounds__(256) void k_build_draw(FusedArgs fa)
         code = 1 | (1 << 2) | (1 << 4);
         ent = 0;
         xj = make_double4(1.0e30, 1.0e30, 1.0e30, 0.0);
-        if (f < total) {
-            while (qrun < 63 && s_rpre[w][qrun + 1] <= f) ++qrun;
-            const int off = f - s_rpre[w][qrun];
-            const int jj = s_rstart[w][qrun] + off;
+        if (f < ctotal) {
+            while (qrun < 63 && t_pre(qrun + 1) <= f) ++qrun;
+            const int off = f - t_pre(qrun);
+            const int jj = t_start(qrun) + off;
             if (jj >= 0 && (int64_t)jj < a.n_slots) {
                 j = jj;
-                code = s_rshift[w][qrun];
+                code = t_shift(qrun);
                 ent = (qrun << kRunOffBits) | off;
                 xj = a.xs[jj];
             } else {
@@ -833,91 +874,95 @@ __global__ __launch_bounds__(256) void k_build_draw(FusedArgs fa)
 
     for (int g0 = 0; g0 < m; g0 += gmax) {
         const int mg = rfl(min(gmax, m - g0));
-        if (lane < mg) s_ctr[w][lane] = a.xs[i0 + g0 + lane];
-        wave_lds_fence();
-        qrun = 0;
-        int cnt_core = 0;
-        uint32_t nshell = 0;  // lane ii: shell candidates of centre ii so far
         const int my_slot = i0 + g0 + lane;
-        int jn, coden, entn;
-        double4 xn;
-        candidate(lane, jn, xn, coden, entn);
-        // the first chunk's candidates are complete before the chunk loop:
-        // with nothing of this load pending at the loop head, the inner loop
-        // waits on no vector-memory counter, and each chunk's prefetch of the
-        // next one overlaps with its tests
-        __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
-        for (int ch = 0; ch < nch; ++ch) {
-            const int jc = jn;
-            const double4 xc = xn;
-            const int code = coden;
-            const int ent = entn;
-            if (ch + 1 < nch) candidate((ch + 1) * 64 + lane, jn, xn, coden, entn);
-            uint32_t mclo = 0, mchi = 0;
-            // one centre particle against the chunk: core ballot to lane ii,
-            // shell candidates appended to its LDS list
-            auto test = [&](int ii, double dx, double dy, double dz) {
-                const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-                const uint64_t other = ~__ballot(jc == i0 + g0 + ii);
-                const uint64_t mc = other & __ballot(r2 < a.thr_core);
-                const uint64_t ms = other & __ballot(r2 >= a.thr_shell_in) & __ballot(r2 < a.thr_out);
-                write_lane2(mclo, mchi, (uint32_t)mc, (uint32_t)(mc >> 32), ii);
-                const int base = rfl((int)__builtin_amdgcn_readlane((int)nshell, ii));
-                // every lane writes (no branch): a selected lane to its list
-                // position (clamped into the room; an overflowing run is
-                // repeated by the host), the others to their write-off word
-                const int pos = ii * cap + min(base + (int)mbcnt(ms), cap - 1);
-                s_lst[select_lanes(ms, pos, budget + lane)] = (unsigned short)ent;
-                nshell = (uint32_t)rbl_writelane(base + (int)__popcll(ms), ii, (int)nshell);
-            };
-            constexpr int kNoShift = 1 | (1 << 2) | (1 << 4);
-            if (SHIFT && __ballot(code != kNoShift) == 0) {
-                // no periodic image in the chunk: (x_i - x_j) + 0 is x_i - x_j
-                for (int ii = 0; ii < mg; ++ii) {
-                    const double4 xi = s_ctr[w][ii];
-                    test(ii, xi.x - xc.x, xi.y - xc.y, xi.z - xc.z);
+        uint32_t nshell = 0;  // lane ii: shell candidates of centre ii so far
+        if (do_core) {
+            if (lane < mg) s_ctr[w][lane] = a.xs[i0 + g0 + lane];
+            wave_lds_fence();
+            qrun = 0;
+            int cnt_core = 0;
+            int jn, coden, entn;
+            double4 xn;
+            candidate(lane, jn, xn, coden, entn);
+            // the first chunk's candidates are complete before the chunk loop:
+            // with nothing of this load pending at the loop head, the inner loop
+            // waits on no vector-memory counter, and each chunk's prefetch of the
+            // next one overlaps with its tests
+            __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+            for (int ch = 0; ch < nch; ++ch) {
+                const int jc = jn;
+                const double4 xc = xn;
+                const int code = coden;
+                const int ent = entn;
+                if (ch + 1 < nch) candidate((ch + 1) * 64 + lane, jn, xn, coden, entn);
+                uint32_t mclo = 0, mchi = 0;
+                // one centre particle against the chunk: core ballot to lane ii,
+                // shell candidates appended to its LDS list
+                auto test = [&](int ii, double dx, double dy, double dz) {
+                    const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+                    const uint64_t other = ~__ballot(jc == i0 + g0 + ii);
+                    const uint64_t mc = other & __ballot(r2 < a.thr_core);
+                    write_lane2(mclo, mchi, (uint32_t)mc, (uint32_t)(mc >> 32), ii);
+                    if constexpr (STENCIL) return;
+                    const uint64_t ms = other & __ballot(r2 >= a.thr_shell_in) & __ballot(r2 < a.thr_out);
+                    const int base = rfl((int)__builtin_amdgcn_readlane((int)nshell, ii));
+                    // every lane writes (no branch): a selected lane to its list
+                    // position (clamped into the room; an overflowing run is
+                    // repeated by the host), the others to their write-off word
+                    const int pos = ii * cap + min(base + (int)mbcnt(ms), cap - 1);
+                    s_lst[select_lanes(ms, pos, budget + lane)] = (unsigned short)ent;
+                    nshell = (uint32_t)rbl_writelane(base + (int)__popcll(ms), ii, (int)nshell);
+                };
+                constexpr int kNoShift = 1 | (1 << 2) | (1 << 4);
+                if (SHIFT && __ballot(code != kNoShift) == 0) {
+                    // no periodic image in the chunk: (x_i - x_j) + 0 is x_i - x_j
+                    for (int ii = 0; ii < mg; ++ii) {
+                        const double4 xi = s_ctr[w][ii];
+                        test(ii, xi.x - xc.x, xi.y - xc.y, xi.z - xc.z);
+                    }
+                } else if (SHIFT) {
+                    const double shx = (double)((code & 3) - 1) * L0;
+                    const double shy = (double)(((code >> 2) & 3) - 1) * L1;
+                    const double shz = (double)(((code >> 4) & 3) - 1) * L2;
+                    for (int ii = 0; ii < mg; ++ii) {
+                        const double4 xi = s_ctr[w][ii];
+                        test(ii, (xi.x - xc.x) + shx, (xi.y - xc.y) + shy, (xi.z - xc.z) + shz);
+                    }
+                } else {
+                    for (int ii = 0; ii < mg; ++ii) {
+                        const double4 xi = s_ctr[w][ii];
+                        test(ii, min_image(xi.x - xc.x, L0, iL0), min_image(xi.y - xc.y, L1, iL1),
+                             min_image(xi.z - xc.z, L2, iL2));
+                    }
                 }
-            } else if (SHIFT) {
-                const double shx = (double)((code & 3) - 1) * L0;
-                const double shy = (double)(((code >> 2) & 3) - 1) * L1;
-                const double shz = (double)(((code >> 4) & 3) - 1) * L2;
-                for (int ii = 0; ii < mg; ++ii) {
-                    const double4 xi = s_ctr[w][ii];
-                    test(ii, (xi.x - xc.x) + shx, (xi.y - xc.y) + shy, (xi.z - xc.z) + shz);
-                }
-            } else {
-                for (int ii = 0; ii < mg; ++ii) {
-                    const double4 xi = s_ctr[w][ii];
-                    test(ii, min_image(xi.x - xc.x, L0, iL0), min_image(xi.y - xc.y, L1, iL1),
-                         min_image(xi.z - xc.z, L2, iL2));
+                uint64_t mcore = ((uint64_t)mchi << 32) | mclo;
+                if (lane >= mg) mcore = 0;
+                while (__ballot(mcore != 0)) {
+                    const int b = mcore ? (int)__builtin_ctzll(mcore) : 0;
+                    const int jb = shfl_i32(jc, b);
+                    if (mcore) {
+                        if (cnt_core < a.cap_core) a.core[ell(my_slot, cnt_core, a.cap_core)] = jb;
+                        ++cnt_core;
+                        mcore &= mcore - 1;
+                    }
                 }
             }
-            uint64_t mcore = ((uint64_t)mchi << 32) | mclo;
-            if (lane >= mg) mcore = 0;
-            while (__ballot(mcore != 0)) {
-                const int b = mcore ? (int)__builtin_ctzll(mcore) : 0;
-                const int jb = shfl_i32(jc, b);
-                if (mcore) {
-                    if (cnt_core < a.cap_core) a.core[ell(my_slot, cnt_core, a.cap_core)] = jb;
-                    ++cnt_core;
-                    mcore &= mcore - 1;
-                }
+            if (lane < mg) a.core_len[my_slot] = min(cnt_core, a.cap_core);
+            const int mxc = wave_max(lane < mg ? cnt_core : 0);
+            const int mxs = STENCIL ? 0 : wave_max(lane < mg ? (int)nshell : 0);
+            if (lane == 0) {
+                raise_max(&a.flags[kFlagMaxCore], mxc);
+                if (!STENCIL) raise_max(&a.flags[kFlagMaxShell], mxs);
+                if (mxc > a.cap_core || mxs > cap) raise_flag(&a.flags[kFlagOverflow]);
             }
         }
-        const int ns = lane < mg ? (int)nshell : 0;
+        // the draw population: the particle's shell list, or N_I
+        const int ns = STENCIL ? total : (lane < mg ? (int)nshell : 0);
         if (lane < mg) {
-            a.core_len[my_slot] = min(cnt_core, a.cap_core);
             a.shell_len[my_slot] = ns;
-            s_ncnt[w][lane] = ns;
+            if (!STENCIL) s_ncnt[w][lane] = ns;
         }
         wave_lds_fence();
-        const int mxc = wave_max(lane < mg ? cnt_core : 0);
-        const int mxs = wave_max(ns);
-        if (lane == 0) {
-            raise_max(&a.flags[kFlagMaxCore], mxc);
-            raise_max(&a.flags[kFlagMaxShell], mxs);
-            if (mxc > a.cap_core || mxs > cap) raise_flag(&a.flags[kFlagOverflow]);
-        }
         // batches: one lane per (particle, step) pair; the k-th shell
         // candidate of centre ii is entry k of its list.  Loop bounds are
         // wave-uniform; a lane whose shell is small (n <= P) takes positions
@@ -931,7 +976,7 @@ __global__ __launch_bounds__(256) void k_build_draw(FusedArgs fa)
                 const int ii = pr / fa.K;
                 const int rr = pr - ii * fa.K;
                 const int islot = i0 + g0 + ii;
-                const int n = s_ncnt[w][ii];
+                const int n = STENCIL ? total : s_ncnt[w][ii];
                 const bool small = n <= P;
                 const unsigned short* lst = &s_lst[ii * cap];
                 int* out = fa.batch + batch_index(rr, islot, 0, a.n_slots, P);
@@ -944,10 +989,21 @@ __global__ __launch_bounds__(256) void k_build_draw(FusedArgs fa)
                     if (qq < P) {
                         const uint32_t k = small ? (uint32_t)qq : S[qq];
                         const bool own = (int)k < n;
-                        // past the list room (an overflowing run, repeated by
-                        // the host) the entry is read from within the room
-                        const int e = lst[min(k, (uint32_t)(cap - 1))];
-                        const int j = s_rstart[w][e >> kRunOffBits] + (e & ((1 << kRunOffBits) - 1));
+                        int j;
+                        if constexpr (STENCIL) {
+                            // run holding stencil particle k: the last run whose
+                            // prefix count is <= k (prefix counts never decrease)
+                            int q = 0;
+#pragma unroll
+                            for (int st = 32; st > 0; st >>= 1)
+                                if (s_rpre[w][q + st] <= (int)k) q += st;
+                            j = s_rstart[w][q] + (int)k - s_rpre[w][q];
+                        } else {
+                            // past the list room (an overflowing run, repeated
+                            // by the host) the entry is read from within the room
+                            const int e = lst[min(k, (uint32_t)(cap - 1))];
+                            j = s_rstart[w][e >> kRunOffBits] + (e & ((1 << kRunOffBits) - 1));
+                        }
                         const bool ok = j >= 0 && (int64_t)j < a.n_slots;
                         bad |= own && !ok;
                         out[qq] = (own && ok) ? j : islot;

@@ -95,6 +95,8 @@ struct rbl_ctx {
     bool shell_counts = false;  // shell_len valid (explicit shell list or fused build)
     bool fused_ok = true;       // false once a stencil outgrew the fused kernel's LDS lists
     int cap_list = 0;           // fused kernel: LDS shell-list room per centre particle
+    bool stencil = false;       // batches drawn from the stencil cells (N_I in d_nI)
+    int* d_nI = nullptr;        // stencil draw population size per slot
     double r_s = 0, r_c = 0;
     std::vector<DevReplica> h_rep;
     int64_t n_cells = 0, cells_alloc = 0;
@@ -519,10 +521,13 @@ rbl_status ensure_batch(rbl_ctx* c, int K, int P);
 // Queues the fused build (core rows, shell counts, batches of K force
 // evaluations from step0, or from *step_dev + step0 when step_dev is set).
 rbl_status launch_fused(rbl_ctx* c, int P, uint64_t seed, uint64_t step0, int K,
-                        const uint64_t* step_dev)
+                        const uint64_t* step_dev, bool draw_only = false)
 {
     FusedArgs fa;
     fa.b = build_args(c);
+    fa.core_reach = c->r_s + c->cfg.skin;
+    fa.draw_only = draw_only ? 1 : 0;
+    if (c->stencil) fa.b.shell_len = c->d_nI;
     fa.perm = c->cur_perm();
     fa.batch = c->d_batch;
     fa.seed = seed;
@@ -535,10 +540,14 @@ rbl_status launch_fused(rbl_ctx* c, int P, uint64_t seed, uint64_t step0, int K,
     // 64 KB of LDS
     fa.list_budget = (int)std::min<int64_t>(kListBudgetMax,
                                             std::max<int64_t>(kListBudgetMin, ((int64_t)8 * c->cap_list + 63) / 64 * 64));
-    const size_t lds = (size_t)4 * (fa.list_budget + 64) * sizeof(unsigned short);
+    const size_t lds = c->stencil ? 0 : (size_t)4 * (fa.list_budget + 64) * sizeof(unsigned short);
     const unsigned g = grid_for(c->n_cells, 4);
     return timed(c, kKBuild, [&] {
-#define RBL_BD(PM) k_build_draw<PM><<<g, kBlock, lds, c->ls>>>(fa)
+#define RBL_BD(PM)                                                    \
+    do {                                                              \
+        if (c->stencil) k_build_draw<PM, true><<<g, kBlock, 0, c->ls>>>(fa); \
+        else k_build_draw<PM, false><<<g, kBlock, lds, c->ls>>>(fa);  \
+    } while (0)
         if (P <= 8) RBL_BD(8);
         else if (P <= 12) RBL_BD(12);
         else if (P <= 16) RBL_BD(16);
@@ -562,6 +571,8 @@ void grow_cap_list(rbl_ctx* c, int need, bool regrow)
     c->cap_list = (int)std::min<int64_t>(cap, 1 << 20);
 }
 
+rbl_status prepare_lists(rbl_ctx* c, int mask);
+
 // Sizes the core rows if needed (a counting pass and one synchronisation,
 // the first time only) and makes sure the shell-count and batch buffers
 // exist for `K` steps of batch size P.
@@ -570,6 +581,11 @@ rbl_status prepare_fused(rbl_ctx* c, int P, int K)
     for (int q = 0; q < 2; ++q)
         if (!c->d_len[q]) RBL_TRY(dalloc(&c->d_len[q], c->n_slots));
     RBL_TRY(ensure_batch(c, K, P));
+    if (c->stencil) {
+        // no shell list: the core rows alone are sized
+        if (!c->d_nI) RBL_TRY(dalloc(&c->d_nI, c->n_slots));
+        return prepare_lists(c, RBL_LIST_CORE);
+    }
     if (c->cap[0] == 0 || c->cap_list == 0) {
         RBL_TRY(clear_list_flags(c));
         BuildArgs a = build_args(c);
@@ -616,7 +632,7 @@ ForceArgs force_args(rbl_ctx* c, int P, uint64_t seed, uint64_t step, bool full)
     a.core_len = full ? c->d_len[2] : c->d_len[0];
     a.cap_core = full ? c->cap[2] : c->cap[0];
     a.shell = c->d_list[1];
-    a.shell_len = c->d_len[1];
+    a.shell_len = c->stencil ? c->d_nI : c->d_len[1];
     a.cap_shell = c->cap[1];
     a.batch = nullptr;
     a.n_slots = c->n_slots;
@@ -884,6 +900,7 @@ std::vector<unsigned char> block_signature(const rbl_ctx* c, const StepParams& s
         sig_put(v, (const void*)c->d_len[q]);
     }
     sig_put(v, (const void*)c->d_batch);
+    sig_put(v, (const void*)c->d_nI);
     sig_put(v, (const void*)c->d_cell_start);
     sig_put(v, (const void*)c->d_cell_rep);
     sig_put(v, c->profiling);
@@ -1025,7 +1042,7 @@ rbl_status md_run(rbl_ctx* c, double* pos, double* vel, double* force, int64_t n
     sp.dt = dt;
     sp.full = full;
     sp.fix = !full && c->cfg.momentum_fix;
-    sp.pre = !full && c->cfg.predraw && c->fused_ok;
+    sp.pre = !full && ((c->cfg.predraw && c->fused_ok) || c->stencil);
     const int mask = full ? RBL_LIST_FULL : (RBL_LIST_CORE | RBL_LIST_SHELL);
     const bool use_graph = c->cfg.graphs && !c->profiling && c->gs;
     LaunchStreamGuard guard{c};
@@ -1050,7 +1067,7 @@ rbl_status md_run(rbl_ctx* c, double* pos, double* vel, double* force, int64_t n
             RBL_TRY(prepare_fused(c, P, (int)K));
             RBL_TRY(launch_fused(c, P, seed, (uint64_t)s, (int)cnt, nullptr));
             c->built_mask = RBL_LIST_CORE;
-            c->shell_counts = true;
+            c->shell_counts = !c->stencil;
         } else {
             RBL_TRY(prepare_lists(c, mask));
             BuildArgs a = build_args(c);
@@ -1079,7 +1096,7 @@ rbl_status md_run(rbl_ctx* c, double* pos, double* vel, double* force, int64_t n
             build_step = s;
             c->built = true;
             c->built_mask = sp.full ? RBL_LIST_FULL : (sp.pre ? RBL_LIST_CORE : mask);
-            c->shell_counts = !sp.full;
+            c->shell_counts = !sp.full && !c->stencil;
             it += K;
             continue;
         }
@@ -1149,6 +1166,8 @@ void rbl_config_init(rbl_config* cfg, int64_t n)
     cfg->capacity_factor = 1.25;
     cfg->replica_offsets = nullptr;
     cfg->charges = nullptr;
+    cfg->shell_source = RBL_SHELL_LIST;
+    cfg->reserved = 0;
 }
 
 const char* rbl_last_error(void) { return g_err.c_str(); }
@@ -1196,6 +1215,7 @@ rbl_status rbl_destroy(rbl_ctx* c)
         dfree(c->d_len[q]);
     }
     dfree(c->d_batch);
+    dfree(c->d_nI);
     dfree(c->d_partial);
     dfree(c->d_part2);
     dfree(c->d_rep_sum);
@@ -1224,6 +1244,9 @@ rbl_status rbl_create(const rbl_config* cfg, void* hip_stream, rbl_ctx** out)
     if (!(cfg->capacity_factor > 0.0) || !std::isfinite(cfg->capacity_factor))
         return fail(RBL_E_ARG, "capacity_factor must be > 0");
     if (cfg->pair == RBL_PAIR_LJ_ERFC && !(cfg->alpha > 0.0)) return fail(RBL_E_ARG, "alpha must be > 0");
+    if (cfg->shell_source != RBL_SHELL_LIST && cfg->shell_source != RBL_SHELL_STENCIL)
+        return fail(RBL_E_ARG, "shell_source must be RBL_SHELL_LIST or RBL_SHELL_STENCIL");
+    if (cfg->reserved != 0) return fail(RBL_E_ARG, "reserved must be 0");
     std::vector<int64_t> off(cfg->n_replicas + 1);
     if (cfg->n_replicas == 1) {
         off[0] = 0;
@@ -1244,6 +1267,7 @@ rbl_status rbl_create(const rbl_config* cfg, void* hip_stream, rbl_ctx** out)
     c->n = cfg->n;
     if (cfg->lanes > 0) c->lpp_rbl = c->lpp_full = cfg->lanes;
     c->persist[0] = c->persist[1] = cfg->persistent == 2;
+    c->stencil = cfg->shell_source == RBL_SHELL_STENCIL;
     {
         int dev = 0, ncu = 0;
         if (hipGetDevice(&dev) == hipSuccess &&
@@ -1343,13 +1367,23 @@ rbl_status rbl_forces(rbl_ctx* c, int P, uint64_t seed, uint64_t step, const dou
     if (!c || !pos || !force) return fail(RBL_E_ARG, "NULL argument");
     RBL_TRY(check_p(P));
     if (!c->built) return fail(RBL_E_STATE, "rbl_forces needs a list build first");
-    if ((c->built_mask & (RBL_LIST_CORE | RBL_LIST_SHELL)) != (RBL_LIST_CORE | RBL_LIST_SHELL))
-        return fail(RBL_E_STATE, "the last build has no core and shell lists");
+    const int need = c->stencil ? RBL_LIST_CORE : (RBL_LIST_CORE | RBL_LIST_SHELL);
+    if ((c->built_mask & need) != need)
+        return fail(RBL_E_STATE, c->stencil ? "the last build has no core list"
+                                            : "the last build has no core and shell lists");
+    if (c->stencil) {
+        // batches from the stencil cells of the build's binning
+        RBL_TRY(ensure_batch(c, 1, P));
+        if (!c->d_nI) RBL_TRY(dalloc(&c->d_nI, c->n_slots));
+        RBL_TRY(launch_fused(c, P, seed, step, 1, nullptr, true));
+    }
     IoArgs io = io_args(c, c->cfg.momentum_fix != 0);
     io.pos_in = pos;
     k_load_positions<<<grid_for(c->n_slots), kBlock, 0, c->ls>>>(io);
     HIP_TRY(hipGetLastError());
-    if (P <= 32) {
+    if (c->stencil) {
+        RBL_TRY(rbl_force_sorted(c, P, seed, step, 0, ev != nullptr));
+    } else if (P <= 32) {
         RBL_TRY(rbl_force_sorted(c, P, seed, step, -1, ev != nullptr));
     } else {
         RBL_TRY(predraw(c, P, seed, step, 1));
@@ -1397,7 +1431,8 @@ rbl_status rbl_step(rbl_ctx* c, double* pos, double* vel, double* force, int64_t
         drop_graphs(c);
         if (c->h_flags[kFlagStencil]) continue;  // rows of the explicit path get counted afresh
         const int mask = full ? RBL_LIST_FULL
-                              : ((c->cfg.predraw && c->fused_ok) ? RBL_LIST_CORE : (RBL_LIST_CORE | RBL_LIST_SHELL));
+                              : (((c->cfg.predraw && c->fused_ok) || c->stencil) ? RBL_LIST_CORE
+                                                                                : (RBL_LIST_CORE | RBL_LIST_SHELL));
         for (int q = 0; q < 3; ++q)
             if ((mask >> q) & 1) RBL_TRY(ensure_list_storage(c, q, c->h_flags[kFlagMaxCore + q], true));
     }
@@ -1505,10 +1540,17 @@ rbl_status rbl_export_batches(rbl_ctx* c, int P, uint64_t seed, uint64_t step, i
 {
     if (!c || !batch || !count || nrows < 0) return fail(RBL_E_ARG, "bad argument");
     RBL_TRY(check_p(P));
-    if (!c->built || !(c->built_mask & RBL_LIST_SHELL)) return fail(RBL_E_STATE, "no shell list built");
+    if (!c->built) return fail(RBL_E_STATE, "no list build");
+    if (!c->stencil && !(c->built_mask & RBL_LIST_SHELL)) return fail(RBL_E_STATE, "no shell list built");
     for (int64_t k = 0; k < nrows; ++k)
         if (!rows || rows[k] < 0 || rows[k] >= c->n) return fail(RBL_E_ARG, "row ID out of range");
-    RBL_TRY(predraw(c, P, seed, step, 1));
+    if (c->stencil) {
+        RBL_TRY(ensure_batch(c, 1, P));
+        if (!c->d_nI) RBL_TRY(dalloc(&c->d_nI, c->n_slots));
+        RBL_TRY(launch_fused(c, P, seed, step, 1, nullptr, true));
+    } else {
+        RBL_TRY(predraw(c, P, seed, step, 1));
+    }
     std::vector<int> h_batch((size_t)P * c->n_slots), h_perm(c->n_slots), h_slot(c->n), h_len(c->n_slots);
     HIP_TRY(hipMemcpyAsync(h_batch.data(), c->d_batch, sizeof(int) * h_batch.size(), hipMemcpyDeviceToHost,
                            c->ls));
@@ -1516,8 +1558,8 @@ rbl_status rbl_export_batches(rbl_ctx* c, int P, uint64_t seed, uint64_t step, i
                            c->ls));
     HIP_TRY(hipMemcpyAsync(h_slot.data(), c->d_slot_of_id, sizeof(int) * c->n, hipMemcpyDeviceToHost,
                            c->ls));
-    HIP_TRY(hipMemcpyAsync(h_len.data(), c->d_len[1], sizeof(int) * c->n_slots, hipMemcpyDeviceToHost,
-                           c->ls));
+    HIP_TRY(hipMemcpyAsync(h_len.data(), c->stencil ? c->d_nI : c->d_len[1], sizeof(int) * c->n_slots,
+                           hipMemcpyDeviceToHost, c->ls));
     HIP_TRY(hipStreamSynchronize(c->ls));
     for (int64_t k = 0; k < nrows; ++k) {
         const int slot = h_slot[rows[k]];

@@ -1,0 +1,149 @@
+"""The stencil draw population (Sec. II: each particle's batch drawn from
+all N_I particles of the stencil cells around its cell, itself included,
+scaled by N_I/P in eq. (4)) on the GPU against the oracle's stencil rows.
+
+Batches must match bit for bit; forces within 1e-12 relative L2 in FP64 and
+2e-5 in the mixed form; trajectories as tightly as the shell-list form's.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2105_04884_amd import Context, RblError, inputs
+from paper_2105_04884_amd import _lib
+
+from gpu_util import (FP64_TOL, MIXED_TOL, RC, RS, SKIN, assert_lists_equal, dev, host,
+                      oracle_rbl_total, rel_l2, torch_cuda)
+
+pytestmark = pytest.mark.gpu
+
+
+def _state(name):
+    if name == "fluid8000":      # 11 cells per axis: 5 x 5 x 5 stencils, 3 x 3 x 3 core table
+        return inputs.lj_fluid(8000, 0.8442, 1.0, seed=21)
+    if name == "fluid1000":      # 5 cells per axis: every stencil is the whole box
+        return inputs.small_fluid(seed=1)
+    if name == "elongated":      # 4, 5 and 12 cells: whole axes beside wrapped runs
+        box = np.array([8.2, 9.5, 24.0])
+        return inputs.random_gas(900, box, seed=6)
+    if name == "ragged_65":
+        box = np.array([8.0, 8.0, 8.0])
+        return inputs.random_gas(65, box, seed=9, min_dist=0.9)
+    raise KeyError(name)
+
+
+@pytest.mark.parametrize("case", ["fluid8000", "fluid1000", "elongated", "ragged_65"])
+def test_stencil_batches_match_oracle(case):
+    torch_cuda()
+    st = _state(case)
+    pos, box = st.pos, st.box
+    n = pos.shape[1]
+    off, idx = oracle.System(pos, box, RS, RC, SKIN).stencil_rows()
+    rows = np.arange(n)
+    with Context(n, shell_source="stencil") as ctx:
+        ctx.build(dev(pos), box, RS, RC)
+        for P in (1, 10, 128):
+            for seed, step in ((1, 0), (2**40 + 3, 2**32 + 5)):
+                batch, count = ctx.export_batches(P, seed, step, rows)
+                for i in range(n):
+                    row = idx[off[i]:off[i + 1]]
+                    kpos = oracle.batch_positions(seed, i, step, 0, P, len(row))
+                    assert count[i] == len(kpos), (case, P, i)
+                    assert np.array_equal(batch[i, :count[i]], row[kpos]), (case, P, seed, i)
+                    assert np.all(batch[i, count[i]:] == -1)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("mixed", MIXED_TOL)])
+@pytest.mark.parametrize("P", [10, 64])
+def test_stencil_forces_match_oracle(precision, tol, P):
+    """At the build state and at displaced positions (partners classified by
+    their current distance), with mean-force subtraction, energy, virial."""
+    torch_cuda()
+    st = _state("fluid8000")
+    pos, box = st.pos, st.box
+    L = oracle.System(pos, box, RS, RC, SKIN).stencil_lists()
+    rng = np.random.default_rng(3)
+    with Context(st.n, precision=precision, shell_source="stencil") as ctx:
+        ctx.build(dev(pos), box, RS, RC)
+        for k, p in enumerate((pos, pos + rng.uniform(-0.1, 0.1, size=pos.shape))):
+            f, ev = ctx.forces(P, seed=11 + k, step=3 * k, pos=dev(p), want_ev=True)
+            fo, eo, wo = oracle_rbl_total(p, box, L, P, 11 + k, 3 * k)
+            assert rel_l2(host(f), fo) < tol
+            U, W = host(ev)
+            assert abs(U - eo) <= tol * max(1.0, abs(eo)) * 10
+            assert abs(W - wo) <= tol * max(1.0, abs(wo)) * 10
+
+
+@pytest.mark.parametrize("rc", [RC, 2.6])
+def test_stencil_trajectory_matches_oracle(rc):
+    """60 velocity-Verlet steps, lists and batches every 10 steps, against
+    the oracle's run on stencil rows.  r_c = 3.5 gives cells of edge 1.9, so
+    the core (r_s + skin = 1.8) is searched in the 3 x 3 x 3 cells; at
+    r_c = 2.6 the edge is 1.45 and the core walks the whole 5 x 5 x 5
+    stencil.  Core rows bit-exact at the final state; captured and
+    step-by-step execution equal."""
+    torch = torch_cuda()
+    st = _state("fluid8000")
+    runs = []
+    for graphs in (True, False):
+        x, v = dev(st.pos), dev(st.vel)
+        f = torch.zeros_like(x)
+        with Context(st.n, lanes=1, graphs=graphs, shell_source="stencil") as ctx:
+            ctx.build(x, st.box, RS, rc)
+            status, ev = ctx.step(x, v, nsteps=60, dt=0.005, P=10, seed=5, rebuild_every=10,
+                                  force=f, want_ev=True)
+            got_core = ctx.export_lists(kinds=("core",))
+        assert status in (0, _lib.RBL_W_SKIN)
+        runs.append((host(x), host(v), host(f), host(ev), got_core))
+    assert np.array_equal(runs[0][0], runs[1][0])
+    assert np.array_equal(runs[0][1], runs[1][1])
+    xo, vo, fo, evo = oracle.md_run(st.pos, st.vel, st.box, RS, rc, SKIN, 0.005, 60, p=10,
+                                    seed=5, K=10, want_ev=True, shell_source="stencil")
+    x, v, f, ev, got_core = runs[0]
+    assert rel_l2(x, xo) < 1e-12
+    assert rel_l2(v, vo) < 1e-9
+    assert rel_l2(f, fo) < 1e-9
+    assert abs(ev[0] - evo[-1, 0]) < 1e-9 * abs(evo[-1, 0])
+    ref = oracle.System(x, st.box, RS, rc, SKIN).lists(kinds=("core",))
+    assert_lists_equal(got_core, ref, kinds=("core",))
+
+
+def test_stencil_ensemble_matches_oracle_per_replica():
+    """Replicas of different sizes and densities (different cell grids) in
+    one context: each replica's trajectory against its own oracle run, with
+    the replica index in the Philox counter."""
+    torch_cuda()
+    specs = [(900, 0.8, 1.0, 1), (2500, 0.6, 1.2, 2), (300, 0.3, 1.0, 4)]
+    states = [inputs.lj_fluid(*s) for s in specs]
+    pos = np.concatenate([s.pos for s in states], axis=1)
+    vel = np.concatenate([s.vel for s in states], axis=1)
+    boxes = np.stack([s.box for s in states])
+    off = np.zeros(len(states) + 1, dtype=np.int64)
+    off[1:] = np.cumsum([s.n for s in states])
+    x, v = dev(pos), dev(vel)
+    with Context(int(off[-1]), replica_offsets=off, lanes=1, shell_source="stencil") as ctx:
+        ctx.build(x, boxes, RS, RC)
+        status, _ = ctx.step(x, v, nsteps=30, dt=0.005, P=10, seed=7, rebuild_every=10)
+    assert status in (0, _lib.RBL_W_SKIN)
+    xg = host(x)
+    for r, s in enumerate(states):
+        xo, _, _, _ = oracle.md_run(s.pos, s.vel, s.box, RS, RC, SKIN, 0.005, 30, p=10, seed=7,
+                                    K=10, replica=r, shell_source="stencil")
+        assert rel_l2(xg[:, off[r]:off[r + 1]], xo) < 1e-12, r
+
+
+def test_stencil_mode_needs_no_shell_list():
+    """With the stencil population rbl_forces works on a build without shell
+    rows; the shell-list form refuses the same build."""
+    torch_cuda()
+    st = _state("fluid1000")
+    L = oracle.System(st.pos, st.box, RS, RC, SKIN).stencil_lists()
+    with Context(st.n, lists=("core",), shell_source="stencil") as ctx:
+        ctx.build(dev(st.pos), st.box, RS, RC)
+        f = ctx.forces(10, seed=2, step=4, pos=dev(st.pos))
+    fo, _, _ = oracle_rbl_total(st.pos, st.box, L, 10, 2, 4)
+    assert rel_l2(host(f), fo) < FP64_TOL
+    with Context(st.n, lists=("core",)) as ctx:
+        ctx.build(dev(st.pos), st.box, RS, RC)
+        with pytest.raises(RblError):
+            ctx.forces(10, seed=2, step=4, pos=dev(st.pos))
