@@ -198,13 +198,13 @@ def force_roofline(res, fk):
     }
 
 
-def run_variant(name, x0, v0, box, precision, P, use_full, steps, warmup, torch):
+def run_variant(name, x0, v0, box, precision, P, use_full, steps, warmup, torch, source="shell"):
     from paper_2105_04884_amd import Context, KIND_FORCE_RBL, KIND_FORCE_FULL, KIND_BUILD, \
         KIND_BIN, KIND_INTEGRATE, KIND_REDUCE, KIND_PREDRAW
     lists = ("full",) if use_full else ("core", "shell")
     x = x0.clone()
     v = v0.clone()
-    ctx = Context(N, precision=precision, lists=lists, skin=SKIN)
+    ctx = Context(N, precision=precision, lists=lists, skin=SKIN, shell_source=source)
     ctx.build(x, box, RS, RC)
     if warmup > 0:
         ctx.step(x, v, nsteps=warmup, dt=DT, P=P, seed=1, step0=0, rebuild_every=K_REBUILD,
@@ -236,7 +236,7 @@ def run_variant(name, x0, v0, box, precision, P, use_full, steps, warmup, torch)
     mean = {"core": float(counts[0].mean()), "shell": float(counts[1].mean()),
             "full": float(counts[2].mean())}
     res = {
-        "name": name, "precision": precision, "P": P, "full": use_full,
+        "name": name, "precision": precision, "P": P, "full": use_full, "shell_source": source,
         "ms_per_step": 1e3 * elapsed / steps,
         "atom_steps_per_s": N * steps / elapsed,
         "status": int(status),
@@ -353,18 +353,22 @@ def run_large(torch, steps=200, warmup=20):
 
 def force_error_vs_oracle(x0, box, torch, rows):
     """Relative L2 error of the raw RBL force (P = 10, no mean subtraction)
-    against the FP64 CPU oracle on sampled rows, for both precisions."""
+    against the FP64 CPU oracle on sampled rows, for both precisions and
+    both draw populations (keys "stencil_*": the stencil cells)."""
     import oracle
     from paper_2105_04884_amd import Context
     pos = x0.cpu().numpy()
-    L = oracle.System(pos, box, RS, RC, SKIN).lists(rows=rows, kinds=("core", "shell"))
-    fo, _, _ = oracle.rbl_forces(pos, box, RS, RC, L, 10, 1, 0)
+    sysm = oracle.System(pos, box, RS, RC, SKIN)
     out = {}
-    for precision in ("fp64", "mixed"):
-        with Context(N, precision=precision, momentum_fix=False) as ctx:
-            ctx.build(x0, box, RS, RC)
-            f = ctx.forces(10, seed=1, step=0, pos=x0).cpu().numpy()[:, rows]
-        out[precision] = float(np.linalg.norm(f - fo) / np.linalg.norm(fo))
+    for source, prefix in (("shell", ""), ("stencil", "stencil_")):
+        L = (sysm.lists(rows=rows, kinds=("core", "shell")) if source == "shell"
+             else sysm.stencil_lists(rows=rows))
+        fo, _, _ = oracle.rbl_forces(pos, box, RS, RC, L, 10, 1, 0)
+        for precision in ("fp64", "mixed"):
+            with Context(N, precision=precision, momentum_fix=False, shell_source=source) as ctx:
+                ctx.build(x0, box, RS, RC)
+                f = ctx.forces(10, seed=1, step=0, pos=x0).cpu().numpy()[:, rows]
+            out[prefix + precision] = float(np.linalg.norm(f - fo) / np.linalg.norm(fo))
     return out
 
 
@@ -421,15 +425,17 @@ def method_error(x0, box):
     """Relative L2 distance of the RBL force from the full-list force at the
     same state (mean force subtracted, as in the MD loop) for each batch
     size: the statistical error of the method itself, not an error of the
-    implementation."""
+    implementation.  Keys "stencil_P" draw from the stencil cells instead of
+    the shell rows."""
     from paper_2105_04884_amd import Context
     out = {}
-    with Context(N, precision="fp64", lists=("core", "shell", "full")) as ctx:
-        ctx.build(x0, box, RS, RC)
-        ff = ctx.full_forces(x0)
-        for P in (5, 10, 20):
-            f = ctx.forces(P, seed=1, step=0, pos=x0)
-            out[str(P)] = float((f - ff).norm() / ff.norm())
+    for source, prefix in (("shell", ""), ("stencil", "stencil_")):
+        with Context(N, precision="fp64", lists=("core", "shell", "full"), shell_source=source) as ctx:
+            ctx.build(x0, box, RS, RC)
+            ff = ctx.full_forces(x0)
+            for P in (5, 10, 20):
+                f = ctx.forces(P, seed=1, step=0, pos=x0)
+                out[prefix + str(P)] = float((f - ff).norm() / ff.norm())
     return out
 
 
@@ -546,21 +552,22 @@ def main():
     x0 = torch.from_numpy(st.pos).cuda()
     v0 = torch.from_numpy(st.vel).cuda()
     variants = [
-        ("rbl_mixed_p10", "mixed", 10, False),
-        ("rbl_fp64_p10", "fp64", 10, False),
-        ("full_mixed", "mixed", 10, True),
-        ("full_fp64", "fp64", 10, True),
-        ("rbl_mixed_p5", "mixed", 5, False),
-        ("rbl_mixed_p20", "mixed", 20, False),
+        ("rbl_mixed_p10", "mixed", 10, False, "shell"),
+        ("rbl_fp64_p10", "fp64", 10, False, "shell"),
+        ("full_mixed", "mixed", 10, True, "shell"),
+        ("full_fp64", "fp64", 10, True, "shell"),
+        ("rbl_mixed_p5", "mixed", 5, False, "shell"),
+        ("rbl_mixed_p20", "mixed", 20, False, "shell"),
+        ("rbl_stencil_mixed_p10", "mixed", 10, False, "stencil"),
     ]
     if args.variants != "all":
         keep = set(args.variants.split(","))
         variants = [v for v in variants if v[0] in keep]
     results = {}
-    for name, prec, P, full in variants:
+    for name, prec, P, full, source in variants:
         log(f"[bench] variant {name}")
         results[name] = run_variant(name, x0, v0, st.box, prec, P, full, args.steps,
-                                    args.warmup, torch)
+                                    args.warmup, torch, source)
     head = results.get("rbl_mixed_p10") or next(iter(results.values()))
 
     log("[bench] force error vs the FP64 oracle (sampled rows)")
