@@ -75,8 +75,13 @@ def load():
     lib.orc_md_run.argtypes = [C.c_int64, _f64p, _f64p, _f64p, C.c_double, C.c_double,
                                C.c_double, C.c_double, C.c_int64, C.c_int, C.c_uint64,
                                C.c_int64, C.c_int, C.c_int, C.c_int, C.c_int, C.c_uint32,
-                               C.c_void_p, C.c_double, C.c_int, _f64p, C.c_void_p]
+                               C.c_void_p, C.c_double, C.c_int, C.c_double, C.c_double,
+                               C.c_void_p, _f64p, C.c_void_p]
     lib.orc_md_run.restype = C.c_int
+    lib.orc_langevin_noise.argtypes = [C.c_uint64, C.c_uint32, C.c_uint64, C.c_uint32, _f64p]
+    lib.orc_rdf.argtypes = [C.c_int64, _f64p, _f64p, C.c_double, C.c_int, C.c_void_p]
+    lib.orc_rdf.restype = C.c_int
+    lib.orc_tail.argtypes = [C.c_double, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double)]
     _lib = lib
     return lib
 
@@ -303,19 +308,61 @@ def mean_subtract(f: np.ndarray):
 
 def md_run(pos, vel, box, rs, rc, skin, dt, nsteps, p=10, seed=1, step0=0, K=10,
            use_full=False, shift=True, momentum_fix=True, replica=0, want_ev=False,
-           charges=None, alpha: float = 0.0, shell_source: str = "shell"):
-    """Velocity-Verlet run (Algorithm 1, NVE).  Returns (pos, vel, force, ev)
-    with ev of shape (nsteps+1, 2) = (U, W) per force evaluation or None."""
+           charges=None, alpha: float = 0.0, shell_source: str = "shell",
+           gamma: float = 0.0, kT: float = 1.0, unwrapped=None):
+    """Run of Algorithm 1: velocity Verlet (NVE) for gamma = 0, Langevin
+    (BAOAB, friction gamma, bath temperature kT) otherwise.  Returns (pos,
+    vel, force, ev) with ev of shape (nsteps+1, 2) = (U, W) per force
+    evaluation or None.  ``unwrapped`` (float64 array shaped like pos,
+    updated in place) follows the positions without wrapping."""
     lib = load()
     x = np.ascontiguousarray(pos, dtype=np.float64).copy()
     v = np.ascontiguousarray(vel, dtype=np.float64).copy()
     f = np.zeros_like(x)
     ev = np.zeros((nsteps + 1, 2)) if want_ev else None
     q = _charges(charges, x.shape[1])
+    if unwrapped is not None:
+        if (not isinstance(unwrapped, np.ndarray) or unwrapped.dtype != np.float64
+                or unwrapped.shape != x.shape or not unwrapped.flags.c_contiguous):
+            raise ValueError("unwrapped must be a contiguous float64 array shaped like pos")
     r = lib.orc_md_run(x.shape[1], x, v, np.asarray(box, dtype=np.float64), rs, rc, skin, dt,
                        nsteps, p, seed, step0, K, int(use_full), int(shift), int(momentum_fix),
                        replica, _ptr_or_null(q), float(alpha),
-                       {"shell": 0, "stencil": 1}[shell_source], f, _ptr_or_null(ev))
+                       {"shell": 0, "stencil": 1}[shell_source], float(gamma), float(kT),
+                       _ptr_or_null(unwrapped), f, _ptr_or_null(ev))
     if r:
         raise RuntimeError(f"orc_md_run failed ({r})")
     return x, v, f, ev
+
+
+# ---------------------------------------------------------------------------
+# thermostat noise and observables (Sec. III)
+
+def langevin_noise(seed: int, pid: int, step: int, replica: int = 0) -> np.ndarray:
+    """The three standard normal numbers of particle pid's Ornstein-Uhlenbeck
+    step at force evaluation ``step``."""
+    lib = load()
+    g = np.zeros(3)
+    lib.orc_langevin_noise(seed, pid, step, replica, g)
+    return g
+
+
+def rdf_counts(pos, box, r_max: float, nbins: int) -> np.ndarray:
+    """Ordered-pair distance histogram (uint64 per bin of width r_max/nbins)."""
+    lib = load()
+    pos = np.ascontiguousarray(pos, dtype=np.float64)
+    counts = np.zeros(nbins, dtype=np.uint64)
+    r = lib.orc_rdf(pos.shape[1], pos, np.asarray(box, dtype=np.float64), float(r_max), int(nbins),
+                    counts.ctypes.data_as(C.c_void_p))
+    if r:
+        raise ValueError("invalid RDF arguments")
+    return counts
+
+
+def tail(rho: float, rc: float):
+    """(energy per particle, pressure) tail corrections beyond rc."""
+    lib = load()
+    u = C.c_double()
+    p = C.c_double()
+    lib.orc_tail(float(rho), float(rc), C.byref(u), C.byref(p))
+    return u.value, p.value

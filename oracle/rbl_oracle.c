@@ -44,7 +44,19 @@
  *                       and f~_ij = 0 outside the shell zone.
  *   orc_mean_subtract   subtraction of the average net force (Sec. II,
  *                       Algorithm 1, F_cor of Appendix A).
- *   orc_md_run          Algorithm 1 with velocity Verlet (NVE).
+ *   orc_md_run          Algorithm 1 with velocity Verlet (NVE), or with the
+ *                       underdamped Langevin thermostat of Sec. II / Sec. III
+ *                       (friction gamma, bath temperature kT) integrated by
+ *                       the BAOAB splitting of Leimkuhler & Matthews (2013),
+ *                       the velocity-Verlet Langevin scheme the paper cites.
+ *   orc_langevin_noise  the three standard normal numbers of one particle's
+ *                       Ornstein-Uhlenbeck step: Box-Muller (1958) on one
+ *                       Philox block.
+ *   orc_rdf             pair-distance histogram behind the radial
+ *                       distribution function g(r) of Sec. III, by brute
+ *                       force over all ordered pairs.
+ *   orc_tail            the mean-field tail corrections of the potential
+ *                       energy per particle and of the pressure (Sec. III).
  */
 #include <math.h>
 #include <stdint.h>
@@ -705,6 +717,86 @@ static int build_all(int64_t n, double* pos, const double box[3], double rs, dou
     return rcode;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Langevin thermostat (Sec. II, m dv = (F - gamma v) dt + sqrt(2 gamma kT)
+ * dW; Sec. III: velocity Verlet with underdamped Langevin, gamma = 1).
+ * The Ornstein-Uhlenbeck part over a step dt is solved exactly:
+ *   v <- c v + sqrt(kT (1 - c^2)) xi,   c = exp(-gamma dt),  xi ~ N(0, 1).
+ * The normal numbers of particle pid at step s come from the Philox block
+ * with counter (pid, s mod 2^32, replica, 2^31), key (seed mod 2^32,
+ * seed >> 32): the batch draws use blocks below 2^31 of the same counters,
+ * so the two streams never share a block.  Each word w gives the uniform
+ * u = (w + 1/2) 2^-32 in (0, 1); the pairs (u0, u1) and (u2, u3) go through
+ * the Box-Muller transform sqrt(-2 ln u) (cos 2 pi u', sin 2 pi u'), and the
+ * first three of the four numbers are used. */
+
+#define ORC_NOISE_BLOCK 0x80000000u
+
+void orc_langevin_noise(uint64_t seed, uint32_t pid, uint64_t step, uint32_t replica, double g[3])
+{
+    uint32_t ctr[4] = {pid, (uint32_t)step, replica, ORC_NOISE_BLOCK};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t w[4];
+    orc_philox4x32_10(ctr, key, w);
+    double u[4];
+    for (int k = 0; k < 4; ++k) u[k] = ((double)w[k] + 0.5) * 2.3283064365386962890625e-10;
+    const double two_pi = 6.283185307179586476925286766559;
+    double r0 = sqrt(-2.0 * log(u[0]));
+    double r1 = sqrt(-2.0 * log(u[2]));
+    g[0] = r0 * cos(two_pi * u[1]);
+    g[1] = r0 * sin(two_pi * u[1]);
+    g[2] = r1 * cos(two_pi * u[3]);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Radial distribution function (Sec. III): g(r) = (1/(N rho)) sum_i
+ * sum_{j != i} <delta(r_ij - r)> / (4 pi r^2).  This is its histogram part:
+ * counts[k] += number of ordered pairs (i, j), i != j, whose minimum-image
+ * distance r falls in [k dr, (k+1) dr), dr = r_max / nbins, r < r_max.  The
+ * bin is decided on r^2 against the squared edges (k dr)(k dr), so that it
+ * does not depend on how the square root rounds. */
+
+static double rdf_edge2(int k, double dr)
+{
+    double e = (double)k * dr;
+    return e * e;
+}
+
+int orc_rdf(int64_t n, const double* pos, const double box[3], double r_max, int nbins,
+            uint64_t* counts)
+{
+    if (n < 0 || nbins < 1 || !(r_max > 0.0)) return -1;
+    double inv[3] = {1.0 / box[0], 1.0 / box[1], 1.0 / box[2]};
+    double dr = r_max / (double)nbins;
+    double top2 = rdf_edge2(nbins, dr);
+    double d[3];
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double r2 = dist2(pos, n, i, j, box, inv, d);
+            if (!(r2 < top2)) continue;
+            int k = (int)(sqrt(r2) / dr);
+            if (k > nbins - 1) k = nbins - 1;
+            while (k > 0 && r2 < rdf_edge2(k, dr)) --k;
+            while (k < nbins - 1 && r2 >= rdf_edge2(k + 1, dr)) ++k;
+            counts[k] += 1;
+        }
+    return 0;
+}
+
+/* Tail corrections for the LJ pairs beyond the cut-off rc (Sec. III, after
+ * Frenkel & Smit), with sigma = epsilon = 1 and number density rho:
+ *   energy per particle  (8/3) pi rho (1/(3 rc^9) - 1/rc^3),
+ *   pressure             (16/3) pi rho^2 (2/(3 rc^9) - 1/rc^3). */
+void orc_tail(double rho, double rc, double* u_tail, double* p_tail)
+{
+    const double pi = 3.141592653589793238462643383279;
+    double i3 = 1.0 / (rc * rc * rc);
+    double i9 = i3 * i3 * i3;
+    *u_tail = (8.0 / 3.0) * pi * rho * (i9 / 3.0 - i3);
+    *p_tail = (16.0 / 3.0) * pi * rho * rho * (2.0 * i9 / 3.0 - i3);
+}
+
 static void total_ev(int64_t n, const double* e, const double* w, double* out)
 {
     double U = 0.0, W = 0.0;
@@ -713,13 +805,27 @@ static void total_ev(int64_t n, const double* e, const double* w, double* out)
     out[1] = W;
 }
 
+/* Algorithm 1.  gamma == 0: velocity Verlet (NVE), per step
+ *   v += (dt/2) F;  x += dt v;  [rebuild];  F = force(s);  v += (dt/2) F.
+ * gamma > 0: BAOAB (Leimkuhler & Matthews 2013), per step
+ *   v += (dt/2) F;  x += (dt/2) v;  v = c v + sqrt(kT (1 - c^2)) xi(s);
+ *   x += (dt/2) v;  [rebuild];  F = force(s);  v += (dt/2) F
+ * with c = exp(-gamma dt) and xi(s) the normal numbers of orc_langevin_noise
+ * for the force evaluation s that the step leads to.  `unwrapped` (may be
+ * NULL) receives the same position increments as pos but is never wrapped
+ * into the box: it is the continuous trajectory (for the mean-squared
+ * displacement), and must hold the starting positions on entry. */
 int orc_md_run(int64_t n, double* pos, double* vel, const double box[3],
                double rs, double rc, double skin, double dt, int64_t nsteps,
                int p, uint64_t seed, int64_t step0, int K, int use_full,
                int shift, int momentum_fix, uint32_t replica,
-               const double* charge, double alpha, int stencil, double* force_out, double* ev_out)
+               const double* charge, double alpha, int stencil,
+               double gamma, double kT, double* unwrapped,
+               double* force_out, double* ev_out)
 {
-    if (K < 1 || n < 1) return -1;
+    if (K < 1 || n < 1 || !(gamma >= 0.0) || !(kT >= 0.0)) return -1;
+    double c_ou = exp(-gamma * dt);
+    double s_ou = sqrt(kT * (1.0 - c_ou * c_ou));
     orc_lists L = {0};
     double* F = (double*)malloc(sizeof(double) * 3 * (size_t)n);
     double* e = (double*)malloc(sizeof(double) * (size_t)n);
@@ -728,10 +834,28 @@ int orc_md_run(int64_t n, double* pos, double* vel, const double box[3],
     int rcode = 0;
     for (int64_t it = 0; it <= nsteps; ++it) {
         int64_t s = step0 + it;
-        if (it > 0) {
+        if (it > 0 && gamma == 0.0) {
             /* first half of step it-1: kick and drift */
             for (int64_t i = 0; i < 3 * n; ++i) vel[i] = vel[i] + h * F[i];
-            for (int64_t i = 0; i < 3 * n; ++i) pos[i] = pos[i] + dt * vel[i];
+            for (int64_t i = 0; i < 3 * n; ++i) {
+                pos[i] = pos[i] + dt * vel[i];
+                if (unwrapped) unwrapped[i] = unwrapped[i] + dt * vel[i];
+            }
+        } else if (it > 0) {
+            /* B, A, O, A of step it-1 */
+            for (int64_t i = 0; i < n; ++i) {
+                double g[3];
+                orc_langevin_noise(seed, (uint32_t)i, (uint64_t)s, replica, g);
+                for (int a = 0; a < 3; ++a) {
+                    int64_t q = a * n + i;
+                    vel[q] = vel[q] + h * F[q];
+                    pos[q] = pos[q] + h * vel[q];
+                    if (unwrapped) unwrapped[q] = unwrapped[q] + h * vel[q];
+                    vel[q] = c_ou * vel[q] + s_ou * g[a];
+                    pos[q] = pos[q] + h * vel[q];
+                    if (unwrapped) unwrapped[q] = unwrapped[q] + h * vel[q];
+                }
+            }
         }
         if (it == 0 || s % K == 0) {
             rcode = build_all(n, pos, box, rs, rc, skin, use_full, stencil, &L);

@@ -616,3 +616,143 @@ def test_stencil_md_conserves_momentum_and_differs_from_shell_draws():
     x2, _, _, _ = oracle.md_run(st.pos, st.vel, st.box, RS, RC, SKIN, 0.005, 20, p=10, seed=2,
                                 K=10, shell_source="shell")
     assert not np.array_equal(x, x2)
+
+
+# ------------------------------------------------- Langevin thermostat ---
+
+def test_langevin_noise_is_standard_normal():
+    """Box-Muller on Philox words: moments, independence of the three
+    components, and a Kolmogorov-Smirnov distance against the normal CDF
+    (written with math.erf)."""
+    g = np.array([oracle.langevin_noise(3, pid, step) for pid in range(400) for step in range(40)])
+    n = g.shape[0]
+    for a in range(3):
+        x = g[:, a]
+        assert abs(x.mean()) < 4.0 / math.sqrt(n)
+        assert abs(x.var() - 1.0) < 4.0 * math.sqrt(2.0 / n)
+        kurt = ((x - x.mean()) ** 4).mean() / x.var() ** 2
+        assert abs(kurt - 3.0) < 0.15
+        xs = np.sort(x)
+        cdf = np.array([0.5 * (1.0 + math.erf(v / math.sqrt(2.0))) for v in xs])
+        ks = max(np.max(np.arange(1, n + 1) / n - cdf), np.max(cdf - np.arange(n) / n))
+        assert ks < 1.63 / math.sqrt(n)   # 1% critical value
+    c = np.corrcoef(g.T)
+    assert np.all(np.abs(c[np.triu_indices(3, 1)]) < 4.0 / math.sqrt(n))
+    # a different seed, replica or step gives different numbers
+    assert not np.array_equal(oracle.langevin_noise(3, 0, 0), oracle.langevin_noise(4, 0, 0))
+    assert not np.array_equal(oracle.langevin_noise(3, 0, 0), oracle.langevin_noise(3, 0, 0, 1))
+
+
+def test_langevin_free_particle_is_an_exact_ou_process():
+    """One particle (no pair in range, F = 0): BAOAB's velocity is the exact
+    Ornstein-Uhlenbeck chain v_n = c^n v_0 + noise, so over independent
+    seeds E[v_n] = c^n v_0 and Var[v_n] = kT (1 - c^(2n)), c = exp(-gamma dt).
+    The unwrapped trajectory differs from the wrapped one by whole box
+    lengths."""
+    box = np.array([8.0, 8.0, 8.0])
+    gamma, kT, dt, steps = 1.0, 0.9, 0.02, 60
+    v0 = np.array([[1.5], [-0.7], [0.2]])
+    vs = []
+    for seed in range(600):
+        x0 = np.array([[4.0], [4.0], [4.0]])
+        u = x0.copy()
+        x, v, _, _ = oracle.md_run(x0, v0, box, RS, RC, SKIN, dt, steps, p=10, seed=seed, K=10,
+                                   gamma=gamma, kT=kT, unwrapped=u)
+        k = (u - x) / box[:, None]
+        assert np.allclose(k, np.round(k), atol=1e-9)
+        vs.append(v[:, 0])
+    vs = np.array(vs)
+    c = math.exp(-gamma * dt)
+    mean = c ** steps * v0[:, 0]
+    var = kT * (1.0 - c ** (2 * steps))
+    m = len(vs)
+    assert np.all(np.abs(vs.mean(axis=0) - mean) < 4.0 * math.sqrt(var / m))
+    assert np.all(np.abs(vs.var(axis=0) - var) < 4.0 * var * math.sqrt(2.0 / m))
+
+
+def test_langevin_without_noise_is_damped_ballistic_motion():
+    """kT = 0: the O step only damps, v -> c v; with F = 0 the position then
+    moves by h (v_n + v_(n+1)) per step, a closed-form geometric sum."""
+    box = np.array([8.0, 8.0, 8.0])
+    gamma, dt, steps = 0.5, 0.01, 50
+    x0 = np.array([[1.0], [2.0], [3.0]])
+    v0 = np.array([[0.3], [-0.2], [0.1]])
+    u = x0.copy()
+    _, v, _, _ = oracle.md_run(x0, v0, box, RS, RC, SKIN, dt, steps, seed=1, K=10,
+                               gamma=gamma, kT=0.0, unwrapped=u)
+    c = math.exp(-gamma * dt)
+    assert np.allclose(v, c ** steps * v0, rtol=1e-12)
+    disp = 0.5 * dt * v0 * (1.0 + c) * (1.0 - c ** steps) / (1.0 - c)
+    assert np.allclose(u - x0, disp, rtol=1e-11)
+
+
+def test_langevin_lj_fluid_settles_at_the_bath_temperature():
+    """An LJ fluid started hot (T = 2) relaxes to the bath, kT = 0.9: with
+    the full list the kinetic temperature averaged over the second half of
+    2000 steps is kT within 3% (equipartition; BAOAB's kinetic-temperature
+    bias is O(dt^2)).  The RBL force's extra variance heats the fluid
+    (Sec. II); under the thermostat the heating stays bounded, within 8% at
+    P = 10, and smaller at P = 40."""
+    st = inputs.lj_fluid(500, 0.8, 2.0, seed=5)
+    kT = 0.9
+    mean_t = {}
+    for use_full, p in ((True, 10), (False, 10), (False, 40)):
+        x, v = st.pos, st.vel
+        temps = []
+        for chunk in range(20):
+            x, v, _, _ = oracle.md_run(x, v, st.box, RS, RC, SKIN, 0.005, 100, p=p, seed=8,
+                                       step0=100 * chunk, K=10, use_full=use_full, gamma=1.0,
+                                       kT=kT)
+            if chunk >= 10:
+                temps.append((v ** 2).sum() / (3 * st.n - 3))
+        mean_t[(use_full, p)] = np.mean(temps)
+    assert abs(mean_t[(True, 10)] / kT - 1.0) < 0.03, mean_t
+    assert 0.97 < mean_t[(False, 10)] / kT < 1.08, mean_t
+    assert mean_t[(False, 40)] < mean_t[(False, 10)], mean_t
+
+
+# ------------------------------------------------------------ observables ---
+
+def test_rdf_counts_of_a_perfect_fcc_crystal():
+    """Ordered-pair counts of a perfect FCC crystal of lattice constant a:
+    12, 6, 24, 12, 24 neighbours per particle at a/sqrt(2), a, a sqrt(3/2),
+    a sqrt(2), a sqrt(5/2), and nothing in between."""
+    st = inputs.perfect_fcc(5, 0.9)
+    a = st.box[0] / 5
+    dr = a / 40.5
+    nbins = int(1.65 * a / dr)
+    counts = oracle.rdf_counts(st.pos, st.box, nbins * dr, nbins)
+    expect = np.zeros(nbins, dtype=np.uint64)
+    for mult, num in ((0.5, 12), (1.0, 6), (1.5, 24), (2.0, 12), (2.5, 24)):
+        expect[int(math.sqrt(mult) * a / dr)] += st.n * num
+    assert np.array_equal(counts, expect)
+
+
+def test_rdf_of_an_ideal_gas_is_flat():
+    """Uniform random points: the expected count in [r, r + dr) is
+    N (N - 1) / V times the shell volume, so g(r) = 1 within Poisson error."""
+    box = np.array([12.0, 12.0, 12.0])
+    st = inputs.random_gas(3000, box, seed=11)
+    nb, rmax = 20, 5.0
+    counts = oracle.rdf_counts(st.pos, box, rmax, nb).astype(float)
+    edges = np.arange(nb + 1) * (rmax / nb)
+    shell = 4.0 / 3.0 * math.pi * (edges[1:] ** 3 - edges[:-1] ** 3)
+    expected = st.n * (st.n - 1) / box.prod() * shell
+    z = (counts - expected) / np.sqrt(2.0 * expected)   # pairs come twice
+    assert np.all(np.abs(z[4:]) < 5.0)
+    assert abs(counts[4:].sum() / expected[4:].sum() - 1.0) < 0.01
+    assert int(counts.sum()) % 2 == 0
+
+
+def test_tail_corrections_equal_the_mean_field_integrals():
+    """(8/3) pi rho (...) and (16/3) pi rho^2 (...) against quadrature of
+    2 pi rho int_rc^inf u(r) r^2 dr and -(2 pi / 3) rho^2 int_rc^inf r u'(r)
+    r^2 dr for u = 4 (r^-12 - r^-6)."""
+    from scipy.integrate import quad
+    for rho, rc in ((0.2, 6.0), (0.8, 2.5), (0.8442, 3.5)):
+        ut, pt = oracle.tail(rho, rc)
+        iu = quad(lambda r: 4.0 * (r ** -12 - r ** -6) * r * r, rc, np.inf, epsabs=0, epsrel=1e-13)[0]
+        ip = quad(lambda r: r * 4.0 * (-12.0 * r ** -13 + 6.0 * r ** -7) * r * r, rc, np.inf,
+                  epsabs=0, epsrel=1e-13)[0]
+        assert ut == pytest.approx(2.0 * math.pi * rho * iu, rel=1e-10)
+        assert pt == pytest.approx(-2.0 * math.pi / 3.0 * rho * rho * ip, rel=1e-10)
