@@ -49,10 +49,15 @@ def parse():
     ap.add_argument("--cpu-rows", type=int, default=400_000,
                     help="rows of the N = 1M state the CPU oracle leg processes")
     ap.add_argument("--variants", default="all", help="comma list or 'all'")
+    ap.add_argument("--table1-equil", type=int, default=200_000,
+                    help="equilibration steps of the table1 workload")
+    ap.add_argument("--table1-prod", type=int, default=100_000,
+                    help="production steps of the table1 workload")
     ap.add_argument("--workloads", default="ensemble,large,slab",
                     help="further workloads reported beside the headline: comma list of "
                          "'ensemble' (512 replicas), 'large' (N = 2^24), 'slab' (charged "
-                         "slab, N = 2M, LJ + erfc), or 'none'")
+                         "slab, N = 2M, LJ + erfc), 'table1' (the Sec. III coexistence "
+                         "study, minutes of GPU time; not in the default), or 'none'")
     ap.add_argument("--summarize", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
                     help="instead of running: write the profiles/ summaries from the output "
                          "folders of a rocprofv3 --kernel-trace --stats run and two --pmc runs "
@@ -351,6 +356,108 @@ def run_large(torch, steps=200, warmup=20):
             "ms_per_step": 1e3 * el / steps, "status": status, "kernels_avg_us": avg}
 
 
+def rdf_from_counts(counts, frames, n, volume, dr):
+    """g(r) of Sec. III from ordered-pair counts per bin of width dr summed
+    over `frames` frames: counts / (frames N rho 4/3 pi ((k+1)^3 - k^3) dr^3),
+    rho = N / V.  Returns (bin centres, g)."""
+    counts = np.asarray(counts, dtype=np.float64)
+    nb = counts.shape[-1]
+    edges = np.arange(nb + 1) * dr
+    shell = 4.0 / 3.0 * np.pi * (edges[1:] ** 3 - edges[:-1] ** 3)
+    rho = n / volume
+    return 0.5 * (edges[1:] + edges[:-1]), counts / (frames * n * rho * shell)
+
+
+def msd_slope(times, msd, lo=0.2, hi=1.0):
+    """Least-squares slope of msd(t) over lo*t_max <= t <= hi*t_max, t_max
+    the longest lag: the long-time limit eta(t)/t of Sec. III (Table I)."""
+    times = np.asarray(times, dtype=np.float64)
+    msd = np.asarray(msd, dtype=np.float64)
+    tmax = times.max()
+    sel = (times >= lo * tmax) & (times <= hi * tmax)
+    A = np.vstack([times[sel], np.ones(sel.sum())]).T
+    return float(np.linalg.lstsq(A, msd[sel], rcond=None)[0][0])
+
+
+def run_table1(torch, equil=200_000, prod=100_000, every=1000, runs=10):
+    """The gas-liquid coexistence study of Sec. III (Table I): N = 2000,
+    density 0.2, T = 0.9, Langevin friction 1, dt = 0.002; direct truncation
+    at r_c = 6, 3, 2, and RBL with r_s = 2, r_c = 6 and P = 10, 20, 50, 100.
+    `runs` independent replicas (seeds 1..runs) per setting run in one
+    context.  After `equil` steps, `prod` steps are sampled every `every`
+    steps: g(r) (pair histogram, bins of 0.01 up to r = 2), the continuous
+    trajectory for the MSD, and u, P with tail corrections.  Reports, averaged
+    over the replicas, the first peak of g(r), the MSD slope lim eta(t)/t
+    (lags up to half the production run), u and P."""
+    from paper_2105_04884_amd import Context, inputs
+    n1, rho, kT, dt, gamma = 2000, 0.2, 0.9, 0.002, 1.0
+    states = [inputs.lj_fluid(n1, rho, kT, seed=s + 1) for s in range(runs)]
+    pos = np.concatenate([s.pos for s in states], axis=1)
+    vel = np.concatenate([s.vel for s in states], axis=1)
+    boxes = np.stack([s.box for s in states])
+    off = np.arange(runs + 1, dtype=np.int64) * n1
+    n = runs * n1
+    volume = float(np.prod(states[0].box))
+    r_max, nbins = 2.0, 200
+    dr = r_max / nbins
+    settings = [("DT r_c=6", True, 1.0, 6.0, 10), ("DT r_c=3", True, 1.0, 3.0, 10),
+                ("DT r_c=2", True, 1.0, 2.0, 10)]
+    settings += [(f"RBL r_s=2 r_c=6 P={P}", False, 2.0, 6.0, P) for P in (10, 20, 50, 100)]
+    frames = prod // every
+    out = {"workload": f"Sec. III gas-liquid coexistence: {runs} replicas of N={n1}, rho={rho}, "
+                       f"T={kT}, Langevin gamma={gamma}, dt={dt}, {equil} equilibration + {prod} "
+                       f"production steps, samples every {every}, lists every 10 steps, FP64",
+           "settings": {}}
+    for name, full, rs, rc, P in settings:
+        x, v = torch.from_numpy(pos).cuda(), torch.from_numpy(vel).cuda()
+        lists = ("full",) if full else ("core", "shell")
+        t0 = time.perf_counter()
+        with Context(n, replica_offsets=off, lists=lists, shift=False, skin=SKIN) as ctx:
+            ctx.set_thermostat(gamma, kT)
+            ctx.build(x, boxes, rs, rc)
+            s = 0
+            chunk = 20_000
+            while s < equil:
+                m = min(chunk, equil - s)
+                ctx.step(x, v, nsteps=m, dt=dt, P=P, seed=1, step0=s, rebuild_every=10, use_full=full)
+                s += m
+            log(f"[bench] table1 {name}: equilibrated ({equil} steps)")
+            counts = torch.zeros((runs, nbins), dtype=torch.int64, device="cuda")
+            snaps, us, ps, tks = [], [], [], []
+            for f in range(frames):
+                _, ev = ctx.step(x, v, nsteps=every, dt=dt, P=P, seed=1, step0=s, rebuild_every=10,
+                                 use_full=full, want_ev=True)
+                s += every
+                ctx.rdf(x, r_max, nbins, counts)
+                snaps.append(ctx.unwrap(x))
+                th = ctx.thermo(ev, v)
+                us.append(th[:, 0])
+                ps.append(th[:, 1])
+                tks.append(th[:, 2])
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            lags = np.arange(1, frames // 2 + 1)
+            msd = np.zeros((len(lags), runs))
+            for k, lag in enumerate(lags):
+                acc = torch.zeros(runs, dtype=torch.float64, device="cuda")
+                for t in range(frames - lag):
+                    acc += ctx.msd(snaps[t + lag], snaps[t])
+                msd[k] = (acc / (frames - lag)).cpu().numpy()
+        _, g = rdf_from_counts(counts.cpu().numpy(), frames, n1, volume, dr)
+        times = lags * every * dt
+        peaks = g.max(axis=1)
+        slopes = np.array([msd_slope(times, msd[:, r], lo=0.2, hi=1.0) for r in range(runs)])
+        res = {"peak_g": float(peaks.mean()), "peak_g_sem": float(peaks.std(ddof=1) / np.sqrt(runs)),
+               "msd_slope": float(slopes.mean()), "msd_slope_sem": float(slopes.std(ddof=1) / np.sqrt(runs)),
+               "u_per_particle": float(np.mean(us)), "pressure": float(np.mean(ps)),
+               "kinetic_T": float(np.mean(tks)), "seconds": el,
+               "atom_steps_per_s": n * (equil + prod) / el}
+        out["settings"][name] = res
+        log(f"[bench] table1 {name}: peak g {res['peak_g']:.3f}, MSD slope {res['msd_slope']:.3f}, "
+            f"u {res['u_per_particle']:.4f}, P {res['pressure']:.4f} ({el:.1f} s)")
+    return out
+
+
 def force_error_vs_oracle(x0, box, torch, rows):
     """Relative L2 error of the raw RBL force (P = 10, no mean subtraction)
     against the FP64 CPU oracle on sampled rows, for both precisions and
@@ -603,6 +710,9 @@ def main():
     if "slab" in wl:
         log("[bench] workload: charged slab")
         extra["slab"] = run_slab(torch)
+    if "table1" in wl:
+        log("[bench] workload: Sec. III gas-liquid coexistence (Table I)")
+        extra["table1"] = run_table1(torch, args.table1_equil, args.table1_prod)
 
     cpu = None
     cpu_full = None

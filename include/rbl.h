@@ -246,6 +246,73 @@ rbl_status rbl_launch_modes(rbl_ctx* ctx, int32_t* persistent_rbl, int32_t* pers
 rbl_status rbl_info(rbl_ctx* ctx, int64_t* n_slots, int32_t* cap_core,
                     int32_t* cap_shell, int32_t* cap_full);
 
+/* ---- thermostat and observables ---- */
+
+/*
+ * Langevin thermostat for rbl_step (Sec. II: m dv = (F - gamma v) dt +
+ * sqrt(2 gamma kT) dW; Sec. III: velocity Verlet with underdamped Langevin
+ * dynamics).  gamma = 0 (the default) is plain velocity Verlet (NVE).  With
+ * gamma > 0 each step is the BAOAB splitting (Leimkuhler & Matthews 2013):
+ *   v += (dt/2) F;  x += (dt/2) v;  v = c v + sqrt(kT (1 - c^2)) xi;
+ *   x += (dt/2) v;  [rebuild];  F = force(s);  v += (dt/2) F
+ * with c = exp(-gamma dt) and xi three standard normal numbers per particle:
+ * Box-Muller on the Philox4x32-10 block (key = seed of rbl_step, counter =
+ * (replica-local ID, s mod 2^32, replica, 2^31)), s being the force
+ * evaluation the step leads to.  Unit mass.  kT: host, one bath temperature
+ * per replica (may be NULL when gamma = 0).  Applies to later rbl_step calls.
+ * Errors: RBL_E_ARG (gamma < 0 or not finite, kT missing, negative or not
+ * finite).
+ */
+rbl_status rbl_set_thermostat(rbl_ctx* ctx, double gamma, const double* kT);
+
+/*
+ * Continuous trajectory for the mean-squared displacement eta(t) of
+ * Sec. III: out = pos + k L per component, where k counts the box lengths
+ * that the list builds of rbl_step took off each particle when wrapping it
+ * into the box (counted since the context was created; a run that is
+ * repeated after a capacity overflow counts once).  pos: positions written
+ * by the last rbl_step; pos, out: device SoA [3][n] (may alias).
+ * Errors: RBL_E_ARG, RBL_E_STATE (no box yet).
+ */
+rbl_status rbl_unwrap(rbl_ctx* ctx, const double* pos, double* out);
+
+/* out[r] = (1/n_r) sum_{i in replica r} |a_i - b_i|^2 (device, one double per
+ * replica): with unwrapped positions at two times, the mean-squared
+ * displacement of Sec. III.  a, b: device SoA [3][n].  Deterministic
+ * (fixed-order sums).  Errors: RBL_E_ARG, RBL_E_STATE (no replica table). */
+rbl_status rbl_msd(rbl_ctx* ctx, const double* a, const double* b, double* out);
+
+/*
+ * Pair-distance histogram behind the radial distribution function of
+ * Sec. III, g(r) = (1/(N rho)) sum_i sum_{j != i} <delta(r_ij - r)>/(4 pi r^2):
+ * counts[r*nbins + k] += the number of ordered pairs (i, j), i != j, of
+ * replica r at positions `pos` whose minimum-image distance lies in
+ * [k dr, (k+1) dr), dr = r_max/nbins (bins decided on r^2 against the squared
+ * edges).  counts: device uint64 [n_replicas][nbins], accumulated (the caller
+ * zeroes it), so frames can be summed; g(r) of bin k is then
+ * counts / (frames N rho 4/3 pi ((k+1)^3 - k^3) dr^3).  Pairs are found
+ * through the cells of the last build, so pos must be within skin/2 of the
+ * positions of that build (as after rbl_step).  pos: device SoA [3][n].
+ * Errors: RBL_E_ARG (NULL, r_max not in (0, r_c], nbins not in 1..2^20),
+ * RBL_E_STATE (no build).
+ */
+rbl_status rbl_rdf(rbl_ctx* ctx, const double* pos, double r_max, int nbins, uint64_t* counts);
+
+/*
+ * Potential energy per particle and pressure with the mean-field tail
+ * corrections of Sec. III (sigma = epsilon = 1, tails beyond r_c):
+ *   u = U/N + (8/3) pi rho (1/(3 r_c^9) - 1/r_c^3),
+ *   P = rho T + W/(3V) + (16/3) pi rho^2 (2/(3 r_c^9) - 1/r_c^3),
+ * with U, W the [U, W] pair of a force call (`ev`, device, 2 doubles per
+ * replica; W/(3V) is the (8/V) sum (2 r^-12 - r^-6) of Sec. III).  out
+ * (host, 4 doubles per replica): u; P with T = the thermostat's kT (NaN
+ * without a thermostat); the kinetic temperature sum v^2/(3 n_r - 3) from
+ * vel (device SoA, or NULL: NaN); P with that kinetic temperature.
+ * Synchronises.  Errors: RBL_E_ARG, RBL_E_STATE (no box, or a pair that is
+ * not the unshifted LJ: cfg.shift must be 0 and cfg.pair RBL_PAIR_LJ).
+ */
+rbl_status rbl_thermo(rbl_ctx* ctx, const double* vel, const double* ev, double* out);
+
 const char* rbl_last_error(void);
 const char* rbl_version(void);
 

@@ -185,6 +185,59 @@ class Context:
                                        int(rebuild_every), int(bool(use_full)), _dev_ptr(ev)))
         return st, ev
 
+    # -- thermostat and observables ----------------------------------------
+    def set_thermostat(self, gamma: float, kT=None):
+        """Langevin friction ``gamma`` (0: NVE) and bath temperature ``kT``
+        (a number or one per replica) for later ``step`` calls."""
+        kt = None
+        if kT is not None:
+            kt = np.ascontiguousarray(np.broadcast_to(np.asarray(kT, dtype=np.float64),
+                                                      (self.n_replicas,)))
+        _check(self._lib.rbl_set_thermostat(
+            self._h, float(gamma), None if kt is None else kt.ctypes.data_as(C.POINTER(C.c_double))))
+
+    def unwrap(self, pos, out=None):
+        """Positions without the wraps of the list builds (continuous
+        trajectory), as a new tensor or in ``out``."""
+        torch = _torch()
+        if out is None:
+            out = torch.empty((3, self.n), dtype=torch.float64, device="cuda")
+        _check(self._lib.rbl_unwrap(self._h, _dev_ptr(pos, (3, self.n), "pos"),
+                                    _dev_ptr(out, (3, self.n), "out")))
+        return out
+
+    def msd(self, a, b):
+        """Per-replica mean of |a_i - b_i|^2 (device tensor)."""
+        torch = _torch()
+        out = torch.empty(self.n_replicas, dtype=torch.float64, device="cuda")
+        _check(self._lib.rbl_msd(self._h, _dev_ptr(a, (3, self.n), "a"), _dev_ptr(b, (3, self.n), "b"),
+                                 _dev_ptr(out)))
+        return out
+
+    def rdf(self, pos, r_max: float, nbins: int, counts=None):
+        """Adds the ordered-pair distance histogram at ``pos`` to ``counts``
+        (int64 tensor [n_replicas, nbins] holding the uint64 counts; a zeroed
+        one is made if None) and returns it."""
+        torch = _torch()
+        if counts is None:
+            counts = torch.zeros((self.n_replicas, int(nbins)), dtype=torch.int64, device="cuda")
+        if (not isinstance(counts, torch.Tensor) or not counts.is_cuda or counts.dtype != torch.int64
+                or not counts.is_contiguous() or tuple(counts.shape) != (self.n_replicas, int(nbins))):
+            raise ValueError("counts must be a contiguous int64 CUDA tensor [n_replicas, nbins]")
+        _check(self._lib.rbl_rdf(self._h, _dev_ptr(pos, (3, self.n), "pos"), float(r_max), int(nbins),
+                                 C.c_void_p(counts.data_ptr())))
+        return counts
+
+    def thermo(self, ev, vel=None) -> np.ndarray:
+        """[n_replicas, 4]: energy per particle and pressure with tail
+        corrections (pressure at the bath kT, kinetic temperature, pressure
+        at the kinetic temperature); see rbl_thermo."""
+        out = np.zeros((self.n_replicas, 4))
+        _check(self._lib.rbl_thermo(self._h, _dev_ptr(vel, (3, self.n), "vel"),
+                                    _dev_ptr(ev, (2 * self.n_replicas,), "ev"),
+                                    out.ctypes.data_as(C.POINTER(C.c_double))))
+        return out
+
     # -- parity exports ----------------------------------------------------
     def row_counts(self, rows=None):
         rows_arr = None if rows is None else np.ascontiguousarray(rows, dtype=np.int64)

@@ -63,6 +63,7 @@ _names = [
     "rbl_config_init", "rbl_create", "rbl_destroy", "rbl_build", "rbl_forces", "rbl_full_forces",
     "rbl_step", "rbl_row_counts", "rbl_export_lists", "rbl_export_batches", "rbl_export_binning",
     "rbl_sync", "rbl_set_profiling", "rbl_kernel_stats", "rbl_info", "rbl_tuning", "rbl_launch_modes",
+    "rbl_set_thermostat", "rbl_unwrap", "rbl_msd", "rbl_rdf", "rbl_thermo",
     "rbl_last_error",
     "rbl_version",
 ]
@@ -103,6 +104,11 @@ def load(path: str = LIB_PATH):
         "rbl_info": (i32, [vp, p64, p32, p32, p32]),
         "rbl_tuning": (i32, [vp, p32, p32, pd]),
         "rbl_launch_modes": (i32, [vp, p32, p32, pd]),
+        "rbl_set_thermostat": (i32, [vp, d, pd]),
+        "rbl_unwrap": (i32, [vp, vp, vp]),
+        "rbl_msd": (i32, [vp, vp, vp, vp]),
+        "rbl_rdf": (i32, [vp, vp, d, i32, vp]),
+        "rbl_thermo": (i32, [vp, vp, vp, pd]),
         "rbl_last_error": (C.c_char_p, []),
         "rbl_version": (C.c_char_p, []),
     }

@@ -303,6 +303,7 @@ struct GatherArgs {
     double* vs;               // may be null
     double* xb;               // positions at the build, [3][n_slots] (skin monitor)
     int* slot_of_id;
+    int* img_delta;           // may be null: [3][n] box lengths taken off by the wrap
 };
 
 template <int SRC, bool VEL>
@@ -342,7 +343,15 @@ __global__ __launch_bounds__(256) void k_gather(GatherArgs a)
     }
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        x[d] = isfinite(x[d]) ? wrap_coord(x[d], R.L[d], R.inv[d]) : 0.0;
+        if (isfinite(x[d])) {
+            // the wrap of wrap_coord, keeping its box count for the
+            // continuous trajectory
+            const double k = floor(x[d] * R.inv[d]);
+            x[d] = fma(-k, R.L[d], x[d]);
+            if (a.img_delta && k != 0.0) a.img_delta[d * a.n + id] += (int)k;
+        } else {
+            x[d] = 0.0;
+        }
         a.xb[d * a.n_slots + s] = x[d];
     }
     a.xs[s] = make_double4(x[0], x[1], x[2], q);
@@ -1483,7 +1492,40 @@ struct IntArgs {
     int momentum_fix;
     double half_skin2;
     int* flags;
+    // Langevin thermostat (BAOAB) when `langevin`: v <- oc v + osig[r] xi
+    int langevin;
+    double oc;
+    const double* osig;    // per replica sqrt(kT (1 - oc^2))
+    const int* perm;
+    uint64_t seed;
+    uint64_t step;             // force evaluation the step leads to
+    const uint64_t* step_dev;  // if set, the step is *step_dev + step
 };
+
+// The three standard normal numbers of the Ornstein-Uhlenbeck step of
+// particle pid (replica-local ID) before force evaluation `step`: the
+// Philox block with counter (pid, step mod 2^32, replica, 2^31) -- batch
+// draws use the blocks below 2^31 -- and Box-Muller (1958) on its two word
+// pairs, each word w taken as the uniform (w + 1/2) 2^-32 in (0, 1).
+constexpr uint32_t kNoiseBlock = 0x80000000u;
+
+__device__ __forceinline__ void langevin_noise(uint64_t seed, uint32_t pid, uint32_t step, uint32_t replica,
+                                               double g[3])
+{
+    uint32_t w0 = pid, w1 = step, w2 = replica, w3 = kNoiseBlock;
+    philox4x32_10(w0, w1, w2, w3, (uint32_t)seed, (uint32_t)(seed >> 32));
+    constexpr double kTwoM32 = 2.3283064365386962890625e-10;  // 2^-32
+    constexpr double kTwoPi = 6.283185307179586476925286766559;
+    const double u0 = ((double)w0 + 0.5) * kTwoM32;
+    const double u1 = ((double)w1 + 0.5) * kTwoM32;
+    const double u2 = ((double)w2 + 0.5) * kTwoM32;
+    const double u3 = ((double)w3 + 0.5) * kTwoM32;
+    const double r0 = sqrt(-2.0 * log(u0));
+    const double r1 = sqrt(-2.0 * log(u2));
+    g[0] = r0 * cos(kTwoPi * u1);
+    g[1] = r0 * sin(kTwoPi * u1);
+    g[2] = r1 * cos(kTwoPi * u3);
+}
 
 template <int MODE>
 __global__ __launch_bounds__(256) void k_integrate(IntArgs a)
@@ -1507,15 +1549,33 @@ __global__ __launch_bounds__(256) void k_integrate(IntArgs a)
         F[d] = a.f[d * a.n_slots + s] - fc[d];
         v[d] = v[d] + a.h * F[d];
         if (MODE == kIntMid) v[d] = v[d] + a.h * F[d];
-        a.vs[d * a.n_slots + s] = v[d];
     }
-    if (MODE != kIntLast) {
+    if (MODE != kIntLast && a.langevin) {
+        // A (half drift), O (exact Ornstein-Uhlenbeck step), A
+        double g[3];
+        const uint64_t step = a.step_dev ? *a.step_dev + a.step : a.step;
+        langevin_noise(a.seed, (uint32_t)(a.perm[s] - R.id_base), (uint32_t)step, (uint32_t)r, g);
+        const double sig = a.osig[r];
+        double4 x = a.xs[s];
+        x.x = x.x + a.h * v[0];
+        x.y = x.y + a.h * v[1];
+        x.z = x.z + a.h * v[2];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) v[d] = a.oc * v[d] + sig * g[d];
+        x.x = x.x + a.h * v[0];
+        x.y = x.y + a.h * v[1];
+        x.z = x.z + a.h * v[2];
+        a.xs[s] = x;
+    } else if (MODE != kIntLast) {
         double4 x = a.xs[s];
         x.x = x.x + a.dt * v[0];
         x.y = x.y + a.dt * v[1];
         x.z = x.z + a.dt * v[2];
         a.xs[s] = x;
-    } else {
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) a.vs[d * a.n_slots + s] = v[d];
+    if (MODE == kIntLast) {
         // displacement since the last build (the rebuilds check their own
         // list lifetimes while binning)
         const double4 x = a.xs[s];
@@ -1545,6 +1605,8 @@ struct IoArgs {
     double* pos_out;
     double* vel_out;
     double* f_out;
+    const int* img_delta;  // if set, added into img ([3][n], caller order)
+    int* img;
 };
 
 // xs[slot] <- caller positions as given (no wrapping), for a force call.
@@ -1582,6 +1644,149 @@ __global__ __launch_bounds__(256) void k_scatter_out(IoArgs a)
         for (int d = 0; d < 3; ++d) {
             const double fc = a.momentum_fix ? a.rep_sum[8 * r + d] / nr : 0.0;
             a.f_out[d * a.n + id] = a.f[d * a.n_slots + s] - fc;
+        }
+    }
+    if (a.img_delta) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) a.img[d * a.n + id] += a.img_delta[d * a.n + id];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Observables of Sec. III: continuous trajectory (for the mean-squared
+// displacement), per-replica sums of squares, and the pair-distance
+// histogram behind the radial distribution function.
+
+// out = pos + img L (caller order): the positions without the wraps the
+// list builds applied since the counters were set up.
+__global__ __launch_bounds__(256) void k_unwrap(const DevReplica* rep, const int* id_rep, const double* pos,
+                                                const int* img, int64_t n, double* out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const DevReplica& R = rep[id_rep[i]];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double k = img ? (double)img[d * n + i] : 0.0;
+        out[d * n + i] = fma(k, R.L[d], pos[d * n + i]);
+    }
+}
+
+// Per replica r and chunk b (grid (nb, R)): partial[r * nb + b] = sum over
+// the replica's particles i = id_base + b*256*kSqIter ... of |a_i - b_i|^2
+// (b may be null), in a fixed order: deterministic.
+constexpr int kSqIter = 16;
+
+__global__ __launch_bounds__(256) void k_sumsq(const DevReplica* rep, const double* x, const double* y, int64_t n,
+                                               int nb, double* partial)
+{
+    __shared__ double s_red[256];
+    const int r = blockIdx.y;
+    const int64_t base = rep[r].id_base;
+    const int64_t nr = rep[r].n;
+    double acc = 0.0;
+    for (int it = 0; it < kSqIter; ++it) {
+        const int64_t k = ((int64_t)blockIdx.x * kSqIter + it) * blockDim.x + threadIdx.x;
+        if (k < nr) {
+            const int64_t i = base + k;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const double v = y ? x[d * n + i] - y[d * n + i] : x[d * n + i];
+                acc = fma(v, v, acc);
+            }
+        }
+    }
+    s_red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) s_red[threadIdx.x] += s_red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[(int64_t)r * nb + blockIdx.x] = s_red[0];
+}
+
+// out[r] = scale_r * sum_b partial[r * nb + b], scale_r = 1 / (n_r * div)
+__global__ void k_sumsq_final(const DevReplica* rep, const double* partial, int nb, int R, double div, double* out)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= R) return;
+    double t = 0.0;
+    for (int b = 0; b < nb; ++b) t += partial[(int64_t)r * nb + b];
+    out[r] = t / ((double)rep[r].n * div);
+}
+
+// Pair-distance histogram: counts[r * nbins + k] += the ordered pairs (i, j),
+// i != j, of replica r with minimum-image distance in [k dr, (k+1) dr),
+// r < r_max = nbins dr; the bin decided on r^2 against the squared edges
+// (k dr)(k dr).  One lane per particle walks the 5x5x5 stencil of its
+// build-time cell (the stencil reaches r_c + skin, so every pair closer
+// than r_max <= r_c is found while no particle has moved skin/2).
+struct RdfArgs {
+    const DevReplica* rep;
+    const int* slice_rep;
+    const int* perm;
+    const double4* xs;
+    const double* xb;
+    const int* cell_start;
+    const int* cell_count;
+    int64_t n_slots;
+    int64_t n_slices;
+    double dr;
+    double top2;   // (nbins dr)^2
+    int nbins;
+    unsigned long long* counts;
+};
+
+__device__ __forceinline__ double rdf_edge2(int k, double dr)
+{
+    const double e = (double)k * dr;
+    return e * e;
+}
+
+__global__ __launch_bounds__(256) void k_rdf(RdfArgs a)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if ((s >> 6) >= a.n_slices) return;
+    const int r = a.slice_rep[s >> 6];
+    const DevReplica& R = a.rep[r];
+    if (s - R.slot_base >= R.n || a.perm[s] < 0) return;
+    int cc[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        // the cell the build put the particle in (xb holds the wrapped
+        // build-time position the binning used)
+        int k = (int)floor(a.xb[d * a.n_slots + s] * R.cscale[d]);
+        cc[d] = k < 0 ? 0 : (k > R.nc[d] - 1 ? R.nc[d] - 1 : k);
+    }
+    const AxisRuns ax = axis_runs(cc[0], R.nc[0]);
+    const AxisRuns ay = axis_runs(cc[1], R.nc[1]);
+    const AxisRuns az = axis_runs(cc[2], R.nc[2]);
+    const double4 xi = a.xs[s];
+    unsigned long long* cnt = a.counts + (int64_t)r * a.nbins;
+    for (int zi = 0; zi < az.l0 + az.l1; ++zi) {
+        const int z = axis_cell(az, zi);
+        for (int yi = 0; yi < ay.l0 + ay.l1; ++yi) {
+            const int y = axis_cell(ay, yi);
+            for (int xi_ = 0; xi_ < ax.l0 + ax.l1; ++xi_) {
+                const int x = axis_cell(ax, xi_);
+                const int64_t c = R.cell_base + ((int64_t)z * R.nc[1] + y) * R.nc[0] + x;
+                const int j0 = a.cell_start[c];
+                const int j1 = j0 + a.cell_count[c];
+                for (int j = j0; j < j1; ++j) {
+                    if (j == s) continue;
+                    const double4 xj = a.xs[j];
+                    const double dx = min_image(xi.x - xj.x, R.L[0], R.inv[0]);
+                    const double dy = min_image(xi.y - xj.y, R.L[1], R.inv[1]);
+                    const double dz = min_image(xi.z - xj.z, R.L[2], R.inv[2]);
+                    const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+                    if (!(r2 < a.top2)) continue;
+                    int k = (int)(sqrt(r2) / a.dr);
+                    if (k > a.nbins - 1) k = a.nbins - 1;
+                    while (k > 0 && r2 < rdf_edge2(k, a.dr)) --k;
+                    while (k < a.nbins - 1 && r2 >= rdf_edge2(k + 1, a.dr)) ++k;
+                    atomicAdd(&cnt[k], 1ull);
+                }
+            }
         }
     }
 }

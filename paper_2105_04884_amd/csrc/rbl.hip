@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <limits>
 #include <string>
 #include <vector>
 
@@ -97,6 +98,17 @@ struct rbl_ctx {
     int cap_list = 0;           // fused kernel: LDS shell-list room per centre particle
     bool stencil = false;       // batches drawn from the stencil cells (N_I in d_nI)
     int* d_nI = nullptr;        // stencil draw population size per slot
+
+    // Langevin thermostat (rbl_set_thermostat) and the continuous trajectory
+    double gamma = 0.0;              // friction; 0: NVE
+    std::vector<double> kT;          // bath temperature per replica
+    double* d_osig = nullptr;        // per replica sqrt(kT (1 - c^2)) of the last run
+    std::vector<double> h_osig;      // its host copy (source of the upload)
+    int* d_img = nullptr;            // [3][n] box lengths the builds of rbl_step took off
+    int* d_img_delta = nullptr;      // the same for the run in progress
+    bool track_images = false;       // binning inside rbl_step counts wraps
+    double* d_sq_part = nullptr;     // partial sums of k_sumsq
+    int sq_nb = 0;
     double r_s = 0, r_c = 0;
     std::vector<DevReplica> h_rep;
     int64_t n_cells = 0, cells_alloc = 0;
@@ -393,6 +405,7 @@ rbl_status bin_particles(rbl_ctx* c, const double* pos, const double* vel, bool 
     g.vs = c->d_vs[nxt];
     g.xb = c->d_xb;
     g.slot_of_id = c->d_slot_of_id;
+    g.img_delta = c->track_images ? c->d_img_delta : nullptr;
     RBL_TRY(timed(c, kKBin, [&] {
         if (with_vel)
             k_gather<SRC, true><<<grid_for(c->n_slots), kBlock, 0, c->ls>>>(g);
@@ -802,6 +815,8 @@ IoArgs io_args(rbl_ctx* c, bool momentum_fix)
     io.pos_out = nullptr;
     io.vel_out = nullptr;
     io.f_out = nullptr;
+    io.img_delta = nullptr;
+    io.img = nullptr;
     return io;
 }
 
@@ -813,9 +828,20 @@ rbl_status emit_ev(rbl_ctx* c, double* ev)
     return RBL_OK;
 }
 
-rbl_status integrate(rbl_ctx* c, int mode, double dt, bool momentum_fix)
+// Velocity-Verlet kick/drift, or with a thermostat the BAOAB step (its
+// noise keyed by the force evaluation `step` the step leads to, or
+// *step_dev + step).
+rbl_status integrate(rbl_ctx* c, int mode, double dt, bool momentum_fix, uint64_t seed = 0,
+                     uint64_t step = 0, const uint64_t* step_dev = nullptr)
 {
     IntArgs a;
+    a.langevin = c->gamma > 0.0 ? 1 : 0;
+    a.oc = std::exp(-c->gamma * dt);
+    a.osig = c->d_osig;
+    a.perm = c->cur_perm();
+    a.seed = seed;
+    a.step = step;
+    a.step_dev = step_dev;
     a.rep = c->d_rep;
     a.slice_rep = c->d_slice_rep;
     a.rep_sum = c->d_rep_sum;
@@ -904,6 +930,9 @@ std::vector<unsigned char> block_signature(const rbl_ctx* c, const StepParams& s
     sig_put(v, (const void*)c->d_cell_start);
     sig_put(v, (const void*)c->d_cell_rep);
     sig_put(v, c->profiling);
+    sig_put(v, c->gamma);
+    sig_put(v, (const void*)c->d_osig);
+    sig_put(v, (const void*)c->d_img_delta);
     return v;
 }
 
@@ -913,7 +942,7 @@ std::vector<unsigned char> block_signature(const rbl_ctx* c, const StepParams& s
 rbl_status queue_block(rbl_ctx* c, const StepParams& sp)
 {
     const int mask = sp.full ? RBL_LIST_FULL : (RBL_LIST_CORE | RBL_LIST_SHELL);
-    RBL_TRY(integrate(c, kIntMid, sp.dt, sp.fix));
+    RBL_TRY(integrate(c, kIntMid, sp.dt, sp.fix, sp.seed, 0, c->d_step));
     RBL_TRY(bin_particles<kSrcSorted>(c, nullptr, nullptr, true));
     if (sp.pre) {
         RBL_TRY(launch_fused(c, sp.P, sp.seed, 0, (int)sp.K, c->d_step));
@@ -922,7 +951,7 @@ rbl_status queue_block(rbl_ctx* c, const StepParams& sp)
         RBL_TRY(timed(c, kKBuild, [&] { launch_build<false>(c, a, mask); }));
     }
     for (int64_t r = 0; r < sp.K; ++r) {
-        if (r > 0) RBL_TRY(integrate(c, kIntMid, sp.dt, sp.fix));
+        if (r > 0) RBL_TRY(integrate(c, kIntMid, sp.dt, sp.fix, sp.seed, (uint64_t)r, c->d_step));
         if (sp.full) RBL_TRY(full_force_sorted(c, false));
         else if (sp.pre) RBL_TRY(rbl_force_sorted(c, sp.P, sp.seed, 0, (int)r, false));
         else RBL_TRY(rbl_force_sorted(c, sp.P, sp.seed, (uint64_t)r, -1, false, c->d_step));
@@ -1052,6 +1081,27 @@ rbl_status md_run(rbl_ctx* c, double* pos, double* vel, double* force, int64_t n
         c->ls = c->gs;
     }
     RBL_TRY(clear_flags(c));
+    // wraps of this run's builds are counted apart and added to the
+    // trajectory's image counters only when the run completes
+    if (!c->d_img) {
+        RBL_TRY(dalloc(&c->d_img, 3 * (size_t)c->n));
+        RBL_TRY(fill_i32(c, c->d_img, 3 * c->n, 0));
+    }
+    if (!c->d_img_delta) RBL_TRY(dalloc(&c->d_img_delta, 3 * (size_t)c->n));
+    RBL_TRY(fill_i32(c, c->d_img_delta, 3 * c->n, 0));
+    struct TrackGuard {
+        rbl_ctx* c;
+        ~TrackGuard() { c->track_images = false; }
+    } track{c};
+    c->track_images = true;
+    if (c->gamma > 0.0) {
+        if (!c->d_osig) RBL_TRY(dalloc(&c->d_osig, (size_t)c->R));
+        const double oc = std::exp(-c->gamma * dt);
+        c->h_osig.resize(c->R);
+        for (int r = 0; r < c->R; ++r) c->h_osig[r] = std::sqrt(c->kT[r] * (1.0 - oc * oc));
+        HIP_TRY(hipMemcpyAsync(c->d_osig, c->h_osig.data(), sizeof(double) * c->R, hipMemcpyHostToDevice,
+                               c->ls));
+    }
     const int64_t last = step0 + nsteps;
     int64_t build_step = step0;
 
@@ -1100,7 +1150,7 @@ rbl_status md_run(rbl_ctx* c, double* pos, double* vel, double* force, int64_t n
             it += K;
             continue;
         }
-        RBL_TRY(integrate(c, it == 1 ? kIntFirst : kIntMid, dt, sp.fix));
+        RBL_TRY(integrate(c, it == 1 ? kIntFirst : kIntMid, dt, sp.fix, seed, (uint64_t)s));
         if (s % K == 0) RBL_TRY(do_build(s, false));
         RBL_TRY(do_force(s, ev != nullptr && it == nsteps));
         ++it;
@@ -1125,6 +1175,8 @@ rbl_status md_run(rbl_ctx* c, double* pos, double* vel, double* force, int64_t n
     io.pos_out = pos;
     io.vel_out = vel;
     io.f_out = force;
+    io.img_delta = c->d_img_delta;
+    io.img = c->d_img;
     k_scatter_out<<<grid_for(c->n_slots), kBlock, 0, c->ls>>>(io);
     HIP_TRY(hipGetLastError());
     RBL_TRY(emit_ev(c, ev));
@@ -1139,6 +1191,24 @@ rbl_status md_run(rbl_ctx* c, double* pos, double* vel, double* force, int64_t n
     return RBL_OK;
 }
 
+// out[r] = (1 / n_r) sum over replica r of |x - y|^2 (y may be null)
+rbl_status mean_sq(rbl_ctx* c, const double* x, const double* y, double* out)
+{
+    int64_t most = 1;
+    for (int r = 0; r < c->R; ++r) most = std::max(most, c->rep_n[r]);
+    const int nb = (int)((most + 256 * kSqIter - 1) / (256 * kSqIter));
+    if (nb > c->sq_nb) {
+        dfree(c->d_sq_part);
+        c->sq_nb = 0;
+        RBL_TRY(dalloc(&c->d_sq_part, (size_t)nb * c->R));
+        c->sq_nb = nb;
+    }
+    k_sumsq<<<dim3(nb, c->R), 256, 0, c->ls>>>(c->d_rep, x, y, c->n, nb, c->d_sq_part);
+    HIP_TRY(hipGetLastError());
+    k_sumsq_final<<<(c->R + 63) / 64, 64, 0, c->ls>>>(c->d_rep, c->d_sq_part, nb, c->R, 1.0, out);
+    HIP_TRY(hipGetLastError());
+    return RBL_OK;
+}
 }  // namespace
 
 // ===========================================================================
@@ -1216,6 +1286,10 @@ rbl_status rbl_destroy(rbl_ctx* c)
     }
     dfree(c->d_batch);
     dfree(c->d_nI);
+    dfree(c->d_osig);
+    dfree(c->d_img);
+    dfree(c->d_img_delta);
+    dfree(c->d_sq_part);
     dfree(c->d_partial);
     dfree(c->d_part2);
     dfree(c->d_rep_sum);
@@ -1268,6 +1342,7 @@ rbl_status rbl_create(const rbl_config* cfg, void* hip_stream, rbl_ctx** out)
     if (cfg->lanes > 0) c->lpp_rbl = c->lpp_full = cfg->lanes;
     c->persist[0] = c->persist[1] = cfg->persistent == 2;
     c->stencil = cfg->shell_source == RBL_SHELL_STENCIL;
+    c->kT.assign(c->R, 1.0);
     {
         int dev = 0, ncu = 0;
         if (hipGetDevice(&dev) == hipSuccess &&
@@ -1656,6 +1731,114 @@ rbl_status rbl_info(rbl_ctx* c, int64_t* n_slots, int32_t* cap_core, int32_t* ca
     if (cap_core) *cap_core = c->cap[0];
     if (cap_shell) *cap_shell = c->cap[1];
     if (cap_full) *cap_full = c->cap[2];
+    return RBL_OK;
+}
+
+// ---- thermostat and observables (Sec. II Langevin dynamics, Sec. III) ----
+
+rbl_status rbl_set_thermostat(rbl_ctx* c, double gamma, const double* kT)
+{
+    if (!c) return fail(RBL_E_ARG, "NULL context");
+    if (!(gamma >= 0.0) || !std::isfinite(gamma)) return fail(RBL_E_ARG, "gamma must be finite and >= 0");
+    if (gamma > 0.0 && !kT) return fail(RBL_E_ARG, "kT is required when gamma > 0");
+    if (kT)
+        for (int r = 0; r < c->R; ++r)
+            if (!(kT[r] >= 0.0) || !std::isfinite(kT[r])) return fail(RBL_E_ARG, "kT must be finite and >= 0");
+    c->gamma = gamma;
+    if (kT) c->kT.assign(kT, kT + c->R);
+    return RBL_OK;
+}
+
+rbl_status rbl_unwrap(rbl_ctx* c, const double* pos, double* out)
+{
+    if (!c || !pos || !out) return fail(RBL_E_ARG, "NULL argument");
+    if (c->r_c <= 0.0) return fail(RBL_E_STATE, "rbl_unwrap needs the boxes of an rbl_build");
+    k_unwrap<<<grid_for(c->n), kBlock, 0, c->ls>>>(c->d_rep, c->d_id_rep, pos, c->d_img, c->n, out);
+    HIP_TRY(hipGetLastError());
+    return RBL_OK;
+}
+
+
+rbl_status rbl_msd(rbl_ctx* c, const double* a, const double* b, double* out)
+{
+    if (!c || !a || !b || !out) return fail(RBL_E_ARG, "NULL argument");
+    if (c->r_c <= 0.0) return fail(RBL_E_STATE, "rbl_msd needs the replica table of an rbl_build");
+    return mean_sq(c, a, b, out);
+}
+
+rbl_status rbl_rdf(rbl_ctx* c, const double* pos, double r_max, int nbins, uint64_t* counts)
+{
+    if (!c || !pos || !counts) return fail(RBL_E_ARG, "NULL argument");
+    if (!c->built) return fail(RBL_E_STATE, "rbl_rdf needs a list build first");
+    if (!(r_max > 0.0) || !(r_max <= c->r_c)) return fail(RBL_E_ARG, "r_max must be in (0, r_c]");
+    if (nbins < 1 || nbins > (1 << 20)) return fail(RBL_E_ARG, "nbins must be in 1 .. 2^20");
+    IoArgs io = io_args(c, false);
+    io.pos_in = pos;
+    k_load_positions<<<grid_for(c->n_slots), kBlock, 0, c->ls>>>(io);
+    HIP_TRY(hipGetLastError());
+    RdfArgs a;
+    a.rep = c->d_rep;
+    a.slice_rep = c->d_slice_rep;
+    a.perm = c->cur_perm();
+    a.xs = c->cur_xs();
+    a.xb = c->d_xb;
+    a.cell_start = c->d_cell_start;
+    a.cell_count = c->d_cell_count;
+    a.n_slots = c->n_slots;
+    a.n_slices = c->n_slices;
+    a.dr = r_max / (double)nbins;
+    {
+        const double e = (double)nbins * a.dr;
+        a.top2 = e * e;
+    }
+    a.nbins = nbins;
+    a.counts = reinterpret_cast<unsigned long long*>(counts);
+    k_rdf<<<grid_for(c->n_slots), kBlock, 0, c->ls>>>(a);
+    HIP_TRY(hipGetLastError());
+    return RBL_OK;
+}
+
+rbl_status rbl_thermo(rbl_ctx* c, const double* vel, const double* ev, double* out)
+{
+    if (!c || !ev || !out) return fail(RBL_E_ARG, "NULL argument");
+    if (c->r_c <= 0.0) return fail(RBL_E_STATE, "rbl_thermo needs the boxes of an rbl_build");
+    if (c->cfg.shift || c->cfg.pair != RBL_PAIR_LJ)
+        return fail(RBL_E_STATE, "rbl_thermo needs the unshifted LJ pair (cfg.shift = 0, RBL_PAIR_LJ)");
+    std::vector<double> h_ev(2 * (size_t)c->R), h_msq(c->R, 0.0);
+    double* d_msq = nullptr;
+    if (vel) {
+        RBL_TRY(dalloc(&d_msq, (size_t)c->R));
+        const rbl_status st = mean_sq(c, vel, nullptr, d_msq);
+        if (st < 0) {
+            dfree(d_msq);
+            return st;
+        }
+        (void)hipMemcpyAsync(h_msq.data(), d_msq, sizeof(double) * c->R, hipMemcpyDeviceToHost, c->ls);
+    }
+    (void)hipMemcpyAsync(h_ev.data(), ev, sizeof(double) * 2 * c->R, hipMemcpyDeviceToHost, c->ls);
+    const hipError_t e = hipStreamSynchronize(c->ls);
+    dfree(d_msq);
+    if (e != hipSuccess) return fail(RBL_E_HIP, hipGetErrorString(e));
+    // mean-field tails beyond r_c (sigma = epsilon = 1):
+    //   u_tail = (8/3) pi rho (r_c^-9 / 3 - r_c^-3),
+    //   p_tail = (16/3) pi rho^2 (2 r_c^-9 / 3 - r_c^-3)
+    const double nan = std::numeric_limits<double>::quiet_NaN();
+    const double c3 = 1.0 / (c->r_c * c->r_c * c->r_c);
+    const double c9 = c3 * c3 * c3;
+    for (int r = 0; r < c->R; ++r) {
+        const DevReplica& R = c->h_rep[r];
+        const double V = R.L[0] * R.L[1] * R.L[2];
+        const double nr = (double)c->rep_n[r];
+        const double rho = nr / V;
+        const double ut = 8.0 / 3.0 * M_PI * rho * (c9 / 3.0 - c3);
+        const double pt = 16.0 / 3.0 * M_PI * rho * rho * (2.0 * c9 / 3.0 - c3);
+        const double pw = h_ev[2 * r + 1] / (3.0 * V);
+        const double tk = (vel && c->rep_n[r] > 1) ? h_msq[r] * nr / (3.0 * nr - 3.0) : nan;
+        out[4 * r + 0] = h_ev[2 * r] / nr + ut;
+        out[4 * r + 1] = c->gamma > 0.0 ? rho * c->kT[r] + pw + pt : nan;
+        out[4 * r + 2] = tk;
+        out[4 * r + 3] = rho * tk + pw + pt;
+    }
     return RBL_OK;
 }
 

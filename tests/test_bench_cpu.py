@@ -59,3 +59,27 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=60)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_rdf_normalisation_of_an_ideal_gas():
+    """g(r) from the oracle's pair counts of uniform random points is 1
+    within Poisson error away from r = 0."""
+    import oracle
+    from paper_2105_04884_amd import inputs
+    box = np.array([12.0, 12.0, 12.0])
+    frames, n, nb, rmax = 3, 1500, 25, 5.0
+    counts = np.zeros(nb)
+    for f in range(frames):
+        st = inputs.random_gas(n, box, seed=20 + f)
+        counts += oracle.rdf_counts(st.pos, box, rmax, nb)
+    r, g = bench.rdf_from_counts(counts, frames, n, float(box.prod()), rmax / nb)
+    assert np.allclose(r[:2], [0.1, 0.3])
+    assert abs(g[5:].mean() - 1.0) < 0.02
+
+
+def test_msd_slope_of_a_line():
+    t = np.linspace(0.1, 10.0, 100)
+    assert bench.msd_slope(t, 2.5 * t + 0.3) == pytest.approx(2.5, rel=1e-12)
+    # a ballistic start is left out of the fit window
+    m = np.where(t < 1.0, t * t, 2.0 * t - 1.0)
+    assert bench.msd_slope(t, m) == pytest.approx(2.0, rel=1e-12)

@@ -94,4 +94,11 @@ def test_calls_reject_null_context(lib):
     assert lib.rbl_step(None, None, None, None, 10, 0.005, 10, 1, 0, 10, 0, None) == _lib.RBL_E_ARG
     assert lib.rbl_sync(None) == _lib.RBL_E_ARG
     assert lib.rbl_set_profiling(None, 1) == _lib.RBL_E_ARG
+    kt = (C.c_double * 1)(1.0)
+    assert lib.rbl_set_thermostat(None, 1.0, kt) == _lib.RBL_E_ARG
+    assert lib.rbl_unwrap(None, None, None) == _lib.RBL_E_ARG
+    assert lib.rbl_msd(None, None, None, None) == _lib.RBL_E_ARG
+    assert lib.rbl_rdf(None, None, 3.0, 100, None) == _lib.RBL_E_ARG
+    out = (C.c_double * 4)()
+    assert lib.rbl_thermo(None, None, None, out) == _lib.RBL_E_ARG
     assert lib.rbl_destroy(None) == _lib.RBL_OK
