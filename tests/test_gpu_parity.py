@@ -573,3 +573,38 @@ def test_autotuner_picks_a_measured_layout():
     assert t["lpp_rbl"] in (1, 2, 4)
     assert all(u > 0 for u in t["rbl_us"])
     assert t["rbl_us"][(1, 2, 4).index(t["lpp_rbl"])] == min(t["rbl_us"])
+
+
+@pytest.mark.parametrize("lanes", [2, 4])
+def test_mixed_classification_at_thresholds_matches_fp64(lanes):
+    """Pairs planted within 1e-7 of r_s and r_c: the mixed kernels classify
+    them on FP64 r^2 as the oracle does, so full-list and RBL forces (the
+    multi-lane kernels) match the FP64 oracle within the mixed tolerance, at
+    the build state and after a displacement, and the planted particles'
+    forces show no pair on the wrong side of a threshold."""
+    torch_cuda()
+    rng = np.random.default_rng(12)
+    box = np.array([16.0, 16.0, 16.0])
+    st = inputs.random_gas(1500, box, seed=13, min_dist=0.85)
+    pos = st.pos.copy()
+    # plant pairs at the thresholds: particle 2k+1 placed at distance r from 2k
+    for k, r in enumerate([RS * (1 - 1e-7), RS * (1 + 1e-7), RC * (1 - 1e-7), RC * (1 + 1e-7), RS, RC]):
+        u = rng.normal(size=3)
+        u /= np.linalg.norm(u)
+        pos[:, 2 * k + 1] = pos[:, 2 * k] + r * u
+    pos = pos % box[:, None]
+    Lf = oracle.System(pos, box, RS, RC, SKIN).lists(kinds=("core", "shell", "full"))
+    with Context(pos.shape[1], precision="mixed", lanes=lanes, lists=("core", "shell", "full")) as ctx:
+        ctx.build(dev(pos), box, RS, RC)
+        planted = np.arange(12)
+        for p in (pos, pos + rng.uniform(-0.05, 0.05, size=pos.shape)):
+            ff = host(ctx.full_forces(dev(p)))
+            fo, _, _ = oracle.full_forces(p, box, RC, Lf)
+            assert rel_l2(ff, fo) < MIXED_TOL
+            # a pair classified on the wrong side of r_c would move its
+            # particles' force by |f(r_c)| ~ 4e-3, of r_s by ~1
+            err = np.linalg.norm(ff[:, planted] - fo[:, planted], axis=0)
+            assert np.all(err <= 1e-5 * np.maximum(np.linalg.norm(fo[:, planted], axis=0), 1.0))
+            f = host(ctx.forces(64, seed=5, step=1, pos=dev(p)))
+            fr, _, _ = oracle_rbl_total(p, box, Lf, 64, 5, 1)
+            assert rel_l2(f, fr) < MIXED_TOL
