@@ -608,3 +608,29 @@ def test_mixed_classification_at_thresholds_matches_fp64(lanes):
             f = host(ctx.forces(64, seed=5, step=1, pos=dev(p)))
             fr, _, _ = oracle_rbl_total(p, box, Lf, 64, 5, 1)
             assert rel_l2(f, fr) < MIXED_TOL
+
+
+@pytest.mark.parametrize("source", ["shell", "stencil"])
+def test_million_particle_md_in_the_bench_configuration(source):
+    """N = 10^6 in the configuration the benchmark times (mixed precision,
+    fused build + draw, autotuned lanes and launch mode, captured list
+    lifetimes): after 20 steps (the last force evaluation right after a
+    rebuild), the raw force of sampled rows equals the oracle's RBL force at
+    the GPU's final positions (lists built there, Philox step 20)."""
+    torch = torch_cuda()
+    st = inputs.million_fluid(seed=1)
+    n = st.n
+    x, v = dev(st.pos), dev(st.vel)
+    f = torch.zeros_like(x)
+    with Context(n, precision="mixed", momentum_fix=False, shell_source=source) as ctx:
+        ctx.build(x, st.box, RS, RC)
+        status, _ = ctx.step(x, v, nsteps=20, dt=0.005, P=10, seed=1, rebuild_every=10, force=f)
+        tuning = ctx.tuning()
+    assert status in (0, _lib.RBL_W_SKIN)
+    assert tuning["lpp_rbl"] in (1, 2, 4)
+    xg = host(x)
+    rows = np.random.default_rng(1).choice(n, size=300, replace=False)
+    sysm = oracle.System(xg, st.box, RS, RC, SKIN)
+    L = sysm.lists(rows=rows, kinds=("core", "shell")) if source == "shell" else sysm.stencil_lists(rows=rows)
+    fo, _, _ = oracle.rbl_forces(xg, st.box, RS, RC, L, 10, 1, 20)
+    assert rel_l2(host(f)[:, rows], fo) < MIXED_TOL
