@@ -62,6 +62,9 @@ def parse():
                     help="instead of running: write the profiles/ summaries from the output "
                          "folders of a rocprofv3 --kernel-trace --stats run and two --pmc runs "
                          "(FETCH_SIZE, WRITE_SIZE) of this script")
+    ap.add_argument("--valu-dir", default=None,
+                    help="with --summarize: the output folder of a rocprofv3 --pmc run of the "
+                         "VALU counters (writes profiles/valu_n1m.txt)")
     ap.add_argument("--profile-command", default="",
                     help="with --summarize: the bench.py arguments the profiled runs used")
     ap.add_argument("--calib-copy-mb", type=int, default=1024,
@@ -131,6 +134,26 @@ def recorded_traffic(key):
                 src_hash = parts[1]
             if len(parts) >= 4 and parts[0] == "traffic" and parts[1] == key:
                 found = float(parts[3])
+    if src_hash != kernel_source_hash():
+        return None
+    return found
+
+
+def recorded_valu(key):
+    """VALU counters per launch of kernel class `key` from the committed
+    rocprofv3 summary (profiles/valu_n1m.txt), or None when it is missing or
+    was taken from other kernel sources."""
+    path = os.path.join(PROFILES, "valu_n1m.txt")
+    if not os.path.exists(path):
+        return None
+    src_hash, found = None, None
+    with open(path) as f:
+        for line in f:
+            parts = line.split()
+            if len(parts) >= 2 and parts[0] == "source_sha256":
+                src_hash = parts[1]
+            if len(parts) >= 3 and parts[0] == "valu" and parts[1] == key:
+                found = json.loads(line.split(None, 2)[2])
     if src_hash != kernel_source_hash():
         return None
     return found
@@ -638,10 +661,66 @@ def summarize(trace_dir, fetch_dir, write_dir, command, calib_mib, P=10):
     print("\n".join(lines))
 
 
+VALU_COUNTERS = ["SQ_INSTS_VALU", "SQ_INSTS_VALU_FLOPS_FP32", "SQ_INSTS_VALU_FLOPS_FP64",
+                 "SQ_INSTS_VALU_ADD_F64", "SQ_INSTS_VALU_MUL_F64", "SQ_INSTS_VALU_FMA_F64",
+                 "SQ_ACTIVE_INST_VALU", "SQ_BUSY_CYCLES", "GRBM_GUI_ACTIVE"]
+
+
+def summarize_valu(valu_dir, trace_dir, command, P=10):
+    """Writes profiles/valu_n1m.txt: per kernel class (the instantiation with
+    the most dispatches), the mean per launch of the VALU counters of one
+    rocprofv3 --pmc run, the launch duration of the kernel trace, and from
+    them the achieved FP64 and FP32 rates against the vector peaks (78.6 and
+    157.3 TFLOP/s) and the VALU busy fraction
+    SQ_ACTIVE_INST_VALU * 4 / (SIMDs * GRBM_GUI_ACTIVE per XCD)."""
+    rows = _read_csv(valu_dir, "counter_collection.csv")
+    stats = {r["Name"]: float(r["AverageNs"]) for r in _read_csv(trace_dir, "kernel_stats.csv")}
+    per = {}
+    for r in rows:
+        per.setdefault(r["Kernel_Name"], {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    simds, xcds = 256 * 4, 8
+    classes = {}
+    for name, d in per.items():
+        cls = kernel_class(name, P)
+        n = len(d.get("SQ_INSTS_VALU", []))
+        if cls and name in stats and (cls not in classes or n > classes[cls][0]):
+            m = {k: float(np.mean(v)) for k, v in d.items()}
+            us = stats[name] / 1e3
+            # the FLOPS counters count per wavefront instruction (an FMA two):
+            # x 64 lanes; for FP64 equal to 64 (ADD + MUL + 2 FMA) instructions
+            f64 = 64.0 * m.get("SQ_INSTS_VALU_FLOPS_FP64", 0.0)
+            f32 = 64.0 * m.get("SQ_INSTS_VALU_FLOPS_FP32", 0.0)
+            gui = m.get("GRBM_GUI_ACTIVE", 0.0) / xcds
+            busy = m.get("SQ_ACTIVE_INST_VALU", 0.0) * 4.0 / (simds * gui) if gui > 0 else None
+            classes[cls] = (n, {"kernel": name, "dispatches": n, "avg_launch_us": us,
+                                "counters_per_launch": m,
+                                "fp64_flops_per_launch": f64, "fp32_flops_per_launch": f32,
+                                "fp64_tflops": f64 / (us * 1e-6) / 1e12,
+                                "fp64_frac_of_78.6": f64 / (us * 1e-6) / 78.6e12,
+                                "fp32_tflops": f32 / (us * 1e-6) / 1e12,
+                                "fp32_frac_of_157.3": f32 / (us * 1e-6) / 157.3e12,
+                                "valu_busy": busy})
+    lines = ["# VALU counters per kernel launch from one rocprofv3 counter run of bench.py,",
+             "# N = 1,000,000 LJ fluid (density 0.8442)",
+             f"# command: rocprofv3 --pmc {' '.join(VALU_COUNTERS)} -d <dir> -o bench "
+             f"--output-format csv -- python3 bench.py {command}",
+             "# durations from the kernel trace of profiles/kernel_trace_n1m.txt; the FLOPS counters "
+             "count per wavefront instruction (an FMA counts two), so flops = 64 x counter",
+             f"source_sha256 {kernel_source_hash()}",
+             "# valu <class> <json>", ""]
+    for cls, (_, d) in sorted(classes.items()):
+        lines.append(f"valu {cls} {json.dumps(d)}")
+    with open(os.path.join(PROFILES, "valu_n1m.txt"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def main():
     args = parse()
     if args.summarize:
         summarize(*args.summarize, args.profile_command, args.calib_copy_mb)
+        if args.valu_dir:
+            summarize_valu(args.valu_dir, args.summarize[0], args.profile_command)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only (this build has no multi-GPU path); "
@@ -696,6 +775,13 @@ def main():
         roof = force_roof
         roof["secondary"] = build_roofline(head)
     roof["dominant_kernel_class"] = dom
+
+    def valu_key(kind):
+        if kind == "build":
+            return "build"
+        return f"force_{'full' if head['full'] else 'rbl'}_{head['precision']}_p{head['P']}"
+    roof["valu_counters"] = recorded_valu(valu_key(dom))
+    roof["secondary"]["valu_counters"] = recorded_valu(valu_key("force" if dom == "build" else "build"))
     roof["share_of_step"] = km[dom]["total_ms"] / sum(k["total_ms"] for k in km.values())
     roof["hbm_copy_GBs"] = copy_gbs
 
