@@ -634,3 +634,19 @@ def test_million_particle_md_in_the_bench_configuration(source):
     L = sysm.lists(rows=rows, kinds=("core", "shell")) if source == "shell" else sysm.stencil_lists(rows=rows)
     fo, _, _ = oracle.rbl_forces(xg, st.box, RS, RC, L, 10, 1, 20)
     assert rel_l2(host(f)[:, rows], fo) < MIXED_TOL
+
+
+@pytest.mark.parametrize("P", [1, 33, 128])
+def test_fused_draw_at_extreme_batch_sizes(P):
+    """The fused build + draw at P = 1, 33 (first unrolled-loop-free Floyd
+    instance) and RBL_MAX_P = 128: a 20-step trajectory of the N = 1000
+    fluid against the oracle's (FP64, one lane per particle)."""
+    torch_cuda()
+    st = inputs.small_fluid(seed=5)
+    x, v = dev(st.pos), dev(st.vel)
+    with Context(st.n, lanes=1) as ctx:
+        ctx.build(x, st.box, RS, RC)
+        ctx.step(x, v, nsteps=20, dt=0.005, P=P, seed=3, rebuild_every=10)
+    xo, vo, _, _ = oracle.md_run(st.pos, st.vel, st.box, RS, RC, SKIN, 0.005, 20, p=P, seed=3, K=10)
+    assert rel_l2(host(x), xo) < 1e-13
+    assert rel_l2(host(v), vo) < 1e-11
