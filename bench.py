@@ -483,23 +483,32 @@ def run_table1(torch, equil=200_000, prod=100_000, every=1000, runs=10):
 
 
 def run_eos(torch, equil=50_000, prod=50_000, every=500, densities=(0.1, 0.2, 0.4, 0.6, 0.8),
-            temps=(2.0, 0.9), copies=2):
+            copies=2):
     """Equation of state of Sec. III (its energy and pressure figures):
     potential energy per particle and pressure, both with tail corrections,
-    of N = 2000 LJ fluids against density at T = 2.0 and 0.9 (Langevin,
-    friction 1, dt = 0.002), for direct truncation at r_c = 6 and 3 and RBL
-    with r_c = 6 and a core of 2 or 3 at P = 20.  Every density runs as
-    `copies` replicas of one context per (setting, T); values are averaged
-    over the production samples and the copies."""
+    of N = 2000 LJ fluids against density (Langevin, friction 1, dt =
+    0.002).  At T = 2.0 and 0.9: direct truncation at r_c = 6 and 3, and RBL
+    with r_c = 6 and a core of 2 or 3 at P = 20.  At T = 1.5: direct
+    truncation at r_c = 6, 3 and 2^(1/6), and RBL with r_c = 3, a core of
+    2^(1/6) and P = 10.  Every density runs as `copies` replicas of one
+    context per (setting, T); values are averaged over the production
+    samples and the copies."""
     from paper_2105_04884_amd import Context, inputs
     n1, gamma, dt = 2000, 1.0, 0.002
-    settings = [("DT r_c=6", True, 1.0, 6.0), ("DT r_c=3", True, 1.0, 3.0),
-                ("RBL r_s=2 r_c=6 P=20", False, 2.0, 6.0), ("RBL r_s=3 r_c=6 P=20", False, 3.0, 6.0)]
-    out = {"workload": f"Sec. III equation of state: N={n1}, densities {list(densities)}, T {list(temps)}, "
+    rmin = 2.0 ** (1.0 / 6.0)
+    studies = []
+    for T in (2.0, 0.9):
+        studies.append((T, [("DT r_c=6", True, 1.0, 6.0, 20), ("DT r_c=3", True, 1.0, 3.0, 20),
+                            ("RBL r_s=2 r_c=6 P=20", False, 2.0, 6.0, 20),
+                            ("RBL r_s=3 r_c=6 P=20", False, 3.0, 6.0, 20)]))
+    studies.append((1.5, [("DT r_c=6", True, 1.0, 6.0, 10), ("DT r_c=3", True, 1.0, 3.0, 10),
+                          ("DT r_c=2^(1/6)", True, 0.5, rmin, 10),
+                          ("RBL r_s=2^(1/6) r_c=3 P=10", False, rmin, 3.0, 10)]))
+    out = {"workload": f"Sec. III equation of state: N={n1}, densities {list(densities)}, "
                        f"{copies} replicas per density, Langevin gamma={gamma}, dt={dt}, {equil} "
                        f"equilibration + {prod} production steps, samples every {every}, FP64",
            "densities": list(densities), "results": {}}
-    for T in temps:
+    for T, settings in studies:
         states = [inputs.lj_fluid(n1, rho, T, seed=100 * k + c + 1)
                   for k, rho in enumerate(densities) for c in range(copies)]
         pos = np.concatenate([st_.pos for st_ in states], axis=1)
@@ -507,18 +516,18 @@ def run_eos(torch, equil=50_000, prod=50_000, every=500, densities=(0.1, 0.2, 0.
         boxes = np.stack([st_.box for st_ in states])
         off = np.arange(len(states) + 1, dtype=np.int64) * n1
         n = int(off[-1])
-        for name, full, rs, rc in settings:
+        for name, full, rs, rc, P in settings:
             x, v = torch.from_numpy(pos).cuda(), torch.from_numpy(vel).cuda()
             lists = ("full",) if full else ("core", "shell")
             t0 = time.perf_counter()
             with Context(n, replica_offsets=off, lists=lists, shift=False, skin=SKIN) as ctx:
                 ctx.set_thermostat(gamma, T)
                 ctx.build(x, boxes, rs, rc)
-                ctx.step(x, v, nsteps=equil, dt=dt, P=20, seed=1, rebuild_every=10, use_full=full)
+                ctx.step(x, v, nsteps=equil, dt=dt, P=P, seed=1, rebuild_every=10, use_full=full)
                 us, ps = [], []
                 s_ = equil
                 for f in range(prod // every):
-                    _, ev = ctx.step(x, v, nsteps=every, dt=dt, P=20, seed=1, step0=s_, rebuild_every=10,
+                    _, ev = ctx.step(x, v, nsteps=every, dt=dt, P=P, seed=1, step0=s_, rebuild_every=10,
                                      use_full=full, want_ev=True)
                     s_ += every
                     th = ctx.thermo(ev)
