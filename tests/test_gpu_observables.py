@@ -186,3 +186,25 @@ def test_thermostat_argument_checks():
         with pytest.raises(RblError):
             ctx.set_thermostat(1.0, -0.5)
         ctx.set_thermostat(0.0)
+
+
+def test_observable_argument_checks_and_missing_values():
+    """rbl_rdf refuses r_max beyond r_c and empty histograms; without a
+    thermostat the bath-temperature pressure is NaN and without velocities
+    the kinetic columns are NaN; unwrap and msd need the boxes of a build."""
+    torch = torch_cuda()
+    st = inputs.small_fluid(seed=1)
+    with Context(st.n, lists=("full",), shift=False) as ctx:
+        with pytest.raises(RblError):
+            ctx.unwrap(dev(st.pos))
+        ctx.build(dev(st.pos), st.box, RS, RC)
+        with pytest.raises(RblError):
+            ctx.rdf(dev(st.pos), RC + 0.1, 10)
+        with pytest.raises(RblError):
+            ctx.rdf(dev(st.pos), 2.0, 0, counts=torch.zeros((1, 0), dtype=torch.int64, device="cuda"))
+        _, ev = ctx.full_forces(dev(st.pos), want_ev=True)
+        out = ctx.thermo(ev)[0]
+        assert np.isfinite(out[0]) and np.isnan(out[1]) and np.isnan(out[2]) and np.isnan(out[3])
+        u = ctx.unwrap(dev(st.pos))
+        assert torch.equal(u, dev(st.pos))
+        assert host(ctx.msd(u, u))[0] == 0.0
