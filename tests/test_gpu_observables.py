@@ -208,3 +208,19 @@ def test_observable_argument_checks_and_missing_values():
         u = ctx.unwrap(dev(st.pos))
         assert torch.equal(u, dev(st.pos))
         assert host(ctx.msd(u, u))[0] == 0.0
+
+
+def test_langevin_with_the_stencil_population():
+    """The thermostat and the stencil draw population together: 60 BAOAB
+    steps of an N = 8000 fluid against the oracle's run."""
+    torch_cuda()
+    st = inputs.lj_fluid(8000, 0.8442, 1.0, seed=21)
+    x, v = dev(st.pos), dev(st.vel)
+    with Context(st.n, lanes=1, shell_source="stencil") as ctx:
+        ctx.set_thermostat(1.0, 1.2)
+        ctx.build(x, st.box, RS, RC)
+        ctx.step(x, v, nsteps=60, dt=0.005, P=10, seed=6, rebuild_every=10)
+    xo, vo, _, _ = oracle.md_run(st.pos, st.vel, st.box, RS, RC, SKIN, 0.005, 60, p=10, seed=6,
+                                 K=10, gamma=1.0, kT=1.2, shell_source="stencil")
+    assert rel_l2(host(x), xo) < 1e-11
+    assert rel_l2(host(v), vo) < 1e-8
