@@ -373,11 +373,17 @@ def run_large(torch, steps=200, warmup=20):
     with Context(n, precision="mixed", skin=SKIN) as ctx:
         ctx.build(x, st.box, 1.3, 4.0)
         el, status, avg = timed_steps(ctx, x, v, steps, warmup, 10, torch, 50)
+        tuning = ctx.tuning()
     log(f"[bench] large: {1e3 * el / steps:.3f} ms/step, {n * steps / el:.3e} atom-steps/s")
     return {"workload": "LJ fluid N=16,777,216 rho=0.8 T=1.2, r_s=1.3 r_c=4.0 skin=0.3, P=10, "
                         "rebuild every 10 steps, dt=0.005, mixed",
             "n_particles": n, "steps": steps, "atom_steps_per_s": n * steps / el,
-            "ms_per_step": 1e3 * el / steps, "status": status, "kernels_avg_us": avg}
+            "ms_per_step": 1e3 * el / steps, "status": status, "kernels_avg_us": avg,
+            # the autotuner's launch-mode choice and times (one block per tile
+            # against the persistent grid) and lanes per particle
+            "force_launch": {"persistent": tuning["persistent_rbl"],
+                             "us_tile_grid_vs_persistent": tuning["rbl_grid_vs_persistent_us"],
+                             "lanes": tuning["lpp_rbl"]}}
 
 
 def rdf_from_counts(counts, frames, n, volume, dr):
