@@ -734,15 +734,19 @@ constexpr int kCtrMax = 16;        // centre particles per group
 constexpr int kListBudgetMin = 3072;  // 16-bit shell-list entries per wavefront, at least
 constexpr int kListBudgetMax = 6912;  // at most (the block's LDS stays within 64 KB)
 constexpr int kRunOffBits = 10;    // list entry = run << 10 | offset in the run
+constexpr int kRing = 128;         // ring of kept candidates per wavefront (two chunks)
+constexpr int kNoShift = 1 | (1 << 2) | (1 << 4);  // image-shift code of no shift
 
 template <int PMAX, bool STENCIL>
-__global__ __launch_bounds__(256) void k_build_draw(FusedArgs fa)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_build_draw(FusedArgs fa)
 {
     __shared__ double4 s_ctr[4][kCtrMax];
     __shared__ int s_rstart[4][64];
     __shared__ int s_rpre[4][64];
     __shared__ int s_rshift[4][64];
     __shared__ int s_ncnt[4][kCtrMax];
+    // kept candidates' list entries on their way to the tests (shell-list form)
+    __shared__ unsigned short s_ring[STENCIL ? 1 : 4][STENCIL ? 1 : kRing];
     // STENCIL: run table of the core test (3 x 3 x 3 cells when they reach)
     __shared__ int s_crstart[STENCIL ? 4 : 1][64];
     __shared__ int s_crpre[STENCIL ? 4 : 1][64];
@@ -863,7 +867,7 @@ __global__ __launch_bounds__(256) void k_build_draw(FusedArgs fa)
     // list entry
     auto candidate = [&](int f, int& j, double4& xj, int& code, int& ent) {
         j = -1;
-        code = 1 | (1 << 2) | (1 << 4);
+        code = kNoShift;
         ent = 0;
         xj = make_double4(1.0e30, 1.0e30, 1.0e30, 0.0);
         if (f < ctotal) {
@@ -890,23 +894,12 @@ __global__ __launch_bounds__(256) void k_build_draw(FusedArgs fa)
             wave_lds_fence();
             qrun = 0;
             int cnt_core = 0;
-            int jn, coden, entn;
-            double4 xn;
-            candidate(lane, jn, xn, coden, entn);
-            // the first chunk's candidates are complete before the chunk loop:
-            // with nothing of this load pending at the loop head, the inner loop
-            // waits on no vector-memory counter, and each chunk's prefetch of the
-            // next one overlaps with its tests
-            __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
-            for (int ch = 0; ch < nch; ++ch) {
-                const int jc = jn;
-                const double4 xc = xn;
-                const int code = coden;
-                const int ent = entn;
-                if (ch + 1 < nch) candidate((ch + 1) * 64 + lane, jn, xn, coden, entn);
+            // the tests of the group's centres against 64 candidates (slot
+            // jc, position xc, image-shift code, list entry ent; slot -1 and
+            // a far position in lanes without one): core ballot to lane ii,
+            // shell candidates appended to its LDS list, core rows written
+            auto test_chunk = [&](int jc, const double4& xc, int code, int ent) {
                 uint32_t mclo = 0, mchi = 0;
-                // one centre particle against the chunk: core ballot to lane ii,
-                // shell candidates appended to its LDS list
                 auto test = [&](int ii, double dx, double dy, double dz) {
                     const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
                     const uint64_t other = ~__ballot(jc == i0 + g0 + ii);
@@ -922,7 +915,6 @@ __global__ __launch_bounds__(256) void k_build_draw(FusedArgs fa)
                     s_lst[select_lanes(ms, pos, budget + lane)] = (unsigned short)ent;
                     nshell = (uint32_t)rbl_writelane(base + (int)__popcll(ms), ii, (int)nshell);
                 };
-                constexpr int kNoShift = 1 | (1 << 2) | (1 << 4);
                 if (SHIFT && __ballot(code != kNoShift) == 0) {
                     // no periodic image in the chunk: (x_i - x_j) + 0 is x_i - x_j
                     for (int ii = 0; ii < mg; ++ii) {
@@ -953,6 +945,104 @@ __global__ __launch_bounds__(256) void k_build_draw(FusedArgs fa)
                         if (cnt_core < a.cap_core) a.core[ell(my_slot, cnt_core, a.cap_core)] = jb;
                         ++cnt_core;
                         mcore &= mcore - 1;
+                    }
+                }
+            };
+            int jn, coden, entn;
+            double4 xn;
+            candidate(lane, jn, xn, coden, entn);
+            // the first chunk's candidates are complete before the chunk loop:
+            // with nothing of this load pending at the loop head, the inner loop
+            // waits on no vector-memory counter, and each chunk's prefetch of the
+            // next one overlaps with the work on the current one
+            __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+            if constexpr (STENCIL) {
+                for (int ch = 0; ch < nch; ++ch) {
+                    const int jc = jn;
+                    const double4 xc = xn;
+                    const int code = coden;
+                    const int ent = entn;
+                    if (ch + 1 < nch) candidate((ch + 1) * 64 + lane, jn, xn, coden, entn);
+                    test_chunk(jc, xc, code, ent);
+                }
+            } else {
+                // The group's bounding box, widened by a margin far above the
+                // rounding of the coordinates: a candidate farther than the
+                // outer radius from the box is farther from every centre of
+                // the group, and skips their tests.  The list entries of the
+                // kept candidates pass through a ring in LDS, in stencil
+                // order, and are tested 64 at a time; each such batch is
+                // loaded one chunk before its tests.
+                double lo0 = 1.0e300, lo1 = 1.0e300, lo2 = 1.0e300;
+                double hi0 = -1.0e300, hi1 = -1.0e300, hi2 = -1.0e300;
+                for (int ii = 0; ii < mg; ++ii) {
+                    const double4 xi = s_ctr[w][ii];
+                    lo0 = fmin(lo0, xi.x);
+                    hi0 = fmax(hi0, xi.x);
+                    lo1 = fmin(lo1, xi.y);
+                    hi1 = fmax(hi1, xi.y);
+                    lo2 = fmin(lo2, xi.z);
+                    hi2 = fmax(hi2, xi.z);
+                }
+                const double margin = 1.0e-9 * (1.0 + L0 + L1 + L2);
+                const double bc0 = rfl(0.5 * (lo0 + hi0)), be0 = rfl(0.5 * (hi0 - lo0) + margin);
+                const double bc1 = rfl(0.5 * (lo1 + hi1)), be1 = rfl(0.5 * (hi1 - lo1) + margin);
+                const double bc2 = rfl(0.5 * (lo2 + hi2)), be2 = rfl(0.5 * (hi2 - lo2) + margin);
+                const double keep_thr = fmax(a.thr_core, a.thr_out);
+                int head = 0, tail = 0;  // ring positions (wave-uniform)
+                bool have = false;       // a batch is loaded and waits for its tests
+                int jb = -1, codeb = kNoShift, entb = 0;
+                double4 xb = make_double4(1.0e30, 1.0e30, 1.0e30, 0.0);
+                for (int ch = 0;; ++ch) {
+                    if (ch < nch) {
+                        const double4 xc = xn;
+                        const int code = coden;
+                        const int ent = entn;
+                        if (ch + 1 < nch) candidate((ch + 1) * 64 + lane, jn, xn, coden, entn);
+                        // (a lane without a candidate has a far position and fails)
+                        double dx, dy, dz;
+                        if (SHIFT && __ballot(code != kNoShift) == 0) {
+                            dx = bc0 - xc.x;
+                            dy = bc1 - xc.y;
+                            dz = bc2 - xc.z;
+                        } else if (SHIFT) {
+                            dx = (bc0 - xc.x) + (double)((code & 3) - 1) * L0;
+                            dy = (bc1 - xc.y) + (double)(((code >> 2) & 3) - 1) * L1;
+                            dz = (bc2 - xc.z) + (double)(((code >> 4) & 3) - 1) * L2;
+                        } else {
+                            dx = min_image(bc0 - xc.x, L0, iL0);
+                            dy = min_image(bc1 - xc.y, L1, iL1);
+                            dz = min_image(bc2 - xc.z, L2, iL2);
+                        }
+                        const double gx = fmax(fabs(dx) - be0, 0.0);
+                        const double gy = fmax(fabs(dy) - be1, 0.0);
+                        const double gz = fmax(fabs(dz) - be2, 0.0);
+                        const bool keep = fma(gz, gz, fma(gy, gy, gx * gx)) < keep_thr;
+                        const uint64_t mk = __ballot(keep);
+                        // after the reads of the previous batch
+                        wave_lds_fence();
+                        if (keep) s_ring[w][(tail + (int)mbcnt(mk)) & (kRing - 1)] = (unsigned short)ent;
+                        tail += (int)__popcll(mk);
+                    }
+                    if (have) test_chunk(jb, xb, codeb, entb);
+                    const bool drained = ch + 1 >= nch;
+                    have = tail - head >= 64 || (drained && tail > head);
+                    if (!have && drained) break;
+                    if (have) {
+                        wave_lds_fence();
+                        const int nb = min(64, tail - head);
+                        jb = -1;
+                        codeb = kNoShift;
+                        entb = 0;
+                        xb = make_double4(1.0e30, 1.0e30, 1.0e30, 0.0);
+                        if (lane < nb) {
+                            entb = s_ring[w][(head + lane) & (kRing - 1)];
+                            const int q = entb >> kRunOffBits;
+                            jb = s_rstart[w][q] + (entb & ((1 << kRunOffBits) - 1));
+                            codeb = s_rshift[w][q];
+                            xb = a.xs[jb];
+                        }
+                        head += nb;
                     }
                 }
             }
