@@ -650,3 +650,41 @@ def test_fused_draw_at_extreme_batch_sizes(P):
     xo, vo, _, _ = oracle.md_run(st.pos, st.vel, st.box, RS, RC, SKIN, 0.005, 20, p=P, seed=3, K=10)
     assert rel_l2(host(x), xo) < 1e-13
     assert rel_l2(host(v), vo) < 1e-11
+
+
+def test_fused_build_on_a_lattice_with_exact_ties():
+    """A simple cubic lattice of spacing 1 with r_c + skin = 2.7 + 0.3 = 3
+    exactly: every (3,0,0) and (2,2,1) neighbour sits at r^2 = 9, on the
+    outer threshold, and must stay out of the shell as in the oracle.  The
+    fused build (with its bounding-box skip of far candidates) at the
+    lattice state gives the oracle's core rows and shell counts bit for bit,
+    and a 20-step run from there follows the oracle's trajectory."""
+    torch_cuda()
+    rc = 2.7
+    assert rc + SKIN == 3.0
+    g = (np.arange(12) + 0.25).astype(np.float64)
+    z, y, x = np.meshgrid(g, g, g, indexing="ij")
+    pos = np.stack([x.ravel(), y.ravel(), z.ravel()])
+    box = np.array([12.0, 12.0, 12.0])
+    n = pos.shape[1]
+    rng = np.random.default_rng(4)
+    vel = rng.normal(size=(3, n))
+    vel -= vel.mean(axis=1, keepdims=True)
+    ref = oracle.System(pos, box, RS, rc, SKIN).lists(kinds=("core", "shell"))
+    shell_len = np.diff(ref.shell_off)
+    assert shell_len.min() == shell_len.max()  # every site sees the same shell
+    with Context(n, lanes=1) as ctx:
+        xg, vg = dev(pos), dev(np.zeros_like(pos))
+        ctx.build(xg, box, RS, rc)
+        ctx.step(xg, vg, nsteps=0, dt=0.005, P=10, seed=3, rebuild_every=10)
+        got = ctx.export_lists(kinds=("core",))
+        counts = ctx.row_counts()
+    assert_lists_equal(got, ref, kinds=("core",))
+    assert np.array_equal(counts[1], shell_len)
+    with Context(n, lanes=1) as ctx:
+        xg, vg = dev(pos), dev(vel)
+        ctx.build(xg, box, RS, rc)
+        ctx.step(xg, vg, nsteps=20, dt=0.005, P=10, seed=3, rebuild_every=10)
+    xo, vo, _, _ = oracle.md_run(pos, vel, box, RS, rc, SKIN, 0.005, 20, p=10, seed=3, K=10)
+    assert rel_l2(host(xg), xo) < 1e-13
+    assert rel_l2(host(vg), vo) < 1e-11
