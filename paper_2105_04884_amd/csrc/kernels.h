@@ -639,8 +639,14 @@ __device__ __forceinline__ void wave_lds_fence()
 //    grids use the canonical formula per pair;
 //  - every cell-level quantity is made wave-uniform with readfirstlane, so
 //    it lives in SGPRs;
-//  - per centre particle and chunk, the core ballot goes to lane ii of two
-//    VGPRs with v_writelane and the core rows are scattered once per chunk
+//  - each chunk is first tested against the bounding box of the group's
+//    centre particles (widened by a margin far above rounding): a
+//    candidate farther than r_c + skin from the box is farther from every
+//    centre and is dropped; the rest (about half of the stencil at liquid
+//    density) pass through an LDS ring, in stencil order, and are tested
+//    64 at a time, each batch loaded one chunk ahead of its tests;
+//  - per centre particle and batch, the core ballot goes to lane ii of two
+//    VGPRs with v_writelane and the core rows are scattered once per batch
 //    by the centre-particle lanes (coalesced ELL writes); the shell ballot
 //    is compacted into the particle's LDS list with mbcnt;
 //  - a centre particle's list has room for every stencil candidate, so the

@@ -54,6 +54,15 @@ def test_recorded_traffic_needs_matching_sources(tmp_path, monkeypatch):
     assert bench.recorded_traffic("build") is None
 
 
+def test_code_tokens_drop_comments_and_layout_only():
+    src = 'int a = 1; // note\nconst char* s = "x // y /* z */";\n/* block\n */ char c = \'/\';  int  b;'
+    assert bench.code_tokens(src) == 'int a = 1; const char* s = "x // y /* z */"; char c = \'/\'; int b;'
+    # a code change shows, a comment change does not
+    assert bench.code_tokens("x = 1; // a") == bench.code_tokens("x  =  1;  /* b */")
+    assert bench.code_tokens("x = 1;") != bench.code_tokens("x = 2;")
+    assert bench.code_tokens('s = "a\\"b"; // c') == 's = "a\\"b";'
+
+
 def test_more_than_one_gpu_is_refused():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True, timeout=60)
