@@ -645,10 +645,11 @@ __device__ __forceinline__ void wave_lds_fence()
 //    centre and is dropped; the rest (about half of the stencil at liquid
 //    density) pass through an LDS ring, in stencil order, and are tested
 //    64 at a time, each batch loaded one chunk ahead of its tests;
-//  - per centre particle and batch, the core ballot goes to lane ii of two
-//    VGPRs with v_writelane and the core rows are scattered once per batch
-//    by the centre-particle lanes (coalesced ELL writes); the shell ballot
-//    is compacted into the particle's LDS list with mbcnt;
+//  - per centre particle and batch, a non-empty core ballot sends its
+//    candidates straight into the particle's sliced-ELL row at the row's
+//    count + mbcnt (the count held in lane ii), so rows keep candidate
+//    order; the shell ballot is compacted into the particle's LDS list the
+//    same way;
 //  - a centre particle's list has room for every stencil candidate, so the
 //    centre particles go in groups of (LDS list budget) / (room) at most,
 //    the budget being set by the host from the shell counts it has seen
@@ -899,18 +900,30 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
             if (lane < mg) s_ctr[w][lane] = a.xs[i0 + g0 + lane];
             wave_lds_fence();
             qrun = 0;
-            int cnt_core = 0;
+            uint32_t ncore = 0;  // lane ii: core partners of centre ii so far
             // the tests of the group's centres against 64 candidates (slot
             // jc, position xc, image-shift code, list entry ent; slot -1 and
-            // a far position in lanes without one): core ballot to lane ii,
-            // shell candidates appended to its LDS list, core rows written
+            // a far position in lanes without one): core partners written
+            // to the centre's row, shell candidates appended to its LDS list
             auto test_chunk = [&](int jc, const double4& xc, int code, int ent) {
-                uint32_t mclo = 0, mchi = 0;
                 auto test = [&](int ii, double dx, double dy, double dz) {
                     const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-                    const uint64_t other = ~__ballot(jc == i0 + g0 + ii);
-                    const uint64_t mc = other & __ballot(r2 < a.thr_core);
-                    write_lane2(mclo, mchi, (uint32_t)mc, (uint32_t)(mc >> 32), ii);
+                    const int slot_ii = i0 + g0 + ii;
+                    const uint64_t other = ~__ballot(jc == slot_ii);
+                    const bool is_core = jc != slot_ii && r2 < a.thr_core;
+                    const uint64_t mc = __ballot(is_core);
+                    if (mc) {
+                        // straight into row ii (sliced ELL) in candidate order;
+                        // entries past the row's room are counted, not written
+                        const int basec = rfl((int)__builtin_amdgcn_readlane((int)ncore, ii));
+                        const int k = basec + (int)mbcnt(mc);
+                        // row start, wave-uniform: slice (slot / 64) of cap_core
+                        // columns of 64, lane slot % 64 (slot < 2^31)
+                        const uint32_t su = (uint32_t)slot_ii;
+                        int* const row = a.core + ((uint64_t)(su >> 6) * (uint32_t)(a.cap_core * 64) + (su & 63u));
+                        if (is_core && k < a.cap_core) row[(uint32_t)k * 64u] = jc;
+                        ncore = (uint32_t)rbl_writelane(basec + (int)__popcll(mc), ii, (int)ncore);
+                    }
                     if constexpr (STENCIL) return;
                     const uint64_t ms = other & __ballot(r2 >= a.thr_shell_in) & __ballot(r2 < a.thr_out);
                     const int base = rfl((int)__builtin_amdgcn_readlane((int)nshell, ii));
@@ -940,17 +953,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
                         const double4 xi = s_ctr[w][ii];
                         test(ii, min_image(xi.x - xc.x, L0, iL0), min_image(xi.y - xc.y, L1, iL1),
                              min_image(xi.z - xc.z, L2, iL2));
-                    }
-                }
-                uint64_t mcore = ((uint64_t)mchi << 32) | mclo;
-                if (lane >= mg) mcore = 0;
-                while (__ballot(mcore != 0)) {
-                    const int b = mcore ? (int)__builtin_ctzll(mcore) : 0;
-                    const int jb = shfl_i32(jc, b);
-                    if (mcore) {
-                        if (cnt_core < a.cap_core) a.core[ell(my_slot, cnt_core, a.cap_core)] = jb;
-                        ++cnt_core;
-                        mcore &= mcore - 1;
                     }
                 }
             };
@@ -1052,6 +1054,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
                     }
                 }
             }
+            const int cnt_core = (int)ncore;
             if (lane < mg) a.core_len[my_slot] = min(cnt_core, a.cap_core);
             const int mxc = wave_max(lane < mg ? cnt_core : 0);
             const int mxs = STENCIL ? 0 : wave_max(lane < mg ? (int)nshell : 0);
