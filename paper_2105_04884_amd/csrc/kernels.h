@@ -738,19 +738,19 @@ __device__ __forceinline__ int select_lanes(uint64_t mask, int a, int b)
 }
 
 constexpr int kCtrMax = 16;        // centre particles per group
-constexpr int kListBudgetMin = 3072;  // 16-bit shell-list entries per wavefront, at least
+constexpr int kListBudgetMin = 2048;  // 16-bit shell-list entries per wavefront, at least
 constexpr int kListBudgetMax = 6912;  // at most (the block's LDS stays within 64 KB)
 constexpr int kRunOffBits = 10;    // list entry = run << 10 | offset in the run
 constexpr int kRing = 128;         // ring of kept candidates per wavefront (two chunks)
 constexpr int kNoShift = 1 | (1 << 2) | (1 << 4);  // image-shift code of no shift
 
 template <int PMAX, bool STENCIL>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_build_draw(FusedArgs fa)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) void k_build_draw(FusedArgs fa)
 {
     __shared__ double4 s_ctr[4][kCtrMax];
     __shared__ int s_rstart[4][64];
     __shared__ int s_rpre[4][64];
-    __shared__ int s_rshift[4][64];
+    __shared__ unsigned char s_rshift[4][64];
     __shared__ int s_ncnt[4][kCtrMax];
     // kept candidates' list entries on their way to the tests (shell-list form)
     __shared__ unsigned short s_ring[STENCIL ? 1 : 4][STENCIL ? 1 : kRing];

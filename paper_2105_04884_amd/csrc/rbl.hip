@@ -550,7 +550,8 @@ rbl_status launch_fused(rbl_ctx* c, int P, uint64_t seed, uint64_t step0, int K,
     fa.P = P;
     fa.cap_list = c->cap_list;
     // room for about eight centre particles per group, within the block's
-    // 64 KB of LDS
+    // 64 KB of LDS (at N = 1e6 and liquid density about 23 KB, so that 7
+    // blocks share a CU)
     fa.list_budget = (int)std::min<int64_t>(kListBudgetMax,
                                             std::max<int64_t>(kListBudgetMin, ((int64_t)8 * c->cap_list + 63) / 64 * 64));
     const size_t lds = c->stencil ? 0 : (size_t)4 * (fa.list_budget + 64) * sizeof(unsigned short);
