@@ -6,6 +6,7 @@
 // synchronisations are the capacity check after a list build and the flag
 // read-back at the end of rbl_step / rbl_sync.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <algorithm>
 #include <cmath>
@@ -153,6 +154,9 @@ struct rbl_ctx {
     int h_flags[kNumFlags];
 
     bool profiling = false;
+    // profiling: events the next launch_k hands to the dispatch itself
+    hipEvent_t lt_a = nullptr, lt_b = nullptr;
+    bool lt_used = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending[kKinds];
     std::vector<hipEvent_t> ev_pool;
     int64_t stat_launches[kKinds] = {0};
@@ -177,20 +181,53 @@ hipEvent_t take_event(rbl_ctx* c)
     return e;
 }
 
-// Runs `fn` (which queues one kernel) between two events when profiling.
+// Queues `kernel` on the context's stream.  While profiling with events
+// armed by timed(..., dispatch = true), the launch carries them itself
+// (hipExtLaunchKernelGGL), so they hold the kernel's own start and end.
+template <typename K, typename... A>
+void launch_k(rbl_ctx* c, K kernel, unsigned grid, size_t shmem, A... args)
+{
+    if (c->lt_a && c->lt_b && !c->lt_used) {
+        hipExtLaunchKernelGGL(kernel, dim3(grid), dim3(kBlock), (uint32_t)shmem, c->ls, c->lt_a, c->lt_b, 0u,
+                              args...);
+        c->lt_used = true;
+    } else {
+        kernel<<<grid, kBlock, shmem, c->ls>>>(args...);
+    }
+}
+
+// Runs `fn` (which queues one kernel) and, when profiling, times it: between
+// two events recorded around it, or (dispatch = true, for an fn that
+// launches through launch_k) with the events the launch itself records,
+// which leave out the dispatch latency that stream events take in.
 template <typename F>
-rbl_status timed(rbl_ctx* c, int kind, F&& fn)
+rbl_status timed(rbl_ctx* c, int kind, F&& fn, bool dispatch = false)
 {
     hipEvent_t a = nullptr, b = nullptr;
     if (c->profiling) {
         a = take_event(c);
         b = take_event(c);
-        if (a && b) HIP_TRY(hipEventRecord(a, c->ls));
+        if (a && b) {
+            if (dispatch) {
+                c->lt_a = a;
+                c->lt_b = b;
+                c->lt_used = false;
+            } else {
+                HIP_TRY(hipEventRecord(a, c->ls));
+            }
+        }
     }
     fn();
+    c->lt_a = c->lt_b = nullptr;
     HIP_TRY(hipGetLastError());
     if (c->profiling && a && b) {
-        HIP_TRY(hipEventRecord(b, c->ls));
+        if (dispatch && !c->lt_used) {
+            // nothing went through launch_k: no time for this call
+            c->ev_pool.push_back(a);
+            c->ev_pool.push_back(b);
+            return RBL_OK;
+        }
+        if (!dispatch) HIP_TRY(hipEventRecord(b, c->ls));
         c->ev_pending[kind].push_back({a, b});
     }
     return RBL_OK;
@@ -559,8 +596,8 @@ rbl_status launch_fused(rbl_ctx* c, int P, uint64_t seed, uint64_t step0, int K,
     return timed(c, kKBuild, [&] {
 #define RBL_BD(PM)                                                    \
     do {                                                              \
-        if (c->stencil) k_build_draw<PM, true><<<g, kBlock, 0, c->ls>>>(fa); \
-        else k_build_draw<PM, false><<<g, kBlock, lds, c->ls>>>(fa);  \
+        if (c->stencil) launch_k(c, k_build_draw<PM, true>, g, 0, fa); \
+        else launch_k(c, k_build_draw<PM, false>, g, lds, fa);         \
     } while (0)
         if (P <= 8) RBL_BD(8);
         else if (P <= 12) RBL_BD(12);
@@ -570,7 +607,7 @@ rbl_status launch_fused(rbl_ctx* c, int P, uint64_t seed, uint64_t step0, int K,
         else if (P <= 64) RBL_BD(64);
         else RBL_BD(128);
 #undef RBL_BD
-    });
+    }, true);
 }
 
 // LDS shell-list room per centre particle of the fused kernel: the longest
@@ -690,10 +727,10 @@ void launch_force_p(rbl_ctx* c, const ForceArgs& a0)
         c->part_per = 1;
         if (a.P <= 16) {
             auto k = k_forces<PREC, MODE, EN, ERFC, 16>;
-            k<<<force_grid(c, k, a.vblocks, pers), kBlock, 0, c->ls>>>(a);
+            launch_k(c, k, force_grid(c, k, a.vblocks, pers), 0, a);
         } else {
             auto k = k_forces<PREC, MODE, EN, ERFC, 32>;
-            k<<<force_grid(c, k, a.vblocks, pers), kBlock, 0, c->ls>>>(a);
+            launch_k(c, k, force_grid(c, k, a.vblocks, pers), 0, a);
         }
     } else {
         const int lpp = MODE == kShellNone ? c->lpp_full : c->lpp_rbl;
@@ -701,11 +738,11 @@ void launch_force_p(rbl_ctx* c, const ForceArgs& a0)
         if (lpp == 4 || lpp == 2) {
             a.vblocks = grid_for(c->n_slots * lpp);
             auto k = lpp == 4 ? k_forces_lpp<PREC, MODE, EN, ERFC, 4> : k_forces_lpp<PREC, MODE, EN, ERFC, 2>;
-            k<<<force_grid(c, k, a.vblocks, pers), kBlock, 0, c->ls>>>(a);
+            launch_k(c, k, force_grid(c, k, a.vblocks, pers), 0, a);
         } else {
             a.vblocks = grid_for(c->n_slots);
             auto k = k_forces<PREC, MODE, EN, ERFC, 1>;
-            k<<<force_grid(c, k, a.vblocks, pers), kBlock, 0, c->ls>>>(a);
+            launch_k(c, k, force_grid(c, k, a.vblocks, pers), 0, a);
         }
     }
 }
@@ -783,9 +820,9 @@ rbl_status rbl_force_sorted(rbl_ctx* c, int P, uint64_t seed, uint64_t step, int
     a.step_dev = step_dev;
     if (batch_rel >= 0) {
         a.batch = c->d_batch + (size_t)batch_rel * P * c->n_slots;
-        RBL_TRY(timed(c, kKForceRbl, [&] { launch_force<kShellPredraw>(c, a, energy); }));
+        RBL_TRY(timed(c, kKForceRbl, [&] { launch_force<kShellPredraw>(c, a, energy); }, true));
     } else {
-        RBL_TRY(timed(c, kKForceRbl, [&] { launch_force<kShellInline>(c, a, energy); }));
+        RBL_TRY(timed(c, kKForceRbl, [&] { launch_force<kShellInline>(c, a, energy); }, true));
     }
     return reduce(c);
 }
@@ -793,7 +830,7 @@ rbl_status rbl_force_sorted(rbl_ctx* c, int P, uint64_t seed, uint64_t step, int
 rbl_status full_force_sorted(rbl_ctx* c, bool energy)
 {
     ForceArgs a = force_args(c, 0, 0, 0, true);
-    RBL_TRY(timed(c, kKForceFull, [&] { launch_force<kShellNone>(c, a, energy); }));
+    RBL_TRY(timed(c, kKForceFull, [&] { launch_force<kShellNone>(c, a, energy); }, true));
     return reduce(c);
 }
 
