@@ -745,7 +745,7 @@ constexpr int kRing = 128;         // ring of kept candidates per wavefront (two
 constexpr int kNoShift = 1 | (1 << 2) | (1 << 4);  // image-shift code of no shift
 
 template <int PMAX, bool STENCIL>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) void k_build_draw(FusedArgs fa)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PMAX <= 32 ? 7 : 2))) void k_build_draw(FusedArgs fa)
 {
     __shared__ double4 s_ctr[4][kCtrMax];
     __shared__ int s_rstart[4][64];
