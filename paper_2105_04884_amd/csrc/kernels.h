@@ -738,14 +738,16 @@ __device__ __forceinline__ int select_lanes(uint64_t mask, int a, int b)
 }
 
 constexpr int kCtrMax = 16;        // centre particles per group
-constexpr int kListBudgetMin = 2048;  // 16-bit shell-list entries per wavefront, at least
-constexpr int kListBudgetMax = 6912;  // at most (the block's LDS stays within 64 KB)
+constexpr int kListBudgetMax = 6912;  // 16-bit shell-list entries per wavefront, at most
+                                      // (the block's LDS stays within 64 KB)
+constexpr int kFusedWavesPerEu = 7;   // occupancy the fused build is compiled for (P <= 32):
+                                      // as many blocks of 4 wavefronts per CU
 constexpr int kRunOffBits = 10;    // list entry = run << 10 | offset in the run
 constexpr int kRing = 128;         // ring of kept candidates per wavefront (two chunks)
 constexpr int kNoShift = 1 | (1 << 2) | (1 << 4);  // image-shift code of no shift
 
 template <int PMAX, bool STENCIL>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PMAX <= 32 ? 7 : 2))) void k_build_draw(FusedArgs fa)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PMAX <= 32 ? kFusedWavesPerEu : 2))) void k_build_draw(FusedArgs fa)
 {
     __shared__ double4 s_ctr[4][kCtrMax];
     __shared__ int s_rstart[4][64];

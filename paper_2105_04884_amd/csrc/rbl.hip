@@ -145,6 +145,8 @@ struct rbl_ctx {
     bool persist[2] = {false, false};  // persistent force grid (RBL, full list)
     double persist_us[2][2] = {{0, 0}, {0, 0}};  // per launch: one block per tile, persistent
     int n_cu = 256;                 // compute units of the device
+    int64_t lds_per_cu = 160 * 1024;  // bytes of LDS per compute unit
+    int64_t fused_static_lds = -1;    // static LDS of the fused build (queried once)
     bool tuned_rbl = false, tuned_full = false;
     double tune_us[2][3] = {{0, 0, 0}, {0, 0, 0}};  // measured force time per LPP 1, 2, 4
     double* d_part2 = nullptr;
@@ -586,11 +588,24 @@ rbl_status launch_fused(rbl_ctx* c, int P, uint64_t seed, uint64_t step0, int K,
     fa.K = K;
     fa.P = P;
     fa.cap_list = c->cap_list;
-    // room for about eight centre particles per group, within the block's
-    // 64 KB of LDS (at N = 1e6 and liquid density about 23 KB, so that 7
-    // blocks share a CU)
+    // LDS list budget per wavefront: the largest with which the blocks the
+    // kernel's registers allow (kFusedWavesPerEu for P <= 32) still fit in
+    // a CU's LDS, but at least two list rooms.  Occupancy outweighs group
+    // size: a cell with more particles than fit one group walks its stencil
+    // once per group, and that costs less than fewer resident blocks (at
+    // N = 1e6: 2112 entries, groups of 8, 7 blocks per CU).
+    if (c->fused_static_lds < 0) {
+        hipFuncAttributes fattr{};
+        c->fused_static_lds = hipFuncGetAttributes(&fattr, reinterpret_cast<const void*>(k_build_draw<12, false>))
+                                      == hipSuccess
+                                  ? (int64_t)fattr.sharedSizeBytes
+                                  : 8192;
+    }
+    const int64_t blocks_per_cu = P <= 32 ? kFusedWavesPerEu : 2;
+    const int64_t per_wave = (c->lds_per_cu / blocks_per_cu - c->fused_static_lds) / (4 * (int64_t)sizeof(unsigned short));
+    const int64_t fit = std::max<int64_t>(64, (per_wave - 64) / 64 * 64);
     fa.list_budget = (int)std::min<int64_t>(kListBudgetMax,
-                                            std::max<int64_t>(kListBudgetMin, ((int64_t)8 * c->cap_list + 63) / 64 * 64));
+                                            std::max<int64_t>(fit, ((int64_t)2 * c->cap_list + 63) / 64 * 64));
     const size_t lds = c->stencil ? 0 : (size_t)4 * (fa.list_budget + 64) * sizeof(unsigned short);
     const unsigned g = grid_for(c->n_cells, 4);
     return timed(c, kKBuild, [&] {
@@ -1386,6 +1401,10 @@ rbl_status rbl_create(const rbl_config* cfg, void* hip_stream, rbl_ctx** out)
         if (hipGetDevice(&dev) == hipSuccess &&
             hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
             c->n_cu = ncu;
+        int lds = 0;
+        if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) == hipSuccess &&
+            lds > 0)
+            c->lds_per_cu = lds;
     }
     int64_t slot = 0;
     for (int r = 0; r < c->R; ++r) {
