@@ -746,6 +746,16 @@ constexpr int kRunOffBits = 10;    // list entry = run << 10 | offset in the run
 constexpr int kRing = 128;         // ring of kept candidates per wavefront (two chunks)
 constexpr int kNoShift = 1 | (1 << 2) | (1 << 4);  // image-shift code of no shift
 
+// Position of a lane without a candidate: NaN, so that every distance test
+// on it fails.  (A far finite position is not safe: the canonical minimum
+// image folds it back into the box, exactly to 0 when the box length
+// divides it.)
+__device__ __forceinline__ double4 no_position()
+{
+    const double q = __builtin_nan("");
+    return make_double4(q, q, q, 0.0);
+}
+
 template <int PMAX, bool STENCIL>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PMAX <= 32 ? kFusedWavesPerEu : 2))) void k_build_draw(FusedArgs fa)
 {
@@ -872,13 +882,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PMAX <= 32 
     wave_lds_fence();
 
     int qrun = 0;  // this lane's current run (its candidate index only grows)
-    // candidate f: slot (-1 past the stencil), position, image-shift code,
-    // list entry
+    // candidate f: slot (-1 past the stencil), position (NaN without one),
+    // image-shift code, list entry
     auto candidate = [&](int f, int& j, double4& xj, int& code, int& ent) {
         j = -1;
         code = kNoShift;
         ent = 0;
-        xj = make_double4(1.0e30, 1.0e30, 1.0e30, 0.0);
+        xj = no_position();
         if (f < ctotal) {
             while (qrun < 63 && t_pre(qrun + 1) <= f) ++qrun;
             const int off = f - t_pre(qrun);
@@ -905,7 +915,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PMAX <= 32 
             uint32_t ncore = 0;  // lane ii: core partners of centre ii so far
             // the tests of the group's centres against 64 candidates (slot
             // jc, position xc, image-shift code, list entry ent; slot -1 and
-            // a far position in lanes without one): core partners written
+            // a NaN position in lanes without one): core partners written
             // to the centre's row, shell candidates appended to its LDS list
             auto test_chunk = [&](int jc, const double4& xc, int code, int ent) {
                 auto test = [&](int ii, double dx, double dy, double dz) {
@@ -1002,14 +1012,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PMAX <= 32 
                 int head = 0, tail = 0;  // ring positions (wave-uniform)
                 bool have = false;       // a batch is loaded and waits for its tests
                 int jb = -1, codeb = kNoShift, entb = 0;
-                double4 xb = make_double4(1.0e30, 1.0e30, 1.0e30, 0.0);
+                double4 xb = no_position();
                 for (int ch = 0;; ++ch) {
                     if (ch < nch) {
+                        const int jc = jn;
                         const double4 xc = xn;
                         const int code = coden;
                         const int ent = entn;
                         if (ch + 1 < nch) candidate((ch + 1) * 64 + lane, jn, xn, coden, entn);
-                        // (a lane without a candidate has a far position and fails)
                         double dx, dy, dz;
                         if (SHIFT && __ballot(code != kNoShift) == 0) {
                             dx = bc0 - xc.x;
@@ -1027,7 +1037,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PMAX <= 32 
                         const double gx = fmax(fabs(dx) - be0, 0.0);
                         const double gy = fmax(fabs(dy) - be1, 0.0);
                         const double gz = fmax(fabs(dz) - be2, 0.0);
-                        const bool keep = fma(gz, gz, fma(gy, gy, gx * gx)) < keep_thr;
+                        // (fmax drops a NaN, so a lane without a candidate is
+                        // excluded by its slot)
+                        const bool keep = jc >= 0 && fma(gz, gz, fma(gy, gy, gx * gx)) < keep_thr;
                         const uint64_t mk = __ballot(keep);
                         // after the reads of the previous batch
                         wave_lds_fence();
@@ -1044,7 +1056,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PMAX <= 32 
                         jb = -1;
                         codeb = kNoShift;
                         entb = 0;
-                        xb = make_double4(1.0e30, 1.0e30, 1.0e30, 0.0);
+                        xb = no_position();
                         if (lane < nb) {
                             entb = s_ring[w][(head + lane) & (kRing - 1)];
                             const int q = entb >> kRunOffBits;

@@ -688,3 +688,37 @@ def test_fused_build_on_a_lattice_with_exact_ties():
     xo, vo, _, _ = oracle.md_run(pos, vel, box, RS, rc, SKIN, 0.005, 20, p=10, seed=3, K=10)
     assert rel_l2(host(xg), xo) < 1e-13
     assert rel_l2(host(vg), vo) < 1e-11
+
+
+@pytest.mark.parametrize("case", ["gas_small_box", "elongated", "tiny_grid", "ragged_65", "vapour",
+                                  "unwrapped"])
+def test_fused_build_on_odd_geometries(case):
+    """The fused build (bounding-box skip, ring of kept candidates, lists in
+    LDS) on small and elongated grids where the stencil wraps onto itself,
+    on sparse and ragged populations and on unwrapped coordinates: core
+    rows and shell counts at the build state bit-exact, then 20 steps from
+    rest against the oracle's trajectory.  The uniform gases hold pairs
+    closer than 0.25 sigma, whose forces fling particles across the box in
+    one step, so their runs start from a gas of the same size and box with
+    no pair closer than 0.9."""
+    torch = torch_cuda()
+    pos, box = _case(case)
+    n = pos.shape[1]
+    ref = oracle.System(pos, box, RS, RC, SKIN).lists(kinds=("core", "shell"))
+    with Context(n, lanes=1) as ctx:
+        x, v = dev(pos), torch.zeros((3, n), dtype=torch.float64, device="cuda")
+        ctx.build(x, box, RS, RC)
+        ctx.step(x, v, nsteps=0, dt=0.005, P=10, seed=9, rebuild_every=10)
+        got = ctx.export_lists(kinds=("core",))
+        counts = ctx.row_counts()
+    assert_lists_equal(got, ref, kinds=("core",))
+    assert np.array_equal(counts[1], np.diff(ref.shell_off))
+    if case in ("gas_small_box", "elongated", "tiny_grid"):
+        pos = inputs.random_gas(n, box, seed=17, min_dist=0.9).pos
+    with Context(n, lanes=1) as ctx:
+        x, v = dev(pos), torch.zeros((3, n), dtype=torch.float64, device="cuda")
+        ctx.build(x, box, RS, RC)
+        ctx.step(x, v, nsteps=20, dt=0.005, P=10, seed=9, rebuild_every=10)
+    xo, vo, _, _ = oracle.md_run(pos, np.zeros_like(pos), box, RS, RC, SKIN, 0.005, 20, p=10, seed=9, K=10)
+    assert rel_l2(host(x), xo) < 1e-12
+    assert rel_l2(host(v), vo) < 1e-9
