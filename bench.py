@@ -68,6 +68,11 @@ def parse():
                          "VALU counters (writes profiles/valu_n1m.txt)")
     ap.add_argument("--profile-command", default="",
                     help="with --summarize: the bench.py arguments the profiled runs used")
+    ap.add_argument("--pin-launch", action="store_true",
+                    help="N = 1e6 variants: fix the force kernels' lanes per particle and launch "
+                         "mode to the autotuner's usual choice there (RBL 2 lanes, full list 4, "
+                         "one block per tile) instead of timing them; for profiler runs, whose "
+                         "per-dispatch overhead distorts the autotuner's timings")
     ap.add_argument("--calib-copy-mb", type=int, default=1024,
                     help="size of the plain device copy timed first: the attainable HBM "
                          "bandwidth, and the reference for the byte counters of a profiler run")
@@ -256,13 +261,15 @@ def force_roofline(res, fk):
     }
 
 
-def run_variant(name, x0, v0, box, precision, P, use_full, steps, warmup, torch, source="shell"):
+def run_variant(name, x0, v0, box, precision, P, use_full, steps, warmup, torch, source="shell",
+                pin=False):
     from paper_2105_04884_amd import Context, KIND_FORCE_RBL, KIND_FORCE_FULL, KIND_BUILD, \
         KIND_BIN, KIND_INTEGRATE, KIND_REDUCE, KIND_PREDRAW
     lists = ("full",) if use_full else ("core", "shell")
     x = x0.clone()
     v = v0.clone()
-    ctx = Context(N, precision=precision, lists=lists, skin=SKIN, shell_source=source)
+    launch = {"lanes": 4 if use_full else 2, "persistent": 1} if pin else {}
+    ctx = Context(N, precision=precision, lists=lists, skin=SKIN, shell_source=source, **launch)
     ctx.build(x, box, RS, RC)
     if warmup > 0:
         ctx.step(x, v, nsteps=warmup, dt=DT, P=P, seed=1, step0=0, rebuild_every=K_REBUILD,
@@ -850,7 +857,7 @@ def main():
     for name, prec, P, full, source in variants:
         log(f"[bench] variant {name}")
         results[name] = run_variant(name, x0, v0, st.box, prec, P, full, args.steps,
-                                    args.warmup, torch, source)
+                                    args.warmup, torch, source, args.pin_launch)
     head = results.get("rbl_mixed_p10") or next(iter(results.values()))
 
     log("[bench] force error vs the FP64 oracle (sampled rows)")
