@@ -147,3 +147,33 @@ def test_stencil_mode_needs_no_shell_list():
         ctx.build(dev(st.pos), st.box, RS, RC)
         with pytest.raises(RblError):
             ctx.forces(10, seed=2, step=4, pos=dev(st.pos))
+
+
+@pytest.mark.parametrize("case", ["ragged_65", "elongated"])
+def test_stencil_core_rows_on_odd_geometries(case):
+    """The stencil form's fused build on an 8.0 box of 4 cells per axis (the
+    minimum image folds any finite far position there, so lanes without a
+    candidate must fail every test by other means) and on an elongated
+    grid: core rows bit-exact at the build state, then 20 steps from rest
+    against the oracle's stencil-population run."""
+    torch = torch_cuda()
+    st = _state(case)
+    pos, box = st.pos, st.box
+    n = pos.shape[1]
+    if case == "elongated":  # the uniform gas holds overlapping pairs: start from a spaced one
+        pos = inputs.random_gas(n, box, seed=17, min_dist=0.9).pos
+    ref = oracle.System(pos, box, RS, RC, SKIN).lists(kinds=("core",))
+    with Context(n, lanes=1, shell_source="stencil") as ctx:
+        x, v = dev(pos), torch.zeros((3, n), dtype=torch.float64, device="cuda")
+        ctx.build(x, box, RS, RC)
+        ctx.step(x, v, nsteps=0, dt=0.005, P=10, seed=4, rebuild_every=10)
+        got = ctx.export_lists(kinds=("core",))
+    assert_lists_equal(got, ref, kinds=("core",))
+    with Context(n, lanes=1, shell_source="stencil") as ctx:
+        x, v = dev(pos), torch.zeros((3, n), dtype=torch.float64, device="cuda")
+        ctx.build(x, box, RS, RC)
+        ctx.step(x, v, nsteps=20, dt=0.005, P=10, seed=4, rebuild_every=10)
+    xo, vo, _, _ = oracle.md_run(pos, np.zeros_like(pos), box, RS, RC, SKIN, 0.005, 20, p=10, seed=4,
+                                 K=10, shell_source="stencil")
+    assert rel_l2(host(x), xo) < 1e-12
+    assert rel_l2(host(v), vo) < 1e-9
