@@ -217,8 +217,10 @@ rbl_status rbl_export_binning(rbl_ctx* ctx, int32_t* ncell, int64_t* slot_of_id,
  * (RBL_E_NONFINITE) or warnings (RBL_W_SKIN), clearing them. */
 rbl_status rbl_sync(rbl_ctx* ctx);
 
-/* Per-kernel timing with HIP events recorded on the context's stream around
- * every launch while enabled.  rbl_kernel_stats fills, for kernel class
+/* Per-kernel timing with HIP events on the context's stream while enabled:
+ * the force kernels and the fused list build carry a start and a stop event
+ * in their dispatch (the kernel's own duration), other kernels have events
+ * recorded around the launch.  rbl_kernel_stats fills, for kernel class
  * `kind` (0 force RBL, 1 force full, 2 list build, 3 binning, 4 integrate,
  * 5 reduce, 6 predraw), the number of launches and their summed duration in
  * milliseconds since profiling was enabled; it synchronises. */
