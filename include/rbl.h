@@ -94,8 +94,9 @@ typedef struct rbl_config {
                                   rbl_step of the context time both and keep the faster
                                   (see rbl_launch_modes).  Results are the same. */
     double capacity_factor;    /* rows are first sized to capacity_factor x the longest row
-                                  seen + 8 (default 1.25); rows that overflow later are regrown
-                                  (rbl_build) or the run is repeated with longer rows
+                                  seen + 8 (default 1.25; the fused build's LDS shell-list
+                                  room takes at most 1.1); rows that overflow later are
+                                  regrown (rbl_build) or the run is repeated with longer rows
                                   (rbl_step), so results never depend on it */
     const int64_t* replica_offsets; /* host, n_replicas + 1 prefix offsets into the particle
                                        arrays; NULL when n_replicas == 1 */

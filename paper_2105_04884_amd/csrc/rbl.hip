@@ -626,11 +626,19 @@ rbl_status launch_fused(rbl_ctx* c, int P, uint64_t seed, uint64_t step0, int K,
 }
 
 // LDS shell-list room per centre particle of the fused kernel: the longest
-// shell row seen, with the context's headroom (at least 1.5x after an
-// overflow), rounded up to 8 entries.
+// shell row seen, with the context's headroom but at most kListRoomFactor
+// (at least 1.5x after an overflow), rounded up to 8 entries.  The room
+// sets how many particles share a wavefront's list budget, so a tighter
+// first room means fewer cells split into two groups; a row that outgrows
+// it is caught and the run repeated with a larger room.  (At N = 1e6 the
+// longest shell row grows from 199 to 210 over 2000 steps as the lattice
+// start melts, against a first room of 232.)
+constexpr double kListRoomFactor = 1.1;
+
 void grow_cap_list(rbl_ctx* c, int need, bool regrow)
 {
-    const double f = regrow ? std::max(1.5, c->cfg.capacity_factor) : c->cfg.capacity_factor;
+    const double f = regrow ? std::max(1.5, c->cfg.capacity_factor)
+                            : std::min(c->cfg.capacity_factor, kListRoomFactor);
     int64_t cap = (int64_t)std::ceil(std::max(need, 1) * f) + 8;
     if (regrow) cap = std::max<int64_t>(cap, (int64_t)c->cap_list + 16);
     cap = (cap + 7) / 8 * 8;
