@@ -717,12 +717,6 @@ __device__ __forceinline__ int64_t rfl(int64_t v)
 // places the lane select (in M0 when the data operand is an SGPR).
 extern "C" __device__ int rbl_writelane(int value, int lane, int old) __asm("llvm.amdgcn.writelane");
 
-// Lane `lane` of v0, v1 takes the wave-uniform values s0, s1.
-__device__ __forceinline__ void write_lane2(uint32_t& v0, uint32_t& v1, uint32_t s0, uint32_t s1, int lane)
-{
-    v0 = (uint32_t)rbl_writelane((int)s0, lane, (int)v0);
-    v1 = (uint32_t)rbl_writelane((int)s1, lane, (int)v1);
-}
 
 // s_waitcnt immediate with vmcnt = 0 and the expcnt / lgkmcnt fields at
 // their maximum (no wait on them)
