@@ -1401,7 +1401,7 @@ __device__ __forceinline__ double group_sum(double v)
 template <int PREC, int MODE, bool ENERGY, bool ERFC, int LPP>
 __device__ __forceinline__ void force_tile_lpp(const ForceArgs& a, int64_t tile)
 {
-    constexpr int U = 2;
+    constexpr int U = (LPP == 2 && !ERFC) ? 4 : 2;  // neighbours per lane in flight
     const int64_t g = tile * blockDim.x + threadIdx.x;
     const int64_t slot = g / LPP;
     const int l = (int)(g % LPP);
