@@ -1100,8 +1100,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PMAX <= 32 
                 const uint32_t pid = (uint32_t)(fa.perm[islot] - id_base);
                 floyd_draw<PMAX>(S, fa.seed, pid, (uint32_t)(s0 + rr), (uint32_t)rep_id, P, small ? P + 1 : n);
                 bool bad = false;
+                int val[PMAX];
 #pragma unroll
                 for (int qq = 0; qq < PMAX; ++qq) {
+                    val[qq] = islot;
                     if (qq < P) {
                         const uint32_t k = small ? (uint32_t)qq : S[qq];
                         const bool own = (int)k < n;
@@ -1122,8 +1124,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PMAX <= 32 
                         }
                         const bool ok = j >= 0 && (int64_t)j < a.n_slots;
                         bad |= own && !ok;
-                        out[qq] = (own && ok) ? j : islot;
+                        val[qq] = (own && ok) ? j : islot;
                     }
+                }
+                // the particle's P entries are contiguous: for even P (rows
+                // 8-byte aligned, PMAX is even) in pairs
+                if ((P & 1) == 0) {
+#pragma unroll
+                    for (int qq = 0; qq < PMAX; qq += 2)
+                        if (qq < P) *reinterpret_cast<int2*>(out + qq) = make_int2(val[qq], val[qq + 1]);
+                } else {
+#pragma unroll
+                    for (int qq = 0; qq < PMAX; ++qq)
+                        if (qq < P) out[qq] = val[qq];
                 }
                 if (bad) atomicOr(&a.flags[kFlagBadSlot], 32);
             }
