@@ -8,11 +8,21 @@ velocity Verlet at dt = 0.005.  One step = one pass of the whole path:
 kick/drift, (every 10th step) binning + list build + batch draw, the force
 and the mean-force reduction.
 
-Variants timed back to back on the same GPU, each for --steps steps after
---warmup steps: RBL in the mixed form (FP32 pair arithmetic, FP64
-classification and accumulation; the headline ``value``), RBL in FP64, and
-the full Verlet list (direct truncation at r_c) in both precisions; batch
-sizes P = 5, 10, 20 for the mixed RBL.
+Variants timed back to back on the same GPU: RBL in the mixed form (FP32
+pair arithmetic, FP64 classification and accumulation; the headline
+``value``), RBL in FP64, and the full Verlet list (direct truncation at r_c)
+in both precisions; batch sizes P = 5, 10, 20 for the mixed RBL.
+
+Timing: the step counts are taken in whole list lifetimes (10 steps).  Each
+variant runs the warm-up (--warmup rounded up to lifetimes, at least one;
+the first run also autotunes the force kernel) from the initial arrays, then
+--repeats timed blocks of --steps steps (rounded up to lifetimes), each
+continuing the state held on the GPU (rbl_continue: every lifetime a replay
+of the captured graph, no list build from host arrays) between device
+synchronisations.  ``ms_per_step`` is the median block's time per step.
+
+The CPU oracle baseline runs first, before the GPU is touched, on one core
+and on all host cores the process may use (at most 16).
 
 Prints one JSON line (rank 0, N = 1 GPU).
 """
@@ -40,14 +50,22 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def parse():
+def parse(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000)
-    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=1000,
+                    help="steps per timed block (rounded up to whole 10-step list lifetimes)")
+    ap.add_argument("--warmup", type=int, default=100,
+                    help="warm-up steps (rounded up to whole list lifetimes, at least one)")
+    ap.add_argument("--repeats", type=int, default=5,
+                    help="timed blocks per variant; the median is reported")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rows", type=int, default=400_000,
-                    help="rows of the N = 1M state the CPU oracle leg processes")
+    ap.add_argument("--cpu-rows", type=int, default=100_000,
+                    help="rows of the N = 1M state the single-core CPU oracle leg processes "
+                         "(the all-core leg takes every row)")
+    ap.add_argument("--cpu-workers", type=int, default=0,
+                    help="processes of the all-core CPU oracle leg (0: the usable host cores, "
+                         "at most 16)")
     ap.add_argument("--variants", default="all", help="comma list or 'all'")
     ap.add_argument("--table1-equil", type=int, default=200_000,
                     help="equilibration steps of the table1 workload")
@@ -76,7 +94,26 @@ def parse():
     ap.add_argument("--calib-copy-mb", type=int, default=1024,
                     help="size of the plain device copy timed first: the attainable HBM "
                          "bandwidth, and the reference for the byte counters of a profiler run")
-    return ap.parse_args()
+    return ap.parse_args(argv)
+
+
+def plan(args):
+    """Checks the arguments and turns the step counts into whole list
+    lifetimes: returns (warm-up steps, steps per timed block).  Exits with
+    status 2 and a message on arguments this bench cannot run."""
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only (this build has no multi-GPU path); "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    if args.steps < 1 or args.warmup < 0 or args.repeats < 1:
+        print("--steps and --repeats must be >= 1 and --warmup >= 0", file=sys.stderr)
+        sys.exit(2)
+    return lifetimes(args.warmup), lifetimes(args.steps)
+
+
+def lifetimes(n, K=K_REBUILD):
+    """n steps rounded up to whole list lifetimes, at least one."""
+    return max(K, -(-int(n) // K) * K)
 
 
 FP64_VECTOR_PEAK_TFLOPS = 78.6   # 256 CUs x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
@@ -261,37 +298,59 @@ def force_roofline(res, fk):
     }
 
 
-def run_variant(name, x0, v0, box, precision, P, use_full, steps, warmup, torch, source="shell",
-                pin=False):
-    from paper_2105_04884_amd import Context, KIND_FORCE_RBL, KIND_FORCE_FULL, KIND_BUILD, \
-        KIND_BIN, KIND_INTEGRATE, KIND_REDUCE, KIND_PREDRAW
+KINDS = ("force_rbl", "force_full", "build", "binning", "integrate", "reduce", "predraw")
+
+
+def timed_blocks(ctx, x, v, torch, P, warmup, steps, repeats, use_full=False):
+    """Warm-up run of `warmup` steps from the arrays x, v (rbl_step; the first
+    run of a context autotunes the force kernel), then `repeats` blocks of
+    `steps` steps that continue the state held on the GPU (rbl_continue:
+    whole captured lifetimes replayed), each timed between device
+    synchronisations, then one more block with per-kernel HIP events on the
+    context's stream.  All blocks start at a list build (step counts are
+    whole lifetimes)."""
+    from paper_2105_04884_amd import (KIND_FORCE_RBL, KIND_FORCE_FULL, KIND_BUILD, KIND_BIN,
+                                      KIND_INTEGRATE, KIND_REDUCE, KIND_PREDRAW)
+    st0, _ = ctx.step(x, v, nsteps=warmup, dt=DT, P=P, seed=1, step0=0, rebuild_every=K_REBUILD,
+                      use_full=use_full)
+    times, statuses, attempts = [], [int(st0)], []
+    for _ in range(repeats):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, _ = ctx.cont(steps)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        statuses.append(int(st))
+        attempts.append(ctx.last_run()["attempts"])
+    ctx.set_profiling(True)
+    st, _ = ctx.cont(steps)
+    statuses.append(int(st))
+    kinds = dict(zip(KINDS, (KIND_FORCE_RBL, KIND_FORCE_FULL, KIND_BUILD, KIND_BIN, KIND_INTEGRATE,
+                             KIND_REDUCE, KIND_PREDRAW)))
+    stats = {k: ctx.kernel_stats(q) for k, q in kinds.items()}
+    ctx.set_profiling(False)
+    med = float(np.median(times))
+    return {
+        "median_s": med,
+        "block_seconds": [round(t, 6) for t in times],
+        # RBL_OK 0 / RBL_W_SKIN 1 over the warm-up, timed and profiled blocks
+        "status": max(statuses),
+        "attempts_max": max(attempts),
+        "kernels_ms": {k: {"launches": s_[0], "total_ms": s_[1],
+                           "avg_us": 1e3 * s_[1] / s_[0] if s_[0] else 0.0} for k, s_ in stats.items()},
+    }
+
+
+def run_variant(name, x0, v0, box, precision, P, use_full, warmup, steps, repeats, torch,
+                source="shell", pin=False):
+    from paper_2105_04884_amd import Context
     lists = ("full",) if use_full else ("core", "shell")
     x = x0.clone()
     v = v0.clone()
     launch = {"lanes": 4 if use_full else 2, "persistent": 1} if pin else {}
     ctx = Context(N, precision=precision, lists=lists, skin=SKIN, shell_source=source, **launch)
     ctx.build(x, box, RS, RC)
-    if warmup > 0:
-        ctx.step(x, v, nsteps=warmup, dt=DT, P=P, seed=1, step0=0, rebuild_every=K_REBUILD,
-                 use_full=use_full)
-    step0 = warmup
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    status, _ = ctx.step(x, v, nsteps=steps, dt=DT, P=P, seed=1, step0=step0,
-                         rebuild_every=K_REBUILD, use_full=use_full)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    # second pass of the same length with per-kernel HIP events on the
-    # context's stream (the events add small gaps, so it is not the clock of
-    # `value`)
-    ctx.set_profiling(True)
-    ctx.step(x, v, nsteps=steps, dt=DT, P=P, seed=1, step0=step0 + steps,
-             rebuild_every=K_REBUILD, use_full=use_full)
-    kinds = {"force_rbl": KIND_FORCE_RBL, "force_full": KIND_FORCE_FULL, "build": KIND_BUILD,
-             "binning": KIND_BIN, "integrate": KIND_INTEGRATE, "reduce": KIND_REDUCE,
-             "predraw": KIND_PREDRAW}
-    stats = {k: ctx.kernel_stats(q) for k, q in kinds.items()}
-    ctx.set_profiling(False)
+    tb = timed_blocks(ctx, x, v, torch, P, warmup, steps, repeats, use_full)
     info = ctx.info()
     tuning = ctx.tuning()
     counts = ctx.row_counts()
@@ -302,21 +361,27 @@ def run_variant(name, x0, v0, box, precision, P, use_full, steps, warmup, torch,
             "full": float(counts[2].mean())}
     res = {
         "name": name, "precision": precision, "P": P, "full": use_full, "shell_source": source,
-        "ms_per_step": 1e3 * elapsed / steps,
-        "atom_steps_per_s": N * steps / elapsed,
-        "status": int(status),
-        "kernels_ms": {k: {"launches": s[0], "total_ms": s[1],
-                           "avg_us": 1e3 * s[1] / s[0] if s[0] else 0.0} for k, s in stats.items()},
+        "ms_per_step": 1e3 * tb["median_s"] / steps,
+        "atom_steps_per_s": N * steps / tb["median_s"],
+        "block_seconds": tb["block_seconds"],
+        "status": tb["status"],
+        "attempts_max": tb["attempts_max"],
+        "kernels_ms": tb["kernels_ms"],
         "mean_row": mean,
         "caps": info,
         "tuning": tuning,
         "build_candidates": candidates,
     }
-    log(f"[bench] {name}: {res['ms_per_step']:.4f} ms/step, {res['atom_steps_per_s']:.3e} atom-steps/s")
+    log(f"[bench] {name}: {res['ms_per_step']:.4f} ms/step, {res['atom_steps_per_s']:.3e} atom-steps/s "
+        f"(blocks {tb['block_seconds']} s, status {tb['status']})")
     return res
 
 
-def run_slab(torch, steps=500, warmup=20, P=20):
+def kernels_avg_us(tb):
+    return {k: round(v["avg_us"], 2) for k, v in tb["kernels_ms"].items() if v["launches"]}
+
+
+def run_slab(torch, warmup, steps, repeats, P=20):
     """Charged liquid slab in vapour, N = 2,000,000, LJ + real-space Ewald
     (alpha 0.3), r_s = 1.5, r_c = 5.0, P = 20, mixed precision."""
     from paper_2105_04884_amd import Context, inputs
@@ -326,41 +391,18 @@ def run_slab(torch, steps=500, warmup=20, P=20):
     q = torch.from_numpy(st.charges).cuda()
     with Context(n, precision="mixed", skin=SKIN, pair="lj_erfc", alpha=0.3, charges=q) as ctx:
         ctx.build(x, st.box, 1.5, 5.0)
-        el, status, avg = timed_steps(ctx, x, v, steps, warmup, P, torch, 50)
+        tb = timed_blocks(ctx, x, v, torch, P, warmup, steps, repeats)
+    el = tb["median_s"]
     log(f"[bench] slab: {1e3 * el / steps:.3f} ms/step, {n * steps / el:.3e} atom-steps/s")
     return {"workload": "charged LJ slab N=2,000,000, box L x L x 3L (L=133.5), liquid rho=0.8 in the "
                         "middle third, vapour rho=0.02, charges +-1, T=0.9; LJ + erfc(alpha r)/r with "
                         "alpha=0.3, r_s=1.5 r_c=5.0 skin=0.3, P=20, rebuild every 10 steps, dt=0.005, mixed",
-            "n_particles": n, "steps": steps, "atom_steps_per_s": n * steps / el,
-            "ms_per_step": 1e3 * el / steps, "status": status, "kernels_avg_us": avg}
+            "n_particles": n, "steps": steps, "repeats": repeats, "atom_steps_per_s": n * steps / el,
+            "ms_per_step": 1e3 * el / steps, "status": tb["status"], "attempts_max": tb["attempts_max"],
+            "kernels_avg_us": kernels_avg_us(tb)}
 
 
-def timed_steps(ctx, x, v, steps, warmup, P, torch, profile_steps):
-    """Warm-up, then `steps` steps between synchronisations (the clock of
-    the result), then a shorter pass with per-kernel events."""
-    from paper_2105_04884_amd import KIND_BUILD, KIND_FORCE_RBL, KIND_INTEGRATE, KIND_BIN, KIND_REDUCE
-    if warmup:
-        ctx.step(x, v, nsteps=warmup, dt=DT, P=P, seed=1, step0=0, rebuild_every=K_REBUILD)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    status, _ = ctx.step(x, v, nsteps=steps, dt=DT, P=P, seed=1, step0=warmup, rebuild_every=K_REBUILD)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    ctx.set_profiling(True)
-    ctx.step(x, v, nsteps=profile_steps, dt=DT, P=P, seed=1, step0=warmup + steps,
-             rebuild_every=K_REBUILD)
-    kinds = {"force_rbl": KIND_FORCE_RBL, "build": KIND_BUILD, "binning": KIND_BIN,
-             "integrate": KIND_INTEGRATE, "reduce": KIND_REDUCE}
-    avg = {}
-    for k, q in kinds.items():
-        nl, ms = ctx.kernel_stats(q)
-        if nl:
-            avg[k] = round(1e3 * ms / nl, 2)
-    ctx.set_profiling(False)
-    return elapsed, int(status), avg
-
-
-def run_ensemble(torch, steps=500, warmup=20, seq_replicas=16, seq_steps=100):
+def run_ensemble(torch, warmup, steps, repeats, seq_replicas=16):
     """512 independent replicas (N log-uniform in [2000, 65536], density
     uniform in [0.6, 0.9], T uniform in [0.8, 1.5]) advanced together, one
     launch per kernel per step, against the same replicas one context each."""
@@ -371,14 +413,16 @@ def run_ensemble(torch, steps=500, warmup=20, seq_replicas=16, seq_steps=100):
     out = {"workload": "512 LJ replicas, N log-uniform in [2000, 65536] (sum %d), density U[0.6, 0.9], "
                        "T U[0.8, 1.5], r_s=1.5 r_c=3.5 skin=0.3, P=10, rebuild every 10 steps, "
                        "dt=0.005" % n,
-           "replicas": 512, "n_total": n, "steps": steps}
+           "replicas": 512, "n_total": n, "steps": steps, "repeats": repeats}
     for precision in ("mixed", "fp64"):
         x, v = torch.from_numpy(pos).cuda(), torch.from_numpy(vel).cuda()
         with Context(n, precision=precision, replica_offsets=off, skin=SKIN) as ctx:
             ctx.build(x, boxes, RS, RC)
-            el, st, avg = timed_steps(ctx, x, v, steps, warmup, 10, torch, 100)
+            tb = timed_blocks(ctx, x, v, torch, 10, warmup, steps, repeats)
+        el = tb["median_s"]
         out[precision] = {"atom_steps_per_s": n * steps / el, "ms_per_step": 1e3 * el / steps,
-                          "status": st, "kernels_avg_us": avg}
+                          "status": tb["status"], "attempts_max": tb["attempts_max"],
+                          "kernels_avg_us": kernels_avg_us(tb)}
         log(f"[bench] ensemble {precision}: {1e3 * el / steps:.3f} ms/step, {n * steps / el:.3e} atom-steps/s")
     # the same replicas one context each, on a sample of them
     picks = np.linspace(0, 511, seq_replicas).astype(int)
@@ -388,18 +432,18 @@ def run_ensemble(torch, steps=500, warmup=20, seq_replicas=16, seq_steps=100):
         x, v = torch.from_numpy(s_.pos).cuda(), torch.from_numpy(s_.vel).cuda()
         with Context(s_.n, precision="mixed", skin=SKIN) as ctx:
             ctx.build(x, s_.box, RS, RC)
-            el, _, _ = timed_steps(ctx, x, v, seq_steps, warmup, 10, torch, 10)
-        tot_atoms += s_.n * seq_steps
-        tot_s += el
+            tb = timed_blocks(ctx, x, v, torch, 10, warmup, steps, 1)
+        tot_atoms += s_.n * steps
+        tot_s += tb["median_s"]
     out["sequential_mixed"] = {"atom_steps_per_s": tot_atoms / tot_s,
                                "sample": f"{seq_replicas} of the 512 replicas, one context each, "
-                                         f"{seq_steps} steps each"}
+                                         f"{steps} steps each"}
     out["speedup_batched_vs_sequential"] = out["mixed"]["atom_steps_per_s"] / (tot_atoms / tot_s)
     log(f"[bench] ensemble sequential: {tot_atoms / tot_s:.3e} atom-steps/s")
     return out
 
 
-def run_large(torch, steps=200, warmup=20):
+def run_large(torch, warmup, steps, repeats):
     """N = 2^24 LJ fluid, density 0.8, T = 1.2, r_s = 1.3, r_c = 4.0, P = 10,
     mixed precision, lists every 10 steps."""
     from paper_2105_04884_amd import Context, inputs
@@ -408,13 +452,15 @@ def run_large(torch, steps=200, warmup=20):
     x, v = torch.from_numpy(st.pos).cuda(), torch.from_numpy(st.vel).cuda()
     with Context(n, precision="mixed", skin=SKIN) as ctx:
         ctx.build(x, st.box, 1.3, 4.0)
-        el, status, avg = timed_steps(ctx, x, v, steps, warmup, 10, torch, 50)
+        tb = timed_blocks(ctx, x, v, torch, 10, warmup, steps, repeats)
         tuning = ctx.tuning()
+    el = tb["median_s"]
     log(f"[bench] large: {1e3 * el / steps:.3f} ms/step, {n * steps / el:.3e} atom-steps/s")
     return {"workload": "LJ fluid N=16,777,216 rho=0.8 T=1.2, r_s=1.3 r_c=4.0 skin=0.3, P=10, "
                         "rebuild every 10 steps, dt=0.005, mixed",
-            "n_particles": n, "steps": steps, "atom_steps_per_s": n * steps / el,
-            "ms_per_step": 1e3 * el / steps, "status": status, "kernels_avg_us": avg,
+            "n_particles": n, "steps": steps, "repeats": repeats, "atom_steps_per_s": n * steps / el,
+            "ms_per_step": 1e3 * el / steps, "status": tb["status"], "attempts_max": tb["attempts_max"],
+            "kernels_avg_us": kernels_avg_us(tb),
             # the autotuner's launch-mode choice and times (one block per tile
             # against the persistent grid) and lanes per particle
             "force_launch": {"persistent": tuning["persistent_rbl"],
@@ -606,53 +652,80 @@ def force_error_vs_oracle(x0, box, torch, rows):
     return out
 
 
-def cpu_baseline(st, rows_n):
-    """The CPU oracle (single thread, FP64, as it stands) on a bounded sample
-    of the workload: one list build and K_REBUILD RBL force evaluations for
-    `rows_n` rows of the N = 1M state; the per-row cost is scaled to
-    atom-steps/s of the full system."""
+# State the CPU oracle workers read (set before the pool forks, so the
+# children share the parent's arrays instead of receiving copies).
+_CPU_STATE = {}
+
+
+def _oracle_rows_job(job):
+    """One worker of the CPU oracle leg: one list build for `rows` and
+    K_REBUILD force evaluations there (RBL at P = 10, or the full list);
+    returns (seconds of the build, seconds of the forces)."""
     import oracle
-    rows = np.arange(0, N, max(1, N // rows_n), dtype=np.int64)[:rows_n]
+    rows, full = job
+    pos, box = _CPU_STATE["pos"], _CPU_STATE["box"]
     t0 = time.perf_counter()
-    sysm = oracle.System(st.pos, st.box, RS, RC, SKIN)
-    L = sysm.lists(rows=rows, kinds=("core", "shell"))
+    L = oracle.System(pos, box, RS, RC, SKIN).lists(rows=rows, kinds=("full",) if full else ("core", "shell"))
     t_build = time.perf_counter() - t0
     t0 = time.perf_counter()
-    for s in range(K_REBUILD):
-        oracle.rbl_forces(st.pos, st.box, RS, RC, L, 10, 1, s)
-    t_force = (time.perf_counter() - t0) / K_REBUILD
-    per_row_step = t_build / K_REBUILD / len(rows) + t_force / len(rows)
-    value = 1.0 / per_row_step
-    return {
-        "value": value,
-        "unit": "atom-steps/s",
-        "cores": 1,
-        "kind": "oracle",
-        "sample": (f"{len(rows)} of the {N} rows of the density-0.8442 fluid: one core+shell "
-                   f"list build ({t_build:.1f} s) and {K_REBUILD} RBL force evaluations at P=10 "
-                   f"({t_force * K_REBUILD:.1f} s), scaled per atom-step with lists rebuilt "
-                   f"every {K_REBUILD} steps; single-threaded FP64 C"),
-        "seconds": t_build + K_REBUILD * t_force,
+    for s_ in range(K_REBUILD):
+        if full:
+            oracle.full_forces(pos, box, RC, L)
+        else:
+            oracle.rbl_forces(pos, box, RS, RC, L, 10, 1, s_)
+    return t_build, time.perf_counter() - t0
+
+
+def usable_cores(limit=16):
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count() or 1
+    return max(1, min(limit, n))
+
+
+def cpu_oracle(st, rows_1core, workers, full=False):
+    """The CPU oracle as it stands (single-threaded FP64 C) on the N = 1M
+    state: one list build and K_REBUILD force evaluations (RBL at P = 10, or
+    the full list) for a sample of rows, scaled to atom-steps/s with lists
+    rebuilt every K_REBUILD steps.  Run on one core for `rows_1core` rows,
+    then on `workers` processes, each a contiguous share of every row
+    (wall-clock time of the whole pool)."""
+    import multiprocessing as mp
+    _CPU_STATE["pos"], _CPU_STATE["box"] = st.pos, st.box
+    rows1 = np.arange(0, N, max(1, N // rows_1core), dtype=np.int64)[:rows_1core]
+    tb, tf = _oracle_rows_job((rows1, full))
+    one = len(rows1) * K_REBUILD / (tb + tf)
+    what = "full-list" if full else "core+shell list"
+    force = "full-list force evaluations" if full else "RBL force evaluations at P=10"
+    out = {
+        "value": one, "unit": "atom-steps/s", "cores": 1, "kind": "oracle",
+        "sample": (f"{len(rows1)} of the {N} rows of the density-0.8442 fluid: one {what} build "
+                   f"({tb:.1f} s) and {K_REBUILD} {force} ({tf:.1f} s), scaled per atom-step with "
+                   f"lists rebuilt every {K_REBUILD} steps; single-threaded FP64 C"),
+        "seconds": tb + tf,
     }
-
-
-def cpu_full_list(st, rows_n):
-    """The same oracle timing for the full Verlet list (direct truncation at
-    r_c), the comparator of the method."""
-    import oracle
-    rows = np.arange(0, N, max(1, N // rows_n), dtype=np.int64)[:rows_n]
-    t0 = time.perf_counter()
-    L = oracle.System(st.pos, st.box, RS, RC, SKIN).lists(rows=rows, kinds=("full",))
-    t_build = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    for _ in range(K_REBUILD):
-        oracle.full_forces(st.pos, st.box, RC, L)
-    t_force = (time.perf_counter() - t0) / K_REBUILD
-    per_row_step = t_build / K_REBUILD / len(rows) + t_force / len(rows)
-    return {"value": 1.0 / per_row_step, "unit": "atom-steps/s", "cores": 1, "kind": "oracle",
-            "sample": (f"{len(rows)} rows: one full-list build ({t_build:.1f} s) and {K_REBUILD} "
-                       f"full-list force evaluations ({t_force * K_REBUILD:.1f} s), scaled per "
-                       f"atom-step; single-threaded FP64 C")}
+    if workers > 1:
+        rows_all = np.arange(N, dtype=np.int64)
+        if full:
+            rows_all = rows_all[: N // 4]
+        jobs = [(c, full) for c in np.array_split(rows_all, workers)]
+        ctx = mp.get_context("fork")
+        t0 = time.perf_counter()
+        with ctx.Pool(workers) as pool:
+            parts = pool.map(_oracle_rows_job, jobs, chunksize=1)
+        wall = time.perf_counter() - t0
+        out["all_cores"] = {
+            "value": len(rows_all) * K_REBUILD / wall, "unit": "atom-steps/s", "cores": workers,
+            "kind": "oracle",
+            "sample": (f"{len(rows_all)} rows split over {workers} processes of the same single-threaded "
+                       f"oracle (one {what} build and {K_REBUILD} {force} each), wall-clock of the "
+                       f"pool {wall:.1f} s"),
+            "seconds": wall,
+            "max_worker_seconds": max(a + b for a, b in parts),
+        }
+    _CPU_STATE.clear()
+    return out
 
 
 def method_error(x0, box):
@@ -819,26 +892,41 @@ def summarize_valu(valu_dir, trace_dir, command, P=10):
     print("\n".join(lines))
 
 
-def main():
-    args = parse()
+def guarded(name, fn, *a, **kw):
+    """Runs an optional part of the bench; a failure is logged and recorded
+    instead of ending the run before the JSON line."""
+    try:
+        return fn(*a, **kw)
+    except Exception as e:  # noqa: BLE001 -- the line is still printed
+        log(f"[bench] {name} failed: {type(e).__name__}: {e}")
+        return {"error": f"{type(e).__name__}: {e}"}
+
+
+def main(argv=None):
+    args = parse(argv)
     if args.summarize:
         summarize(*args.summarize, args.profile_command, args.calib_copy_mb)
         if args.valu_dir:
             summarize_valu(args.valu_dir, args.summarize[0], args.profile_command)
         return
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only (this build has no multi-GPU path); "
-              "run with --gpus 1", file=sys.stderr)
-        sys.exit(2)
-    if args.steps % K_REBUILD or args.warmup % K_REBUILD:
-        print("--steps and --warmup must be multiples of 10 (the list lifetime)", file=sys.stderr)
-        sys.exit(2)
-    import torch
+    warmup, steps = plan(args)
     from paper_2105_04884_amd import inputs
 
-    copy_gbs = copy_bandwidth(torch, args.calib_copy_mb)
     log("[bench] generating the N=1M fluid")
     st = inputs.million_fluid(seed=1)
+    # the CPU oracle first, before anything touches the GPU
+    cpu = cpu_full = None
+    if not args.no_cpu_baseline:
+        workers = args.cpu_workers or usable_cores()
+        log(f"[bench] CPU oracle baseline (1 core, then {workers} processes)")
+        cpu = guarded("cpu baseline", cpu_oracle, st, args.cpu_rows, workers)
+        cpu_full = guarded("cpu baseline (full list)", cpu_oracle, st, max(1, args.cpu_rows // 4),
+                           workers, full=True)
+        log(f"[bench] CPU oracle: {cpu.get('value', 0):.3e} atom-steps/s on 1 core, "
+            f"{cpu.get('all_cores', {}).get('value', 0):.3e} on {workers}")
+
+    import torch
+    copy_gbs = copy_bandwidth(torch, args.calib_copy_mb)
     x0 = torch.from_numpy(st.pos).cuda()
     v0 = torch.from_numpy(st.vel).cuda()
     variants = [
@@ -853,21 +941,16 @@ def main():
     if args.variants != "all":
         keep = set(args.variants.split(","))
         variants = [v for v in variants if v[0] in keep]
+    log(f"[bench] {warmup} warm-up steps, {args.repeats} timed blocks of {steps} steps per variant")
     results = {}
     for name, prec, P, full, source in variants:
         log(f"[bench] variant {name}")
-        results[name] = run_variant(name, x0, v0, st.box, prec, P, full, args.steps,
-                                    args.warmup, torch, source, args.pin_launch)
+        results[name] = run_variant(name, x0, v0, st.box, prec, P, full, warmup, steps, args.repeats,
+                                    torch, source, args.pin_launch)
     head = results.get("rbl_mixed_p10") or next(iter(results.values()))
 
-    log("[bench] force error vs the FP64 oracle (sampled rows)")
-    rows = np.random.default_rng(0).choice(N, size=2000, replace=False)
-    errs = force_error_vs_oracle(x0, st.box, torch, rows)
-    log("[bench] method error of RBL against the full list")
-    merr = method_error(x0, st.box)
-
     # roofline of the dominant kernel of the headline variant (largest
-    # share of the event-timed pass), and of the force kernel beside it
+    # share of the event-timed block), and of the force kernel beside it
     km = head["kernels_ms"]
     dom = max(km, key=lambda k: km[k]["total_ms"])
     fk = "force_full" if head["full"] else "force_rbl"
@@ -889,30 +972,29 @@ def main():
     roof["share_of_step"] = km[dom]["total_ms"] / sum(k["total_ms"] for k in km.values())
     roof["hbm_copy_GBs"] = copy_gbs
 
+    log("[bench] force error vs the FP64 oracle (sampled rows)")
+    rows = np.random.default_rng(0).choice(N, size=2000, replace=False)
+    errs = guarded("force error", force_error_vs_oracle, x0, st.box, torch, rows)
+    log("[bench] method error of RBL against the full list")
+    merr = guarded("method error", method_error, x0, st.box)
+
     extra = {}
     wl = [w for w in args.workloads.split(",") if w and w != "none"]
     if "ensemble" in wl:
         log("[bench] workload: 512-replica ensemble")
-        extra["ensemble"] = run_ensemble(torch)
+        extra["ensemble"] = guarded("ensemble", run_ensemble, torch, warmup, steps, args.repeats)
     if "large" in wl:
         log("[bench] workload: N = 2^24")
-        extra["large"] = run_large(torch)
+        extra["large"] = guarded("large", run_large, torch, warmup, steps, args.repeats)
     if "slab" in wl:
         log("[bench] workload: charged slab")
-        extra["slab"] = run_slab(torch)
+        extra["slab"] = guarded("slab", run_slab, torch, warmup, steps, args.repeats)
     if "eos" in wl:
         log("[bench] workload: Sec. III equation of state")
-        extra["eos"] = run_eos(torch)
+        extra["eos"] = guarded("eos", run_eos, torch)
     if "table1" in wl:
         log("[bench] workload: Sec. III gas-liquid coexistence (Table I)")
-        extra["table1"] = run_table1(torch, args.table1_equil, args.table1_prod)
-
-    cpu = None
-    cpu_full = None
-    if not args.no_cpu_baseline:
-        log("[bench] CPU oracle baseline")
-        cpu = cpu_baseline(st, args.cpu_rows)
-        cpu_full = cpu_full_list(st, max(1, args.cpu_rows // 4))
+        extra["table1"] = guarded("table1", run_table1, torch, args.table1_equil, args.table1_prod)
 
     def speed(name):
         r = results.get(name)
@@ -923,8 +1005,14 @@ def main():
         "value": head["atom_steps_per_s"],
         "unit": "atom-steps/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
+        "steps": steps,
+        "warmup": warmup,
+        "steps_requested": args.steps,
+        "warmup_requested": args.warmup,
+        "repeats": args.repeats,
+        "timing": ("median over the repeats of one block of `steps` steps (whole 10-step list "
+                   "lifetimes replayed as captured graphs, continuing the GPU-resident state after "
+                   "`warmup` steps), between device synchronisations"),
         "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
@@ -934,13 +1022,16 @@ def main():
         "config": {"workload": "LJ fluid N=1,000,000 rho=0.8442 T=1.0, r_s=1.5 r_c=3.5 skin=0.3, "
                                "P=10, rebuild every 10 steps, dt=0.005, velocity Verlet NVE",
                    "n_particles": N, "P": head["P"], "precision": head["precision"]},
+        "status": head["status"],
         "roofline": roof,
         "cpu_baseline": cpu,
         "variants": {k: {"atom_steps_per_s": r["atom_steps_per_s"], "ms_per_step": r["ms_per_step"],
-                         "kernels_avg_us": {q: round(s["avg_us"], 2) for q, s in r["kernels_ms"].items()
-                                            if s["launches"]},
-                         "kernels_total_ms": {q: round(s["total_ms"], 3) for q, s in r["kernels_ms"].items()
-                                              if s["launches"]},
+                         "block_seconds": r["block_seconds"], "status": r["status"],
+                         "attempts_max": r["attempts_max"],
+                         "kernels_avg_us": {q: round(s_["avg_us"], 2) for q, s_ in r["kernels_ms"].items()
+                                            if s_["launches"]},
+                         "kernels_total_ms": {q: round(s_["total_ms"], 3) for q, s_ in r["kernels_ms"].items()
+                                              if s_["launches"]},
                          "mean_row": r["mean_row"], "tuning": r["tuning"], "caps": r["caps"]}
                      for k, r in results.items()},
         "speedup_rbl_mixed_vs_full_fp64": (speed("rbl_mixed_p10") / speed("full_fp64")

@@ -182,6 +182,37 @@ rbl_status rbl_step(rbl_ctx* ctx, double* pos, double* vel, double* force,
                     int64_t nsteps, double dt, int P, uint64_t seed, int64_t step0,
                     int rebuild_every, int use_full, double* ev);
 
+/*
+ * Continues the last completed rbl_step (or rbl_continue) of this context
+ * for nsteps >= 1 more steps of the same schedule (Algorithm 1), from the
+ * state that run left in the context's device memory: its positions and
+ * velocities, the force of its last evaluation, and the lists and batches
+ * in use then.  dt, P, seed, rebuild_every and use_full are that run's;
+ * the steps are numbered on from its end (force evaluations end+1 ..
+ * end+nsteps), so that rbl_step over a + b steps and rbl_step over a steps
+ * followed by rbl_continue over b steps give bit-identical results.  The
+ * thermostat is the one set now.  pos, vel, force (device SoA [3][n], each
+ * may be NULL) receive the final state in the caller's order; ev (device,
+ * may be NULL) the final [U, W] per replica.  With all of them NULL the
+ * state stays in the context: a caller that advances a system in pieces
+ * pays no list build from its arrays and no copy per piece.  Lists whose
+ * rows outgrow their room are regrown and the call repeated from its
+ * starting state with a list build at its first step (the results are
+ * then those of an rbl_step started there).
+ * Errors: RBL_E_ARG (nsteps < 1), RBL_E_STATE (no completed run, or a call
+ * since then that loaded positions or drew batches: rbl_build, rbl_forces,
+ * rbl_full_forces, rbl_export_batches, rbl_rdf), RBL_E_NONFINITE,
+ * RBL_E_CAPACITY, RBL_E_NOMEM, RBL_E_HIP.  Returns RBL_W_SKIN as rbl_step.
+ */
+rbl_status rbl_continue(rbl_ctx* ctx, double* pos, double* vel, double* force,
+                        int64_t nsteps, double* ev);
+
+/* The last rbl_step / rbl_continue: attempts = passes it took (1, or more
+ * when a list outgrew its room and the call was repeated), end_step = index
+ * of its last force evaluation, resumable = 1 if rbl_continue may follow.
+ * Any pointer may be NULL. */
+rbl_status rbl_last_run(rbl_ctx* ctx, int32_t* attempts, int64_t* end_step, int32_t* resumable);
+
 /* ---- parity exports (host buffers, caller-allocated; synchronising) ---- */
 
 /* Row lengths of the last build for the particles rows[0..nrows) (IDs; NULL
@@ -204,6 +235,23 @@ rbl_status rbl_export_lists(rbl_ctx* ctx, int64_t nrows, const int64_t* rows,
 rbl_status rbl_export_batches(rbl_ctx* ctx, int P, uint64_t seed, uint64_t step,
                               int64_t nrows, const int64_t* rows,
                               int32_t* batch, int32_t* count);
+
+/* The batches stored on the device now, as the force kernels read them
+ * (eq. (4); Algorithm 1, the random choice of p partners): after an
+ * rbl_step or rbl_continue whose loop draws at each list build (cfg.predraw,
+ * or the stencil population), those the last build drew for every force
+ * evaluation of its list lifetime; after rbl_forces or rbl_export_batches
+ * that drew one step, that step.  *nsteps, *P_out and *step0 (each may be
+ * NULL) receive how many steps are stored, the batch size and the first
+ * step; with batch and count both NULL nothing else is done.  Otherwise
+ * batch (host, [nsteps][nrows][P]) receives, for step step0 + r and particle
+ * rows[k], the IDs of its drawn partners in increasing batch position, -1
+ * past count[k] = min(n_i, P) (host, [nrows]).  Synchronises.
+ * Errors: RBL_E_ARG (row out of range, only one of batch and count given),
+ * RBL_E_STATE (nothing stored: no build, or the last run drew inline). */
+rbl_status rbl_export_drawn_batches(rbl_ctx* ctx, int64_t nrows, const int64_t* rows,
+                                    int32_t* batch, int32_t* count, int32_t* nsteps,
+                                    int32_t* P_out, int64_t* step0);
 
 /* Cell binning of the last build: ncell[3r..3r+2] cells per axis of replica
  * r; slot_of_id[i] = position of particle i in the cell-sorted order of its

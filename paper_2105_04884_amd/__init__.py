@@ -185,6 +185,25 @@ class Context:
                                        int(rebuild_every), int(bool(use_full)), _dev_ptr(ev)))
         return st, ev
 
+    def cont(self, nsteps: int, pos=None, vel=None, force=None, want_ev: bool = False):
+        """Continues the last ``step``/``cont`` run for ``nsteps`` steps from
+        the state held in the context (rbl_continue); writes the final state
+        into whichever of pos, vel, force are given.  Returns (status, ev)."""
+        ev = self._ev(want_ev)
+        st = _check(self._lib.rbl_continue(self._h, _dev_ptr(pos, (3, self.n), "pos"),
+                                           _dev_ptr(vel, (3, self.n), "vel"),
+                                           _dev_ptr(force, (3, self.n), "force"),
+                                           int(nsteps), _dev_ptr(ev)))
+        return st, ev
+
+    def last_run(self):
+        """Passes the last run took, its last force-evaluation index and
+        whether ``cont`` may follow."""
+        a, r = C.c_int32(), C.c_int32()
+        e = C.c_int64()
+        _check(self._lib.rbl_last_run(self._h, C.byref(a), C.byref(e), C.byref(r)))
+        return {"attempts": a.value, "end_step": e.value, "resumable": bool(r.value)}
+
     # -- thermostat and observables ----------------------------------------
     def set_thermostat(self, gamma: float, kT=None):
         """Langevin friction ``gamma`` (0: NVE) and bath temperature ``kT``
@@ -270,6 +289,21 @@ class Context:
         _check(self._lib.rbl_export_batches(self._h, int(P), int(seed), int(step), rows_arr.shape[0],
                                             _i64(rows_arr), _i32(batch), _i32(count)))
         return batch, count
+
+    def export_drawn_batches(self, rows):
+        """The batches stored on the device (rbl_export_drawn_batches):
+        returns (batch [nsteps][len(rows)][P] of partner IDs, -1 padded;
+        count [len(rows)]; first step)."""
+        rows_arr = np.ascontiguousarray(rows, dtype=np.int64)
+        ns, p = C.c_int32(), C.c_int32()
+        s0 = C.c_int64()
+        _check(self._lib.rbl_export_drawn_batches(self._h, 0, None, None, None, C.byref(ns), C.byref(p),
+                                                  C.byref(s0)))
+        batch = np.zeros((ns.value, rows_arr.shape[0], max(p.value, 1)), dtype=np.int32)
+        count = np.zeros(rows_arr.shape[0], dtype=np.int32)
+        _check(self._lib.rbl_export_drawn_batches(self._h, rows_arr.shape[0], _i64(rows_arr), _i32(batch),
+                                                  _i32(count), None, None, None))
+        return batch, count, s0.value
 
     def export_binning(self, with_counts: bool = False):
         ncell = np.zeros(3 * self.n_replicas, dtype=np.int32)

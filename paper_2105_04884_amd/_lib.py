@@ -61,7 +61,8 @@ class Config(C.Structure):
 _lib = None
 _names = [
     "rbl_config_init", "rbl_create", "rbl_destroy", "rbl_build", "rbl_forces", "rbl_full_forces",
-    "rbl_step", "rbl_row_counts", "rbl_export_lists", "rbl_export_batches", "rbl_export_binning",
+    "rbl_step", "rbl_continue", "rbl_last_run", "rbl_row_counts", "rbl_export_lists", "rbl_export_batches", "rbl_export_drawn_batches",
+    "rbl_export_binning",
     "rbl_sync", "rbl_set_profiling", "rbl_kernel_stats", "rbl_info", "rbl_tuning", "rbl_launch_modes",
     "rbl_set_thermostat", "rbl_unwrap", "rbl_msd", "rbl_rdf", "rbl_thermo",
     "rbl_last_error",
@@ -94,9 +95,12 @@ def load(path: str = LIB_PATH):
         "rbl_forces": (i32, [vp, i32, u64, u64, vp, vp, vp]),
         "rbl_full_forces": (i32, [vp, vp, vp, vp]),
         "rbl_step": (i32, [vp, vp, vp, vp, i64, d, i32, u64, i64, i32, i32, vp]),
+        "rbl_continue": (i32, [vp, vp, vp, vp, i64, vp]),
+        "rbl_last_run": (i32, [vp, p32, p64, p32]),
         "rbl_row_counts": (i32, [vp, i64, p64, p64]),
         "rbl_export_lists": (i32, [vp, i64, p64, p64, p32, p64, p32, p64, p32]),
         "rbl_export_batches": (i32, [vp, i32, u64, u64, i64, p64, p32, p32]),
+        "rbl_export_drawn_batches": (i32, [vp, i64, p64, p32, p32, p32, p32, p64]),
         "rbl_export_binning": (i32, [vp, p32, p64, p32]),
         "rbl_sync": (i32, [vp]),
         "rbl_set_profiling": (i32, [vp, i32]),

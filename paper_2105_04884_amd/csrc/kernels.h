@@ -1596,6 +1596,9 @@ __global__ __launch_bounds__(256) void k_reduce_final(const DevReplica* rep, int
 //   first: v += h F';           x += dt v
 //   mid:   v += h F'; v += h F'; x += dt v   (end of one step + start of next)
 //   last:  v += h F'
+// A mid step given `pending` takes the closing half-kick only when
+// *pending != 0: a captured list lifetime then serves both a state whose
+// velocities await that half-kick and one whose velocities are complete.
 // The skin monitor flags a particle that moved more than skin/2 since the
 // last build: at the end of a run here, at every rebuild in k_bin_count.
 struct IntArgs {
@@ -1620,6 +1623,7 @@ struct IntArgs {
     uint64_t seed;
     uint64_t step;             // force evaluation the step leads to
     const uint64_t* step_dev;  // if set, the step is *step_dev + step
+    const uint64_t* pending;   // mid steps: closing half-kick only if *pending (null: always)
 };
 
 // The three standard normal numbers of the Ornstein-Uhlenbeck step of
@@ -1662,13 +1666,14 @@ __global__ __launch_bounds__(256) void k_integrate(IntArgs a)
         fc[1] = a.rep_sum[8 * r + 1] / nr;
         fc[2] = a.rep_sum[8 * r + 2] / nr;
     }
+    const bool close = MODE == kIntMid && (a.pending == nullptr || *a.pending != 0);
     double v[3], F[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         v[d] = a.vs[d * a.n_slots + s];
         F[d] = a.f[d * a.n_slots + s] - fc[d];
         v[d] = v[d] + a.h * F[d];
-        if (MODE == kIntMid) v[d] = v[d] + a.h * F[d];
+        if (close) v[d] = v[d] + a.h * F[d];
     }
     if (MODE != kIntLast && a.langevin) {
         // A (half drift), O (exact Ornstein-Uhlenbeck step), A

@@ -86,7 +86,8 @@ struct rbl_ctx {
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     std::vector<unsigned char> gsig;  // parameters the captured blocks were made with
-    uint64_t* d_step = nullptr;       // device step counter read by captured kernels
+    uint64_t* d_step = nullptr;       // [0]: step counter read by captured kernels; [1]: pending
+                                      // half-kick flag of a captured lifetime's first step
     int R = 1;
     int64_t n = 0, n_slots = 0, n_slices = 0;
     std::vector<int64_t> id_base, rep_n, slot_base;
@@ -138,6 +139,10 @@ struct rbl_ctx {
 
     int* d_batch = nullptr;
     size_t batch_alloc = 0;
+    // what d_batch holds: batches of P partners for force evaluations
+    // draw_step0 .. draw_step0 + draw_steps - 1 (0 steps: none)
+    int draw_steps = 0, draw_P = 0;
+    int64_t draw_step0 = 0;
 
     double* d_partial = nullptr;    // [5][n_slices * 4] wavefront partial sums
     int part_per = 1;               // partial entries per slice of the last force launch
@@ -154,6 +159,24 @@ struct rbl_ctx {
     double* d_rep_sum = nullptr;
     int* d_flags = nullptr;
     int h_flags[kNumFlags];
+
+    // The last completed rbl_step / rbl_continue: the state it left in the
+    // buffers above (positions, complete velocities, F at end_step, lists
+    // built at build_step with the batches of their whole lifetime) is what
+    // rbl_continue resumes.  Calls that load other positions or draws clear
+    // `valid`.
+    struct RunState {
+        bool valid = false;
+        int P = 0;
+        uint64_t seed = 0;
+        int64_t K = 1;
+        double dt = 0.0;
+        bool full = false;
+        int64_t end_step = 0;
+        int64_t build_step = 0;
+        int attempts = 0;  // md_run passes the last call took (more than 1 after a capacity regrow)
+    } run;
+    double* d_ckpt = nullptr;  // [6][n] caller-order positions and velocities at a continued run's start
 
     bool profiling = false;
     // profiling: events the next launch_k hands to the dispatch itself
@@ -893,7 +916,8 @@ rbl_status emit_ev(rbl_ctx* c, double* ev)
 // noise keyed by the force evaluation `step` the step leads to, or
 // *step_dev + step).
 rbl_status integrate(rbl_ctx* c, int mode, double dt, bool momentum_fix, uint64_t seed = 0,
-                     uint64_t step = 0, const uint64_t* step_dev = nullptr)
+                     uint64_t step = 0, const uint64_t* step_dev = nullptr,
+                     const uint64_t* pending = nullptr)
 {
     IntArgs a;
     a.langevin = c->gamma > 0.0 ? 1 : 0;
@@ -903,6 +927,7 @@ rbl_status integrate(rbl_ctx* c, int mode, double dt, bool momentum_fix, uint64_
     a.seed = seed;
     a.step = step;
     a.step_dev = step_dev;
+    a.pending = pending;
     a.rep = c->d_rep;
     a.slice_rep = c->d_slice_rep;
     a.rep_sum = c->d_rep_sum;
@@ -937,9 +962,12 @@ rbl_status check_p(int P)
 // ---------------------------------------------------------------------------
 // molecular-dynamics driver and captured step blocks
 
-__global__ void k_set_u64(uint64_t* p, uint64_t v)
+__global__ void k_set_block(uint64_t* p, uint64_t step, uint64_t pending)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        p[0] = step;
+        p[1] = pending;
+    }
 }
 
 void drop_graphs(rbl_ctx* c)
@@ -997,24 +1025,30 @@ std::vector<unsigned char> block_signature(const rbl_ctx* c, const StepParams& s
     return v;
 }
 
-// Queues one list lifetime: steps s_b .. s_b+K-1 (kick/drift, rebuild at
-// s_b, force, reduction at every step).  Step-dependent values come from
-// the device counter d_step = s_b, so the same queue serves every block.
+// Queues one list lifetime as steps s_b+1 .. s_b+K, where s_b is a
+// multiple of K whose lists and batches are already built: K kick/drift +
+// force + reduction steps, the last one preceded by the rebuild at s_b+K
+// (binning, lists, and the batches of s_b+K .. s_b+2K-1).  Step-dependent
+// values come from the device counter d_step[0] = s_b, so the same queue
+// serves every lifetime; d_step[1] says whether the velocities await the
+// closing half-kick of step s_b.
 rbl_status queue_block(rbl_ctx* c, const StepParams& sp)
 {
     const int mask = sp.full ? RBL_LIST_FULL : (RBL_LIST_CORE | RBL_LIST_SHELL);
-    RBL_TRY(integrate(c, kIntMid, sp.dt, sp.fix, sp.seed, 0, c->d_step));
-    RBL_TRY(bin_particles<kSrcSorted>(c, nullptr, nullptr, true));
-    if (sp.pre) {
-        RBL_TRY(launch_fused(c, sp.P, sp.seed, 0, (int)sp.K, c->d_step));
-    } else {
-        BuildArgs a = build_args(c);
-        RBL_TRY(timed(c, kKBuild, [&] { launch_build<false>(c, a, mask); }));
-    }
-    for (int64_t r = 0; r < sp.K; ++r) {
-        if (r > 0) RBL_TRY(integrate(c, kIntMid, sp.dt, sp.fix, sp.seed, (uint64_t)r, c->d_step));
+    for (int64_t r = 1; r <= sp.K; ++r) {
+        RBL_TRY(integrate(c, kIntMid, sp.dt, sp.fix, sp.seed, (uint64_t)r, c->d_step,
+                          r == 1 ? c->d_step + 1 : nullptr));
+        if (r == sp.K) {
+            RBL_TRY(bin_particles<kSrcSorted>(c, nullptr, nullptr, true));
+            if (sp.pre) {
+                RBL_TRY(launch_fused(c, sp.P, sp.seed, (uint64_t)sp.K, (int)sp.K, c->d_step));
+            } else {
+                BuildArgs a = build_args(c);
+                RBL_TRY(timed(c, kKBuild, [&] { launch_build<false>(c, a, mask); }));
+            }
+        }
         if (sp.full) RBL_TRY(full_force_sorted(c, false));
-        else if (sp.pre) RBL_TRY(rbl_force_sorted(c, sp.P, sp.seed, 0, (int)r, false));
+        else if (sp.pre) RBL_TRY(rbl_force_sorted(c, sp.P, sp.seed, 0, r == sp.K ? 0 : (int)r, false));
         else RBL_TRY(rbl_force_sorted(c, sp.P, sp.seed, (uint64_t)r, -1, false, c->d_step));
     }
     return RBL_OK;
@@ -1042,7 +1076,9 @@ rbl_status capture_block(rbl_ctx* c, int parity, const StepParams& sp)
     return RBL_OK;
 }
 
-rbl_status run_block(rbl_ctx* c, int64_t s_b, const StepParams& sp)
+// Replays the captured lifetime s_b+1 .. s_b+K (capturing it first for the
+// current buffer parity if needed).
+rbl_status run_block(rbl_ctx* c, int64_t s_b, bool pending, const StepParams& sp)
 {
     std::vector<unsigned char> sig = block_signature(c, sp);
     if (sig != c->gsig) {
@@ -1051,7 +1087,7 @@ rbl_status run_block(rbl_ctx* c, int64_t s_b, const StepParams& sp)
     }
     const int parity = c->cur;
     if (!c->gexec[parity]) RBL_TRY(capture_block(c, parity, sp));
-    k_set_u64<<<1, 64, 0, c->ls>>>(c->d_step, (uint64_t)s_b);
+    k_set_block<<<1, 64, 0, c->ls>>>(c->d_step, (uint64_t)s_b, pending ? 1u : 0u);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipGraphLaunch(c->gexec[parity], c->ls));
     c->cur = 1 - parity;
@@ -1121,8 +1157,22 @@ struct LaunchStreamGuard {
     ~LaunchStreamGuard() { c->ls = c->stream; }
 };
 
-rbl_status md_run(rbl_ctx* c, double* pos, double* vel, double* force, int64_t nsteps, double dt, int P,
-                  uint64_t seed, int64_t step0, int64_t K, bool full, double* ev, bool& overflow)
+void set_draw(rbl_ctx* c, int64_t step0, int steps, int P)
+{
+    c->draw_step0 = step0;
+    c->draw_steps = steps;
+    c->draw_P = P;
+}
+
+// One run of Algorithm 1 (readings of the step schedule in include/rbl.h):
+// from the caller's arrays (pos_in, vel_in; a list build at step0) or, with
+// `resume`, from the state the last run left in the context.  Writes the
+// final positions, velocities and forces to whichever of pos_out, vel_out
+// and force are given.  `overflow` reports a list that outgrew its room;
+// the run's results are then void and it has to be repeated.
+rbl_status md_run(rbl_ctx* c, const double* pos_in, const double* vel_in, double* pos_out, double* vel_out,
+                  double* force, int64_t nsteps, double dt, int P, uint64_t seed, int64_t step0, int64_t K,
+                  bool full, double* ev, bool resume, bool& overflow)
 {
     overflow = false;
     StepParams sp;
@@ -1141,6 +1191,8 @@ rbl_status md_run(rbl_ctx* c, double* pos, double* vel, double* force, int64_t n
         HIP_TRY(hipStreamWaitEvent(c->gs, c->ev_in, 0));
         c->ls = c->gs;
     }
+    const int64_t resume_build = c->run.build_step;
+    c->run.valid = false;
     RBL_TRY(clear_flags(c));
     // wraps of this run's builds are counted apart and added to the
     // trajectory's image counters only when the run completes
@@ -1164,25 +1216,27 @@ rbl_status md_run(rbl_ctx* c, double* pos, double* vel, double* force, int64_t n
                                c->ls));
     }
     const int64_t last = step0 + nsteps;
-    int64_t build_step = step0;
+    int64_t build_step = resume ? resume_build : step0;
 
     auto do_build = [&](int64_t s, bool from_caller) -> rbl_status {
-        if (from_caller) RBL_TRY(bin_particles<kSrcCaller>(c, pos, vel, true));
+        if (from_caller) RBL_TRY(bin_particles<kSrcCaller>(c, pos_in, vel_in, true));
         else RBL_TRY(bin_particles<kSrcSorted>(c, nullptr, nullptr, true));
         c->built = false;
         build_step = s;
         if (sp.pre) {
-            // batches for every force evaluation until the next rebuild
-            const int64_t until = (s / K + 1) * K;
-            const int64_t cnt = std::min(until, last + 1) - s;
+            // batches for every force evaluation of the list lifetime, also
+            // those past this run's end (a continued run uses them)
+            const int64_t cnt = (s / K + 1) * K - s;
             RBL_TRY(prepare_fused(c, P, (int)K));
             RBL_TRY(launch_fused(c, P, seed, (uint64_t)s, (int)cnt, nullptr));
+            set_draw(c, s, (int)cnt, P);
             c->built_mask = RBL_LIST_CORE;
             c->shell_counts = !c->stencil;
         } else {
             RBL_TRY(prepare_lists(c, mask));
             BuildArgs a = build_args(c);
             RBL_TRY(timed(c, kKBuild, [&] { launch_build<false>(c, a, mask); }));
+            set_draw(c, 0, 0, 0);
             c->built_mask = mask;
             c->shell_counts = (mask & RBL_LIST_SHELL) != 0;
         }
@@ -1194,29 +1248,39 @@ rbl_status md_run(rbl_ctx* c, double* pos, double* vel, double* force, int64_t n
         return rbl_force_sorted(c, P, seed, (uint64_t)s, sp.pre ? (int)(s - build_step) : -1, energy);
     };
 
-    RBL_TRY(do_build(step0, true));
-    if (c->cfg.lanes == 0 || c->cfg.persistent == 0) RBL_TRY(autotune_forces(c, sp));
-    RBL_TRY(do_force(step0, ev != nullptr && nsteps == 0));
+    if (!resume) {
+        RBL_TRY(do_build(step0, true));
+        if (c->cfg.lanes == 0 || c->cfg.persistent == 0) RBL_TRY(autotune_forces(c, sp));
+        RBL_TRY(do_force(step0, ev != nullptr && nsteps == 0));
+    }
+    // pending: the velocities await the closing half-kick of the last force
+    bool pending = false;
     int64_t it = 1;
     while (it <= nsteps) {
         const int64_t s = step0 + it;
-        // whole list lifetimes strictly before the last force evaluation run
-        // as captured blocks; the rest is queued step by step
-        if (use_graph && it >= 2 && s % K == 0 && s + K - 1 < last) {
-            RBL_TRY(run_block(c, s, sp));
-            build_step = s;
+        const int64_t s_b = s - 1;
+        // A whole list lifetime s_b+1 .. s_b+K whose lists were built at s_b
+        // replays as a captured block (not the run's last lifetime when its
+        // energy is asked for: that force is queued with the energy sums).
+        if (use_graph && s_b % K == 0 && build_step == s_b && (s_b + K < last || (s_b + K == last && !ev))) {
+            RBL_TRY(run_block(c, s_b, pending, sp));
+            build_step = s_b + K;
+            if (sp.pre) set_draw(c, build_step, (int)K, P);
+            else set_draw(c, 0, 0, 0);
             c->built = true;
             c->built_mask = sp.full ? RBL_LIST_FULL : (sp.pre ? RBL_LIST_CORE : mask);
             c->shell_counts = !sp.full && !c->stencil;
+            pending = true;
             it += K;
             continue;
         }
-        RBL_TRY(integrate(c, it == 1 ? kIntFirst : kIntMid, dt, sp.fix, seed, (uint64_t)s));
+        RBL_TRY(integrate(c, pending ? kIntMid : kIntFirst, dt, sp.fix, seed, (uint64_t)s));
         if (s % K == 0) RBL_TRY(do_build(s, false));
         RBL_TRY(do_force(s, ev != nullptr && it == nsteps));
+        pending = true;
         ++it;
     }
-    if (nsteps > 0) RBL_TRY(integrate(c, kIntLast, dt, sp.fix));
+    if (pending) RBL_TRY(integrate(c, kIntLast, dt, sp.fix));
     RBL_TRY(read_flags(c));
     if (c->h_flags[kFlagStencil]) {
         // a stencil held more candidates than the fused kernel's LDS lists:
@@ -1233,8 +1297,8 @@ rbl_status md_run(rbl_ctx* c, double* pos, double* vel, double* force, int64_t n
     if (c->h_flags[kFlagNonfinite]) return fail(RBL_E_NONFINITE, "non-finite position during the run");
     if (c->h_flags[kFlagBadSlot]) return fail(RBL_E_HIP, "inconsistent cell binning");
     IoArgs io = io_args(c, sp.fix);
-    io.pos_out = pos;
-    io.vel_out = vel;
+    io.pos_out = pos_out;
+    io.vel_out = vel_out;
     io.f_out = force;
     io.img_delta = c->d_img_delta;
     io.img = c->d_img;
@@ -1245,10 +1309,32 @@ rbl_status md_run(rbl_ctx* c, double* pos, double* vel, double* force, int64_t n
         HIP_TRY(hipEventRecord(c->ev_out, c->gs));
         HIP_TRY(hipStreamWaitEvent(c->stream, c->ev_out, 0));
     }
+    c->run.valid = true;
+    c->run.P = P;
+    c->run.seed = seed;
+    c->run.K = K;
+    c->run.dt = dt;
+    c->run.full = full;
+    c->run.end_step = last;
+    c->run.build_step = build_step;
     if (c->h_flags[kFlagSkin]) {
         g_err = "a particle moved more than skin/2 within one list lifetime";
         return RBL_W_SKIN;
     }
+    return RBL_OK;
+}
+
+// After a run whose rows outgrew their room: grows the rows of the lists
+// the repeat will build (the fused kernel's LDS room grew in md_run).
+rbl_status grow_after_overflow(rbl_ctx* c, bool full)
+{
+    drop_graphs(c);
+    if (c->h_flags[kFlagStencil]) return RBL_OK;  // rows of the explicit path get counted afresh
+    const int mask = full ? RBL_LIST_FULL
+                          : (((c->cfg.predraw && c->fused_ok) || c->stencil) ? RBL_LIST_CORE
+                                                                            : (RBL_LIST_CORE | RBL_LIST_SHELL));
+    for (int q = 0; q < 3; ++q)
+        if ((mask >> q) & 1) RBL_TRY(ensure_list_storage(c, q, c->h_flags[kFlagMaxCore + q], true));
     return RBL_OK;
 }
 
@@ -1270,6 +1356,15 @@ rbl_status mean_sq(rbl_ctx* c, const double* x, const double* y, double* out)
     HIP_TRY(hipGetLastError());
     return RBL_OK;
 }
+// Parameters of the run rbl_continue resumes.
+struct RbRun {
+    int P;
+    uint64_t seed;
+    int64_t K;
+    double dt;
+    bool full;
+    int64_t step0;
+};
 }  // namespace
 
 // ===========================================================================
@@ -1350,6 +1445,7 @@ rbl_status rbl_destroy(rbl_ctx* c)
     dfree(c->d_osig);
     dfree(c->d_img);
     dfree(c->d_img_delta);
+    dfree(c->d_ckpt);
     dfree(c->d_sq_part);
     dfree(c->d_partial);
     dfree(c->d_part2);
@@ -1459,7 +1555,7 @@ rbl_status rbl_create(const rbl_config* cfg, void* hip_stream, rbl_ctx** out)
     CR(dalloc(&c->d_part2, (size_t)5 * c->red_blocks * c->R));
     CR(dalloc(&c->d_rep_sum, 8 * c->R));
     CR(dalloc(&c->d_flags, kNumFlags));
-    CR(dalloc(&c->d_step, 1));
+    CR(dalloc(&c->d_step, 2));
     if (hipStreamCreateWithFlags(&c->gs, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) != hipSuccess)
@@ -1492,6 +1588,8 @@ rbl_status rbl_build(rbl_ctx* c, const double* pos, const double* box, double r_
     if (!(r_s > 0.0) || !(r_c > r_s) || !std::isfinite(r_c))
         return fail(RBL_E_ARG, "radii must satisfy 0 < r_s < r_c");
     RBL_TRY(setup_geometry(c, box, r_s, r_c));
+    c->run.valid = false;
+    set_draw(c, 0, 0, 0);
     c->built = false;
     c->shell_counts = false;
     RBL_TRY(clear_flags(c));
@@ -1511,11 +1609,13 @@ rbl_status rbl_forces(rbl_ctx* c, int P, uint64_t seed, uint64_t step, const dou
     if ((c->built_mask & need) != need)
         return fail(RBL_E_STATE, c->stencil ? "the last build has no core list"
                                             : "the last build has no core and shell lists");
+    c->run.valid = false;
     if (c->stencil) {
         // batches from the stencil cells of the build's binning
         RBL_TRY(ensure_batch(c, 1, P));
         if (!c->d_nI) RBL_TRY(dalloc(&c->d_nI, c->n_slots));
         RBL_TRY(launch_fused(c, P, seed, step, 1, nullptr, true));
+        set_draw(c, (int64_t)step, 1, P);
     }
     IoArgs io = io_args(c, c->cfg.momentum_fix != 0);
     io.pos_in = pos;
@@ -1527,6 +1627,7 @@ rbl_status rbl_forces(rbl_ctx* c, int P, uint64_t seed, uint64_t step, const dou
         RBL_TRY(rbl_force_sorted(c, P, seed, step, -1, ev != nullptr));
     } else {
         RBL_TRY(predraw(c, P, seed, step, 1));
+        set_draw(c, (int64_t)step, 1, P);
         RBL_TRY(rbl_force_sorted(c, P, seed, step, 0, ev != nullptr));
     }
     io.f_out = force;
@@ -1540,6 +1641,7 @@ rbl_status rbl_full_forces(rbl_ctx* c, const double* pos, double* force, double*
     if (!c || !pos || !force) return fail(RBL_E_ARG, "NULL argument");
     if (!c->built) return fail(RBL_E_STATE, "rbl_full_forces needs a list build first");
     if (!(c->built_mask & RBL_LIST_FULL)) return fail(RBL_E_STATE, "the last build has no full list");
+    c->run.valid = false;
     IoArgs io = io_args(c, false);
     io.pos_in = pos;
     k_load_positions<<<grid_for(c->n_slots), kBlock, 0, c->ls>>>(io);
@@ -1565,18 +1667,51 @@ rbl_status rbl_step(rbl_ctx* c, double* pos, double* vel, double* force, int64_t
     // arrays (written only at the end) with rows sized to what it saw.
     for (int attempt = 0; attempt < 3; ++attempt) {
         bool overflow = false;
-        const rbl_status st = md_run(c, pos, vel, force, nsteps, dt, P, seed, step0, rebuild_every,
-                                     full, ev, overflow);
+        c->run.attempts = attempt + 1;
+        const rbl_status st = md_run(c, pos, vel, pos, vel, force, nsteps, dt, P, seed, step0, rebuild_every,
+                                     full, ev, false, overflow);
         if (st < 0 || !overflow) return st;
-        drop_graphs(c);
-        if (c->h_flags[kFlagStencil]) continue;  // rows of the explicit path get counted afresh
-        const int mask = full ? RBL_LIST_FULL
-                              : (((c->cfg.predraw && c->fused_ok) || c->stencil) ? RBL_LIST_CORE
-                                                                                : (RBL_LIST_CORE | RBL_LIST_SHELL));
-        for (int q = 0; q < 3; ++q)
-            if ((mask >> q) & 1) RBL_TRY(ensure_list_storage(c, q, c->h_flags[kFlagMaxCore + q], true));
+        RBL_TRY(grow_after_overflow(c, full));
     }
     return fail(RBL_E_CAPACITY, "neighbour rows kept overflowing their capacity");
+}
+
+rbl_status rbl_continue(rbl_ctx* c, double* pos, double* vel, double* force, int64_t nsteps, double* ev)
+{
+    if (!c) return fail(RBL_E_ARG, "NULL context");
+    if (nsteps < 1) return fail(RBL_E_ARG, "nsteps must be >= 1");
+    if (!c->run.valid)
+        return fail(RBL_E_STATE, "rbl_continue needs a completed rbl_step or rbl_continue on this context "
+                                 "and no call since that loaded positions or drew batches");
+    const RbRun r{c->run.P, c->run.seed, c->run.K, c->run.dt, c->run.full, c->run.end_step};
+    // the starting state in caller order, for a repeat after an overflow
+    if (!c->d_ckpt) RBL_TRY(dalloc(&c->d_ckpt, 6 * (size_t)c->n));
+    {
+        IoArgs io = io_args(c, false);
+        io.pos_out = c->d_ckpt;
+        io.vel_out = c->d_ckpt + 3 * c->n;
+        k_scatter_out<<<grid_for(c->n_slots), kBlock, 0, c->ls>>>(io);
+        HIP_TRY(hipGetLastError());
+    }
+    for (int attempt = 0; attempt < 3; ++attempt) {
+        bool overflow = false;
+        c->run.attempts = attempt + 1;
+        // the repeat rebuilds at its first step from the checkpoint
+        const rbl_status st = md_run(c, c->d_ckpt, c->d_ckpt + 3 * c->n, pos, vel, force, nsteps, r.dt, r.P,
+                                     r.seed, r.step0, r.K, r.full, ev, attempt == 0, overflow);
+        if (st < 0 || !overflow) return st;
+        RBL_TRY(grow_after_overflow(c, r.full));
+    }
+    return fail(RBL_E_CAPACITY, "neighbour rows kept overflowing their capacity");
+}
+
+rbl_status rbl_last_run(rbl_ctx* c, int32_t* attempts, int64_t* end_step, int32_t* resumable)
+{
+    if (!c) return fail(RBL_E_ARG, "NULL context");
+    if (attempts) *attempts = c->run.attempts;
+    if (end_step) *end_step = c->run.end_step;
+    if (resumable) *resumable = c->run.valid ? 1 : 0;
+    return RBL_OK;
 }
 
 rbl_status rbl_row_counts(rbl_ctx* c, int64_t nrows, const int64_t* rows, int64_t* counts)
@@ -1684,6 +1819,7 @@ rbl_status rbl_export_batches(rbl_ctx* c, int P, uint64_t seed, uint64_t step, i
     if (!c->stencil && !(c->built_mask & RBL_LIST_SHELL)) return fail(RBL_E_STATE, "no shell list built");
     for (int64_t k = 0; k < nrows; ++k)
         if (!rows || rows[k] < 0 || rows[k] >= c->n) return fail(RBL_E_ARG, "row ID out of range");
+    c->run.valid = false;
     if (c->stencil) {
         RBL_TRY(ensure_batch(c, 1, P));
         if (!c->d_nI) RBL_TRY(dalloc(&c->d_nI, c->n_slots));
@@ -1691,6 +1827,7 @@ rbl_status rbl_export_batches(rbl_ctx* c, int P, uint64_t seed, uint64_t step, i
     } else {
         RBL_TRY(predraw(c, P, seed, step, 1));
     }
+    set_draw(c, (int64_t)step, 1, P);
     std::vector<int> h_batch((size_t)P * c->n_slots), h_perm(c->n_slots), h_slot(c->n), h_len(c->n_slots);
     HIP_TRY(hipMemcpyAsync(h_batch.data(), c->d_batch, sizeof(int) * h_batch.size(), hipMemcpyDeviceToHost,
                            c->ls));
@@ -1707,6 +1844,42 @@ rbl_status rbl_export_batches(rbl_ctx* c, int P, uint64_t seed, uint64_t step, i
         count[k] = cnt;
         for (int m = 0; m < P; ++m)
             batch[k * P + m] = m < cnt ? h_perm[h_batch[(size_t)slot * P + m]] : -1;
+    }
+    return RBL_OK;
+}
+
+rbl_status rbl_export_drawn_batches(rbl_ctx* c, int64_t nrows, const int64_t* rows, int32_t* batch,
+                                    int32_t* count, int32_t* nsteps, int32_t* P_out, int64_t* step0)
+{
+    if (!c || nrows < 0 || (nrows > 0 && !rows)) return fail(RBL_E_ARG, "bad argument");
+    if (nsteps) *nsteps = c->draw_steps;
+    if (P_out) *P_out = c->draw_P;
+    if (step0) *step0 = c->draw_step0;
+    if (!batch && !count) return RBL_OK;
+    if (!c->built || c->draw_steps == 0) return fail(RBL_E_STATE, "no stored batches (last build drew none)");
+    if (!batch || !count) return fail(RBL_E_ARG, "batch and count are both required");
+    for (int64_t k = 0; k < nrows; ++k)
+        if (rows[k] < 0 || rows[k] >= c->n) return fail(RBL_E_ARG, "row ID out of range");
+    const int P = c->draw_P, K = c->draw_steps;
+    std::vector<int> h_batch((size_t)K * P * c->n_slots), h_perm(c->n_slots), h_slot(c->n), h_len(c->n_slots);
+    HIP_TRY(hipMemcpyAsync(h_batch.data(), c->d_batch, sizeof(int) * h_batch.size(), hipMemcpyDeviceToHost,
+                           c->ls));
+    HIP_TRY(hipMemcpyAsync(h_perm.data(), c->cur_perm(), sizeof(int) * c->n_slots, hipMemcpyDeviceToHost,
+                           c->ls));
+    HIP_TRY(hipMemcpyAsync(h_slot.data(), c->d_slot_of_id, sizeof(int) * c->n, hipMemcpyDeviceToHost,
+                           c->ls));
+    HIP_TRY(hipMemcpyAsync(h_len.data(), c->stencil ? c->d_nI : c->d_len[1], sizeof(int) * c->n_slots,
+                           hipMemcpyDeviceToHost, c->ls));
+    HIP_TRY(hipStreamSynchronize(c->ls));
+    for (int64_t k = 0; k < nrows; ++k) {
+        const int slot = h_slot[rows[k]];
+        const int cnt = std::min(h_len[slot], P);
+        count[k] = cnt;
+        for (int r = 0; r < K; ++r)
+            for (int m = 0; m < P; ++m) {
+                const int e = h_batch[((size_t)r * c->n_slots + slot) * P + m];
+                batch[((size_t)r * nrows + k) * P + m] = m < cnt ? h_perm[e] : -1;
+            }
     }
     return RBL_OK;
 }
@@ -1837,6 +2010,7 @@ rbl_status rbl_rdf(rbl_ctx* c, const double* pos, double r_max, int nbins, uint6
     if (!c->built) return fail(RBL_E_STATE, "rbl_rdf needs a list build first");
     if (!(r_max > 0.0) || !(r_max <= c->r_c)) return fail(RBL_E_ARG, "r_max must be in (0, r_c]");
     if (nbins < 1 || nbins > (1 << 20)) return fail(RBL_E_ARG, "nbins must be in 1 .. 2^20");
+    c->run.valid = false;
     IoArgs io = io_args(c, false);
     io.pos_in = pos;
     k_load_positions<<<grid_for(c->n_slots), kBlock, 0, c->ls>>>(io);

@@ -30,6 +30,26 @@ def rel_l2(a, b):
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b))) / (nb if nb > 0 else 1.0)
 
 
+def max_row_err(a, b):
+    """max_i |a_i - b_i| / rms_i |b_i| over the particles (columns) of two
+    [3][n] force arrays: one bad row shows here even when it hides in the
+    relative L2 error of all rows."""
+    a, b = np.asarray(a), np.asarray(b)
+    d = np.sqrt(((a - b) ** 2).sum(axis=0))
+    rms = float(np.sqrt((b ** 2).sum(axis=0).mean()))
+    return float(d.max()) / (rms if rms > 0 else 1.0) if d.size else 0.0
+
+
+def assert_forces_close(got, ref, tol, what=""):
+    """Relative L2 error below tol over all rows, and no single row off by
+    more than 10 tol relative to the rms force."""
+    e = rel_l2(got, ref)
+    m = max_row_err(got, ref)
+    assert e < tol, f"{what} relative L2 {e:.3e} >= {tol:.1e}"
+    assert m < 10 * tol, f"{what} worst row {m:.3e} (relative to the rms force) >= {10 * tol:.1e}"
+    return e, m
+
+
 def assert_lists_equal(gpu, orc, kinds=("core", "shell", "full")):
     for kind in kinds:
         go, gi = gpu[kind + "_off"], gpu[kind + "_idx"]

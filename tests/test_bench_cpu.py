@@ -92,3 +92,38 @@ def test_msd_slope_of_a_line():
     # a ballistic start is left out of the fit window
     m = np.where(t < 1.0, t * t, 2.0 * t - 1.0)
     assert bench.msd_slope(t, m) == pytest.approx(2.0, rel=1e-12)
+
+
+def test_driver_command_plans_whole_lifetimes():
+    """The driver's command line (any step counts) is accepted; the counts
+    become whole 10-step list lifetimes, the warm-up at least one."""
+    assert bench.plan(bench.parse(["--gpus", "1", "--steps", "20", "--warmup", "5"])) == (10, 20)
+    assert bench.plan(bench.parse(["--steps", "25", "--warmup", "0"])) == (10, 30)
+    assert bench.plan(bench.parse(["--steps", "1", "--warmup", "11"])) == (20, 10)
+    assert bench.plan(bench.parse([])) == (100, 1000)
+
+
+@pytest.mark.parametrize("argv", [["--steps", "0"], ["--warmup", "-1"], ["--repeats", "0"]])
+def test_unusable_step_counts_are_refused(argv):
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), *argv],
+                       capture_output=True, text=True, timeout=60)
+    assert r.returncode == 2
+    assert ">=" in r.stderr
+
+
+def test_cpu_oracle_leg_on_a_small_sample():
+    """The CPU baseline leg as the bench runs it (before any GPU work): one
+    core on a row sample, then a process pool over every row; both report
+    a positive rate and the core count they used."""
+    from paper_2105_04884_amd import inputs
+    st = inputs.million_fluid(seed=1)
+    orig = bench.N
+    try:
+        # rows of the first 20k IDs only keep the pool run short
+        bench.N = 20_000
+        res = bench.cpu_oracle(st, 500, 2)
+    finally:
+        bench.N = orig
+    assert res["cores"] == 1 and res["value"] > 0
+    assert res["all_cores"]["cores"] == 2 and res["all_cores"]["value"] > 0
+    assert bench.usable_cores() >= 1

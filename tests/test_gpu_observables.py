@@ -14,7 +14,7 @@ import oracle
 from paper_2105_04884_amd import Context, RblError, inputs
 from paper_2105_04884_amd import _lib
 
-from gpu_util import RC, RS, SKIN, dev, host, rel_l2, torch_cuda
+from gpu_util import RC, RS, SKIN, assert_forces_close, dev, host, rel_l2, torch_cuda
 
 pytestmark = pytest.mark.gpu
 
@@ -43,7 +43,7 @@ def test_langevin_trajectory_matches_oracle(use_full):
     x, v, f = runs[0]
     assert rel_l2(x, xo) < 1e-11
     assert rel_l2(v, vo) < 1e-8
-    assert rel_l2(f, fo) < 1e-7
+    assert_forces_close(f, fo, 1e-7)
     # the thermostat acted: NVE from the same start ends elsewhere
     xn, _, _, _ = oracle.md_run(st.pos, st.vel, st.box, RS, RC, SKIN, 0.005, 100, p=10, seed=3,
                                 K=10, use_full=use_full)

@@ -11,8 +11,8 @@ import oracle
 from paper_2105_04884_amd import Context, RblError, inputs
 from paper_2105_04884_amd import _lib
 
-from gpu_util import (FP64_TOL, MIXED_TOL, RC, RS, SKIN, assert_lists_equal, dev, host,
-                      oracle_rbl_total, rel_l2, torch_cuda)
+from gpu_util import (FP64_TOL, MIXED_TOL, RC, RS, SKIN, assert_forces_close, assert_lists_equal, dev,
+                      host, oracle_rbl_total, rel_l2, torch_cuda)
 
 pytestmark = pytest.mark.gpu
 
@@ -94,6 +94,78 @@ def test_batches_match_oracle(P):
                 assert np.all(batch[i, count[i]:] == -1)
 
 
+def _draw_rows(pos, box, source, rows, rc=RC):
+    """Oracle draw population per row (positions k of a batch index it):
+    the shell row, or the stencil row of the paper's form."""
+    sysm = oracle.System(pos, box, RS, rc, SKIN)
+    if source == "shell":
+        L = sysm.lists(rows=rows, kinds=("shell",))
+        return [L.row("shell", k) for k in range(len(rows))]
+    off, idx = sysm.stencil_rows(rows)
+    return [idx[off[k]:off[k + 1]] for k in range(len(rows))]
+
+
+def _check_drawn(batch, count, step0, popl, rows, P, seed, replica=0, pid=None):
+    """Every stored batch against the oracle's Floyd draw, entry by entry."""
+    nsteps = batch.shape[0]
+    for k, i in enumerate(rows):
+        pop = popl[k]
+        assert count[k] == min(len(pop), P), (i, count[k], len(pop))
+        for r in range(nsteps):
+            kpos = oracle.batch_positions(seed, int(i if pid is None else pid[k]), step0 + r, replica,
+                                          P, len(pop))
+            assert np.array_equal(batch[r, k, :count[k]], pop[kpos]), (i, step0 + r)
+            assert np.all(batch[r, k, count[k]:] == -1)
+
+
+@pytest.mark.parametrize("source", ["shell", "stencil"])
+@pytest.mark.parametrize("P", [1, 10, 33, 128])
+def test_fused_build_batches_match_oracle(source, P):
+    """The batches the fused build + draw kernel stores for a list lifetime
+    (the ones the MD loop's force kernel reads), exported and compared bit
+    for bit with the oracle's Floyd draw on the oracle's own rows: for every
+    particle and every step of the lifetime.  Entry builds at a lifetime
+    start, inside a lifetime and past 2^32 steps, then a build inside a
+    captured lifetime (graph replay, device step counter)."""
+    torch = torch_cuda()
+    st = inputs.small_fluid(seed=1)
+    n = st.n
+    rows = np.arange(n)
+    x0 = dev(st.pos)
+    with Context(n, lanes=1, shell_source=source) as ctx:
+        ctx.build(x0, st.box, RS, RC)
+        for seed, step0 in ((1, 0), (7, 13), (2**40 + 3, 2**32 + 5)):
+            x, v = dev(st.pos), dev(st.vel)
+            ctx.step(x, v, nsteps=0, dt=0.005, P=P, seed=seed, step0=step0, rebuild_every=10)
+            batch, count, s0 = ctx.export_drawn_batches(rows)
+            assert s0 == step0 and batch.shape == (10 - step0 % 10, n, P)
+            _check_drawn(batch, count, s0, _draw_rows(st.pos, st.box, source, rows), rows, P, seed)
+        # 20 steps: the second lifetime's build runs inside the captured graph
+        x, v = dev(st.pos), dev(st.vel)
+        ctx.step(x, v, nsteps=20, dt=0.005, P=P, seed=3, step0=0, rebuild_every=10)
+        batch, count, s0 = ctx.export_drawn_batches(rows)
+        assert s0 == 20 and batch.shape[0] == 10
+        # the final positions are those of the build at step 20
+        _check_drawn(batch, count, s0, _draw_rows(host(x), st.box, source, rows), rows, P, 3)
+
+
+def test_fused_build_batches_million_sampled():
+    """The stored batches of the N = 1M fluid (mixed precision, autotuned
+    lanes: the bench's configuration) on 300 sampled rows, all 10 steps of
+    the lifetime, for both draw populations."""
+    torch = torch_cuda()
+    st = inputs.million_fluid(seed=1)
+    rows = np.random.default_rng(5).choice(st.n, size=300, replace=False)
+    for source in ("shell", "stencil"):
+        x, v = dev(st.pos), dev(st.vel)
+        with Context(st.n, precision="mixed", shell_source=source) as ctx:
+            ctx.build(x, st.box, RS, RC)
+            ctx.step(x, v, nsteps=20, dt=0.005, P=10, seed=1, step0=0, rebuild_every=10)
+            batch, count, s0 = ctx.export_drawn_batches(rows)
+        assert s0 == 20 and batch.shape == (10, 300, 10)
+        _check_drawn(batch, count, s0, _draw_rows(host(x), st.box, source, rows), rows, 10, 1)
+
+
 def _displaced(pos, amount, seed):
     rng = np.random.default_rng(seed)
     return pos + rng.uniform(-amount, amount, size=pos.shape)
@@ -113,7 +185,7 @@ def test_rbl_forces_match_oracle(precision, tol, P):
         for k, p in enumerate((pos, _displaced(pos, 0.1, 3))):
             f, ev = ctx.forces(P, seed=11 + k, step=3 * k, pos=dev(p), want_ev=True)
             fo, eo, wo = oracle_rbl_total(p, box, L, P, 11 + k, 3 * k)
-            assert rel_l2(host(f), fo) < tol
+            assert_forces_close(host(f), fo, tol)
             U, W = host(ev)
             assert abs(U - eo) <= tol * max(1.0, abs(eo)) * 10
             assert abs(W - wo) <= tol * max(1.0, abs(wo)) * 10
@@ -131,7 +203,7 @@ def test_full_forces_match_oracle(precision, tol):
             p = _displaced(pos, 0.05, 1)
             f, ev = ctx.full_forces(dev(p), want_ev=True)
             fo, eo, wo = oracle.full_forces(p, box, RC, L)
-            assert rel_l2(host(f), fo) < tol, case
+            assert_forces_close(host(f), fo, tol, case)
             U, W = host(ev)
             assert abs(U - eo.sum()) <= 10 * tol * abs(eo.sum())
             assert abs(W - wo.sum()) <= 10 * tol * abs(wo.sum())
@@ -152,7 +224,7 @@ def test_rbl_forces_edge_cases():
                 if np.linalg.norm(fo) == 0:
                     assert np.abs(host(f)).max() == 0.0
                 else:
-                    assert rel_l2(host(f), fo) < FP64_TOL, (case, P)
+                    assert_forces_close(host(f), fo, FP64_TOL, (case, P))
 
 
 def test_trajectory_matches_oracle():
@@ -177,7 +249,7 @@ def test_trajectory_matches_oracle():
                                     seed=1, K=10, want_ev=True)
     assert rel_l2(host(x), xo) < 1e-12
     assert rel_l2(host(v), vo) < 1e-9
-    assert rel_l2(host(f), fo) < 1e-9
+    assert_forces_close(host(f), fo, 1e-9)
     assert abs(host(ev)[0] - evo[-1, 0]) < 1e-9 * abs(evo[-1, 0])
     xg = host(x)
     ref = oracle.System(xg, st.box, RS, RC, SKIN).lists(kinds=("core", "shell"))
@@ -213,6 +285,87 @@ def test_step_restart_and_determinism(predraw):
             ctx.step(x2, v2, nsteps=40, dt=0.005, P=10, seed=9, step0=0, rebuild_every=10)
         assert np.array_equal(runs[0][0], host(x2)), kw
         assert np.array_equal(runs[0][1], host(v2)), kw
+
+
+@pytest.mark.parametrize("use_full", [False, True])
+@pytest.mark.parametrize("graphs", [True, False])
+@pytest.mark.parametrize("chunks", [(20, 20), (15, 25), (7, 13, 1, 19)])
+def test_continue_equals_one_run(chunks, graphs, use_full):
+    """rbl_step over the first chunk followed by rbl_continue over the rest
+    (state kept on the GPU, outputs written only by the last call) equals
+    one rbl_step over all 40 steps bit for bit, whether the chunks end on a
+    list rebuild or inside a list lifetime."""
+    torch = torch_cuda()
+    st = inputs.small_fluid(seed=5)
+    lists = ("full",) if use_full else ("core", "shell")
+    x, v = dev(st.pos), dev(st.vel)
+    f = torch.zeros_like(x)
+    with Context(st.n, lanes=1, graphs=graphs, lists=lists) as ctx:
+        ctx.build(x, st.box, RS, RC)
+        ctx.step(x, v, nsteps=40, dt=0.005, P=10, seed=4, step0=0, rebuild_every=10,
+                 use_full=use_full, force=f)
+    ref = (host(x), host(v), host(f))
+    x, v = dev(st.pos), dev(st.vel)
+    f = torch.zeros_like(x)
+    with Context(st.n, lanes=1, graphs=graphs, lists=lists) as ctx:
+        ctx.build(x, st.box, RS, RC)
+        ctx.step(x, v, nsteps=chunks[0], dt=0.005, P=10, seed=4, step0=0, rebuild_every=10,
+                 use_full=use_full)
+        for k, c in enumerate(chunks[1:]):
+            lastc = k == len(chunks) - 2
+            ctx.cont(c, pos=x if lastc else None, vel=v if lastc else None, force=f if lastc else None)
+        info = ctx.last_run()
+    assert info == {"attempts": 1, "end_step": 40, "resumable": True}
+    for a, b in zip((host(x), host(v), host(f)), ref):
+        assert np.array_equal(a, b)
+
+
+def test_continue_needs_an_unchanged_run():
+    torch_cuda()
+    st = inputs.small_fluid(seed=5)
+    x, v = dev(st.pos), dev(st.vel)
+    with Context(st.n) as ctx:
+        ctx.build(x, st.box, RS, RC)
+        with pytest.raises(RblError, match="RBL_E_STATE"):
+            ctx.cont(10)
+        ctx.step(x, v, nsteps=10, dt=0.005, P=10, seed=1)
+        with pytest.raises(RblError, match="RBL_E_ARG"):
+            ctx.cont(0)
+        ctx.cont(10)
+        assert ctx.last_run()["end_step"] == 20
+        ctx.rdf(x, 2.0, 10)                       # loads the caller's positions
+        assert not ctx.last_run()["resumable"]
+        with pytest.raises(RblError, match="RBL_E_STATE"):
+            ctx.cont(10)
+        ctx.step(x, v, nsteps=10, dt=0.005, P=10, seed=1, step0=20)
+        ctx.build(x, st.box, RS, RC)              # a new build
+        with pytest.raises(RblError, match="RBL_E_STATE"):
+            ctx.cont(10)
+
+
+def test_continue_overflow_repeats_from_its_start():
+    """Rows sized tightly at the lattice start overflow once the fluid
+    melts during a continued run; the call is repeated from its starting
+    state (a list rebuild there, at a lifetime boundary) and matches a run
+    that never overflowed, bit for bit; the repeat is counted.  (With
+    capacity factor 1 the fused build's shell room is 192 entries for a
+    longest first shell row of 178; the oracle's run of this fluid first
+    exceeds it at step 170, with 196.)"""
+    torch_cuda()
+    st = inputs.small_fluid(seed=4)
+    runs, attempts = [], []
+    for factor in (1.0, 3.0):
+        x, v = dev(st.pos), dev(st.vel)
+        with Context(st.n, capacity_factor=factor, lists=("core",), lanes=4) as ctx:
+            ctx.build(x, st.box, RS, RC)
+            # the first force only: the rows grow while the continued run melts the lattice
+            ctx.step(x, v, nsteps=0, dt=0.005, P=10, seed=2, rebuild_every=10)
+            ctx.cont(200, pos=x, vel=v)
+            attempts.append(ctx.last_run()["attempts"])
+        runs.append((host(x), host(v)))
+    assert attempts == [2, 1], attempts
+    assert np.array_equal(runs[0][0], runs[1][0])
+    assert np.array_equal(runs[0][1], runs[1][1])
 
 
 @pytest.mark.parametrize("n,rc,steps", [
@@ -301,9 +454,9 @@ def test_ensemble_matches_oracle_per_replica():
             assert np.array_equal(go - go[0], getattr(L, kind + "_off"))
             assert np.array_equal(gi, getattr(L, kind + "_idx"))
         fo, _, _ = oracle_rbl_total(s.pos, s.box, L, 10, 3, 7, replica=r)
-        assert rel_l2(f[:, sl], fo) < FP64_TOL
+        assert_forces_close(f[:, sl], fo, FP64_TOL)
         fu, _, _ = oracle.full_forces(s.pos, s.box, RC, L)
-        assert rel_l2(ff[:, sl], fu) < FP64_TOL
+        assert_forces_close(ff[:, sl], fu, FP64_TOL)
 
 
 def test_million_particle_sampled_parity():
@@ -331,10 +484,10 @@ def test_million_particle_sampled_parity():
                     assert np.array_equal(batch[k, :count[k]], sh[kp])
             f = host(ctx.forces(10, seed=1, step=0, pos=x))[:, rows]
             fo, _, _ = oracle.rbl_forces(st.pos, st.box, RS, RC, L, 10, 1, 0)
-            assert rel_l2(f, fo) < tol
+            assert_forces_close(f, fo, tol)
             ff = host(ctx.full_forces(x))[:, rows]
             ffo, _, _ = oracle.full_forces(st.pos, st.box, RC, L)
-            assert rel_l2(ff, ffo) < tol
+            assert_forces_close(ff, ffo, tol)
 
 
 def test_large_fluid_sampled_parity():
@@ -361,7 +514,7 @@ def test_large_fluid_sampled_parity():
             assert np.array_equal(batch[k, :count[k]], sh[kp])
         f = host(ctx.forces(10, seed=1, step=0, pos=x))[:, rows]
         fo, _, _ = oracle.rbl_forces(st.pos, st.box, rs, rc, L, 10, 1, 0)
-        assert rel_l2(f, fo) < FP64_TOL
+        assert_forces_close(f, fo, FP64_TOL)
         v = dev(st.vel)
         status, _ = ctx.step(x, v, nsteps=10, dt=0.005, P=10, seed=1, rebuild_every=10)
         assert status in (0, _lib.RBL_W_SKIN)
@@ -417,10 +570,10 @@ def test_charged_slab_forces_match_oracle():
             if precision == "fp64":
                 assert_lists_equal(ctx.export_lists(), L)
             f, ev = ctx.forces(P, seed=4, step=3, pos=x, want_ev=True)
-            assert rel_l2(host(f), fo) < tol
+            assert_forces_close(host(f), fo, tol)
             assert abs(host(ev)[0] - eo.sum()) < 10 * tol * abs(eo.sum())
             ff, evf = ctx.full_forces(x, want_ev=True)
-            assert rel_l2(host(ff), ffo) < tol
+            assert_forces_close(host(ff), ffo, tol)
             assert abs(host(evf)[0] - efo.sum()) < 10 * tol * abs(efo.sum())
 
 
@@ -466,7 +619,7 @@ def test_slab_two_million_sampled_parity():
             assert np.array_equal(batch[k, :count[k]], sh[kp])
         f = host(ctx.forces(P, seed=1, step=0, pos=x))[:, rows]
         fo, _, _ = oracle.rbl_forces(st.pos, st.box, RS, rc, L, P, 1, 0, charges=st.charges, alpha=ALPHA)
-        assert rel_l2(f, fo) < FP64_TOL
+        assert_forces_close(f, fo, FP64_TOL)
         v = dev(st.vel)
         status, _ = ctx.step(x, v, nsteps=10, dt=0.004, P=P, seed=1, rebuild_every=10)
         assert status in (0, _lib.RBL_W_SKIN)
@@ -600,14 +753,14 @@ def test_mixed_classification_at_thresholds_matches_fp64(lanes):
         for p in (pos, pos + rng.uniform(-0.05, 0.05, size=pos.shape)):
             ff = host(ctx.full_forces(dev(p)))
             fo, _, _ = oracle.full_forces(p, box, RC, Lf)
-            assert rel_l2(ff, fo) < MIXED_TOL
+            assert_forces_close(ff, fo, MIXED_TOL)
             # a pair classified on the wrong side of r_c would move its
             # particles' force by |f(r_c)| ~ 4e-3, of r_s by ~1
             err = np.linalg.norm(ff[:, planted] - fo[:, planted], axis=0)
             assert np.all(err <= 1e-5 * np.maximum(np.linalg.norm(fo[:, planted], axis=0), 1.0))
             f = host(ctx.forces(64, seed=5, step=1, pos=dev(p)))
             fr, _, _ = oracle_rbl_total(p, box, Lf, 64, 5, 1)
-            assert rel_l2(f, fr) < MIXED_TOL
+            assert_forces_close(f, fr, MIXED_TOL)
 
 
 @pytest.mark.parametrize("source", ["shell", "stencil"])
@@ -633,7 +786,79 @@ def test_million_particle_md_in_the_bench_configuration(source):
     sysm = oracle.System(xg, st.box, RS, RC, SKIN)
     L = sysm.lists(rows=rows, kinds=("core", "shell")) if source == "shell" else sysm.stencil_lists(rows=rows)
     fo, _, _ = oracle.rbl_forces(xg, st.box, RS, RC, L, 10, 1, 20)
-    assert rel_l2(host(f)[:, rows], fo) < MIXED_TOL
+    assert_forces_close(host(f)[:, rows], fo, MIXED_TOL)
+
+
+def _bench_config_md(st, rs, rc, P, charges=None, steps=20):
+    """`steps` MD steps in the benchmark's configuration (mixed precision,
+    fused build + draw, autotuned lanes and launch mode, captured list
+    lifetimes, no mean subtraction so the force is the raw estimate); returns
+    the final positions and the force of the last evaluation (step `steps`,
+    right after a rebuild)."""
+    torch = torch_cuda()
+    x, v = dev(st.pos), dev(st.vel)
+    f = torch.zeros_like(x)
+    kw = {}
+    if charges is not None:
+        kw = {"pair": "lj_erfc", "alpha": ALPHA, "charges": dev(charges)}
+    with Context(st.n, precision="mixed", momentum_fix=False, **kw) as ctx:
+        ctx.build(x, st.box, rs, rc)
+        status, _ = ctx.step(x, v, nsteps=steps, dt=0.005, P=P, seed=1, rebuild_every=10, force=f)
+        assert ctx.last_run()["attempts"] >= 1
+    assert status in (0, _lib.RBL_W_SKIN)
+    return host(x), host(f)
+
+
+def test_large_fluid_mixed_in_the_bench_configuration():
+    """N = 2^24 (r_s = 1.3, r_c = 4.0, P = 10) as the benchmark runs it:
+    sampled raw forces after 20 steps against the FP64 oracle at the GPU's
+    final positions, within the mixed tolerance (error reported)."""
+    st = inputs.large_fluid(seed=1)
+    xg, f = _bench_config_md(st, 1.3, 4.0, 10)
+    rows = np.random.default_rng(2).choice(st.n, size=300, replace=False)
+    L = oracle.System(xg, st.box, 1.3, 4.0, SKIN).lists(rows=rows, kinds=("core", "shell"))
+    fo, _, _ = oracle.rbl_forces(xg, st.box, 1.3, 4.0, L, 10, 1, 20)
+    e, m = assert_forces_close(f[:, rows], fo, MIXED_TOL)
+    print(f"2^24 mixed: relative L2 {e:.2e}, worst row {m:.2e}")
+
+
+def test_slab_mixed_in_the_bench_configuration():
+    """The N = 2M charged slab (LJ + erfc, r_c = 5.0, P = 20) as the
+    benchmark runs it, sampled raw forces after 20 steps against the FP64
+    oracle."""
+    st = inputs.slab(seed=1)
+    xg, f = _bench_config_md(st, RS, 5.0, 20, charges=st.charges)
+    rows = np.random.default_rng(4).choice(st.n, size=300, replace=False)
+    L = oracle.System(xg, st.box, RS, 5.0, SKIN).lists(rows=rows, kinds=("core", "shell"))
+    fo, _, _ = oracle.rbl_forces(xg, st.box, RS, 5.0, L, 20, 1, 20, charges=st.charges, alpha=ALPHA)
+    e, m = assert_forces_close(f[:, rows], fo, MIXED_TOL)
+    print(f"slab mixed: relative L2 {e:.2e}, worst row {m:.2e}")
+
+
+def test_ensemble_512_mixed_in_the_bench_configuration():
+    """The 512-replica ensemble advanced together as the benchmark runs it
+    (mixed, autotuned lanes and launch mode on the uneven 64-slot replica
+    slices): on eight sampled replicas every raw force after 20 steps
+    against the FP64 oracle of that replica alone (replica index in the
+    Philox counter)."""
+    torch = torch_cuda()
+    ens = inputs.ensemble(512, seed=1)
+    pos, vel, boxes, off = ens.concat()
+    n = int(off[-1])
+    x, v = dev(pos), dev(vel)
+    f = torch.zeros_like(x)
+    with Context(n, precision="mixed", momentum_fix=False, replica_offsets=off) as ctx:
+        ctx.build(x, boxes, RS, RC)
+        status, _ = ctx.step(x, v, nsteps=20, dt=0.005, P=10, seed=5, rebuild_every=10, force=f)
+    assert status in (0, _lib.RBL_W_SKIN)
+    xg, fg = host(x), host(f)
+    for r in np.linspace(0, 511, 8).astype(int):
+        sl = slice(off[r], off[r + 1])
+        xr = np.ascontiguousarray(xg[:, sl])
+        L = oracle.System(xr, boxes[r], RS, RC, SKIN).lists(kinds=("core", "shell"))
+        fo, _, _ = oracle.rbl_forces(xr, boxes[r], RS, RC, L, 10, 5, 20, replica=int(r))
+        e, m = assert_forces_close(fg[:, sl], fo, MIXED_TOL, f"replica {r}")
+        print(f"ensemble mixed replica {r}: relative L2 {e:.2e}, worst row {m:.2e}")
 
 
 @pytest.mark.parametrize("P", [1, 33, 128])
