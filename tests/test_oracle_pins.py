@@ -247,13 +247,125 @@ def test_full_force_is_minus_energy_gradient():
             assert abs(g - f[a, i]) < 2e-5 * max(1.0, abs(f[a, i])), (i, a, g, f[a, i])
 
 
-def test_full_force_newton_third_law_and_virial():
+def test_full_force_newton_third_law():
     st = inputs.small_fluid(seed=4)
     L = oracle.System(st.pos, st.box, RS, RC, SKIN).lists()
     f, e, w = oracle.full_forces(st.pos, st.box, RC, L)
     assert np.all(np.abs(f.sum(axis=1)) < 1e-9 * np.abs(f).sum(axis=1))
-    # virial as sum over unordered pairs of r.f equals 0.5 sum_i sum_j
     assert np.isfinite(w).all() and np.isfinite(e).all()
+
+
+def _scaled_energy(pos, box, rc, lists, lam, **kw):
+    """Total (shifted) energy with every coordinate and the box scaled by
+    lam: the volume derivative of the configuration energy."""
+    _, e, _ = oracle.full_forces(pos * lam, box * lam, rc, lists, **kw)
+    return float(e.sum())
+
+
+@pytest.mark.parametrize("charged", [False, True])
+def test_virial_is_the_volume_derivative_of_the_energy(charged):
+    """The virial W = sum over pairs of r_ij . f_ij, behind the pressure
+    P = rho T + W/(3V) of Sec. III, equals -dU/d(lambda) at lambda = 1 when
+    all coordinates and the box are scaled by lambda (that is -3V dU/dV),
+    by central differences of the total energy.  The shifted energy is
+    continuous at the cut-off, so pairs near it do not spoil the
+    difference.  A wrong factor (r instead of r^2, a missing half, the
+    wrong sign) fails this."""
+    box = np.array([10.0, 10.0, 10.0])
+    if charged:
+        st, q = _charged_gas(160, box, 31)
+        kw = {"charges": q, "alpha": 0.3}
+        rc = 4.5
+    else:
+        st = inputs.random_gas(160, box, seed=30, min_dist=0.95)
+        kw = {}
+        rc = RC
+    L = oracle.System(st.pos, box, RS, rc, SKIN).lists()
+    _, _, w = oracle.full_forces(st.pos, box, rc, L, **kw)
+    W = float(w.sum())
+    h = 1e-6
+    dudl = (_scaled_energy(st.pos, box, rc, L, 1 + h, **kw)
+            - _scaled_energy(st.pos, box, rc, L, 1 - h, **kw)) / (2 * h)
+    assert abs(W - (-dudl)) < 1e-6 * max(1.0, abs(W)), (W, -dudl)
+    # and per pair, by brute force over all pairs: sum of r^2 fmag(r)
+    d = st.pos[:, :, None] - st.pos[:, None, :]
+    d -= box[:, None, None] * np.rint(d / box[:, None, None])
+    r2 = (d ** 2).sum(axis=0)
+    iu = np.triu_indices(st.n, 1)
+    sel = r2[iu] < rc * rc
+    wsum = 0.0
+    for a, b, rr in zip(iu[0][sel], iu[1][sel], r2[iu][sel]):
+        fm, _ = oracle.lj(rr)
+        if charged:
+            fe, _ = oracle.erfc_pair(rr, q[a] * q[b], 0.3)
+            fm += fe
+        wsum += fm * rr
+    assert abs(W - wsum) < 1e-10 * abs(wsum)
+
+
+def test_energy_shift_closed_forms():
+    """Truncated-shifted LJ (Sec. II): a dimer's energy is U(r) - U(r_c),
+    with hand-worked values (tests/golden/lj_shifted_dimers.txt)."""
+    rows = np.loadtxt(os.path.join(GOLDEN, "lj_shifted_dimers.txt"))
+    box = np.array([12.0, 12.0, 12.0])
+    for r2, rc, u_want in rows:
+        pos = np.array([[1.0, 1.0 + math.sqrt(r2)], [2.0, 2.0], [3.0, 3.0]])
+        L = oracle.System(pos, box, 0.5, rc, SKIN).lists()
+        _, e, _ = oracle.full_forces(pos, box, rc, L)
+        assert abs(e.sum() - u_want) < 1e-14, (r2, rc, e.sum(), u_want)
+        _, e0, _ = oracle.full_forces(pos, box, rc, L, shift=False)
+        assert abs(e0.sum() - (u_want + _lj_u_hand(rc * rc))) < 1e-14
+
+
+def _lj_u_hand(r2):
+    """4 (r^-12 - r^-6), written out independently of the oracle."""
+    s6 = 1.0 / r2 ** 3
+    return 4.0 * (s6 * s6 - s6)
+
+
+def test_shifted_energy_vanishes_at_the_cutoff():
+    """The shifted pair energy goes continuously to zero as r -> r_c from
+    below (a dimer at r_c (1 - eps) has energy of order U'(r_c) r_c eps), and
+    a pair at r_c or beyond contributes nothing."""
+    box = np.array([12.0, 12.0, 12.0])
+    for rc in (2.5, RC, 5.0):
+        dudr = -24.0 * (2.0 * rc ** -13 - rc ** -7)
+        for eps in (1e-3, 1e-6, 1e-9):
+            r = rc * (1 - eps)
+            pos = np.array([[1.0, 1.0 + r], [2.0, 2.0], [3.0, 3.0]])
+            L = oracle.System(pos, box, 0.5, rc, SKIN).lists()
+            _, e, _ = oracle.full_forces(pos, box, rc, L)
+            # first order in eps; the second-order term is relatively O(eps)
+            want = -dudr * rc * eps
+            assert abs(e.sum() - want) < 10 * eps * abs(want) + 1e-16, (rc, eps, e.sum(), want)
+        pos = np.array([[1.0, 1.0 + rc * (1 + 1e-12)], [2.0, 2.0], [3.0, 3.0]])
+        L = oracle.System(pos, box, 0.5, rc, SKIN).lists()
+        f, e, w = oracle.full_forces(pos, box, rc, L)
+        assert e.sum() == 0.0 and np.all(f == 0.0) and w.sum() == 0.0
+
+
+def test_shift_adds_n_pairs_times_the_cutoff_energy():
+    """U_shifted - U_unshifted = -(number of pairs within r_c) U(r_c), the
+    pair count by brute force over all pairs; with charges the erfc part is
+    shifted by sum over those pairs of q_i q_j erfc(alpha r_c)/r_c
+    (math.erfc, not the oracle's)."""
+    box = np.array([9.0, 9.0, 9.0])
+    st, q = _charged_gas(140, box, 33)
+    for charged in (False, True):
+        kw = {"charges": q, "alpha": 0.3} if charged else {}
+        L = oracle.System(st.pos, box, RS, RC, SKIN).lists()
+        _, e1, _ = oracle.full_forces(st.pos, box, RC, L, **kw)
+        _, e0, _ = oracle.full_forces(st.pos, box, RC, L, shift=False, **kw)
+        d = st.pos[:, :, None] - st.pos[:, None, :]
+        d -= box[:, None, None] * np.rint(d / box[:, None, None])
+        r2 = (d ** 2).sum(axis=0)
+        iu = np.triu_indices(st.n, 1)
+        sel = r2[iu] < RC * RC
+        want = -sel.sum() * _lj_u_hand(RC * RC)
+        if charged:
+            qq = (q[:, None] * q[None, :])[iu][sel].sum()
+            want -= qq * math.erfc(0.3 * RC) / RC
+        assert abs((e1.sum() - e0.sum()) - want) < 1e-10 * max(1.0, abs(want)), charged
 
 
 def test_perfect_fcc_has_zero_force():
@@ -317,12 +429,12 @@ def _shell_terms(st, L, k):
 def test_rbl_unbiased_with_exact_srswor_variance(p):
     """Appendix A: E[F~_is] = F_is, and, sampling without replacement,
     Var[F~_is] = n (n - p) S^2 / p with S^2 the finite-population variance
-    of the candidate terms.  Checked over 3000 seeds on 30 particles."""
+    of the candidate terms.  Checked over 10^4 seeds on 30 particles."""
     st = inputs.small_fluid(seed=8)
     sysm = oracle.System(st.pos, st.box, RS, RC, SKIN)
     rows = np.arange(0, 1000, 33)
     L = sysm.lists(rows=rows)
-    seeds = 3000
+    seeds = 10_000
     samples = np.zeros((seeds, 3, len(rows)))
     for s in range(seeds):
         samples[s], _, _ = oracle.rbl_forces(st.pos, st.box, RS, RC, L, p, seed=1000 + s, step=0)
@@ -565,7 +677,7 @@ def test_stencil_rows_contain_the_shell_rows():
 
 def test_stencil_rbl_unbiased_with_exact_srswor_variance():
     """The paper's form of eq. (4), drawing from the stencil cells with
-    N_I/p: unbiased, and the variance over 3000 seeds equals the exact
+    N_I/p: unbiased, and the variance over 10^4 seeds equals the exact
     without-replacement variance N_I (N_I - p) S^2 / p with zero terms for
     the population members outside the shell zone (Appendix A)."""
     p = 10
@@ -573,7 +685,7 @@ def test_stencil_rbl_unbiased_with_exact_srswor_variance():
     S = oracle.System(st.pos, st.box, RS, RC, SKIN)
     rows = np.arange(0, 3000, 101)
     L = S.stencil_lists(rows=rows)
-    seeds = 3000
+    seeds = 10_000
     samples = np.zeros((seeds, 3, len(rows)))
     for s in range(seeds):
         samples[s], _, _ = oracle.rbl_forces(st.pos, st.box, RS, RC, L, p, seed=5000 + s, step=0)
