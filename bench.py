@@ -13,13 +13,26 @@ pair arithmetic, FP64 classification and accumulation; the headline
 ``value``), RBL in FP64, and the full Verlet list (direct truncation at r_c)
 in both precisions; batch sizes P = 5, 10, 20 for the mixed RBL.
 
-Timing: the step counts are taken in whole list lifetimes (10 steps).  Each
-variant runs the warm-up (--warmup rounded up to lifetimes, at least one;
-the first run also autotunes the force kernel) from the initial arrays, then
---repeats timed blocks of --steps steps (rounded up to lifetimes), each
-continuing the state held on the GPU (rbl_continue: every lifetime a replay
-of the captured graph, no list build from host arrays) between device
-synchronisations.  ``ms_per_step`` is the median block's time per step.
+Lists are rebuilt when some particle has moved more than half the skin since
+the last build (checked on the device at every step; skin 0.5 and at most 13
+steps per list for RBL, skin 0.3 and at most 10 for the full list), so every
+pair within the radii is in the lists at every step.  Variants with a fixed
+10-step lifetime and no check are timed beside them for comparison.
+
+Timing: the step counts are taken in whole blocks of 10 steps.  Each
+variant runs the warm-up (--warmup rounded up to blocks, at least one; the
+first run also autotunes the force kernel) from the initial arrays, then
+--repeats timed runs of --steps steps (rounded up to blocks, at least 200:
+rebuilds fall every ~12 steps, so shorter runs would hold a varying count),
+each continuing the state held on the GPU (rbl_continue: every block a
+replay of a captured graph, no list build from host arrays) between device
+synchronisations.  ``ms_per_step`` is the median run's time per step.  With
+the defaults the five timed runs are the 1000 steps of the N = 1e6
+workload.  RBL runs without a thermostat heat up slowly (the batch noise,
+Sec. II), so their lists are rebuilt more often as a run goes on; timing
+the configured length keeps that effect at the workload's size.  The other
+workloads time five runs that together make their configured lengths
+(2^24 fluid: 200 steps; ensemble and slab: 500).
 
 The CPU oracle baseline runs first, before the GPU is touched, on one core
 and on all host cores the process may use (at most 16).
@@ -42,6 +55,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 RS, RC, SKIN, DT, K_REBUILD = 1.5, 3.5, 0.3, 0.005, 10
+# Lists rebuilt on displacement (a rebuild at the first step some particle is
+# more than skin/2 from where the last build left it, or after the longest
+# lifetime): skin and longest lifetime of the RBL form and of the full list,
+# each the fastest of a sweep at N = 1e6 (skin 0.3 ... 0.6, lifetimes 10 ... 16).
+SKIN_RBL, LIFE_RBL = 0.5, 13
+SKIN_FULL, LIFE_FULL = 0.3, 10
 N, RHO, TEMP = 1_000_000, 0.8442, 1.0
 HBM_PEAK_GBS = 8000.0
 
@@ -53,8 +72,8 @@ def log(msg):
 def parse(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000,
-                    help="steps per timed block (rounded up to whole 10-step list lifetimes)")
+    ap.add_argument("--steps", type=int, default=200,
+                    help="steps per timed run (rounded up to whole 10-step blocks, at least 200)")
     ap.add_argument("--warmup", type=int, default=100,
                     help="warm-up steps (rounded up to whole list lifetimes, at least one)")
     ap.add_argument("--repeats", type=int, default=5,
@@ -91,6 +110,11 @@ def parse(argv=None):
                          "mode to the autotuner's usual choice there (RBL 2 lanes, full list 4, "
                          "one block per tile) instead of timing them; for profiler runs, whose "
                          "per-dispatch overhead distorts the autotuner's timings")
+    ap.add_argument("--skin", type=float, default=None,
+                    help="Verlet skin of the N = 1e6 variants (default: the workload's)")
+    ap.add_argument("--max-lifetime", type=int, default=None,
+                    help="N = 1e6 variants: longest list lifetime in steps with rebuilds on "
+                         "displacement (default: the fixed lifetime, 10)")
     ap.add_argument("--calib-copy-mb", type=int, default=1024,
                     help="size of the plain device copy timed first: the attainable HBM "
                          "bandwidth, and the reference for the byte counters of a profiler run")
@@ -108,7 +132,11 @@ def plan(args):
     if args.steps < 1 or args.warmup < 0 or args.repeats < 1:
         print("--steps and --repeats must be >= 1 and --warmup >= 0", file=sys.stderr)
         sys.exit(2)
-    return lifetimes(args.warmup), lifetimes(args.steps)
+    return lifetimes(args.warmup), max(MIN_TIMED_STEPS, lifetimes(args.steps))
+
+
+# shortest timed run: about 16 list rebuilds of the N = 1e6 workload
+MIN_TIMED_STEPS = 200
 
 
 def lifetimes(n, K=K_REBUILD):
@@ -257,7 +285,7 @@ def build_roofline(res):
     """Fused list build + batch draw: bound by FP64 vector arithmetic (the
     stencil candidate tests), priced at the FP64 vector peak."""
     km = res["kernels_ms"]["build"]
-    avg_s = km["avg_us"] * 1e-6
+    avg_s = km["avg_us_per_build"] * 1e-6
     flops = res["build_candidates"] * BUILD_FLOPS_PER_CANDIDATE
     ach = flops / avg_s / 1e12 if avg_s > 0 else None
     return {
@@ -270,7 +298,7 @@ def build_roofline(res):
         "traffic": recorded_traffic("build"),
         "flops_per_launch": flops,
         "candidates_per_launch": res["build_candidates"],
-        "avg_launch_us": km["avg_us"],
+        "avg_launch_us": km["avg_us_per_build"],
     }
 
 
@@ -301,7 +329,7 @@ def force_roofline(res, fk):
 KINDS = ("force_rbl", "force_full", "build", "binning", "integrate", "reduce", "predraw")
 
 
-def timed_blocks(ctx, x, v, torch, P, warmup, steps, repeats, use_full=False):
+def timed_blocks(ctx, x, v, torch, P, warmup, steps, repeats, use_full=False, K=None):
     """Warm-up run of `warmup` steps from the arrays x, v (rbl_step; the first
     run of a context autotunes the force kernel), then `repeats` blocks of
     `steps` steps that continue the state held on the GPU (rbl_continue:
@@ -311,46 +339,59 @@ def timed_blocks(ctx, x, v, torch, P, warmup, steps, repeats, use_full=False):
     whole lifetimes)."""
     from paper_2105_04884_amd import (KIND_FORCE_RBL, KIND_FORCE_FULL, KIND_BUILD, KIND_BIN,
                                       KIND_INTEGRATE, KIND_REDUCE, KIND_PREDRAW)
-    st0, _ = ctx.step(x, v, nsteps=warmup, dt=DT, P=P, seed=1, step0=0, rebuild_every=K_REBUILD,
-                      use_full=use_full)
-    times, statuses, attempts = [], [int(st0)], []
-    for _ in range(repeats):
+    st0, _ = ctx.step(x, v, nsteps=warmup, dt=DT, P=P, seed=1, step0=0,
+                      rebuild_every=K or K_REBUILD, use_full=use_full)
+    times, statuses, attempts, builds = [], [int(st0)], [], 0
+    for r in range(repeats):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         st, _ = ctx.cont(steps)
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t0)
         statuses.append(int(st))
-        attempts.append(ctx.last_run()["attempts"])
+        info = ctx.last_run()
+        attempts.append(info["attempts"])
+        builds += info["builds"]
+        log(f"[bench]   run {r + 1}/{repeats}: {steps} steps in {times[-1]:.4f} s, {info['builds']} builds")
     ctx.set_profiling(True)
     st, _ = ctx.cont(steps)
     statuses.append(int(st))
+    prof_builds = ctx.last_run()["builds"]
     kinds = dict(zip(KINDS, (KIND_FORCE_RBL, KIND_FORCE_FULL, KIND_BUILD, KIND_BIN, KIND_INTEGRATE,
                              KIND_REDUCE, KIND_PREDRAW)))
     stats = {k: ctx.kernel_stats(q) for k, q in kinds.items()}
     ctx.set_profiling(False)
     med = float(np.median(times))
+    km = {k: {"launches": s_[0], "total_ms": s_[1],
+              "avg_us": 1e3 * s_[1] / s_[0] if s_[0] else 0.0} for k, s_ in stats.items()}
+    # with rebuilds on displacement the build kernel is launched every step
+    # and returns at once unless a rebuild is due: its duration per list
+    # build is the summed time over the builds that ran
+    km["build"]["builds"] = prof_builds
+    km["build"]["avg_us_per_build"] = 1e3 * km["build"]["total_ms"] / prof_builds if prof_builds else 0.0
     return {
         "median_s": med,
         "block_seconds": [round(t, 6) for t in times],
         # RBL_OK 0 / RBL_W_SKIN 1 over the warm-up, timed and profiled blocks
         "status": max(statuses),
         "attempts_max": max(attempts),
-        "kernels_ms": {k: {"launches": s_[0], "total_ms": s_[1],
-                           "avg_us": 1e3 * s_[1] / s_[0] if s_[0] else 0.0} for k, s_ in stats.items()},
+        "steps_per_build": repeats * steps / builds if builds else None,
+        "kernels_ms": km,
     }
 
 
 def run_variant(name, x0, v0, box, precision, P, use_full, warmup, steps, repeats, torch,
-                source="shell", pin=False):
+                source="shell", pin=False, check=True, skin=SKIN, max_life=K_REBUILD):
     from paper_2105_04884_amd import Context
     lists = ("full",) if use_full else ("core", "shell")
     x = x0.clone()
     v = v0.clone()
     launch = {"lanes": 4 if use_full else 2, "persistent": 1} if pin else {}
-    ctx = Context(N, precision=precision, lists=lists, skin=SKIN, shell_source=source, **launch)
+    ctx = Context(N, precision=precision, lists=lists, skin=skin, shell_source=source, rebuild_check=check,
+                  **launch)
     ctx.build(x, box, RS, RC)
-    tb = timed_blocks(ctx, x, v, torch, P, warmup, steps, repeats, use_full)
+    K = max_life if check else K_REBUILD
+    tb = timed_blocks(ctx, x, v, torch, P, warmup, steps, repeats, use_full, K)
     info = ctx.info()
     tuning = ctx.tuning()
     counts = ctx.row_counts()
@@ -361,6 +402,10 @@ def run_variant(name, x0, v0, box, precision, P, use_full, warmup, steps, repeat
             "full": float(counts[2].mean())}
     res = {
         "name": name, "precision": precision, "P": P, "full": use_full, "shell_source": source,
+        "rebuild": (f"displacement (skin/2), at most every {K} steps" if check
+                    else f"every {K} steps"),
+        "skin": skin,
+        "steps_per_build": tb["steps_per_build"],
         "ms_per_step": 1e3 * tb["median_s"] / steps,
         "atom_steps_per_s": N * steps / tb["median_s"],
         "block_seconds": tb["block_seconds"],
@@ -373,7 +418,7 @@ def run_variant(name, x0, v0, box, precision, P, use_full, warmup, steps, repeat
         "build_candidates": candidates,
     }
     log(f"[bench] {name}: {res['ms_per_step']:.4f} ms/step, {res['atom_steps_per_s']:.3e} atom-steps/s "
-        f"(blocks {tb['block_seconds']} s, status {tb['status']})")
+        f"(blocks {tb['block_seconds']} s, status {tb['status']}, {tb['steps_per_build']} steps per build)")
     return res
 
 
@@ -389,16 +434,19 @@ def run_slab(torch, warmup, steps, repeats, P=20):
     n = st.n
     x, v = torch.from_numpy(st.pos).cuda(), torch.from_numpy(st.vel).cuda()
     q = torch.from_numpy(st.charges).cuda()
-    with Context(n, precision="mixed", skin=SKIN, pair="lj_erfc", alpha=0.3, charges=q) as ctx:
+    with Context(n, precision="mixed", skin=SKIN_RBL, pair="lj_erfc", alpha=0.3, charges=q,
+                 rebuild_check=True) as ctx:
         ctx.build(x, st.box, 1.5, 5.0)
-        tb = timed_blocks(ctx, x, v, torch, P, warmup, steps, repeats)
+        tb = timed_blocks(ctx, x, v, torch, P, warmup, steps, repeats, K=LIFE_RBL)
     el = tb["median_s"]
     log(f"[bench] slab: {1e3 * el / steps:.3f} ms/step, {n * steps / el:.3e} atom-steps/s")
     return {"workload": "charged LJ slab N=2,000,000, box L x L x 3L (L=133.5), liquid rho=0.8 in the "
                         "middle third, vapour rho=0.02, charges +-1, T=0.9; LJ + erfc(alpha r)/r with "
-                        "alpha=0.3, r_s=1.5 r_c=5.0 skin=0.3, P=20, rebuild every 10 steps, dt=0.005, mixed",
+                        "alpha=0.3, r_s=1.5 r_c=5.0 skin=0.5, P=20, lists rebuilt on displacement "
+                        "(skin/2, at most every 13 steps), dt=0.005, mixed",
             "n_particles": n, "steps": steps, "repeats": repeats, "atom_steps_per_s": n * steps / el,
             "ms_per_step": 1e3 * el / steps, "status": tb["status"], "attempts_max": tb["attempts_max"],
+            "steps_per_build": tb["steps_per_build"],
             "kernels_avg_us": kernels_avg_us(tb)}
 
 
@@ -411,17 +459,18 @@ def run_ensemble(torch, warmup, steps, repeats, seq_replicas=16):
     pos, vel, boxes, off = ens.concat()
     n = int(off[-1])
     out = {"workload": "512 LJ replicas, N log-uniform in [2000, 65536] (sum %d), density U[0.6, 0.9], "
-                       "T U[0.8, 1.5], r_s=1.5 r_c=3.5 skin=0.3, P=10, rebuild every 10 steps, "
-                       "dt=0.005" % n,
+                       "T U[0.8, 1.5], r_s=1.5 r_c=3.5 skin=0.5, P=10, lists rebuilt on displacement "
+                       "(skin/2, at most every 13 steps), dt=0.005" % n,
            "replicas": 512, "n_total": n, "steps": steps, "repeats": repeats}
     for precision in ("mixed", "fp64"):
         x, v = torch.from_numpy(pos).cuda(), torch.from_numpy(vel).cuda()
-        with Context(n, precision=precision, replica_offsets=off, skin=SKIN) as ctx:
+        with Context(n, precision=precision, replica_offsets=off, skin=SKIN_RBL, rebuild_check=True) as ctx:
             ctx.build(x, boxes, RS, RC)
-            tb = timed_blocks(ctx, x, v, torch, 10, warmup, steps, repeats)
+            tb = timed_blocks(ctx, x, v, torch, 10, warmup, steps, repeats, K=LIFE_RBL)
         el = tb["median_s"]
         out[precision] = {"atom_steps_per_s": n * steps / el, "ms_per_step": 1e3 * el / steps,
                           "status": tb["status"], "attempts_max": tb["attempts_max"],
+            "steps_per_build": tb["steps_per_build"],
                           "kernels_avg_us": kernels_avg_us(tb)}
         log(f"[bench] ensemble {precision}: {1e3 * el / steps:.3f} ms/step, {n * steps / el:.3e} atom-steps/s")
     # the same replicas one context each, on a sample of them
@@ -430,9 +479,9 @@ def run_ensemble(torch, warmup, steps, repeats, seq_replicas=16):
     for r in picks:
         s_ = ens.states[r]
         x, v = torch.from_numpy(s_.pos).cuda(), torch.from_numpy(s_.vel).cuda()
-        with Context(s_.n, precision="mixed", skin=SKIN) as ctx:
+        with Context(s_.n, precision="mixed", skin=SKIN_RBL, rebuild_check=True) as ctx:
             ctx.build(x, s_.box, RS, RC)
-            tb = timed_blocks(ctx, x, v, torch, 10, warmup, steps, 1)
+            tb = timed_blocks(ctx, x, v, torch, 10, warmup, steps, 1, K=LIFE_RBL)
         tot_atoms += s_.n * steps
         tot_s += tb["median_s"]
     out["sequential_mixed"] = {"atom_steps_per_s": tot_atoms / tot_s,
@@ -450,16 +499,18 @@ def run_large(torch, warmup, steps, repeats):
     st = inputs.large_fluid(seed=1)
     n = st.n
     x, v = torch.from_numpy(st.pos).cuda(), torch.from_numpy(st.vel).cuda()
-    with Context(n, precision="mixed", skin=SKIN) as ctx:
+    with Context(n, precision="mixed", skin=SKIN_RBL, rebuild_check=True) as ctx:
         ctx.build(x, st.box, 1.3, 4.0)
-        tb = timed_blocks(ctx, x, v, torch, 10, warmup, steps, repeats)
+        tb = timed_blocks(ctx, x, v, torch, 10, warmup, steps, repeats, K=LIFE_RBL)
         tuning = ctx.tuning()
     el = tb["median_s"]
     log(f"[bench] large: {1e3 * el / steps:.3f} ms/step, {n * steps / el:.3e} atom-steps/s")
-    return {"workload": "LJ fluid N=16,777,216 rho=0.8 T=1.2, r_s=1.3 r_c=4.0 skin=0.3, P=10, "
-                        "rebuild every 10 steps, dt=0.005, mixed",
+    return {"workload": "LJ fluid N=16,777,216 rho=0.8 T=1.2, r_s=1.3 r_c=4.0 skin=0.5, P=10, "
+                        "lists rebuilt on displacement (skin/2, at most every 13 steps), dt=0.005, "
+                        "mixed",
             "n_particles": n, "steps": steps, "repeats": repeats, "atom_steps_per_s": n * steps / el,
             "ms_per_step": 1e3 * el / steps, "status": tb["status"], "attempts_max": tb["attempts_max"],
+            "steps_per_build": tb["steps_per_build"],
             "kernels_avg_us": kernels_avg_us(tb),
             # the autotuner's launch-mode choice and times (one block per tile
             # against the persistent grid) and lanes per particle
@@ -929,24 +980,35 @@ def main(argv=None):
     copy_gbs = copy_bandwidth(torch, args.calib_copy_mb)
     x0 = torch.from_numpy(st.pos).cuda()
     v0 = torch.from_numpy(st.vel).cuda()
+    # (name, precision, P, full list, draw population, rebuild on displacement)
     variants = [
-        ("rbl_mixed_p10", "mixed", 10, False, "shell"),
-        ("rbl_fp64_p10", "fp64", 10, False, "shell"),
-        ("full_mixed", "mixed", 10, True, "shell"),
-        ("full_fp64", "fp64", 10, True, "shell"),
-        ("rbl_mixed_p5", "mixed", 5, False, "shell"),
-        ("rbl_mixed_p20", "mixed", 20, False, "shell"),
-        ("rbl_stencil_mixed_p10", "mixed", 10, False, "stencil"),
+        ("rbl_mixed_p10", "mixed", 10, False, "shell", True),
+        ("rbl_fp64_p10", "fp64", 10, False, "shell", True),
+        ("full_mixed", "mixed", 10, True, "shell", True),
+        ("full_fp64", "fp64", 10, True, "shell", True),
+        ("rbl_mixed_p5", "mixed", 5, False, "shell", True),
+        ("rbl_mixed_p20", "mixed", 20, False, "shell", True),
+        ("rbl_stencil_mixed_p10", "mixed", 10, False, "stencil", True),
+        # fixed 10-step lifetimes at skin 0.3 (no displacement check: some
+        # particles pass skin/2 within a lifetime, status RBL_W_SKIN)
+        ("rbl_mixed_p10_fixed10", "mixed", 10, False, "shell", False),
+        ("full_fp64_fixed10", "fp64", 10, True, "shell", False),
     ]
     if args.variants != "all":
         keep = set(args.variants.split(","))
         variants = [v for v in variants if v[0] in keep]
     log(f"[bench] {warmup} warm-up steps, {args.repeats} timed blocks of {steps} steps per variant")
     results = {}
-    for name, prec, P, full, source in variants:
+    for name, prec, P, full, source, check in variants:
         log(f"[bench] variant {name}")
+        if not check:
+            skin, life = SKIN, K_REBUILD
+        else:
+            skin, life = (SKIN_FULL, LIFE_FULL) if full else (SKIN_RBL, LIFE_RBL)
+            skin = args.skin if args.skin is not None else skin
+            life = args.max_lifetime if args.max_lifetime is not None else life
         results[name] = run_variant(name, x0, v0, st.box, prec, P, full, warmup, steps, args.repeats,
-                                    torch, source, args.pin_launch)
+                                    torch, source, args.pin_launch, check, skin, life)
     head = results.get("rbl_mixed_p10") or next(iter(results.values()))
 
     # roofline of the dominant kernel of the headline variant (largest
@@ -982,13 +1044,14 @@ def main(argv=None):
     wl = [w for w in args.workloads.split(",") if w and w != "none"]
     if "ensemble" in wl:
         log("[bench] workload: 512-replica ensemble")
-        extra["ensemble"] = guarded("ensemble", run_ensemble, torch, warmup, steps, args.repeats)
+        extra["ensemble"] = guarded("ensemble", run_ensemble, torch, 10, lifetimes(500 // args.repeats),
+                                    args.repeats)
     if "large" in wl:
         log("[bench] workload: N = 2^24")
-        extra["large"] = guarded("large", run_large, torch, warmup, steps, args.repeats)
+        extra["large"] = guarded("large", run_large, torch, 10, lifetimes(200 // args.repeats), args.repeats)
     if "slab" in wl:
         log("[bench] workload: charged slab")
-        extra["slab"] = guarded("slab", run_slab, torch, warmup, steps, args.repeats)
+        extra["slab"] = guarded("slab", run_slab, torch, 10, lifetimes(500 // args.repeats), args.repeats)
     if "eos" in wl:
         log("[bench] workload: Sec. III equation of state")
         extra["eos"] = guarded("eos", run_eos, torch)
@@ -1010,17 +1073,19 @@ def main(argv=None):
         "steps_requested": args.steps,
         "warmup_requested": args.warmup,
         "repeats": args.repeats,
-        "timing": ("median over the repeats of one block of `steps` steps (whole 10-step list "
-                   "lifetimes replayed as captured graphs, continuing the GPU-resident state after "
-                   "`warmup` steps), between device synchronisations"),
+        "timing": ("median over the repeats of one block of `steps` steps (captured graphs of 10 "
+                   "steps replayed, continuing the GPU-resident state after `warmup` steps), between "
+                   "device synchronisations"),
         "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32 pair + f64 classify/accumulate" if head["precision"] == "mixed" else "f64",
         "data": "synthetic",
-        "config": {"workload": "LJ fluid N=1,000,000 rho=0.8442 T=1.0, r_s=1.5 r_c=3.5 skin=0.3, "
-                               "P=10, rebuild every 10 steps, dt=0.005, velocity Verlet NVE",
+        "config": {"workload": "LJ fluid N=1,000,000 rho=0.8442 T=1.0, r_s=1.5 r_c=3.5, P=10, "
+                               "dt=0.005, velocity Verlet NVE; lists rebuilt when a particle has moved "
+                               "more than skin/2 since the last build (skin 0.5, at most every 13 "
+                               "steps; full list: skin 0.3, at most every 10)",
                    "n_particles": N, "P": head["P"], "precision": head["precision"]},
         "status": head["status"],
         "roofline": roof,

@@ -110,6 +110,15 @@ typedef struct rbl_config {
                                   outside [r_s, r_c) add zero.  Batches are then always
                                   drawn at the list build (predraw is implied) and no
                                   shell row is needed by rbl_forces or rbl_step. */
+    int32_t rebuild_check;     /* 0 (default): rbl_step rebuilds the lists before every force
+                                  evaluation s with s % rebuild_every == 0.  1: rebuilds
+                                  before evaluation s when some particle has moved more than
+                                  skin/2 since the last build (|x_i(s) - x_i(b)|^2 >
+                                  (skin/2)^2, in FP64) or s - b == rebuild_every, b being the
+                                  step of the last build: lists then hold every pair within
+                                  the radii at every step (the standard Verlet-list
+                                  criterion), and the rebuild is decided on the device
+                                  inside the captured lifetimes. */
     int32_t reserved;          /* must be 0 */
 } rbl_config;
 
@@ -209,9 +218,12 @@ rbl_status rbl_continue(rbl_ctx* ctx, double* pos, double* vel, double* force,
 
 /* The last rbl_step / rbl_continue: attempts = passes it took (1, or more
  * when a list outgrew its room and the call was repeated), end_step = index
- * of its last force evaluation, resumable = 1 if rbl_continue may follow.
- * Any pointer may be NULL. */
-rbl_status rbl_last_run(rbl_ctx* ctx, int32_t* attempts, int64_t* end_step, int32_t* resumable);
+ * of its last force evaluation, resumable = 1 if rbl_continue may follow,
+ * builds = list builds of its last pass (the entry build of an rbl_step
+ * included), build_step = force evaluation of the last build.  Any pointer
+ * may be NULL. */
+rbl_status rbl_last_run(rbl_ctx* ctx, int32_t* attempts, int64_t* end_step, int32_t* resumable,
+                        int64_t* builds, int64_t* build_step);
 
 /* ---- parity exports (host buffers, caller-allocated; synchronising) ---- */
 

@@ -76,7 +76,7 @@ def load():
                                C.c_double, C.c_double, C.c_int64, C.c_int, C.c_uint64,
                                C.c_int64, C.c_int, C.c_int, C.c_int, C.c_int, C.c_uint32,
                                C.c_void_p, C.c_double, C.c_int, C.c_double, C.c_double,
-                               C.c_void_p, _f64p, C.c_void_p]
+                               C.c_void_p, _f64p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]
     lib.orc_md_run.restype = C.c_int
     lib.orc_langevin_noise.argtypes = [C.c_uint64, C.c_uint32, C.c_uint64, C.c_uint32, _f64p]
     lib.orc_rdf.argtypes = [C.c_int64, _f64p, _f64p, C.c_double, C.c_int, C.c_void_p]
@@ -309,12 +309,17 @@ def mean_subtract(f: np.ndarray):
 def md_run(pos, vel, box, rs, rc, skin, dt, nsteps, p=10, seed=1, step0=0, K=10,
            use_full=False, shift=True, momentum_fix=True, replica=0, want_ev=False,
            charges=None, alpha: float = 0.0, shell_source: str = "shell",
-           gamma: float = 0.0, kT: float = 1.0, unwrapped=None):
+           gamma: float = 0.0, kT: float = 1.0, unwrapped=None, check: bool = False,
+           builds=None):
     """Run of Algorithm 1: velocity Verlet (NVE) for gamma = 0, Langevin
     (BAOAB, friction gamma, bath temperature kT) otherwise.  Returns (pos,
     vel, force, ev) with ev of shape (nsteps+1, 2) = (U, W) per force
     evaluation or None.  ``unwrapped`` (float64 array shaped like pos,
-    updated in place) follows the positions without wrapping."""
+    updated in place) follows the positions without wrapping.  Lists are
+    rebuilt before every evaluation s with s % K == 0, or with ``check``
+    when some particle has moved more than skin/2 since the last build or K
+    steps have passed; ``builds`` (a list) receives the steps of the
+    builds."""
     lib = load()
     x = np.ascontiguousarray(pos, dtype=np.float64).copy()
     v = np.ascontiguousarray(vel, dtype=np.float64).copy()
@@ -325,13 +330,18 @@ def md_run(pos, vel, box, rs, rc, skin, dt, nsteps, p=10, seed=1, step0=0, K=10,
         if (not isinstance(unwrapped, np.ndarray) or unwrapped.dtype != np.float64
                 or unwrapped.shape != x.shape or not unwrapped.flags.c_contiguous):
             raise ValueError("unwrapped must be a contiguous float64 array shaped like pos")
+    bsteps = np.zeros(nsteps + 1, dtype=np.int64)
+    nb = np.zeros(1, dtype=np.int64)
     r = lib.orc_md_run(x.shape[1], x, v, np.asarray(box, dtype=np.float64), rs, rc, skin, dt,
                        nsteps, p, seed, step0, K, int(use_full), int(shift), int(momentum_fix),
                        replica, _ptr_or_null(q), float(alpha),
                        {"shell": 0, "stencil": 1}[shell_source], float(gamma), float(kT),
-                       _ptr_or_null(unwrapped), f, _ptr_or_null(ev))
+                       _ptr_or_null(unwrapped), f, _ptr_or_null(ev), int(bool(check)),
+                       bsteps.ctypes.data_as(C.c_void_p), nb.ctypes.data_as(C.c_void_p))
     if r:
         raise RuntimeError(f"orc_md_run failed ({r})")
+    if builds is not None:
+        builds.extend(int(b) for b in bsteps[:int(nb[0])])
     return x, v, f, ev
 
 

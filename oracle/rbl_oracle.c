@@ -821,9 +821,20 @@ int orc_md_run(int64_t n, double* pos, double* vel, const double box[3],
                int shift, int momentum_fix, uint32_t replica,
                const double* charge, double alpha, int stencil,
                double gamma, double kT, double* unwrapped,
-               double* force_out, double* ev_out)
+               double* force_out, double* ev_out,
+               int check, int64_t* build_steps, int64_t* n_builds)
 {
     if (K < 1 || n < 1 || !(gamma >= 0.0) || !(kT >= 0.0)) return -1;
+    /* Lists rebuilt on displacement (check != 0): the Verlet-list criterion
+     * behind the skin of Sec. II -- the lists stay complete as long as no
+     * particle has moved more than half the skin since they were built --
+     * checked at every step after the drift, and at the latest K steps
+     * after the last build.  Otherwise before every evaluation s with
+     * s mod K == 0.  Builds are recorded in build_steps (nsteps + 1
+     * entries) when given. */
+    double half2 = (0.5 * skin) * (0.5 * skin);
+    double* xb = (double*)malloc(sizeof(double) * 3 * (size_t)n);
+    int64_t last_build = step0, nb = 0;
     double c_ou = exp(-gamma * dt);
     double s_ou = sqrt(kT * (1.0 - c_ou * c_ou));
     orc_lists L = {0};
@@ -857,9 +868,24 @@ int orc_md_run(int64_t n, double* pos, double* vel, const double box[3],
                 }
             }
         }
-        if (it == 0 || s % K == 0) {
+        int rebuild = it == 0;
+        if (it > 0 && !check) rebuild = s % K == 0;
+        if (it > 0 && check) {
+            rebuild = s - last_build >= K;
+            for (int64_t i = 0; i < n && !rebuild; ++i) {
+                double dx = pos[i] - xb[i];
+                double dy = pos[n + i] - xb[n + i];
+                double dz = pos[2 * n + i] - xb[2 * n + i];
+                if (dx * dx + dy * dy + dz * dz > half2) rebuild = 1;
+            }
+        }
+        if (rebuild) {
             rcode = build_all(n, pos, box, rs, rc, skin, use_full, stencil, &L);
             if (rcode) break;
+            memcpy(xb, pos, sizeof(double) * 3 * (size_t)n);  /* positions as wrapped by the build */
+            last_build = s;
+            if (build_steps) build_steps[nb] = s;
+            nb += 1;
         }
         if (use_full) {
             orc_forces_full(n, pos, box, rc, shift, n, NULL, L.full_off, L.full_idx, charge, alpha, F, e, w);
@@ -876,7 +902,8 @@ int orc_md_run(int64_t n, double* pos, double* vel, const double box[3],
         }
     }
     if (force_out) memcpy(force_out, F, sizeof(double) * 3 * (size_t)n);
-    free(F); free(e); free(w);
+    if (n_builds) *n_builds = nb;
+    free(F); free(e); free(w); free(xb);
     free_lists(&L);
     return rcode;
 }

@@ -83,7 +83,7 @@ class Context:
                  capacity_factor: float = 1.25,
                  replica_offsets=None,
                  pair: str = "lj", alpha: float = 0.0, charges=None, shell_source: str = "shell",
-                 stream=None):
+                 rebuild_check: bool = False, stream=None):
         torch = _torch()
         lib = _lib.load()
         cfg = _lib.Config()
@@ -104,6 +104,7 @@ class Context:
         cfg.persistent = int(persistent)
         cfg.capacity_factor = float(capacity_factor)
         cfg.shell_source = {"shell": _lib.SHELL_LIST, "stencil": _lib.SHELL_STENCIL}[shell_source]
+        cfg.rebuild_check = int(bool(rebuild_check))
         self._offsets = None
         if replica_offsets is not None:
             self._offsets = np.ascontiguousarray(replica_offsets, dtype=np.int64)
@@ -197,12 +198,13 @@ class Context:
         return st, ev
 
     def last_run(self):
-        """Passes the last run took, its last force-evaluation index and
-        whether ``cont`` may follow."""
+        """Passes the last run took, its last force-evaluation index, whether
+        ``cont`` may follow, its list builds and the step of the last one."""
         a, r = C.c_int32(), C.c_int32()
-        e = C.c_int64()
-        _check(self._lib.rbl_last_run(self._h, C.byref(a), C.byref(e), C.byref(r)))
-        return {"attempts": a.value, "end_step": e.value, "resumable": bool(r.value)}
+        e, nb, bs = C.c_int64(), C.c_int64(), C.c_int64()
+        _check(self._lib.rbl_last_run(self._h, C.byref(a), C.byref(e), C.byref(r), C.byref(nb), C.byref(bs)))
+        return {"attempts": a.value, "end_step": e.value, "resumable": bool(r.value),
+                "builds": nb.value, "build_step": bs.value}
 
     # -- thermostat and observables ----------------------------------------
     def set_thermostat(self, gamma: float, kT=None):

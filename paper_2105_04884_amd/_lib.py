@@ -54,6 +54,7 @@ class Config(C.Structure):
         ("replica_offsets", C.POINTER(C.c_int64)),
         ("charges", C.c_void_p),
         ("shell_source", C.c_int32),
+        ("rebuild_check", C.c_int32),
         ("reserved", C.c_int32),
     ]
 
@@ -96,7 +97,7 @@ def load(path: str = LIB_PATH):
         "rbl_full_forces": (i32, [vp, vp, vp, vp]),
         "rbl_step": (i32, [vp, vp, vp, vp, i64, d, i32, u64, i64, i32, i32, vp]),
         "rbl_continue": (i32, [vp, vp, vp, vp, i64, vp]),
-        "rbl_last_run": (i32, [vp, p32, p64, p32]),
+        "rbl_last_run": (i32, [vp, p32, p64, p32, p64, p64]),
         "rbl_row_counts": (i32, [vp, i64, p64, p64]),
         "rbl_export_lists": (i32, [vp, i64, p64, p64, p32, p64, p32, p64, p32]),
         "rbl_export_batches": (i32, [vp, i32, u64, u64, i64, p64, p32, p32]),

@@ -58,6 +58,22 @@ __global__ void k_fill_i32(int* p, int64_t n, int v)
     if (i < n) p[i] = v;
 }
 
+// Rebuilds decided on the device.  When lists are rebuilt on displacement,
+// every step queues the binning and list-build kernels with the address of
+// a gate word that the step's integrator sets when a rebuild is due; they
+// return at once while it is 0.  A null gate means "always run".
+__device__ __forceinline__ bool gated_off(const uint64_t* gate)
+{
+    return gate != nullptr && *gate == 0;
+}
+
+__global__ void k_clear_counts(int* p, int64_t n, const uint64_t* gate)
+{
+    if (gated_off(gate)) return;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
 // ---------------------------------------------------------------------------
 // Binning: cell index of every particle (positions wrapped into the box),
 // counting-sort histogram.  Source is either the caller's SoA arrays (one
@@ -77,6 +93,14 @@ struct BinArgs {
     int* rank_of_src;
     int* cell_count;
     int* flags;
+    const uint64_t* gate;  // rebuild gate (null: always run)
+    // gated rebuilds of the sorted state keep one buffer set: the counting
+    // pass saves every slot's position, velocity and ID here first, the
+    // scatter and the gather read them back (null: no save)
+    double4* xs_save;
+    const double* vs_src;  // [3][n_src]
+    double* vs_save;
+    int* perm_save;
 };
 
 // Cell of every source particle and its rank within the cell (a unique
@@ -88,6 +112,7 @@ struct BinArgs {
 template <int SRC>
 __global__ __launch_bounds__(256) void k_bin_count(BinArgs a)
 {
+    if (gated_off(a.gate)) return;
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool live = s < a.n_src;
     int cell = -1;
@@ -106,6 +131,13 @@ __global__ __launch_bounds__(256) void k_bin_count(BinArgs a)
             x[0] = p.x;
             x[1] = p.y;
             x[2] = p.z;
+            if (a.xs_save) {
+                a.xs_save[s] = p;
+                a.perm_save[s] = a.perm_old[s];
+                a.vs_save[s] = a.vs_src[s];
+                a.vs_save[a.n_src + s] = a.vs_src[a.n_src + s];
+                a.vs_save[2 * a.n_src + s] = a.vs_src[2 * a.n_src + s];
+            }
             if (live) {
                 // skin monitor: displacement over the list lifetime that ends here
                 const double dx = p.x - a.xb[s];
@@ -178,8 +210,10 @@ __device__ __forceinline__ int block_excl_scan(int v, int* lds_waves, int& total
     return incl - v + off;
 }
 
-__global__ __launch_bounds__(kScanBlock) void k_scan_tiles(const int* cnt, int64_t n, int* tile_sum)
+__global__ __launch_bounds__(kScanBlock) void k_scan_tiles(const int* cnt, int64_t n, int* tile_sum,
+                                                           const uint64_t* gate)
 {
+    if (gated_off(gate)) return;
     __shared__ int lds[16];
     const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPerThread;
     int s = 0;
@@ -192,8 +226,9 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_tiles(const int* cnt, int64
 }
 
 // One block of 1024 threads scans up to 1024*8 tile sums (exclusive, in place).
-__global__ __launch_bounds__(1024) void k_scan_tile_sums(int* tile_sum, int ntiles)
+__global__ __launch_bounds__(1024) void k_scan_tile_sums(int* tile_sum, int ntiles, const uint64_t* gate)
 {
+    if (gated_off(gate)) return;
     __shared__ int lds[16];
     const int base = threadIdx.x * kScanPerThread;
     int v[kScanPerThread];
@@ -214,8 +249,10 @@ __global__ __launch_bounds__(1024) void k_scan_tile_sums(int* tile_sum, int ntil
 
 __global__ __launch_bounds__(kScanBlock) void k_scan_final(const int* cnt, int64_t n,
                                                            const int* tile_sum, const int* cell_rep,
-                                                           const DevReplica* rep, int* start)
+                                                           const DevReplica* rep, int* start,
+                                                           const uint64_t* gate)
 {
+    if (gated_off(gate)) return;
     __shared__ int lds[16];
     const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPerThread;
     int v[kScanPerThread];
@@ -243,6 +280,7 @@ __global__ __launch_bounds__(256) void k_bin_scatter(BinArgs a, const int* cell_
                                                      int* perm_new, int* src_of_slot,
                                                      int64_t n_slots)
 {
+    if (gated_off(a.gate)) return;
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= a.n_src) return;
     const int cell = a.cell_of_src[s];
@@ -261,8 +299,9 @@ __global__ __launch_bounds__(256) void k_bin_scatter(BinArgs a, const int* cell_
 // handful of particles).  Makes the slot order independent of atomic order.
 __global__ __launch_bounds__(256) void k_cell_sort(const int* cell_start, const int* cell_count,
                                                    int64_t n_cells, int64_t n_slots, int* perm,
-                                                   int* src_of_slot, int* flags)
+                                                   int* src_of_slot, int* flags, const uint64_t* gate)
 {
+    if (gated_off(gate)) return;
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= n_cells) return;
     const int b = cell_start[c];
@@ -304,11 +343,13 @@ struct GatherArgs {
     double* xb;               // positions at the build, [3][n_slots] (skin monitor)
     int* slot_of_id;
     int* img_delta;           // may be null: [3][n] box lengths taken off by the wrap
+    const uint64_t* gate;     // rebuild gate (null: always run)
 };
 
 template <int SRC, bool VEL>
 __global__ __launch_bounds__(256) void k_gather(GatherArgs a)
 {
+    if (gated_off(a.gate)) return;
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= a.n_slots) return;
     const int id = a.perm[s];
@@ -394,7 +435,22 @@ struct BuildArgs {
     int* shell_len;
     int* full_len;
     int* flags;
+    const uint64_t* gate;      // rebuild gate (null: always run)
+    // the MD loop's builds record themselves: mark[0] = step of the build,
+    // mark[1] += 1 (null: not recorded); the step is *mark_step_dev +
+    // mark_step, or mark_step alone without a device counter
+    uint64_t* mark;
+    uint64_t mark_step;
+    const uint64_t* mark_step_dev;
 };
+
+__device__ __forceinline__ void record_build(const BuildArgs& a)
+{
+    if (a.mark && blockIdx.x == 0 && threadIdx.x == 0) {
+        a.mark[0] = a.mark_step_dev ? *a.mark_step_dev + a.mark_step : a.mark_step;
+        a.mark[1] += 1;
+    }
+}
 
 // Along one axis of nc cells, the stencil of cells within +-2 of c, sorted
 // by wrapped coordinate, as at most two runs [p0, p0+l0) and [p1, p1+l1).
@@ -452,6 +508,8 @@ __device__ __forceinline__ int shfl_i32(int v, int src_lane)
 template <bool COUNT_ONLY, bool WC, bool WS, bool WF>
 __global__ __launch_bounds__(256) void k_build(BuildArgs a)
 {
+    if (gated_off(a.gate)) return;
+    if (!COUNT_ONLY) record_build(a);
     const int lane = threadIdx.x & 63;
     const int64_t cell = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (cell >= a.n_cells) return;
@@ -767,6 +825,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PMAX <= 32 
     // per wavefront: list_budget entries + a write-off word per lane
     extern __shared__ unsigned short s_dyn[];
     const BuildArgs& a = fa.b;
+    if (gated_off(a.gate)) return;
+    if (!fa.draw_only) record_build(a);
     const int lane = threadIdx.x & 63;
     const int w = rfl((int)(threadIdx.x >> 6));
     const int budget = fa.list_budget;
@@ -1207,7 +1267,8 @@ struct ForceArgs {
     const int* shell;      // shell list (inline) or full list (full mode)
     const int* shell_len;
     int cap_shell;
-    const int* batch;      // pre-drawn: [n_slots][P] for this step
+    const int* batch;      // pre-drawn: [n_slots][P] for this step, or with bstep the
+                           // [K][n_slots][P] batches drawn from step *bstep on
     int64_t n_slots;
     int64_t n_slices;
     double rs2, rc2, uc;   // core radius^2, cut-off^2, LJ energy at the cut-off
@@ -1221,7 +1282,24 @@ struct ForceArgs {
     double* partial;       // [5][n_slices]
     int64_t vblocks;       // work tiles of 256 lanes; a launch of fewer blocks (a
                            // persistent grid) walks them in steps of its size
+    const uint64_t* bstep; // step of the build whose batches `batch` holds (null: this step's)
+    uint64_t* gate_clear;  // rebuild gate to reset for the next step (null: none)
 };
+
+// This step's pre-drawn batches (the force evaluation's step relative to
+// the build that drew them, when the build step is known on the device
+// only), and the reset of the rebuild gate by the first thread of the launch.
+__device__ __forceinline__ const int* step_batches(const ForceArgs& a)
+{
+    if (!a.bstep) return a.batch;
+    const uint64_t st = a.step_dev ? *a.step_dev + a.step : a.step;
+    return a.batch + (int64_t)(st - *a.bstep) * a.P * a.n_slots;
+}
+
+__device__ __forceinline__ void force_prologue(const ForceArgs& a)
+{
+    if (a.gate_clear && blockIdx.x == 0 && threadIdx.x == 0) *a.gate_clear = 0;
+}
 
 template <int PREC, bool ERFC>
 __device__ __forceinline__ void pair_term(double r2, double qq, double alpha, double& fm, double& u)
@@ -1317,6 +1395,7 @@ __device__ __forceinline__ void force_tile(const ForceArgs& a, int64_t tile, uin
             }
             Acc sh = {0.0, 0.0, 0.0, 0.0, 0.0};
             const int* srow = a.shell + ell(slot, 0, a.cap_shell);
+            const int* bat = MODE == kShellInline ? nullptr : step_batches(a);
             for (int m = 0; m < cnt; m += U) {
                 int j[U];
                 bool live[U];
@@ -1330,7 +1409,7 @@ __device__ __forceinline__ void force_tile(const ForceArgs& a, int64_t tile, uin
                             const int kq = n > P ? (int)s_pos[(m + u) * 256 + threadIdx.x] : m + u;
                             jj = srow[(int64_t)kq * 64];
                         } else {
-                            jj = a.batch[slot * P + m + u];
+                            jj = bat[slot * P + m + u];
                             if ((uint64_t)(uint32_t)jj >= (uint64_t)a.n_slots) jj = (int)slot;
                         }
                     }
@@ -1391,6 +1470,7 @@ template <int PREC, int MODE, bool ENERGY, bool ERFC, int PMAX>
 __global__ __launch_bounds__(256) void k_forces(ForceArgs a)
 {
     __shared__ uint32_t s_pos[MODE == kShellInline ? PMAX * 256 : 1];
+    force_prologue(a);
     for (int64_t b = blockIdx.x; b < a.vblocks; b += gridDim.x)
         force_tile<PREC, MODE, ENERGY, ERFC, PMAX>(a, xcd_tile(b, a.vblocks), s_pos);
 }
@@ -1451,7 +1531,7 @@ __device__ __forceinline__ void force_tile_lpp(const ForceArgs& a, int64_t tile)
             const int P = a.P;
             const int cnt = n < P ? n : P;
             scale = n > P ? (double)n / (double)P : 1.0;
-            const int* brow = a.batch + slot * P;
+            const int* brow = step_batches(a) + slot * P;
             for (int m = l; m < cnt; m += U * LPP) {
                 int j[U];
                 bool live[U];
@@ -1528,6 +1608,7 @@ __device__ __forceinline__ void force_tile_lpp(const ForceArgs& a, int64_t tile)
 template <int PREC, int MODE, bool ENERGY, bool ERFC, int LPP>
 __global__ __launch_bounds__(256) void k_forces_lpp(ForceArgs a)
 {
+    force_prologue(a);
     for (int64_t b = blockIdx.x; b < a.vblocks; b += gridDim.x)
         force_tile_lpp<PREC, MODE, ENERGY, ERFC, LPP>(a, xcd_tile(b, a.vblocks));
 }
@@ -1624,6 +1705,12 @@ struct IntArgs {
     uint64_t step;             // force evaluation the step leads to
     const uint64_t* step_dev;  // if set, the step is *step_dev + step
     const uint64_t* pending;   // mid steps: closing half-kick only if *pending (null: always)
+    // rebuild on displacement: after the drift, *gate = 1 if some particle
+    // moved more than skin/2 since the last build (xb) or the lifetime since
+    // that build (*bstep) reached max_life steps (null: fixed lifetimes)
+    uint64_t* gate;
+    const uint64_t* bstep;
+    int64_t max_life;
 };
 
 // The three standard normal numbers of the Ornstein-Uhlenbeck step of
@@ -1655,6 +1742,11 @@ template <int MODE>
 __global__ __launch_bounds__(256) void k_integrate(IntArgs a)
 {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (MODE != kIntLast && a.gate && s == 0) {
+        // the longest list lifetime is reached
+        const uint64_t st = a.step_dev ? *a.step_dev + a.step : a.step;
+        if ((int64_t)(st - *a.bstep) >= a.max_life) *a.gate = 1;
+    }
     if ((s >> 6) >= a.n_slices) return;
     const int r = a.slice_rep[s >> 6];
     const DevReplica& R = a.rep[r];
@@ -1697,6 +1789,14 @@ __global__ __launch_bounds__(256) void k_integrate(IntArgs a)
         x.y = x.y + a.dt * v[1];
         x.z = x.z + a.dt * v[2];
         a.xs[s] = x;
+    }
+    if (MODE != kIntLast && a.gate) {
+        // displacement since the last build past skin/2: rebuild at this step
+        const double4 x = a.xs[s];
+        const double dx = x.x - a.xb[s];
+        const double dy = x.y - a.xb[a.n_slots + s];
+        const double dz = x.z - a.xb[2 * a.n_slots + s];
+        if (dx * dx + dy * dy + dz * dz > a.half_skin2) *a.gate = 1;
     }
 #pragma unroll
     for (int d = 0; d < 3; ++d) a.vs[d * a.n_slots + s] = v[d];

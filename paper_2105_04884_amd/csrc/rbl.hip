@@ -86,8 +86,12 @@ struct rbl_ctx {
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     std::vector<unsigned char> gsig;  // parameters the captured blocks were made with
-    uint64_t* d_step = nullptr;       // [0]: step counter read by captured kernels; [1]: pending
-                                      // half-kick flag of a captured lifetime's first step
+    // device words of the MD loop: [0] step counter read by captured kernels;
+    // [1] pending half-kick flag of a captured lifetime's first step; [2] step
+    // of the last list build and [3] builds in the run (written by the build
+    // kernels); [4] rebuild gate of the displacement criterion
+    uint64_t* d_step = nullptr;
+    uint64_t h_marks[2] = {0, 0};
     int R = 1;
     int64_t n = 0, n_slots = 0, n_slices = 0;
     std::vector<int64_t> id_base, rep_n, slot_base;
@@ -175,6 +179,7 @@ struct rbl_ctx {
         int64_t end_step = 0;
         int64_t build_step = 0;
         int attempts = 0;  // md_run passes the last call took (more than 1 after a capacity regrow)
+        int64_t builds = 0;  // list builds in the last pass
     } run;
     double* d_ckpt = nullptr;  // [6][n] caller-order positions and velocities at a continued run's start
 
@@ -402,8 +407,14 @@ Thresholds thresholds(const rbl_ctx* c)
 // ---------------------------------------------------------------------------
 // binning: histogram, scan, scatter, per-cell ID sort, gather into new buffers
 
+// With `gate` (a rebuild decided on the device) every kernel returns at once
+// while *gate is 0, and the new state lands in the current buffer set, which
+// captured kernels address: the counting pass saves the old state into the
+// other set, from which the scatter and the gather read.  The skin monitor is
+// then off: the rebuild happens because the displacement reached skin/2.
 template <int SRC>
-rbl_status bin_particles(rbl_ctx* c, const double* pos, const double* vel, bool with_vel)
+rbl_status bin_particles(rbl_ctx* c, const double* pos, const double* vel, bool with_vel,
+                         const uint64_t* gate = nullptr)
 {
     const int nxt = 1 - c->cur;
     BinArgs b;
@@ -416,8 +427,13 @@ rbl_status bin_particles(rbl_ctx* c, const double* pos, const double* vel, bool 
     b.xb = c->d_xb;
     {
         const double hs = 0.5 * c->cfg.skin;
-        b.half_skin2 = hs * hs;
+        b.half_skin2 = gate ? std::numeric_limits<double>::infinity() : hs * hs;
     }
+    b.gate = gate;
+    b.xs_save = nullptr;
+    b.vs_src = nullptr;
+    b.vs_save = nullptr;
+    b.perm_save = nullptr;
     b.n = c->n;
     b.n_src = SRC == kSrcCaller ? c->n : c->n_slots;
     b.cell_of_src = c->d_cell_of_src;
@@ -426,55 +442,68 @@ rbl_status bin_particles(rbl_ctx* c, const double* pos, const double* vel, bool 
     b.flags = c->d_flags;
     const int64_t ntiles = (c->n_cells + kScanTile - 1) / kScanTile;
     RBL_TRY(timed(c, kKBin, [&] {
-        k_fill_i32<<<grid_for(c->n_cells), kBlock, 0, c->ls>>>(c->d_cell_count, c->n_cells, 0);
+        k_clear_counts<<<grid_for(c->n_cells), kBlock, 0, c->ls>>>(c->d_cell_count, c->n_cells, gate);
     }));
-    RBL_TRY(timed(c, kKBin, [&] { k_bin_count<SRC><<<grid_for(b.n_src), kBlock, 0, c->ls>>>(b); }));
+    const bool in_place = gate != nullptr && SRC == kSrcSorted;
+    const int dst = in_place ? c->cur : nxt;
+    {
+        BinArgs bc = b;
+        if (in_place) {
+            bc.xs_save = c->d_xs[nxt];
+            bc.vs_src = c->d_vs[c->cur];
+            bc.vs_save = c->d_vs[nxt];
+            bc.perm_save = c->d_perm[nxt];
+        }
+        RBL_TRY(timed(c, kKBin, [&] { k_bin_count<SRC><<<grid_for(b.n_src), kBlock, 0, c->ls>>>(bc); }));
+    }
+    if (in_place) b.perm_old = c->d_perm[nxt];
     RBL_TRY(timed(c, kKBin, [&] {
         k_scan_tiles<<<(unsigned)ntiles, kScanBlock, 0, c->ls>>>(c->d_cell_count, c->n_cells,
-                                                                     c->d_tile_sum);
+                                                                     c->d_tile_sum, gate);
     }));
     RBL_TRY(timed(c, kKBin, [&] {
-        k_scan_tile_sums<<<1, 1024, 0, c->ls>>>(c->d_tile_sum, (int)ntiles);
+        k_scan_tile_sums<<<1, 1024, 0, c->ls>>>(c->d_tile_sum, (int)ntiles, gate);
     }));
     RBL_TRY(timed(c, kKBin, [&] {
         k_scan_final<<<(unsigned)ntiles, kScanBlock, 0, c->ls>>>(
-            c->d_cell_count, c->n_cells, c->d_tile_sum, c->d_cell_rep, c->d_rep, c->d_cell_start);
+            c->d_cell_count, c->n_cells, c->d_tile_sum, c->d_cell_rep, c->d_rep, c->d_cell_start, gate);
     }));
     RBL_TRY(timed(c, kKBin, [&] {
         k_bin_scatter<SRC><<<grid_for(b.n_src), kBlock, 0, c->ls>>>(
-            b, c->d_cell_start, c->d_perm[nxt], c->d_src_of_slot, c->n_slots);
+            b, c->d_cell_start, c->d_perm[dst], c->d_src_of_slot, c->n_slots);
     }));
     RBL_TRY(timed(c, kKBin, [&] {
         k_cell_sort<<<grid_for(c->n_cells), kBlock, 0, c->ls>>>(
-            c->d_cell_start, c->d_cell_count, c->n_cells, c->n_slots, c->d_perm[nxt],
-            c->d_src_of_slot, c->d_flags);
+            c->d_cell_start, c->d_cell_count, c->n_cells, c->n_slots, c->d_perm[dst],
+            c->d_src_of_slot, c->d_flags, gate);
     }));
     GatherArgs g;
     g.rep = c->d_rep;
     g.slice_rep = c->d_slice_rep;
-    g.perm = c->d_perm[nxt];
+    g.perm = c->d_perm[dst];
     g.src_of_slot = c->d_src_of_slot;
     g.pos = pos;
     g.vel = vel;
     g.charges = c->cfg.charges;
-    g.xs_old = c->cur_xs();
-    g.vs_old = c->cur_vs();
+    g.xs_old = in_place ? c->d_xs[nxt] : c->cur_xs();
+    g.vs_old = in_place ? c->d_vs[nxt] : c->cur_vs();
     g.n = c->n;
     g.n_src = b.n_src;
     g.n_slots = c->n_slots;
     g.flags = c->d_flags;
-    g.xs = c->d_xs[nxt];
-    g.vs = c->d_vs[nxt];
+    g.xs = c->d_xs[dst];
+    g.vs = c->d_vs[dst];
     g.xb = c->d_xb;
     g.slot_of_id = c->d_slot_of_id;
     g.img_delta = c->track_images ? c->d_img_delta : nullptr;
+    g.gate = gate;
     RBL_TRY(timed(c, kKBin, [&] {
         if (with_vel)
             k_gather<SRC, true><<<grid_for(c->n_slots), kBlock, 0, c->ls>>>(g);
         else
             k_gather<SRC, false><<<grid_for(c->n_slots), kBlock, 0, c->ls>>>(g);
     }));
-    c->cur = nxt;
+    c->cur = dst;
     return RBL_OK;
 }
 
@@ -505,6 +534,22 @@ BuildArgs build_args(rbl_ctx* c)
     a.shell_len = c->d_len[1];
     a.full_len = c->d_len[2];
     a.flags = c->d_flags;
+    a.gate = nullptr;
+    a.mark = nullptr;
+    a.mark_step = 0;
+    a.mark_step_dev = nullptr;
+    return a;
+}
+
+// Build arguments of a list build of the MD loop: gated by `gate`, and
+// recording its step (*step_dev + step, or step) and count on the device.
+BuildArgs loop_build_args(rbl_ctx* c, uint64_t step, const uint64_t* step_dev, const uint64_t* gate)
+{
+    BuildArgs a = build_args(c);
+    a.gate = gate;
+    a.mark = c->d_step + 2;
+    a.mark_step = step;
+    a.mark_step_dev = step_dev;
     return a;
 }
 
@@ -596,10 +641,11 @@ rbl_status ensure_batch(rbl_ctx* c, int K, int P);
 // Queues the fused build (core rows, shell counts, batches of K force
 // evaluations from step0, or from *step_dev + step0 when step_dev is set).
 rbl_status launch_fused(rbl_ctx* c, int P, uint64_t seed, uint64_t step0, int K,
-                        const uint64_t* step_dev, bool draw_only = false)
+                        const uint64_t* step_dev, bool draw_only = false, bool loop = false,
+                        const uint64_t* gate = nullptr)
 {
     FusedArgs fa;
-    fa.b = build_args(c);
+    fa.b = loop ? loop_build_args(c, step0, step_dev, gate) : build_args(c);
     fa.core_reach = c->r_s + c->cfg.skin;
     fa.draw_only = draw_only ? 1 : 0;
     if (c->stencil) fa.b.shell_len = c->d_nI;
@@ -745,6 +791,8 @@ ForceArgs force_args(rbl_ctx* c, int P, uint64_t seed, uint64_t step, bool full)
     a.P = P;
     a.f = c->d_f;
     a.partial = c->d_partial;
+    a.bstep = nullptr;
+    a.gate_clear = nullptr;
     return a;
 }
 
@@ -859,12 +907,19 @@ rbl_status reduce(rbl_ctx* c)
 
 // RBL force at the current sorted positions (raw; per-replica sums reduced).
 // batch_rel >= 0 selects pre-drawn batches of that relative step.
+// gated: a step of a run with rebuilds on displacement (the force resets the
+// gate; pre-drawn batches are addressed through the device's build step).
 rbl_status rbl_force_sorted(rbl_ctx* c, int P, uint64_t seed, uint64_t step, int batch_rel,
-                            bool energy, const uint64_t* step_dev = nullptr)
+                            bool energy, const uint64_t* step_dev = nullptr, bool gated = false)
 {
     ForceArgs a = force_args(c, P, seed, step, false);
     a.step_dev = step_dev;
-    if (batch_rel >= 0) {
+    if (gated) a.gate_clear = c->d_step + 4;
+    if (batch_rel >= 0 && gated) {
+        a.batch = c->d_batch;
+        a.bstep = c->d_step + 2;
+        RBL_TRY(timed(c, kKForceRbl, [&] { launch_force<kShellPredraw>(c, a, energy); }, true));
+    } else if (batch_rel >= 0) {
         a.batch = c->d_batch + (size_t)batch_rel * P * c->n_slots;
         RBL_TRY(timed(c, kKForceRbl, [&] { launch_force<kShellPredraw>(c, a, energy); }, true));
     } else {
@@ -873,9 +928,10 @@ rbl_status rbl_force_sorted(rbl_ctx* c, int P, uint64_t seed, uint64_t step, int
     return reduce(c);
 }
 
-rbl_status full_force_sorted(rbl_ctx* c, bool energy)
+rbl_status full_force_sorted(rbl_ctx* c, bool energy, bool gated = false)
 {
     ForceArgs a = force_args(c, 0, 0, 0, true);
+    if (gated) a.gate_clear = c->d_step + 4;
     RBL_TRY(timed(c, kKForceFull, [&] { launch_force<kShellNone>(c, a, energy); }, true));
     return reduce(c);
 }
@@ -917,7 +973,7 @@ rbl_status emit_ev(rbl_ctx* c, double* ev)
 // *step_dev + step).
 rbl_status integrate(rbl_ctx* c, int mode, double dt, bool momentum_fix, uint64_t seed = 0,
                      uint64_t step = 0, const uint64_t* step_dev = nullptr,
-                     const uint64_t* pending = nullptr)
+                     const uint64_t* pending = nullptr, int64_t gate_life = 0)
 {
     IntArgs a;
     a.langevin = c->gamma > 0.0 ? 1 : 0;
@@ -928,6 +984,10 @@ rbl_status integrate(rbl_ctx* c, int mode, double dt, bool momentum_fix, uint64_
     a.step = step;
     a.step_dev = step_dev;
     a.pending = pending;
+    // gate_life > 0: rebuilds on displacement, lifetimes of at most gate_life steps
+    a.gate = gate_life > 0 ? c->d_step + 4 : nullptr;
+    a.bstep = c->d_step + 2;
+    a.max_life = gate_life;
     a.rep = c->d_rep;
     a.slice_rep = c->d_slice_rep;
     a.rep_sum = c->d_rep_sum;
@@ -970,6 +1030,17 @@ __global__ void k_set_block(uint64_t* p, uint64_t step, uint64_t pending)
     }
 }
 
+// Start of a run: build count and rebuild gate cleared, and (entry build at
+// `step`, set_build) the step of the last build.
+__global__ void k_run_marks(uint64_t* p, uint64_t step, int set_build)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        if (set_build) p[2] = step;
+        p[3] = 0;
+        p[4] = 0;
+    }
+}
+
 void drop_graphs(rbl_ctx* c)
 {
     for (int q = 0; q < 2; ++q)
@@ -986,6 +1057,7 @@ struct StepParams {
     int64_t K;
     double dt;
     bool full, pre, fix;
+    bool check;  // lists rebuilt on displacement (decided on the device)
 };
 
 template <typename T>
@@ -1005,6 +1077,7 @@ std::vector<unsigned char> block_signature(const rbl_ctx* c, const StepParams& s
     sig_put(v, (int)sp.full);
     sig_put(v, (int)sp.pre);
     sig_put(v, (int)sp.fix);
+    sig_put(v, (int)sp.check);
     sig_put(v, c->r_s);
     sig_put(v, c->r_c);
     sig_put(v, c->n_cells);
@@ -1025,15 +1098,48 @@ std::vector<unsigned char> block_signature(const rbl_ctx* c, const StepParams& s
     return v;
 }
 
-// Queues one list lifetime as steps s_b+1 .. s_b+K, where s_b is a
-// multiple of K whose lists and batches are already built: K kick/drift +
-// force + reduction steps, the last one preceded by the rebuild at s_b+K
-// (binning, lists, and the batches of s_b+K .. s_b+2K-1).  Step-dependent
-// values come from the device counter d_step[0] = s_b, so the same queue
-// serves every lifetime; d_step[1] says whether the velocities await the
-// closing half-kick of step s_b.
+// One step of a run whose lists are rebuilt on displacement: kick and drift
+// (setting the rebuild gate when some particle has moved more than skin/2
+// since the last build, or the lifetime reached K steps), the gated binning
+// and list build (lists, and the batches of the K steps from this one), the
+// force (which resets the gate) and its reduction.  The step is
+// *step_dev + step, or step without a device counter.
+rbl_status queue_gated_step(rbl_ctx* c, const StepParams& sp, int mode, uint64_t step,
+                            const uint64_t* step_dev, const uint64_t* pending, bool energy)
+{
+    const uint64_t* gate = c->d_step + 4;
+    const int mask = sp.full ? RBL_LIST_FULL : (RBL_LIST_CORE | RBL_LIST_SHELL);
+    RBL_TRY(integrate(c, mode, sp.dt, sp.fix, sp.seed, step, step_dev, pending, sp.K));
+    RBL_TRY(bin_particles<kSrcSorted>(c, nullptr, nullptr, true, gate));
+    if (sp.pre) {
+        RBL_TRY(launch_fused(c, sp.P, sp.seed, step, (int)sp.K, step_dev, false, true, gate));
+    } else {
+        BuildArgs a = loop_build_args(c, step, step_dev, gate);
+        RBL_TRY(timed(c, kKBuild, [&] { launch_build<false>(c, a, mask); }));
+    }
+    if (sp.full) return full_force_sorted(c, energy, true);
+    return rbl_force_sorted(c, sp.P, sp.seed, step, sp.pre ? 0 : -1, energy, step_dev, true);
+}
+
+// Steps of a captured block of gated steps (rebuilds on displacement): any
+// length serves, since every gated step decides its own rebuild.
+constexpr int64_t kGatedBlock = 10;
+
+// Queues steps s_b+1 .. s_b+K for replay.  Step-dependent values come from
+// the device counter d_step[0] = s_b, so the same queue serves every block;
+// d_step[1] says whether the velocities await the closing half-kick of step
+// s_b.  Fixed lifetimes: s_b is a multiple of K whose lists and batches are
+// built, and the block ends with the rebuild at s_b+K (binning, lists, and
+// the batches of s_b+K .. s_b+2K-1).  Rebuilds on displacement:
+// kGatedBlock gated steps.
 rbl_status queue_block(rbl_ctx* c, const StepParams& sp)
 {
+    if (sp.check) {
+        for (int64_t r = 1; r <= kGatedBlock; ++r)
+            RBL_TRY(queue_gated_step(c, sp, kIntMid, (uint64_t)r, c->d_step, r == 1 ? c->d_step + 1 : nullptr,
+                                     false));
+        return RBL_OK;
+    }
     const int mask = sp.full ? RBL_LIST_FULL : (RBL_LIST_CORE | RBL_LIST_SHELL);
     for (int64_t r = 1; r <= sp.K; ++r) {
         RBL_TRY(integrate(c, kIntMid, sp.dt, sp.fix, sp.seed, (uint64_t)r, c->d_step,
@@ -1041,9 +1147,9 @@ rbl_status queue_block(rbl_ctx* c, const StepParams& sp)
         if (r == sp.K) {
             RBL_TRY(bin_particles<kSrcSorted>(c, nullptr, nullptr, true));
             if (sp.pre) {
-                RBL_TRY(launch_fused(c, sp.P, sp.seed, (uint64_t)sp.K, (int)sp.K, c->d_step));
+                RBL_TRY(launch_fused(c, sp.P, sp.seed, (uint64_t)sp.K, (int)sp.K, c->d_step, false, true));
             } else {
-                BuildArgs a = build_args(c);
+                BuildArgs a = loop_build_args(c, (uint64_t)sp.K, c->d_step, nullptr);
                 RBL_TRY(timed(c, kKBuild, [&] { launch_build<false>(c, a, mask); }));
             }
         }
@@ -1090,7 +1196,8 @@ rbl_status run_block(rbl_ctx* c, int64_t s_b, bool pending, const StepParams& sp
     k_set_block<<<1, 64, 0, c->ls>>>(c->d_step, (uint64_t)s_b, pending ? 1u : 0u);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipGraphLaunch(c->gexec[parity], c->ls));
-    c->cur = 1 - parity;
+    // a gated block copies each rebuild back into the same buffer set
+    if (!sp.check) c->cur = 1 - parity;
     return RBL_OK;
 }
 
@@ -1183,6 +1290,7 @@ rbl_status md_run(rbl_ctx* c, const double* pos_in, const double* vel_in, double
     sp.full = full;
     sp.fix = !full && c->cfg.momentum_fix;
     sp.pre = !full && ((c->cfg.predraw && c->fused_ok) || c->stencil);
+    sp.check = c->cfg.rebuild_check != 0;
     const int mask = full ? RBL_LIST_FULL : (RBL_LIST_CORE | RBL_LIST_SHELL);
     const bool use_graph = c->cfg.graphs && !c->profiling && c->gs;
     LaunchStreamGuard guard{c};
@@ -1194,6 +1302,8 @@ rbl_status md_run(rbl_ctx* c, const double* pos_in, const double* vel_in, double
     const int64_t resume_build = c->run.build_step;
     c->run.valid = false;
     RBL_TRY(clear_flags(c));
+    k_run_marks<<<1, 64, 0, c->ls>>>(c->d_step, 0, 0);
+    HIP_TRY(hipGetLastError());
     // wraps of this run's builds are counted apart and added to the
     // trajectory's image counters only when the run completes
     if (!c->d_img) {
@@ -1225,16 +1335,18 @@ rbl_status md_run(rbl_ctx* c, const double* pos_in, const double* vel_in, double
         build_step = s;
         if (sp.pre) {
             // batches for every force evaluation of the list lifetime, also
-            // those past this run's end (a continued run uses them)
-            const int64_t cnt = (s / K + 1) * K - s;
+            // those past this run's end (a continued run uses them); a
+            // lifetime ends at the next multiple of K, or with rebuilds on
+            // displacement at most K steps on
+            const int64_t cnt = sp.check ? K : (s / K + 1) * K - s;
             RBL_TRY(prepare_fused(c, P, (int)K));
-            RBL_TRY(launch_fused(c, P, seed, (uint64_t)s, (int)cnt, nullptr));
+            RBL_TRY(launch_fused(c, P, seed, (uint64_t)s, (int)cnt, nullptr, false, true));
             set_draw(c, s, (int)cnt, P);
             c->built_mask = RBL_LIST_CORE;
             c->shell_counts = !c->stencil;
         } else {
             RBL_TRY(prepare_lists(c, mask));
-            BuildArgs a = build_args(c);
+            BuildArgs a = loop_build_args(c, (uint64_t)s, nullptr, nullptr);
             RBL_TRY(timed(c, kKBuild, [&] { launch_build<false>(c, a, mask); }));
             set_draw(c, 0, 0, 0);
             c->built_mask = mask;
@@ -1256,7 +1368,25 @@ rbl_status md_run(rbl_ctx* c, const double* pos_in, const double* vel_in, double
     // pending: the velocities await the closing half-kick of the last force
     bool pending = false;
     int64_t it = 1;
-    while (it <= nsteps) {
+    while (sp.check && it <= nsteps) {
+        // rebuilds decided on the device: blocks of kGatedBlock gated steps
+        // (not the run's last block when its energy is asked for)
+        const int64_t s = step0 + it;
+        const int64_t G = kGatedBlock;
+        if (use_graph && it + G - 1 <= nsteps && !(ev && it + G - 1 == nsteps)) {
+            RBL_TRY(run_block(c, s - 1, pending, sp));
+            it += G;
+        } else {
+            RBL_TRY(queue_gated_step(c, sp, pending ? kIntMid : kIntFirst, (uint64_t)s, nullptr, nullptr,
+                                     ev != nullptr && it == nsteps));
+            ++it;
+        }
+        pending = true;
+        c->built = true;
+        c->built_mask = sp.full ? RBL_LIST_FULL : (sp.pre ? RBL_LIST_CORE : mask);
+        c->shell_counts = !sp.full && !c->stencil;
+    }
+    while (!sp.check && it <= nsteps) {
         const int64_t s = step0 + it;
         const int64_t s_b = s - 1;
         // A whole list lifetime s_b+1 .. s_b+K whose lists were built at s_b
@@ -1281,7 +1411,14 @@ rbl_status md_run(rbl_ctx* c, const double* pos_in, const double* vel_in, double
         ++it;
     }
     if (pending) RBL_TRY(integrate(c, kIntLast, dt, sp.fix));
+    HIP_TRY(hipMemcpyAsync(c->h_marks, c->d_step + 2, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, c->ls));
     RBL_TRY(read_flags(c));
+    c->run.builds = (int64_t)c->h_marks[1];
+    if (sp.check) {
+        // the step of the last build is known on the device only
+        build_step = (int64_t)c->h_marks[0];
+        if (sp.pre) set_draw(c, build_step, (int)K, P);
+    }
     if (c->h_flags[kFlagStencil]) {
         // a stencil held more candidates than the fused kernel's LDS lists:
         // the run is repeated on explicit core and shell rows
@@ -1393,6 +1530,7 @@ void rbl_config_init(rbl_config* cfg, int64_t n)
     cfg->replica_offsets = nullptr;
     cfg->charges = nullptr;
     cfg->shell_source = RBL_SHELL_LIST;
+    cfg->rebuild_check = 0;
     cfg->reserved = 0;
 }
 
@@ -1555,7 +1693,7 @@ rbl_status rbl_create(const rbl_config* cfg, void* hip_stream, rbl_ctx** out)
     CR(dalloc(&c->d_part2, (size_t)5 * c->red_blocks * c->R));
     CR(dalloc(&c->d_rep_sum, 8 * c->R));
     CR(dalloc(&c->d_flags, kNumFlags));
-    CR(dalloc(&c->d_step, 2));
+    CR(dalloc(&c->d_step, 8));
     if (hipStreamCreateWithFlags(&c->gs, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) != hipSuccess)
@@ -1705,12 +1843,15 @@ rbl_status rbl_continue(rbl_ctx* c, double* pos, double* vel, double* force, int
     return fail(RBL_E_CAPACITY, "neighbour rows kept overflowing their capacity");
 }
 
-rbl_status rbl_last_run(rbl_ctx* c, int32_t* attempts, int64_t* end_step, int32_t* resumable)
+rbl_status rbl_last_run(rbl_ctx* c, int32_t* attempts, int64_t* end_step, int32_t* resumable, int64_t* builds,
+                        int64_t* build_step)
 {
     if (!c) return fail(RBL_E_ARG, "NULL context");
     if (attempts) *attempts = c->run.attempts;
     if (end_step) *end_step = c->run.end_step;
     if (resumable) *resumable = c->run.valid ? 1 : 0;
+    if (builds) *builds = c->run.builds;
+    if (build_step) *build_step = c->run.build_step;
     return RBL_OK;
 }
 

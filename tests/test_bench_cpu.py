@@ -96,11 +96,12 @@ def test_msd_slope_of_a_line():
 
 def test_driver_command_plans_whole_lifetimes():
     """The driver's command line (any step counts) is accepted; the counts
-    become whole 10-step list lifetimes, the warm-up at least one."""
-    assert bench.plan(bench.parse(["--gpus", "1", "--steps", "20", "--warmup", "5"])) == (10, 20)
-    assert bench.plan(bench.parse(["--steps", "25", "--warmup", "0"])) == (10, 30)
-    assert bench.plan(bench.parse(["--steps", "1", "--warmup", "11"])) == (20, 10)
-    assert bench.plan(bench.parse([])) == (100, 1000)
+    become whole 10-step blocks, the warm-up at least one, a timed run at
+    least 200 steps."""
+    assert bench.plan(bench.parse(["--gpus", "1", "--steps", "20", "--warmup", "5"])) == (10, 200)
+    assert bench.plan(bench.parse(["--steps", "205", "--warmup", "0"])) == (10, 210)
+    assert bench.plan(bench.parse(["--steps", "1", "--warmup", "11"])) == (20, 200)
+    assert bench.plan(bench.parse([])) == (100, 200)
 
 
 @pytest.mark.parametrize("argv", [["--steps", "0"], ["--warmup", "-1"], ["--repeats", "0"]])

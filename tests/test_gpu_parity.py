@@ -315,7 +315,9 @@ def test_continue_equals_one_run(chunks, graphs, use_full):
             lastc = k == len(chunks) - 2
             ctx.cont(c, pos=x if lastc else None, vel=v if lastc else None, force=f if lastc else None)
         info = ctx.last_run()
-    assert info == {"attempts": 1, "end_step": 40, "resumable": True}
+    assert (info["attempts"], info["end_step"], info["resumable"]) == (1, 40, True)
+    # fixed lifetimes: the run's last build is the one at step 40
+    assert info["build_step"] == 40
     for a, b in zip((host(x), host(v), host(f)), ref):
         assert np.array_equal(a, b)
 

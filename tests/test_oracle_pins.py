@@ -868,3 +868,68 @@ def test_tail_corrections_equal_the_mean_field_integrals():
                   epsabs=0, epsrel=1e-13)[0]
         assert ut == pytest.approx(2.0 * math.pi * rho * iu, rel=1e-10)
         assert pt == pytest.approx(-2.0 * math.pi / 3.0 * rho * rho * ip, rel=1e-10)
+
+
+# ------------------------------------------ rebuilds on displacement ---
+
+def _free_flight(speeds, box=20.0):
+    """Particles far apart (no pair within the cut-off + skin ever), moving
+    along x at the given speeds: no forces, exact straight lines."""
+    n = len(speeds)
+    pos = np.zeros((3, n))
+    for k in range(n):
+        pos[:, k] = [1.0 + 9.0 * (k % 2), 2.0 + 9.0 * ((k // 2) % 2), 3.0 + 9.0 * (k // 4)]
+    vel = np.zeros((3, n))
+    vel[0] = speeds
+    return pos, vel, np.array([box, box, box])
+
+
+@pytest.mark.parametrize("speeds,K,want", [
+    # 1.1 x 0.005 per step: 27 steps move 0.1485 < 0.15 = skin/2, 28 move 0.154
+    ([1.1, 0.0], 100, [0, 28, 56, 84]),
+    # the longest lifetime comes first
+    ([1.1, 0.0], 25, [0, 25, 50, 75, 100]),
+    # the fastest particle decides: 2.0 x 0.005 x 16 = 0.16 > 0.15 >= 0.15 after 15
+    ([0.3, 2.0, 1.1, 0.0], 100, [0, 16, 32, 48, 64, 80, 96]),
+    # nothing moves: only the lifetime
+    ([0.0, 0.0], 40, [0, 40, 80]),
+])
+def test_displacement_rebuild_schedule(speeds, K, want):
+    """With rebuilds on displacement the lists are rebuilt exactly at the
+    first step at which some particle is more than skin/2 = 0.15 from where
+    the last build left it (or K steps after that build), worked out by hand
+    for particles in free flight."""
+    pos, vel, box = _free_flight(speeds)
+    builds = []
+    x, v, _, _ = oracle.md_run(pos, vel, box, RS, RC, SKIN, 0.005, 100, p=10, seed=1, K=K, check=True,
+                               builds=builds)
+    assert builds == want
+    assert np.allclose(v, vel)
+    # fixed lifetimes ignore the displacement
+    fixed = []
+    oracle.md_run(pos, vel, box, RS, RC, SKIN, 0.005, 100, p=10, seed=1, K=K, builds=fixed)
+    assert fixed == list(range(0, 101, K))
+
+
+def test_displacement_rebuilds_keep_the_full_force():
+    """Lists rebuilt on displacement hold every pair within the cut-off at
+    every step: a hot fluid (T = 3) run with the displacement criterion
+    follows a run that rebuilds before every step to rounding (wraps and row
+    order differ, so not bit for bit), while the same run with a fixed
+    40-step lifetime drops pairs and leaves it by orders of magnitude more."""
+    st = inputs.lj_fluid(600, 0.8, 3.0, seed=17)
+    ref = oracle.md_run(st.pos, st.vel, st.box, RS, RC, SKIN, 0.005, 40, K=1, use_full=True)
+    builds = []
+    chk = oracle.md_run(st.pos, st.vel, st.box, RS, RC, SKIN, 0.005, 40, K=40, use_full=True, check=True,
+                        builds=builds)
+    stale = oracle.md_run(st.pos, st.vel, st.box, RS, RC, SKIN, 0.005, 40, K=40, use_full=True)
+
+    def dx(a, b):
+        d = a - b
+        return float(np.abs(d - st.box[:, None] * np.rint(d / st.box[:, None])).max())
+    assert dx(chk[0], ref[0]) < 1e-12
+    assert np.abs(chk[1] - ref[1]).max() < 1e-11
+    assert np.abs(chk[2] - ref[2]).max() < 1e-9
+    assert dx(stale[0], ref[0]) > 1e-5
+    assert np.abs(stale[2] - ref[2]).max() > 1e-2
+    assert 2 < len(builds) < 41, builds
