@@ -167,6 +167,27 @@ rbl_status rbl_build(rbl_ctx* ctx, const double* pos, const double* box,
 rbl_status rbl_forces(rbl_ctx* ctx, int P, uint64_t seed, uint64_t step,
                       const double* pos, double* force, double* ev);
 
+/*
+ * rbl_forces for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, results and errors as rbl_forces (bit-identical forces and
+ * [U, W]); it calls no hipMalloc, hipFree or other allocating routine.  Its
+ * scratch (per-wavefront force partials, reduction partials, per-replica
+ * sums, and for the stencil population or P > 32 the drawn batches and
+ * population sizes) lives in one static device array of 64 MiB per device
+ * (kept until the process ends), whose address rbl_create takes on its
+ * device.  Nothing in it needs clearing between calls: every call writes
+ * what it reads.  Limit: 160 n_slots/64 + 40 (red_blocks + 1) n_replicas
+ * bytes, plus 4 P n_slots (+ 4 n_slots for the stencil population) when
+ * batches are drawn, must fit in 64 MiB (n_slots: see rbl_info); otherwise
+ * RBL_E_CAPACITY and nothing is queued.  All calls on one device share the
+ * array, so calls that overlap on one device (other streams, other host
+ * threads) race: order them on one stream.  The context's own stored
+ * batches are left as they were.
+ */
+rbl_status rbl_forces_noalloc(rbl_ctx* ctx, int P, uint64_t seed, uint64_t step,
+                              const double* pos, double* force, double* ev);
+
 /* Direct-truncation force at `pos` from the full list (needs
  * RBL_LIST_FULL in cfg.lists): F_i = sum_{j, r < r_c} f_ij.  No mean-force
  * subtraction.  Same pointer conventions as rbl_forces. */

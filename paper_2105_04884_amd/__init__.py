@@ -166,6 +166,16 @@ class Context:
                                     _dev_ptr(force, (3, self.n), "force"), _dev_ptr(ev)))
         return (force, ev) if want_ev else force
 
+    def forces_noalloc(self, P: int, seed: int, step: int, pos, force, ev=None):
+        """rbl_forces_noalloc: the RBL force into the given ``force`` (and
+        ``ev``, 2 doubles per replica, if given) with no device allocation
+        (the caller supplies every output)."""
+        _check(self._lib.rbl_forces_noalloc(self._h, int(P), int(seed), int(step),
+                                            _dev_ptr(pos, (3, self.n), "pos"),
+                                            _dev_ptr(force, (3, self.n), "force"),
+                                            _dev_ptr(ev, (2 * self.n_replicas,), "ev")))
+        return force
+
     def full_forces(self, pos, force=None, want_ev: bool = False):
         torch = _torch()
         if force is None:

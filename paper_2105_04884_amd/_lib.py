@@ -61,7 +61,8 @@ class Config(C.Structure):
 
 _lib = None
 _names = [
-    "rbl_config_init", "rbl_create", "rbl_destroy", "rbl_build", "rbl_forces", "rbl_full_forces",
+    "rbl_config_init", "rbl_create", "rbl_destroy", "rbl_build", "rbl_forces", "rbl_forces_noalloc",
+    "rbl_full_forces",
     "rbl_step", "rbl_continue", "rbl_last_run", "rbl_row_counts", "rbl_export_lists", "rbl_export_batches", "rbl_export_drawn_batches",
     "rbl_export_binning",
     "rbl_sync", "rbl_set_profiling", "rbl_kernel_stats", "rbl_info", "rbl_tuning", "rbl_launch_modes",
@@ -94,6 +95,7 @@ def load(path: str = LIB_PATH):
         "rbl_destroy": (i32, [vp]),
         "rbl_build": (i32, [vp, vp, pd, d, d]),
         "rbl_forces": (i32, [vp, i32, u64, u64, vp, vp, vp]),
+        "rbl_forces_noalloc": (i32, [vp, i32, u64, u64, vp, vp, vp]),
         "rbl_full_forces": (i32, [vp, vp, vp, vp]),
         "rbl_step": (i32, [vp, vp, vp, vp, i64, d, i32, u64, i64, i32, i32, vp]),
         "rbl_continue": (i32, [vp, vp, vp, vp, i64, vp]),

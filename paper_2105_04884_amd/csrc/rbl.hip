@@ -13,6 +13,7 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -74,6 +75,37 @@ void dfree(T*& p)
 {
     if (p) (void)hipFree(p);
     p = nullptr;
+}
+
+// Device memory of rbl_forces_noalloc: one static array per device (each GPU
+// holds its own copy for the life of the process).  Host code never passes
+// the array's name to a kernel: its device address is taken once per device
+// with hipGetSymbolAddress (rbl_create, with that device current) and kept
+// in scratch_dev[device].  Calls on one device share the array.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+constexpr int kScratchDevices = 64;
+std::mutex scratch_mu;
+void* scratch_dev[kScratchDevices] = {};
+bool scratch_tried[kScratchDevices] = {};
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+// Address of the scratch array on the current device (null if unavailable).
+void* scratch_setup(int dev)
+{
+    if (dev < 0 || dev >= kScratchDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_tried[dev]) {
+        scratch_tried[dev] = true;
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) == hipSuccess) scratch_dev[dev] = p;
+        else (void)hipGetLastError();
+    }
+    return scratch_dev[dev];
 }
 
 }  // namespace
@@ -153,6 +185,7 @@ struct rbl_ctx {
     int lpp_rbl = 4, lpp_full = 4;  // lanes per particle of the force kernels
     bool persist[2] = {false, false};  // persistent force grid (RBL, full list)
     double persist_us[2][2] = {{0, 0}, {0, 0}};  // per launch: one block per tile, persistent
+    int device = 0;                 // device the context was created on
     int n_cu = 256;                 // compute units of the device
     int64_t lds_per_cu = 160 * 1024;  // bytes of LDS per compute unit
     int64_t fused_static_lds = -1;    // static LDS of the fused build (queried once)
@@ -1643,6 +1676,9 @@ rbl_status rbl_create(const rbl_config* cfg, void* hip_stream, rbl_ctx** out)
         if (hipGetDevice(&dev) == hipSuccess &&
             hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
             c->n_cu = ncu;
+        c->device = dev;
+        // the allocation-free force call's array on this device
+        (void)scratch_setup(dev);
         int lds = 0;
         if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) == hipSuccess &&
             lds > 0)
@@ -1737,8 +1773,11 @@ rbl_status rbl_build(rbl_ctx* c, const double* pos, const double* box, double r_
     return RBL_OK;
 }
 
-rbl_status rbl_forces(rbl_ctx* c, int P, uint64_t seed, uint64_t step, const double* pos,
-                      double* force, double* ev)
+}  // extern "C"
+
+namespace {
+
+rbl_status forces_check(rbl_ctx* c, int P, const double* pos, const double* force)
 {
     if (!c || !pos || !force) return fail(RBL_E_ARG, "NULL argument");
     RBL_TRY(check_p(P));
@@ -1747,13 +1786,21 @@ rbl_status rbl_forces(rbl_ctx* c, int P, uint64_t seed, uint64_t step, const dou
     if ((c->built_mask & need) != need)
         return fail(RBL_E_STATE, c->stencil ? "the last build has no core list"
                                             : "the last build has no core and shell lists");
+    return RBL_OK;
+}
+
+// The RBL force of rbl_forces (arguments checked).  `record`: the batches
+// drawn here are the context's stored ones (rbl_export_drawn_batches).
+rbl_status forces_call(rbl_ctx* c, int P, uint64_t seed, uint64_t step, const double* pos, double* force,
+                       double* ev, bool record)
+{
     c->run.valid = false;
     if (c->stencil) {
         // batches from the stencil cells of the build's binning
         RBL_TRY(ensure_batch(c, 1, P));
         if (!c->d_nI) RBL_TRY(dalloc(&c->d_nI, c->n_slots));
         RBL_TRY(launch_fused(c, P, seed, step, 1, nullptr, true));
-        set_draw(c, (int64_t)step, 1, P);
+        if (record) set_draw(c, (int64_t)step, 1, P);
     }
     IoArgs io = io_args(c, c->cfg.momentum_fix != 0);
     io.pos_in = pos;
@@ -1765,13 +1812,72 @@ rbl_status rbl_forces(rbl_ctx* c, int P, uint64_t seed, uint64_t step, const dou
         RBL_TRY(rbl_force_sorted(c, P, seed, step, -1, ev != nullptr));
     } else {
         RBL_TRY(predraw(c, P, seed, step, 1));
-        set_draw(c, (int64_t)step, 1, P);
+        if (record) set_draw(c, (int64_t)step, 1, P);
         RBL_TRY(rbl_force_sorted(c, P, seed, step, 0, ev != nullptr));
     }
     io.f_out = force;
     k_scatter_out<<<grid_for(c->n_slots), kBlock, 0, c->ls>>>(io);
     HIP_TRY(hipGetLastError());
     return emit_ev(c, ev);
+}
+
+}  // namespace
+
+extern "C" {
+
+rbl_status rbl_forces(rbl_ctx* c, int P, uint64_t seed, uint64_t step, const double* pos,
+                      double* force, double* ev)
+{
+    RBL_TRY(forces_check(c, P, pos, force));
+    return forces_call(c, P, seed, step, pos, force, ev, true);
+}
+
+rbl_status rbl_forces_noalloc(rbl_ctx* c, int P, uint64_t seed, uint64_t step, const double* pos,
+                              double* force, double* ev)
+{
+    RBL_TRY(forces_check(c, P, pos, force));
+    unsigned char* const base = static_cast<unsigned char*>(scratch_dev[c->device]);
+    if (!base) return fail(RBL_E_STATE, "the scratch array's device address is unavailable on this device");
+    // carve the call's buffers out of the array, 256-byte aligned
+    const bool draws = c->stencil || P > 32;
+    size_t off = 0;
+    auto carve = [&](size_t bytes) {
+        const size_t at = off;
+        off += (bytes + 255) / 256 * 256;
+        return at;
+    };
+    const size_t o_partial = carve(sizeof(double) * 5 * 4 * (size_t)c->n_slices);
+    const size_t o_part2 = carve(sizeof(double) * 5 * (size_t)c->red_blocks * c->R);
+    const size_t o_rep = carve(sizeof(double) * 8 * (size_t)c->R);
+    const size_t o_batch = draws ? carve(sizeof(int) * (size_t)P * c->n_slots) : 0;
+    const size_t o_ni = c->stencil ? carve(sizeof(int) * (size_t)c->n_slots) : 0;
+    if (off > kScratchBytes)
+        return fail(RBL_E_CAPACITY, "rbl_forces_noalloc needs " + std::to_string(off) + " bytes of scratch for " +
+                                        std::to_string(c->n_slots) + " slots at P = " + std::to_string(P) +
+                                        ", above its " + std::to_string(kScratchBytes) + "-byte array");
+    // the context's own buffers stand aside for the call
+    struct Swap {
+        rbl_ctx* c;
+        double *partial, *part2, *rep_sum;
+        int *batch, *nI;
+        size_t batch_alloc;
+        ~Swap()
+        {
+            c->d_partial = partial;
+            c->d_part2 = part2;
+            c->d_rep_sum = rep_sum;
+            c->d_batch = batch;
+            c->d_nI = nI;
+            c->batch_alloc = batch_alloc;
+        }
+    } swap{c, c->d_partial, c->d_part2, c->d_rep_sum, c->d_batch, c->d_nI, c->batch_alloc};
+    c->d_partial = reinterpret_cast<double*>(base + o_partial);
+    c->d_part2 = reinterpret_cast<double*>(base + o_part2);
+    c->d_rep_sum = reinterpret_cast<double*>(base + o_rep);
+    c->d_batch = draws ? reinterpret_cast<int*>(base + o_batch) : nullptr;
+    c->batch_alloc = draws ? (size_t)P * c->n_slots : 0;
+    c->d_nI = c->stencil ? reinterpret_cast<int*>(base + o_ni) : nullptr;
+    return forces_call(c, P, seed, step, pos, force, ev, false);
 }
 
 rbl_status rbl_full_forces(rbl_ctx* c, const double* pos, double* force, double* ev)
