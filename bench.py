@@ -94,8 +94,7 @@ def parse(argv=None):
                     help="further workloads reported beside the headline: comma list of "
                          "'ensemble' (512 replicas), 'large' (N = 2^24), 'slab' (charged "
                          "slab, N = 2M, LJ + erfc), 'table1' (the Sec. III coexistence "
-                         "study) and 'eos' (its equation of state; both minutes of GPU time "
-                         "and not in the default), or 'none'")
+                         "study: minutes of GPU time, not in the default), or 'none'")
     ap.add_argument("--summarize", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
                     help="instead of running: write the profiles/ summaries from the output "
                          "folders of a rocprofv3 --kernel-trace --stats run and two --pmc runs "
@@ -621,67 +620,6 @@ def run_table1(torch, equil=200_000, prod=100_000, every=1000, runs=10):
     return out
 
 
-def run_eos(torch, equil=50_000, prod=50_000, every=500, densities=(0.1, 0.2, 0.4, 0.6, 0.8),
-            copies=2):
-    """Equation of state of Sec. III (its energy and pressure figures):
-    potential energy per particle and pressure, both with tail corrections,
-    of N = 2000 LJ fluids against density (Langevin, friction 1, dt =
-    0.002).  At T = 2.0 and 0.9: direct truncation at r_c = 6 and 3, and RBL
-    with r_c = 6 and a core of 2 or 3 at P = 20.  At T = 1.5: direct
-    truncation at r_c = 6, 3 and 2^(1/6), and RBL with r_c = 3, a core of
-    2^(1/6) and P = 10.  Every density runs as `copies` replicas of one
-    context per (setting, T); values are averaged over the production
-    samples and the copies."""
-    from paper_2105_04884_amd import Context, inputs
-    n1, gamma, dt = 2000, 1.0, 0.002
-    rmin = 2.0 ** (1.0 / 6.0)
-    studies = []
-    for T in (2.0, 0.9):
-        studies.append((T, [("DT r_c=6", True, 1.0, 6.0, 20), ("DT r_c=3", True, 1.0, 3.0, 20),
-                            ("RBL r_s=2 r_c=6 P=20", False, 2.0, 6.0, 20),
-                            ("RBL r_s=3 r_c=6 P=20", False, 3.0, 6.0, 20)]))
-    studies.append((1.5, [("DT r_c=6", True, 1.0, 6.0, 10), ("DT r_c=3", True, 1.0, 3.0, 10),
-                          ("DT r_c=2^(1/6)", True, 0.5, rmin, 10),
-                          ("RBL r_s=2^(1/6) r_c=3 P=10", False, rmin, 3.0, 10)]))
-    out = {"workload": f"Sec. III equation of state: N={n1}, densities {list(densities)}, "
-                       f"{copies} replicas per density, Langevin gamma={gamma}, dt={dt}, {equil} "
-                       f"equilibration + {prod} production steps, samples every {every}, FP64",
-           "densities": list(densities), "results": {}}
-    for T, settings in studies:
-        states = [inputs.lj_fluid(n1, rho, T, seed=100 * k + c + 1)
-                  for k, rho in enumerate(densities) for c in range(copies)]
-        pos = np.concatenate([st_.pos for st_ in states], axis=1)
-        vel = np.concatenate([st_.vel for st_ in states], axis=1)
-        boxes = np.stack([st_.box for st_ in states])
-        off = np.arange(len(states) + 1, dtype=np.int64) * n1
-        n = int(off[-1])
-        for name, full, rs, rc, P in settings:
-            x, v = torch.from_numpy(pos).cuda(), torch.from_numpy(vel).cuda()
-            lists = ("full",) if full else ("core", "shell")
-            t0 = time.perf_counter()
-            with Context(n, replica_offsets=off, lists=lists, shift=False, skin=SKIN) as ctx:
-                ctx.set_thermostat(gamma, T)
-                ctx.build(x, boxes, rs, rc)
-                ctx.step(x, v, nsteps=equil, dt=dt, P=P, seed=1, rebuild_every=10, use_full=full)
-                us, ps = [], []
-                s_ = equil
-                for f in range(prod // every):
-                    _, ev = ctx.step(x, v, nsteps=every, dt=dt, P=P, seed=1, step0=s_, rebuild_every=10,
-                                     use_full=full, want_ev=True)
-                    s_ += every
-                    th = ctx.thermo(ev)
-                    us.append(th[:, 0])
-                    ps.append(th[:, 1])
-            el = time.perf_counter() - t0
-            u = np.mean(us, axis=0).reshape(len(densities), copies).mean(axis=1)
-            p = np.mean(ps, axis=0).reshape(len(densities), copies).mean(axis=1)
-            out["results"][f"T={T} {name}"] = {"u_per_particle": u.tolist(), "pressure": p.tolist(),
-                                               "seconds": el}
-            log(f"[bench] eos T={T} {name}: u {np.round(u, 3).tolist()} P {np.round(p, 3).tolist()} "
-                f"({el:.1f} s)")
-    return out
-
-
 def force_error_vs_oracle(x0, box, torch, rows):
     """Relative L2 error of the raw RBL force (P = 10, no mean subtraction)
     against the FP64 CPU oracle on sampled rows, for both precisions and
@@ -1052,9 +990,6 @@ def main(argv=None):
     if "slab" in wl:
         log("[bench] workload: charged slab")
         extra["slab"] = guarded("slab", run_slab, torch, 10, lifetimes(500 // args.repeats), args.repeats)
-    if "eos" in wl:
-        log("[bench] workload: Sec. III equation of state")
-        extra["eos"] = guarded("eos", run_eos, torch)
     if "table1" in wl:
         log("[bench] workload: Sec. III gas-liquid coexistence (Table I)")
         extra["table1"] = guarded("table1", run_table1, torch, args.table1_equil, args.table1_prod)

@@ -128,3 +128,39 @@ def test_cpu_oracle_leg_on_a_small_sample():
     assert res["cores"] == 1 and res["value"] > 0
     assert res["all_cores"]["cores"] == 2 and res["all_cores"]["value"] > 0
     assert bench.usable_cores() >= 1
+
+
+def test_msd_of_a_free_langevin_particle():
+    """The mean-squared displacement eta(t) of Sec. III, taken as the bench
+    takes it (unwrapped positions, average over time origins, least-squares
+    slope over the late lags), for free particles under the Langevin
+    thermostat: eta(t) = 6 (kT/gamma^2) (gamma t - 1 + exp(-gamma t)) for a
+    velocity drawn from the bath, long-time slope 6 kT / gamma.  Oracle
+    runs of one particle in an empty box (no pair in range, F = 0), many
+    seeds."""
+    import math
+    import oracle
+    box = np.array([8.0, 8.0, 8.0])
+    gamma, kT, dt, every, frames = 1.0, 0.9, 0.01, 50, 80
+    rng = np.random.default_rng(3)
+    runs = 300
+    msd = np.zeros(frames // 2)
+    for seed in range(runs):
+        x = np.array([[4.0], [4.0], [4.0]])
+        v = rng.normal(0.0, math.sqrt(kT), size=(3, 1))
+        u = x.copy()
+        snaps = [u.copy()]
+        for f in range(frames):
+            x, v, _, _ = oracle.md_run(x, v, box, 1.5, 3.5, 0.3, dt, every, p=10, seed=seed + 1,
+                                       step0=f * every, K=10, gamma=gamma, kT=kT, unwrapped=u)
+            snaps.append(u.copy())
+        snaps = np.array(snaps)[:, :, 0]
+        for lag in range(1, frames // 2 + 1):
+            d = snaps[lag:] - snaps[:-lag]
+            msd[lag - 1] += float((d ** 2).sum(axis=1).mean())
+    msd /= runs
+    t = np.arange(1, frames // 2 + 1) * every * dt
+    exact = 6.0 * kT / gamma ** 2 * (gamma * t - 1.0 + np.exp(-gamma * t))
+    assert np.all(np.abs(msd - exact) < 0.08 * exact), (msd[:5], exact[:5])
+    slope = bench.msd_slope(t, msd)
+    assert abs(slope - 6.0 * kT / gamma) < 0.1 * 6.0 * kT / gamma, slope
