@@ -77,6 +77,10 @@ def load():
                                C.c_int64, C.c_int, C.c_int, C.c_int, C.c_int, C.c_uint32,
                                C.c_void_p, C.c_double, C.c_int, C.c_double, C.c_double,
                                C.c_void_p, _f64p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]
+    lib.orc_paper_stencil_rows.argtypes = [C.c_int64, _f64p, _f64p, C.c_double, C.c_double, C.c_double,
+                                           C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                           C.c_void_p]
+    lib.orc_paper_stencil_rows.restype = C.c_int
     lib.orc_md_run.restype = C.c_int
     lib.orc_langevin_noise.argtypes = [C.c_uint64, C.c_uint32, C.c_uint64, C.c_uint32, _f64p]
     lib.orc_rdf.argtypes = [C.c_int64, _f64p, _f64p, C.c_double, C.c_int, C.c_void_p]
@@ -242,6 +246,37 @@ class System:
         if r:
             raise RuntimeError(f"orc_stencil_rows failed ({r})")
         return off, idx
+
+    def paper_stencil_rows(self, rows=None):
+        """(off, idx, ncell, h): the stencil population on the paper's own
+        grid (cells of edge rs + skin, (2h+1)^3 cells around i's cell with
+        h = floor((rc + skin)/w) + 1), members in that grid's slot order."""
+        lib = self._lib
+        rows_arr = (np.arange(self.n, dtype=np.int64) if rows is None
+                    else np.ascontiguousarray(rows, dtype=np.int64))
+        nrows = rows_arr.shape[0]
+        cnt = np.zeros(max(nrows, 1), dtype=np.int64)
+        nc = np.zeros(3, dtype=np.int32)
+        h = np.zeros(1, dtype=np.int32)
+        rp = rows_arr.ctypes.data_as(C.c_void_p)
+        args = (self.n, self.pos, self.box, self.rs, self.rc, self.skin, nrows, rp)
+        if lib.orc_paper_stencil_rows(*args, cnt.ctypes.data_as(C.c_void_p), None,
+                                      nc.ctypes.data_as(C.c_void_p), h.ctypes.data_as(C.c_void_p)):
+            raise ValueError("bad row index or stencil too large")
+        off = np.zeros(nrows + 1, dtype=np.int64)
+        off[1:] = np.cumsum(cnt[:nrows])
+        idx = np.zeros(int(off[-1]), dtype=np.int32)
+        if lib.orc_paper_stencil_rows(*args, off.ctypes.data_as(C.c_void_p), idx.ctypes.data_as(C.c_void_p),
+                                      None, None):
+            raise RuntimeError("orc_paper_stencil_rows failed")
+        return off, idx, nc, int(h[0])
+
+    def paper_stencil_lists(self, rows=None) -> Lists:
+        """Core rows as in lists(), shell rows replaced by the paper-grid
+        stencil population."""
+        L = self.lists(rows=rows, kinds=("core",))
+        off, idx, _, _ = self.paper_stencil_rows(rows)
+        return Lists(L.rows, L.core_off, L.core_idx, off, idx, L.full_off, L.full_idx)
 
     def stencil_lists(self, rows=None) -> Lists:
         """Core rows as in lists(), shell rows replaced by the stencil rows:

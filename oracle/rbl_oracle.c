@@ -42,6 +42,10 @@
  *                       them (Sec. II, Fig. 1); with these rows in place of
  *                       the shell rows, orc_forces_rbl is eq. (4) with N_I/p
  *                       and f~_ij = 0 outside the shell zone.
+ *   orc_paper_stencil_rows  the same population on the paper's own grid:
+ *                       cells of edge at least the core radius plus skin,
+ *                       (2 floor((rc + skin)/w) + 3)^3 of them around i's
+ *                       cell (Sec. II, Fig. 1).
  *   orc_mean_subtract   subtraction of the average net force (Sec. II,
  *                       Algorithm 1, F_cor of Appendix A).
  *   orc_md_run          Algorithm 1 with velocity Verlet (NVE), or with the
@@ -550,6 +554,93 @@ int orc_stencil_rows(const orc_sys* s, int64_t nrows, const int64_t* rows, int64
     }
     free(buf);
     return 0;
+}
+
+/* The stencil population on the grid the paper describes (Sec. II): cells of
+ * edge w at least the core radius (here rs + skin, times 1 + 1e-6, so that the
+ * 27 nearest cells hold every core candidate), and around particle i's cell
+ * the (2h+1)^3 cells with h = floor((rc + skin)/w) + 1 -- the paper's
+ * (2 floor(r/w) + 3)^3 with the outer radius widened by the skin, which the
+ * list lifetime needs (every particle within rc + skin of i is in these
+ * cells).  An axis of fewer than 2h+1 cells contributes every cell once.
+ * Members, i included, are listed in the slot order of that grid (cell by
+ * z-major index, then ID).  off/idx as orc_stencil_rows (idx NULL: counts
+ * into off[k]); ncell and h (may be NULL) receive the grid and half-width. */
+int orc_paper_stencil_rows(int64_t n, const double* pos, const double box[3], double rs, double rc,
+                           double skin, int64_t nrows, const int64_t* rows, int64_t* off, int32_t* idx,
+                           int32_t* ncell_out, int32_t* h_out)
+{
+    double w = (rs + skin) * 1.000001;
+    int nc[3];
+    for (int a = 0; a < 3; ++a) {
+        double c = floor(box[a] / w);
+        nc[a] = c < 1.0 ? 1 : (int)c;
+    }
+    int h = (int)floor((rc + skin) / w) + 1;
+    if (ncell_out) for (int a = 0; a < 3; ++a) ncell_out[a] = nc[a];
+    if (h_out) *h_out = h;
+    double* wp = (double*)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
+    memcpy(wp, pos, sizeof(double) * 3 * (size_t)n);
+    orc_wrap(n, wp, box);
+    int64_t ncells = (int64_t)nc[0] * nc[1] * nc[2];
+    int64_t* cell_of = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n + 1));
+    int64_t* start = (int64_t*)calloc((size_t)ncells + 1, sizeof(int64_t));
+    int64_t* id_of = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n + 1));
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t c[3];
+        for (int a = 0; a < 3; ++a) {
+            double f = floor(wp[a * n + i] * ((double)nc[a] / box[a]));
+            int64_t k = (int64_t)f;
+            if (k < 0) k = 0;
+            if (k > nc[a] - 1) k = nc[a] - 1;
+            c[a] = k;
+        }
+        cell_of[i] = (c[2] * nc[1] + c[1]) * nc[0] + c[0];
+        start[cell_of[i] + 1] += 1;
+    }
+    for (int64_t c = 0; c < ncells; ++c) start[c + 1] += start[c];
+    int64_t* fill = (int64_t*)malloc(sizeof(int64_t) * (size_t)(ncells + 1));
+    memcpy(fill, start, sizeof(int64_t) * (size_t)(ncells + 1));
+    for (int64_t i = 0; i < n; ++i) id_of[fill[cell_of[i]]++] = i;  /* IDs ascending within a cell */
+    int rcode = 0;
+    for (int64_t k = 0; k < nrows && !rcode; ++k) {
+        int64_t i = rows ? rows[k] : k;
+        if (i < 0 || i >= n) { rcode = -1; break; }
+        int64_t ci = cell_of[i];
+        int ctr[3] = {(int)(ci % nc[0]), (int)((ci / nc[0]) % nc[1]), (int)(ci / ((int64_t)nc[0] * nc[1]))};
+        /* the member cells per axis, ascending */
+        int ax[3][64], na[3];
+        for (int a = 0; a < 3; ++a) {
+            char on[4096] = {0};
+            if (nc[a] > 4096 || 2 * h + 1 > 64) { rcode = -3; break; }
+            if (2 * h + 1 >= nc[a]) {
+                for (int q = 0; q < nc[a]; ++q) on[q] = 1;
+            } else {
+                for (int d = -h; d <= h; ++d) on[((ctr[a] + d) % nc[a] + nc[a]) % nc[a]] = 1;
+            }
+            na[a] = 0;
+            for (int q = 0; q < nc[a]; ++q)
+                if (on[q]) ax[a][na[a]++] = q;
+        }
+        if (rcode) break;
+        int64_t m = 0;
+        for (int zz = 0; zz < na[2]; ++zz)
+            for (int yy = 0; yy < na[1]; ++yy)
+                for (int xx = 0; xx < na[0]; ++xx) {
+                    int64_t cell = ((int64_t)ax[2][zz] * nc[1] + ax[1][yy]) * nc[0] + ax[0][xx];
+                    for (int64_t q = start[cell]; q < start[cell + 1]; ++q) {
+                        if (idx) {
+                            if (off[k] + m >= off[k + 1]) { rcode = -2; break; }
+                            idx[off[k] + m] = (int32_t)id_of[q];
+                        }
+                        m += 1;
+                    }
+                }
+        if (!idx) off[k] = m;
+        else if (!rcode && off[k] + m != off[k + 1]) rcode = -2;
+    }
+    free(wp); free(cell_of); free(start); free(id_of); free(fill);
+    return rcode;
 }
 
 /* ------------------------------------------------------------------------ */

@@ -933,3 +933,122 @@ def test_displacement_rebuilds_keep_the_full_force():
     assert dx(stale[0], ref[0]) > 1e-5
     assert np.abs(stale[2] - ref[2]).max() > 1e-2
     assert 2 < len(builds) < 41, builds
+
+
+# -------------------------------------------- the paper's own stencil grid ---
+
+def _paper_rows_brute(pos, box, rs, rc, skin, rows):
+    """Sec. II by hand: cells of edge at least rs + skin, the (2h+1)^3 cells
+    around the particle's cell with h = floor((rc + skin)/w) + 1 (every cell
+    once on an axis of fewer), members ordered by cell (z-major) then ID."""
+    w = (rs + skin) * 1.000001
+    nc = np.maximum(1, np.floor(box / w)).astype(int)
+    h = int(math.floor((rc + skin) / w)) + 1
+    wp = pos - box[:, None] * np.floor(pos / box[:, None])
+    cell = np.clip(np.floor(wp * (nc / box)[:, None]).astype(int), 0, (nc - 1)[:, None])
+    lin = (cell[2] * nc[1] + cell[1]) * nc[0] + cell[0]
+    order = np.lexsort((np.arange(pos.shape[1]), lin))
+    out = []
+    for i in rows:
+        ok = np.ones(pos.shape[1], dtype=bool)
+        for a in range(3):
+            if 2 * h + 1 < nc[a]:
+                d = (cell[a] - cell[a, i]) % nc[a]
+                ok &= (d <= h) | (d >= nc[a] - h)
+        out.append(np.array([j for j in order if ok[j]], dtype=np.int32))
+    return out, nc, h
+
+
+@pytest.mark.parametrize("n,rho,rs,rc", [(2000, 0.2, 2.0, 6.0), (3000, 0.8442, RS, RC), (500, 0.5, 1.0, 2.5)])
+def test_paper_stencil_rows_are_the_papers_cells(n, rho, rs, rc):
+    """The paper-grid population equals its definition worked out by hand,
+    and holds every particle within rc + skin of its centre."""
+    st = inputs.lj_fluid(n, rho, 1.0, seed=40 + n)
+    S = oracle.System(st.pos, st.box, rs, rc, SKIN)
+    rows = np.arange(0, n, max(1, n // 60))
+    off, idx, nc, h = S.paper_stencil_rows(rows)
+    want, nc_b, h_b = _paper_rows_brute(st.pos, st.box, rs, rc, SKIN, rows)
+    assert np.array_equal(nc, nc_b) and h == h_b
+    for k, i in enumerate(rows):
+        row = idx[off[k]:off[k + 1]]
+        assert np.array_equal(row, want[k]), i
+        d = st.pos - st.pos[:, [i]]
+        d -= st.box[:, None] * np.rint(d / st.box[:, None])
+        near = np.nonzero((d ** 2).sum(axis=0) < (rc + SKIN) ** 2)[0]
+        assert set(near.tolist()) <= set(row.tolist())
+
+
+def test_paper_stencil_estimator_unbiased_with_exact_variance():
+    """Eq. (4) with N_I/p on the paper-grid population: unbiased over 10^4
+    seeds, variance equal to the exact without-replacement variance with
+    zero terms outside the shell zone (Appendix A); a batch as large as the
+    population gives the full force."""
+    p = 10
+    st = inputs.lj_fluid(2000, 0.2, 0.9, seed=41)
+    rs, rc = 2.0, 6.0
+    S = oracle.System(st.pos, st.box, rs, rc, SKIN)
+    rows = np.arange(0, 2000, 67)
+    L = S.paper_stencil_lists(rows=rows)
+    seeds = 10_000
+    samples = np.zeros((seeds, 3, len(rows)))
+    for s in range(seeds):
+        samples[s], _, _ = oracle.rbl_forces(st.pos, st.box, rs, rc, L, p, seed=7000 + s, step=0)
+    exact_var = np.zeros((3, len(rows)))
+    for k in range(len(rows)):
+        i = L.rows[k]
+        terms = []
+        for j in L.row("shell", k):
+            d = st.pos[:, i] - st.pos[:, j]
+            d -= st.box * np.rint(d / st.box)
+            r2 = float(d @ d)
+            terms.append(oracle.lj(r2)[0] * d if rs * rs <= r2 < rc * rc else np.zeros(3))
+        t = np.array(terms)
+        m = t.shape[0]
+        exact_var[:, k] = m * (m - p) * t.var(axis=0, ddof=1) / p
+    full, _, _ = oracle.full_forces(st.pos, st.box, rc, S.lists(rows=rows, kinds=("full",)))
+    mean = samples.mean(axis=0)
+    sem = np.sqrt(exact_var / seeds)
+    z = (mean - full) / np.where(sem > 0, sem, 1.0)
+    assert np.all(np.abs(z[sem > 0]) < 5.0)
+    ratio = samples.var(axis=0, ddof=1).sum() / exact_var.sum()
+    assert abs(ratio - 1.0) < 0.05, ratio
+    pmax = int(np.diff(L.shell_off).max())
+    fr, _, _ = oracle.rbl_forces(st.pos, st.box, rs, rc, L, pmax, seed=1, step=0)
+    assert np.abs(fr - full).max() < 1e-12 * np.abs(full).max()
+
+
+def _method_error(st, rs, rc, rows_of, P, seeds=40):
+    """Relative L2 distance of the RBL force from the full force at one
+    state, averaged over seeds (the statistical error of eq. (4))."""
+    S = oracle.System(st.pos, st.box, rs, rc, SKIN)
+    full, _, _ = oracle.full_forces(st.pos, st.box, rc, S.lists(kinds=("full",)))
+    L = rows_of(S)
+    err = []
+    for s in range(seeds):
+        f, _, _ = oracle.rbl_forces(st.pos, st.box, rs, rc, L, P, seed=100 + s, step=0)
+        err.append(np.linalg.norm(f - full) / np.linalg.norm(full))
+    return float(np.mean(err)), float(np.diff(L.shell_off).mean())
+
+
+def test_paper_grid_against_the_built_grid_at_the_table_i_radii():
+    """At the radii of the Sec. III coexistence study (N = 2000, rho = 0.2,
+    T = 0.9, core 2, cut-off 6) the paper's grid (cells of edge 2.3, 7^3 of
+    them) draws from fewer particles than the (r_c + skin)/2 grid's 5^3
+    cells, and its method error is smaller by the factor the exact variance
+    predicts (about sqrt of the population ratio); both far above the
+    shell-row population's.  Prints N_I and the errors per P."""
+    st = inputs.lj_fluid(2000, 0.2, 0.9, seed=42)
+    rs, rc = 2.0, 6.0
+    res = {}
+    for name, rows_of in (("shell rows", lambda S: S.lists(kinds=("core", "shell"))),
+                          ("stencil, (r_c+skin)/2 cells", lambda S: S.stencil_lists()),
+                          ("stencil, paper cells", lambda S: S.paper_stencil_lists())):
+        res[name] = {P: _method_error(st, rs, rc, rows_of, P) for P in (10, 20, 50)}
+    for name, r in res.items():
+        print(name, {P: (round(e, 4), round(n, 1)) for P, (e, n) in r.items()})
+    for P in (10, 20, 50):
+        e_shell, n_shell = res["shell rows"][P]
+        e_grid, n_grid = res["stencil, (r_c+skin)/2 cells"][P]
+        e_paper, n_paper = res["stencil, paper cells"][P]
+        assert n_paper < n_grid
+        assert e_shell < e_paper < e_grid
