@@ -344,7 +344,26 @@ struct GatherArgs {
     int* slot_of_id;
     int* img_delta;           // may be null: [3][n] box lengths taken off by the wrap
     const uint64_t* gate;     // rebuild gate (null: always run)
+    int4* xq;                 // may be null: fixed-point copy of xs (mixed-precision forces)
 };
+
+// Fixed-point coordinate for the mixed-precision force kernels: x / L mod 1
+// in units of 2^-32 (one rounding, at most half a unit, i.e. L 2^-33).  The
+// difference of two such words taken as a signed 32-bit integer is the
+// minimum-image displacement in the same units, so a neighbour costs one
+// 16-byte load (three words and the charge as FP32 bits) and no image
+// arithmetic, while the displacement error stays L 2^-32 whatever the box.
+__device__ __forceinline__ int fixq(double x, double inv)
+{
+    const double t = x * inv;
+    const double f = t - floor(t);  // [0, 1]; 1 wraps to 0 below
+    return (int)(uint32_t)(uint64_t)rint(f * 4294967296.0);
+}
+
+__device__ __forceinline__ int4 fixq4(double x, double y, double z, double q, const DevReplica& R)
+{
+    return make_int4(fixq(x, R.inv[0]), fixq(y, R.inv[1]), fixq(z, R.inv[2]), __float_as_int((float)q));
+}
 
 template <int SRC, bool VEL>
 __global__ __launch_bounds__(256) void k_gather(GatherArgs a)
@@ -355,6 +374,7 @@ __global__ __launch_bounds__(256) void k_gather(GatherArgs a)
     const int id = a.perm[s];
     if (id < 0) {
         a.xs[s] = make_double4(0.0, 0.0, 0.0, 0.0);
+        if (a.xq) a.xq[s] = make_int4(0, 0, 0, 0);
         if (VEL) {
             a.vs[s] = 0.0;
             a.vs[a.n_slots + s] = 0.0;
@@ -396,6 +416,7 @@ __global__ __launch_bounds__(256) void k_gather(GatherArgs a)
         a.xb[d * a.n_slots + s] = x[d];
     }
     a.xs[s] = make_double4(x[0], x[1], x[2], q);
+    if (a.xq) a.xq[s] = fixq4(x[0], x[1], x[2], q, R);
     if (VEL) {
         if (SRC == kSrcCaller) {
             a.vs[s] = a.vel[src];
@@ -1284,6 +1305,11 @@ struct ForceArgs {
                            // persistent grid) walks them in steps of its size
     const uint64_t* bstep; // step of the build whose batches `batch` holds (null: this step's)
     uint64_t* gate_clear;  // rebuild gate to reset for the next step (null: none)
+    // mixed precision: fixed-point copy of the positions (fixq), one 16-byte
+    // load per neighbour; a pair whose r^2 lies within `guard` of a bound it
+    // is tested against is classified from the FP64 positions
+    const int4* xq;
+    double guard;
 };
 
 // This step's pre-drawn batches (the force evaluation's step relative to
@@ -1345,6 +1371,67 @@ __device__ __forceinline__ void accumulate(const double4& xi, const double4 (&xj
     }
 }
 
+// Mixed precision: the displacement from the fixed-point copy (an exact
+// integer difference, scaled by L 2^-32 in FP64), the pair term in FP32 and
+// the force accumulated in FP64.  Classification stays that of the FP64
+// positions: |r^2 - r^2_FP64| <= guard (host bound from the two roundings),
+// so a pair farther than the guard from both bounds falls on the same side,
+// and one within it is decided from the FP64 positions.
+template <bool ENERGY, bool ERFC, int U>
+__device__ __forceinline__ void accumulate_mixed(const double4& xi, const int4& qi, const int4 (&xj)[U],
+                                                 const int (&j)[U], const bool (&live)[U], double lo2,
+                                                 double hi2, const DevReplica& R, const ForceArgs& a, Acc& acc)
+{
+    constexpr double k2m32 = 2.3283064365386962890625e-10;  // 2^-32
+    const double s0 = R.L[0] * k2m32, s1 = R.L[1] * k2m32, s2 = R.L[2] * k2m32;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const double dx = (double)(int)((uint32_t)qi.x - (uint32_t)xj[u].x) * s0;
+        const double dy = (double)(int)((uint32_t)qi.y - (uint32_t)xj[u].y) * s1;
+        const double dz = (double)(int)((uint32_t)qi.z - (uint32_t)xj[u].z) * s2;
+        const double r2q = fma(dz, dz, fma(dy, dy, dx * dx));
+        bool in = live[u] && r2q >= lo2 && r2q < hi2;
+        if (live[u] && (fabs(r2q - lo2) <= a.guard || fabs(r2q - hi2) <= a.guard)) {
+            const Delta d = delta(xi, a.xs[j[u]], R);
+            in = d.r2 >= lo2 && d.r2 < hi2;
+        }
+        const double r2 = in ? r2q : 1.0;
+        const double qq = ERFC ? (double)__int_as_float(qi.w) * (double)__int_as_float(xj[u].w) : 0.0;
+        double fm, en;
+        pair_term<kMixed, ERFC>(r2, qq, a.alpha, fm, en);
+        fm = in ? fm : 0.0;
+        acc.fx += fm * dx;
+        acc.fy += fm * dy;
+        acc.fz += fm * dz;
+        if (ENERGY) {
+            const double shift = ERFC ? a.uc + qq * a.uce : a.uc;
+            acc.e += in ? en - shift : 0.0;
+            acc.w += fm * r2;
+        }
+    }
+}
+
+// Gathers the positions of U partners (all loads in flight first) and
+// accumulates their pair terms: FP64 positions, or the fixed-point copy
+// (mixed).
+template <int PREC, bool ENERGY, bool ERFC, int U>
+__device__ __forceinline__ void gather_accumulate(const ForceArgs& a, const double4& xi, const int4& qi,
+                                                  const int (&j)[U], const bool (&live)[U], double lo2,
+                                                  double hi2, const DevReplica& R, Acc& acc)
+{
+    if constexpr (PREC == kMixed) {
+        int4 xj[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) xj[u] = a.xq[j[u]];
+        accumulate_mixed<ENERGY, ERFC, U>(xi, qi, xj, j, live, lo2, hi2, R, a, acc);
+    } else {
+        double4 xj[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) xj[u] = a.xs[j[u]];
+        accumulate<PREC, ENERGY, ERFC, U>(xi, xj, live, lo2, hi2, R, a, acc);
+    }
+}
+
 constexpr int kGatherBatch = 4;
 
 template <int PREC, int MODE, bool ENERGY, bool ERFC, int PMAX>
@@ -1360,6 +1447,7 @@ __device__ __forceinline__ void force_tile(const ForceArgs& a, int64_t tile, uin
     double fx = 0.0, fy = 0.0, fz = 0.0, e = 0.0, w = 0.0;
     if (real) {
         const double4 xi = a.xs[slot];
+        const int4 qi = PREC == kMixed ? a.xq[slot] : make_int4(0, 0, 0, 0);
         // core rows (or the full list in direct-truncation mode): r < cut
         Acc c = {0.0, 0.0, 0.0, 0.0, 0.0};
         {
@@ -1369,15 +1457,12 @@ __device__ __forceinline__ void force_tile(const ForceArgs& a, int64_t tile, uin
             for (int k = 0; k < len; k += U) {
                 int j[U];
                 bool live[U];
-                double4 xj[U];
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     live[u] = k + u < len;
                     j[u] = live[u] ? row[(int64_t)(k + u) * 64] : (int)slot;
                 }
-#pragma unroll
-                for (int u = 0; u < U; ++u) xj[u] = a.xs[j[u]];
-                accumulate<PREC, ENERGY, ERFC, U>(xi, xj, live, -1.0, cut, R, a, c);
+                gather_accumulate<PREC, ENERGY, ERFC, U>(a, xi, qi, j, live, -1.0, cut, R, c);
             }
         }
         if (MODE != kShellNone) {
@@ -1399,7 +1484,6 @@ __device__ __forceinline__ void force_tile(const ForceArgs& a, int64_t tile, uin
             for (int m = 0; m < cnt; m += U) {
                 int j[U];
                 bool live[U];
-                double4 xj[U];
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     live[u] = m + u < cnt;
@@ -1415,9 +1499,7 @@ __device__ __forceinline__ void force_tile(const ForceArgs& a, int64_t tile, uin
                     }
                     j[u] = jj;
                 }
-#pragma unroll
-                for (int u = 0; u < U; ++u) xj[u] = a.xs[j[u]];
-                accumulate<PREC, ENERGY, ERFC, U>(xi, xj, live, a.rs2, a.rc2, R, a, sh);
+                gather_accumulate<PREC, ENERGY, ERFC, U>(a, xi, qi, j, live, a.rs2, a.rc2, R, sh);
             }
             fx = c.fx + scale * sh.fx;
             fy = c.fy + scale * sh.fy;
@@ -1508,6 +1590,7 @@ __device__ __forceinline__ void force_tile_lpp(const ForceArgs& a, int64_t tile)
     double scale = 1.0;
     if (real) {
         const double4 xi = a.xs[slot];
+        const int4 qi = PREC == kMixed ? a.xq[slot] : make_int4(0, 0, 0, 0);
         {
             const double cut = MODE == kShellNone ? a.rc2 : a.rs2;
             const int len = a.core_len[slot];
@@ -1515,15 +1598,12 @@ __device__ __forceinline__ void force_tile_lpp(const ForceArgs& a, int64_t tile)
             for (int k = l; k < len; k += U * LPP) {
                 int j[U];
                 bool live[U];
-                double4 xj[U];
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     live[u] = k + u * LPP < len;
                     j[u] = live[u] ? row[(int64_t)(k + u * LPP) * 64] : (int)slot;
                 }
-#pragma unroll
-                for (int u = 0; u < U; ++u) xj[u] = a.xs[j[u]];
-                accumulate<PREC, ENERGY, ERFC, U>(xi, xj, live, -1.0, cut, R, a, c);
+                gather_accumulate<PREC, ENERGY, ERFC, U>(a, xi, qi, j, live, -1.0, cut, R, c);
             }
         }
         if (MODE != kShellNone) {
@@ -1535,7 +1615,6 @@ __device__ __forceinline__ void force_tile_lpp(const ForceArgs& a, int64_t tile)
             for (int m = l; m < cnt; m += U * LPP) {
                 int j[U];
                 bool live[U];
-                double4 xj[U];
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     live[u] = m + u * LPP < cnt;
@@ -1544,9 +1623,7 @@ __device__ __forceinline__ void force_tile_lpp(const ForceArgs& a, int64_t tile)
                     // particle itself, whose pair term is zero
                     if ((uint64_t)(uint32_t)j[u] >= (uint64_t)a.n_slots) j[u] = (int)slot;
                 }
-#pragma unroll
-                for (int u = 0; u < U; ++u) xj[u] = a.xs[j[u]];
-                accumulate<PREC, ENERGY, ERFC, U>(xi, xj, live, a.rs2, a.rc2, R, a, sh);
+                gather_accumulate<PREC, ENERGY, ERFC, U>(a, xi, qi, j, live, a.rs2, a.rc2, R, sh);
             }
         }
     }
@@ -1711,6 +1788,7 @@ struct IntArgs {
     uint64_t* gate;
     const uint64_t* bstep;
     int64_t max_life;
+    int4* xq;                  // may be null: fixed-point copy of the positions, kept in step
 };
 
 // The three standard normal numbers of the Ornstein-Uhlenbeck step of
@@ -1783,12 +1861,14 @@ __global__ __launch_bounds__(256) void k_integrate(IntArgs a)
         x.y = x.y + a.h * v[1];
         x.z = x.z + a.h * v[2];
         a.xs[s] = x;
+        if (a.xq) a.xq[s] = fixq4(x.x, x.y, x.z, x.w, R);
     } else if (MODE != kIntLast) {
         double4 x = a.xs[s];
         x.x = x.x + a.dt * v[0];
         x.y = x.y + a.dt * v[1];
         x.z = x.z + a.dt * v[2];
         a.xs[s] = x;
+        if (a.xq) a.xq[s] = fixq4(x.x, x.y, x.z, x.w, R);
     }
     if (MODE != kIntLast && a.gate) {
         // displacement since the last build past skin/2: rebuild at this step
@@ -1832,6 +1912,7 @@ struct IoArgs {
     double* f_out;
     const int* img_delta;  // if set, added into img ([3][n], caller order)
     int* img;
+    int4* xq;              // may be null: fixed-point copy of xs
 };
 
 // xs[slot] <- caller positions as given (no wrapping), for a force call.
@@ -1843,6 +1924,8 @@ __global__ __launch_bounds__(256) void k_load_positions(IoArgs a)
     if (id < 0) return;
     const double q = a.charges ? a.charges[id] : 0.0;
     a.xs[s] = make_double4(a.pos_in[id], a.pos_in[a.n + id], a.pos_in[2 * a.n + id], q);
+    if (a.xq) a.xq[s] = fixq4(a.pos_in[id], a.pos_in[a.n + id], a.pos_in[2 * a.n + id], q,
+                              a.rep[a.slice_rep[s >> 6]]);
 }
 
 __global__ __launch_bounds__(256) void k_scatter_out(IoArgs a)

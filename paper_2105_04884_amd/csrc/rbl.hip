@@ -165,6 +165,8 @@ struct rbl_ctx {
     int cur = 0;
     int* d_slot_of_id = nullptr;
     double4* d_xs[2] = {nullptr, nullptr};
+    int4* d_xq = nullptr;           // mixed precision: fixed-point copy of the current positions
+    double guard_q = 0.0;           // bound on |r^2 fixed-point - r^2 FP64| of the mixed kernels
     double* d_vs[2] = {nullptr, nullptr};
     double* d_xb = nullptr;
     double* d_f = nullptr;
@@ -405,6 +407,26 @@ rbl_status setup_geometry(rbl_ctx* c, const double* box, double r_s, double r_c)
     }
     c->r_s = r_s;
     c->r_c = r_c;
+    // Mixed-precision forces classify from fixed-point copies of the
+    // positions (x / L mod 1 in units of 2^-32).  With u = 2^-53 and
+    // coordinates below X = 1024 (L_max + r_c) in magnitude, a stored word
+    // is off by at most half a unit plus u X twice (1/L and x/L rounded), so
+    // the scaled difference of two is off from the true displacement by
+    // L 2^-32 + u (4 X + r) per component, and the FP64 path's min-image
+    // difference by u (4 X + 3 L_max + r); with e the sum of the two, the
+    // two r^2 (three roundings each) differ by at most
+    // 2 sqrt(3) r e + 3 e^2 + 8 u r^2, r <= r_c + 1 near a bound; the guard
+    // doubles that.
+    {
+        double lmax = 0.0;
+        for (const auto& d : reps)
+            for (int a = 0; a < 3; ++a) lmax = std::max(lmax, d.L[a]);
+        const double u = std::ldexp(1.0, -53);
+        const double X = 1024.0 * (lmax + r_c);
+        const double r = r_c + 1.0;
+        const double e = std::ldexp(lmax, -32) + u * (8.0 * X + 3.0 * lmax + 2.0 * r);
+        c->guard_q = 2.0 * (2.0 * std::sqrt(3.0) * r * e + 3.0 * e * e + 8.0 * u * r * r);
+    }
     return RBL_OK;
 }
 
@@ -530,6 +552,7 @@ rbl_status bin_particles(rbl_ctx* c, const double* pos, const double* vel, bool 
     g.slot_of_id = c->d_slot_of_id;
     g.img_delta = c->track_images ? c->d_img_delta : nullptr;
     g.gate = gate;
+    g.xq = c->d_xq;
     RBL_TRY(timed(c, kKBin, [&] {
         if (with_vel)
             k_gather<SRC, true><<<grid_for(c->n_slots), kBlock, 0, c->ls>>>(g);
@@ -826,6 +849,8 @@ ForceArgs force_args(rbl_ctx* c, int P, uint64_t seed, uint64_t step, bool full)
     a.partial = c->d_partial;
     a.bstep = nullptr;
     a.gate_clear = nullptr;
+    a.xq = c->d_xq;
+    a.guard = c->guard_q;
     return a;
 }
 
@@ -990,6 +1015,7 @@ IoArgs io_args(rbl_ctx* c, bool momentum_fix)
     io.f_out = nullptr;
     io.img_delta = nullptr;
     io.img = nullptr;
+    io.xq = c->d_xq;
     return io;
 }
 
@@ -1021,6 +1047,7 @@ rbl_status integrate(rbl_ctx* c, int mode, double dt, bool momentum_fix, uint64_
     a.gate = gate_life > 0 ? c->d_step + 4 : nullptr;
     a.bstep = c->d_step + 2;
     a.max_life = gate_life;
+    a.xq = c->d_xq;
     a.rep = c->d_rep;
     a.slice_rep = c->d_slice_rep;
     a.rep_sum = c->d_rep_sum;
@@ -1603,6 +1630,7 @@ rbl_status rbl_destroy(rbl_ctx* c)
     dfree(c->d_slot_of_id);
     dfree(c->d_xs[0]);
     dfree(c->d_xs[1]);
+    dfree(c->d_xq);
     dfree(c->d_vs[0]);
     dfree(c->d_vs[1]);
     dfree(c->d_xb);
@@ -1716,6 +1744,7 @@ rbl_status rbl_create(const rbl_config* cfg, void* hip_stream, rbl_ctx** out)
     CR(dalloc(&c->d_slot_of_id, c->n));
     CR(dalloc(&c->d_xs[0], c->n_slots));
     CR(dalloc(&c->d_xs[1], c->n_slots));
+    if (cfg->precision == RBL_PREC_MIXED) CR(dalloc(&c->d_xq, c->n_slots));
     CR(dalloc(&c->d_vs[0], 3 * c->n_slots));
     CR(dalloc(&c->d_vs[1], 3 * c->n_slots));
     CR(dalloc(&c->d_xb, 3 * c->n_slots));
