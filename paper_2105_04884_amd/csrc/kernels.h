@@ -709,8 +709,12 @@ __device__ __forceinline__ void wave_lds_fence()
 // k-th shell candidate being one LDS read away.  Bit-identical to k_build +
 // k_predraw, without writing or re-reading the shell rows.  Details:
 //  - the stencil's cells merge into x-runs of contiguous slots (at most 50);
-//    run starts, prefix counts and image shifts sit in LDS, and every lane
-//    walks the runs forward as its candidate index grows by 64 per chunk;
+//    the runs with particles sit in LDS (start, prefix count, image shift),
+//    and a lane finds the run of its candidate from two ballots over the
+//    prefix counts (runs starting before its chunk, and the few starting
+//    inside it), with no per-lane search;
+//  - lanes past the end of the candidates carry a `live` flag instead of a
+//    poisoned position, so no per-chunk initialisation is needed;
 //  - the periodic image of every candidate run is known from the stencil
 //    geometry when every axis has >= 7 cells, so dx = (x_i - x_j) + s with
 //    s in {-L, 0, L} exactly equals the canonical fma(-rint(d/L), L, d)
@@ -819,16 +823,6 @@ constexpr int kRunOffBits = 10;    // list entry = run << 10 | offset in the run
 constexpr int kRing = 128;         // ring of kept candidates per wavefront (two chunks)
 constexpr int kNoShift = 1 | (1 << 2) | (1 << 4);  // image-shift code of no shift
 
-// Position of a lane without a candidate: NaN, so that every distance test
-// on it fails.  (A far finite position is not safe: the canonical minimum
-// image folds it back into the box, exactly to 0 when the box length
-// divides it.)
-__device__ __forceinline__ double4 no_position()
-{
-    const double q = __builtin_nan("");
-    return make_double4(q, q, q, 0.0);
-}
-
 template <int PMAX, bool STENCIL>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PMAX <= 32 ? kFusedWavesPerEu : 2))) void k_build_draw(FusedArgs fa)
 {
@@ -842,7 +836,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PMAX <= 32 
     // STENCIL: run table of the core test (3 x 3 x 3 cells when they reach)
     __shared__ int s_crstart[STENCIL ? 4 : 1][64];
     __shared__ int s_crpre[STENCIL ? 4 : 1][64];
-    __shared__ int s_crshift[STENCIL ? 4 : 1][64];
+    __shared__ unsigned char s_crshift[STENCIL ? 4 : 1][64];
     // per wavefront: list_budget entries + a write-off word per lane
     extern __shared__ unsigned short s_dyn[];
     const BuildArgs& a = fa.b;
@@ -907,28 +901,50 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PMAX <= 32 
             rshift = (sx + 1) | ((sy + 1) << 2) | ((sz + 1) << 4);
         }
     };
+    // The run tables in LDS: entry q is the q-th run with particles, in
+    // stencil order (slot start, prefix count, image-shift code); runs
+    // without particles are dropped, so a chunk of 64 consecutive
+    // candidates crosses few run starts.  Entries past the last run hold
+    // the total (the stencil draw's binary search relies on it).  A run
+    // outside the slot range stops the cell, so every candidate slot taken
+    // from a run is valid.
+    auto compact_runs = [&](int rs, int rl, int rsh, int* t_st, int* t_pr, unsigned char* t_sh, int& tot,
+                            int& nr) -> bool {
+        const uint64_t nz = __ballot(rl > 0);
+        const int incl = wave_incl_scan(rl);
+        tot = rfl(__builtin_amdgcn_readlane(incl, 63));
+        nr = (int)__popcll(nz);
+        const int qc = (int)mbcnt(nz);
+        if (rl > 0) {
+            t_st[qc] = rs;
+            t_pr[qc] = incl - rl;
+            t_sh[qc] = (unsigned char)rsh;
+        }
+        if (lane >= nr) {
+            t_st[lane] = 0;
+            t_pr[lane] = tot;
+            t_sh[lane] = (unsigned char)kNoShift;
+        }
+        return __ballot(rl > 0 && (rs < 0 || (int64_t)rs + rl > a.n_slots)) == 0;
+    };
     int rstart, rlen, rshift;
     run_table(2, rstart, rlen, rshift);
-    const int incl = wave_incl_scan(rlen);
-    const int total = rfl(__builtin_amdgcn_readlane(incl, 63));
-    const int rpre = incl - rlen;
-    s_rstart[w][lane] = rstart;
-    s_rpre[w][lane] = rpre;
-    s_rshift[w][lane] = rshift;
+    int total, nruns;
+    bool runs_ok = compact_runs(rstart, rlen, rshift, s_rstart[w], s_rpre[w], s_rshift[w], total, nruns);
     // the table the core test walks: the stencil's own, or (STENCIL, when
     // r_s + skin fits one cell edge with the cell grid's margin) the
     // 3 x 3 x 3 cells around the centre cell
-    int ctotal = total;
+    int ctotal = total, cnruns = nruns;
     if constexpr (STENCIL) {
         const double edge = fmin(L0 / nc0, fmin(L1 / nc1, L2 / nc2));
         const int hc = fa.core_reach * (1.0 + 1e-6) <= edge ? 1 : 2;
         int cs, cl, csh;
         run_table(hc, cs, cl, csh);
-        const int cincl = wave_incl_scan(cl);
-        ctotal = rfl(__builtin_amdgcn_readlane(cincl, 63));
-        s_crstart[w][lane] = cs;
-        s_crpre[w][lane] = cincl - cl;
-        s_crshift[w][lane] = csh;
+        runs_ok = compact_runs(cs, cl, csh, s_crstart[w], s_crpre[w], s_crshift[w], ctotal, cnruns) && runs_ok;
+    }
+    if (!runs_ok) {
+        if (lane == 0) atomicOr(&a.flags[kFlagBadSlot], 64);
+        return;
     }
     auto t_start = [&](int q) { if constexpr (STENCIL) return s_crstart[w][q]; else return s_rstart[w][q]; };
     auto t_pre = [&](int q) { if constexpr (STENCIL) return s_crpre[w][q]; else return s_rpre[w][q]; };
@@ -956,27 +972,30 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PMAX <= 32 
     const bool do_core = !STENCIL || !fa.draw_only;
     wave_lds_fence();
 
-    int qrun = 0;  // this lane's current run (its candidate index only grows)
-    // candidate f: slot (-1 past the stencil), position (NaN without one),
-    // image-shift code, list entry
-    auto candidate = [&](int f, int& j, double4& xj, int& code, int& ent) {
-        j = -1;
-        code = kNoShift;
-        ent = 0;
-        xj = no_position();
-        if (f < ctotal) {
-            while (qrun < 63 && t_pre(qrun + 1) <= f) ++qrun;
-            const int off = f - t_pre(qrun);
-            const int jj = t_start(qrun) + off;
-            if (jj >= 0 && (int64_t)jj < a.n_slots) {
-                j = jj;
-                code = t_shift(qrun);
-                ent = (qrun << kRunOffBits) | off;
-                xj = a.xs[jj];
-            } else {
-                atomicOr(&a.flags[kFlagBadSlot], 64);
-            }
+    // Candidate f0 + lane of the core test's table: `live` (false past the
+    // table's end), slot (the centre cell's first slot when not live),
+    // position, image-shift code and list entry.  The lane's run is the
+    // last one whose prefix count is <= its index: the runs starting at or
+    // before f0, plus one per run start inside the chunk (wave-uniform,
+    // few as the runs are dense).
+    const int tpre_v = t_pre(lane);
+    const int tnr = STENCIL ? cnruns : nruns;
+    auto candidate = [&](int f0, int& j, double4& xj, int& code, int& ent, bool& live) {
+        const uint64_t below = __ballot(lane < tnr && tpre_v <= f0);
+        uint64_t inside = __ballot(lane < tnr && tpre_v > f0 && tpre_v < f0 + 64);
+        int q = (int)__popcll(below) - 1;
+        while (inside) {
+            const int b = (int)__builtin_ctzll(inside);
+            inside &= inside - 1;
+            q += lane >= __builtin_amdgcn_readlane(tpre_v, b) - f0 ? 1 : 0;
         }
+        const int f = f0 + lane;
+        const int off = f - t_pre(q);
+        live = f < ctotal;
+        j = live ? t_start(q) + off : i0;
+        code = live ? (int)t_shift(q) : kNoShift;
+        ent = (q << kRunOffBits) | off;
+        xj = a.xs[j];
     };
 
     for (int g0 = 0; g0 < m; g0 += gmax) {
@@ -986,18 +1005,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PMAX <= 32 
         if (do_core) {
             if (lane < mg) s_ctr[w][lane] = a.xs[i0 + g0 + lane];
             wave_lds_fence();
-            qrun = 0;
             uint32_t ncore = 0;  // lane ii: core partners of centre ii so far
             // the tests of the group's centres against 64 candidates (slot
-            // jc, position xc, image-shift code, list entry ent; slot -1 and
-            // a NaN position in lanes without one): core partners written
-            // to the centre's row, shell candidates appended to its LDS list
-            auto test_chunk = [&](int jc, const double4& xc, int code, int ent) {
+            // jc, position xc, image-shift code, list entry ent, in the
+            // lanes where `live`): core partners written to the centre's
+            // row, shell candidates appended to its LDS list
+            auto test_chunk = [&](int jc, const double4& xc, int code, int ent, bool live) {
                 auto test = [&](int ii, double dx, double dy, double dz) {
                     const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
                     const int slot_ii = i0 + g0 + ii;
-                    const uint64_t other = ~__ballot(jc == slot_ii);
-                    const bool is_core = jc != slot_ii && r2 < a.thr_core;
+                    const bool other = live && jc != slot_ii;
+                    const bool is_core = other && r2 < a.thr_core;
                     const uint64_t mc = __ballot(is_core);
                     if (mc) {
                         // straight into row ii (sliced ELL) in candidate order;
@@ -1012,7 +1030,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PMAX <= 32 
                         ncore = (uint32_t)rbl_writelane(basec + (int)__popcll(mc), ii, (int)ncore);
                     }
                     if constexpr (STENCIL) return;
-                    const uint64_t ms = other & __ballot(r2 >= a.thr_shell_in) & __ballot(r2 < a.thr_out);
+                    const uint64_t ms = __ballot(other && r2 >= a.thr_shell_in && r2 < a.thr_out);
                     const int base = rfl((int)__builtin_amdgcn_readlane((int)nshell, ii));
                     // every lane writes (no branch): a selected lane to its list
                     // position (clamped into the room; an overflowing run is
@@ -1045,7 +1063,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PMAX <= 32 
             };
             int jn, coden, entn;
             double4 xn;
-            candidate(lane, jn, xn, coden, entn);
+            bool liven;
+            candidate(0, jn, xn, coden, entn, liven);
             // the first chunk's candidates are complete before the chunk loop:
             // with nothing of this load pending at the loop head, the inner loop
             // waits on no vector-memory counter, and each chunk's prefetch of the
@@ -1057,8 +1076,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PMAX <= 32 
                     const double4 xc = xn;
                     const int code = coden;
                     const int ent = entn;
-                    if (ch + 1 < nch) candidate((ch + 1) * 64 + lane, jn, xn, coden, entn);
-                    test_chunk(jc, xc, code, ent);
+                    const bool live = liven;
+                    if (ch + 1 < nch) candidate((ch + 1) * 64, jn, xn, coden, entn, liven);
+                    test_chunk(jc, xc, code, ent, live);
                 }
             } else {
                 // The group's bounding box, widened by a margin far above the
@@ -1086,15 +1106,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PMAX <= 32 
                 const double keep_thr = fmax(a.thr_core, a.thr_out);
                 int head = 0, tail = 0;  // ring positions (wave-uniform)
                 bool have = false;       // a batch is loaded and waits for its tests
-                int jb = -1, codeb = kNoShift, entb = 0;
-                double4 xb = no_position();
+                int jb = i0, codeb = kNoShift, entb = 0;
+                bool liveb = false;
+                double4 xb = make_double4(0.0, 0.0, 0.0, 0.0);
                 for (int ch = 0;; ++ch) {
                     if (ch < nch) {
                         const int jc = jn;
                         const double4 xc = xn;
                         const int code = coden;
                         const int ent = entn;
-                        if (ch + 1 < nch) candidate((ch + 1) * 64 + lane, jn, xn, coden, entn);
+                        const bool live = liven;
+                        if (ch + 1 < nch) candidate((ch + 1) * 64, jn, xn, coden, entn, liven);
                         double dx, dy, dz;
                         if (SHIFT && __ballot(code != kNoShift) == 0) {
                             dx = bc0 - xc.x;
@@ -1112,33 +1134,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PMAX <= 32 
                         const double gx = fmax(fabs(dx) - be0, 0.0);
                         const double gy = fmax(fabs(dy) - be1, 0.0);
                         const double gz = fmax(fabs(dz) - be2, 0.0);
-                        // (fmax drops a NaN, so a lane without a candidate is
-                        // excluded by its slot)
-                        const bool keep = jc >= 0 && fma(gz, gz, fma(gy, gy, gx * gx)) < keep_thr;
+                        const bool keep = live && fma(gz, gz, fma(gy, gy, gx * gx)) < keep_thr;
                         const uint64_t mk = __ballot(keep);
                         // after the reads of the previous batch
                         wave_lds_fence();
                         if (keep) s_ring[w][(tail + (int)mbcnt(mk)) & (kRing - 1)] = (unsigned short)ent;
                         tail += (int)__popcll(mk);
                     }
-                    if (have) test_chunk(jb, xb, codeb, entb);
+                    if (have) test_chunk(jb, xb, codeb, entb, liveb);
                     const bool drained = ch + 1 >= nch;
                     have = tail - head >= 64 || (drained && tail > head);
                     if (!have && drained) break;
                     if (have) {
                         wave_lds_fence();
                         const int nb = min(64, tail - head);
-                        jb = -1;
-                        codeb = kNoShift;
-                        entb = 0;
-                        xb = no_position();
-                        if (lane < nb) {
-                            entb = s_ring[w][(head + lane) & (kRing - 1)];
-                            const int q = entb >> kRunOffBits;
-                            jb = s_rstart[w][q] + (entb & ((1 << kRunOffBits) - 1));
-                            codeb = s_rshift[w][q];
-                            xb = a.xs[jb];
-                        }
+                        // lanes past the batch read a stale ring entry (still
+                        // a run of the table) and take the centre cell's
+                        // first slot
+                        liveb = lane < nb;
+                        entb = s_ring[w][(head + lane) & (kRing - 1)];
+                        const int q = entb >> kRunOffBits;
+                        jb = liveb ? s_rstart[w][q] + (entb & ((1 << kRunOffBits) - 1)) : i0;
+                        codeb = liveb ? (int)s_rshift[w][q] : kNoShift;
+                        xb = a.xs[jb];
                         head += nb;
                     }
                 }
