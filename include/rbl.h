@@ -55,7 +55,7 @@ typedef enum rbl_status {
 enum { RBL_PREC_FP64 = 0, RBL_PREC_MIXED = 1 };
 enum { RBL_PAIR_LJ = 0, RBL_PAIR_LJ_ERFC = 1 };
 enum { RBL_LIST_CORE = 1, RBL_LIST_SHELL = 2, RBL_LIST_FULL = 4 };
-enum { RBL_SHELL_LIST = 0, RBL_SHELL_STENCIL = 1 };
+enum { RBL_SHELL_LIST = 0, RBL_SHELL_STENCIL = 1, RBL_SHELL_PAPER = 2 };
 
 /* Largest batch size P accepted by rbl_forces, rbl_step and
  * rbl_export_batches. */
@@ -109,7 +109,14 @@ typedef struct rbl_config {
                                   form of Sec. II), n_i = N_I of that cell; partners
                                   outside [r_s, r_c) add zero.  Batches are then always
                                   drawn at the list build (predraw is implied) and no
-                                  shell row is needed by rbl_forces or rbl_step. */
+                                  shell row is needed by rbl_forces or rbl_step.
+                                  RBL_SHELL_PAPER: the same form on the grid Sec. II and
+                                  Fig. 1 describe: cells of edge w = (r_s + skin)(1 + 1e-6),
+                                  the (2h+1)^3 cells around the particle's cell with
+                                  h = floor((r_c + skin)/w) + 1 (an axis of at most 2h+1
+                                  cells taken whole), members listed by ascending z, y, x
+                                  cell index, then ID; 2 (2h+1)^2 <= 256 is required
+                                  (rbl_build fails with RBL_E_ARG otherwise). */
     int32_t rebuild_check;     /* 0 (default): rbl_step rebuilds the lists before every force
                                   evaluation s with s % rebuild_every == 0.  1: rebuilds
                                   before evaluation s when some particle has moved more than
@@ -250,7 +257,10 @@ rbl_status rbl_last_run(rbl_ctx* ctx, int32_t* attempts, int64_t* end_step, int3
 
 /* Row lengths of the last build for the particles rows[0..nrows) (IDs; NULL
  * = all n): counts[k] core, counts[nrows+k] shell, counts[2 nrows+k] full
- * (0 for a list that was not built). */
+ * (0 for a list that was not built).  With a stencil draw population
+ * (RBL_SHELL_STENCIL, RBL_SHELL_PAPER) and no shell rows built, the shell
+ * column holds N_I once a batch has been drawn from the last build (a force
+ * call, a batch export or a run), else 0. */
 rbl_status rbl_row_counts(rbl_ctx* ctx, int64_t nrows, const int64_t* rows, int64_t* counts);
 
 /* Rows of the last build as CSR over the requested rows; partners are

@@ -370,7 +370,7 @@ def md_run(pos, vel, box, rs, rc, skin, dt, nsteps, p=10, seed=1, step0=0, K=10,
     r = lib.orc_md_run(x.shape[1], x, v, np.asarray(box, dtype=np.float64), rs, rc, skin, dt,
                        nsteps, p, seed, step0, K, int(use_full), int(shift), int(momentum_fix),
                        replica, _ptr_or_null(q), float(alpha),
-                       {"shell": 0, "stencil": 1}[shell_source], float(gamma), float(kT),
+                       {"shell": 0, "stencil": 1, "paper": 2}[shell_source], float(gamma), float(kT),
                        _ptr_or_null(unwrapped), f, _ptr_or_null(ev), int(bool(check)),
                        bsteps.ctypes.data_as(C.c_void_p), nb.ctypes.data_as(C.c_void_p))
     if r:

@@ -794,15 +794,22 @@ static int build_all(int64_t n, double* pos, const double box[3], double rs, dou
                               stencil ? NULL : L->shell_off, stencil ? NULL : L->shell_idx,
                               L->full_off, L->full_idx);
     if (!rcode && stencil && !use_full) {
-        /* the draw population is the stencil cells (the paper's own form) */
+        /* the draw population is the stencil cells (the paper's own form):
+         * on the 5x5x5 search grid (stencil 1) or on the grid Sec. II
+         * describes (stencil 2, orc_paper_stencil_rows) */
         int64_t* cnt = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
-        orc_stencil_rows(s, n, NULL, cnt, NULL);
-        L->shell_off[0] = 0;
-        for (int64_t i = 0; i < n; ++i) L->shell_off[i + 1] = L->shell_off[i] + cnt[i];
+        if (stencil == 2) rcode = orc_paper_stencil_rows(n, pos, box, rs, rc, skin, n, NULL, cnt, NULL, NULL, NULL);
+        else orc_stencil_rows(s, n, NULL, cnt, NULL);
+        if (!rcode) {
+            L->shell_off[0] = 0;
+            for (int64_t i = 0; i < n; ++i) L->shell_off[i + 1] = L->shell_off[i] + cnt[i];
+            free(L->shell_idx);
+            L->shell_idx = (int32_t*)malloc(sizeof(int32_t) * (size_t)(L->shell_off[n] + 1));
+            rcode = stencil == 2 ? orc_paper_stencil_rows(n, pos, box, rs, rc, skin, n, NULL, L->shell_off,
+                                                          L->shell_idx, NULL, NULL)
+                                 : orc_stencil_rows(s, n, NULL, L->shell_off, L->shell_idx);
+        }
         free(cnt);
-        free(L->shell_idx);
-        L->shell_idx = (int32_t*)malloc(sizeof(int32_t) * (size_t)(L->shell_off[n] + 1));
-        rcode = orc_stencil_rows(s, n, NULL, L->shell_off, L->shell_idx);
     }
     orc_sys_free(s);
     return rcode;

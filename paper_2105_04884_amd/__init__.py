@@ -103,7 +103,8 @@ class Context:
         cfg.lanes = int(lanes)
         cfg.persistent = int(persistent)
         cfg.capacity_factor = float(capacity_factor)
-        cfg.shell_source = {"shell": _lib.SHELL_LIST, "stencil": _lib.SHELL_STENCIL}[shell_source]
+        cfg.shell_source = {"shell": _lib.SHELL_LIST, "stencil": _lib.SHELL_STENCIL,
+                            "paper": _lib.SHELL_PAPER}[shell_source]
         cfg.rebuild_check = int(bool(rebuild_check))
         self._offsets = None
         if replica_offsets is not None:

@@ -29,7 +29,7 @@ STATUS_NAMES = {
 PREC_FP64, PREC_MIXED = 0, 1
 PAIR_LJ, PAIR_LJ_ERFC = 0, 1
 LIST_CORE, LIST_SHELL, LIST_FULL = 1, 2, 4
-SHELL_LIST, SHELL_STENCIL = 0, 1
+SHELL_LIST, SHELL_STENCIL, SHELL_PAPER = 0, 1, 2
 MAX_P = 128
 
 KIND_FORCE_RBL, KIND_FORCE_FULL, KIND_BUILD, KIND_BIN, KIND_INTEGRATE, KIND_REDUCE, KIND_PREDRAW = range(7)

@@ -268,8 +268,8 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_final(const int* cnt, int64
     for (int k = 0; k < kScanPerThread; ++k) {
         const int64_t c = base + k;
         if (c < n) {
-            const DevReplica& R = rep[cell_rep[c]];
-            start[c] = run + (int)(R.slot_base - R.id_base);
+            // replica r starts at its slot base (no shift without a table)
+            start[c] = cell_rep ? run + (int)(rep[cell_rep[c]].slot_base - rep[cell_rep[c]].id_base) : run;
         }
         run += v[k];
     }
@@ -1241,6 +1241,270 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PMAX <= 32 
             }
         }
         wave_lds_fence();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// The draw population on the paper's own cell grid (Sec. II, Fig. 1): cells
+// of edge w >= r_s + skin, and around particle i's cell the (2h+1)^3 cells
+// with h = floor((r_c + skin)/w) + 1 (an axis of at most 2h+1 cells taken
+// whole, each cell once).  The population is every particle of those cells,
+// i included, N_I of them, listed cell by cell in ascending z, y, x cell
+// index and by particle ID within a cell; the batch is drawn from it as
+// from a shell row, and eq. (4) scales it by N_I/P with the pair term zero
+// outside the shell zone.  The grid is binned at every list build (count,
+// scan, scatter, in-cell sort by ID), and its members are kept for the
+// draws of the list lifetime.
+struct PaperGrid {
+    double scale[3];    // cells per unit length: nc / L
+    int nc[3];
+    int h;              // stencil half-width in cells
+    int64_t cell_base;  // first global cell of the replica
+};
+
+struct PaperArgs {
+    const PaperGrid* grid;  // per replica
+    const DevReplica* rep;
+    const int* slice_rep;
+    const int* cell_rep;    // paper cell -> replica
+    const double4* xs;
+    const int* perm;        // slot -> ID (< 0: padding)
+    int64_t n_slots;
+    int64_t n_cells;
+    int* cell_of_slot;      // [n_slots] (-1: padding)
+    int* rank;              // [n_slots]: arrival rank in the cell
+    int* count;             // [n_cells]
+    int* start;             // [n_cells]: first member position of the cell
+    int* member;            // [n_slots]: member position -> slot
+    int* flags;
+    const uint64_t* gate;
+};
+
+// Paper-grid cell of every slot (positions as wrapped at the build, the
+// cell coordinate floor(x nc / L) clamped into the grid) and arrival ranks.
+__global__ __launch_bounds__(256) void k_paper_count(PaperArgs a)
+{
+    if (gated_off(a.gate)) return;
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= a.n_slots) return;
+    if (a.perm[s] < 0) {
+        a.cell_of_slot[s] = -1;
+        return;
+    }
+    const PaperGrid& G = a.grid[a.slice_rep[s >> 6]];
+    const double4 x = a.xs[s];
+    const double xv[3] = {x.x, x.y, x.z};
+    int c[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double f = floor(xv[d] * G.scale[d]);
+        c[d] = f < 0.0 ? 0 : (f > (double)(G.nc[d] - 1) ? G.nc[d] - 1 : (int)f);
+    }
+    const int64_t cell = G.cell_base + ((int64_t)c[2] * G.nc[1] + c[1]) * G.nc[0] + c[0];
+    a.cell_of_slot[s] = (int)cell;
+    a.rank[s] = atomicAdd(&a.count[cell], 1);
+}
+
+__global__ __launch_bounds__(256) void k_paper_scatter(PaperArgs a)
+{
+    if (gated_off(a.gate)) return;
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= a.n_slots) return;
+    const int cell = a.cell_of_slot[s];
+    if (cell < 0) return;
+    const int64_t q = (int64_t)a.start[cell] + a.rank[s];
+    if (q < 0 || q >= a.n_slots) {
+        atomicOr(&a.flags[kFlagBadSlot], 16);
+        return;
+    }
+    a.member[q] = (int)s;
+}
+
+// Within each paper cell, members by ID (insertion sort; cells hold a
+// handful of particles), so that the order does not depend on atomics.
+__global__ __launch_bounds__(256) void k_paper_sort(PaperArgs a)
+{
+    if (gated_off(a.gate)) return;
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= a.n_cells) return;
+    const int b = a.start[c];
+    const int m = a.count[c];
+    if (b < 0 || (int64_t)b + m > a.n_slots) {
+        atomicOr(&a.flags[kFlagBadSlot], 16);
+        return;
+    }
+    for (int i = 0; i < m; ++i)
+        if ((uint64_t)(uint32_t)a.member[b + i] >= (uint64_t)a.n_slots) {
+            atomicOr(&a.flags[kFlagBadSlot], 16);
+            return;
+        }
+    for (int i = 1; i < m; ++i) {
+        const int sv = a.member[b + i];
+        const int key = a.perm[sv];
+        int j = i - 1;
+        while (j >= 0 && a.perm[a.member[b + j]] > key) {
+            a.member[b + j + 1] = a.member[b + j];
+            --j;
+        }
+        a.member[b + j + 1] = sv;
+    }
+}
+
+struct PaperDrawArgs {
+    PaperArgs p;
+    int* batch;                // [K][n_slots][P]
+    int* n_pop;                // [n_slots]: N_I
+    uint64_t seed;
+    uint64_t step0;
+    const uint64_t* step_dev;  // if set, the draw's first step is *step_dev + step0
+    int K;
+    int P;
+};
+
+constexpr int kPaperRuns = 256;  // x-runs of a stencil: 2 (2h+1)^2 <= 256, h <= 5
+
+// The members of a stencil axis around cell c, ascending: cells p0..p0+l0-1
+// then p1..p1+l1-1 (l1 = 0 without a periodic wrap).
+__device__ __forceinline__ void paper_axis(int c, int nc, int h, int& p0, int& l0, int& p1, int& l1)
+{
+    p1 = 0;
+    l1 = 0;
+    if (2 * h + 1 >= nc) {
+        p0 = 0;
+        l0 = nc;
+        return;
+    }
+    const int lo = c - h, hi = c + h;
+    if (lo < 0) {
+        p0 = 0;
+        l0 = hi + 1;
+        p1 = lo + nc;
+        l1 = -lo;
+    } else if (hi > nc - 1) {
+        p0 = 0;
+        l0 = hi - nc + 1;
+        p1 = lo;
+        l1 = nc - lo;
+    } else {
+        p0 = lo;
+        l0 = 2 * h + 1;
+    }
+}
+
+// One wavefront per paper cell: the stencil's x-runs (contiguous member
+// positions) with their prefix counts in LDS, N_I = their total; then one
+// lane per (particle, step) pair draws P positions k in [0, N_I) (Floyd on
+// the same Philox stream as the shell draw) and maps each to its member by
+// a binary search over the prefix counts.
+template <int PMAX>
+__global__ __launch_bounds__(256) void k_paper_draw(PaperDrawArgs d)
+{
+    __shared__ int s_start[4][kPaperRuns];
+    __shared__ int s_pre[4][kPaperRuns];
+    const PaperArgs& a = d.p;
+    if (gated_off(a.gate)) return;
+    const int lane = threadIdx.x & 63;
+    const int w = rfl((int)(threadIdx.x >> 6));
+    const int64_t cell = xcd_tile(blockIdx.x, gridDim.x) * 4 + w;
+    if (cell >= a.n_cells) return;
+    const int m = rfl(a.count[cell]);
+    if (m == 0) return;
+    const int b = rfl(a.start[cell]);
+    const int r = rfl(a.cell_rep[cell]);
+    const PaperGrid* G = a.grid + r;
+    const int nc0 = rfl(G->nc[0]), nc1 = rfl(G->nc[1]), nc2 = rfl(G->nc[2]);
+    const int h = rfl(G->h);
+    const int64_t base = rfl(G->cell_base);
+    const int64_t lc = cell - base;
+    const int cx = (int)(lc % nc0);
+    const int cy = (int)((lc / nc0) % nc1);
+    const int cz = (int)(lc / ((int64_t)nc0 * nc1));
+    int px0, lx0, px1, lx1, py0, ly0, py1, ly1, pz0, lz0, pz1, lz1;
+    paper_axis(cx, nc0, h, px0, lx0, px1, lx1);
+    paper_axis(cy, nc1, h, py0, ly0, py1, ly1);
+    paper_axis(cz, nc2, h, pz0, lz0, pz1, lz1);
+    const int nxr = lx1 > 0 ? 2 : 1;
+    const int ny = ly0 + ly1;
+    const int nruns = (lz0 + lz1) * ny * nxr;
+    if (nruns > kPaperRuns || b < 0 || (int64_t)b + m > a.n_slots) {
+        if (lane == 0) atomicOr(&a.flags[kFlagBadSlot], 16);
+        return;
+    }
+    // run q = (z index, y index, x part); entries past the last run hold
+    // the total, which the binary search relies on
+    int carry = 0;
+    bool bad = false;
+#pragma unroll
+    for (int k = 0; k < kPaperRuns / 64; ++k) {
+        const int q = k * 64 + lane;
+        int st = 0, len = 0;
+        if (q < nruns) {
+            const int xr = q % nxr;
+            const int yz = q / nxr;
+            const int yi = yz % ny;
+            const int zi = yz / ny;
+            const int zc = zi < lz0 ? pz0 + zi : pz1 + (zi - lz0);
+            const int yc = yi < ly0 ? py0 + yi : py1 + (yi - ly0);
+            const int px = xr == 0 ? px0 : px1;
+            const int lx = xr == 0 ? lx0 : lx1;
+            const int64_t row = base + ((int64_t)zc * nc1 + yc) * nc0;
+            st = a.start[row + px];
+            len = a.start[row + px + lx - 1] + a.count[row + px + lx - 1] - st;
+            bad |= st < 0 || len < 0 || (int64_t)st + len > a.n_slots;
+        }
+        const int incl = wave_incl_scan(len);
+        s_start[w][q] = st;
+        s_pre[w][q] = carry + incl - len;
+        carry += __builtin_amdgcn_readlane(incl, 63);
+    }
+    for (int t = lane; t < m; t += 64) bad |= (uint64_t)(uint32_t)a.member[b + t] >= (uint64_t)a.n_slots;
+    if (__ballot(bad)) {
+        if (lane == 0) atomicOr(&a.flags[kFlagBadSlot], 16);
+        return;
+    }
+    const int NI = rfl(carry);
+    for (int t = lane; t < m; t += 64) d.n_pop[a.member[b + t]] = NI;
+    wave_lds_fence();
+    const uint64_t s0 = d.step_dev ? *d.step_dev + d.step0 : d.step0;
+    const int P = d.P;
+    const bool small = NI <= P;
+    const int64_t id_base = rfl(a.rep[r].id_base);
+    const int pairs = m * d.K;
+    for (int pb = 0; pb < pairs; pb += 64) {
+        const int pr = pb + lane;
+        if (pr >= pairs) continue;
+        const int ii = pr / d.K;
+        const int rr = pr - ii * d.K;
+        const int si = a.member[b + ii];
+        const uint32_t pid = (uint32_t)(a.perm[si] - id_base);
+        uint32_t S[PMAX];
+        floyd_draw<PMAX>(S, d.seed, pid, (uint32_t)(s0 + rr), (uint32_t)r, P, small ? P + 1 : NI);
+        int* out = d.batch + batch_index(rr, si, 0, a.n_slots, P);
+        int val[PMAX];
+#pragma unroll
+        for (int qq = 0; qq < PMAX; ++qq) {
+            val[qq] = si;
+            if (qq < P) {
+                const uint32_t k = small ? (uint32_t)qq : S[qq];
+                if ((int)k < NI) {
+                    int q = 0;
+#pragma unroll
+                    for (int st = kPaperRuns / 2; st > 0; st >>= 1)
+                        if (s_pre[w][q + st] <= (int)k) q += st;
+                    const int j = a.member[s_start[w][q] + (int)k - s_pre[w][q]];
+                    val[qq] = (uint64_t)(uint32_t)j < (uint64_t)a.n_slots ? j : si;
+                }
+            }
+        }
+        if ((P & 1) == 0) {
+#pragma unroll
+            for (int qq = 0; qq < PMAX; qq += 2)
+                if (qq < P) *reinterpret_cast<int2*>(out + qq) = make_int2(val[qq], val[qq + 1]);
+        } else {
+#pragma unroll
+            for (int qq = 0; qq < PMAX; ++qq)
+                if (qq < P) out[qq] = val[qq];
+        }
     }
 }
 

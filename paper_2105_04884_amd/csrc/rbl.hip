@@ -136,6 +136,20 @@ struct rbl_ctx {
     int cap_list = 0;           // fused kernel: LDS shell-list room per centre particle
     bool stencil = false;       // batches drawn from the stencil cells (N_I in d_nI)
     int* d_nI = nullptr;        // stencil draw population size per slot
+    // the paper's own grid (shell_source RBL_SHELL_PAPER): per-replica grids,
+    // per-cell counts and starts, per-slot cell and rank, members by cell
+    bool paper = false;
+    bool pop_valid = false;     // d_nI holds N_I of the last build (a draw ran on it)
+    int64_t n_pcells = 0;
+    int64_t pcells_alloc = 0;
+    PaperGrid* d_pgrid = nullptr;
+    int* d_pcell_rep = nullptr;
+    int* d_pcount = nullptr;
+    int* d_pstart = nullptr;
+    int* d_ptile = nullptr;
+    int* d_pcell_of_slot = nullptr;
+    int* d_prank = nullptr;
+    int* d_pmember = nullptr;
 
     // Langevin thermostat (rbl_set_thermostat) and the continuous trajectory
     double gamma = 0.0;              // friction; 0: NVE
@@ -340,6 +354,64 @@ rbl_status clear_list_flags(rbl_ctx* c) { return fill_i32(c, c->d_flags, kFlagMa
 // ---------------------------------------------------------------------------
 // geometry
 
+// The paper's own grid (Sec. II): cells of edge w = (r_s + skin)(1 + 1e-6)
+// per replica, stencil half-width h = floor((r_c + skin)/w) + 1.  The x-runs
+// of one stencil, 2 (2h+1)^2 at most, must fit the draw kernel's table.
+rbl_status setup_paper_grid(rbl_ctx* c, double r_s, double r_c)
+{
+    const double skin = c->cfg.skin;
+    const double w = (r_s + skin) * 1.000001;
+    const int h = (int)std::floor((r_c + skin) / w) + 1;
+    std::vector<PaperGrid> g(c->R);
+    int64_t base = 0;
+    for (int r = 0; r < c->R; ++r) {
+        PaperGrid& G = g[r];
+        std::memset(&G, 0, sizeof(G));
+        int64_t runs = 1, cells = 1;
+        for (int a = 0; a < 3; ++a) {
+            const double L = c->h_rep[r].L[a];
+            double nc = std::floor(L / w);
+            if (nc < 1.0) nc = 1.0;
+            if (nc > 4096) return fail(RBL_E_BOX, "box too large for the paper's cell grid");
+            G.nc[a] = (int)nc;
+            G.scale[a] = (double)G.nc[a] / L;
+            const int64_t span = std::min<int64_t>(2 * h + 1, G.nc[a]);
+            runs *= a == 0 ? (2 * h + 1 < G.nc[a] ? 2 : 1) : span;
+            cells *= G.nc[a];
+        }
+        if (runs > kPaperRuns)
+            return fail(RBL_E_ARG, "the paper's stencil (half-width " + std::to_string(h) +
+                                       " cells) exceeds the draw kernel's run table");
+        G.h = h;
+        G.cell_base = base;
+        base += cells;
+    }
+    if (base > (int64_t)1 << 30) return fail(RBL_E_BOX, "too many cells in the paper's grid");
+    if ((base + kScanTile - 1) / kScanTile > 1024 * kScanPerThread)
+        return fail(RBL_E_BOX, "the paper's grid exceeds the scan capacity");
+    if (base > c->pcells_alloc) {
+        dfree(c->d_pcell_rep);
+        dfree(c->d_pcount);
+        dfree(c->d_pstart);
+        dfree(c->d_ptile);
+        RBL_TRY(dalloc(&c->d_pcell_rep, base));
+        RBL_TRY(dalloc(&c->d_pcount, base));
+        RBL_TRY(dalloc(&c->d_pstart, base));
+        RBL_TRY(dalloc(&c->d_ptile, (base + kScanTile - 1) / kScanTile + 1));
+        c->pcells_alloc = base;
+    }
+    std::vector<int> cell_rep(base);
+    for (int r = 0; r < c->R; ++r) {
+        const int64_t nc = (int64_t)g[r].nc[0] * g[r].nc[1] * g[r].nc[2];
+        std::fill(cell_rep.begin() + g[r].cell_base, cell_rep.begin() + g[r].cell_base + nc, r);
+    }
+    HIP_TRY(hipMemcpyAsync(c->d_pgrid, g.data(), sizeof(PaperGrid) * c->R, hipMemcpyHostToDevice, c->ls));
+    HIP_TRY(hipMemcpyAsync(c->d_pcell_rep, cell_rep.data(), sizeof(int) * base, hipMemcpyHostToDevice, c->ls));
+    HIP_TRY(hipStreamSynchronize(c->ls));
+    c->n_pcells = base;
+    return RBL_OK;
+}
+
 rbl_status setup_geometry(rbl_ctx* c, const double* box, double r_s, double r_c)
 {
     const double skin = c->cfg.skin;
@@ -407,6 +479,7 @@ rbl_status setup_geometry(rbl_ctx* c, const double* box, double r_s, double r_c)
     }
     c->r_s = r_s;
     c->r_c = r_c;
+    if (c->paper) RBL_TRY(setup_paper_grid(c, r_s, r_c));
     // Mixed-precision forces classify from fixed-point copies of the
     // positions (x / L mod 1 in units of 2^-32).  With u = 2^-53 and
     // coordinates below X = 1024 (L_max + r_c) in magnitude, a stored word
@@ -694,6 +767,70 @@ rbl_status build_lists(rbl_ctx* c, int mask)
 // step0+K-1 in one pass (no shell rows in HBM).
 rbl_status ensure_batch(rbl_ctx* c, int K, int P);
 
+PaperArgs paper_args(rbl_ctx* c, const uint64_t* gate)
+{
+    PaperArgs a;
+    a.grid = c->d_pgrid;
+    a.rep = c->d_rep;
+    a.slice_rep = c->d_slice_rep;
+    a.cell_rep = c->d_pcell_rep;
+    a.xs = c->cur_xs();
+    a.perm = c->cur_perm();
+    a.n_slots = c->n_slots;
+    a.n_cells = c->n_pcells;
+    a.cell_of_slot = c->d_pcell_of_slot;
+    a.rank = c->d_prank;
+    a.count = c->d_pcount;
+    a.start = c->d_pstart;
+    a.member = c->d_pmember;
+    a.flags = c->d_flags;
+    a.gate = gate;
+    return a;
+}
+
+// Bins the current (build) positions into the paper's grid: counts, an
+// exclusive scan into member positions, scatter, and the in-cell order by
+// ID.  Gated like the rest of a build.
+void paper_bin(rbl_ctx* c, const uint64_t* gate)
+{
+    const PaperArgs a = paper_args(c, gate);
+    const int64_t tiles = (c->n_pcells + kScanTile - 1) / kScanTile;
+    k_clear_counts<<<grid_for(c->n_pcells), kBlock, 0, c->ls>>>(c->d_pcount, c->n_pcells, gate);
+    k_paper_count<<<grid_for(c->n_slots), kBlock, 0, c->ls>>>(a);
+    k_scan_tiles<<<(unsigned)tiles, kScanBlock, 0, c->ls>>>(c->d_pcount, c->n_pcells, c->d_ptile, gate);
+    k_scan_tile_sums<<<1, 1024, 0, c->ls>>>(c->d_ptile, (int)tiles, gate);
+    k_scan_final<<<(unsigned)tiles, kScanBlock, 0, c->ls>>>(c->d_pcount, c->n_pcells, c->d_ptile, nullptr,
+                                                          nullptr, c->d_pstart, gate);
+    k_paper_scatter<<<grid_for(c->n_slots), kBlock, 0, c->ls>>>(a);
+    k_paper_sort<<<grid_for(c->n_pcells), kBlock, 0, c->ls>>>(a);
+}
+
+// The batches of K force evaluations from step0 (or *step_dev + step0),
+// drawn from the paper-grid stencils of the last build, and N_I per slot.
+void paper_draw(rbl_ctx* c, int P, uint64_t seed, uint64_t step0, int K, const uint64_t* step_dev,
+                const uint64_t* gate)
+{
+    PaperDrawArgs d;
+    d.p = paper_args(c, gate);
+    d.batch = c->d_batch;
+    d.n_pop = c->d_nI;
+    d.seed = seed;
+    d.step0 = step0;
+    d.step_dev = step_dev;
+    d.K = K;
+    d.P = P;
+    const unsigned g = grid_for(c->n_pcells, 4);
+#define RBL_PD(PM) k_paper_draw<PM><<<g, kBlock, 0, c->ls>>>(d)
+    if (P <= 8) RBL_PD(8);
+    else if (P <= 12) RBL_PD(12);
+    else if (P <= 16) RBL_PD(16);
+    else if (P <= 24) RBL_PD(24);
+    else if (P <= 32) RBL_PD(32);
+    else if (P <= 64) RBL_PD(64);
+    else RBL_PD(128);
+#undef RBL_PD
+}
+
 // Queues the fused build (core rows, shell counts, batches of K force
 // evaluations from step0, or from *step_dev + step0 when step_dev is set).
 rbl_status launch_fused(rbl_ctx* c, int P, uint64_t seed, uint64_t step0, int K,
@@ -733,6 +870,19 @@ rbl_status launch_fused(rbl_ctx* c, int P, uint64_t seed, uint64_t step0, int K,
                                             std::max<int64_t>(fit, ((int64_t)2 * c->cap_list + 63) / 64 * 64));
     const size_t lds = c->stencil ? 0 : (size_t)4 * (fa.list_budget + 64) * sizeof(unsigned short);
     const unsigned g = grid_for(c->n_cells, 4);
+    if (c->paper) {
+        // core rows on the binning grid (no draws there), then the paper
+        // grid's binning at a build, and the draws from its stencils
+        if (!draw_only) {
+            FusedArgs fc = fa;
+            fc.K = 0;
+            RBL_TRY(timed(c, kKBuild, [&] { launch_k(c, k_build_draw<8, true>, g, 0, fc); }, true));
+            RBL_TRY(timed(c, kKBuild, [&] { paper_bin(c, fa.b.gate); }));
+        }
+        c->pop_valid = true;
+        return timed(c, kKBuild, [&] { paper_draw(c, P, seed, step0, K, step_dev, fa.b.gate); });
+    }
+    if (c->stencil) c->pop_valid = true;
     return timed(c, kKBuild, [&] {
 #define RBL_BD(PM)                                                    \
     do {                                                              \
@@ -1641,6 +1791,14 @@ rbl_status rbl_destroy(rbl_ctx* c)
     }
     dfree(c->d_batch);
     dfree(c->d_nI);
+    dfree(c->d_pgrid);
+    dfree(c->d_pcell_rep);
+    dfree(c->d_pcount);
+    dfree(c->d_pstart);
+    dfree(c->d_ptile);
+    dfree(c->d_pcell_of_slot);
+    dfree(c->d_prank);
+    dfree(c->d_pmember);
     dfree(c->d_osig);
     dfree(c->d_img);
     dfree(c->d_img_delta);
@@ -1674,8 +1832,9 @@ rbl_status rbl_create(const rbl_config* cfg, void* hip_stream, rbl_ctx** out)
     if (!(cfg->capacity_factor > 0.0) || !std::isfinite(cfg->capacity_factor))
         return fail(RBL_E_ARG, "capacity_factor must be > 0");
     if (cfg->pair == RBL_PAIR_LJ_ERFC && !(cfg->alpha > 0.0)) return fail(RBL_E_ARG, "alpha must be > 0");
-    if (cfg->shell_source != RBL_SHELL_LIST && cfg->shell_source != RBL_SHELL_STENCIL)
-        return fail(RBL_E_ARG, "shell_source must be RBL_SHELL_LIST or RBL_SHELL_STENCIL");
+    if (cfg->shell_source != RBL_SHELL_LIST && cfg->shell_source != RBL_SHELL_STENCIL &&
+        cfg->shell_source != RBL_SHELL_PAPER)
+        return fail(RBL_E_ARG, "shell_source must be RBL_SHELL_LIST, RBL_SHELL_STENCIL or RBL_SHELL_PAPER");
     if (cfg->reserved != 0) return fail(RBL_E_ARG, "reserved must be 0");
     std::vector<int64_t> off(cfg->n_replicas + 1);
     if (cfg->n_replicas == 1) {
@@ -1697,7 +1856,8 @@ rbl_status rbl_create(const rbl_config* cfg, void* hip_stream, rbl_ctx** out)
     c->n = cfg->n;
     if (cfg->lanes > 0) c->lpp_rbl = c->lpp_full = cfg->lanes;
     c->persist[0] = c->persist[1] = cfg->persistent == 2;
-    c->stencil = cfg->shell_source == RBL_SHELL_STENCIL;
+    c->stencil = cfg->shell_source != RBL_SHELL_LIST;
+    c->paper = cfg->shell_source == RBL_SHELL_PAPER;
     c->kT.assign(c->R, 1.0);
     {
         int dev = 0, ncu = 0;
@@ -1745,6 +1905,12 @@ rbl_status rbl_create(const rbl_config* cfg, void* hip_stream, rbl_ctx** out)
     CR(dalloc(&c->d_xs[0], c->n_slots));
     CR(dalloc(&c->d_xs[1], c->n_slots));
     if (cfg->precision == RBL_PREC_MIXED) CR(dalloc(&c->d_xq, c->n_slots));
+    if (c->paper) {
+        CR(dalloc(&c->d_pgrid, c->R));
+        CR(dalloc(&c->d_pcell_of_slot, c->n_slots));
+        CR(dalloc(&c->d_prank, c->n_slots));
+        CR(dalloc(&c->d_pmember, c->n_slots));
+    }
     CR(dalloc(&c->d_vs[0], 3 * c->n_slots));
     CR(dalloc(&c->d_vs[1], 3 * c->n_slots));
     CR(dalloc(&c->d_xb, 3 * c->n_slots));
@@ -1792,11 +1958,13 @@ rbl_status rbl_build(rbl_ctx* c, const double* pos, const double* box, double r_
         return fail(RBL_E_ARG, "radii must satisfy 0 < r_s < r_c");
     RBL_TRY(setup_geometry(c, box, r_s, r_c));
     c->run.valid = false;
+    c->pop_valid = false;
     set_draw(c, 0, 0, 0);
     c->built = false;
     c->shell_counts = false;
     RBL_TRY(clear_flags(c));
     RBL_TRY(bin_particles<kSrcCaller>(c, pos, nullptr, false));
+    if (c->paper) paper_bin(c, nullptr);
     RBL_TRY(build_lists(c, c->cfg.lists));
     c->built = true;
     return RBL_OK;
@@ -2016,7 +2184,7 @@ rbl_status rbl_row_counts(rbl_ctx* c, int64_t nrows, const int64_t* rows, int64_
     (void)hipMemcpyAsync(d_rows, h_rows.data(), sizeof(int64_t) * nrows, hipMemcpyHostToDevice, c->ls);
     for (int q = 0; q < 3; ++q) {
         const bool valid = q == 1 ? c->shell_counts : ((c->built_mask >> q) & 1) != 0;
-        const int* len = valid ? c->d_len[q] : nullptr;
+        const int* len = valid ? c->d_len[q] : (q == 1 && c->stencil && c->pop_valid ? c->d_nI : nullptr);
         k_row_counts<<<grid_for(nrows), kBlock, 0, c->ls>>>(d_rows, nrows, c->d_slot_of_id, len, d_cnt);
         (void)hipMemcpyAsync(counts + q * nrows, d_cnt, sizeof(int64_t) * nrows, hipMemcpyDeviceToHost,
                              c->ls);

@@ -1052,3 +1052,22 @@ def test_paper_grid_against_the_built_grid_at_the_table_i_radii():
         e_paper, n_paper = res["stencil, paper cells"][P]
         assert n_paper < n_grid
         assert e_shell < e_paper < e_grid
+
+
+def test_paper_grid_md_run_draws_from_the_paper_rows():
+    """The oracle's run with the paper-grid population: its first force
+    evaluation after the entry build equals rbl_forces on the paper-grid
+    rows of the build state (mean-subtracted), and differs from the run on
+    the (r_c + skin)/2 grid's stencil rows."""
+    st = inputs.lj_fluid(1500, 0.8442, 1.0, seed=8)
+    runs = {}
+    for src in ("paper", "stencil"):
+        runs[src] = oracle.md_run(st.pos, st.vel, st.box, RS, RC, SKIN, 0.005, 1, p=10, seed=4, K=10,
+                                  shell_source=src)
+    x1, _, f1, _ = runs["paper"]
+    x0 = oracle.wrap(st.pos, st.box)
+    L = oracle.System(x0, st.box, RS, RC, SKIN).paper_stencil_lists()
+    f, _, _ = oracle.rbl_forces(x1, st.box, RS, RC, L, 10, 4, 1)
+    f, _ = oracle.mean_subtract(f)
+    assert np.max(np.abs(f - f1)) <= 1e-12 * np.max(np.abs(f1))
+    assert not np.allclose(runs["stencil"][2], f1)
