@@ -623,15 +623,17 @@ def run_table1(torch, equil=200_000, prod=100_000, every=1000, runs=10):
 def force_error_vs_oracle(x0, box, torch, rows):
     """Relative L2 error of the raw RBL force (P = 10, no mean subtraction)
     against the FP64 CPU oracle on sampled rows, for both precisions and
-    both draw populations (keys "stencil_*": the stencil cells)."""
+    the three draw populations (keys "stencil_*": the stencil cells of the
+    search grid, "paper_*": those of the paper's own grid)."""
     import oracle
     from paper_2105_04884_amd import Context
     pos = x0.cpu().numpy()
     sysm = oracle.System(pos, box, RS, RC, SKIN)
     out = {}
-    for source, prefix in (("shell", ""), ("stencil", "stencil_")):
+    for source, prefix in (("shell", ""), ("stencil", "stencil_"), ("paper", "paper_")):
         L = (sysm.lists(rows=rows, kinds=("core", "shell")) if source == "shell"
-             else sysm.stencil_lists(rows=rows))
+             else sysm.stencil_lists(rows=rows) if source == "stencil"
+             else sysm.paper_stencil_lists(rows=rows))
         fo, _, _ = oracle.rbl_forces(pos, box, RS, RC, L, 10, 1, 0)
         for precision in ("fp64", "mixed"):
             with Context(N, precision=precision, momentum_fix=False, shell_source=source) as ctx:
@@ -717,21 +719,25 @@ def cpu_oracle(st, rows_1core, workers, full=False):
     return out
 
 
-def method_error(x0, box):
+def method_error(x0, box, rs=RS, rc=RC, Ps=(5, 10, 20)):
     """Relative L2 distance of the RBL force from the full-list force at the
     same state (mean force subtracted, as in the MD loop) for each batch
     size: the statistical error of the method itself, not an error of the
-    implementation.  Keys "stencil_P" draw from the stencil cells instead of
-    the shell rows."""
+    implementation.  Keys "stencil_P" draw from the stencil cells of the
+    search grid, "paper_P" from those of the paper's own grid, instead of
+    the shell rows; "population" holds the mean draw population (n_i, or
+    N_I) of each."""
     from paper_2105_04884_amd import Context
-    out = {}
-    for source, prefix in (("shell", ""), ("stencil", "stencil_")):
-        with Context(N, precision="fp64", lists=("core", "shell", "full"), shell_source=source) as ctx:
-            ctx.build(x0, box, RS, RC)
+    out = {"population": {}}
+    for source, prefix in (("shell", ""), ("stencil", "stencil_"), ("paper", "paper_")):
+        lists = ("core", "shell", "full") if source == "shell" else ("core", "full")
+        with Context(N, precision="fp64", lists=lists, shell_source=source) as ctx:
+            ctx.build(x0, box, rs, rc)
             ff = ctx.full_forces(x0)
-            for P in (5, 10, 20):
+            for P in Ps:
                 f = ctx.forces(P, seed=1, step=0, pos=x0)
                 out[prefix + str(P)] = float((f - ff).norm() / ff.norm())
+            out["population"][source] = float(ctx.row_counts()[1].mean())
     return out
 
 
@@ -927,6 +933,9 @@ def main(argv=None):
         ("rbl_mixed_p5", "mixed", 5, False, "shell", True),
         ("rbl_mixed_p20", "mixed", 20, False, "shell", True),
         ("rbl_stencil_mixed_p10", "mixed", 10, False, "stencil", True),
+        # the paper's own grid at skin 0.3 (cells of 1.8, 7^3 of them): at
+        # skin 0.5 its cells of 2.0 would coincide with the search grid's
+        ("rbl_paper_mixed_p10", "mixed", 10, False, "paper", True),
         # fixed 10-step lifetimes at skin 0.3 (no displacement check: some
         # particles pass skin/2 within a lifetime, status RBL_W_SKIN)
         ("rbl_mixed_p10_fixed10", "mixed", 10, False, "shell", False),
@@ -942,7 +951,7 @@ def main(argv=None):
         if not check:
             skin, life = SKIN, K_REBUILD
         else:
-            skin, life = (SKIN_FULL, LIFE_FULL) if full else (SKIN_RBL, LIFE_RBL)
+            skin, life = (SKIN_FULL, LIFE_FULL) if full or source == "paper" else (SKIN_RBL, LIFE_RBL)
             skin = args.skin if args.skin is not None else skin
             life = args.max_lifetime if args.max_lifetime is not None else life
         results[name] = run_variant(name, x0, v0, st.box, prec, P, full, warmup, steps, args.repeats,
@@ -977,6 +986,8 @@ def main(argv=None):
     errs = guarded("force error", force_error_vs_oracle, x0, st.box, torch, rows)
     log("[bench] method error of RBL against the full list")
     merr = guarded("method error", method_error, x0, st.box)
+    log("[bench] method error at the Sec. III radii (r_s = 2, r_c = 6)")
+    merr_wide = guarded("method error (r_s = 2, r_c = 6)", method_error, x0, st.box, 2.0, 6.0, (10, 20, 50))
 
     extra = {}
     wl = [w for w in args.workloads.split(",") if w and w != "none"]
@@ -1042,6 +1053,7 @@ def main(argv=None):
                                           if speed("rbl_mixed_p10") and speed("rbl_fp64_p10") else None),
         "force_rel_l2_err_vs_fp64_oracle": errs,
         "method_rel_l2_rbl_vs_full_list": merr,
+        "method_rel_l2_rbl_vs_full_list_rs2_rc6": merr_wide,
         "cpu_baseline_full_list": cpu_full,
         "workloads": extra,
     }
