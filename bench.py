@@ -764,6 +764,34 @@ def kernel_class(name, P):
     return None
 
 
+# A kernel that is launched every step but works only at some (the list
+# build with rebuilds on displacement returns at once while its gate is
+# clear) is summarised over its working dispatches: those whose primary
+# measure (duration, or the counter of the run) reaches ACTIVE_FRACTION of
+# the kernel's largest.
+ACTIVE_FRACTION = 0.05
+
+
+def active_mean(values):
+    """(count, mean) over the working dispatches of one kernel (see
+    ACTIVE_FRACTION); all of them when none stands out."""
+    v = np.asarray(values, dtype=float)
+    if v.size == 0:
+        return 0, 0.0
+    keep = v[v >= ACTIVE_FRACTION * v.max()] if v.max() > 0 else v
+    return int(keep.size), float(keep.mean())
+
+
+def trace_durations(trace_dir):
+    """Per kernel name, the list of dispatch durations (ns) of a rocprofv3
+    kernel trace."""
+    rows = _read_csv(trace_dir, "kernel_trace.csv")
+    out = {}
+    for r in rows:
+        out.setdefault(r["Kernel_Name"], []).append(float(r["End_Timestamp"]) - float(r["Start_Timestamp"]))
+    return out
+
+
 def summarize(trace_dir, fetch_dir, write_dir, command, calib_mib, P=10):
     """Writes profiles/kernel_trace_n1m.txt (per-kernel launch statistics)
     and profiles/hbm_traffic_n1m.txt (HBM bytes per launch of each kernel
@@ -781,6 +809,13 @@ def summarize(trace_dir, fetch_dir, write_dir, command, calib_mib, P=10):
         lines.append(f"{int(r['Calls']):7d} {float(r['TotalDurationNs']) / 1e6:10.3f} "
                      f"{float(r['AverageNs']) / 1e3:10.2f} {float(r['MinNs']) / 1e3:10.2f} "
                      f"{float(r['MaxNs']) / 1e3:10.2f} {float(r['Percentage']):6.2f}  {r['Name']}")
+    durs = trace_durations(trace_dir)
+    lines += ["", "# working dispatches (duration >= 5% of the kernel's longest) of kernels",
+              "# that also return at once: calls, average us, kernel"]
+    for name, v in sorted(durs.items()):
+        n_act, mean = active_mean(v)
+        if n_act < len(v):
+            lines.append(f"active {n_act:7d} {mean / 1e3:10.2f}  {name}")
     with open(os.path.join(PROFILES, "kernel_trace_n1m.txt"), "w") as f:
         f.write("\n".join(lines) + "\n")
 
@@ -801,7 +836,7 @@ def summarize(trace_dir, fetch_dir, write_dir, command, calib_mib, P=10):
                 continue
             agg.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
         for name, vals in agg.items():
-            per.setdefault(name, {})[tag] = (len(vals), float(np.mean(vals)))
+            per.setdefault(name, {})[tag] = active_mean(vals)
     lines = ["# HBM traffic per kernel launch from two rocprofv3 counter runs of bench.py,",
              "# N = 1,000,000 LJ fluid (density 0.8442)",
              f"# command 1: rocprofv3 --pmc FETCH_SIZE -d <dir> -o bench --output-format csv "
@@ -813,7 +848,8 @@ def summarize(trace_dir, fetch_dir, write_dir, command, calib_mib, P=10):
              f"WRITE_SIZE x{factors['WRITE_SIZE']:.4f} of that",
              f"calibration fetch_factor {factors['FETCH_SIZE']:.6f} write_factor {factors['WRITE_SIZE']:.6f}",
              f"source_sha256 {kernel_source_hash()}",
-             "# per kernel: dispatches, mean FETCH_SIZE KiB, mean WRITE_SIZE KiB (raw), name", ""]
+             "# per kernel: working dispatches (counter >= 5% of its largest), mean FETCH_SIZE KiB,",
+             "# mean WRITE_SIZE KiB (raw), name", ""]
     classes = {}
     for name, d in sorted(per.items(), key=lambda kv: -kv[1].get("FETCH_SIZE", (0, 0))[1]):
         nf, fk = d.get("FETCH_SIZE", (0, 0.0))
@@ -846,10 +882,21 @@ def summarize_valu(valu_dir, trace_dir, command, P=10):
     157.3 TFLOP/s) and the VALU busy fraction
     SQ_ACTIVE_INST_VALU * 4 / (SIMDs * GRBM_GUI_ACTIVE per XCD)."""
     rows = _read_csv(valu_dir, "counter_collection.csv")
-    stats = {r["Name"]: float(r["AverageNs"]) for r in _read_csv(trace_dir, "kernel_stats.csv")}
-    per = {}
+    stats = {name: active_mean(v)[1] for name, v in trace_durations(trace_dir).items()}
+    by_dispatch = {}
     for r in rows:
-        per.setdefault(r["Kernel_Name"], {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+        by_dispatch.setdefault((r["Kernel_Name"], r["Dispatch_Id"]), {})[r["Counter_Name"]] = float(r["Counter_Value"])
+    per = {}
+    for (name, _), d in by_dispatch.items():
+        per.setdefault(name, []).append(d)
+    for name, ds in per.items():
+        top = max(d.get("SQ_INSTS_VALU", 0.0) for d in ds)
+        work = [d for d in ds if d.get("SQ_INSTS_VALU", 0.0) >= ACTIVE_FRACTION * top] if top > 0 else ds
+        merged = {}
+        for d in work:
+            for k, v in d.items():
+                merged.setdefault(k, []).append(v)
+        per[name] = merged
     simds, xcds = 256 * 4, 8
     classes = {}
     for name, d in per.items():
@@ -876,7 +923,7 @@ def summarize_valu(valu_dir, trace_dir, command, P=10):
              "# N = 1,000,000 LJ fluid (density 0.8442)",
              f"# command: rocprofv3 --pmc {' '.join(VALU_COUNTERS)} -d <dir> -o bench "
              f"--output-format csv -- python3 bench.py {command}",
-             "# durations from the kernel trace of profiles/kernel_trace_n1m.txt; the FLOPS counters "
+             "# durations and counters over working dispatches (see kernel_trace_n1m.txt); the FLOPS counters "
              "count per wavefront instruction (an FMA counts two), so flops = 64 x counter",
              f"source_sha256 {kernel_source_hash()}",
              "# valu <class> <json>", ""]

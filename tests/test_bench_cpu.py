@@ -164,3 +164,14 @@ def test_msd_of_a_free_langevin_particle():
     assert np.all(np.abs(msd - exact) < 0.08 * exact), (msd[:5], exact[:5])
     slope = bench.msd_slope(t, msd)
     assert abs(slope - 6.0 * kT / gamma) < 0.1 * 6.0 * kT / gamma, slope
+
+
+def test_active_mean_skips_dispatches_that_return_at_once():
+    """A build kernel launched every step that works at one step in ten:
+    its summary averages the working dispatches only; a kernel that works at
+    every dispatch keeps all of them."""
+    gated = [1.2e6] + [3e3] * 9 + [1.25e6] + [2.5e3] * 9
+    assert bench.active_mean(gated) == (2, 1.225e6)
+    steady = [110.0, 108.0, 112.0]
+    assert bench.active_mean(steady) == (3, 110.0)
+    assert bench.active_mean([]) == (0, 0.0)
