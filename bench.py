@@ -95,6 +95,9 @@ def parse(argv=None):
                          "'ensemble' (512 replicas), 'large' (N = 2^24), 'slab' (charged "
                          "slab, N = 2M, LJ + erfc), 'table1' (the Sec. III coexistence "
                          "study: minutes of GPU time, not in the default), or 'none'")
+    ap.add_argument("--summarize-requests", nargs=2, metavar=("READ_DIR", "WRITE_DIR"),
+                    help="write profiles/request_sizes_n1m.txt from two rocprofv3 --pmc runs "
+                         "of the request counters (see REQUEST_COUNTERS)")
     ap.add_argument("--summarize", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
                     help="instead of running: write the profiles/ summaries from the output "
                          "folders of a rocprofv3 --kernel-trace --stats run and two --pmc runs "
@@ -934,6 +937,55 @@ def summarize_valu(valu_dir, trace_dir, command, P=10):
     print("\n".join(lines))
 
 
+REQUEST_COUNTERS = (["TCC_EA0_RDREQ_DRAM_32B", "TCC_EA0_RDREQ", "TCC_EA0_RDREQ_32B", "TCC_BUBBLE"],
+                    ["TCC_EA0_WRREQ", "TCC_EA0_WRREQ_64B", "TCC_EA0_WRREQ_DRAM"])
+
+
+def summarize_requests(rd_dir, wr_dir, command, P=10):
+    """Writes profiles/request_sizes_n1m.txt: per kernel class, the L2-to-memory
+    read and write requests by size over the working dispatches, the bytes
+    they imply (TCC_EA0_RDREQ_DRAM_32B counts a request in 32-byte units),
+    and what FETCH_SIZE's formula makes of the same requests, so that the
+    copy calibration of the traffic figures can be checked kernel by kernel."""
+    per = {}
+    for tag, folder, key in (("rd", rd_dir, "TCC_EA0_RDREQ"), ("wr", wr_dir, "TCC_EA0_WRREQ")):
+        by = {}
+        for r in _read_csv(folder, "counter_collection.csv"):
+            by.setdefault((r["Kernel_Name"], r["Dispatch_Id"]), {})[r["Counter_Name"]] = float(r["Counter_Value"])
+        names = {}
+        for (name, _), d in by.items():
+            names.setdefault(name, []).append(d)
+        for name, ds in names.items():
+            top = max(d.get(key, 0.0) for d in ds)
+            work = [d for d in ds if d.get(key, 0.0) >= ACTIVE_FRACTION * top] if top > 0 else ds
+            m = {c: float(np.mean([d.get(c, 0.0) for d in work])) for c in work[0]}
+            per.setdefault(name, {}).update(m)
+    lines = ["# L2-to-memory requests by size per kernel launch (working dispatches), two rocprofv3",
+             "# counter runs of bench.py, N = 1,000,000 LJ fluid (density 0.8442)",
+             f"# command 1: rocprofv3 --pmc {' '.join(REQUEST_COUNTERS[0])} -d <dir> -o bench "
+             f"--output-format csv -- python3 bench.py {command}",
+             f"# command 2: rocprofv3 --pmc {' '.join(REQUEST_COUNTERS[1])} -d <dir> -o bench "
+             f"--output-format csv -- python3 bench.py {command}",
+             "# read bytes = 32 x TCC_EA0_RDREQ_DRAM_32B (a request counted in 32-byte units);",
+             "# FETCH_SIZE's formula on this architecture: 128 BUBBLE + 64 (RDREQ - BUBBLE - RDREQ_32B)",
+             "# + 32 RDREQ_32B bytes; write bytes = 64 WRREQ_64B + 32 (WRREQ - WRREQ_64B)",
+             f"source_sha256 {kernel_source_hash()}",
+             "# columns: RDREQ, RDREQ_32B, BUBBLE, RDREQ_DRAM_32B, read MB, FETCH_SIZE formula MB,",
+             "# bytes per read request, WRREQ, WRREQ_64B, write MB, kernel", ""]
+    shown = [(n, m) for n, m in per.items() if kernel_class(n, P) or "copyBuffer" in n]
+    for name, m in sorted(shown, key=lambda kv: -kv[1].get("TCC_EA0_RDREQ", 0.0)):
+        rq, r32, bub = m.get("TCC_EA0_RDREQ", 0.0), m.get("TCC_EA0_RDREQ_32B", 0.0), m.get("TCC_BUBBLE", 0.0)
+        dram = m.get("TCC_EA0_RDREQ_DRAM_32B", 0.0)
+        fetch = bub * 128 + (rq - bub - r32) * 64 + r32 * 32
+        wq, w64 = m.get("TCC_EA0_WRREQ", 0.0), m.get("TCC_EA0_WRREQ_64B", 0.0)
+        lines.append(f"{rq:11.4e} {r32:10.3e} {bub:10.3e} {dram:11.4e} {32 * dram / 1e6:9.1f} {fetch / 1e6:9.1f} "
+                     f"{32 * dram / rq if rq else 0.0:6.1f} {wq:11.4e} {w64:11.4e} "
+                     f"{(w64 * 64 + (wq - w64) * 32) / 1e6:9.1f}  {name}")
+    with open(os.path.join(PROFILES, "request_sizes_n1m.txt"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def guarded(name, fn, *a, **kw):
     """Runs an optional part of the bench; a failure is logged and recorded
     instead of ending the run before the JSON line."""
@@ -946,6 +998,9 @@ def guarded(name, fn, *a, **kw):
 
 def main(argv=None):
     args = parse(argv)
+    if args.summarize_requests:
+        summarize_requests(*args.summarize_requests, args.profile_command)
+        return
     if args.summarize:
         summarize(*args.summarize, args.profile_command, args.calib_copy_mb)
         if args.valu_dir:
