@@ -814,6 +814,18 @@ __device__ __forceinline__ int select_lanes(uint64_t mask, int a, int b)
     return r;
 }
 
+// Wave masks of per-lane FP64 compares (llvm.amdgcn.fcmp; an ordered
+// predicate, so a NaN compares false).
+__device__ __forceinline__ uint64_t cmp_lt_mask(double x, double t)
+{
+    return __builtin_amdgcn_fcmp(x, t, 4);  // FCMP_OLT
+}
+
+__device__ __forceinline__ uint64_t cmp_ge_mask(double x, double t)
+{
+    return __builtin_amdgcn_fcmp(x, t, 3);  // FCMP_OGE
+}
+
 constexpr int kCtrMax = 16;        // centre particles per group
 constexpr int kListBudgetMax = 6912;  // 16-bit shell-list entries per wavefront, at most
                                       // (the block's LDS stays within 64 KB)
@@ -1011,13 +1023,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PMAX <= 32 
             // lanes where `live`): core partners written to the centre's
             // row, shell candidates appended to its LDS list
             auto test_chunk = [&](int jc, const double4& xc, int code, int ent, bool live) {
+                const uint64_t lmask = __builtin_amdgcn_ballot_w64(live);
                 auto test = [&](int ii, double dx, double dy, double dz) {
                     const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
                     const int slot_ii = i0 + g0 + ii;
-                    const bool other = live && jc != slot_ii;
-                    const bool is_core = other && r2 < a.thr_core;
-                    const uint64_t mc = __ballot(is_core);
+                    // the classifications as wave masks, each compare a
+                    // single v_cmp (a ballot of a combined bool would first
+                    // turn it into 0/1 in a VGPR and compare that again)
+                    const uint64_t other = lmask & __builtin_amdgcn_ballot_w64(jc != slot_ii);
+                    const uint64_t mc = other & cmp_lt_mask(r2, a.thr_core);
                     if (mc) {
+                        const bool is_core = __builtin_amdgcn_inverse_ballot_w64(mc);
                         // straight into row ii (sliced ELL) in candidate order;
                         // entries past the row's room are counted, not written
                         const int basec = rfl((int)__builtin_amdgcn_readlane((int)ncore, ii));
@@ -1030,7 +1046,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PMAX <= 32 
                         ncore = (uint32_t)rbl_writelane(basec + (int)__popcll(mc), ii, (int)ncore);
                     }
                     if constexpr (STENCIL) return;
-                    const uint64_t ms = __ballot(other && r2 >= a.thr_shell_in && r2 < a.thr_out);
+                    const uint64_t ms = other & cmp_ge_mask(r2, a.thr_shell_in) & cmp_lt_mask(r2, a.thr_out);
                     const int base = rfl((int)__builtin_amdgcn_readlane((int)nshell, ii));
                     // every lane writes (no branch): a selected lane to its list
                     // position (clamped into the room; an overflowing run is
