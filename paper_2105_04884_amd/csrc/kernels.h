@@ -1752,14 +1752,21 @@ __device__ __forceinline__ void force_tile(const ForceArgs& a, int64_t tile, uin
             const double cut = MODE == kShellNone ? a.rc2 : a.rs2;
             const int len = a.core_len[slot];
             const int* row = a.core + ell(slot, 0, a.cap_core);
+            // the row entries of the next group are loaded before this
+            // group's gathers, so their latency overlaps the gathers'
+            int jn[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) jn[u] = u < len ? row[(int64_t)u * 64] : (int)slot;
             for (int k = 0; k < len; k += U) {
                 int j[U];
                 bool live[U];
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     live[u] = k + u < len;
-                    j[u] = live[u] ? row[(int64_t)(k + u) * 64] : (int)slot;
+                    j[u] = jn[u];
                 }
+#pragma unroll
+                for (int u = 0; u < U; ++u) jn[u] = k + U + u < len ? row[(int64_t)(k + U + u) * 64] : (int)slot;
                 gather_accumulate<PREC, ENERGY, ERFC, U>(a, xi, qi, j, live, -1.0, cut, R, c);
             }
         }
@@ -1893,13 +1900,27 @@ __device__ __forceinline__ void force_tile_lpp(const ForceArgs& a, int64_t tile)
             const double cut = MODE == kShellNone ? a.rc2 : a.rs2;
             const int len = a.core_len[slot];
             const int* row = a.core + ell(slot, 0, a.cap_core);
+            // next group's row entries in flight during this group's gathers
+            // (not for FP64 records at 4 lanes, whose two loads per
+            // neighbour already fill the memory pipeline: 9% slower there)
+            constexpr bool PF = PREC == kMixed || LPP <= 2;
+            int jn[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) jn[u] = l + u * LPP < len ? row[(int64_t)(l + u * LPP) * 64] : (int)slot;
             for (int k = l; k < len; k += U * LPP) {
                 int j[U];
                 bool live[U];
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     live[u] = k + u * LPP < len;
-                    j[u] = live[u] ? row[(int64_t)(k + u * LPP) * 64] : (int)slot;
+                    j[u] = PF ? jn[u] : (live[u] ? row[(int64_t)(k + u * LPP) * 64] : (int)slot);
+                }
+                if constexpr (PF) {
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        const int kn = k + U * LPP + u * LPP;
+                        jn[u] = kn < len ? row[(int64_t)kn * 64] : (int)slot;
+                    }
                 }
                 gather_accumulate<PREC, ENERGY, ERFC, U>(a, xi, qi, j, live, -1.0, cut, R, c);
             }
