@@ -48,6 +48,13 @@ def load():
     lib.orc_cell_grid.argtypes = [_f64p, C.c_double, C.c_double, _i32p]
     lib.orc_sys_new.argtypes = [C.c_int64, _f64p, _f64p, C.c_double, C.c_double, C.c_double]
     lib.orc_sys_new.restype = C.c_void_p
+    lib.orc_sys_new_typed.argtypes = [C.c_int64, _f64p, _f64p, C.c_double, C.c_double, C.c_double,
+                                      C.c_int, C.c_void_p, C.c_void_p]
+    lib.orc_sys_new_typed.restype = C.c_void_p
+    lib.orc_sys_stencil.argtypes = [C.c_void_p, C.c_int, _i32p]
+    lib.orc_sys_stencil.restype = C.c_int
+    lib.orc_lj_typed.argtypes = [C.c_double, C.c_double, C.c_double,
+                                 C.POINTER(C.c_double), C.POINTER(C.c_double)]
     lib.orc_sys_free.argtypes = [C.c_void_p]
     lib.orc_sys_ncells.argtypes = [C.c_void_p]
     lib.orc_sys_ncells.restype = C.c_int64
@@ -61,11 +68,12 @@ def load():
     lib.orc_forces_rbl.argtypes = [C.c_int64, _f64p, _f64p, C.c_double, C.c_double, C.c_int,
                                    C.c_int64, C.c_void_p, _i64p, _i32p, _i64p, _i32p,
                                    C.c_int, C.c_uint64, C.c_uint64, C.c_uint32, C.c_void_p,
-                                   C.c_void_p, C.c_double, _f64p, _f64p, _f64p]
+                                   C.c_void_p, C.c_double, _f64p, _f64p, _f64p,
+                                   C.c_int, C.c_void_p, C.c_void_p]
     lib.orc_forces_rbl.restype = C.c_int
     lib.orc_forces_full.argtypes = [C.c_int64, _f64p, _f64p, C.c_double, C.c_int,
                                     C.c_int64, C.c_void_p, _i64p, _i32p, C.c_void_p, C.c_double,
-                                    _f64p, _f64p, _f64p]
+                                    _f64p, _f64p, _f64p, C.c_int, C.c_void_p, C.c_void_p]
     lib.orc_forces_full.restype = C.c_int
     lib.orc_mean_subtract.argtypes = [C.c_int64, _f64p, _f64p]
     lib.orc_stencil_rows.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]
@@ -76,7 +84,8 @@ def load():
                                C.c_double, C.c_double, C.c_int64, C.c_int, C.c_uint64,
                                C.c_int64, C.c_int, C.c_int, C.c_int, C.c_int, C.c_uint32,
                                C.c_void_p, C.c_double, C.c_int, C.c_double, C.c_double,
-                               C.c_void_p, _f64p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]
+                               C.c_void_p, _f64p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p,
+                               C.c_int, C.c_void_p, C.c_void_p]
     lib.orc_paper_stencil_rows.argtypes = [C.c_int64, _f64p, _f64p, C.c_double, C.c_double, C.c_double,
                                            C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                            C.c_void_p]
@@ -126,6 +135,30 @@ def lj(r2: float):
     return f.value, u.value
 
 
+def lj_typed(r2: float, eps: float, sig: float):
+    """(fmag, u) of the LJ pair with its own epsilon and sigma (unshifted)."""
+    lib = load()
+    f = C.c_double()
+    u = C.c_double()
+    lib.orc_lj_typed(float(r2), float(eps), float(sig), C.byref(f), C.byref(u))
+    return f.value, u.value
+
+
+def _types(types, eps_sig, n):
+    """(nt, type array, table) for the C calls: nt = 0 without types."""
+    if types is None:
+        if eps_sig is not None:
+            raise ValueError("eps_sig needs types")
+        return 0, None, None
+    t = np.ascontiguousarray(types, dtype=np.int32)
+    es = np.ascontiguousarray(eps_sig, dtype=np.float64)
+    if t.shape != (n,):
+        raise ValueError("types must have one entry per particle")
+    if es.ndim != 3 or es.shape[0] != es.shape[1] or es.shape[2] != 2:
+        raise ValueError("eps_sig must be shaped (n_types, n_types, 2)")
+    return int(es.shape[0]), t, es
+
+
 def erfc_pair(r2: float, qq: float, alpha: float):
     """(fmag, u) of the real-space Ewald term qq erfc(alpha r)/r (unshifted)."""
     lib = load()
@@ -172,14 +205,31 @@ class System:
     """Positions at a list build: wrapped copy, canonical cell binning, and
     neighbour lists for any subset of rows."""
 
-    def __init__(self, pos, box, rs: float, rc: float, skin: float):
+    def __init__(self, pos, box, rs: float, rc: float, skin: float, types=None, eps_sig=None):
+        """``types`` (one per particle) and ``eps_sig`` ((n_types, n_types, 2)
+        table of epsilon_ab, sigma_ab): a system of several particle types,
+        pair radii rs sigma_ab and rc sigma_ab, cells sized by the smallest
+        cut-off and one stencil per type."""
         lib = load()
+        self._lib = lib
+        self._h = None
         self.pos = np.ascontiguousarray(pos, dtype=np.float64)
         self.box = np.ascontiguousarray(box, dtype=np.float64)
         self.n = int(self.pos.shape[1])
         self.rs, self.rc, self.skin = float(rs), float(rc), float(skin)
-        self._h = lib.orc_sys_new(self.n, self.pos, self.box, rs, rc, skin)
-        self._lib = lib
+        self.nt, self.types, self.eps_sig = _types(types, eps_sig, self.n)
+        h = lib.orc_sys_new_typed(self.n, self.pos, self.box, rs, rc, skin, self.nt,
+                                  _ptr_or_null(self.types), _ptr_or_null(self.eps_sig))
+        if not h:
+            raise ValueError("invalid type table")
+        self._h = h
+
+    def type_stencil(self, a: int) -> np.ndarray:
+        """Stencil half-widths (3,) of centre type a (typed systems)."""
+        out = np.zeros(3, dtype=np.int32)
+        if self._lib.orc_sys_stencil(self._h, int(a), out):
+            raise ValueError("untyped system or bad type")
+        return out
 
     def __del__(self):
         if getattr(self, "_h", None):
@@ -299,10 +349,12 @@ def _charges(charges, n):
 
 
 def rbl_forces(pos, box, rs, rc, lists: Lists, p: int, seed: int, step: int,
-               replica: int = 0, shift: bool = True, pid=None, charges=None, alpha: float = 0.0):
+               replica: int = 0, shift: bool = True, pid=None, charges=None, alpha: float = 0.0,
+               types=None, eps_sig=None):
     """Raw RBL force (before mean subtraction) for the rows of ``lists``.
     With ``charges`` the real-space Ewald term (screening ``alpha``) is added
-    to the LJ pair.  Returns (f (3, nrows), e (nrows,), w (nrows,))."""
+    to the LJ pair; with ``types``/``eps_sig`` each pair takes its own LJ
+    parameters and radii.  Returns (f (3, nrows), e (nrows,), w (nrows,))."""
     lib = load()
     pos = np.ascontiguousarray(pos, dtype=np.float64)
     nrows = lists.rows.shape[0]
@@ -311,25 +363,33 @@ def rbl_forces(pos, box, rs, rc, lists: Lists, p: int, seed: int, step: int,
     w = np.zeros(nrows)
     pid_arr = None if pid is None else np.ascontiguousarray(pid, dtype=np.int64)
     q = _charges(charges, pos.shape[1])
-    lib.orc_forces_rbl(pos.shape[1], pos, np.asarray(box, dtype=np.float64), rs, rc, int(shift),
-                       nrows, lists.rows.ctypes.data_as(C.c_void_p),
-                       lists.core_off, lists.core_idx, lists.shell_off, lists.shell_idx,
-                       p, seed, step, replica, _ptr_or_null(pid_arr), _ptr_or_null(q), float(alpha),
-                       f, e, w)
+    nt, t, es = _types(types, eps_sig, pos.shape[1])
+    r = lib.orc_forces_rbl(pos.shape[1], pos, np.asarray(box, dtype=np.float64), rs, rc, int(shift),
+                           nrows, lists.rows.ctypes.data_as(C.c_void_p),
+                           lists.core_off, lists.core_idx, lists.shell_off, lists.shell_idx,
+                           p, seed, step, replica, _ptr_or_null(pid_arr), _ptr_or_null(q), float(alpha),
+                           f, e, w, nt, _ptr_or_null(t), _ptr_or_null(es))
+    if r:
+        raise ValueError(f"orc_forces_rbl failed ({r})")
     return f, e, w
 
 
-def full_forces(pos, box, rc, lists: Lists, shift: bool = True, charges=None, alpha: float = 0.0):
+def full_forces(pos, box, rc, lists: Lists, shift: bool = True, charges=None, alpha: float = 0.0,
+                types=None, eps_sig=None):
     lib = load()
     pos = np.ascontiguousarray(pos, dtype=np.float64)
     q = _charges(charges, pos.shape[1])
+    nt, t, es = _types(types, eps_sig, pos.shape[1])
     nrows = lists.rows.shape[0]
     f = np.zeros((3, nrows))
     e = np.zeros(nrows)
     w = np.zeros(nrows)
-    lib.orc_forces_full(pos.shape[1], pos, np.asarray(box, dtype=np.float64), rc, int(shift),
-                        nrows, lists.rows.ctypes.data_as(C.c_void_p),
-                        lists.full_off, lists.full_idx, _ptr_or_null(q), float(alpha), f, e, w)
+    r = lib.orc_forces_full(pos.shape[1], pos, np.asarray(box, dtype=np.float64), rc, int(shift),
+                            nrows, lists.rows.ctypes.data_as(C.c_void_p),
+                            lists.full_off, lists.full_idx, _ptr_or_null(q), float(alpha), f, e, w,
+                            nt, _ptr_or_null(t), _ptr_or_null(es))
+    if r:
+        raise ValueError(f"orc_forces_full failed ({r})")
     return f, e, w
 
 
@@ -345,7 +405,7 @@ def md_run(pos, vel, box, rs, rc, skin, dt, nsteps, p=10, seed=1, step0=0, K=10,
            use_full=False, shift=True, momentum_fix=True, replica=0, want_ev=False,
            charges=None, alpha: float = 0.0, shell_source: str = "shell",
            gamma: float = 0.0, kT: float = 1.0, unwrapped=None, check: bool = False,
-           builds=None):
+           builds=None, types=None, eps_sig=None):
     """Run of Algorithm 1: velocity Verlet (NVE) for gamma = 0, Langevin
     (BAOAB, friction gamma, bath temperature kT) otherwise.  Returns (pos,
     vel, force, ev) with ev of shape (nsteps+1, 2) = (U, W) per force
@@ -354,13 +414,14 @@ def md_run(pos, vel, box, rs, rc, skin, dt, nsteps, p=10, seed=1, step0=0, K=10,
     rebuilt before every evaluation s with s % K == 0, or with ``check``
     when some particle has moved more than skin/2 since the last build or K
     steps have passed; ``builds`` (a list) receives the steps of the
-    builds."""
+    builds.  ``types``/``eps_sig``: particle types (see System)."""
     lib = load()
     x = np.ascontiguousarray(pos, dtype=np.float64).copy()
     v = np.ascontiguousarray(vel, dtype=np.float64).copy()
     f = np.zeros_like(x)
     ev = np.zeros((nsteps + 1, 2)) if want_ev else None
     q = _charges(charges, x.shape[1])
+    nt, t, es = _types(types, eps_sig, x.shape[1])
     if unwrapped is not None:
         if (not isinstance(unwrapped, np.ndarray) or unwrapped.dtype != np.float64
                 or unwrapped.shape != x.shape or not unwrapped.flags.c_contiguous):
@@ -372,7 +433,8 @@ def md_run(pos, vel, box, rs, rc, skin, dt, nsteps, p=10, seed=1, step0=0, K=10,
                        replica, _ptr_or_null(q), float(alpha),
                        {"shell": 0, "stencil": 1, "paper": 2}[shell_source], float(gamma), float(kT),
                        _ptr_or_null(unwrapped), f, _ptr_or_null(ev), int(bool(check)),
-                       bsteps.ctypes.data_as(C.c_void_p), nb.ctypes.data_as(C.c_void_p))
+                       bsteps.ctypes.data_as(C.c_void_p), nb.ctypes.data_as(C.c_void_p),
+                       nt, _ptr_or_null(t), _ptr_or_null(es))
     if r:
         raise RuntimeError(f"orc_md_run failed ({r})")
     if builds is not None:

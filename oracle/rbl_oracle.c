@@ -27,6 +27,14 @@
  *                       without-replacement moments of Appendix A.
  *   orc_lj              LJ 12-6 pair potential eq. (1), truncated at the
  *                       cut-off and shifted to zero there (Sec. II).
+ *   orc_lj_typed        the same with the pair's epsilon and sigma, for
+ *                       systems of several particle types whose interaction
+ *                       lengths differ (Sec. II): pair (a, b) has its own
+ *                       epsilon_ab, sigma_ab, core radius rs sigma_ab and
+ *                       cut-off rc sigma_ab; the cell grid takes its width
+ *                       from the smallest cut-off and each type searches its
+ *                       own stencil of cells, wide enough for its largest
+ *                       cut-off (orc_sys_new_typed).
  *   orc_erfc_pair       real-space Ewald term q_i q_j erfc(alpha r)/r of a
  *                       pair of charges, added to the LJ pair for charged
  *                       systems (the short-range part that a random-batch
@@ -174,6 +182,19 @@ void orc_lj(double r2, double* fmag, double* u)
     *u = 4.0 * sr6 * (sr6 - 1.0);
 }
 
+/* Pair term of eq. (1) with the pair's own parameters:
+ *   U(r) = 4 eps ((sigma/r)^12 - (sigma/r)^6),
+ *   fmag = -dU/dr / r = 24 eps r^-2 (sigma/r)^6 (2 (sigma/r)^6 - 1).
+ * With eps = sigma = 1 every operation below is that of orc_lj. */
+void orc_lj_typed(double r2, double eps, double sig, double* fmag, double* u)
+{
+    double r2i = 1.0 / r2;
+    double s2 = (sig * sig) * r2i;
+    double sr6 = s2 * s2 * s2;
+    *fmag = (24.0 * eps) * r2i * sr6 * (2.0 * sr6 - 1.0);
+    *u = (4.0 * eps) * sr6 * (sr6 - 1.0);
+}
+
 /* Real-space Ewald pair of charges with product qq at squared distance r2:
  *   u(r) = qq erfc(alpha r) / r,
  *   -du/dr = qq [erfc(alpha r) / r^2 + (2 alpha / sqrt(pi)) exp(-alpha^2 r^2) / r],
@@ -239,6 +260,66 @@ static double dist2(const double* pos, int64_t n, int64_t i, int64_t j,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Particle types (Sec. II, systems with a large disparity in interaction
+ * lengths).  nt types, nt <= ORC_MAX_TYPES; type[i] of particle ID i;
+ * eps_sig[(a nt + b) 2 + 0 / 1] = epsilon_ab / sigma_ab of pair (a, b),
+ * symmetric, positive.  Pair (a, b) interacts by orc_lj_typed with core
+ * radius rs sigma_ab and cut-off rc sigma_ab (rs, rc in units of sigma);
+ * with `shift` its energy is shifted to zero at its own cut-off.  nt = 0
+ * means one type with epsilon = sigma = 1 (eq. (1) as in orc_lj). */
+
+#define ORC_MAX_TYPES 4
+
+typedef struct {
+    int nt;
+    int32_t* type;                                     /* own copy, per ID */
+    double eps[ORC_MAX_TYPES][ORC_MAX_TYPES];
+    double sig[ORC_MAX_TYPES][ORC_MAX_TYPES];
+    double rs2[ORC_MAX_TYPES][ORC_MAX_TYPES];          /* (rs sigma_ab)^2 */
+    double rc2[ORC_MAX_TYPES][ORC_MAX_TYPES];          /* (rc sigma_ab)^2 */
+    double ush[ORC_MAX_TYPES][ORC_MAX_TYPES];          /* energy at the cut-off (0: no shift) */
+} orc_types;
+
+/* Fills T (T->type is malloc'ed; free with types_free).  Returns 0, or -4
+ * for an invalid type count, table or type index. */
+static int types_setup(orc_types* T, int64_t n, int nt, const int32_t* type, const double* eps_sig,
+                       double rs, double rc, int shift)
+{
+    memset(T, 0, sizeof(*T));
+    if (nt == 0) return 0;
+    if (nt < 1 || nt > ORC_MAX_TYPES || !type || !eps_sig) return -4;
+    for (int a = 0; a < nt; ++a)
+        for (int b = 0; b < nt; ++b) {
+            double e = eps_sig[(a * nt + b) * 2 + 0], g = eps_sig[(a * nt + b) * 2 + 1];
+            if (!(e >= 0.0) || !(g > 0.0) || !isfinite(e) || !isfinite(g)) return -4;
+            if (e != eps_sig[(b * nt + a) * 2 + 0] || g != eps_sig[(b * nt + a) * 2 + 1]) return -4;
+            T->eps[a][b] = e;
+            T->sig[a][b] = g;
+            double rsab = rs * g, rcab = rc * g;
+            T->rs2[a][b] = rsab * rsab;
+            T->rc2[a][b] = rcab * rcab;
+            T->ush[a][b] = 0.0;
+            if (shift) {
+                double fm;
+                orc_lj_typed(T->rc2[a][b], e, g, &fm, &T->ush[a][b]);
+            }
+        }
+    T->type = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; ++i) {
+        if (type[i] < 0 || type[i] >= nt) { free(T->type); T->type = NULL; return -4; }
+        T->type[i] = type[i];
+    }
+    T->nt = nt;
+    return 0;
+}
+
+static void types_free(orc_types* T)
+{
+    free(T->type);
+    T->type = NULL;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Canonical cell list.  Positions are first wrapped into the box; cells have
  * edge >= (rc + skin)/2, so any pair closer than rc + skin lies within two
  * cells of each other in every direction.  Particles are ordered by cell
@@ -259,6 +340,8 @@ typedef struct orc_sys {
     int64_t *slot_of;     /* per ID */
     int64_t *id_of;       /* per slot */
     int64_t *cell_start;  /* ncells + 1 */
+    orc_types T;          /* particle types (T.nt == 0: one type) */
+    int h[ORC_MAX_TYPES][3];  /* typed: stencil half-width per centre type and axis */
 } orc_sys;
 
 void orc_wrap(int64_t n, double* pos, const double box[3])
@@ -298,10 +381,21 @@ static int64_t cell_of_pos(const orc_sys* s, int64_t i)
     return (c[2] * s->ncell[1] + c[1]) * s->ncell[0] + c[0];
 }
 
-orc_sys* orc_sys_new(int64_t n, const double* pos, const double box[3],
-                     double rs, double rc, double skin)
+/* With particle types (nt > 0) the cells take their width from the
+ * smallest pair cut-off, rc times the smallest sigma_ab, and a centre of
+ * type a searches the cells within h_a of its own along each axis, h_a the
+ * number of cell edges (times 1 + 1e-6) that its largest pair cut-off plus
+ * the skin spans: the per-type stencils of Sec. II.  Returns NULL for an
+ * invalid type table. */
+orc_sys* orc_sys_new_typed(int64_t n, const double* pos, const double box[3],
+                           double rs, double rc, double skin,
+                           int nt, const int32_t* type, const double* eps_sig)
 {
     orc_sys* s = (orc_sys*)calloc(1, sizeof(orc_sys));
+    if (types_setup(&s->T, n, nt, type, eps_sig, rs, rc, 0)) {
+        free(s);
+        return NULL;
+    }
     s->n = n;
     for (int a = 0; a < 3; ++a) {
         s->box[a] = box[a];
@@ -311,7 +405,25 @@ orc_sys* orc_sys_new(int64_t n, const double* pos, const double box[3],
     s->pos = (double*)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
     memcpy(s->pos, pos, sizeof(double) * 3 * (size_t)n);
     orc_wrap(n, s->pos, box);
-    orc_cell_grid(box, rc, skin, s->ncell);
+    if (nt == 0) {
+        orc_cell_grid(box, rc, skin, s->ncell);
+    } else {
+        double smin = s->T.sig[0][0];
+        for (int a = 0; a < nt; ++a)
+            for (int b = 0; b < nt; ++b)
+                if (s->T.sig[a][b] < smin) smin = s->T.sig[a][b];
+        orc_cell_grid(box, rc * smin, skin, s->ncell);
+        for (int a = 0; a < nt; ++a) {
+            double smax = 0.0;
+            for (int b = 0; b < nt; ++b)
+                if (s->T.sig[a][b] > smax) smax = s->T.sig[a][b];
+            double reach = (rc * smax + skin) * 1.000001;
+            for (int ax = 0; ax < 3; ++ax) {
+                double edge = box[ax] / (double)s->ncell[ax];
+                s->h[a][ax] = (int)ceil(reach / edge);
+            }
+        }
+    }
     s->ncells = (int64_t)s->ncell[0] * s->ncell[1] * s->ncell[2];
     s->cell_of = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n + 1));
     s->slot_of = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n + 1));
@@ -334,11 +446,27 @@ orc_sys* orc_sys_new(int64_t n, const double* pos, const double box[3],
     return s;
 }
 
+orc_sys* orc_sys_new(int64_t n, const double* pos, const double box[3],
+                     double rs, double rc, double skin)
+{
+    return orc_sys_new_typed(n, pos, box, rs, rc, skin, 0, NULL, NULL);
+}
+
 void orc_sys_free(orc_sys* s)
 {
     if (!s) return;
     free(s->pos); free(s->cell_of); free(s->slot_of); free(s->id_of); free(s->cell_start);
+    types_free(&s->T);
     free(s);
+}
+
+/* Stencil half-widths of a typed system for centre type a (h[3]); returns
+ * -1 for an untyped system or a bad type. */
+int orc_sys_stencil(const orc_sys* s, int a, int32_t h[3])
+{
+    if (s->T.nt == 0 || a < 0 || a >= s->T.nt) return -1;
+    for (int ax = 0; ax < 3; ++ax) h[ax] = s->h[a][ax];
+    return 0;
 }
 
 int64_t orc_sys_ncells(const orc_sys* s) { return s->ncells; }
@@ -399,20 +527,26 @@ static void classify(const orc_sys* s, orc_thr th, int64_t i, int64_t j,
 {
     double d[3];
     double r2 = dist2(s->pos, s->n, i, j, s->box, s->inv, d);
+    if (s->T.nt) {
+        /* the pair's own radii: core rs sigma_ab, cut-off rc sigma_ab */
+        double g = s->T.sig[s->T.type[i]][s->T.type[j]];
+        th = thresholds(s->rs * g, s->rc * g, s->skin);
+    }
     if (r2 < th.core) row_push(&row->core, &row->nc, &cap->ccap, j);
     if (r2 >= th.shell_in && r2 < th.out) row_push(&row->shell, &row->ns, &cap->scap, j);
     if (r2 < th.out) row_push(&row->full, &row->nf, &cap->fcap, j);
 }
 
-/* unique wrapped cell coordinates within +-2 of c along an axis of nc cells */
-static int stencil_axis(int c, int nc, int out[5])
+/* unique wrapped cell coordinates within +-h of c along an axis of nc
+ * cells (out holds min(2h + 1, nc) entries) */
+static int stencil_axis(int c, int nc, int h, int* out)
 {
     int k = 0;
-    if (nc <= 2 * ORC_HALF_STENCIL + 1) {
+    if (nc <= 2 * h + 1) {
         for (int q = 0; q < nc; ++q) out[k++] = q;
         return k;
     }
-    for (int d = -ORC_HALF_STENCIL; d <= ORC_HALF_STENCIL; ++d)
+    for (int d = -h; d <= h; ++d)
         out[k++] = ((c + d) % nc + nc) % nc;
     return k;
 }
@@ -437,10 +571,18 @@ static void build_row(const orc_sys* s, orc_thr th, int method, int64_t i,
         int cx = (int)(ci % s->ncell[0]);
         int cy = (int)((ci / s->ncell[0]) % s->ncell[1]);
         int cz = (int)(ci / ((int64_t)s->ncell[0] * s->ncell[1]));
-        int sx[5], sy[5], sz[5];
-        int nx = stencil_axis(cx, s->ncell[0], sx);
-        int ny = stencil_axis(cy, s->ncell[1], sy);
-        int nz = stencil_axis(cz, s->ncell[2], sz);
+        /* the stencil: +-2 cells, or a typed centre's own half-widths */
+        int hx = ORC_HALF_STENCIL, hy = ORC_HALF_STENCIL, hz = ORC_HALF_STENCIL;
+        if (s->T.nt) {
+            int t = s->T.type[i];
+            hx = s->h[t][0]; hy = s->h[t][1]; hz = s->h[t][2];
+        }
+        int* sx = (int*)malloc(sizeof(int) * (size_t)(2 * hx + 1));
+        int* sy = (int*)malloc(sizeof(int) * (size_t)(2 * hy + 1));
+        int* sz = (int*)malloc(sizeof(int) * (size_t)(2 * hz + 1));
+        int nx = stencil_axis(cx, s->ncell[0], hx, sx);
+        int ny = stencil_axis(cy, s->ncell[1], hy, sy);
+        int nz = stencil_axis(cz, s->ncell[2], hz, sz);
         for (int a = 0; a < nz; ++a)
             for (int b = 0; b < ny; ++b)
                 for (int c = 0; c < nx; ++c) {
@@ -450,6 +592,7 @@ static void build_row(const orc_sys* s, orc_thr th, int method, int64_t i,
                         if (j != i) classify(s, th, i, j, row, cap);
                     }
                 }
+        free(sx); free(sy); free(sz);
     }
     g_sort_sys = s;
     qsort(row->core, (size_t)row->nc, sizeof(int64_t), cmp_slot);
@@ -517,6 +660,7 @@ int orc_list_fill(const orc_sys* s, int method, int64_t nrows, const int64_t* ro
 int orc_stencil_rows(const orc_sys* s, int64_t nrows, const int64_t* rows, int64_t* off,
                      int32_t* idx)
 {
+    if (s->T.nt) return -4;  /* the stencil population is a one-type form */
     int64_t cap = 64;
     int64_t* buf = (int64_t*)malloc(sizeof(int64_t) * (size_t)cap);
     for (int64_t k = 0; k < nrows; ++k) {
@@ -527,9 +671,9 @@ int orc_stencil_rows(const orc_sys* s, int64_t nrows, const int64_t* rows, int64
         int cy = (int)((ci / s->ncell[0]) % s->ncell[1]);
         int cz = (int)(ci / ((int64_t)s->ncell[0] * s->ncell[1]));
         int sx[5], sy[5], sz[5];
-        int nx = stencil_axis(cx, s->ncell[0], sx);
-        int ny = stencil_axis(cy, s->ncell[1], sy);
-        int nz = stencil_axis(cz, s->ncell[2], sz);
+        int nx = stencil_axis(cx, s->ncell[0], ORC_HALF_STENCIL, sx);
+        int ny = stencil_axis(cy, s->ncell[1], ORC_HALF_STENCIL, sy);
+        int nz = stencil_axis(cz, s->ncell[2], ORC_HALF_STENCIL, sz);
         int64_t m = 0;
         for (int a = 0; a < nz; ++a)
             for (int b = 0; b < ny; ++b)
@@ -644,12 +788,42 @@ int orc_paper_stencil_rows(int64_t n, const double* pos, const double box[3], do
 }
 
 /* ------------------------------------------------------------------------ */
+/* Pair (i, j) at squared distance r2: the factor of x_i - x_j and the energy
+ * shifted by the cut-off value (one type: LJ plus the erfc term of charges;
+ * typed: the pair's own LJ), and the pair's squared radii. */
+static void pair_eval(const orc_types* T, orc_shift sh, const double* q, double alpha,
+                      int64_t i, int64_t j, double r2, double* fmag, double* ushifted)
+{
+    double u;
+    if (T->nt) {
+        int a = T->type[i], b = T->type[j];
+        orc_lj_typed(r2, T->eps[a][b], T->sig[a][b], fmag, &u);
+        *ushifted = u - T->ush[a][b];
+        return;
+    }
+    pair_term(r2, q, alpha, i, j, fmag, &u);
+    *ushifted = u - pair_shift(sh, q, i, j);
+}
+
+static double pair_rs2(const orc_types* T, double rs2, int64_t i, int64_t j)
+{
+    return T->nt ? T->rs2[T->type[i]][T->type[j]] : rs2;
+}
+
+static double pair_rc2(const orc_types* T, double rc2, int64_t i, int64_t j)
+{
+    return T->nt ? T->rc2[T->type[i]][T->type[j]] : rc2;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Forces.  Positions `pos` ([3][n]) are the current ones (not necessarily
  * the ones the lists were built at); every pair is classified by its current
  * squared distance.  Row k of the CSR lists belongs to particle rows[k]
  * (rows == NULL: row k is particle k).  Outputs per row: f ([3][nrows]),
  * e (pair energy, half per particle), w (virial sum of r.f, half per
- * particle).  No mean-force subtraction here. */
+ * particle).  No mean-force subtraction here.  nt, type, eps_sig: particle
+ * types as in orc_sys_new_typed (nt = 0: one type; not with charges);
+ * returns -4 for an invalid type table. */
 
 int orc_forces_rbl(int64_t n, const double* pos, const double box[3],
                    double rs, double rc, int shift,
@@ -658,11 +832,14 @@ int orc_forces_rbl(int64_t n, const double* pos, const double box[3],
                    const int64_t* shell_off, const int32_t* shell_idx,
                    int p, uint64_t seed, uint64_t step, uint32_t replica,
                    const int64_t* pid, const double* charge, double alpha,
-                   double* f, double* e, double* w)
+                   double* f, double* e, double* w,
+                   int nt, const int32_t* type, const double* eps_sig)
 {
     double inv[3] = {1.0 / box[0], 1.0 / box[1], 1.0 / box[2]};
     double rs2 = rs * rs, rc2 = rc * rc;
     orc_shift sh = cutoff_shift(rc2, shift, charge, alpha);
+    orc_types T;
+    if ((nt && charge) || types_setup(&T, n, nt, type, eps_sig, rs, rc, shift)) return -4;
     int32_t* K = (int32_t*)malloc(sizeof(int32_t) * (size_t)(p > 0 ? p : 1));
     for (int64_t k = 0; k < nrows; ++k) {
         int64_t i = rows ? rows[k] : k;
@@ -672,10 +849,10 @@ int orc_forces_rbl(int64_t n, const double* pos, const double box[3],
         for (int64_t q = core_off[k]; q < core_off[k + 1]; ++q) {
             int64_t j = core_idx[q];
             double r2 = dist2(pos, n, i, j, box, inv, d);
-            if (r2 < rs2) {
-                pair_term(r2, charge, alpha, i, j, &fm, &u);
+            if (r2 < pair_rs2(&T, rs2, i, j)) {
+                pair_eval(&T, sh, charge, alpha, i, j, r2, &fm, &u);
                 for (int a = 0; a < 3; ++a) Fc[a] += fm * d[a];
-                ec += u - pair_shift(sh, charge, i, j);
+                ec += u;
                 wc += fm * r2;
             }
         }
@@ -689,10 +866,10 @@ int orc_forces_rbl(int64_t n, const double* pos, const double box[3],
         for (int m = 0; m < cnt; ++m) {
             int64_t j = shell_idx[shell_off[k] + K[m]];
             double r2 = dist2(pos, n, i, j, box, inv, d);
-            if (r2 >= rs2 && r2 < rc2) {
-                pair_term(r2, charge, alpha, i, j, &fm, &u);
+            if (r2 >= pair_rs2(&T, rs2, i, j) && r2 < pair_rc2(&T, rc2, i, j)) {
+                pair_eval(&T, sh, charge, alpha, i, j, r2, &fm, &u);
                 for (int a = 0; a < 3; ++a) Fs[a] += fm * d[a];
-                es += u - pair_shift(sh, charge, i, j);
+                es += u;
                 ws += fm * r2;
             }
         }
@@ -701,17 +878,22 @@ int orc_forces_rbl(int64_t n, const double* pos, const double box[3],
         if (w) w[k] = 0.5 * (wc + scale * ws);
     }
     free(K);
+    types_free(&T);
     return 0;
 }
 
 int orc_forces_full(int64_t n, const double* pos, const double box[3],
                     double rc, int shift, int64_t nrows, const int64_t* rows,
                     const int64_t* full_off, const int32_t* full_idx,
-                    const double* charge, double alpha, double* f, double* e, double* w)
+                    const double* charge, double alpha, double* f, double* e, double* w,
+                    int nt, const int32_t* type, const double* eps_sig)
 {
     double inv[3] = {1.0 / box[0], 1.0 / box[1], 1.0 / box[2]};
     double rc2 = rc * rc;
     orc_shift sh = cutoff_shift(rc2, shift, charge, alpha);
+    orc_types T;
+    /* the core radius does not enter the full list: 0 for the table */
+    if ((nt && charge) || types_setup(&T, n, nt, type, eps_sig, 0.0, rc, shift)) return -4;
     for (int64_t k = 0; k < nrows; ++k) {
         int64_t i = rows ? rows[k] : k;
         double d[3], fm, u;
@@ -719,10 +901,10 @@ int orc_forces_full(int64_t n, const double* pos, const double box[3],
         for (int64_t q = full_off[k]; q < full_off[k + 1]; ++q) {
             int64_t j = full_idx[q];
             double r2 = dist2(pos, n, i, j, box, inv, d);
-            if (r2 < rc2) {
-                pair_term(r2, charge, alpha, i, j, &fm, &u);
+            if (r2 < pair_rc2(&T, rc2, i, j)) {
+                pair_eval(&T, sh, charge, alpha, i, j, r2, &fm, &u);
                 for (int a = 0; a < 3; ++a) F[a] += fm * d[a];
-                ei += u - pair_shift(sh, charge, i, j);
+                ei += u;
                 wi += fm * r2;
             }
         }
@@ -730,6 +912,7 @@ int orc_forces_full(int64_t n, const double* pos, const double box[3],
         if (e) e[k] = 0.5 * ei;
         if (w) w[k] = 0.5 * wi;
     }
+    types_free(&T);
     return 0;
 }
 
@@ -768,11 +951,14 @@ static void free_lists(orc_lists* L)
 }
 
 static int build_all(int64_t n, double* pos, const double box[3], double rs, double rc,
-                     double skin, int use_full, int stencil, orc_lists* L)
+                     double skin, int use_full, int stencil, orc_lists* L,
+                     int nt, const int32_t* type, const double* eps_sig)
 {
     free_lists(L);
+    if (nt && stencil) return -4;
     orc_wrap(n, pos, box);
-    orc_sys* s = orc_sys_new(n, pos, box, rs, rc, skin);
+    orc_sys* s = orc_sys_new_typed(n, pos, box, rs, rc, skin, nt, type, eps_sig);
+    if (!s) return -4;
     int64_t* counts = (int64_t*)malloc(sizeof(int64_t) * 3 * (size_t)n);
     orc_list_counts(s, 0, n, NULL, counts);
     L->core_off = (int64_t*)calloc((size_t)n + 1, sizeof(int64_t));
@@ -912,7 +1098,8 @@ static void total_ev(int64_t n, const double* e, const double* w, double* out)
  * for the force evaluation s that the step leads to.  `unwrapped` (may be
  * NULL) receives the same position increments as pos but is never wrapped
  * into the box: it is the continuous trajectory (for the mean-squared
- * displacement), and must hold the starting positions on entry. */
+ * displacement), and must hold the starting positions on entry.  nt, type,
+ * eps_sig: particle types as in orc_sys_new_typed (nt = 0: one type). */
 int orc_md_run(int64_t n, double* pos, double* vel, const double box[3],
                double rs, double rc, double skin, double dt, int64_t nsteps,
                int p, uint64_t seed, int64_t step0, int K, int use_full,
@@ -920,7 +1107,8 @@ int orc_md_run(int64_t n, double* pos, double* vel, const double box[3],
                const double* charge, double alpha, int stencil,
                double gamma, double kT, double* unwrapped,
                double* force_out, double* ev_out,
-               int check, int64_t* build_steps, int64_t* n_builds)
+               int check, int64_t* build_steps, int64_t* n_builds,
+               int nt, const int32_t* type, const double* eps_sig)
 {
     if (K < 1 || n < 1 || !(gamma >= 0.0) || !(kT >= 0.0)) return -1;
     /* Lists rebuilt on displacement (check != 0): the Verlet-list criterion
@@ -978,7 +1166,7 @@ int orc_md_run(int64_t n, double* pos, double* vel, const double box[3],
             }
         }
         if (rebuild) {
-            rcode = build_all(n, pos, box, rs, rc, skin, use_full, stencil, &L);
+            rcode = build_all(n, pos, box, rs, rc, skin, use_full, stencil, &L, nt, type, eps_sig);
             if (rcode) break;
             memcpy(xb, pos, sizeof(double) * 3 * (size_t)n);  /* positions as wrapped by the build */
             last_build = s;
@@ -986,13 +1174,15 @@ int orc_md_run(int64_t n, double* pos, double* vel, const double box[3],
             nb += 1;
         }
         if (use_full) {
-            orc_forces_full(n, pos, box, rc, shift, n, NULL, L.full_off, L.full_idx, charge, alpha, F, e, w);
+            rcode = orc_forces_full(n, pos, box, rc, shift, n, NULL, L.full_off, L.full_idx, charge, alpha,
+                                    F, e, w, nt, type, eps_sig);
         } else {
-            orc_forces_rbl(n, pos, box, rs, rc, shift, n, NULL, L.core_off, L.core_idx,
-                           L.shell_off, L.shell_idx, p, seed, (uint64_t)s, replica, NULL,
-                           charge, alpha, F, e, w);
+            rcode = orc_forces_rbl(n, pos, box, rs, rc, shift, n, NULL, L.core_off, L.core_idx,
+                                   L.shell_off, L.shell_idx, p, seed, (uint64_t)s, replica, NULL,
+                                   charge, alpha, F, e, w, nt, type, eps_sig);
             if (momentum_fix) orc_mean_subtract(n, F, NULL);
         }
+        if (rcode) break;
         if (ev_out) total_ev(n, e, w, ev_out + 2 * it);
         if (it > 0) {
             /* second half of step it-1: kick with the new force */

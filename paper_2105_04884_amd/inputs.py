@@ -32,6 +32,7 @@ class State:
     vel: np.ndarray  # (3, N) float64
     box: np.ndarray  # (3,) float64
     charges: Optional[np.ndarray] = None  # (N,) float64, charged systems only
+    types: Optional[np.ndarray] = None    # (N,) int32, multi-type systems only
 
     @property
     def n(self) -> int:
@@ -87,6 +88,18 @@ def lj_fluid(n: int, density: float, temperature: float, seed: int,
     return State(np.ascontiguousarray(pos), np.ascontiguousarray(vel), box)
 
 
+def mixture(n: int, density: float, temperature: float, seed: int, fractions,
+            jitter: float = 0.05) -> State:
+    """Multi-type LJ fluid: the lattice, jitter and velocities of
+    ``lj_fluid``, and each particle of type t with probability
+    ``fractions[t]`` (independent draws from a second PCG64 stream)."""
+    st = lj_fluid(n, density, temperature, seed, jitter)
+    p = np.asarray(fractions, dtype=np.float64)
+    rng = np.random.default_rng([seed, 2])
+    st.types = rng.choice(p.shape[0], size=n, p=p / p.sum()).astype(np.int32)
+    return st
+
+
 def perfect_fcc(cells: int, density: float) -> State:
     """Perfect FCC crystal of 4*cells^3 particles, no jitter, zero velocity."""
     n = 4 * cells**3
@@ -131,6 +144,13 @@ def small_fluid(seed: int = 1) -> State:
 def million_fluid(seed: int = 1) -> State:
     """N = 1,000,000, density 0.8442, T = 1.0: the headline throughput case."""
     return lj_fluid(1_000_000, 0.8442, 1.0, seed)
+
+
+def binary_mixture(n: int = 1_000_000, seed: int = 1) -> State:
+    """Binary LJ mixture for the per-type cut-off path: 80% small (type 0)
+    and 20% large (type 1) particles on the lattice of a density-0.5 fluid,
+    T = 1.0."""
+    return mixture(n, 0.5, 1.0, seed, (0.8, 0.2))
 
 
 def large_fluid(seed: int = 1) -> State:
