@@ -27,7 +27,8 @@
  *    x, pos[n..2n) y, pos[2n..3n) z (same for velocities and forces).
  *    For an ensemble the replicas are concatenated in replica order.
  *  - A context is not thread-safe; use one per host thread.
- *  - Units are reduced LJ units: epsilon = sigma = mass = 1.
+ *  - Units are reduced LJ units: epsilon = sigma = mass = 1 (with particle
+ *    types, lengths are in units of the sigma that pair_coeffs scales).
  */
 #ifndef RBL_H
 #define RBL_H
@@ -44,7 +45,8 @@ typedef enum rbl_status {
     RBL_OK = 0,
     RBL_W_SKIN = 1,        /* warning: some particle moved more than skin/2 between list builds */
     RBL_E_ARG = -1,        /* invalid argument (NULL pointer, non-positive size, bad radius, P out of range) */
-    RBL_E_BOX = -2,        /* a box edge is not larger than 2 (r_c + skin) */
+    RBL_E_BOX = -2,        /* a box edge is not larger than 2 (r_c + skin) (largest pair cut-off with
+                              particle types), or a type's stencil spans more than 15 cells */
     RBL_E_STATE = -3,      /* call needs a list build first, or the build lacks the list asked for */
     RBL_E_CAPACITY = -4,   /* neighbour rows exceeded their capacity and could not be regrown */
     RBL_E_NONFINITE = -5,  /* a position was NaN or infinite at a list build */
@@ -127,6 +129,29 @@ typedef struct rbl_config {
                                   criterion), and the rebuild is decided on the device
                                   inside the captured lifetimes. */
     int32_t reserved;          /* must be 0 */
+    int32_t n_types;           /* 0 (default): one particle type, eq. (1) with epsilon = sigma = 1.
+                                  1..4: particle types whose interaction lengths differ (Sec. II):
+                                  pair (a, b) interacts by eq. (1) with its own epsilon_ab and
+                                  sigma_ab, has the core radius r_s sigma_ab and the cut-off
+                                  r_c sigma_ab (r_s, r_c of rbl_build in units of sigma; with
+                                  `shift` its energy is zero at its own cut-off), and its
+                                  lists use those radii with the skin.  The cells are sized by
+                                  the smallest pair cut-off (edge >= (r_c sigma_min + skin)/2),
+                                  and a particle of type a searches the cells within
+                                  h_a = ceil((r_c max_b sigma_ab + skin)(1 + 1e-6) / w) of its
+                                  own along each axis, w the narrowest cell edge of any
+                                  replica: one stencil per type, as Sec. II describes.
+                                  Box edges must exceed 2 (r_c sigma_max + skin), and h_a <= 15
+                                  (else rbl_build fails with RBL_E_BOX).  Not with charges, and
+                                  with shell_source RBL_SHELL_LIST only.  The lists are built
+                                  as explicit rows (no fused build), so rbl_step draws its
+                                  batches in the force kernel and takes P <= 32; rbl_rdf takes
+                                  r_max <= r_c sigma_min. */
+    const int32_t* types;      /* host, n types in caller order (values 0 .. n_types - 1), or
+                                  NULL when n_types == 0; copied by rbl_create */
+    const double* pair_coeffs; /* host, n_types x n_types x 2 doubles: (epsilon_ab, sigma_ab) of
+                                  pair (a, b) at [(a n_types + b) 2], symmetric, epsilon >= 0,
+                                  sigma > 0; NULL when n_types == 0; copied by rbl_create */
 } rbl_config;
 
 /* Fills *cfg with the defaults above for n particles in one replica. */

@@ -83,7 +83,10 @@ class Context:
                  capacity_factor: float = 1.25,
                  replica_offsets=None,
                  pair: str = "lj", alpha: float = 0.0, charges=None, shell_source: str = "shell",
-                 rebuild_check: bool = False, stream=None):
+                 rebuild_check: bool = False, types=None, eps_sig=None, stream=None):
+        """``types`` (n ints) and ``eps_sig`` ((n_types, n_types, 2) table of
+        epsilon_ab, sigma_ab): particle types with per-pair LJ parameters and
+        radii r_s sigma_ab, r_c sigma_ab (rbl_config.n_types)."""
         torch = _torch()
         lib = _lib.load()
         cfg = _lib.Config()
@@ -114,6 +117,19 @@ class Context:
         self._charges = charges
         if charges is not None:
             cfg.charges = _dev_ptr(charges, (n,), "charges").value
+        if types is not None or eps_sig is not None:
+            if types is None or eps_sig is None:
+                raise ValueError("types and eps_sig go together")
+            self._types = np.ascontiguousarray(types, dtype=np.int32).reshape(-1)
+            self._eps_sig = np.ascontiguousarray(eps_sig, dtype=np.float64)
+            if self._types.shape != (int(n),):
+                raise ValueError("types needs one entry per particle")
+            if (self._eps_sig.ndim != 3 or self._eps_sig.shape[0] != self._eps_sig.shape[1]
+                    or self._eps_sig.shape[2] != 2):
+                raise ValueError("eps_sig must be shaped (n_types, n_types, 2)")
+            cfg.n_types = int(self._eps_sig.shape[0])
+            cfg.types = _i32(self._types)
+            cfg.pair_coeffs = self._eps_sig.ctypes.data_as(C.POINTER(C.c_double))
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream

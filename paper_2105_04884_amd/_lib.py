@@ -56,6 +56,9 @@ class Config(C.Structure):
         ("shell_source", C.c_int32),
         ("rebuild_check", C.c_int32),
         ("reserved", C.c_int32),
+        ("n_types", C.c_int32),
+        ("types", C.POINTER(C.c_int32)),
+        ("pair_coeffs", C.POINTER(C.c_double)),
     ]
 
 

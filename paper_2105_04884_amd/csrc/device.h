@@ -182,6 +182,40 @@ struct LJ<kMixed> {
     }
 };
 
+// LJ pair of particle types a, b with their own parameters, eq. (1) with
+// epsilon_ab and sigma_ab: the constants come precomputed per pair (24 eps,
+// 4 eps, sigma^2), so that eps = sigma = 1 repeats LJ<PREC> operation for
+// operation.
+template <int PREC>
+struct LJt;
+
+template <>
+struct LJt<kFP64> {
+    __device__ __forceinline__ static void eval(double r2, double eps24, double eps4, double sig2, double& fmag,
+                                                double& u)
+    {
+        const double r2i = 1.0 / r2;
+        const double s2 = sig2 * r2i;
+        const double sr6 = s2 * s2 * s2;
+        fmag = eps24 * r2i * sr6 * (2.0 * sr6 - 1.0);
+        u = eps4 * sr6 * (sr6 - 1.0);
+    }
+};
+
+template <>
+struct LJt<kMixed> {
+    __device__ __forceinline__ static void eval(double r2, double eps24, double eps4, double sig2, double& fmag,
+                                                double& u)
+    {
+        const float r2f = (float)r2;
+        const float r2i = __builtin_amdgcn_rcpf(r2f);
+        const float s2 = (float)sig2 * r2i;
+        const float sr6 = s2 * s2 * s2;
+        fmag = (double)((float)eps24 * r2i * sr6 * (2.0f * sr6 - 1.0f));
+        u = (double)((float)eps4 * sr6 * (sr6 - 1.0f));
+    }
+};
+
 // Real-space Ewald term q_i q_j erfc(alpha r)/r added to the LJ pair.
 template <int PREC>
 struct Erfc;

@@ -19,6 +19,36 @@ enum { kShellNone = 0, kShellInline = 1, kShellPredraw = 2 };
 enum { kIntFirst = 0, kIntMid = 1, kIntLast = 2 };
 enum { kFlagOverflow = 0, kFlagMaxCore = 1, kFlagMaxShell = 2, kFlagMaxFull = 3,
        kFlagNonfinite = 4, kFlagSkin = 5, kFlagBadSlot = 6, kFlagStencil = 7, kNumFlags = 8 };
+// pair term of the force kernels: LJ of eq. (1); LJ plus the erfc term of
+// charges; LJ with per-type parameters and radii
+enum { kPairLJ = 0, kPairErfc = 1, kPairTyped = 2 };
+// radius zone a force sum tests its partners against
+enum { kZoneCore = 0, kZoneShell = 1, kZoneFull = 2 };
+
+// Particle types (Sec. II: systems whose interaction lengths differ).  A
+// particle's type travels in the w word of its position record (xs: as a
+// double, xq: as FP32 bits).  Pair (a, b) has its own LJ constants, its core
+// radius r_s sigma_ab and cut-off r_c sigma_ab; the cell grid is sized by the
+// smallest cut-off and a centre of type a searches the cells within h[a] of
+// its own.
+constexpr int kMaxTypes = 4;
+
+struct TypePair {
+    double eps24, eps4, sig2;          // 24 eps_ab, 4 eps_ab, sigma_ab^2
+    double rs2, rc2, uc;               // (r_s sigma_ab)^2, (r_c sigma_ab)^2, energy at the cut-off
+    double thr_core, thr_in, thr_out;  // list thresholds: squared radii with the skin
+    double pad;
+};
+
+struct TypeTable {
+    TypePair p[kMaxTypes * kMaxTypes];  // pair (a, b) at a * kMaxTypes + b
+    int h[kMaxTypes];                   // stencil half-width in cells of centre type a
+    int n_types;
+    int pad;
+};
+
+// type of a particle from the w word of its record (masked into the table)
+__device__ __forceinline__ int type_of(double w) { return (int)w & (kMaxTypes - 1); }
 
 // Block -> work-tile map.  Blocks are dispatched to the 8 XCDs round-robin
 // (block b to XCD b % 8); this map hands every XCD chunks of kXcdChunk
@@ -457,6 +487,7 @@ struct BuildArgs {
     int* full_len;
     int* flags;
     const uint64_t* gate;      // rebuild gate (null: always run)
+    const TypeTable* types;    // particle types (k_build_typed), else null
     // the MD loop's builds record themselves: mark[0] = step of the build,
     // mark[1] += 1 (null: not recorded); the step is *mark_step_dev +
     // mark_step, or mark_step alone without a device counter
@@ -634,6 +665,162 @@ __global__ __launch_bounds__(256) void k_build(BuildArgs a)
                         if (p < a.cap_full) a.full[ell(islot, p, a.cap_full)] = j;
                     }
                     if (lane == ii) cnt_f += __popcll(mk);
+                }
+            }
+        }
+        const bool mine = lane < mg;
+        const int islot = i0 + g0 + lane;
+        if (WC) {
+            if (mine && !COUNT_ONLY) a.core_len[islot] = min(cnt_c, a.cap_core);
+            const int mx = wave_max(mine ? cnt_c : 0);
+            if (lane == 0) {
+                raise_max(&a.flags[kFlagMaxCore], mx);
+                if (!COUNT_ONLY && mx > a.cap_core) raise_flag(&a.flags[kFlagOverflow]);
+            }
+        }
+        if (WS) {
+            if (mine && !COUNT_ONLY) a.shell_len[islot] = min(cnt_s, a.cap_shell);
+            const int mx = wave_max(mine ? cnt_s : 0);
+            if (lane == 0) {
+                raise_max(&a.flags[kFlagMaxShell], mx);
+                if (!COUNT_ONLY && mx > a.cap_shell) raise_flag(&a.flags[kFlagOverflow]);
+            }
+        }
+        if (WF) {
+            if (mine && !COUNT_ONLY) a.full_len[islot] = min(cnt_f, a.cap_full);
+            const int mx = wave_max(mine ? cnt_f : 0);
+            if (lane == 0) {
+                raise_max(&a.flags[kFlagMaxFull], mx);
+                if (!COUNT_ONLY && mx > a.cap_full) raise_flag(&a.flags[kFlagOverflow]);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Core / shell / full list build for particle types (Sec. II).  The cells
+// are sized by the smallest pair cut-off; the centres of one type at a time
+// walk the stencil of that type's half-width h (every cell within h of the
+// centre cell along each axis, each cell once), one z-slab after the other.
+// In a slab, lane q describes run q = (y-row q / 2, x-part q % 2) as k_build
+// does for its whole stencil, so candidates come in ascending slot order and
+// rows need no sort.  Each candidate is tested with the thresholds of its
+// pair of types.  2 (2h + 1) <= 64 runs per slab (the host keeps h <= 15).
+template <bool COUNT_ONLY, bool WC, bool WS, bool WF>
+__global__ __launch_bounds__(256) void k_build_typed(BuildArgs a)
+{
+    __shared__ double s_thr[3][kMaxTypes * kMaxTypes];  // core, shell inner, outer thresholds per pair
+    if (gated_off(a.gate)) return;
+    if (!COUNT_ONLY) record_build(a);
+    for (int k = threadIdx.x; k < kMaxTypes * kMaxTypes; k += blockDim.x) {
+        s_thr[0][k] = a.types->p[k].thr_core;
+        s_thr[1][k] = a.types->p[k].thr_in;
+        s_thr[2][k] = a.types->p[k].thr_out;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int64_t cell = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (cell >= a.n_cells) return;
+    const int m = a.cell_count[cell];
+    if (m == 0) return;
+    const int i0 = a.cell_start[cell];
+    if (i0 < 0 || (int64_t)i0 + m > a.n_slots) {
+        if (lane == 0) atomicOr(&a.flags[kFlagBadSlot], 2);
+        return;
+    }
+    const DevReplica& R = a.rep[a.cell_rep[cell]];
+    const int64_t lc = cell - R.cell_base;
+    const int cx = (int)(lc % R.nc[0]);
+    const int cy = (int)((lc / R.nc[0]) % R.nc[1]);
+    const int cz = (int)(lc / ((int64_t)R.nc[0] * R.nc[1]));
+    const int ntypes = a.types->n_types;
+
+    for (int g0 = 0; g0 < m; g0 += 64) {
+        const int mg = min(64, m - g0);
+        double4 xc = make_double4(0.0, 0.0, 0.0, 0.0);
+        if (lane < mg) xc = a.xs[i0 + g0 + lane];
+        const int tc = lane < mg ? type_of(xc.w) : -1;
+        int cnt_c = 0, cnt_s = 0, cnt_f = 0;
+        for (int t = 0; t < ntypes; ++t) {
+            const uint64_t centres = __ballot(tc == t);
+            if (centres == 0) continue;
+            const int h = a.types->h[t];
+            const AxisRuns ax = axis_runs(cx, R.nc[0], h);
+            const AxisRuns ay = axis_runs(cy, R.nc[1], h);
+            const AxisRuns az = axis_runs(cz, R.nc[2], h);
+            const int ny_s = ay.l0 + ay.l1;
+            const int nz_s = az.l0 + az.l1;
+            for (int zi = 0; zi < nz_s; ++zi) {
+                const int zc = axis_cell(az, zi);
+                int rstart = 0, rlen = 0;
+                {
+                    const int yi = lane >> 1;
+                    const int xr = lane & 1;
+                    const int px = xr == 0 ? ax.p0 : ax.p1;
+                    const int lx = xr == 0 ? ax.l0 : ax.l1;
+                    if (yi < ny_s && lx > 0) {
+                        const int yc = axis_cell(ay, yi);
+                        const int64_t row = R.cell_base + ((int64_t)zc * R.nc[1] + yc) * R.nc[0];
+                        rstart = a.cell_start[row + px];
+                        rlen = a.cell_start[row + px + lx - 1] + a.cell_count[row + px + lx - 1] - rstart;
+                    }
+                }
+                const int incl = wave_incl_scan(rlen);
+                const int total = __builtin_amdgcn_readlane(incl, 63);
+                const int rpre = incl - rlen;
+                for (int base = 0; base < total; base += 64) {
+                    const int f = base + lane;
+                    int q = 0;
+#pragma unroll
+                    for (int step = 32; step > 0; step >>= 1) {
+                        const int tq = shfl_i32(rpre, q + step);
+                        if (tq <= f) q += step;
+                    }
+                    const int j = shfl_i32(rstart, q) + (f - shfl_i32(rpre, q));
+                    const bool valid = f < total && j >= 0 && (int64_t)j < a.n_slots;
+                    double4 xj = make_double4(0.0, 0.0, 0.0, 0.0);
+                    if (valid) xj = a.xs[j];
+                    const int pe = t * kMaxTypes + type_of(xj.w);
+                    const double thr_core = s_thr[0][pe];
+                    const double thr_in = s_thr[1][pe];
+                    const double thr_out = s_thr[2][pe];
+                    for (uint64_t rest = centres; rest; rest &= rest - 1) {
+                        const int ii = (int)__builtin_ctzll(rest);
+                        const int islot = i0 + g0 + ii;
+                        const double4 xi = make_double4(bcast(xc.x, ii), bcast(xc.y, ii), bcast(xc.z, ii), 0.0);
+                        const Delta d = delta(xi, xj, R);
+                        const bool ok = valid && j != islot;
+                        if (WC) {
+                            const bool in = ok && d.r2 < thr_core;
+                            const uint64_t mk = __ballot(in);
+                            const int b0 = __builtin_amdgcn_readlane(cnt_c, ii);
+                            if (!COUNT_ONLY && in) {
+                                const int p = b0 + (int)mbcnt(mk);
+                                if (p < a.cap_core) a.core[ell(islot, p, a.cap_core)] = j;
+                            }
+                            if (lane == ii) cnt_c += __popcll(mk);
+                        }
+                        if (WS) {
+                            const bool in = ok && d.r2 >= thr_in && d.r2 < thr_out;
+                            const uint64_t mk = __ballot(in);
+                            const int b0 = __builtin_amdgcn_readlane(cnt_s, ii);
+                            if (!COUNT_ONLY && in) {
+                                const int p = b0 + (int)mbcnt(mk);
+                                if (p < a.cap_shell) a.shell[ell(islot, p, a.cap_shell)] = j;
+                            }
+                            if (lane == ii) cnt_s += __popcll(mk);
+                        }
+                        if (WF) {
+                            const bool in = ok && d.r2 < thr_out;
+                            const uint64_t mk = __ballot(in);
+                            const int b0 = __builtin_amdgcn_readlane(cnt_f, ii);
+                            if (!COUNT_ONLY && in) {
+                                const int p = b0 + (int)mbcnt(mk);
+                                if (p < a.cap_full) a.full[ell(islot, p, a.cap_full)] = j;
+                            }
+                            if (lane == ii) cnt_f += __popcll(mk);
+                        }
+                    }
                 }
             }
         }
@@ -1608,6 +1795,7 @@ struct ForceArgs {
     // is tested against is classified from the FP64 positions
     const int4* xq;
     double guard;
+    const TypeTable* types;  // pair constants of particle types (kPairTyped)
 };
 
 // This step's pre-drawn batches (the force evaluation's step relative to
@@ -1645,11 +1833,45 @@ struct Acc {
     double fx, fy, fz, e, w;
 };
 
-template <int PREC, bool ENERGY, bool ERFC, int U>
+// Typed pairs (PAIR == kPairTyped) take lo2 / hi2 from the pair's radii by
+// `zone` (core [0, r_s^2), shell [r_s^2, r_c^2), full [0, r_c^2)) and its
+// LJ constants from `tp` (the type table in LDS).
+
+__device__ __forceinline__ void zone_bounds(const TypePair& pp, int zone, double& lo2, double& hi2)
+{
+    lo2 = zone == kZoneShell ? pp.rs2 : -1.0;
+    hi2 = zone == kZoneCore ? pp.rs2 : pp.rc2;
+}
+
+template <int PREC, bool ENERGY, int PAIR, int U>
 __device__ __forceinline__ void accumulate(const double4& xi, const double4 (&xj)[U], const bool (&live)[U],
                                            double lo2, double hi2, const DevReplica& R,
-                                           const ForceArgs& a, Acc& acc)
+                                           const ForceArgs& a, Acc& acc, const TypePair* tp, int zone)
 {
+    constexpr bool ERFC = PAIR == kPairErfc;
+    if constexpr (PAIR == kPairTyped) {
+        const TypePair* row = tp + type_of(xi.w) * kMaxTypes;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const Delta d = delta(xi, xj[u], R);
+            const TypePair& pp = row[type_of(xj[u].w)];
+            double lo, hi;
+            zone_bounds(pp, zone, lo, hi);
+            const bool in = live[u] && d.r2 >= lo && d.r2 < hi;
+            const double r2 = in ? d.r2 : 1.0;
+            double fm, en;
+            LJt<PREC>::eval(r2, pp.eps24, pp.eps4, pp.sig2, fm, en);
+            fm = in ? fm : 0.0;
+            acc.fx += fm * d.x;
+            acc.fy += fm * d.y;
+            acc.fz += fm * d.z;
+            if (ENERGY) {
+                acc.e += in ? en - pp.uc : 0.0;
+                acc.w += fm * r2;
+            }
+        }
+        return;
+    }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const Delta d = delta(xi, xj[u], R);
@@ -1675,13 +1897,45 @@ __device__ __forceinline__ void accumulate(const double4& xi, const double4 (&xj
 // positions: |r^2 - r^2_FP64| <= guard (host bound from the two roundings),
 // so a pair farther than the guard from both bounds falls on the same side,
 // and one within it is decided from the FP64 positions.
-template <bool ENERGY, bool ERFC, int U>
+template <bool ENERGY, int PAIR, int U>
 __device__ __forceinline__ void accumulate_mixed(const double4& xi, const int4& qi, const int4 (&xj)[U],
                                                  const int (&j)[U], const bool (&live)[U], double lo2,
-                                                 double hi2, const DevReplica& R, const ForceArgs& a, Acc& acc)
+                                                 double hi2, const DevReplica& R, const ForceArgs& a, Acc& acc,
+                                                 const TypePair* tp, int zone)
 {
+    constexpr bool ERFC = PAIR == kPairErfc;
     constexpr double k2m32 = 2.3283064365386962890625e-10;  // 2^-32
     const double s0 = R.L[0] * k2m32, s1 = R.L[1] * k2m32, s2 = R.L[2] * k2m32;
+    if constexpr (PAIR == kPairTyped) {
+        const TypePair* row = tp + type_of((double)__int_as_float(qi.w)) * kMaxTypes;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const double dx = (double)(int)((uint32_t)qi.x - (uint32_t)xj[u].x) * s0;
+            const double dy = (double)(int)((uint32_t)qi.y - (uint32_t)xj[u].y) * s1;
+            const double dz = (double)(int)((uint32_t)qi.z - (uint32_t)xj[u].z) * s2;
+            const double r2q = fma(dz, dz, fma(dy, dy, dx * dx));
+            const TypePair& pp = row[type_of((double)__int_as_float(xj[u].w))];
+            double lo, hi;
+            zone_bounds(pp, zone, lo, hi);
+            bool in = live[u] && r2q >= lo && r2q < hi;
+            if (live[u] && (fabs(r2q - lo) <= a.guard || fabs(r2q - hi) <= a.guard)) {
+                const Delta d = delta(xi, a.xs[j[u]], R);
+                in = d.r2 >= lo && d.r2 < hi;
+            }
+            const double r2 = in ? r2q : 1.0;
+            double fm, en;
+            LJt<kMixed>::eval(r2, pp.eps24, pp.eps4, pp.sig2, fm, en);
+            fm = in ? fm : 0.0;
+            acc.fx += fm * dx;
+            acc.fy += fm * dy;
+            acc.fz += fm * dz;
+            if (ENERGY) {
+                acc.e += in ? en - pp.uc : 0.0;
+                acc.w += fm * r2;
+            }
+        }
+        return;
+    }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const double dx = (double)(int)((uint32_t)qi.x - (uint32_t)xj[u].x) * s0;
@@ -1712,28 +1966,39 @@ __device__ __forceinline__ void accumulate_mixed(const double4& xi, const int4& 
 // Gathers the positions of U partners (all loads in flight first) and
 // accumulates their pair terms: FP64 positions, or the fixed-point copy
 // (mixed).
-template <int PREC, bool ENERGY, bool ERFC, int U>
+template <int PREC, bool ENERGY, int PAIR, int U>
 __device__ __forceinline__ void gather_accumulate(const ForceArgs& a, const double4& xi, const int4& qi,
                                                   const int (&j)[U], const bool (&live)[U], double lo2,
-                                                  double hi2, const DevReplica& R, Acc& acc)
+                                                  double hi2, const DevReplica& R, Acc& acc,
+                                                  const TypePair* tp, int zone)
 {
     if constexpr (PREC == kMixed) {
         int4 xj[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) xj[u] = a.xq[j[u]];
-        accumulate_mixed<ENERGY, ERFC, U>(xi, qi, xj, j, live, lo2, hi2, R, a, acc);
+        accumulate_mixed<ENERGY, PAIR, U>(xi, qi, xj, j, live, lo2, hi2, R, a, acc, tp, zone);
     } else {
         double4 xj[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) xj[u] = a.xs[j[u]];
-        accumulate<PREC, ENERGY, ERFC, U>(xi, xj, live, lo2, hi2, R, a, acc);
+        accumulate<PREC, ENERGY, PAIR, U>(xi, xj, live, lo2, hi2, R, a, acc, tp, zone);
     }
+}
+
+// The type table of a force launch, copied into LDS by the block.
+__device__ __forceinline__ void load_type_table(const ForceArgs& a, TypePair* s_tp)
+{
+    constexpr int words = (int)(sizeof(TypePair) * kMaxTypes * kMaxTypes / 8);
+    const double* src = reinterpret_cast<const double*>(a.types->p);
+    double* dst = reinterpret_cast<double*>(s_tp);
+    for (int k = threadIdx.x; k < words; k += blockDim.x) dst[k] = src[k];
+    __syncthreads();
 }
 
 constexpr int kGatherBatch = 4;
 
-template <int PREC, int MODE, bool ENERGY, bool ERFC, int PMAX>
-__device__ __forceinline__ void force_tile(const ForceArgs& a, int64_t tile, uint32_t* s_pos)
+template <int PREC, int MODE, bool ENERGY, int PAIR, int PMAX>
+__device__ __forceinline__ void force_tile(const ForceArgs& a, int64_t tile, uint32_t* s_pos, const TypePair* tp)
 {
     constexpr int U = kGatherBatch;
     const int64_t slot = tile * blockDim.x + threadIdx.x;
@@ -1767,7 +2032,8 @@ __device__ __forceinline__ void force_tile(const ForceArgs& a, int64_t tile, uin
                 }
 #pragma unroll
                 for (int u = 0; u < U; ++u) jn[u] = k + U + u < len ? row[(int64_t)(k + U + u) * 64] : (int)slot;
-                gather_accumulate<PREC, ENERGY, ERFC, U>(a, xi, qi, j, live, -1.0, cut, R, c);
+                gather_accumulate<PREC, ENERGY, PAIR, U>(a, xi, qi, j, live, -1.0, cut, R, c, tp,
+                                                         MODE == kShellNone ? kZoneFull : kZoneCore);
             }
         }
         if (MODE != kShellNone) {
@@ -1804,7 +2070,7 @@ __device__ __forceinline__ void force_tile(const ForceArgs& a, int64_t tile, uin
                     }
                     j[u] = jj;
                 }
-                gather_accumulate<PREC, ENERGY, ERFC, U>(a, xi, qi, j, live, a.rs2, a.rc2, R, sh);
+                gather_accumulate<PREC, ENERGY, PAIR, U>(a, xi, qi, j, live, a.rs2, a.rc2, R, sh, tp, kZoneShell);
             }
             fx = c.fx + scale * sh.fx;
             fy = c.fy + scale * sh.fy;
@@ -1853,13 +2119,15 @@ __device__ __forceinline__ void force_tile(const ForceArgs& a, int64_t tile, uin
 // One tile per block, or (persistent grid) tiles b, b + gridDim.x, ... in
 // turn; the grid is a multiple of 8 blocks, so a block keeps to its XCD's
 // tiles of the XCD map.
-template <int PREC, int MODE, bool ENERGY, bool ERFC, int PMAX>
+template <int PREC, int MODE, bool ENERGY, int PAIR, int PMAX>
 __global__ __launch_bounds__(256) void k_forces(ForceArgs a)
 {
     __shared__ uint32_t s_pos[MODE == kShellInline ? PMAX * 256 : 1];
+    __shared__ TypePair s_tp[PAIR == kPairTyped ? kMaxTypes * kMaxTypes : 1];
     force_prologue(a);
+    if constexpr (PAIR == kPairTyped) load_type_table(a, s_tp);
     for (int64_t b = blockIdx.x; b < a.vblocks; b += gridDim.x)
-        force_tile<PREC, MODE, ENERGY, ERFC, PMAX>(a, xcd_tile(b, a.vblocks), s_pos);
+        force_tile<PREC, MODE, ENERGY, PAIR, PMAX>(a, xcd_tile(b, a.vblocks), s_pos, s_tp);
 }
 
 template <int CTRL>
@@ -1878,10 +2146,10 @@ __device__ __forceinline__ double group_sum(double v)
     return v;
 }
 
-template <int PREC, int MODE, bool ENERGY, bool ERFC, int LPP>
-__device__ __forceinline__ void force_tile_lpp(const ForceArgs& a, int64_t tile)
+template <int PREC, int MODE, bool ENERGY, int PAIR, int LPP>
+__device__ __forceinline__ void force_tile_lpp(const ForceArgs& a, int64_t tile, const TypePair* tp)
 {
-    constexpr int U = (LPP == 2 && !ERFC) ? 4 : 2;  // neighbours per lane in flight
+    constexpr int U = (LPP == 2 && PAIR == kPairLJ) ? 4 : 2;  // neighbours per lane in flight
     const int64_t g = tile * blockDim.x + threadIdx.x;
     const int64_t slot = g / LPP;
     const int l = (int)(g % LPP);
@@ -1922,7 +2190,8 @@ __device__ __forceinline__ void force_tile_lpp(const ForceArgs& a, int64_t tile)
                         jn[u] = kn < len ? row[(int64_t)kn * 64] : (int)slot;
                     }
                 }
-                gather_accumulate<PREC, ENERGY, ERFC, U>(a, xi, qi, j, live, -1.0, cut, R, c);
+                gather_accumulate<PREC, ENERGY, PAIR, U>(a, xi, qi, j, live, -1.0, cut, R, c, tp,
+                                                         MODE == kShellNone ? kZoneFull : kZoneCore);
             }
         }
         if (MODE != kShellNone) {
@@ -1942,7 +2211,7 @@ __device__ __forceinline__ void force_tile_lpp(const ForceArgs& a, int64_t tile)
                     // particle itself, whose pair term is zero
                     if ((uint64_t)(uint32_t)j[u] >= (uint64_t)a.n_slots) j[u] = (int)slot;
                 }
-                gather_accumulate<PREC, ENERGY, ERFC, U>(a, xi, qi, j, live, a.rs2, a.rc2, R, sh);
+                gather_accumulate<PREC, ENERGY, PAIR, U>(a, xi, qi, j, live, a.rs2, a.rc2, R, sh, tp, kZoneShell);
             }
         }
     }
@@ -2001,12 +2270,14 @@ __device__ __forceinline__ void force_tile_lpp(const ForceArgs& a, int64_t tile)
     }
 }
 
-template <int PREC, int MODE, bool ENERGY, bool ERFC, int LPP>
+template <int PREC, int MODE, bool ENERGY, int PAIR, int LPP>
 __global__ __launch_bounds__(256) void k_forces_lpp(ForceArgs a)
 {
+    __shared__ TypePair s_tp[PAIR == kPairTyped ? kMaxTypes * kMaxTypes : 1];
     force_prologue(a);
+    if constexpr (PAIR == kPairTyped) load_type_table(a, s_tp);
     for (int64_t b = blockIdx.x; b < a.vblocks; b += gridDim.x)
-        force_tile_lpp<PREC, MODE, ENERGY, ERFC, LPP>(a, xcd_tile(b, a.vblocks));
+        force_tile_lpp<PREC, MODE, ENERGY, PAIR, LPP>(a, xcd_tile(b, a.vblocks), s_tp);
 }
 
 // Per-replica sums of the wavefront partials in a fixed order, so the result

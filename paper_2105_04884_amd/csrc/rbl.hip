@@ -162,6 +162,14 @@ struct rbl_ctx {
     double* d_sq_part = nullptr;     // partial sums of k_sumsq
     int sq_nb = 0;
     double r_s = 0, r_c = 0;
+    // particle types (n_types > 0): the type of each particle as a double in
+    // caller order (the w word of the position records), the pair table of
+    // the last build, and the extremes of sigma_ab
+    bool typed = false;
+    double* d_tcol = nullptr;
+    TypeTable* d_tt = nullptr;
+    std::vector<double> eps_sig;    // [n_types][n_types][2]
+    double sig_min = 1.0, sig_max = 1.0;
     std::vector<DevReplica> h_rep;
     int64_t n_cells = 0, cells_alloc = 0;
 
@@ -242,6 +250,8 @@ struct rbl_ctx {
     double stat_ms[kKinds] = {0};
 
     int* cur_perm() { return d_perm[cur]; }
+    // the w words of the position records: charges, or the particle types
+    const double* wcol() const { return typed ? d_tcol : cfg.charges; }
     double4* cur_xs() { return d_xs[cur]; }
     double* cur_vs() { return d_vs[cur]; }
 };
@@ -412,25 +422,88 @@ rbl_status setup_paper_grid(rbl_ctx* c, double r_s, double r_c)
     return RBL_OK;
 }
 
+// The pair table of a typed context for radii r_s, r_c (in units of sigma)
+// on the cell grid of `reps`: per pair (a, b) the LJ constants of eps_ab and
+// sigma_ab, the radii r_s sigma_ab and r_c sigma_ab with the energy at the
+// cut-off, the list thresholds with the skin, and per centre type the
+// stencil half-width: the cell edges (times 1 + 1e-6) that its largest pair
+// cut-off plus the skin spans, on the narrowest edge of any replica.
+rbl_status setup_types(rbl_ctx* c, const std::vector<DevReplica>& reps, double r_s, double r_c)
+{
+    const int T = c->cfg.n_types;
+    const double skin = c->cfg.skin;
+    TypeTable t;
+    std::memset(&t, 0, sizeof(t));
+    t.n_types = T;
+    double edge = std::numeric_limits<double>::infinity();
+    for (const auto& d : reps)
+        for (int ax = 0; ax < 3; ++ax) edge = std::min(edge, d.L[ax] / d.nc[ax]);
+    for (int a = 0; a < T; ++a) {
+        double smax = 0.0;
+        for (int b = 0; b < T; ++b) {
+            const double eps = c->eps_sig[(a * T + b) * 2 + 0];
+            const double sig = c->eps_sig[(a * T + b) * 2 + 1];
+            smax = std::max(smax, sig);
+            TypePair& p = t.p[a * kMaxTypes + b];
+            p.eps24 = 24.0 * eps;
+            p.eps4 = 4.0 * eps;
+            p.sig2 = sig * sig;
+            const double rs = r_s * sig, rc = r_c * sig;
+            p.rs2 = rs * rs;
+            p.rc2 = rc * rc;
+            p.uc = 0.0;
+            if (c->cfg.shift) {
+                const double r2i = 1.0 / p.rc2;
+                const double s2 = p.sig2 * r2i;
+                const double sr6 = s2 * s2 * s2;
+                p.uc = p.eps4 * sr6 * (sr6 - 1.0);
+            }
+            const double ca = rs + skin;
+            double cb = rs - skin;
+            if (cb < 0.0) cb = 0.0;
+            const double co = rc + skin;
+            p.thr_core = ca * ca;
+            p.thr_in = cb * cb;
+            p.thr_out = co * co;
+        }
+        const double h = std::ceil((r_c * smax + skin) * 1.000001 / edge);
+        if (!(h <= 15.0))
+            return fail(RBL_E_BOX, "the stencil of particle type " + std::to_string(a) + " spans " +
+                                       std::to_string((int)h) + " cells, more than 15: use fewer, wider cells "
+                                       "(a smaller disparity of cut-offs)");
+        t.h[a] = (int)h;
+    }
+    if (!c->d_tt) RBL_TRY(dalloc(&c->d_tt, 1));
+    HIP_TRY(hipMemcpyAsync(c->d_tt, &t, sizeof(t), hipMemcpyHostToDevice, c->ls));
+    HIP_TRY(hipStreamSynchronize(c->ls));
+    return RBL_OK;
+}
+
 rbl_status setup_geometry(rbl_ctx* c, const double* box, double r_s, double r_c)
 {
     const double skin = c->cfg.skin;
-    const double reach = r_c + skin;
+    // the largest pair cut-off decides the box check; the smallest sizes the
+    // cells (one type: both are r_c)
+    const double reach = r_c * c->sig_max + skin;
+    const double r_cell = r_c * c->sig_min;
     std::vector<DevReplica> reps(c->R);
     int64_t cell_base = 0;
     for (int r = 0; r < c->R; ++r) {
         DevReplica& d = reps[r];
         std::memset(&d, 0, sizeof(d));
         // cells of edge >= (r_c + skin)/2 with a small margin, so that any pair
-        // closer than r_c + skin lies within two cells along every axis
-        const double w = 0.5 * (r_c + skin) * 1.000001;
+        // closer than r_c + skin lies within two cells along every axis (with
+        // particle types: r_c of the smallest pair cut-off, and each type's
+        // stencil reaches its own largest one)
+        const double w = 0.5 * (r_cell + skin) * 1.000001;
         int64_t ncell = 1;
         for (int a = 0; a < 3; ++a) {
             const double L = box[3 * r + a];
             if (!(std::isfinite(L) && L > 2.0 * reach))
                 return fail(RBL_E_BOX, "box edge " + std::to_string(L) + " of replica " +
                                            std::to_string(r) + " must exceed 2 (r_c + skin) = " +
-                                           std::to_string(2.0 * reach));
+                                           std::to_string(2.0 * reach) +
+                                           (c->typed ? " (largest pair cut-off)" : ""));
             double nc = std::floor(L / w);
             if (nc < 1.0) nc = 1.0;
             if (nc > 1 << 20) return fail(RBL_E_BOX, "box too large for the cell grid");
@@ -480,6 +553,7 @@ rbl_status setup_geometry(rbl_ctx* c, const double* box, double r_s, double r_c)
     c->r_s = r_s;
     c->r_c = r_c;
     if (c->paper) RBL_TRY(setup_paper_grid(c, r_s, r_c));
+    if (c->typed) RBL_TRY(setup_types(c, reps, r_s, r_c));
     // Mixed-precision forces classify from fixed-point copies of the
     // positions (x / L mod 1 in units of 2^-32).  With u = 2^-53 and
     // coordinates below X = 1024 (L_max + r_c) in magnitude, a stored word
@@ -495,8 +569,8 @@ rbl_status setup_geometry(rbl_ctx* c, const double* box, double r_s, double r_c)
         for (const auto& d : reps)
             for (int a = 0; a < 3; ++a) lmax = std::max(lmax, d.L[a]);
         const double u = std::ldexp(1.0, -53);
-        const double X = 1024.0 * (lmax + r_c);
-        const double r = r_c + 1.0;
+        const double X = 1024.0 * (lmax + r_c * c->sig_max);
+        const double r = r_c * c->sig_max + 1.0;
         const double e = std::ldexp(lmax, -32) + u * (8.0 * X + 3.0 * lmax + 2.0 * r);
         c->guard_q = 2.0 * (2.0 * std::sqrt(3.0) * r * e + 3.0 * e * e + 8.0 * u * r * r);
     }
@@ -612,7 +686,7 @@ rbl_status bin_particles(rbl_ctx* c, const double* pos, const double* vel, bool 
     g.src_of_slot = c->d_src_of_slot;
     g.pos = pos;
     g.vel = vel;
-    g.charges = c->cfg.charges;
+    g.charges = c->wcol();
     g.xs_old = in_place ? c->d_xs[nxt] : c->cur_xs();
     g.vs_old = in_place ? c->d_vs[nxt] : c->cur_vs();
     g.n = c->n;
@@ -664,6 +738,7 @@ BuildArgs build_args(rbl_ctx* c)
     a.full_len = c->d_len[2];
     a.flags = c->d_flags;
     a.gate = nullptr;
+    a.types = c->typed ? c->d_tt : nullptr;
     a.mark = nullptr;
     a.mark_step = 0;
     a.mark_step_dev = nullptr;
@@ -687,6 +762,18 @@ void launch_build(rbl_ctx* c, const BuildArgs& a, int mask)
 {
     const unsigned g = grid_for(c->n_cells, 4);
     const bool wc = mask & RBL_LIST_CORE, ws = mask & RBL_LIST_SHELL, wf = mask & RBL_LIST_FULL;
+    if (c->typed) {
+#define RBL_B(C, S, F) k_build_typed<COUNT_ONLY, C, S, F><<<g, kBlock, 0, c->ls>>>(a)
+        if (wc && ws && wf) RBL_B(true, true, true);
+        else if (wc && ws) RBL_B(true, true, false);
+        else if (wc && wf) RBL_B(true, false, true);
+        else if (ws && wf) RBL_B(false, true, true);
+        else if (wc) RBL_B(true, false, false);
+        else if (ws) RBL_B(false, true, false);
+        else RBL_B(false, false, true);
+#undef RBL_B
+        return;
+    }
 #define RBL_B(C, S, F) k_build<COUNT_ONLY, C, S, F><<<g, kBlock, 0, c->ls>>>(a)
     if (wc && ws && wf) RBL_B(true, true, true);
     else if (wc && ws) RBL_B(true, true, false);
@@ -1001,6 +1088,7 @@ ForceArgs force_args(rbl_ctx* c, int P, uint64_t seed, uint64_t step, bool full)
     a.gate_clear = nullptr;
     a.xq = c->d_xq;
     a.guard = c->guard_q;
+    a.types = c->typed ? c->d_tt : nullptr;
     return a;
 }
 
@@ -1019,7 +1107,7 @@ unsigned force_grid(rbl_ctx* c, Kernel kernel, int64_t vblocks, bool persistent)
     return (unsigned)std::min<int64_t>(g, vblocks);
 }
 
-template <int PREC, int MODE, bool EN, bool ERFC>
+template <int PREC, int MODE, bool EN, int PAIR>
 void launch_force_p(rbl_ctx* c, const ForceArgs& a0)
 {
     ForceArgs a = a0;
@@ -1028,10 +1116,10 @@ void launch_force_p(rbl_ctx* c, const ForceArgs& a0)
         a.vblocks = grid_for(c->n_slots);
         c->part_per = 1;
         if (a.P <= 16) {
-            auto k = k_forces<PREC, MODE, EN, ERFC, 16>;
+            auto k = k_forces<PREC, MODE, EN, PAIR, 16>;
             launch_k(c, k, force_grid(c, k, a.vblocks, pers), 0, a);
         } else {
-            auto k = k_forces<PREC, MODE, EN, ERFC, 32>;
+            auto k = k_forces<PREC, MODE, EN, PAIR, 32>;
             launch_k(c, k, force_grid(c, k, a.vblocks, pers), 0, a);
         }
     } else {
@@ -1039,11 +1127,11 @@ void launch_force_p(rbl_ctx* c, const ForceArgs& a0)
         c->part_per = lpp;
         if (lpp == 4 || lpp == 2) {
             a.vblocks = grid_for(c->n_slots * lpp);
-            auto k = lpp == 4 ? k_forces_lpp<PREC, MODE, EN, ERFC, 4> : k_forces_lpp<PREC, MODE, EN, ERFC, 2>;
+            auto k = lpp == 4 ? k_forces_lpp<PREC, MODE, EN, PAIR, 4> : k_forces_lpp<PREC, MODE, EN, PAIR, 2>;
             launch_k(c, k, force_grid(c, k, a.vblocks, pers), 0, a);
         } else {
             a.vblocks = grid_for(c->n_slots);
-            auto k = k_forces<PREC, MODE, EN, ERFC, 1>;
+            auto k = k_forces<PREC, MODE, EN, PAIR, 1>;
             launch_k(c, k, force_grid(c, k, a.vblocks, pers), 0, a);
         }
     }
@@ -1053,16 +1141,19 @@ template <int MODE>
 void launch_force(rbl_ctx* c, const ForceArgs& a, bool energy)
 {
     const bool mixed = c->cfg.precision == RBL_PREC_MIXED;
-    const bool erfc = c->cfg.pair == RBL_PAIR_LJ_ERFC;
+    const int pair = c->typed ? kPairTyped : (c->cfg.pair == RBL_PAIR_LJ_ERFC ? kPairErfc : kPairLJ);
 #define RBL_F(P, E, X) launch_force_p<P, MODE, E, X>(c, a)
-    if (!mixed && !energy && !erfc) RBL_F(kFP64, false, false);
-    else if (!mixed && energy && !erfc) RBL_F(kFP64, true, false);
-    else if (mixed && !energy && !erfc) RBL_F(kMixed, false, false);
-    else if (mixed && energy && !erfc) RBL_F(kMixed, true, false);
-    else if (!mixed && !energy) RBL_F(kFP64, false, true);
-    else if (!mixed) RBL_F(kFP64, true, true);
-    else if (!energy) RBL_F(kMixed, false, true);
-    else RBL_F(kMixed, true, true);
+#define RBL_FP(X)                                       \
+    do {                                                \
+        if (!mixed && !energy) RBL_F(kFP64, false, X);  \
+        else if (!mixed) RBL_F(kFP64, true, X);         \
+        else if (!energy) RBL_F(kMixed, false, X);      \
+        else RBL_F(kMixed, true, X);                    \
+    } while (0)
+    if (pair == kPairLJ) RBL_FP(kPairLJ);
+    else if (pair == kPairErfc) RBL_FP(kPairErfc);
+    else RBL_FP(kPairTyped);
+#undef RBL_FP
 #undef RBL_F
 }
 
@@ -1151,7 +1242,7 @@ IoArgs io_args(rbl_ctx* c, bool momentum_fix)
     io.slice_rep = c->d_slice_rep;
     io.perm = c->cur_perm();
     io.rep_sum = c->d_rep_sum;
-    io.charges = c->cfg.charges;
+    io.charges = c->wcol();
     io.n = c->n;
     io.n_slots = c->n_slots;
     io.n_slices = c->n_slices;
@@ -1501,6 +1592,10 @@ rbl_status md_run(rbl_ctx* c, const double* pos_in, const double* vel_in, double
     sp.fix = !full && c->cfg.momentum_fix;
     sp.pre = !full && ((c->cfg.predraw && c->fused_ok) || c->stencil);
     sp.check = c->cfg.rebuild_check != 0;
+    if (!full && !sp.pre && P > 32)
+        return fail(RBL_E_ARG, "this context draws its batches in the force kernel (explicit shell rows: "
+                               "particle types, predraw off, or a stencil beyond the fused build), "
+                               "which takes P <= 32");
     const int mask = full ? RBL_LIST_FULL : (RBL_LIST_CORE | RBL_LIST_SHELL);
     const bool use_graph = c->cfg.graphs && !c->profiling && c->gs;
     LaunchStreamGuard guard{c};
@@ -1742,6 +1837,9 @@ void rbl_config_init(rbl_config* cfg, int64_t n)
     cfg->shell_source = RBL_SHELL_LIST;
     cfg->rebuild_check = 0;
     cfg->reserved = 0;
+    cfg->n_types = 0;
+    cfg->types = nullptr;
+    cfg->pair_coeffs = nullptr;
 }
 
 const char* rbl_last_error(void) { return g_err.c_str(); }
@@ -1781,6 +1879,8 @@ rbl_status rbl_destroy(rbl_ctx* c)
     dfree(c->d_xs[0]);
     dfree(c->d_xs[1]);
     dfree(c->d_xq);
+    dfree(c->d_tcol);
+    dfree(c->d_tt);
     dfree(c->d_vs[0]);
     dfree(c->d_vs[1]);
     dfree(c->d_xb);
@@ -1836,6 +1936,29 @@ rbl_status rbl_create(const rbl_config* cfg, void* hip_stream, rbl_ctx** out)
         cfg->shell_source != RBL_SHELL_PAPER)
         return fail(RBL_E_ARG, "shell_source must be RBL_SHELL_LIST, RBL_SHELL_STENCIL or RBL_SHELL_PAPER");
     if (cfg->reserved != 0) return fail(RBL_E_ARG, "reserved must be 0");
+    if (cfg->n_types < 0 || cfg->n_types > kMaxTypes)
+        return fail(RBL_E_ARG, "n_types must be in 0 .. " + std::to_string(kMaxTypes));
+    if (cfg->n_types == 0 && (cfg->types || cfg->pair_coeffs))
+        return fail(RBL_E_ARG, "types and pair_coeffs need n_types >= 1");
+    if (cfg->n_types > 0) {
+        const int T = cfg->n_types;
+        if (!cfg->types || !cfg->pair_coeffs) return fail(RBL_E_ARG, "n_types >= 1 needs types and pair_coeffs");
+        if (cfg->pair != RBL_PAIR_LJ || cfg->charges)
+            return fail(RBL_E_ARG, "particle types take the LJ pair only (no charges)");
+        if (cfg->shell_source != RBL_SHELL_LIST)
+            return fail(RBL_E_ARG, "particle types take shell_source RBL_SHELL_LIST");
+        for (int a = 0; a < T; ++a)
+            for (int b = 0; b < T; ++b) {
+                const double e = cfg->pair_coeffs[(a * T + b) * 2], g = cfg->pair_coeffs[(a * T + b) * 2 + 1];
+                if (!(e >= 0.0) || !(g > 0.0) || !std::isfinite(e) || !std::isfinite(g))
+                    return fail(RBL_E_ARG, "pair_coeffs: epsilon must be >= 0 and sigma > 0, finite");
+                if (e != cfg->pair_coeffs[(b * T + a) * 2] || g != cfg->pair_coeffs[(b * T + a) * 2 + 1])
+                    return fail(RBL_E_ARG, "pair_coeffs must be symmetric");
+            }
+        for (int64_t i = 0; i < cfg->n; ++i)
+            if (cfg->types[i] < 0 || cfg->types[i] >= T)
+                return fail(RBL_E_ARG, "particle " + std::to_string(i) + " has a type outside 0 .. n_types-1");
+    }
     std::vector<int64_t> off(cfg->n_replicas + 1);
     if (cfg->n_replicas == 1) {
         off[0] = 0;
@@ -1850,6 +1973,20 @@ rbl_status rbl_create(const rbl_config* cfg, void* hip_stream, rbl_ctx** out)
     rbl_ctx* c = new rbl_ctx();
     c->cfg = *cfg;
     c->cfg.replica_offsets = nullptr;
+    c->cfg.types = nullptr;
+    c->cfg.pair_coeffs = nullptr;
+    if (cfg->n_types > 0) {
+        const int T = cfg->n_types;
+        c->typed = true;
+        // explicit rows: a type's stencil may exceed the fused build's
+        c->fused_ok = false;
+        c->eps_sig.assign(cfg->pair_coeffs, cfg->pair_coeffs + 2 * T * T);
+        c->sig_min = c->sig_max = cfg->pair_coeffs[1];
+        for (int k = 0; k < T * T; ++k) {
+            c->sig_min = std::min(c->sig_min, cfg->pair_coeffs[2 * k + 1]);
+            c->sig_max = std::max(c->sig_max, cfg->pair_coeffs[2 * k + 1]);
+        }
+    }
     c->stream = (hipStream_t)hip_stream;
     c->ls = c->stream;
     c->R = cfg->n_replicas;
@@ -1904,6 +2041,12 @@ rbl_status rbl_create(const rbl_config* cfg, void* hip_stream, rbl_ctx** out)
     CR(dalloc(&c->d_slot_of_id, c->n));
     CR(dalloc(&c->d_xs[0], c->n_slots));
     CR(dalloc(&c->d_xs[1], c->n_slots));
+    if (c->typed) {
+        CR(dalloc(&c->d_tcol, c->n));
+        std::vector<double> tv(cfg->types, cfg->types + cfg->n);
+        if (hipMemcpy(c->d_tcol, tv.data(), sizeof(double) * c->n, hipMemcpyHostToDevice) != hipSuccess)
+            return bail(fail(RBL_E_HIP, "upload of particle types failed"));
+    }
     if (cfg->precision == RBL_PREC_MIXED) CR(dalloc(&c->d_xq, c->n_slots));
     if (c->paper) {
         CR(dalloc(&c->d_pgrid, c->R));
@@ -2452,7 +2595,10 @@ rbl_status rbl_rdf(rbl_ctx* c, const double* pos, double r_max, int nbins, uint6
 {
     if (!c || !pos || !counts) return fail(RBL_E_ARG, "NULL argument");
     if (!c->built) return fail(RBL_E_STATE, "rbl_rdf needs a list build first");
-    if (!(r_max > 0.0) || !(r_max <= c->r_c)) return fail(RBL_E_ARG, "r_max must be in (0, r_c]");
+    // the histogram walks +-2 cells of the build grid: up to the smallest
+    // pair cut-off with particle types
+    if (!(r_max > 0.0) || !(r_max <= c->r_c * c->sig_min))
+        return fail(RBL_E_ARG, c->typed ? "r_max must be in (0, r_c sigma_min]" : "r_max must be in (0, r_c]");
     if (nbins < 1 || nbins > (1 << 20)) return fail(RBL_E_ARG, "nbins must be in 1 .. 2^20");
     c->run.valid = false;
     IoArgs io = io_args(c, false);

@@ -86,6 +86,49 @@ def test_create_rejects_bad_config(lib, over):
     assert lib.rbl_last_error().decode()
 
 
+def test_config_type_fields_default_off(lib):
+    cfg = _lib.Config()
+    lib.rbl_config_init(C.byref(cfg), 10)
+    assert cfg.n_types == 0 and not cfg.types and not cfg.pair_coeffs
+    # the pointers follow the two int32 words at the end of the C struct
+    assert _lib.Config.types.offset == _lib.Config.n_types.offset + 4
+    assert _lib.Config.types.offset % 8 == 0
+
+
+def _typed(lib, types, table, **over):
+    t = (C.c_int32 * len(types))(*types)
+    flat = [v for row in table for pair in row for v in pair]
+    e = (C.c_double * len(flat))(*flat)
+    return _create(lib, n=len(types), n_types=len(table), types=C.cast(t, C.POINTER(C.c_int32)),
+                   pair_coeffs=C.cast(e, C.POINTER(C.c_double)), **over)
+
+
+GOOD2 = [[(1.0, 1.0), (1.0, 1.3)], [(1.0, 1.3), (1.0, 1.6)]]
+
+
+@pytest.mark.parametrize("types,table,over", [
+    ([0, 1, 2], GOOD2, {}),                                          # type out of range
+    ([0, 1, -1], GOOD2, {}),
+    ([0, 1, 1], [[(1.0, 1.0), (1.0, 1.3)], [(1.0, 1.2), (1.0, 1.6)]], {}),   # not symmetric
+    ([0, 1, 1], [[(1.0, 1.0), (1.0, 0.0)], [(1.0, 0.0), (1.0, 1.6)]], {}),   # sigma 0
+    ([0, 1, 1], [[(-1.0, 1.0), (1.0, 1.3)], [(1.0, 1.3), (1.0, 1.6)]], {}),  # epsilon < 0
+    ([0, 1, 1], GOOD2, {"pair": 1, "alpha": 1.0}),                   # no charges with types
+    ([0, 1, 1], GOOD2, {"shell_source": 1}),                         # shell rows only
+    ([0] * 3, [[(1.0, 1.0)] * 5] * 5, {}),                           # more than 4 types
+])
+def test_create_rejects_bad_types(lib, types, table, over):
+    st, h = _typed(lib, types, table, **over)
+    assert st == _lib.RBL_E_ARG
+    assert not h.value
+    assert lib.rbl_last_error().decode()
+
+
+def test_create_rejects_types_without_count(lib):
+    t = (C.c_int32 * 3)(0, 0, 0)
+    st, h = _create(lib, n=3, types=C.cast(t, C.POINTER(C.c_int32)))
+    assert st == _lib.RBL_E_ARG and not h.value
+
+
 def test_calls_reject_null_context(lib):
     box = (C.c_double * 3)(10.0, 10.0, 10.0)
     assert lib.rbl_build(None, None, box, 1.5, 3.5) == _lib.RBL_E_ARG

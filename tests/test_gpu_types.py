@@ -1,0 +1,196 @@
+"""Particle types on the GPU (Sec. II: interaction lengths that differ by
+type).  Pair (a, b) has its own epsilon_ab, sigma_ab, core radius
+r_s sigma_ab and cut-off r_c sigma_ab; the cells are sized by the smallest
+pair cut-off and each type walks its own stencil of cells.
+
+Against the typed oracle: neighbour rows and batches bit for bit, forces
+within 1e-12 relative L2 in FP64 and 2e-5 mixed (with energy and virial),
+trajectories; a table of ones reproduces the one-type kernels bit for bit.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2105_04884_amd import Context, RblError, inputs
+from paper_2105_04884_amd import _lib
+
+from gpu_util import (FP64_TOL, MIXED_TOL, RC, RS, SKIN, assert_forces_close, assert_lists_equal, dev,
+                      host, rel_l2, torch_cuda)
+
+pytestmark = pytest.mark.gpu
+
+# binary: small (0) and large (1) particles; sigma_01 keeps type 0 on a
+# 5-cell stencil while type 1 needs 7 cells per axis
+TABLE2 = np.ascontiguousarray(np.array([[[1.0, 1.0], [1.5, 1.05]], [[1.5, 1.05], [0.5, 1.6]]]))
+EPS3 = np.array([[1.0, 1.5, 0.7], [1.5, 0.5, 1.2], [0.7, 1.2, 2.0]])
+SIG3 = np.array([[1.0, 0.8, 1.3], [0.8, 0.88, 1.1], [1.3, 1.1, 1.6]])
+TABLE3 = np.ascontiguousarray(np.stack([EPS3, SIG3], axis=-1))
+
+
+def _case(name):
+    if name == "binary6000":     # 12 cells of 2.06 per axis: stencils of 5 and 7 cells
+        return inputs.mixture(6000, 0.4, 1.0, 4, (0.8, 0.2)), TABLE2
+    if name == "ternary4000":    # three types, every pair different
+        return inputs.mixture(4000, 0.4, 1.0, 5, (0.5, 0.3, 0.2)), TABLE3
+    if name == "binary700":      # 6 cells per axis: type 1's stencil takes whole axes; ragged slice
+        return inputs.mixture(700, 0.4, 1.0, 6, (0.7, 0.3)), TABLE2
+    raise KeyError(name)
+
+
+CASES = ["binary6000", "ternary4000", "binary700"]
+
+
+def _oracle_lists(pos, box, types, table, kinds=("core", "shell", "full")):
+    return oracle.System(pos, box, RS, RC, SKIN, types=types, eps_sig=table).lists(kinds=kinds)
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_typed_lists_match_oracle(case):
+    """Core, shell and full rows of every particle, entry by entry."""
+    torch_cuda()
+    st, table = _case(case)
+    with Context(st.n, lists=("core", "shell", "full"), types=st.types, eps_sig=table) as ctx:
+        ctx.build(dev(st.pos), st.box, RS, RC)
+        got = ctx.export_lists()
+    assert_lists_equal(got, _oracle_lists(st.pos, st.box, st.types, table))
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_typed_batches_match_oracle(case):
+    """Single-evaluation batches at P = 1, 10 and 40, two seeds and steps
+    (one past 2^32), entry by entry."""
+    torch_cuda()
+    st, table = _case(case)
+    L = _oracle_lists(st.pos, st.box, st.types, table, kinds=("shell",))
+    rows = np.arange(st.n)
+    with Context(st.n, types=st.types, eps_sig=table) as ctx:
+        ctx.build(dev(st.pos), st.box, RS, RC)
+        for P in (1, 10, 40):
+            for seed, step in ((1, 0), (2**40 + 3, 2**32 + 5)):
+                batch, count = ctx.export_batches(P, seed, step, rows)
+                for i in range(0, st.n, 3):
+                    row = L.row("shell", i)
+                    kpos = oracle.batch_positions(seed, i, step, 0, P, len(row))
+                    assert count[i] == len(kpos), (case, P, i)
+                    assert np.array_equal(batch[i, :count[i]], row[kpos]), (case, P, seed, i)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("mixed", MIXED_TOL)])
+@pytest.mark.parametrize("case", ["binary6000", "ternary4000"])
+def test_typed_forces_match_oracle(case, precision, tol):
+    """RBL force (P = 10 inline, P = 40 pre-drawn) and the typed direct
+    truncation, at the build state and at displaced positions, with the
+    mean-force subtraction, energy and virial."""
+    torch_cuda()
+    st, table = _case(case)
+    pos, box = st.pos, st.box
+    L = _oracle_lists(pos, box, st.types, table)
+    rng = np.random.default_rng(3)
+    kw = dict(types=st.types, eps_sig=table)
+    with Context(st.n, precision=precision, lists=("core", "shell", "full"), **kw) as ctx:
+        ctx.build(dev(pos), box, RS, RC)
+        for k, p in enumerate((pos, pos + rng.uniform(-0.1, 0.1, size=pos.shape))):
+            for P in (10, 40):
+                f, ev = ctx.forces(P, seed=11 + k, step=3 * k, pos=dev(p), want_ev=True)
+                fo, eo, wo = oracle.rbl_forces(p, box, RS, RC, L, P, 11 + k, 3 * k, **kw)
+                fo, _ = oracle.mean_subtract(fo)
+                assert_forces_close(host(f), fo, tol, (case, precision, P, k))
+                U, W = host(ev)
+                assert abs(U - eo.sum()) <= tol * max(1.0, abs(eo.sum())) * 10
+                assert abs(W - wo.sum()) <= tol * max(1.0, abs(wo.sum())) * 10
+            g, evf = ctx.full_forces(dev(p), want_ev=True)
+            go, ego, wgo = oracle.full_forces(p, box, RC, L, **kw)
+            assert_forces_close(host(g), go, tol, (case, precision, "full", k))
+            U, W = host(evf)
+            assert abs(U - ego.sum()) <= tol * max(1.0, abs(ego.sum())) * 10
+            assert abs(W - wgo.sum()) <= tol * max(1.0, abs(wgo.sum())) * 10
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_typed_table_of_ones_is_the_one_type_path(precision):
+    """epsilon = sigma = 1 for every pair, types drawn at random: the typed
+    kernels give the one-type kernels' lists and forces bit for bit."""
+    torch_cuda()
+    st = inputs.mixture(5000, 0.8442, 1.0, 7, (0.4, 0.3, 0.3))
+    ones = np.ones((3, 3, 2))
+    out = []
+    for kw in ({}, {"types": st.types, "eps_sig": ones}):
+        with Context(st.n, precision=precision, lists=("core", "shell", "full"), **kw) as ctx:
+            ctx.build(dev(st.pos), st.box, RS, RC)
+            lists = ctx.export_lists()
+            f, ev = ctx.forces(10, seed=2, step=5, pos=dev(st.pos), want_ev=True)
+            g = ctx.full_forces(dev(st.pos))
+            out.append((lists, host(f), host(ev), host(g)))
+    (l0, f0, e0, g0), (l1, f1, e1, g1) = out
+    for kind in ("core", "shell", "full"):
+        assert np.array_equal(l0[kind + "_off"], l1[kind + "_off"])
+        assert np.array_equal(l0[kind + "_idx"], l1[kind + "_idx"])
+    assert np.array_equal(f0, f1) and np.array_equal(e0, e1) and np.array_equal(g0, g1)
+
+
+@pytest.mark.parametrize("check", [False, True])
+def test_typed_trajectory_matches_oracle(check):
+    """60 velocity-Verlet steps of the binary mixture (P = 10), lists every
+    10 steps or on displacement: final state, force and energy against the
+    typed oracle run."""
+    torch = torch_cuda()
+    st, table = _case("binary6000")
+    x, v = dev(st.pos), dev(st.vel)
+    f = torch.zeros_like(x)
+    with Context(st.n, types=st.types, eps_sig=table, rebuild_check=check) as ctx:
+        ctx.build(x, st.box, RS, RC)
+        status, ev = ctx.step(x, v, nsteps=60, dt=0.002, P=10, seed=4, step0=0, rebuild_every=10,
+                              force=f, want_ev=True)
+    xo, vo, fo, evo = oracle.md_run(st.pos, st.vel, st.box, RS, RC, SKIN, 0.002, 60, p=10, seed=4, K=10,
+                                    want_ev=True, check=check, types=st.types, eps_sig=table)
+    assert rel_l2(host(x), xo) < 1e-12
+    assert rel_l2(host(v), vo) < 1e-9
+    assert_forces_close(host(f), fo, 1e-9)
+    assert abs(host(ev)[0] - evo[-1, 0]) < 1e-9 * abs(evo[-1, 0])
+
+
+def test_typed_mixed_trajectory_stays_close():
+    """The mixed-precision typed run tracks the FP64 oracle over 40 steps."""
+    torch = torch_cuda()
+    st, table = _case("ternary4000")
+    x, v = dev(st.pos), dev(st.vel)
+    with Context(st.n, precision="mixed", types=st.types, eps_sig=table, rebuild_check=True) as ctx:
+        ctx.build(x, st.box, RS, RC)
+        ctx.step(x, v, nsteps=40, dt=0.002, P=10, seed=8, step0=0, rebuild_every=10)
+    xo, vo, _, _ = oracle.md_run(st.pos, st.vel, st.box, RS, RC, SKIN, 0.002, 40, p=10, seed=8, K=10,
+                                 check=True, types=st.types, eps_sig=table)
+    assert rel_l2(host(x), xo) < 1e-8
+    assert rel_l2(host(v), vo) < 1e-4
+
+
+def test_typed_large_mixture_sampled_rows():
+    """A 200,000-particle binary mixture: sampled rows' lists and raw
+    forces (no mean subtraction) against the oracle."""
+    torch_cuda()
+    st = inputs.binary_mixture(200_000, seed=2)
+    table = TABLE2
+    rows = np.random.default_rng(1).choice(st.n, 300, replace=False)
+    S = oracle.System(st.pos, st.box, RS, RC, SKIN, types=st.types, eps_sig=table)
+    L = S.lists(rows=rows)
+    for precision, tol in (("fp64", FP64_TOL), ("mixed", MIXED_TOL)):
+        with Context(st.n, precision=precision, momentum_fix=False, types=st.types, eps_sig=table) as ctx:
+            ctx.build(dev(st.pos), st.box, RS, RC)
+            got = ctx.export_lists(rows=rows, kinds=("core", "shell"))
+            f = host(ctx.forces(10, seed=3, step=1, pos=dev(st.pos)))
+        assert_lists_equal(got, L, kinds=("core", "shell"))
+        fo, _, _ = oracle.rbl_forces(st.pos, st.box, RS, RC, L, 10, 3, 1, types=st.types, eps_sig=table)
+        assert_forces_close(f[:, rows], fo, tol, precision)
+
+
+def test_typed_limits():
+    """rbl_step takes P <= 32 with types (batches drawn in the force
+    kernel), and the pair histogram reaches the smallest pair cut-off."""
+    torch_cuda()
+    st, table = _case("binary700")
+    with Context(st.n, types=st.types, eps_sig=table) as ctx:
+        ctx.build(dev(st.pos), st.box, RS, RC)
+        with pytest.raises(RblError):
+            ctx.step(dev(st.pos), dev(st.vel), nsteps=2, dt=0.002, P=33)
+        ctx.rdf(dev(st.pos), RC * 1.0, 50)
+        with pytest.raises(RblError):
+            ctx.rdf(dev(st.pos), RC * 1.01, 50)
