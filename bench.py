@@ -90,11 +90,12 @@ def parse(argv=None):
                     help="equilibration steps of the table1 workload")
     ap.add_argument("--table1-prod", type=int, default=100_000,
                     help="production steps of the table1 workload")
-    ap.add_argument("--workloads", default="ensemble,large,slab",
+    ap.add_argument("--workloads", default="ensemble,large,slab,mixture",
                     help="further workloads reported beside the headline: comma list of "
                          "'ensemble' (512 replicas), 'large' (N = 2^24), 'slab' (charged "
-                         "slab, N = 2M, LJ + erfc), 'table1' (the Sec. III coexistence "
-                         "study: minutes of GPU time, not in the default), or 'none'")
+                         "slab, N = 2M, LJ + erfc), 'mixture' (binary mixture with per-type "
+                         "cut-offs, N = 1M), 'table1' (the Sec. III coexistence study: minutes "
+                         "of GPU time, not in the default), or 'none'")
     ap.add_argument("--summarize-requests", nargs=2, metavar=("READ_DIR", "WRITE_DIR"),
                     help="write profiles/request_sizes_n1m.txt from two rocprofv3 --pmc runs "
                          "of the request counters (see REQUEST_COUNTERS)")
@@ -450,6 +451,43 @@ def run_slab(torch, warmup, steps, repeats, P=20):
             "ms_per_step": 1e3 * el / steps, "status": tb["status"], "attempts_max": tb["attempts_max"],
             "steps_per_build": tb["steps_per_build"],
             "kernels_avg_us": kernels_avg_us(tb)}
+
+
+# binary mixture of the per-type cut-off workload: epsilon 1 for every pair,
+# sigma 1 (small), 1.4 (large) and 1.2 between them
+MIXTURE_TABLE = np.array([[[1.0, 1.0], [1.0, 1.2]], [[1.0, 1.2], [1.0, 1.4]]])
+
+
+def run_mixture(torch, warmup, steps, repeats, P=10):
+    """Binary LJ mixture, N = 1,000,000 (80% sigma 1, 20% sigma 1.4,
+    density 0.5, T = 1): pair radii r_s sigma_ab, r_c sigma_ab, cells from
+    the smallest cut-off and one stencil per type (Sec. II).  RBL (P = 10)
+    and the typed direct truncation, both mixed, lists rebuilt on
+    displacement."""
+    from paper_2105_04884_amd import Context, inputs
+    st = inputs.binary_mixture(1_000_000, seed=1)
+    n = st.n
+    out = {"workload": "binary LJ mixture N=1,000,000 (80% sigma=1, 20% sigma=1.4, sigma_AB=1.2, "
+                       "epsilon=1), density 0.5, T=1.0, pair radii r_s sigma_ab and r_c sigma_ab "
+                       "(r_s=1.5, r_c=3.5), cells from the smallest cut-off, one stencil per type, "
+                       "P=10, dt=0.005, mixed, lists rebuilt on displacement",
+           "n_particles": n, "steps": steps, "repeats": repeats}
+    for name, full, skin, life in (("rbl", False, SKIN_RBL, LIFE_RBL), ("full_list", True, SKIN_FULL, LIFE_FULL)):
+        x, v = torch.from_numpy(st.pos).cuda(), torch.from_numpy(st.vel).cuda()
+        lists = ("full",) if full else ("core", "shell")
+        with Context(n, precision="mixed", lists=lists, skin=skin, rebuild_check=True, types=st.types,
+                     eps_sig=MIXTURE_TABLE) as ctx:
+            ctx.build(x, st.box, RS, RC)
+            tb = timed_blocks(ctx, x, v, torch, P, warmup, steps, repeats, full, K=life)
+        el = tb["median_s"]
+        log(f"[bench] mixture {name}: {1e3 * el / steps:.3f} ms/step, {n * steps / el:.3e} atom-steps/s")
+        out[name] = {"skin": skin, "atom_steps_per_s": n * steps / el, "ms_per_step": 1e3 * el / steps,
+                     "status": tb["status"], "attempts_max": tb["attempts_max"],
+                     "steps_per_build": tb["steps_per_build"], "kernels_avg_us": kernels_avg_us(tb),
+                     "build_us_per_build": round(tb["kernels_ms"]["build"]["avg_us_per_build"], 1)}
+    if "rbl" in out and "full_list" in out:
+        out["rbl_speedup_vs_full_list"] = out["rbl"]["atom_steps_per_s"] / out["full_list"]["atom_steps_per_s"]
+    return out
 
 
 def run_ensemble(torch, warmup, steps, repeats, seq_replicas=16):
@@ -1100,6 +1138,10 @@ def main(argv=None):
     if "large" in wl:
         log("[bench] workload: N = 2^24")
         extra["large"] = guarded("large", run_large, torch, 10, lifetimes(200 // args.repeats), args.repeats)
+    if "mixture" in wl:
+        log("[bench] workload: binary mixture with per-type cut-offs")
+        extra["mixture"] = guarded("mixture", run_mixture, torch, 10, lifetimes(500 // args.repeats),
+                                   args.repeats)
     if "slab" in wl:
         log("[bench] workload: charged slab")
         extra["slab"] = guarded("slab", run_slab, torch, 10, lifetimes(500 // args.repeats), args.repeats)
