@@ -194,3 +194,67 @@ def test_typed_limits():
         ctx.rdf(dev(st.pos), RC * 1.0, 50)
         with pytest.raises(RblError):
             ctx.rdf(dev(st.pos), RC * 1.01, 50)
+
+
+def test_typed_ensemble_matches_oracle_per_replica():
+    """Replicas of different sizes and type fractions in one context share
+    the pair table: every replica's rows and forces against the oracle."""
+    torch_cuda()
+    specs = [(700, 0.4, 6, (0.8, 0.2)), (1100, 0.35, 7, (0.5, 0.5)), (900, 0.45, 8, (0.95, 0.05))]
+    states = [inputs.mixture(n, rho, 1.0, seed, fr) for n, rho, seed, fr in specs]
+    pos = np.concatenate([s.pos for s in states], axis=1)
+    types = np.concatenate([s.types for s in states])
+    boxes = np.stack([s.box for s in states])
+    off = np.zeros(len(states) + 1, dtype=np.int64)
+    off[1:] = np.cumsum([s.n for s in states])
+    n = int(off[-1])
+    with Context(n, replica_offsets=off, lists=("core", "shell", "full"), types=types, eps_sig=TABLE2) as ctx:
+        ctx.build(dev(pos), boxes, RS, RC)
+        got = ctx.export_lists()
+        f = host(ctx.forces(10, seed=3, step=7, pos=dev(pos)))
+        g = host(ctx.full_forces(dev(pos)))
+    for r, s in enumerate(states):
+        kw = dict(types=s.types, eps_sig=TABLE2)
+        L = oracle.System(s.pos, s.box, RS, RC, SKIN, **kw).lists()
+        for kind in ("core", "shell", "full"):
+            go = got[kind + "_off"][off[r]:off[r + 1] + 1]
+            gi = got[kind + "_idx"][go[0]:go[-1]] - off[r]
+            assert np.array_equal(go - go[0], getattr(L, kind + "_off")), (r, kind)
+            assert np.array_equal(gi, getattr(L, kind + "_idx")), (r, kind)
+        sl = slice(off[r], off[r + 1])
+        fo, _, _ = oracle.rbl_forces(s.pos, s.box, RS, RC, L, 10, 3, 7, replica=r, **kw)
+        fo, _ = oracle.mean_subtract(fo)
+        assert_forces_close(f[:, sl], fo, FP64_TOL, r)
+        go_, _, _ = oracle.full_forces(s.pos, s.box, RC, L, **kw)
+        assert_forces_close(g[:, sl], go_, FP64_TOL, r)
+
+
+def test_typed_langevin_trajectory_matches_oracle():
+    """60 BAOAB steps (gamma = 1, kT = 0.9) of the binary mixture."""
+    torch = torch_cuda()
+    st, table = _case("binary6000")
+    x, v = dev(st.pos), dev(st.vel)
+    with Context(st.n, types=st.types, eps_sig=table) as ctx:
+        ctx.set_thermostat(1.0, 0.9)
+        ctx.build(x, st.box, RS, RC)
+        ctx.step(x, v, nsteps=60, dt=0.002, P=10, seed=3, rebuild_every=10)
+    xo, vo, _, _ = oracle.md_run(st.pos, st.vel, st.box, RS, RC, SKIN, 0.002, 60, p=10, seed=3, K=10,
+                                 gamma=1.0, kT=0.9, types=st.types, eps_sig=table)
+    assert rel_l2(host(x), xo) < 1e-11
+    assert rel_l2(host(v), vo) < 1e-8
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_typed_noalloc_equals_rbl_forces(precision):
+    """The allocation-free force call on a typed context gives the same
+    forces and energies as rbl_forces, bit for bit, P = 10 and 40."""
+    torch = torch_cuda()
+    st, table = _case("ternary4000")
+    with Context(st.n, precision=precision, types=st.types, eps_sig=table) as ctx:
+        ctx.build(dev(st.pos), st.box, RS, RC)
+        for P in (10, 40):
+            f, ev = ctx.forces(P, seed=4, step=2, pos=dev(st.pos), want_ev=True)
+            g = torch.empty_like(f)
+            evg = torch.zeros_like(ev)
+            ctx.forces_noalloc(P, 4, 2, dev(st.pos), g, evg)
+            assert torch.equal(f, g) and torch.equal(ev, evg), P
