@@ -237,7 +237,10 @@ rbl_status rbl_full_forces(rbl_ctx* ctx, const double* pos, double* force, doubl
  * force (device, may be NULL) receives the final force, ev (device, may be
  * NULL) the final [U, W] per replica.  Box and radii are those of the last
  * rbl_build.  Returns RBL_W_SKIN if any particle moved more than skin/2
- * within one list lifetime.
+ * within one list lifetime.  P is at most RBL_MAX_P when the batches are
+ * drawn at the list builds (cfg.predraw, one particle type), and at most 32
+ * when the force kernel draws them from explicit shell rows (predraw off,
+ * particle types, or a stencil too wide for the fused build).
  * Errors: RBL_E_ARG, RBL_E_STATE, RBL_E_NONFINITE, RBL_E_NOMEM, RBL_E_HIP.
  */
 rbl_status rbl_step(rbl_ctx* ctx, double* pos, double* vel, double* force,
