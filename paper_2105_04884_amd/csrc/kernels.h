@@ -557,9 +557,25 @@ __device__ __forceinline__ int shfl_i32(int v, int src_lane)
     return __builtin_amdgcn_ds_bpermute(src_lane << 2, v);
 }
 
+// Ordering of one wavefront's LDS accesses across its lanes: earlier reads
+// done before the writes, the writes visible before the reads after them.
+__device__ __forceinline__ void lds_fence_before_write()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ void lds_fence_after_write()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <bool COUNT_ONLY, bool WC, bool WS, bool WF>
 __global__ __launch_bounds__(256) void k_build(BuildArgs a)
 {
+    __shared__ double4 s_ctr[4][64];  // the group's centre positions, per wavefront
     if (gated_off(a.gate)) return;
     if (!COUNT_ONLY) record_build(a);
     const int lane = threadIdx.x & 63;
@@ -611,10 +627,16 @@ __global__ __launch_bounds__(256) void k_build(BuildArgs a)
     const int total = __builtin_amdgcn_readlane(incl, 63);
     const int rpre = incl - rlen;
 
+    double4* const ctr = s_ctr[threadIdx.x >> 6];
     for (int g0 = 0; g0 < m; g0 += 64) {
         const int mg = min(64, m - g0);
         double4 xc = make_double4(0.0, 0.0, 0.0, 0.0);
         if (lane < mg) xc = a.xs[i0 + g0 + lane];
+        // centre positions for the tests: one LDS read (the same address in
+        // every lane) per test instead of six lane reads
+        lds_fence_before_write();
+        ctr[lane] = xc;
+        lds_fence_after_write();
         int cnt_c = 0, cnt_s = 0, cnt_f = 0;
         for (int base = 0; base < total; base += 64) {
             const int f = base + lane;
@@ -633,7 +655,7 @@ __global__ __launch_bounds__(256) void k_build(BuildArgs a)
             if (valid) xj = a.xs[j];
             for (int ii = 0; ii < mg; ++ii) {
                 const int islot = i0 + g0 + ii;
-                const double4 xi = make_double4(bcast(xc.x, ii), bcast(xc.y, ii), bcast(xc.z, ii), 0.0);
+                const double4 xi = ctr[ii];
                 const Delta d = delta(xi, xj, R);
                 const bool ok = valid && j != islot;
                 if (WC) {
@@ -710,6 +732,7 @@ template <bool COUNT_ONLY, bool WC, bool WS, bool WF>
 __global__ __launch_bounds__(256) void k_build_typed(BuildArgs a)
 {
     __shared__ double s_thr[3][kMaxTypes * kMaxTypes];  // core, shell inner, outer thresholds per pair
+    __shared__ double4 s_ctr[4][64];                     // the group's centre positions, per wavefront
     if (gated_off(a.gate)) return;
     if (!COUNT_ONLY) record_build(a);
     for (int k = threadIdx.x; k < kMaxTypes * kMaxTypes; k += blockDim.x) {
@@ -734,12 +757,18 @@ __global__ __launch_bounds__(256) void k_build_typed(BuildArgs a)
     const int cy = (int)((lc / R.nc[0]) % R.nc[1]);
     const int cz = (int)(lc / ((int64_t)R.nc[0] * R.nc[1]));
     const int ntypes = a.types->n_types;
+    double4* const ctr = s_ctr[threadIdx.x >> 6];
 
     for (int g0 = 0; g0 < m; g0 += 64) {
         const int mg = min(64, m - g0);
         double4 xc = make_double4(0.0, 0.0, 0.0, 0.0);
         if (lane < mg) xc = a.xs[i0 + g0 + lane];
         const int tc = lane < mg ? type_of(xc.w) : -1;
+        // centre positions for the tests: one LDS read (the same address in
+        // every lane) per test instead of six lane reads
+        lds_fence_before_write();
+        ctr[lane] = xc;
+        lds_fence_after_write();
         int cnt_c = 0, cnt_s = 0, cnt_f = 0;
         for (int t = 0; t < ntypes; ++t) {
             const uint64_t centres = __ballot(tc == t);
@@ -787,7 +816,7 @@ __global__ __launch_bounds__(256) void k_build_typed(BuildArgs a)
                     for (uint64_t rest = centres; rest; rest &= rest - 1) {
                         const int ii = (int)__builtin_ctzll(rest);
                         const int islot = i0 + g0 + ii;
-                        const double4 xi = make_double4(bcast(xc.x, ii), bcast(xc.y, ii), bcast(xc.z, ii), 0.0);
+                        const double4 xi = ctr[ii];
                         const Delta d = delta(xi, xj, R);
                         const bool ok = valid && j != islot;
                         if (WC) {
