@@ -545,6 +545,51 @@ __device__ __forceinline__ int axis_cell(const AxisRuns& a, int k)
     return k < a.l0 ? a.p0 + k : a.p1 + (k - a.l0);
 }
 
+struct AxisRunsS {
+    int p0, l0, p1, l1;
+    int s0, s1;  // image shift (in box lengths, added to x_i - x_j) of run 0 / run 1
+};
+
+__device__ __forceinline__ AxisRunsS axis_runs_s(int c, int nc, int h = 2)
+{
+    AxisRunsS a;
+    const AxisRuns b = axis_runs(c, nc, h);
+    a.p0 = b.p0;
+    a.l0 = b.l0;
+    a.p1 = b.p1;
+    a.l1 = b.l1;
+    a.s0 = 0;
+    a.s1 = 0;
+    if (nc > 2 * h + 1) {
+        const int lo = c - h, hi = c + h;
+        if (lo < 0) {
+            a.s1 = 1;   // cells lo+nc..nc-1 are images one box below
+        } else if (hi > nc - 1) {
+            a.s0 = -1;  // cells 0..hi-nc are images one box above
+        }
+    }
+    return a;
+}
+
+__device__ __forceinline__ int axis_shift(const AxisRunsS& a, int k)
+{
+    return k < a.l0 ? a.s0 : a.s1;
+}
+
+// Wave masks of per-lane FP64 compares (llvm.amdgcn.fcmp; an ordered
+// predicate, so a NaN compares false).
+__device__ __forceinline__ uint64_t cmp_lt_mask(double x, double t)
+{
+    return __builtin_amdgcn_fcmp(x, t, 4);  // FCMP_OLT
+}
+
+__device__ __forceinline__ uint64_t cmp_ge_mask(double x, double t)
+{
+    return __builtin_amdgcn_fcmp(x, t, 3);  // FCMP_OGE
+}
+
+constexpr int kNoShift = 1 | (1 << 2) | (1 << 4);  // image-shift code of no shift
+
 __device__ __forceinline__ double bcast(double v, int lane)
 {
     const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
@@ -593,22 +638,27 @@ __global__ __launch_bounds__(256) void k_build(BuildArgs a)
     const int cx = (int)(lc % R.nc[0]);
     const int cy = (int)((lc / R.nc[0]) % R.nc[1]);
     const int cz = (int)(lc / ((int64_t)R.nc[0] * R.nc[1]));
-    const AxisRuns ax = axis_runs(cx, R.nc[0]);
-    const AxisRuns ay = axis_runs(cy, R.nc[1]);
-    const AxisRuns az = axis_runs(cz, R.nc[2]);
+    const AxisRunsS ax = axis_runs_s(cx, R.nc[0]);
+    const AxisRunsS ay = axis_runs_s(cy, R.nc[1]);
+    const AxisRunsS az = axis_runs_s(cz, R.nc[2]);
     const int ny_s = ay.l0 + ay.l1;
     const int nz_s = az.l0 + az.l1;
+    // with at least 7 cells per axis the periodic image of every run is
+    // known, and x_i - x_j plus that image's shift (0 or -+L) is exactly
+    // the minimum-image displacement (as in the fused build)
+    const bool SHIFT = R.nc[0] >= 7 && R.nc[1] >= 7 && R.nc[2] >= 7;
 
-    // lane q describes run q = ((z * ny_s) + y) * 2 + xrun of the stencil
-    int rstart = 0, rlen = 0;
+    // lane q describes run q = ((z * ny_s) + y) * 2 + xrun of the stencil:
+    // slot start, length and image-shift code
+    int rstart = 0, rlen = 0, rshift = kNoShift;
     {
         const int q = lane;
         const int zi = q / (2 * ny_s);
         const int yi = (q >> 1) % ny_s;
         const int xr = q & 1;
         if (zi < nz_s) {
-            const int zc = axis_cell(az, zi);
-            const int yc = axis_cell(ay, yi);
+            const int zc = axis_cell(AxisRuns{az.p0, az.l0, az.p1, az.l1}, zi);
+            const int yc = axis_cell(AxisRuns{ay.p0, ay.l0, ay.p1, ay.l1}, yi);
             const int px = xr == 0 ? ax.p0 : ax.p1;
             const int lx = xr == 0 ? ax.l0 : ax.l1;
             if (lx > 0) {
@@ -618,6 +668,8 @@ __global__ __launch_bounds__(256) void k_build(BuildArgs a)
                 rstart = a.cell_start[c0];
                 rlen = a.cell_start[c1] + a.cell_count[c1] - rstart;
             }
+            const int sx = xr == 0 ? ax.s0 : ax.s1;
+            rshift = (sx + 1) | ((axis_shift(ay, yi) + 1) << 2) | ((axis_shift(az, zi) + 1) << 4);
         }
     }
     // exclusive prefix of the run lengths: non-decreasing over the lanes, so
@@ -651,42 +703,66 @@ __global__ __launch_bounds__(256) void k_build(BuildArgs a)
             const int qp = shfl_i32(rpre, q);
             const int j = qs + (f - qp);
             const bool valid = f < total && j >= 0 && (int64_t)j < a.n_slots;
+            // (the lane read runs in every lane: a lane permute from a lane
+            // that is switched off reads zero)
+            const int code_q = shfl_i32(rshift, q);
+            const int code = valid ? code_q : kNoShift;
             double4 xj = make_double4(0.0, 0.0, 0.0, 0.0);
             if (valid) xj = a.xs[j];
-            for (int ii = 0; ii < mg; ++ii) {
+            const uint64_t vmask = __builtin_amdgcn_ballot_w64(valid);
+            // the tests of centre ii against the chunk, each classification
+            // one compare that writes its wave mask
+            auto test = [&](int ii, double dx, double dy, double dz) {
+                const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
                 const int islot = i0 + g0 + ii;
-                const double4 xi = ctr[ii];
-                const Delta d = delta(xi, xj, R);
-                const bool ok = valid && j != islot;
+                const uint64_t ok = vmask & __builtin_amdgcn_ballot_w64(j != islot);
                 if (WC) {
-                    const bool in = ok && d.r2 < a.thr_core;
-                    const uint64_t mk = __ballot(in);
+                    const uint64_t mk = ok & cmp_lt_mask(r2, a.thr_core);
                     const int b0 = __builtin_amdgcn_readlane(cnt_c, ii);
-                    if (!COUNT_ONLY && in) {
+                    if (!COUNT_ONLY && __builtin_amdgcn_inverse_ballot_w64(mk)) {
                         const int p = b0 + (int)mbcnt(mk);
                         if (p < a.cap_core) a.core[ell(islot, p, a.cap_core)] = j;
                     }
                     if (lane == ii) cnt_c += __popcll(mk);
                 }
                 if (WS) {
-                    const bool in = ok && d.r2 >= a.thr_shell_in && d.r2 < a.thr_out;
-                    const uint64_t mk = __ballot(in);
+                    const uint64_t mk = ok & cmp_ge_mask(r2, a.thr_shell_in) & cmp_lt_mask(r2, a.thr_out);
                     const int b0 = __builtin_amdgcn_readlane(cnt_s, ii);
-                    if (!COUNT_ONLY && in) {
+                    if (!COUNT_ONLY && __builtin_amdgcn_inverse_ballot_w64(mk)) {
                         const int p = b0 + (int)mbcnt(mk);
                         if (p < a.cap_shell) a.shell[ell(islot, p, a.cap_shell)] = j;
                     }
                     if (lane == ii) cnt_s += __popcll(mk);
                 }
                 if (WF) {
-                    const bool in = ok && d.r2 < a.thr_out;
-                    const uint64_t mk = __ballot(in);
+                    const uint64_t mk = ok & cmp_lt_mask(r2, a.thr_out);
                     const int b0 = __builtin_amdgcn_readlane(cnt_f, ii);
-                    if (!COUNT_ONLY && in) {
+                    if (!COUNT_ONLY && __builtin_amdgcn_inverse_ballot_w64(mk)) {
                         const int p = b0 + (int)mbcnt(mk);
                         if (p < a.cap_full) a.full[ell(islot, p, a.cap_full)] = j;
                     }
                     if (lane == ii) cnt_f += __popcll(mk);
+                }
+            };
+            if (SHIFT && __ballot(code != kNoShift) == 0) {
+                // no periodic image in the chunk: (x_i - x_j) + 0 is x_i - x_j
+                for (int ii = 0; ii < mg; ++ii) {
+                    const double4 xi = ctr[ii];
+                    test(ii, xi.x - xj.x, xi.y - xj.y, xi.z - xj.z);
+                }
+            } else if (SHIFT) {
+                const double shx = (double)((code & 3) - 1) * R.L[0];
+                const double shy = (double)(((code >> 2) & 3) - 1) * R.L[1];
+                const double shz = (double)(((code >> 4) & 3) - 1) * R.L[2];
+                for (int ii = 0; ii < mg; ++ii) {
+                    const double4 xi = ctr[ii];
+                    test(ii, (xi.x - xj.x) + shx, (xi.y - xj.y) + shy, (xi.z - xj.z) + shz);
+                }
+            } else {
+                for (int ii = 0; ii < mg; ++ii) {
+                    const double4 xi = ctr[ii];
+                    test(ii, min_image(xi.x - xj.x, R.L[0], R.inv[0]), min_image(xi.y - xj.y, R.L[1], R.inv[1]),
+                         min_image(xi.z - xj.z, R.L[2], R.inv[2]));
                 }
             }
         }
@@ -965,37 +1041,6 @@ __device__ __forceinline__ void wave_lds_fence()
 // the centre cell when r_s + skin fits one cell edge (else the 5 x 5 x 5
 // stencil), and with draw_only set the kernel writes just the batches and
 // N_I (the batch export and single force evaluations of a build).
-struct AxisRunsS {
-    int p0, l0, p1, l1;
-    int s0, s1;  // image shift (in box lengths, added to x_i - x_j) of run 0 / run 1
-};
-
-__device__ __forceinline__ AxisRunsS axis_runs_s(int c, int nc, int h = 2)
-{
-    AxisRunsS a;
-    const AxisRuns b = axis_runs(c, nc, h);
-    a.p0 = b.p0;
-    a.l0 = b.l0;
-    a.p1 = b.p1;
-    a.l1 = b.l1;
-    a.s0 = 0;
-    a.s1 = 0;
-    if (nc > 2 * h + 1) {
-        const int lo = c - h, hi = c + h;
-        if (lo < 0) {
-            a.s1 = 1;   // cells lo+nc..nc-1 are images one box below
-        } else if (hi > nc - 1) {
-            a.s0 = -1;  // cells 0..hi-nc are images one box above
-        }
-    }
-    return a;
-}
-
-__device__ __forceinline__ int axis_shift(const AxisRunsS& a, int k)
-{
-    return k < a.l0 ? a.s0 : a.s1;
-}
-
 __device__ __forceinline__ int rfl(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 __device__ __forceinline__ double rfl(double v)
@@ -1030,18 +1075,6 @@ __device__ __forceinline__ int select_lanes(uint64_t mask, int a, int b)
     return r;
 }
 
-// Wave masks of per-lane FP64 compares (llvm.amdgcn.fcmp; an ordered
-// predicate, so a NaN compares false).
-__device__ __forceinline__ uint64_t cmp_lt_mask(double x, double t)
-{
-    return __builtin_amdgcn_fcmp(x, t, 4);  // FCMP_OLT
-}
-
-__device__ __forceinline__ uint64_t cmp_ge_mask(double x, double t)
-{
-    return __builtin_amdgcn_fcmp(x, t, 3);  // FCMP_OGE
-}
-
 constexpr int kCtrMax = 16;        // centre particles per group
 constexpr int kListBudgetMax = 6912;  // 16-bit shell-list entries per wavefront, at most
                                       // (the block's LDS stays within 64 KB)
@@ -1049,7 +1082,6 @@ constexpr int kFusedWavesPerEu = 7;   // occupancy the fused build is compiled f
                                       // as many blocks of 4 wavefronts per CU
 constexpr int kRunOffBits = 10;    // list entry = run << 10 | offset in the run
 constexpr int kRing = 128;         // ring of kept candidates per wavefront (two chunks)
-constexpr int kNoShift = 1 | (1 << 2) | (1 << 4);  // image-shift code of no shift
 
 template <int PMAX, bool STENCIL>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PMAX <= 32 ? kFusedWavesPerEu : 2))) void k_build_draw(FusedArgs fa)
