@@ -2056,12 +2056,16 @@ __device__ __forceinline__ void load_type_table(const ForceArgs& a, TypePair* s_
     __syncthreads();
 }
 
-constexpr int kGatherBatch = 4;
+// neighbours per lane in flight at one lane per particle: 6 for the
+// 16-byte fixed-point records (106 against 109 µs at 4 on the N = 10^6
+// fluid; 8 costs occupancy), 4 for the FP64 double4 records
+template <int PREC>
+constexpr int kGatherBatch = PREC == kMixed ? 6 : 4;
 
 template <int PREC, int MODE, bool ENERGY, int PAIR, int PMAX>
 __device__ __forceinline__ void force_tile(const ForceArgs& a, int64_t tile, uint32_t* s_pos, const TypePair* tp)
 {
-    constexpr int U = kGatherBatch;
+    constexpr int U = kGatherBatch<PREC>;
     const int64_t slot = tile * blockDim.x + threadIdx.x;
     const int64_t slice = slot >> 6;
     if (slice >= a.n_slices) return;
