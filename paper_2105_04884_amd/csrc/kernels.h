@@ -2076,6 +2076,18 @@ __device__ __forceinline__ void force_tile(const ForceArgs& a, int64_t tile, uin
     if (real) {
         const double4 xi = a.xs[slot];
         const int4 qi = PREC == kMixed ? a.xq[slot] : make_int4(0, 0, 0, 0);
+        // pre-drawn batches: the shell size and the first group's batch
+        // entries are loaded with the core rows, so that the shell sum
+        // starts with its indices at hand
+        int bn[U];
+        int nb = 0;
+        const int* brow = nullptr;
+        if constexpr (MODE == kShellPredraw) {
+            nb = min(a.shell_len[slot], a.P);
+            brow = step_batches(a) + slot * a.P;
+#pragma unroll
+            for (int u = 0; u < U; ++u) bn[u] = u < nb ? brow[u] : (int)slot;
+        }
         // core rows (or the full list in direct-truncation mode): r < cut
         Acc c = {0.0, 0.0, 0.0, 0.0, 0.0};
         {
@@ -2116,7 +2128,6 @@ __device__ __forceinline__ void force_tile(const ForceArgs& a, int64_t tile, uin
             }
             Acc sh = {0.0, 0.0, 0.0, 0.0, 0.0};
             const int* srow = a.shell + ell(slot, 0, a.cap_shell);
-            const int* bat = MODE == kShellInline ? nullptr : step_batches(a);
             for (int m = 0; m < cnt; m += U) {
                 int j[U];
                 bool live[U];
@@ -2124,16 +2135,22 @@ __device__ __forceinline__ void force_tile(const ForceArgs& a, int64_t tile, uin
                 for (int u = 0; u < U; ++u) {
                     live[u] = m + u < cnt;
                     int jj = (int)slot;
-                    if (live[u]) {
-                        if (MODE == kShellInline) {
+                    if constexpr (MODE == kShellInline) {
+                        if (live[u]) {
                             const int kq = n > P ? (int)s_pos[(m + u) * 256 + threadIdx.x] : m + u;
                             jj = srow[(int64_t)kq * 64];
-                        } else {
-                            jj = bat[slot * P + m + u];
-                            if ((uint64_t)(uint32_t)jj >= (uint64_t)a.n_slots) jj = (int)slot;
                         }
+                    } else {
+                        // a batch entry outside the slots (never written)
+                        // reads the particle itself, whose pair term is zero
+                        jj = bn[u];
+                        if ((uint64_t)(uint32_t)jj >= (uint64_t)a.n_slots) jj = (int)slot;
                     }
                     j[u] = jj;
+                }
+                if constexpr (MODE == kShellPredraw) {
+#pragma unroll
+                    for (int u = 0; u < U; ++u) bn[u] = m + U + u < nb ? brow[m + U + u] : (int)slot;
                 }
                 gather_accumulate<PREC, ENERGY, PAIR, U>(a, xi, qi, j, live, a.rs2, a.rc2, R, sh, tp, kZoneShell);
             }
