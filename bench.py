@@ -110,7 +110,7 @@ def parse(argv=None):
                     help="with --summarize: the bench.py arguments the profiled runs used")
     ap.add_argument("--pin-launch", action="store_true",
                     help="N = 1e6 variants: fix the force kernels' lanes per particle and launch "
-                         "mode to the autotuner's usual choice there (RBL 2 lanes, full list 4, "
+                         "mode to the autotuner's usual choice there (RBL 1 lane mixed, 2 FP64, full list 4, "
                          "one block per tile) instead of timing them; for profiler runs, whose "
                          "per-dispatch overhead distorts the autotuner's timings")
     ap.add_argument("--skin", type=float, default=None,
@@ -389,7 +389,8 @@ def run_variant(name, x0, v0, box, precision, P, use_full, warmup, steps, repeat
     lists = ("full",) if use_full else ("core", "shell")
     x = x0.clone()
     v = v0.clone()
-    launch = {"lanes": 4 if use_full else 2, "persistent": 1} if pin else {}
+    pinned_lanes = 4 if use_full else (1 if precision == "mixed" else 2)
+    launch = {"lanes": pinned_lanes, "persistent": 1} if pin else {}
     ctx = Context(N, precision=precision, lists=lists, skin=skin, shell_source=source, rebuild_check=check,
                   **launch)
     ctx.build(x, box, RS, RC)
