@@ -182,6 +182,34 @@ def test_typed_large_mixture_sampled_rows():
         assert_forces_close(f[:, rows], fo, tol, precision)
 
 
+def test_typed_million_mixture_in_the_bench_configuration():
+    """The N = 10^6 binary mixture (80% sigma 1, 20% sigma 1.4, sigma_AB 1.2,
+    density 0.5) as the benchmark runs it: mixed precision, autotuned lanes
+    and launch mode, captured list lifetimes, batches pre-drawn per step.
+    After 20 steps (the last force evaluation right after a rebuild) the raw
+    force of sampled rows equals the oracle's typed RBL force at the GPU's
+    final positions, and their core and shell rows match bit for bit."""
+    torch = torch_cuda()
+    st = inputs.binary_mixture(1_000_000, seed=1)
+    table = np.array([[[1.0, 1.0], [1.0, 1.2]], [[1.0, 1.2], [1.0, 1.4]]])
+    x, v = dev(st.pos), dev(st.vel)
+    f = torch.zeros_like(x)
+    rows = np.random.default_rng(6).choice(st.n, size=300, replace=False)
+    with Context(st.n, precision="mixed", momentum_fix=False, types=st.types, eps_sig=table) as ctx:
+        ctx.build(x, st.box, RS, RC)
+        status, _ = ctx.step(x, v, nsteps=20, dt=0.005, P=10, seed=1, rebuild_every=10, force=f)
+        got = ctx.export_lists(rows=rows, kinds=("core", "shell"))
+        tuning = ctx.tuning()
+    assert status in (0, _lib.RBL_W_SKIN)
+    assert tuning["lpp_rbl"] in (1, 2, 4)
+    xg = host(x)
+    L = oracle.System(xg, st.box, RS, RC, SKIN, types=st.types, eps_sig=table).lists(rows=rows)
+    assert_lists_equal(got, L, kinds=("core", "shell"))
+    fo, _, _ = oracle.rbl_forces(xg, st.box, RS, RC, L, 10, 1, 20, types=st.types, eps_sig=table)
+    e, m = assert_forces_close(host(f)[:, rows], fo, MIXED_TOL)
+    print(f"mixture mixed: relative L2 {e:.2e}, worst row {m:.2e}")
+
+
 def test_typed_limits():
     """rbl_step takes P <= 32 with types (batches drawn in the force
     kernel), and the pair histogram reaches the smallest pair cut-off."""
