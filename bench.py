@@ -129,7 +129,7 @@ def plan(args):
     lifetimes: returns (warm-up steps, steps per timed block).  Exits with
     status 2 and a message on arguments this bench cannot run."""
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only (this build has no multi-GPU path); "
+        print("bench.py measures one GPU only (the library has no multi-GPU path); "
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     if args.steps < 1 or args.warmup < 0 or args.repeats < 1:

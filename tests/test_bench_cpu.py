@@ -94,8 +94,8 @@ def test_msd_slope_of_a_line():
     assert bench.msd_slope(t, m) == pytest.approx(2.0, rel=1e-12)
 
 
-def test_driver_command_plans_whole_lifetimes():
-    """The driver's command line (any step counts) is accepted; the counts
+def test_short_command_plans_whole_lifetimes():
+    """A short command line (any step counts) is accepted; the counts
     become whole 10-step blocks, the warm-up at least one, a timed run at
     least 200 steps."""
     assert bench.plan(bench.parse(["--gpus", "1", "--steps", "20", "--warmup", "5"])) == (10, 200)
