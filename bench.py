@@ -61,6 +61,10 @@ RS, RC, SKIN, DT, K_REBUILD = 1.5, 3.5, 0.3, 0.005, 10
 # each the fastest of a sweep at N = 1e6 (skin 0.3 ... 0.6, lifetimes 10 ... 16).
 SKIN_RBL, LIFE_RBL = 0.5, 13
 SKIN_FULL, LIFE_FULL = 0.3, 10
+# core rows filtered to r_s + skin/2 in the runs with rebuilds on
+# displacement where the library's timing finds it pays (rbl_config.core_filter
+# = 2); --no-core-filter turns it off
+CORE_FILTER = "auto"
 N, RHO, TEMP = 1_000_000, 0.8442, 1.0
 HBM_PEAK_GBS = 8000.0
 
@@ -108,6 +112,9 @@ def parse(argv=None):
                          "VALU counters (writes profiles/valu_n1m.txt)")
     ap.add_argument("--profile-command", default="",
                     help="with --summarize: the bench.py arguments the profiled runs used")
+    ap.add_argument("--no-core-filter", action="store_true",
+                    help="keep the force kernel on the built core rows (rbl_config.core_filter = 0) "
+                         "instead of the rows filtered to r_s + skin/2")
     ap.add_argument("--pin-launch", action="store_true",
                     help="N = 1e6 variants: fix the force kernels' lanes per particle and launch "
                          "mode to the autotuner's usual choice there (RBL 1 lane mixed, 2 FP64, full list 4, "
@@ -392,12 +399,14 @@ def run_variant(name, x0, v0, box, precision, P, use_full, warmup, steps, repeat
     pinned_lanes = 4 if use_full else (1 if precision == "mixed" else 2)
     launch = {"lanes": pinned_lanes, "persistent": 1} if pin else {}
     ctx = Context(N, precision=precision, lists=lists, skin=skin, shell_source=source, rebuild_check=check,
+                  core_filter=CORE_FILTER,
                   **launch)
     ctx.build(x, box, RS, RC)
     K = max_life if check else K_REBUILD
     tb = timed_blocks(ctx, x, v, torch, P, warmup, steps, repeats, use_full, K)
     info = ctx.info()
     tuning = ctx.tuning()
+    cfilt = ctx.core_filter()
     counts = ctx.row_counts()
     ncell, _, cell_counts = ctx.export_binning(with_counts=True)
     candidates = stencil_candidates(ncell[0], cell_counts)
@@ -419,6 +428,7 @@ def run_variant(name, x0, v0, box, precision, P, use_full, warmup, steps, repeat
         "mean_row": mean,
         "caps": info,
         "tuning": tuning,
+        "core_filter": cfilt,
         "build_candidates": candidates,
     }
     log(f"[bench] {name}: {res['ms_per_step']:.4f} ms/step, {res['atom_steps_per_s']:.3e} atom-steps/s "
@@ -438,10 +448,11 @@ def run_slab(torch, warmup, steps, repeats, P=20):
     n = st.n
     x, v = torch.from_numpy(st.pos).cuda(), torch.from_numpy(st.vel).cuda()
     q = torch.from_numpy(st.charges).cuda()
-    with Context(n, precision="mixed", skin=SKIN_RBL, pair="lj_erfc", alpha=0.3, charges=q,
+    with Context(n, precision="mixed", skin=SKIN_RBL, pair="lj_erfc", alpha=0.3, charges=q, core_filter=CORE_FILTER,
                  rebuild_check=True) as ctx:
         ctx.build(x, st.box, 1.5, 5.0)
         tb = timed_blocks(ctx, x, v, torch, P, warmup, steps, repeats, K=LIFE_RBL)
+        cfilt = ctx.core_filter()
     el = tb["median_s"]
     log(f"[bench] slab: {1e3 * el / steps:.3f} ms/step, {n * steps / el:.3e} atom-steps/s")
     return {"workload": "charged LJ slab N=2,000,000, box L x L x 3L (L=133.5), liquid rho=0.8 in the "
@@ -451,7 +462,7 @@ def run_slab(torch, warmup, steps, repeats, P=20):
             "n_particles": n, "steps": steps, "repeats": repeats, "atom_steps_per_s": n * steps / el,
             "ms_per_step": 1e3 * el / steps, "status": tb["status"], "attempts_max": tb["attempts_max"],
             "steps_per_build": tb["steps_per_build"],
-            "kernels_avg_us": kernels_avg_us(tb)}
+            "kernels_avg_us": kernels_avg_us(tb), "core_filter": cfilt}
 
 
 # binary mixture of the per-type cut-off workload: epsilon 1 for every pair,
@@ -505,14 +516,16 @@ def run_ensemble(torch, warmup, steps, repeats, seq_replicas=16):
            "replicas": 512, "n_total": n, "steps": steps, "repeats": repeats}
     for precision in ("mixed", "fp64"):
         x, v = torch.from_numpy(pos).cuda(), torch.from_numpy(vel).cuda()
-        with Context(n, precision=precision, replica_offsets=off, skin=SKIN_RBL, rebuild_check=True) as ctx:
+        with Context(n, precision=precision, replica_offsets=off, skin=SKIN_RBL, rebuild_check=True,
+                     core_filter=CORE_FILTER) as ctx:
             ctx.build(x, boxes, RS, RC)
             tb = timed_blocks(ctx, x, v, torch, 10, warmup, steps, repeats, K=LIFE_RBL)
+            cfilt = ctx.core_filter()
         el = tb["median_s"]
         out[precision] = {"atom_steps_per_s": n * steps / el, "ms_per_step": 1e3 * el / steps,
                           "status": tb["status"], "attempts_max": tb["attempts_max"],
-            "steps_per_build": tb["steps_per_build"],
-                          "kernels_avg_us": kernels_avg_us(tb)}
+                          "steps_per_build": tb["steps_per_build"],
+                          "kernels_avg_us": kernels_avg_us(tb), "core_filter": cfilt}
         log(f"[bench] ensemble {precision}: {1e3 * el / steps:.3f} ms/step, {n * steps / el:.3e} atom-steps/s")
     # the same replicas one context each, on a sample of them
     picks = np.linspace(0, 511, seq_replicas).astype(int)
@@ -520,7 +533,7 @@ def run_ensemble(torch, warmup, steps, repeats, seq_replicas=16):
     for r in picks:
         s_ = ens.states[r]
         x, v = torch.from_numpy(s_.pos).cuda(), torch.from_numpy(s_.vel).cuda()
-        with Context(s_.n, precision="mixed", skin=SKIN_RBL, rebuild_check=True) as ctx:
+        with Context(s_.n, precision="mixed", skin=SKIN_RBL, rebuild_check=True, core_filter=CORE_FILTER) as ctx:
             ctx.build(x, s_.box, RS, RC)
             tb = timed_blocks(ctx, x, v, torch, 10, warmup, steps, 1, K=LIFE_RBL)
         tot_atoms += s_.n * steps
@@ -540,10 +553,11 @@ def run_large(torch, warmup, steps, repeats):
     st = inputs.large_fluid(seed=1)
     n = st.n
     x, v = torch.from_numpy(st.pos).cuda(), torch.from_numpy(st.vel).cuda()
-    with Context(n, precision="mixed", skin=SKIN_RBL, rebuild_check=True) as ctx:
+    with Context(n, precision="mixed", skin=SKIN_RBL, rebuild_check=True, core_filter=CORE_FILTER) as ctx:
         ctx.build(x, st.box, 1.3, 4.0)
         tb = timed_blocks(ctx, x, v, torch, 10, warmup, steps, repeats, K=LIFE_RBL)
         tuning = ctx.tuning()
+        cfilt = ctx.core_filter()
     el = tb["median_s"]
     log(f"[bench] large: {1e3 * el / steps:.3f} ms/step, {n * steps / el:.3e} atom-steps/s")
     return {"workload": "LJ fluid N=16,777,216 rho=0.8 T=1.2, r_s=1.3 r_c=4.0 skin=0.5, P=10, "
@@ -557,7 +571,8 @@ def run_large(torch, warmup, steps, repeats):
             # against the persistent grid) and lanes per particle
             "force_launch": {"persistent": tuning["persistent_rbl"],
                              "us_tile_grid_vs_persistent": tuning["rbl_grid_vs_persistent_us"],
-                             "lanes": tuning["lpp_rbl"]}}
+                             "lanes": tuning["lpp_rbl"]},
+            "core_filter": cfilt}
 
 
 def rdf_from_counts(counts, frames, n, volume, dr):
@@ -1036,7 +1051,9 @@ def guarded(name, fn, *a, **kw):
 
 
 def main(argv=None):
+    global CORE_FILTER
     args = parse(argv)
+    CORE_FILTER = False if args.no_core_filter else "auto"
     if args.summarize_requests:
         summarize_requests(*args.summarize_requests, args.profile_command)
         return
@@ -1188,7 +1205,8 @@ def main(argv=None):
                                             if s_["launches"]},
                          "kernels_total_ms": {q: round(s_["total_ms"], 3) for q, s_ in r["kernels_ms"].items()
                                               if s_["launches"]},
-                         "mean_row": r["mean_row"], "tuning": r["tuning"], "caps": r["caps"]}
+                         "mean_row": r["mean_row"], "tuning": r["tuning"], "core_filter": r["core_filter"],
+                         "caps": r["caps"]}
                      for k, r in results.items()},
         "speedup_rbl_mixed_vs_full_fp64": (speed("rbl_mixed_p10") / speed("full_fp64")
                                            if speed("rbl_mixed_p10") and speed("full_fp64") else None),

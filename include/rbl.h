@@ -128,7 +128,21 @@ typedef struct rbl_config {
                                   the radii at every step (the standard Verlet-list
                                   criterion), and the rebuild is decided on the device
                                   inside the captured lifetimes. */
-    int32_t reserved;          /* must be 0 */
+    int32_t core_filter;       /* Core rows filtered to the partners within r_s + skin/2, in
+                                  runs with rebuild_check on one particle type with one lane
+                                  per particle in the RBL force kernel and core rows of at
+                                  most 64 entries: filtered again at every rebuild and
+                                  whenever some particle has moved skin/4 (less a rounding
+                                  margin) since, so that every partner that can reach r < r_s
+                                  is kept and the forces are those of the built rows bit for
+                                  bit, with fewer partners read per step.  0: off; 1: on;
+                                  2 (default): off in the context's first such run (often a
+                                  lattice start) and decided once at its end, by timing the
+                                  force kernel on its final state and lists (kept if a
+                                  filtered step saves enough to repay a filtering within
+                                  0.4 rebuild_every steps; off for RBL_SHELL_PAPER, whose
+                                  lifetimes are short), see rbl_core_filter.  Other values:
+                                  RBL_E_ARG. */
     int32_t n_types;           /* 0 (default): one particle type, eq. (1) with epsilon = sigma = 1.
                                   1..4: particle types whose interaction lengths differ (Sec. II):
                                   pair (a, b) interacts by eq. (1) with its own epsilon_ab and
@@ -362,6 +376,13 @@ rbl_status rbl_tuning(rbl_ctx* ctx, int32_t* lpp_rbl, int32_t* lpp_full, double*
  * persistent grid of the large single-system workload). */
 rbl_status rbl_launch_modes(rbl_ctx* ctx, int32_t* persistent_rbl, int32_t* persistent_full,
                             double* force_us);
+
+/* Core-row filter (rbl_config.core_filter): *used = 1 if the last rbl_step /
+ * rbl_continue read filtered core rows, and the times of the core_filter = 2
+ * decision: force_us[0] an unfiltered force launch, [1] a launch on the
+ * filtered rows, [2] the filtering launch, in microseconds (zeros before
+ * the decision).  Any pointer may be NULL. */
+rbl_status rbl_core_filter(rbl_ctx* ctx, int32_t* used, double* force_us);
 
 /* Size information: n_slots (particles plus per-replica padding to 64) and
  * current list capacities (entries per row). */

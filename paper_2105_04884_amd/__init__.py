@@ -83,7 +83,8 @@ class Context:
                  capacity_factor: float = 1.25,
                  replica_offsets=None,
                  pair: str = "lj", alpha: float = 0.0, charges=None, shell_source: str = "shell",
-                 rebuild_check: bool = False, types=None, eps_sig=None, stream=None):
+                 rebuild_check: bool = False, core_filter="auto", types=None, eps_sig=None,
+                 stream=None):
         """``types`` (n ints) and ``eps_sig`` ((n_types, n_types, 2) table of
         epsilon_ab, sigma_ab): particle types with per-pair LJ parameters and
         radii r_s sigma_ab, r_c sigma_ab (rbl_config.n_types)."""
@@ -109,6 +110,7 @@ class Context:
         cfg.shell_source = {"shell": _lib.SHELL_LIST, "stencil": _lib.SHELL_STENCIL,
                             "paper": _lib.SHELL_PAPER}[shell_source]
         cfg.rebuild_check = int(bool(rebuild_check))
+        cfg.core_filter = 2 if core_filter == "auto" else int(bool(core_filter))
         self._offsets = None
         if replica_offsets is not None:
             self._offsets = np.ascontiguousarray(replica_offsets, dtype=np.int64)
@@ -373,6 +375,14 @@ class Context:
                 "persistent_rbl": pr.value, "persistent_full": pf.value,
                 "rbl_grid_vs_persistent_us": list(pus[0:2]),
                 "full_grid_vs_persistent_us": list(pus[2:4])}
+
+    def core_filter(self):
+        """Whether the last run read filtered core rows, and the times of the
+        automatic decision (unfiltered, filtered and filtering launch, us)."""
+        used = C.c_int32()
+        us = (C.c_double * 3)()
+        _check(self._lib.rbl_core_filter(self._h, C.byref(used), us))
+        return {"used": bool(used.value), "force_us": list(us)}
 
     def info(self):
         ns = C.c_int64()

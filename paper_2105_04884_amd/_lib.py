@@ -55,7 +55,7 @@ class Config(C.Structure):
         ("charges", C.c_void_p),
         ("shell_source", C.c_int32),
         ("rebuild_check", C.c_int32),
-        ("reserved", C.c_int32),
+        ("core_filter", C.c_int32),
         ("n_types", C.c_int32),
         ("types", C.POINTER(C.c_int32)),
         ("pair_coeffs", C.POINTER(C.c_double)),
@@ -69,6 +69,7 @@ _names = [
     "rbl_step", "rbl_continue", "rbl_last_run", "rbl_row_counts", "rbl_export_lists", "rbl_export_batches", "rbl_export_drawn_batches",
     "rbl_export_binning",
     "rbl_sync", "rbl_set_profiling", "rbl_kernel_stats", "rbl_info", "rbl_tuning", "rbl_launch_modes",
+    "rbl_core_filter",
     "rbl_set_thermostat", "rbl_unwrap", "rbl_msd", "rbl_rdf", "rbl_thermo",
     "rbl_last_error",
     "rbl_version",
@@ -113,6 +114,7 @@ def load(path: str = LIB_PATH):
         "rbl_kernel_stats": (i32, [vp, i32, p64, pd]),
         "rbl_info": (i32, [vp, p64, p32, p32, p32]),
         "rbl_tuning": (i32, [vp, p32, p32, pd]),
+        "rbl_core_filter": (i32, [vp, p32, pd]),
         "rbl_launch_modes": (i32, [vp, p32, p32, pd]),
         "rbl_set_thermostat": (i32, [vp, d, pd]),
         "rbl_unwrap": (i32, [vp, vp, vp]),

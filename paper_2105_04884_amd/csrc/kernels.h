@@ -1857,6 +1857,20 @@ struct ForceArgs {
     const int4* xq;
     double guard;
     const TypeTable* types;  // pair constants of particle types (kPairTyped)
+    // Filtered core rows (one lane per particle, rows of at most 64
+    // entries, runs with rebuilds on displacement; null fgate: off).  With
+    // *fgate set, the launch reads the built rows, writes the partners with
+    // r^2 < filt2 = (r_s + d_f)^2 to fcore / fcore_len in row order and the
+    // positions to xf; otherwise it reads fcore.  The integrator raises
+    // *fgate at every rebuild and when a particle has moved more than d_f/2
+    // (less a rounding margin) from xf, so a dropped partner stays at
+    // r >= r_s, whose term is an exact zero: the sums are those of the
+    // built rows bit for bit.
+    const uint64_t* fgate;
+    int* fcore;
+    int* fcore_len;
+    float* xf;             // [3][n_slots]
+    double filt2;
 };
 
 // This step's pre-drawn batches (the force evaluation's step relative to
@@ -1907,7 +1921,8 @@ __device__ __forceinline__ void zone_bounds(const TypePair& pp, int zone, double
 template <int PREC, bool ENERGY, int PAIR, int U>
 __device__ __forceinline__ void accumulate(const double4& xi, const double4 (&xj)[U], const bool (&live)[U],
                                            double lo2, double hi2, const DevReplica& R,
-                                           const ForceArgs& a, Acc& acc, const TypePair* tp, int zone)
+                                           const ForceArgs& a, Acc& acc, const TypePair* tp, int zone,
+                                           double keep2, uint32_t& keep)
 {
     constexpr bool ERFC = PAIR == kPairErfc;
     if constexpr (PAIR == kPairTyped) {
@@ -1915,6 +1930,7 @@ __device__ __forceinline__ void accumulate(const double4& xi, const double4 (&xj
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const Delta d = delta(xi, xj[u], R);
+            keep |= (live[u] && d.r2 < keep2 ? 1u : 0u) << u;
             const TypePair& pp = row[type_of(xj[u].w)];
             double lo, hi;
             zone_bounds(pp, zone, lo, hi);
@@ -1936,6 +1952,7 @@ __device__ __forceinline__ void accumulate(const double4& xi, const double4 (&xj
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const Delta d = delta(xi, xj[u], R);
+        keep |= (live[u] && d.r2 < keep2 ? 1u : 0u) << u;
         const bool in = live[u] && d.r2 >= lo2 && d.r2 < hi2;
         const double r2 = in ? d.r2 : 1.0;
         double fm, en;
@@ -1962,7 +1979,7 @@ template <bool ENERGY, int PAIR, int U>
 __device__ __forceinline__ void accumulate_mixed(const double4& xi, const int4& qi, const int4 (&xj)[U],
                                                  const int (&j)[U], const bool (&live)[U], double lo2,
                                                  double hi2, const DevReplica& R, const ForceArgs& a, Acc& acc,
-                                                 const TypePair* tp, int zone)
+                                                 const TypePair* tp, int zone, double keep2, uint32_t& keep)
 {
     constexpr bool ERFC = PAIR == kPairErfc;
     constexpr double k2m32 = 2.3283064365386962890625e-10;  // 2^-32
@@ -1975,6 +1992,7 @@ __device__ __forceinline__ void accumulate_mixed(const double4& xi, const int4& 
             const double dy = (double)(int)((uint32_t)qi.y - (uint32_t)xj[u].y) * s1;
             const double dz = (double)(int)((uint32_t)qi.z - (uint32_t)xj[u].z) * s2;
             const double r2q = fma(dz, dz, fma(dy, dy, dx * dx));
+            keep |= (live[u] && r2q < keep2 ? 1u : 0u) << u;
             const TypePair& pp = row[type_of((double)__int_as_float(xj[u].w))];
             double lo, hi;
             zone_bounds(pp, zone, lo, hi);
@@ -2003,6 +2021,7 @@ __device__ __forceinline__ void accumulate_mixed(const double4& xi, const int4& 
         const double dy = (double)(int)((uint32_t)qi.y - (uint32_t)xj[u].y) * s1;
         const double dz = (double)(int)((uint32_t)qi.z - (uint32_t)xj[u].z) * s2;
         const double r2q = fma(dz, dz, fma(dy, dy, dx * dx));
+        keep |= (live[u] && r2q < keep2 ? 1u : 0u) << u;
         bool in = live[u] && r2q >= lo2 && r2q < hi2;
         if (live[u] && (fabs(r2q - lo2) <= a.guard || fabs(r2q - hi2) <= a.guard)) {
             const Delta d = delta(xi, a.xs[j[u]], R);
@@ -2026,24 +2045,35 @@ __device__ __forceinline__ void accumulate_mixed(const double4& xi, const int4& 
 
 // Gathers the positions of U partners (all loads in flight first) and
 // accumulates their pair terms: FP64 positions, or the fixed-point copy
-// (mixed).
+// (mixed).  Bit u of `keep` is set for a live partner with r^2 < keep2 (as
+// classified).
+template <int PREC, bool ENERGY, int PAIR, int U>
+__device__ __forceinline__ void gather_accumulate(const ForceArgs& a, const double4& xi, const int4& qi,
+                                                  const int (&j)[U], const bool (&live)[U], double lo2,
+                                                  double hi2, const DevReplica& R, Acc& acc,
+                                                  const TypePair* tp, int zone, double keep2, uint32_t& keep)
+{
+    if constexpr (PREC == kMixed) {
+        int4 xj[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) xj[u] = a.xq[j[u]];
+        accumulate_mixed<ENERGY, PAIR, U>(xi, qi, xj, j, live, lo2, hi2, R, a, acc, tp, zone, keep2, keep);
+    } else {
+        double4 xj[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) xj[u] = a.xs[j[u]];
+        accumulate<PREC, ENERGY, PAIR, U>(xi, xj, live, lo2, hi2, R, a, acc, tp, zone, keep2, keep);
+    }
+}
+
 template <int PREC, bool ENERGY, int PAIR, int U>
 __device__ __forceinline__ void gather_accumulate(const ForceArgs& a, const double4& xi, const int4& qi,
                                                   const int (&j)[U], const bool (&live)[U], double lo2,
                                                   double hi2, const DevReplica& R, Acc& acc,
                                                   const TypePair* tp, int zone)
 {
-    if constexpr (PREC == kMixed) {
-        int4 xj[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) xj[u] = a.xq[j[u]];
-        accumulate_mixed<ENERGY, PAIR, U>(xi, qi, xj, j, live, lo2, hi2, R, a, acc, tp, zone);
-    } else {
-        double4 xj[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) xj[u] = a.xs[j[u]];
-        accumulate<PREC, ENERGY, PAIR, U>(xi, xj, live, lo2, hi2, R, a, acc, tp, zone);
-    }
+    uint32_t keep = 0;
+    gather_accumulate<PREC, ENERGY, PAIR, U>(a, xi, qi, j, live, lo2, hi2, R, acc, tp, zone, -1.0, keep);
 }
 
 // The type table of a force launch, copied into LDS by the block.
@@ -2062,8 +2092,9 @@ __device__ __forceinline__ void load_type_table(const ForceArgs& a, TypePair* s_
 template <int PREC>
 constexpr int kGatherBatch = PREC == kMixed ? 6 : 4;
 
-template <int PREC, int MODE, bool ENERGY, int PAIR, int PMAX>
-__device__ __forceinline__ void force_tile(const ForceArgs& a, int64_t tile, uint32_t* s_pos, const TypePair* tp)
+template <int PREC, int MODE, bool ENERGY, int PAIR, int PMAX, bool FILT>
+__device__ __forceinline__ void force_tile(const ForceArgs& a, int64_t tile, uint32_t* s_pos, const TypePair* tp,
+                                           int* s_keep)
 {
     constexpr int U = kGatherBatch<PREC>;
     const int64_t slot = tile * blockDim.x + threadIdx.x;
@@ -2092,8 +2123,13 @@ __device__ __forceinline__ void force_tile(const ForceArgs& a, int64_t tile, uin
         Acc c = {0.0, 0.0, 0.0, 0.0, 0.0};
         {
             const double cut = MODE == kShellNone ? a.rc2 : a.rs2;
-            const int len = a.core_len[slot];
-            const int* row = a.core + ell(slot, 0, a.cap_core);
+            // filtered core rows (see ForceArgs): FILT reads the built rows
+            // and writes the filtered ones, the other instance reads those
+            constexpr bool filt = FILT && MODE != kShellNone;
+            const bool use_f = !FILT && MODE != kShellNone && a.fgate != nullptr;
+            const int len = use_f ? a.fcore_len[slot] : a.core_len[slot];
+            const int* row = (use_f ? a.fcore : a.core) + ell(slot, 0, a.cap_core);
+            int nf = 0;
             // the row entries of the next group are loaded before this
             // group's gathers, so their latency overlaps the gathers'
             int jn[U];
@@ -2109,8 +2145,31 @@ __device__ __forceinline__ void force_tile(const ForceArgs& a, int64_t tile, uin
                 }
 #pragma unroll
                 for (int u = 0; u < U; ++u) jn[u] = k + U + u < len ? row[(int64_t)(k + U + u) * 64] : (int)slot;
+                uint32_t keep = 0;
                 gather_accumulate<PREC, ENERGY, PAIR, U>(a, xi, qi, j, live, -1.0, cut, R, c, tp,
-                                                         MODE == kShellNone ? kZoneFull : kZoneCore);
+                                                         MODE == kShellNone ? kZoneFull : kZoneCore,
+                                                         filt ? a.filt2 : -1.0, keep);
+                if constexpr (filt) {
+                    // the kept partners go to this lane's column of LDS
+                    // (entry q at q * blockDim + lane: no bank conflicts)
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        if ((keep >> u) & 1u) {
+                            s_keep[nf * (int)blockDim.x + (int)threadIdx.x] = j[u];
+                            ++nf;
+                        }
+                    }
+                }
+            }
+            if constexpr (filt) {
+                // entry q of every lane's filtered row in one store: whole
+                // cache lines of the sliced rows
+                int* frow = a.fcore + ell(slot, 0, a.cap_core);
+                for (int q = 0; q < nf; ++q) frow[(int64_t)q * 64] = s_keep[q * (int)blockDim.x + (int)threadIdx.x];
+                a.fcore_len[slot] = nf;
+                a.xf[slot] = (float)xi.x;
+                a.xf[a.n_slots + slot] = (float)xi.y;
+                a.xf[2 * a.n_slots + slot] = (float)xi.z;
             }
         }
         if (MODE != kShellNone) {
@@ -2201,15 +2260,23 @@ __device__ __forceinline__ void force_tile(const ForceArgs& a, int64_t tile, uin
 // One tile per block, or (persistent grid) tiles b, b + gridDim.x, ... in
 // turn; the grid is a multiple of 8 blocks, so a block keeps to its XCD's
 // tiles of the XCD map.
-template <int PREC, int MODE, bool ENERGY, int PAIR, int PMAX>
+// With filtered core rows (a.fgate set) two instances are queued per
+// step: FILT works when the filter gate is raised (built rows in, filtered
+// rows out, staged through cap_core x 256 ints of dynamic LDS), the other
+// when it is clear (filtered rows in); each returns at once otherwise.
+// Separate instances keep the filtering's registers and LDS out of the
+// kernel that runs on most steps.
+template <int PREC, int MODE, bool ENERGY, int PAIR, int PMAX, bool FILT = false>
 __global__ __launch_bounds__(256) void k_forces(ForceArgs a)
 {
+    if (a.fgate && (*a.fgate != 0) != FILT) return;
     __shared__ uint32_t s_pos[MODE == kShellInline ? PMAX * 256 : 1];
     __shared__ TypePair s_tp[PAIR == kPairTyped ? kMaxTypes * kMaxTypes : 1];
+    extern __shared__ int s_keep[];
     force_prologue(a);
     if constexpr (PAIR == kPairTyped) load_type_table(a, s_tp);
     for (int64_t b = blockIdx.x; b < a.vblocks; b += gridDim.x)
-        force_tile<PREC, MODE, ENERGY, PAIR, PMAX>(a, xcd_tile(b, a.vblocks), s_pos, s_tp);
+        force_tile<PREC, MODE, ENERGY, PAIR, PMAX, FILT>(a, xcd_tile(b, a.vblocks), s_pos, s_tp, s_keep);
 }
 
 template <int CTRL>
@@ -2371,11 +2438,13 @@ constexpr int kReduceSlicesPerBlock = 256;
 
 __global__ __launch_bounds__(256) void k_reduce(const DevReplica* rep, const double* partial,
                                                int64_t n_slices, int per, int blocks_per_rep,
-                                               double* part2)
+                                               double* part2, uint64_t* fgate_clear)
 {
     __shared__ double lds[5][4];
     const int r = blockIdx.y;
     const int b = blockIdx.x;
+    // the filter gate of the force launch before is reset for the next step
+    if (fgate_clear && r == 0 && b == 0 && threadIdx.x == 0) *fgate_clear = 0;
     const DevReplica& R = rep[r];
     // `per` partial entries per slice (one per wavefront of the force kernel)
     const int64_t s0 = (R.slot_base >> 6) * per;
@@ -2461,6 +2530,12 @@ struct IntArgs {
     const uint64_t* bstep;
     int64_t max_life;
     int4* xq;                  // may be null: fixed-point copy of the positions, kept in step
+    // filtered core rows (null: off): *fgate = 1 with every rebuild and when
+    // a particle is farther than sqrt(fhalf2) from its position xf at the
+    // last filtering, compared in FP32
+    uint64_t* fgate;
+    const float* xf;
+    float fhalf2;
 };
 
 // The three standard normal numbers of the Ornstein-Uhlenbeck step of
@@ -2495,7 +2570,10 @@ __global__ __launch_bounds__(256) void k_integrate(IntArgs a)
     if (MODE != kIntLast && a.gate && s == 0) {
         // the longest list lifetime is reached
         const uint64_t st = a.step_dev ? *a.step_dev + a.step : a.step;
-        if ((int64_t)(st - *a.bstep) >= a.max_life) *a.gate = 1;
+        if ((int64_t)(st - *a.bstep) >= a.max_life) {
+            *a.gate = 1;
+            if (a.fgate) *a.fgate = 1;
+        }
     }
     if ((s >> 6) >= a.n_slices) return;
     const int r = a.slice_rep[s >> 6];
@@ -2548,7 +2626,16 @@ __global__ __launch_bounds__(256) void k_integrate(IntArgs a)
         const double dx = x.x - a.xb[s];
         const double dy = x.y - a.xb[a.n_slots + s];
         const double dz = x.z - a.xb[2 * a.n_slots + s];
-        if (dx * dx + dy * dy + dz * dz > a.half_skin2) *a.gate = 1;
+        if (dx * dx + dy * dy + dz * dz > a.half_skin2) {
+            *a.gate = 1;
+            if (a.fgate) *a.fgate = 1;
+        }
+        if (a.fgate) {
+            const float ex = (float)x.x - a.xf[s];
+            const float ey = (float)x.y - a.xf[a.n_slots + s];
+            const float ez = (float)x.z - a.xf[2 * a.n_slots + s];
+            if (ex * ex + ey * ey + ez * ez > a.fhalf2) *a.fgate = 1;
+        }
     }
 #pragma unroll
     for (int d = 0; d < 3; ++d) a.vs[d * a.n_slots + s] = v[d];

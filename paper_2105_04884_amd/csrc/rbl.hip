@@ -121,7 +121,8 @@ struct rbl_ctx {
     // device words of the MD loop: [0] step counter read by captured kernels;
     // [1] pending half-kick flag of a captured lifetime's first step; [2] step
     // of the last list build and [3] builds in the run (written by the build
-    // kernels); [4] rebuild gate of the displacement criterion
+    // kernels); [4] rebuild gate of the displacement criterion; [5] gate of
+    // the filtered core rows
     uint64_t* d_step = nullptr;
     uint64_t h_marks[2] = {0, 0};
     int R = 1;
@@ -192,6 +193,16 @@ struct rbl_ctx {
     double* d_vs[2] = {nullptr, nullptr};
     double* d_xb = nullptr;
     double* d_f = nullptr;
+    // filtered core rows of runs with rebuilds on displacement (one lane per
+    // particle): rows of cap[0] entries, their lengths, the positions at the
+    // filtering; filt_run while a run uses them, with the thresholds below
+    int* d_fcore = nullptr;
+    int* d_fcore_len = nullptr;
+    float* d_xf = nullptr;
+    int64_t fcore_alloc = 0;
+    bool filt_run = false;
+    double filt2 = 0.0;
+    float fhalf2 = 0.0f;
 
     int cap[3] = {0, 0, 0};
     int* d_list[3] = {nullptr, nullptr, nullptr};
@@ -214,6 +225,11 @@ struct rbl_ctx {
     int64_t lds_per_cu = 160 * 1024;  // bytes of LDS per compute unit
     int64_t fused_static_lds = -1;    // static LDS of the fused build (queried once)
     bool tuned_rbl = false, tuned_full = false;
+    // core_filter == 2: decided once per context by timing (filt_tuned);
+    // filt_us: unfiltered step, filtered step, filtering launch
+    bool filt_tuned = false, filt_auto_on = false;
+    bool filt_last = false;  // the last run read filtered rows
+    double filt_us[3] = {0, 0, 0};
     double tune_us[2][3] = {{0, 0, 0}, {0, 0, 0}};  // measured force time per LPP 1, 2, 4
     double* d_part2 = nullptr;
     int red_blocks = 1;
@@ -282,6 +298,21 @@ void launch_k(rbl_ctx* c, K kernel, unsigned grid, size_t shmem, A... args)
         c->lt_used = true;
     } else {
         kernel<<<grid, kBlock, shmem, c->ls>>>(args...);
+    }
+}
+
+// Two dispatches timed as one (the start of the first to the end of the
+// second), e.g. the two instances of a force step of which one returns at once.
+template <typename K1, typename K2, typename... A>
+void launch_k2(rbl_ctx* c, K1 k1, unsigned g1, size_t sh1, K2 k2, unsigned g2, size_t sh2, A... args)
+{
+    if (c->lt_a && c->lt_b && !c->lt_used) {
+        hipExtLaunchKernelGGL(k1, dim3(g1), dim3(kBlock), (uint32_t)sh1, c->ls, c->lt_a, nullptr, 0u, args...);
+        hipExtLaunchKernelGGL(k2, dim3(g2), dim3(kBlock), (uint32_t)sh2, c->ls, nullptr, c->lt_b, 0u, args...);
+        c->lt_used = true;
+    } else {
+        k1<<<g1, kBlock, sh1, c->ls>>>(args...);
+        k2<<<g2, kBlock, sh2, c->ls>>>(args...);
     }
 }
 
@@ -1089,6 +1120,11 @@ ForceArgs force_args(rbl_ctx* c, int P, uint64_t seed, uint64_t step, bool full)
     a.xq = c->d_xq;
     a.guard = c->guard_q;
     a.types = c->typed ? c->d_tt : nullptr;
+    a.fgate = nullptr;
+    a.fcore = nullptr;
+    a.fcore_len = nullptr;
+    a.xf = nullptr;
+    a.filt2 = 0.0;
     return a;
 }
 
@@ -1112,15 +1148,25 @@ void launch_force_p(rbl_ctx* c, const ForceArgs& a0)
 {
     ForceArgs a = a0;
     const bool pers = c->persist[MODE == kShellNone ? 1 : 0];
+    // filtering instance: LDS column of cap_core entries per lane
+    const size_t keep_lds = (size_t)kBlock * a.cap_core * sizeof(int);
     if constexpr (MODE == kShellInline) {
         a.vblocks = grid_for(c->n_slots);
         c->part_per = 1;
         if (a.P <= 16) {
             auto k = k_forces<PREC, MODE, EN, PAIR, 16>;
-            launch_k(c, k, force_grid(c, k, a.vblocks, pers), 0, a);
+            auto kf = k_forces<PREC, MODE, EN, PAIR, 16, true>;
+            if (a.fgate)
+                launch_k2(c, kf, force_grid(c, kf, a.vblocks, pers), keep_lds, k,
+                          force_grid(c, k, a.vblocks, pers), 0, a);
+            else launch_k(c, k, force_grid(c, k, a.vblocks, pers), 0, a);
         } else {
             auto k = k_forces<PREC, MODE, EN, PAIR, 32>;
-            launch_k(c, k, force_grid(c, k, a.vblocks, pers), 0, a);
+            auto kf = k_forces<PREC, MODE, EN, PAIR, 32, true>;
+            if (a.fgate)
+                launch_k2(c, kf, force_grid(c, kf, a.vblocks, pers), keep_lds, k,
+                          force_grid(c, k, a.vblocks, pers), 0, a);
+            else launch_k(c, k, force_grid(c, k, a.vblocks, pers), 0, a);
         }
     } else {
         const int lpp = MODE == kShellNone ? c->lpp_full : c->lpp_rbl;
@@ -1132,6 +1178,14 @@ void launch_force_p(rbl_ctx* c, const ForceArgs& a0)
         } else {
             a.vblocks = grid_for(c->n_slots);
             auto k = k_forces<PREC, MODE, EN, PAIR, 1>;
+            if constexpr (MODE != kShellNone) {
+                if (a.fgate) {
+                    auto kf = k_forces<PREC, MODE, EN, PAIR, 1, true>;
+                    launch_k2(c, kf, force_grid(c, kf, a.vblocks, pers), keep_lds, k,
+                              force_grid(c, k, a.vblocks, pers), 0, a);
+                    return;
+                }
+            }
             launch_k(c, k, force_grid(c, k, a.vblocks, pers), 0, a);
         }
     }
@@ -1194,11 +1248,12 @@ rbl_status predraw(rbl_ctx* c, int P, uint64_t seed, uint64_t step0, int K)
     });
 }
 
-rbl_status reduce(rbl_ctx* c)
+rbl_status reduce(rbl_ctx* c, bool gated = false)
 {
+    uint64_t* fclear = gated && c->filt_run ? c->d_step + 5 : nullptr;
     return timed(c, kKReduce, [&] {
         k_reduce<<<dim3(c->red_blocks, c->R), kBlock, 0, c->ls>>>(
-            c->d_rep, c->d_partial, c->n_slices, c->part_per, c->red_blocks, c->d_part2);
+            c->d_rep, c->d_partial, c->n_slices, c->part_per, c->red_blocks, c->d_part2, fclear);
         k_reduce_final<<<c->R, kBlock, 0, c->ls>>>(c->d_rep, c->part_per, c->red_blocks, c->d_part2,
                                                    c->d_rep_sum);
     });
@@ -1214,6 +1269,13 @@ rbl_status rbl_force_sorted(rbl_ctx* c, int P, uint64_t seed, uint64_t step, int
     ForceArgs a = force_args(c, P, seed, step, false);
     a.step_dev = step_dev;
     if (gated) a.gate_clear = c->d_step + 4;
+    if (gated && c->filt_run) {
+        a.fgate = c->d_step + 5;
+        a.fcore = c->d_fcore;
+        a.fcore_len = c->d_fcore_len;
+        a.xf = c->d_xf;
+        a.filt2 = c->filt2;
+    }
     if (batch_rel >= 0 && gated) {
         a.batch = c->d_batch;
         a.bstep = c->d_step + 2;
@@ -1224,7 +1286,7 @@ rbl_status rbl_force_sorted(rbl_ctx* c, int P, uint64_t seed, uint64_t step, int
     } else {
         RBL_TRY(timed(c, kKForceRbl, [&] { launch_force<kShellInline>(c, a, energy); }, true));
     }
-    return reduce(c);
+    return reduce(c, gated);
 }
 
 rbl_status full_force_sorted(rbl_ctx* c, bool energy, bool gated = false)
@@ -1288,6 +1350,9 @@ rbl_status integrate(rbl_ctx* c, int mode, double dt, bool momentum_fix, uint64_
     a.gate = gate_life > 0 ? c->d_step + 4 : nullptr;
     a.bstep = c->d_step + 2;
     a.max_life = gate_life;
+    a.fgate = gate_life > 0 && c->filt_run ? c->d_step + 5 : nullptr;
+    a.xf = c->d_xf;
+    a.fhalf2 = c->fhalf2;
     a.xq = c->d_xq;
     a.rep = c->d_rep;
     a.slice_rep = c->d_slice_rep;
@@ -1331,14 +1396,16 @@ __global__ void k_set_block(uint64_t* p, uint64_t step, uint64_t pending)
     }
 }
 
-// Start of a run: build count and rebuild gate cleared, and (entry build at
-// `step`, set_build) the step of the last build.
+// Start of a run: build count and rebuild gate cleared, the filter gate
+// raised (the first gated force filters the rows it is given), and (entry
+// build at `step`, set_build) the step of the last build.
 __global__ void k_run_marks(uint64_t* p, uint64_t step, int set_build)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         if (set_build) p[2] = step;
         p[3] = 0;
         p[4] = 0;
+        p[5] = 1;
     }
 }
 
@@ -1396,6 +1463,10 @@ std::vector<unsigned char> block_signature(const rbl_ctx* c, const StepParams& s
     sig_put(v, c->gamma);
     sig_put(v, (const void*)c->d_osig);
     sig_put(v, (const void*)c->d_img_delta);
+    sig_put(v, (int)c->filt_run);
+    sig_put(v, (const void*)c->d_fcore);
+    sig_put(v, c->filt2);
+    sig_put(v, c->fhalf2);
     return v;
 }
 
@@ -1458,6 +1529,151 @@ rbl_status queue_block(rbl_ctx* c, const StepParams& sp)
         else if (sp.pre) RBL_TRY(rbl_force_sorted(c, sp.P, sp.seed, 0, r == sp.K ? 0 : (int)r, false));
         else RBL_TRY(rbl_force_sorted(c, sp.P, sp.seed, (uint64_t)r, -1, false, c->d_step));
     }
+    return RBL_OK;
+}
+
+__global__ void k_set_u64(uint64_t* p, uint64_t v)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+
+// Filtered core rows for a run with rebuilds on displacement (RBL, one type,
+// one lane per particle, core rows of at most 64 entries).  Rows keep the
+// partners within r_s + d_f, d_f = skin/2, and are filtered again once a
+// particle has moved d_f/2 - m from its position then.  The positions are
+// compared in FP32: stored and current values each round by at most
+// 2^-24 (L + skin) (coordinates drift less than skin/2 out of the box
+// between rebuilds), and m = 4 2^-24 (L_max + skin) + 1e-6 bounds both with
+// room to spare.  A dropped partner was at r >= r_s + d_f and both
+// particles have since moved less than d_f/2, so it stays beyond r_s (by at
+// least m, far above the rounding of r^2).
+// Whether the filter can serve this run, and if so its buffers and
+// thresholds (*ok).
+rbl_status prepare_core_filter(rbl_ctx* c, const StepParams& sp, bool& ok)
+{
+    ok = false;
+    if (!c->cfg.core_filter || sp.full || c->typed || (sp.pre && c->lpp_rbl != 1) || c->cap[0] > 64)
+        return RBL_OK;
+    if (c->cfg.core_filter == 2 && c->paper) return RBL_OK;
+    double lmax = 0.0;
+    for (int r = 0; r < c->R; ++r)
+        for (int a = 0; a < 3; ++a) lmax = std::max(lmax, c->h_rep[r].L[a]);
+    const double df = 0.5 * c->cfg.skin;
+    const double m = 4.0 * std::ldexp(lmax + c->cfg.skin, -24) + 1e-6;
+    if (!(df > 0.0) || m >= 0.25 * df) return RBL_OK;
+    const int64_t need = (int64_t)c->cap[0] * c->n_slots;
+    if (need > c->fcore_alloc) {
+        dfree(c->d_fcore);
+        c->fcore_alloc = 0;
+        RBL_TRY(dalloc(&c->d_fcore, (size_t)need));
+        c->fcore_alloc = need;
+    }
+    if (!c->d_fcore_len) RBL_TRY(dalloc(&c->d_fcore_len, (size_t)c->n_slots));
+    if (!c->d_xf) RBL_TRY(dalloc(&c->d_xf, 3 * (size_t)c->n_slots));
+    const double rf = c->r_s + df;
+    const double hf = 0.5 * df - m;
+    c->filt2 = rf * rf;
+    c->fhalf2 = (float)(hf * hf);
+    ok = true;
+    return RBL_OK;
+}
+
+// At a run's start: core_filter 1 filters whenever it can; 2 once the
+// decision (taken at the end of the context's first such run) says so.
+rbl_status setup_core_filter(rbl_ctx* c, const StepParams& sp)
+{
+    c->filt_run = false;
+    bool ok = false;
+    RBL_TRY(prepare_core_filter(c, sp, ok));
+    c->filt_run = ok && (c->cfg.core_filter == 1 || (c->filt_tuned && c->filt_auto_on));
+    return RBL_OK;
+}
+
+// core_filter == 2, at the end of the context's first run with rebuilds on
+// displacement (a first run often starts from a lattice, whose regular
+// neighbourhoods time the kernels unlike the fluid it becomes): times, on
+// the final state and its lists, an unfiltered force launch (t_u), the
+// filtering launch (t_F) and a launch on the filtered rows (t_f), each
+// after 64 MB of stores that push the lists and positions out of L2 as the
+// integrator does in a step, and keeps the filter if a filtered step saves
+// enough to repay a filtering within R = 0.4 K steps (a filtering comes
+// about every half list lifetime, and lifetimes end before the longest, K):
+// (t_u - t_f - o) R > t_F - t_f, o being the per-step cost of the gate (the
+// FP32 position compare in the integrator and the launch that returns at
+// once).  The state and the run's results are left as they are.
+rbl_status tune_core_filter(rbl_ctx* c, const StepParams& sp)
+{
+    c->filt_tuned = true;
+    c->filt_auto_on = false;
+    bool ok = false;
+    RBL_TRY(prepare_core_filter(c, sp, ok));
+    if (!ok) return RBL_OK;
+    // the timed launches write forces and partial sums of their own: the
+    // context's hold the run's state (the force the first half-kick takes)
+    struct Scratch {
+        double* f = nullptr;
+        double* part = nullptr;
+        int* flush = nullptr;
+        ~Scratch()
+        {
+            dfree(f);
+            dfree(part);
+            dfree(flush);
+        }
+    } tmp;
+    constexpr int64_t kFlushInts = 16 << 20;  // 64 MB
+    RBL_TRY(dalloc(&tmp.f, 3 * (size_t)c->n_slots));
+    RBL_TRY(dalloc(&tmp.part, 5 * 4 * (size_t)c->n_slices));
+    RBL_TRY(dalloc(&tmp.flush, (size_t)kFlushInts));
+    hipEvent_t e0 = take_event(c), e1 = take_event(c);
+    if (!e0 || !e1) return fail(RBL_E_HIP, "event creation failed");
+    const bool prof = c->profiling;
+    c->profiling = false;
+    // microseconds per launch (mean of the second and third of three); gate
+    // < 0: unfiltered, else the filter gate's value for the launch
+    auto time_force = [&](int gate, double& us) -> rbl_status {
+        float total = 0.f;
+        for (int rep = 0; rep < 3; ++rep) {
+            ForceArgs a = force_args(c, sp.P, sp.seed, 0, false);
+            a.f = tmp.f;
+            a.partial = tmp.part;
+            if (gate >= 0) {
+                k_set_u64<<<1, 64, 0, c->ls>>>(c->d_step + 5, (uint64_t)gate);
+                a.fgate = c->d_step + 5;
+                a.fcore = c->d_fcore;
+                a.fcore_len = c->d_fcore_len;
+                a.xf = c->d_xf;
+                a.filt2 = c->filt2;
+            }
+            k_fill_i32<<<grid_for(kFlushInts), kBlock, 0, c->ls>>>(tmp.flush, kFlushInts, rep);
+            HIP_TRY(hipEventRecord(e0, c->ls));
+            if (sp.pre) {
+                a.batch = c->d_batch;
+                launch_force<kShellPredraw>(c, a, false);
+            } else {
+                launch_force<kShellInline>(c, a, false);
+            }
+            HIP_TRY(hipEventRecord(e1, c->ls));
+            HIP_TRY(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+            if (rep > 0) total += ms;
+        }
+        us = 1e3 * total / 2.0;
+        return RBL_OK;
+    };
+    RBL_TRY(time_force(-1, c->filt_us[0]));
+    RBL_TRY(time_force(1, c->filt_us[2]));
+    RBL_TRY(time_force(0, c->filt_us[1]));
+    c->profiling = prof;
+    c->ev_pool.push_back(e0);
+    c->ev_pool.push_back(e1);
+    const double o = 1.6 + 12.0 * (double)c->n_slots / 5.0e6;  // us: launch + 12 bytes per slot at 5 TB/s
+    const double R = 0.4 * (double)sp.K;
+    c->filt_auto_on = (c->filt_us[0] - c->filt_us[1] - o) * R > c->filt_us[2] - c->filt_us[1];
+    // the run's first gated force filters again
+    k_set_u64<<<1, 64, 0, c->ls>>>(c->d_step + 5, 1);
+    HIP_TRY(hipGetLastError());
     return RBL_OK;
 }
 
@@ -1670,6 +1886,13 @@ rbl_status md_run(rbl_ctx* c, const double* pos_in, const double* vel_in, double
         if (c->cfg.lanes == 0 || c->cfg.persistent == 0) RBL_TRY(autotune_forces(c, sp));
         RBL_TRY(do_force(step0, ev != nullptr && nsteps == 0));
     }
+    struct FilterGuard {
+        rbl_ctx* c;
+        ~FilterGuard() { c->filt_run = false; }
+    } fguard{c};
+    if (sp.check) RBL_TRY(setup_core_filter(c, sp));
+    else c->filt_run = false;
+    c->filt_last = c->filt_run;
     // pending: the velocities await the closing half-kick of the last force
     bool pending = false;
     int64_t it = 1;
@@ -1738,6 +1961,7 @@ rbl_status md_run(rbl_ctx* c, const double* pos_in, const double* vel_in, double
     }
     if (c->h_flags[kFlagNonfinite]) return fail(RBL_E_NONFINITE, "non-finite position during the run");
     if (c->h_flags[kFlagBadSlot]) return fail(RBL_E_HIP, "inconsistent cell binning");
+    if (sp.check && c->cfg.core_filter == 2 && !c->filt_tuned) RBL_TRY(tune_core_filter(c, sp));
     IoArgs io = io_args(c, sp.fix);
     io.pos_out = pos_out;
     io.vel_out = vel_out;
@@ -1836,7 +2060,7 @@ void rbl_config_init(rbl_config* cfg, int64_t n)
     cfg->charges = nullptr;
     cfg->shell_source = RBL_SHELL_LIST;
     cfg->rebuild_check = 0;
-    cfg->reserved = 0;
+    cfg->core_filter = 2;
     cfg->n_types = 0;
     cfg->types = nullptr;
     cfg->pair_coeffs = nullptr;
@@ -1885,6 +2109,9 @@ rbl_status rbl_destroy(rbl_ctx* c)
     dfree(c->d_vs[1]);
     dfree(c->d_xb);
     dfree(c->d_f);
+    dfree(c->d_fcore);
+    dfree(c->d_fcore_len);
+    dfree(c->d_xf);
     for (int q = 0; q < 3; ++q) {
         dfree(c->d_list[q]);
         dfree(c->d_len[q]);
@@ -1935,7 +2162,7 @@ rbl_status rbl_create(const rbl_config* cfg, void* hip_stream, rbl_ctx** out)
     if (cfg->shell_source != RBL_SHELL_LIST && cfg->shell_source != RBL_SHELL_STENCIL &&
         cfg->shell_source != RBL_SHELL_PAPER)
         return fail(RBL_E_ARG, "shell_source must be RBL_SHELL_LIST, RBL_SHELL_STENCIL or RBL_SHELL_PAPER");
-    if (cfg->reserved != 0) return fail(RBL_E_ARG, "reserved must be 0");
+    if (cfg->core_filter < 0 || cfg->core_filter > 2) return fail(RBL_E_ARG, "core_filter must be 0, 1 or 2");
     if (cfg->n_types < 0 || cfg->n_types > kMaxTypes)
         return fail(RBL_E_ARG, "n_types must be in 0 .. " + std::to_string(kMaxTypes));
     if (cfg->n_types == 0 && (cfg->types || cfg->pair_coeffs))
@@ -2535,6 +2762,15 @@ rbl_status rbl_tuning(rbl_ctx* c, int32_t* lpp_rbl, int32_t* lpp_full, double* f
     if (force_us)
         for (int k = 0; k < 2; ++k)
             for (int q = 0; q < 3; ++q) force_us[3 * k + q] = c->tune_us[k][q];
+    return RBL_OK;
+}
+
+rbl_status rbl_core_filter(rbl_ctx* c, int32_t* used, double* force_us)
+{
+    if (!c) return fail(RBL_E_ARG, "NULL context");
+    if (used) *used = c->filt_last ? 1 : 0;
+    if (force_us)
+        for (int q = 0; q < 3; ++q) force_us[q] = c->filt_us[q];
     return RBL_OK;
 }
 

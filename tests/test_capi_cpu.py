@@ -51,7 +51,7 @@ def test_config_defaults(lib):
     assert cfg.lists == _lib.LIST_CORE | _lib.LIST_SHELL
     assert cfg.skin == 0.3 and cfg.shift == 1 and cfg.momentum_fix == 1 and cfg.predraw == 1
     assert cfg.capacity_factor == 1.25 and cfg.lanes == 0 and cfg.persistent == 0
-    assert cfg.shell_source == _lib.SHELL_LIST and cfg.reserved == 0
+    assert cfg.shell_source == _lib.SHELL_LIST and cfg.core_filter == 2
     assert lib.rbl_version().decode().startswith("librbl")
 
 
@@ -74,7 +74,7 @@ def _create(lib, **over):
     {"n": 0}, {"n": -5}, {"n_replicas": 0}, {"precision": 7}, {"pair": 3}, {"lists": 0},
     {"lists": 9}, {"skin": -0.1}, {"skin": float("nan")}, {"pair": 1, "alpha": 0.0},
     {"capacity_factor": 0.0}, {"lanes": 3}, {"lanes": -1}, {"persistent": 3}, {"persistent": -1},
-    {"shell_source": 3}, {"shell_source": -1}, {"reserved": 1},
+    {"shell_source": 3}, {"shell_source": -1}, {"core_filter": 3}, {"core_filter": -1},
     {"n_replicas": 2},                                   # offsets missing
     {"n": 10, "n_replicas": 2, "offsets": [0, 4, 9]},    # does not end at n
     {"n": 10, "n_replicas": 2, "offsets": [0, 0, 10]},   # empty replica
