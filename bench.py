@@ -116,10 +116,11 @@ def parse(argv=None):
                     help="keep the force kernel on the built core rows (rbl_config.core_filter = 0) "
                          "instead of the rows filtered to r_s + skin/2")
     ap.add_argument("--pin-launch", action="store_true",
-                    help="N = 1e6 variants: fix the force kernels' lanes per particle and launch "
-                         "mode to the autotuner's usual choice there (RBL 1 lane mixed, 2 FP64, full list 4, "
-                         "one block per tile) instead of timing them; for profiler runs, whose "
-                         "per-dispatch overhead distorts the autotuner's timings")
+                    help="N = 1e6 variants: fix the force kernels' lanes per particle, launch "
+                         "mode and core-row filter to the automatic choice there (RBL 1 lane mixed "
+                         "with the filter, 2 FP64, full list 4, one block per tile) instead of "
+                         "timing them; for profiler runs, whose per-dispatch overhead distorts "
+                         "those timings")
     ap.add_argument("--skin", type=float, default=None,
                     help="Verlet skin of the N = 1e6 variants (default: the workload's)")
     ap.add_argument("--max-lifetime", type=int, default=None,
@@ -319,8 +320,13 @@ def force_roofline(res, fk):
         nbytes = full_force_algorithmic_bytes(N, res["mean_row"]["full"])
         name = "k_forces (full list)"
     else:
-        nbytes = force_algorithmic_bytes(N, res["P"], res["mean_row"]["core"])
-        name = "k_forces (RBL, pre-drawn batches)"
+        # with filtered core rows, the rows read on the steps between
+        # filterings (the filtering steps read the built rows: an undercount)
+        filt = res.get("core_filter") or {}
+        core = filt["mean_kept"] if filt.get("used") and filt.get("mean_kept") else res["mean_row"]["core"]
+        nbytes = force_algorithmic_bytes(N, res["P"], core)
+        name = ("k_forces (RBL, pre-drawn batches, filtered core rows)" if filt.get("used")
+                else "k_forces (RBL, pre-drawn batches)")
     ach = nbytes / avg_s / 1e9 if avg_s > 0 else None
     key = f"force_{'full' if res['full'] else 'rbl'}_{res['precision']}_p{res['P']}"
     return {
@@ -398,8 +404,12 @@ def run_variant(name, x0, v0, box, precision, P, use_full, warmup, steps, repeat
     v = v0.clone()
     pinned_lanes = 4 if use_full else (1 if precision == "mixed" else 2)
     launch = {"lanes": pinned_lanes, "persistent": 1} if pin else {}
+    if pin:
+        # the automatic core-row filter times the kernels, which a profiler
+        # distorts: fixed to its usual choice (on at one lane per particle)
+        launch["core_filter"] = bool(pinned_lanes == 1 and source != "paper")
     ctx = Context(N, precision=precision, lists=lists, skin=skin, shell_source=source, rebuild_check=check,
-                  core_filter=CORE_FILTER,
+                  core_filter=launch.pop("core_filter", CORE_FILTER),
                   **launch)
     ctx.build(x, box, RS, RC)
     K = max_life if check else K_REBUILD
@@ -873,6 +883,18 @@ def summarize(trace_dir, fetch_dir, write_dir, command, calib_mib, P=10):
         n_act, mean = active_mean(v)
         if n_act < len(v):
             lines.append(f"active {n_act:7d} {mean / 1e3:10.2f}  {name}")
+    # a force step with filtered core rows queues two instances (one returns
+    # at once): the class's time per step sums them, as the bench's own
+    # events around the step's force launches do
+    per_class = {}
+    for name, v in durs.items():
+        cls = kernel_class(name, P)
+        if cls:
+            tot, steps = per_class.get(cls, (0.0, 0))
+            per_class[cls] = (tot + sum(v), max(steps, len(v)))
+    lines += ["", "# per kernel class: force steps, microseconds per step (all instances)"]
+    for cls, (tot, steps) in sorted(per_class.items()):
+        lines.append(f"step {cls} {steps:7d} {tot / steps / 1e3:10.2f}")
     with open(os.path.join(PROFILES, "kernel_trace_n1m.txt"), "w") as f:
         f.write("\n".join(lines) + "\n")
 

@@ -378,11 +378,13 @@ rbl_status rbl_launch_modes(rbl_ctx* ctx, int32_t* persistent_rbl, int32_t* pers
                             double* force_us);
 
 /* Core-row filter (rbl_config.core_filter): *used = 1 if the last rbl_step /
- * rbl_continue read filtered core rows, and the times of the core_filter = 2
+ * rbl_continue read filtered core rows; the times of the core_filter = 2
  * decision: force_us[0] an unfiltered force launch, [1] a launch on the
  * filtered rows, [2] the filtering launch, in microseconds (zeros before
- * the decision).  Any pointer may be NULL. */
-rbl_status rbl_core_filter(rbl_ctx* ctx, int32_t* used, double* force_us);
+ * the decision); *mean_kept the mean length of the filtered rows at the
+ * last filtering (0 if none).  Any pointer may be NULL; with mean_kept the
+ * call copies the row lengths to the host and synchronises. */
+rbl_status rbl_core_filter(rbl_ctx* ctx, int32_t* used, double* force_us, double* mean_kept);
 
 /* Size information: n_slots (particles plus per-replica padding to 64) and
  * current list capacities (entries per row). */

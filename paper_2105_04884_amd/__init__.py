@@ -377,12 +377,14 @@ class Context:
                 "full_grid_vs_persistent_us": list(pus[2:4])}
 
     def core_filter(self):
-        """Whether the last run read filtered core rows, and the times of the
-        automatic decision (unfiltered, filtered and filtering launch, us)."""
+        """Whether the last run read filtered core rows, the times of the
+        automatic decision (unfiltered, filtered and filtering launch, us)
+        and the mean filtered row length at the last filtering."""
         used = C.c_int32()
         us = (C.c_double * 3)()
-        _check(self._lib.rbl_core_filter(self._h, C.byref(used), us))
-        return {"used": bool(used.value), "force_us": list(us)}
+        kept = C.c_double()
+        _check(self._lib.rbl_core_filter(self._h, C.byref(used), us, C.byref(kept)))
+        return {"used": bool(used.value), "force_us": list(us), "mean_kept": kept.value}
 
     def info(self):
         ns = C.c_int64()

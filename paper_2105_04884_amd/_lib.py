@@ -114,7 +114,7 @@ def load(path: str = LIB_PATH):
         "rbl_kernel_stats": (i32, [vp, i32, p64, pd]),
         "rbl_info": (i32, [vp, p64, p32, p32, p32]),
         "rbl_tuning": (i32, [vp, p32, p32, pd]),
-        "rbl_core_filter": (i32, [vp, p32, pd]),
+        "rbl_core_filter": (i32, [vp, p32, pd, pd]),
         "rbl_launch_modes": (i32, [vp, p32, p32, pd]),
         "rbl_set_thermostat": (i32, [vp, d, pd]),
         "rbl_unwrap": (i32, [vp, vp, vp]),

@@ -2765,12 +2765,31 @@ rbl_status rbl_tuning(rbl_ctx* c, int32_t* lpp_rbl, int32_t* lpp_full, double* f
     return RBL_OK;
 }
 
-rbl_status rbl_core_filter(rbl_ctx* c, int32_t* used, double* force_us)
+rbl_status rbl_core_filter(rbl_ctx* c, int32_t* used, double* force_us, double* mean_kept)
 {
     if (!c) return fail(RBL_E_ARG, "NULL context");
     if (used) *used = c->filt_last ? 1 : 0;
     if (force_us)
         for (int q = 0; q < 3; ++q) force_us[q] = c->filt_us[q];
+    if (mean_kept) {
+        *mean_kept = 0.0;
+        if (c->filt_last && c->d_fcore_len) {
+            std::vector<int> len((size_t)c->n_slots), perm((size_t)c->n_slots);
+            HIP_TRY(hipMemcpyAsync(len.data(), c->d_fcore_len, sizeof(int) * c->n_slots, hipMemcpyDeviceToHost,
+                                   c->stream));
+            HIP_TRY(hipMemcpyAsync(perm.data(), c->cur_perm(), sizeof(int) * c->n_slots, hipMemcpyDeviceToHost,
+                                   c->stream));
+            HIP_TRY(hipStreamSynchronize(c->stream));
+            double sum = 0.0;
+            int64_t cnt = 0;
+            for (int64_t s = 0; s < c->n_slots; ++s)
+                if (perm[s] >= 0) {
+                    sum += len[s];
+                    ++cnt;
+                }
+            *mean_kept = cnt ? sum / (double)cnt : 0.0;
+        }
+    }
     return RBL_OK;
 }
 

@@ -49,6 +49,9 @@ def test_filtered_rows_give_the_unfiltered_run(precision, source, predraw, graph
     off = _run(st, 0, 60, **kw)
     assert on[4]["used"] and not off[4]["used"]
     assert on[3] >= 3
+    # the rows at the last filtering hold the partners within r_s + skin/2:
+    # about (2.0 / 2.5)^3 of the built rows' r_s + skin, a lattice-free fluid
+    assert 0 < on[4]["mean_kept"] < 26
     _assert_same(on, off)
 
 
@@ -111,5 +114,5 @@ def test_automatic_filter_at_the_benchmark_size():
     print(f"core filter: used {auto[4]['used']}, unfiltered {us[0]:.1f} us, filtered {us[1]:.1f} us, "
           f"filtering {us[2]:.1f} us")
     if auto[4]["used"]:
-        assert all(t > 0 for t in us)
+        assert all(t > 0 for t in us) and auto[4]["mean_kept"] > 0
     _assert_same(auto, off)
