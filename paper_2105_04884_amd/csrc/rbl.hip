@@ -1583,9 +1583,10 @@ rbl_status prepare_core_filter(rbl_ctx* c, const StepParams& sp, bool& ok)
 rbl_status setup_core_filter(rbl_ctx* c, const StepParams& sp)
 {
     c->filt_run = false;
+    if (c->cfg.core_filter == 2 && !(c->filt_tuned && c->filt_auto_on)) return RBL_OK;
     bool ok = false;
     RBL_TRY(prepare_core_filter(c, sp, ok));
-    c->filt_run = ok && (c->cfg.core_filter == 1 || (c->filt_tuned && c->filt_auto_on));
+    c->filt_run = ok;
     return RBL_OK;
 }
 
@@ -1674,6 +1675,14 @@ rbl_status tune_core_filter(rbl_ctx* c, const StepParams& sp)
     // the run's first gated force filters again
     k_set_u64<<<1, 64, 0, c->ls>>>(c->d_step + 5, 1);
     HIP_TRY(hipGetLastError());
+    if (!c->filt_auto_on) {
+        // declined for good: the rows' memory goes back (hipFree waits for
+        // the launches above)
+        dfree(c->d_fcore);
+        dfree(c->d_fcore_len);
+        dfree(c->d_xf);
+        c->fcore_alloc = 0;
+    }
     return RBL_OK;
 }
 
