@@ -140,9 +140,11 @@ typedef struct rbl_config {
                                   lattice start) and decided once at its end, by timing the
                                   force kernel on its final state and lists (kept if a
                                   filtered step saves enough to repay a filtering within
-                                  0.4 rebuild_every steps; off for RBL_SHELL_PAPER, whose
-                                  lifetimes are short), see rbl_core_filter.  Other values:
-                                  RBL_E_ARG. */
+                                  0.4 rebuild_every steps; with lanes = 0 a pre-drawn RBL
+                                  kernel of 2 or 4 lanes is weighed against one lane with
+                                  the filter and moved to it if that is faster; off for
+                                  RBL_SHELL_PAPER, whose lifetimes are short), see
+                                  rbl_core_filter.  Other values: RBL_E_ARG. */
     int32_t n_types;           /* 0 (default): one particle type, eq. (1) with epsilon = sigma = 1.
                                   1..4: particle types whose interaction lengths differ (Sec. II):
                                   pair (a, b) interacts by eq. (1) with its own epsilon_ab and

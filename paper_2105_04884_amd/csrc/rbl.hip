@@ -1549,10 +1549,13 @@ __global__ void k_set_u64(uint64_t* p, uint64_t v)
 // least m, far above the rounding of r^2).
 // Whether the filter can serve this run, and if so its buffers and
 // thresholds (*ok).
-rbl_status prepare_core_filter(rbl_ctx* c, const StepParams& sp, bool& ok)
+// any_lanes: the decision of core_filter = 2 with autotuned lanes, which may
+// move a pre-drawn RBL kernel of 2 or 4 lanes to one lane with the filter.
+rbl_status prepare_core_filter(rbl_ctx* c, const StepParams& sp, bool& ok, bool any_lanes = false)
 {
     ok = false;
-    if (!c->cfg.core_filter || sp.full || c->typed || (sp.pre && c->lpp_rbl != 1) || c->cap[0] > 64)
+    if (!c->cfg.core_filter || sp.full || c->typed || (sp.pre && c->lpp_rbl != 1 && !any_lanes) ||
+        c->cap[0] > 64)
         return RBL_OK;
     if (c->cfg.core_filter == 2 && c->paper) return RBL_OK;
     double lmax = 0.0;
@@ -1606,9 +1609,13 @@ rbl_status tune_core_filter(rbl_ctx* c, const StepParams& sp)
 {
     c->filt_tuned = true;
     c->filt_auto_on = false;
+    // with autotuned lanes a kernel of 2 or 4 lanes per particle competes
+    // with one lane on filtered rows
+    const bool relane = c->cfg.lanes == 0 && sp.pre;
     bool ok = false;
-    RBL_TRY(prepare_core_filter(c, sp, ok));
+    RBL_TRY(prepare_core_filter(c, sp, ok, relane));
     if (!ok) return RBL_OK;
+    const int lpp0 = c->lpp_rbl;
     // the timed launches write forces and partial sums of their own: the
     // context's hold the run's state (the force the first half-kick takes)
     struct Scratch {
@@ -1663,7 +1670,10 @@ rbl_status tune_core_filter(rbl_ctx* c, const StepParams& sp)
         us = 1e3 * total / 2.0;
         return RBL_OK;
     };
+    // the layout in use, unfiltered; then one lane per particle with the
+    // filter (the filtered kernels are one-lane)
     RBL_TRY(time_force(-1, c->filt_us[0]));
+    c->lpp_rbl = 1;
     RBL_TRY(time_force(1, c->filt_us[2]));
     RBL_TRY(time_force(0, c->filt_us[1]));
     c->profiling = prof;
@@ -1671,7 +1681,9 @@ rbl_status tune_core_filter(rbl_ctx* c, const StepParams& sp)
     c->ev_pool.push_back(e1);
     const double o = 1.6 + 12.0 * (double)c->n_slots / 5.0e6;  // us: launch + 12 bytes per slot at 5 TB/s
     const double R = 0.4 * (double)sp.K;
+    // per step: t_f + o + (t_F - t_f) / R against t_u
     c->filt_auto_on = (c->filt_us[0] - c->filt_us[1] - o) * R > c->filt_us[2] - c->filt_us[1];
+    if (!c->filt_auto_on) c->lpp_rbl = lpp0;
     // the run's first gated force filters again
     k_set_u64<<<1, 64, 0, c->ls>>>(c->d_step + 5, 1);
     HIP_TRY(hipGetLastError());
