@@ -83,6 +83,28 @@ def test_filtered_rows_with_lj_erfc_and_replicas():
     _assert_same(out[0], out[1])
 
 
+def test_filtered_rows_with_the_langevin_thermostat():
+    """BAOAB Langevin steps (gamma = 1, kT = 2.0) move the particles with
+    noise between the displacement tests: forced filter against none, bit
+    for bit."""
+    torch = torch_cuda()
+    st = inputs.lj_fluid(12_000, 0.8442, 2.0, seed=9)
+    out = []
+    for cf in (1, 0):
+        x, v = dev(st.pos), dev(st.vel)
+        f = torch.zeros_like(x)
+        with Context(st.n, precision="mixed", rebuild_check=True, skin=0.5, lanes=1, core_filter=cf) as ctx:
+            ctx.set_thermostat(1.0, 2.0)
+            ctx.build(x, st.box, RS, RC)
+            status, _ = ctx.step(x, v, nsteps=50, dt=0.005, P=10, seed=6, rebuild_every=13, force=f)
+            used = ctx.core_filter()["used"]
+            builds = ctx.last_run()["builds"]
+        assert status == 0
+        out.append((host(x), host(v), host(f), builds, used))
+    assert out[0][4] and not out[1][4]
+    _assert_same(out[0], out[1])
+
+
 def _two_runs(st, core_filter, **kw):
     """40 steps, then 40 more continued from the state the first left;
     returns the final state and the filter report after each run."""
