@@ -144,7 +144,10 @@ typedef struct rbl_config {
                                   kernel of 2 or 4 lanes is weighed against one lane with
                                   the filter and moved to it if that is faster; off for
                                   RBL_SHELL_PAPER, whose lifetimes are short), see
-                                  rbl_core_filter.  Other values: RBL_E_ARG. */
+                                  rbl_core_filter.  While in use the context holds one
+                                  more core-row array (the core rows' room in ints per
+                                  particle), its lengths and FP32 positions, 16 bytes per
+                                  particle beside the rows.  Other values: RBL_E_ARG. */
     int32_t n_types;           /* 0 (default): one particle type, eq. (1) with epsilon = sigma = 1.
                                   1..4: particle types whose interaction lengths differ (Sec. II):
                                   pair (a, b) interacts by eq. (1) with its own epsilon_ab and
