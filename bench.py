@@ -498,15 +498,17 @@ def run_mixture(torch, warmup, steps, repeats, P=10):
         x, v = torch.from_numpy(st.pos).cuda(), torch.from_numpy(st.vel).cuda()
         lists = ("full",) if full else ("core", "shell")
         with Context(n, precision="mixed", lists=lists, skin=skin, rebuild_check=True, types=st.types,
-                     eps_sig=MIXTURE_TABLE) as ctx:
+                     eps_sig=MIXTURE_TABLE, core_filter=CORE_FILTER) as ctx:
             ctx.build(x, st.box, RS, RC)
             tb = timed_blocks(ctx, x, v, torch, P, warmup, steps, repeats, full, K=life)
+            cfilt = ctx.core_filter()
         el = tb["median_s"]
         log(f"[bench] mixture {name}: {1e3 * el / steps:.3f} ms/step, {n * steps / el:.3e} atom-steps/s")
         out[name] = {"skin": skin, "atom_steps_per_s": n * steps / el, "ms_per_step": 1e3 * el / steps,
                      "status": tb["status"], "attempts_max": tb["attempts_max"],
                      "steps_per_build": tb["steps_per_build"], "kernels_avg_us": kernels_avg_us(tb),
-                     "build_us_per_build": round(tb["kernels_ms"]["build"]["avg_us_per_build"], 1)}
+                     "build_us_per_build": round(tb["kernels_ms"]["build"]["avg_us_per_build"], 1),
+                     "core_filter": cfilt}
     if "rbl" in out and "full_list" in out:
         out["rbl_speedup_vs_full_list"] = out["rbl"]["atom_steps_per_s"] / out["full_list"]["atom_steps_per_s"]
     return out

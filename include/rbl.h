@@ -128,10 +128,11 @@ typedef struct rbl_config {
                                   the radii at every step (the standard Verlet-list
                                   criterion), and the rebuild is decided on the device
                                   inside the captured lifetimes. */
-    int32_t core_filter;       /* Core rows filtered to the partners within r_s + skin/2, in
-                                  runs with rebuild_check on one particle type with one lane
-                                  per particle in the RBL force kernel and core rows of at
-                                  most 64 entries: filtered again at every rebuild and
+    int32_t core_filter;       /* Core rows filtered to the partners within r_s + skin/2
+                                  (with types r_s sigma_ab + skin/2), in runs with
+                                  rebuild_check with one lane per particle in the RBL force
+                                  kernel and core rows of at most 64 entries: filtered again
+                                  at every rebuild and
                                   whenever some particle has moved skin/4 (less a rounding
                                   margin) since, so that every partner that can reach r < r_s
                                   is kept and the forces are those of the built rows bit for

@@ -37,7 +37,7 @@ struct TypePair {
     double eps24, eps4, sig2;          // 24 eps_ab, 4 eps_ab, sigma_ab^2
     double rs2, rc2, uc;               // (r_s sigma_ab)^2, (r_c sigma_ab)^2, energy at the cut-off
     double thr_core, thr_in, thr_out;  // list thresholds: squared radii with the skin
-    double pad;
+    double filt2;                      // core-row filter: (r_s sigma_ab + skin/2)^2
 };
 
 struct TypeTable {
@@ -1860,7 +1860,8 @@ struct ForceArgs {
     // Filtered core rows (one lane per particle, rows of at most 64
     // entries, runs with rebuilds on displacement; null fgate: off).  With
     // *fgate set, the launch reads the built rows, writes the partners with
-    // r^2 < filt2 = (r_s + d_f)^2 to fcore / fcore_len in row order and the
+    // r^2 < filt2 = (r_s + d_f)^2 (with types the pair's (r_s sigma_ab +
+    // d_f)^2 from the table) to fcore / fcore_len in row order and the
     // positions to xf; otherwise it reads fcore.  The integrator raises
     // *fgate at every rebuild and when a particle has moved more than d_f/2
     // (less a rounding margin) from xf, so a dropped partner stays at
@@ -1930,8 +1931,9 @@ __device__ __forceinline__ void accumulate(const double4& xi, const double4 (&xj
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const Delta d = delta(xi, xj[u], R);
-            keep |= (live[u] && d.r2 < keep2 ? 1u : 0u) << u;
             const TypePair& pp = row[type_of(xj[u].w)];
+            // the filter threshold is the pair's own (keep2 > 0: filtering)
+            keep |= (live[u] && d.r2 < (keep2 > 0.0 ? pp.filt2 : -1.0) ? 1u : 0u) << u;
             double lo, hi;
             zone_bounds(pp, zone, lo, hi);
             const bool in = live[u] && d.r2 >= lo && d.r2 < hi;
@@ -1992,8 +1994,8 @@ __device__ __forceinline__ void accumulate_mixed(const double4& xi, const int4& 
             const double dy = (double)(int)((uint32_t)qi.y - (uint32_t)xj[u].y) * s1;
             const double dz = (double)(int)((uint32_t)qi.z - (uint32_t)xj[u].z) * s2;
             const double r2q = fma(dz, dz, fma(dy, dy, dx * dx));
-            keep |= (live[u] && r2q < keep2 ? 1u : 0u) << u;
             const TypePair& pp = row[type_of((double)__int_as_float(xj[u].w))];
+            keep |= (live[u] && r2q < (keep2 > 0.0 ? pp.filt2 : -1.0) ? 1u : 0u) << u;
             double lo, hi;
             zone_bounds(pp, zone, lo, hi);
             bool in = live[u] && r2q >= lo && r2q < hi;

@@ -496,6 +496,8 @@ rbl_status setup_types(rbl_ctx* c, const std::vector<DevReplica>& reps, double r
             p.thr_core = ca * ca;
             p.thr_in = cb * cb;
             p.thr_out = co * co;
+            const double cf = rs + 0.5 * skin;
+            p.filt2 = cf * cf;
         }
         const double h = std::ceil((r_c * smax + skin) * 1.000001 / edge);
         if (!(h <= 15.0))
@@ -1537,9 +1539,10 @@ __global__ void k_set_u64(uint64_t* p, uint64_t v)
     if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
 }
 
-// Filtered core rows for a run with rebuilds on displacement (RBL, one type,
-// one lane per particle, core rows of at most 64 entries).  Rows keep the
-// partners within r_s + d_f, d_f = skin/2, and are filtered again once a
+// Filtered core rows for a run with rebuilds on displacement (RBL, one lane
+// per particle, core rows of at most 64 entries).  Rows keep the partners
+// within r_s + d_f, d_f = skin/2 (with types r_s sigma_ab + d_f, from the
+// pair table), and are filtered again once a
 // particle has moved d_f/2 - m from its position then.  The positions are
 // compared in FP32: stored and current values each round by at most
 // 2^-24 (L + skin) (coordinates drift less than skin/2 out of the box
@@ -1554,8 +1557,7 @@ __global__ void k_set_u64(uint64_t* p, uint64_t v)
 rbl_status prepare_core_filter(rbl_ctx* c, const StepParams& sp, bool& ok, bool any_lanes = false)
 {
     ok = false;
-    if (!c->cfg.core_filter || sp.full || c->typed || (sp.pre && c->lpp_rbl != 1 && !any_lanes) ||
-        c->cap[0] > 64)
+    if (!c->cfg.core_filter || sp.full || (sp.pre && c->lpp_rbl != 1 && !any_lanes) || c->cap[0] > 64)
         return RBL_OK;
     if (c->cfg.core_filter == 2 && c->paper) return RBL_OK;
     double lmax = 0.0;

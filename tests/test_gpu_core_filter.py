@@ -83,6 +83,38 @@ def test_filtered_rows_with_lj_erfc_and_replicas():
     _assert_same(out[0], out[1])
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("ntypes", [2, 3])
+def test_filtered_rows_with_particle_types(precision, ntypes):
+    """Particle types (pair radii r_s sigma_ab, r_c sigma_ab; each pair's
+    filter radius r_s sigma_ab + skin/2): a hot mixture, forced filter
+    against none, bit for bit."""
+    torch = torch_cuda()
+    if ntypes == 2:
+        st = inputs.mixture(16_000, 0.5, 2.0, 11, (0.8, 0.2))
+        table = np.array([[[1.0, 1.0], [1.0, 1.2]], [[1.0, 1.2], [1.0, 1.4]]])
+    else:
+        st = inputs.mixture(12_000, 0.45, 2.0, 12, (0.5, 0.3, 0.2))
+        eps = np.array([[1.0, 1.5, 0.7], [1.5, 0.5, 1.2], [0.7, 1.2, 2.0]])
+        sig = np.array([[1.0, 0.8, 1.3], [0.8, 0.88, 1.1], [1.3, 1.1, 1.6]])
+        table = np.ascontiguousarray(np.stack([eps, sig], axis=-1))
+    out = []
+    for cf in (1, 0):
+        x, v = dev(st.pos), dev(st.vel)
+        f = torch.zeros_like(x)
+        with Context(st.n, precision=precision, rebuild_check=True, skin=0.5, lanes=1, core_filter=cf,
+                     types=st.types, eps_sig=table) as ctx:
+            ctx.build(x, st.box, RS, RC)
+            status, _ = ctx.step(x, v, nsteps=50, dt=0.004, P=10, seed=2, rebuild_every=13, force=f)
+            used = ctx.core_filter()["used"]
+            builds = ctx.last_run()["builds"]
+        assert status == 0
+        out.append((host(x), host(v), host(f), builds, used))
+    assert out[0][4] and not out[1][4]
+    assert out[0][3] >= 2
+    _assert_same(out[0], out[1])
+
+
 def test_filtered_rows_with_the_langevin_thermostat():
     """BAOAB Langevin steps (gamma = 1, kT = 2.0) move the particles with
     noise between the displacement tests: forced filter against none, bit
