@@ -2094,11 +2094,17 @@ __device__ __forceinline__ void load_type_table(const ForceArgs& a, TypePair* s_
 template <int PREC>
 constexpr int kGatherBatch = PREC == kMixed ? 6 : 4;
 
+// LDS entries per lane of the filtering instance (its dynamic LDS holds
+// min(cap_core, kKeepLds) of them)
+constexpr int kKeepLds = 32;
+
 template <int PREC, int MODE, bool ENERGY, int PAIR, int PMAX, bool FILT>
 __device__ __forceinline__ void force_tile(const ForceArgs& a, int64_t tile, uint32_t* s_pos, const TypePair* tp,
                                            int* s_keep)
 {
-    constexpr int U = kGatherBatch<PREC>;
+    // the filtering instance keeps at most 5 neighbours in flight, which
+    // holds it to 4 waves per SIMD with its staging
+    constexpr int U = FILT && kGatherBatch<PREC> > 5 ? 5 : kGatherBatch<PREC>;
     const int64_t slot = tile * blockDim.x + threadIdx.x;
     const int64_t slice = slot >> 6;
     if (slice >= a.n_slices) return;
@@ -2152,12 +2158,14 @@ __device__ __forceinline__ void force_tile(const ForceArgs& a, int64_t tile, uin
                                                          MODE == kShellNone ? kZoneFull : kZoneCore,
                                                          filt ? a.filt2 : -1.0, keep);
                 if constexpr (filt) {
-                    // the kept partners go to this lane's column of LDS
-                    // (entry q at q * blockDim + lane: no bank conflicts)
+                    // the first kKeepLds kept partners go to this lane's
+                    // column of LDS (entry q at q * blockDim + lane: no bank
+                    // conflicts), any further ones straight to the row
 #pragma unroll
                     for (int u = 0; u < U; ++u) {
                         if ((keep >> u) & 1u) {
-                            s_keep[nf * (int)blockDim.x + (int)threadIdx.x] = j[u];
+                            if (nf < kKeepLds) s_keep[nf * (int)blockDim.x + (int)threadIdx.x] = j[u];
+                            else a.fcore[ell(slot, nf, a.cap_core)] = j[u];
                             ++nf;
                         }
                     }
@@ -2167,7 +2175,8 @@ __device__ __forceinline__ void force_tile(const ForceArgs& a, int64_t tile, uin
                 // entry q of every lane's filtered row in one store: whole
                 // cache lines of the sliced rows
                 int* frow = a.fcore + ell(slot, 0, a.cap_core);
-                for (int q = 0; q < nf; ++q) frow[(int64_t)q * 64] = s_keep[q * (int)blockDim.x + (int)threadIdx.x];
+                const int nl = nf < kKeepLds ? nf : kKeepLds;
+                for (int q = 0; q < nl; ++q) frow[(int64_t)q * 64] = s_keep[q * (int)blockDim.x + (int)threadIdx.x];
                 a.fcore_len[slot] = nf;
                 a.xf[slot] = (float)xi.x;
                 a.xf[a.n_slots + slot] = (float)xi.y;

@@ -1151,7 +1151,7 @@ void launch_force_p(rbl_ctx* c, const ForceArgs& a0)
     ForceArgs a = a0;
     const bool pers = c->persist[MODE == kShellNone ? 1 : 0];
     // filtering instance: LDS column of cap_core entries per lane
-    const size_t keep_lds = (size_t)kBlock * a.cap_core * sizeof(int);
+    const size_t keep_lds = (size_t)kBlock * std::min(a.cap_core, kKeepLds) * sizeof(int);
     if constexpr (MODE == kShellInline) {
         a.vblocks = grid_for(c->n_slots);
         c->part_per = 1;
